@@ -1,0 +1,757 @@
+/*
+ * FP64 CPU oracle -- test infrastructure only (see abd_oracle.h).
+ *
+ * Kinematic representation.  Every DOF is one elementary hinge "frame".  A
+ * link with d DOFs is d consecutive frames: the first is translated by the
+ * joint offset and rotates about the first axis, the others have zero offset
+ * and rotate about the following axes; only the link's last frame carries its
+ * mass moment tensor.  A ball joint is thus three consecutive hinges with
+ * massless zero-length intermediate frames.  With one DOF per frame, Alg. 1
+ * applies verbatim: T^f = T^{parent(f)} t_f(q_f) in the forward pass, and in
+ * the backward pass  A <- A + dE/dT^f ;  g_f += (T^{parent(f)} dt_f/dq_f) : A ;
+ * A_parent <- A_parent + A t_f^T  (the tree form of "A <- A t^T").
+ *
+ * Objective (Sec. 4, Eq. EQ, multiplied by dt^2 so the minimizer is unchanged):
+ *   E(q) = sum_l 1/2 tr(D_l M_l D_l^T) - dt^2 sum_l g^T A_l(q) M_l e4 - dt^2 tau.q
+ *   D_l  = A_l(q) - 2 A_l(q_k) + A_l(q_{k-1}),  A = [R|t] (3x4)
+ * since  int rho |P_a - 2P_b + P_c|^2 / 2 dp = 1/2 tr(D M D^T)  exactly when
+ * M = int rho (p;1)(p;1)^T dp (Eq. ATOM), and the gravity potential density
+ * -rho g.P integrates to -g^T A M e4.
+ */
+#include "abd_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+struct orc_model {
+  int n_models, n_links, n_dofs;
+  int *link_offset, *parent, *dofs_per_link;
+  double *axis, *offset, *mm;
+  double g[3];
+  int *link_dof;     /* [n_links] first global dof of the link */
+  int *model_dof;    /* [n_models+1] */
+  int *frame_parent; /* [n_dofs] parent frame (global dof index), -1 = world */
+  int *frame_link;   /* [n_dofs] link owning the frame */
+  int *frame_first;  /* [n_dofs] 1 if first frame of its link */
+  int *frame_mass;   /* [n_dofs] link whose mass the frame carries, -1 = massless */
+};
+
+/* ------------------------------------------------------------------ 4x4 -- */
+static void m4_eye(double* A) {
+  memset(A, 0, 16 * sizeof(double));
+  A[0] = A[5] = A[10] = A[15] = 1.0;
+}
+static void m4_mul(const double* A, const double* B, double* C) {
+  double t[16];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 4; ++k) s += A[4 * i + k] * B[4 * k + j];
+      t[4 * i + j] = s;
+    }
+  memcpy(C, t, sizeof t);
+}
+/* C += A B^T */
+static void m4_add_mul_bt(const double* A, const double* B, double* C) {
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 4; ++k) s += A[4 * i + k] * B[4 * j + k];
+      C[4 * i + j] += s;
+    }
+}
+static double m4_frob(const double* A, const double* B) {
+  double s = 0.0;
+  for (int i = 0; i < 16; ++i) s += A[i] * B[i];
+  return s;
+}
+/* inverse of a rigid transform [R t; 0 1] */
+static void m4_rigid_inv(const double* T, double* Ti) {
+  memset(Ti, 0, 16 * sizeof(double));
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Ti[4 * i + j] = T[4 * j + i];
+  for (int i = 0; i < 3; ++i)
+    Ti[4 * i + 3] = -(Ti[4 * i + 0] * T[3] + Ti[4 * i + 1] * T[7] + Ti[4 * i + 2] * T[11]);
+  Ti[15] = 1.0;
+}
+/* symmetric 4x4 from its upper triangle (00 01 02 03 11 12 13 22 23 33) */
+static void mm_full(const double* u, double* M) {
+  static const int idx[16] = {0, 1, 2, 3, 1, 4, 5, 6, 2, 5, 7, 8, 3, 6, 8, 9};
+  for (int i = 0; i < 16; ++i) M[i] = u[idx[i]];
+}
+
+/* Rodrigues: R = I + sin(th) K + (1-cos(th)) K^2, K = [a]x.  t = [R o; 0 1]. */
+static void local_tf(const double* a, const double* o, double th, double* t) {
+  double K[9] = {0, -a[2], a[1], a[2], 0, -a[0], -a[1], a[0], 0};
+  double K2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0;
+      for (int k = 0; k < 3; ++k) s += K[3 * i + k] * K[3 * k + j];
+      K2[3 * i + j] = s;
+    }
+  double s = sin(th), c = 1.0 - cos(th);
+  memset(t, 0, 16 * sizeof(double));
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) t[4 * i + j] = (i == j ? 1.0 : 0.0) + s * K[3 * i + j] + c * K2[3 * i + j];
+  for (int i = 0; i < 3; ++i) t[4 * i + 3] = o ? o[i] : 0.0;
+  t[15] = 1.0;
+}
+/* dt/dth = [cos(th) K + sin(th) K^2, 0; 0 0] */
+static void local_dtf(const double* a, double th, double* dt) {
+  double K[9] = {0, -a[2], a[1], a[2], 0, -a[0], -a[1], a[0], 0};
+  double K2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0;
+      for (int k = 0; k < 3; ++k) s += K[3 * i + k] * K[3 * k + j];
+      K2[3 * i + j] = s;
+    }
+  double c = cos(th), s = sin(th);
+  memset(dt, 0, 16 * sizeof(double));
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) dt[4 * i + j] = c * K[3 * i + j] + s * K2[3 * i + j];
+}
+
+/* --------------------------------------------------------------- model -- */
+orc_model* orc_create(int n_models, const int* link_offset, const int* parent,
+                      const int* dofs_per_link, const double* axis, const double* offset,
+                      const double* mass_moment, const double* gravity) {
+  orc_model* m = (orc_model*)calloc(1, sizeof(orc_model));
+  m->n_models = n_models;
+  m->n_links = link_offset[n_models];
+  int L = m->n_links;
+  m->link_offset = (int*)malloc((n_models + 1) * sizeof(int));
+  memcpy(m->link_offset, link_offset, (n_models + 1) * sizeof(int));
+  m->parent = (int*)malloc((L > 0 ? L : 1) * sizeof(int));
+  m->dofs_per_link = (int*)malloc((L > 0 ? L : 1) * sizeof(int));
+  memcpy(m->parent, parent, L * sizeof(int));
+  memcpy(m->dofs_per_link, dofs_per_link, L * sizeof(int));
+  m->link_dof = (int*)malloc((L > 0 ? L : 1) * sizeof(int));
+  int nd = 0;
+  for (int l = 0; l < L; ++l) {
+    m->link_dof[l] = nd;
+    nd += dofs_per_link[l];
+  }
+  m->n_dofs = nd;
+  m->model_dof = (int*)malloc((n_models + 1) * sizeof(int));
+  for (int i = 0; i <= n_models; ++i)
+    m->model_dof[i] = (link_offset[i] < L) ? m->link_dof[link_offset[i]] : nd;
+  m->axis = (double*)malloc((nd > 0 ? 3 * nd : 1) * sizeof(double));
+  memcpy(m->axis, axis, 3 * nd * sizeof(double));
+  m->offset = (double*)malloc((L > 0 ? 3 * L : 1) * sizeof(double));
+  memcpy(m->offset, offset, 3 * L * sizeof(double));
+  m->mm = (double*)malloc((L > 0 ? 10 * L : 1) * sizeof(double));
+  memcpy(m->mm, mass_moment, 10 * L * sizeof(double));
+  memcpy(m->g, gravity, 3 * sizeof(double));
+  int nd1 = nd > 0 ? nd : 1;
+  m->frame_parent = (int*)malloc(nd1 * sizeof(int));
+  m->frame_link = (int*)malloc(nd1 * sizeof(int));
+  m->frame_first = (int*)malloc(nd1 * sizeof(int));
+  m->frame_mass = (int*)malloc(nd1 * sizeof(int));
+  for (int i = 0; i < n_models; ++i) {
+    int lo = link_offset[i];
+    for (int l = lo; l < link_offset[i + 1]; ++l) {
+      int d = m->link_dof[l], k = dofs_per_link[l];
+      for (int j = 0; j < k; ++j) {
+        int f = d + j;
+        m->frame_link[f] = l;
+        m->frame_first[f] = (j == 0);
+        m->frame_mass[f] = (j == k - 1) ? l : -1;
+        if (j > 0)
+          m->frame_parent[f] = f - 1;
+        else if (parent[l] < 0)
+          m->frame_parent[f] = -1;
+        else {
+          int pl = lo + parent[l];
+          m->frame_parent[f] = m->link_dof[pl] + dofs_per_link[pl] - 1;
+        }
+      }
+    }
+  }
+  return m;
+}
+
+void orc_free(orc_model* m) {
+  if (!m) return;
+  free(m->link_offset); free(m->parent); free(m->dofs_per_link); free(m->axis);
+  free(m->offset); free(m->mm); free(m->link_dof); free(m->model_dof);
+  free(m->frame_parent); free(m->frame_link); free(m->frame_first); free(m->frame_mass);
+  free(m);
+}
+
+static int model_nd(const orc_model* m, int i) { return m->model_dof[i + 1] - m->model_dof[i]; }
+
+/* Forward pass of Alg. 1 for model i: T[j] (world) and tl[j] (local), j local frame index. */
+static void fk_model(const orc_model* m, int i, const double* q, double* T, double* tl) {
+  int d0 = m->model_dof[i], nd = model_nd(m, i);
+  double I4[16];
+  m4_eye(I4);
+  for (int j = 0; j < nd; ++j) {
+    int f = d0 + j;
+    const double* o = m->frame_first[f] ? m->offset + 3 * m->frame_link[f] : NULL;
+    double* t = tl + 16 * j;
+    local_tf(m->axis + 3 * f, o, q[f], t);
+    int p = m->frame_parent[f];
+    m4_mul(p >= 0 ? T + 16 * (p - d0) : I4, t, T + 16 * j);
+  }
+}
+
+typedef struct {
+  double *Tk, *Tkm1, *T, *tl, *Adj;
+} eval_ws;
+
+static void ws_alloc(eval_ws* w, int nd) {
+  size_t n = (size_t)(nd > 0 ? nd : 1) * 16;
+  w->Tk = (double*)malloc(n * sizeof(double));
+  w->Tkm1 = (double*)malloc(n * sizeof(double));
+  w->T = (double*)malloc(n * sizeof(double));
+  w->tl = (double*)malloc(n * sizeof(double));
+  w->Adj = (double*)malloc(n * sizeof(double));
+}
+static void ws_free(eval_ws* w) {
+  free(w->Tk); free(w->Tkm1); free(w->T); free(w->tl); free(w->Adj);
+}
+
+/* Backward pass of Alg. 1 over the frames of model i.  Adj holds the per-frame
+ * seeds dE/dT^f on entry (accumulated with child contributions as it runs).
+ * g (global indexing) receives dE/dq_f. */
+static void alg1_backward(const orc_model* m, int i, const double* T, const double* tl,
+                          double* Adj, const double* q, double* g) {
+  int d0 = m->model_dof[i], nd = model_nd(m, i);
+  double I4[16], dt[16], W[16];
+  m4_eye(I4);
+  for (int j = nd - 1; j >= 0; --j) {
+    int f = d0 + j;
+    int p = m->frame_parent[f];
+    local_dtf(m->axis + 3 * f, q[f], dt);
+    m4_mul(p >= 0 ? T + 16 * (p - d0) : I4, dt, W);
+    g[f] = m4_frob(W, Adj + 16 * j);
+    if (p >= 0) m4_add_mul_bt(Adj + 16 * j, tl + 16 * j, Adj + 16 * (p - d0));
+  }
+}
+
+/* Objective and gradient of model i at q.  Tk, Tkm1 = frame poses at q_k, q_{k-1}. */
+static double eval_model(const orc_model* m, int i, double dt, const double* q, const double* tau,
+                         eval_ws* w, double* g, double* S) {
+  int d0 = m->model_dof[i], nd = model_nd(m, i);
+  fk_model(m, i, q, w->T, w->tl);
+  memset(w->Adj, 0, (size_t)nd * 16 * sizeof(double));
+  double E = 0.0, Ssum = 0.0, dt2 = dt * dt;
+  for (int l = m->link_offset[i]; l < m->link_offset[i + 1]; ++l) {
+    int j = m->link_dof[l] + m->dofs_per_link[l] - 1 - d0;
+    double M[16];
+    mm_full(m->mm + 10 * l, M);
+    const double *A = w->T + 16 * j, *Ak = w->Tk + 16 * j, *Akm1 = w->Tkm1 + 16 * j;
+    double e = 0.0;
+    for (int r = 0; r < 3; ++r) {
+      double D[4], DM[4];
+      for (int c = 0; c < 4; ++c) D[c] = A[4 * r + c] - 2.0 * Ak[4 * r + c] + Akm1[4 * r + c];
+      for (int c = 0; c < 4; ++c) {
+        DM[c] = 0.0;
+        for (int k = 0; k < 4; ++k) DM[c] += D[k] * M[4 * k + c];
+      }
+      for (int c = 0; c < 4; ++c) e += 0.5 * DM[c] * D[c];
+      /* potential row r: -dt^2 g_r (A_r . M e4) */
+      double AMe4 = 0.0;
+      for (int k = 0; k < 4; ++k) AMe4 += A[4 * r + k] * M[4 * k + 3];
+      e -= dt2 * m->g[r] * AMe4;
+      /* seed row r of dE/dA: D M - dt^2 g (M e4)^T */
+      for (int c = 0; c < 4; ++c) w->Adj[16 * j + 4 * r + c] += DM[c] - dt2 * m->g[r] * M[4 * c + 3];
+    }
+    E += e;
+    Ssum += fabs(e);
+  }
+  if (tau)
+    for (int j = 0; j < nd; ++j) {
+      double t = dt2 * tau[d0 + j] * q[d0 + j];
+      E -= t;
+      Ssum += fabs(t);
+    }
+  if (g) {
+    alg1_backward(m, i, w->T, w->tl, w->Adj, q, g);
+    if (tau)
+      for (int j = 0; j < nd; ++j) g[d0 + j] -= dt2 * tau[d0 + j];
+  }
+  if (S) *S = Ssum;
+  return E;
+}
+
+/* ------------------------------------------------------------ queries -- */
+void orc_poses(const orc_model* m, const double* q, double* poses, int n_threads) {
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int i = 0; i < m->n_models; ++i) {
+    int nd = model_nd(m, i), d0 = m->model_dof[i];
+    eval_ws w;
+    ws_alloc(&w, nd);
+    fk_model(m, i, q, w.T, w.tl);
+    for (int l = m->link_offset[i]; l < m->link_offset[i + 1]; ++l) {
+      int j = m->link_dof[l] + m->dofs_per_link[l] - 1 - d0;
+      memcpy(poses + 12 * (size_t)l, w.T + 16 * j, 12 * sizeof(double));
+    }
+    ws_free(&w);
+  }
+}
+
+void orc_objective_grad(const orc_model* m, double dt, const double* q, const double* q_hist,
+                        const double* tau, double* E, double* grad, double* S, int n_threads) {
+  const double* qkm1 = q_hist;
+  const double* qk = q_hist + m->n_dofs;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int i = 0; i < m->n_models; ++i) {
+    eval_ws w;
+    ws_alloc(&w, model_nd(m, i));
+    fk_model(m, i, qk, w.Tk, w.tl);
+    fk_model(m, i, qkm1, w.Tkm1, w.tl);
+    double s;
+    E[i] = eval_model(m, i, dt, q, tau, &w, grad, &s);
+    if (S) S[i] = s;
+    ws_free(&w);
+  }
+}
+
+/* I(q_a,q_b) of Eq. ATOM for model i with the homogeneous 4x4 transforms:
+ * [T_a^T T_b] : M minus the homogeneous 1*1 entry (the body mass). */
+static double atom_I(const orc_model* m, int i, const double* Ta, const double* Tb) {
+  int d0 = m->model_dof[i];
+  double I = 0.0;
+  for (int l = m->link_offset[i]; l < m->link_offset[i + 1]; ++l) {
+    int j = m->link_dof[l] + m->dofs_per_link[l] - 1 - d0;
+    double M[16];
+    mm_full(m->mm + 10 * l, M);
+    const double *A = Ta + 16 * j, *B = Tb + 16 * j;
+    double s = 0.0; /* tr((Ta^T Tb)^T M) = sum_k row_k(Ta) M row_k(Tb)^T */
+    for (int k = 0; k < 4; ++k)
+      for (int x = 0; x < 4; ++x)
+        for (int y = 0; y < 4; ++y) s += A[4 * k + x] * M[4 * x + y] * B[4 * k + y];
+    I += s - M[15];
+  }
+  return I;
+}
+
+void orc_alg1_I(const orc_model* m, const double* q_a, const double* q_b, double* I,
+                double* dI_dqb, int n_threads) {
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int i = 0; i < m->n_models; ++i) {
+    int nd = model_nd(m, i), d0 = m->model_dof[i];
+    eval_ws w;
+    ws_alloc(&w, nd);
+    fk_model(m, i, q_a, w.Tk, w.tl);
+    fk_model(m, i, q_b, w.T, w.tl);
+    I[i] = atom_I(m, i, w.Tk, w.T);
+    /* seed dI^f/dT^f(q_b) = T^f(q_a) M on mass-carrying frames */
+    memset(w.Adj, 0, (size_t)nd * 16 * sizeof(double));
+    for (int l = m->link_offset[i]; l < m->link_offset[i + 1]; ++l) {
+      int j = m->link_dof[l] + m->dofs_per_link[l] - 1 - d0;
+      double M[16];
+      mm_full(m->mm + 10 * l, M);
+      m4_mul(w.Tk + 16 * j, M, w.Adj + 16 * j);
+    }
+    alg1_backward(m, i, w.T, w.tl, w.Adj, q_b, dI_dqb);
+    ws_free(&w);
+  }
+}
+
+static double potential(const orc_model* m, int i, const double* T) {
+  int d0 = m->model_dof[i];
+  double V = 0.0;
+  for (int l = m->link_offset[i]; l < m->link_offset[i + 1]; ++l) {
+    int j = m->link_dof[l] + m->dofs_per_link[l] - 1 - d0;
+    const double* u = m->mm + 10 * l;
+    const double Me4[4] = {u[3], u[6], u[8], u[9]};
+    for (int r = 0; r < 3; ++r) {
+      double s = 0.0;
+      for (int k = 0; k < 4; ++k) s += T[16 * j + 4 * r + k] * Me4[k];
+      V -= m->g[r] * s;
+    }
+  }
+  return V;
+}
+
+void orc_objective_Iform(const orc_model* m, double dt, const double* q, const double* q_hist,
+                         const double* tau, double* E, int n_threads) {
+  const double* qkm1 = q_hist;
+  const double* qk = q_hist + m->n_dofs;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int i = 0; i < m->n_models; ++i) {
+    int nd = model_nd(m, i), d0 = m->model_dof[i];
+    eval_ws w;
+    ws_alloc(&w, nd);
+    fk_model(m, i, qk, w.Tk, w.tl);
+    fk_model(m, i, qkm1, w.Tkm1, w.tl);
+    fk_model(m, i, q, w.T, w.tl);
+    double e = 0.5 * atom_I(m, i, w.T, w.T) - 2.0 * atom_I(m, i, w.T, w.Tk) + atom_I(m, i, w.T, w.Tkm1);
+    e += dt * dt * potential(m, i, w.T);
+    if (tau)
+      for (int j = 0; j < nd; ++j) e -= dt * dt * tau[d0 + j] * q[d0 + j];
+    E[i] = e;
+    ws_free(&w);
+  }
+}
+
+/* Joint-space inertia diagonal of model i by the plain definition:
+ * h_n = sum over mass frames f below DOF n of tr(dA_f M dA_f^T),
+ * dT^f/dq_n = T^{parent(n)} dt_n (T^n)^{-1} T^f. */
+static void inertia_diag_model(const orc_model* m, int i, const double* q, eval_ws* w, double* h,
+                               char* desc) {
+  int d0 = m->model_dof[i], nd = model_nd(m, i);
+  fk_model(m, i, q, w->T, w->tl);
+  double I4[16], dtl[16], W[16], Ti[16], tmp[16], dA[16], M[16];
+  m4_eye(I4);
+  for (int j = 0; j < nd; ++j) {
+    int f = d0 + j, p = m->frame_parent[f];
+    local_dtf(m->axis + 3 * f, q[f], dtl);
+    m4_mul(p >= 0 ? w->T + 16 * (p - d0) : I4, dtl, tmp);
+    m4_rigid_inv(w->T + 16 * j, Ti);
+    m4_mul(tmp, Ti, W);
+    double s = 0.0;
+    for (int k = j; k < nd; ++k) {
+      int pk = m->frame_parent[d0 + k];
+      desc[k] = (k == j) || (pk >= d0 + j && desc[pk - d0]);
+      int l = m->frame_mass[d0 + k];
+      if (!desc[k] || l < 0) continue;
+      mm_full(m->mm + 10 * l, M);
+      m4_mul(W, w->T + 16 * k, dA);
+      for (int r = 0; r < 3; ++r)
+        for (int x = 0; x < 4; ++x)
+          for (int y = 0; y < 4; ++y) s += dA[4 * r + x] * M[4 * x + y] * dA[4 * r + y];
+    }
+    h[f] = s;
+  }
+}
+
+void orc_inertia_diag(const orc_model* m, const double* q, double* h, int n_threads) {
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int i = 0; i < m->n_models; ++i) {
+    int nd = model_nd(m, i);
+    eval_ws w;
+    ws_alloc(&w, nd);
+    char* desc = (char*)malloc(nd > 0 ? nd : 1);
+    inertia_diag_model(m, i, q, &w, h, desc);
+    free(desc);
+    ws_free(&w);
+  }
+}
+
+void orc_energy_report(const orc_model* m, double dt, const double* q_prev, const double* q_curr,
+                       double* H, int n_threads) {
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int i = 0; i < m->n_models; ++i) {
+    int nd = model_nd(m, i), d0 = m->model_dof[i];
+    eval_ws w;
+    ws_alloc(&w, nd);
+    fk_model(m, i, q_curr, w.Tk, w.tl);
+    fk_model(m, i, q_prev, w.Tkm1, w.tl);
+    double ke = 0.0;
+    for (int l = m->link_offset[i]; l < m->link_offset[i + 1]; ++l) {
+      int j = m->link_dof[l] + m->dofs_per_link[l] - 1 - d0;
+      double M[16];
+      mm_full(m->mm + 10 * l, M);
+      for (int r = 0; r < 3; ++r) {
+        double D[4];
+        for (int c = 0; c < 4; ++c) D[c] = w.Tk[16 * j + 4 * r + c] - w.Tkm1[16 * j + 4 * r + c];
+        for (int x = 0; x < 4; ++x)
+          for (int y = 0; y < 4; ++y) ke += 0.5 * D[x] * M[4 * x + y] * D[y];
+      }
+    }
+    H[i] = ke / (dt * dt) + potential(m, i, w.Tk);
+    ws_free(&w);
+  }
+}
+
+/* Joint-space inertia of model i at q by its plain definition
+ *   H_ij = sum_l tr(dA_l/dq_i M_l dA_l/dq_j^T),   dT^l/dq_n = W_n T^l,
+ *   W_n  = T^{parent(n)} (dt_n/dq_n) (T^n)^{-1},
+ * grouped by the distributive law: only links below both DOFs contribute, so
+ * for i an ancestor-or-self of j,  H_ij = tr(W_i C_j W_j^T)  with
+ * C_j = sum_{l below j} T^l M_l T^{lT}  (world moment tensor of the subtree). */
+static void inertia_matrix_model(const orc_model* m, int i, const double* q, eval_ws* w, double* H,
+                                 double* Wb, double* Cb) {
+  int d0 = m->model_dof[i], nd = model_nd(m, i);
+  fk_model(m, i, q, w->T, w->tl);
+  double I4[16], dtl[16], tmp[16], Ti[16], M[16];
+  m4_eye(I4);
+  for (int j = 0; j < nd; ++j) {
+    int f = d0 + j, p = m->frame_parent[f];
+    local_dtf(m->axis + 3 * f, q[f], dtl);
+    m4_mul(p >= 0 ? w->T + 16 * (p - d0) : I4, dtl, tmp);
+    m4_rigid_inv(w->T + 16 * j, Ti);
+    m4_mul(tmp, Ti, Wb + 16 * j);
+    memset(Cb + 16 * j, 0, 16 * sizeof(double));
+    int l = m->frame_mass[f];
+    if (l >= 0) {
+      mm_full(m->mm + 10 * l, M);
+      m4_mul(w->T + 16 * j, M, tmp);
+      m4_add_mul_bt(tmp, w->T + 16 * j, Cb + 16 * j);
+    }
+  }
+  for (int j = nd - 1; j >= 0; --j) {
+    int p = m->frame_parent[d0 + j];
+    if (p >= 0)
+      for (int k = 0; k < 16; ++k) Cb[16 * (p - d0) + k] += Cb[16 * j + k];
+  }
+  memset(H, 0, (size_t)nd * nd * sizeof(double));
+  for (int j = 0; j < nd; ++j) {
+    for (int a = j; a >= 0; a = m->frame_parent[d0 + a] >= 0 ? m->frame_parent[d0 + a] - d0 : -1) {
+      m4_mul(Wb + 16 * a, Cb + 16 * j, tmp);
+      double v = m4_frob(tmp, Wb + 16 * j);
+      H[(size_t)a * nd + j] = v;
+      H[(size_t)j * nd + a] = v;
+    }
+  }
+}
+
+void orc_inertia_matrix(const orc_model* m, const double* q, double* H, int n_threads) {
+  size_t* off = (size_t*)malloc((m->n_models + 1) * sizeof(size_t));
+  off[0] = 0;
+  for (int i = 0; i < m->n_models; ++i) off[i + 1] = off[i] + (size_t)model_nd(m, i) * model_nd(m, i);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int i = 0; i < m->n_models; ++i) {
+    int nd = model_nd(m, i);
+    eval_ws w;
+    ws_alloc(&w, nd);
+    double* Wb = (double*)malloc((size_t)(nd > 0 ? nd : 1) * 32 * sizeof(double));
+    inertia_matrix_model(m, i, q, &w, H + off[i], Wb, Wb + 16 * (size_t)(nd > 0 ? nd : 1));
+    free(Wb);
+    ws_free(&w);
+  }
+  free(off);
+}
+
+/* Dense Cholesky H = L L^T in place (lower triangle); 0 on success. */
+static int cholesky(double* A, int n) {
+  for (int j = 0; j < n; ++j) {
+    double s = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+    if (!(s > 0.0)) return -1;
+    double ljj = sqrt(s);
+    A[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+      A[(size_t)i * n + j] = t / ljj;
+    }
+  }
+  return 0;
+}
+/* x <- (L L^T)^{-1} x */
+static void chol_solve(const double* L, int n, double* x) {
+  for (int i = 0; i < n; ++i) {
+    double t = x[i];
+    for (int k = 0; k < i; ++k) t -= L[(size_t)i * n + k] * x[k];
+    x[i] = t / L[(size_t)i * n + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double t = x[i];
+    for (int k = i + 1; k < n; ++k) t -= L[(size_t)k * n + i] * x[k];
+    x[i] = t / L[(size_t)i * n + i];
+  }
+}
+
+/* ------------------------------------------------------------- L-BFGS -- */
+static double dotv(const double* a, const double* b, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+static int finitev(const double* a, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!isfinite(a[i])) return 0;
+  return 1;
+}
+
+/* v <- gamma * H0 v for the chosen initial inverse Hessian. */
+static void apply_H0(int mode, const double* P, const double* L, int nd, double gamma, double* v) {
+  if (mode == 2) {
+    chol_solve(L, nd, v);
+  } else {
+    for (int j = 0; j < nd; ++j) v[j] *= gamma * P[j];
+  }
+}
+
+/* One step of model i (K = 2): preconditioned L-BFGS (two-loop recursion,
+ * Liu & Nocedal) from the warm start 2 q_k - q_{k-1}, with a backtracking line
+ * search that requires decrease of E (Sec. 4); when the change of E is below
+ * the evaluation's own rounding level the sign of the directional derivative
+ * decides instead.  Local vectors have length nd; the objective routine uses
+ * global DOF indexing, so trial points live in full-length scratch copies. */
+static void step_model(const orc_model* m, int i, const orc_opts* o, const double* qkm1,
+                       const double* qk, const double* tau, double* qfull, double* gfull,
+                       double* q_out, orc_stats* st) {
+  const int d0 = m->model_dof[i], nd = model_nd(m, i), M = o->lbfgs_m > 0 ? o->lbfgs_m : 1;
+  int mode = o->precond;
+  orc_stats s = {0, 0, 0, 0, 0.0, 0.0};
+  if (nd == 0) {
+    s.flag = 1;
+    *st = s;
+    return;
+  }
+  eval_ws w;
+  ws_alloc(&w, nd);
+  double* buf = (double*)calloc((size_t)nd * (6 + 2 * M) + 3 * M, sizeof(double));
+  double *q = buf, *g = q + nd, *d = g + nd, *qt = d + nd, *gt = qt + nd, *P = gt + nd;
+  double *Sv = P + nd, *Yv = Sv + (size_t)M * nd, *rho = Yv + (size_t)M * nd, *alp = rho + M,
+         *gam = alp + M;
+  double* L = NULL;
+  char* desc = (char*)malloc(nd);
+
+  fk_model(m, i, qk, w.Tk, w.tl);
+  fk_model(m, i, qkm1, w.Tkm1, w.tl);
+  /* warm start: constant-velocity extrapolation */
+  for (int j = 0; j < nd; ++j) q[j] = 2.0 * qk[d0 + j] - qkm1[d0 + j];
+  for (int j = 0; j < nd; ++j) qfull[d0 + j] = q[j];
+  for (int j = 0; j < nd; ++j) P[j] = 1.0;
+  if (mode == 2) {
+    L = (double*)malloc(((size_t)nd * nd + 32 * (size_t)nd) * sizeof(double));
+    inertia_matrix_model(m, i, qfull, &w, L, L + (size_t)nd * nd, L + (size_t)nd * nd + 16 * nd);
+    if (cholesky(L, nd) != 0) mode = 1; /* not positive definite: fall back to the diagonal */
+  }
+  if (mode == 1) {
+    inertia_diag_model(m, i, qfull, &w, gfull, desc);
+    for (int j = 0; j < nd; ++j) {
+      double h = gfull[d0 + j];
+      P[j] = (h > 0.0 && isfinite(h)) ? 1.0 / h : 1.0;
+    }
+  }
+  double Sn;
+  double E = eval_model(m, i, o->dt, qfull, tau, &w, gfull, &Sn);
+  for (int j = 0; j < nd; ++j) g[j] = gfull[d0 + j];
+  s.evaluations = 1;
+  if (!isfinite(E) || !finitev(g, nd)) {
+    s.flag = 8;
+    s.energy = E;
+    s.grad_norm = NAN;
+    goto done;
+  }
+  double g0 = sqrt(dotv(g, g, nd)), gn = g0;
+  if (g0 == 0.0) {
+    s.flag = 1;
+    goto finish;
+  }
+  int head = 0, count = 0;
+  const double c1 = 1e-4, dlt = 0.1;
+  for (int it = 0; it < o->max_iter; ++it) {
+    /* two-loop recursion, newest pair first */
+    for (int j = 0; j < nd; ++j) d[j] = g[j];
+    for (int t = 0; t < count; ++t) {
+      int k = (head + count - 1 - t) % M;
+      alp[k] = rho[k] * dotv(Sv + (size_t)k * nd, d, nd);
+      for (int j = 0; j < nd; ++j) d[j] -= alp[k] * Yv[(size_t)k * nd + j];
+    }
+    double gamma = (count > 0 && mode != 2) ? gam[(head + count - 1) % M] : 1.0;
+    apply_H0(mode, P, L, nd, gamma, d);
+    for (int t = count - 1; t >= 0; --t) {
+      int k = (head + count - 1 - t) % M;
+      double b = rho[k] * dotv(Yv + (size_t)k * nd, d, nd);
+      for (int j = 0; j < nd; ++j) d[j] += (alp[k] - b) * Sv[(size_t)k * nd + j];
+    }
+    for (int j = 0; j < nd; ++j) d[j] = -d[j];
+    double gd = dotv(g, d, nd);
+    if (!(gd < 0.0)) { /* not a descent direction: drop the history */
+      count = 0;
+      for (int j = 0; j < nd; ++j) d[j] = g[j];
+      apply_H0(mode, P, L, nd, 1.0, d);
+      for (int j = 0; j < nd; ++j) d[j] = -d[j];
+      gd = dotv(g, d, nd);
+    }
+    /* backtracking line search */
+    double alpha = 1.0, Et = 0.0, St = 0.0;
+    int ok = 0;
+    for (int ls = 0; ls < o->max_ls; ++ls) {
+      for (int j = 0; j < nd; ++j) qt[j] = q[j] + alpha * d[j];
+      for (int j = 0; j < nd; ++j) qfull[d0 + j] = qt[j];
+      Et = eval_model(m, i, o->dt, qfull, tau, &w, gfull, &St);
+      for (int j = 0; j < nd; ++j) gt[j] = gfull[d0 + j];
+      s.evaluations++;
+      if (isfinite(Et) && finitev(gt, nd)) {
+        if (Et <= E + c1 * alpha * gd)
+          ok = 1;
+        else if (fabs(Et - E) <= 10.0 * o->eps_w * St) {
+          /* change of E within rounding: accept unless the slope shows overshoot */
+          double gtd = dotv(gt, d, nd);
+          if (gtd <= (2.0 * dlt - 1.0) * gd) ok = 1;
+        }
+      }
+      if (ok) break;
+      alpha *= 0.5;
+    }
+    if (!ok) {
+      s.flag = 2;
+      break;
+    }
+    /* curvature pair */
+    for (int j = 0; j < nd; ++j) qt[j] -= q[j]; /* s = accepted point - q */
+    double sy = 0.0, ss = 0.0, yy = 0.0, yPy = 0.0;
+    for (int j = 0; j < nd; ++j) {
+      double yj = gt[j] - g[j];
+      sy += qt[j] * yj;
+      ss += qt[j] * qt[j];
+      yy += yj * yj;
+      yPy += yj * P[j] * yj;
+    }
+    if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
+      int k;
+      if (count < M) {
+        k = (head + count) % M;
+        count++;
+      } else {
+        k = head;
+        head = (head + 1) % M;
+      }
+      for (int j = 0; j < nd; ++j) {
+        Sv[(size_t)k * nd + j] = qt[j];
+        Yv[(size_t)k * nd + j] = gt[j] - g[j];
+      }
+      rho[k] = 1.0 / sy;
+      gam[k] = sy / yPy;
+    }
+    for (int j = 0; j < nd; ++j) {
+      q[j] = qfull[d0 + j];
+      g[j] = gt[j];
+    }
+    E = Et;
+    s.iterations++;
+    gn = sqrt(dotv(g, g, nd));
+    if (gn <= o->tol * g0) {
+      s.flag = 1;
+      break;
+    }
+  }
+  if (s.flag == 0) s.flag = 4;
+finish:
+  s.grad_norm = gn;
+  s.energy = E;
+done:
+  for (int j = 0; j < nd; ++j) q_out[d0 + j] = q[j];
+  *st = s;
+  free(L);
+  free(desc);
+  free(buf);
+  ws_free(&w);
+}
+
+int orc_step(const orc_model* m, const orc_opts* o, const double* q_hist, const double* tau,
+             double* q_out, orc_stats* stats, int n_threads) {
+  if (o->order_K != 2) return -1;
+  const double* qkm1 = q_hist;
+  const double* qk = q_hist + m->n_dofs;
+  int nd = m->n_dofs > 0 ? m->n_dofs : 1;
+  int nt = n_threads > 0 ? n_threads : 1;
+  double* scratch = (double*)malloc((size_t)nt * 2 * nd * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  for (int i = 0; i < m->n_models; ++i) {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    double* qfull = scratch + (size_t)tid * 2 * nd;
+    double* gfull = qfull + nd;
+    step_model(m, i, o, qkm1, qk, tau, qfull, gfull, q_out, stats + i);
+  }
+  free(scratch);
+  return 0;
+}

@@ -1,0 +1,91 @@
+/*
+ * FP64 CPU oracle for position-based articulated dynamics (Pan & Manocha,
+ * "Time Integrating Articulated Body Dynamics Using Position-Based Collocation
+ * Methods").  TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark call it; the product path never does.
+ * It shares no code, header or table with the HIP library.
+ *
+ * Every routine is a plain, slow, sequential restatement of the paper:
+ *   - link poses by the sequential transform product of Alg. 1 (forward pass),
+ *   - the objective of Eq. EQ scaled by dt^2, with the body integral done
+ *     exactly through the per-link mass moment tensor (Eq. ATOM),
+ *   - its gradient by the literal 4x4 adjoint backward pass of Alg. 1,
+ *   - the quasi-Newton solve of Sec. 5 (L-BFGS with a backtracking line search
+ *     that enforces decrease, as the paper requires of the optimizer).
+ * All arithmetic is double precision.
+ */
+#ifndef ABD_ORACLE_H
+#define ABD_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_model orc_model;
+
+typedef struct {
+  double dt;
+  int order_K;     /* 2 = Eq. EQ; >2 = Eq. EQHOC (collocation) */
+  int lbfgs_m;     /* history length */
+  double tol;      /* stop when |g| <= tol*|g(q0)| */
+  int max_iter;
+  int max_ls;      /* line-search halvings before giving up */
+  double eps_w;    /* working-precision epsilon used by the noise test */
+  int precond;     /* initial inverse Hessian H0: 0 gamma*I, 1 gamma*diag(H_q)^-1,
+                      2 H_q^-1 (joint-space inertia at the warm start) */
+} orc_opts;
+
+typedef struct {
+  int iterations;
+  int evaluations;
+  int flag;        /* 1 converged, 2 line-search floor, 4 max-iter, 8 non-finite */
+  int pad;
+  double grad_norm;
+  double energy;
+} orc_stats;
+
+orc_model* orc_create(int n_models, const int* link_offset, const int* parent,
+                      const int* dofs_per_link, const double* axis, const double* offset,
+                      const double* mass_moment, const double* gravity);
+void orc_free(orc_model* m);
+
+/* World poses A = [R|t] (3x4 row-major, 12 doubles) of every link at q. */
+void orc_poses(const orc_model* m, const double* q, double* poses, int n_threads);
+
+/* Objective (dt^2-scaled Eq. EQ, D-form) and gradient (Alg. 1) for every model.
+ * q_hist = [q_{k-1} ; q_k] (2*n_dofs).  tau may be NULL.  grad may be NULL.
+ * S (may be NULL) receives sum_l |e_l| (the noise scale of the line search). */
+void orc_objective_grad(const orc_model* m, double dt, const double* q, const double* q_hist,
+                        const double* tau, double* E, double* grad, double* S, int n_threads);
+
+/* Objective of the same step assembled from the pairwise integrals of
+ * Appendix A: 1/2 I(q,q) - 2 I(q,q_k) + I(q,q_{k-1}) + potential - dt^2 tau.q.
+ * Differs from orc_objective_grad's E by a q-independent constant. */
+void orc_objective_Iform(const orc_model* m, double dt, const double* q, const double* q_hist,
+                         const double* tau, double* E, int n_threads);
+
+/* Eq. ATOM and Alg. 1: I(q_a,q_b) per model and dI/dq_b (n_dofs). */
+void orc_alg1_I(const orc_model* m, const double* q_a, const double* q_b, double* I,
+                double* dI_dqb, int n_threads);
+
+/* Diagonal of the joint-space inertia sum_l tr(dA_l/dq_n M_l dA_l/dq_n^T) at q. */
+void orc_inertia_diag(const orc_model* m, const double* q, double* h, int n_threads);
+
+/* Joint-space inertia H_ij = sum_l tr(dA_l/dq_i M_l dA_l/dq_j^T) at q, one dense
+ * row-major block per model, packed model after model (sum of n_i^2 doubles). */
+void orc_inertia_matrix(const orc_model* m, const double* q, double* H, int n_threads);
+
+/* One time step for every model: q_out = argmin of the step objective,
+ * reached by preconditioned L-BFGS from the warm start 2 q_k - q_{k-1}. */
+int orc_step(const orc_model* m, const orc_opts* o, const double* q_hist, const double* tau,
+             double* q_out, orc_stats* stats, int n_threads);
+
+/* Reported total energy at step k: (1/2dt^2) sum tr(dA M dA^T) + V(q_k),
+ * dA = A(q_k) - A(q_{k-1}). */
+void orc_energy_report(const orc_model* m, double dt, const double* q_prev, const double* q_curr,
+                       double* H, int n_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

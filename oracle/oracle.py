@@ -1,0 +1,225 @@
+"""ctypes front end of the FP64 CPU oracle (abd_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark.  The product path (the HIP library and its
+Python binding) never imports this module.
+
+Besides marshalling, this module holds two plain numerical helpers that use
+the C routines as their only source of objective values and gradients:
+``newton_polish`` (Newton iterations with a central-difference Hessian of the
+Alg. 1 gradient, used to pin the L-BFGS result to the exact minimizer) and
+``rollout`` (a loop of steps).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "abd_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+FLAG_CONVERGED, FLAG_LS_FLOOR, FLAG_MAX_ITER, FLAG_NONFINITE = 1, 2, 4, 8
+EPS64 = 2.0 ** -53
+EPS32 = 2.0 ** -24
+
+
+class OrcOpts(C.Structure):
+    _fields_ = [("dt", C.c_double), ("order_K", C.c_int), ("lbfgs_m", C.c_int),
+                ("tol", C.c_double), ("max_iter", C.c_int), ("max_ls", C.c_int),
+                ("eps_w", C.c_double), ("precond", C.c_int)]
+
+
+class OrcStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("evaluations", C.c_int), ("flag", C.c_int),
+                ("pad", C.c_int), ("grad_norm", C.c_double), ("energy", C.c_double)]
+
+
+STATS_DTYPE = np.dtype([("iterations", np.int32), ("evaluations", np.int32), ("flag", np.int32),
+                        ("pad", np.int32), ("grad_norm", np.float64), ("energy", np.float64)])
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, IEEE arithmetic, OpenMP over models)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
+        _lib.orc_create.restype = C.c_void_p
+        _lib.orc_create.argtypes = [C.c_int, ip, ip, ip, dp, dp, dp, dp]
+        _lib.orc_free.argtypes = [C.c_void_p]
+        _lib.orc_poses.argtypes = [C.c_void_p, dp, dp, C.c_int]
+        _lib.orc_objective_grad.argtypes = [C.c_void_p, C.c_double, dp, dp, dp, dp, dp, dp, C.c_int]
+        _lib.orc_objective_Iform.argtypes = [C.c_void_p, C.c_double, dp, dp, dp, dp, C.c_int]
+        _lib.orc_alg1_I.argtypes = [C.c_void_p, dp, dp, dp, dp, C.c_int]
+        _lib.orc_inertia_diag.argtypes = [C.c_void_p, dp, dp, C.c_int]
+        _lib.orc_inertia_matrix.argtypes = [C.c_void_p, dp, dp, C.c_int]
+        _lib.orc_step.argtypes = [C.c_void_p, C.POINTER(OrcOpts), dp, dp, dp, C.c_void_p, C.c_int]
+        _lib.orc_step.restype = C.c_int
+        _lib.orc_energy_report.argtypes = [C.c_void_p, C.c_double, dp, dp, dp, C.c_int]
+    return _lib
+
+
+def _d(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _i(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+class Oracle:
+    """FP64 oracle bound to one batch of models (a ``workloads.ModelDesc``)."""
+
+    def __init__(self, desc, threads: Optional[int] = None):
+        self.desc = desc
+        self.threads = threads or default_threads()
+        self._keep = [np.ascontiguousarray(desc.link_offset, dtype=np.int32),
+                      np.ascontiguousarray(desc.parent, dtype=np.int32),
+                      np.ascontiguousarray(desc.dofs_per_link, dtype=np.int32),
+                      _f64(desc.axis), _f64(desc.offset), _f64(desc.mass_moment),
+                      _f64(desc.gravity)]
+        k = self._keep
+        self._h = lib().orc_create(desc.n_models, _i(k[0]), _i(k[1]), _i(k[2]),
+                                   _d(k[3]), _d(k[4]), _d(k[5]), _d(k[6]))
+        self.n_models, self.n_dofs, self.n_links = desc.n_models, desc.n_dofs, desc.n_links
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_free(h)
+            self._h = None
+
+    # ---------------------------------------------------------------- queries
+    def poses(self, q) -> np.ndarray:
+        out = np.zeros((self.n_links, 3, 4))
+        lib().orc_poses(self._h, _d(_f64(q)), _d(out), self.threads)
+        return out
+
+    def objective_grad(self, q, q_prev, q_curr, dt, tau=None):
+        E = np.zeros(self.n_models)
+        g = np.zeros(self.n_dofs)
+        S = np.zeros(self.n_models)
+        hist = _f64(np.concatenate([q_prev, q_curr]))
+        tau = None if tau is None else _f64(tau)
+        lib().orc_objective_grad(self._h, dt, _d(_f64(q)), _d(hist), _d(tau), _d(E), _d(g), _d(S),
+                                 self.threads)
+        return E, g, S
+
+    def objective_Iform(self, q, q_prev, q_curr, dt, tau=None):
+        E = np.zeros(self.n_models)
+        hist = _f64(np.concatenate([q_prev, q_curr]))
+        tau = None if tau is None else _f64(tau)
+        lib().orc_objective_Iform(self._h, dt, _d(_f64(q)), _d(hist), _d(tau), _d(E), self.threads)
+        return E
+
+    def alg1_I(self, q_a, q_b):
+        I = np.zeros(self.n_models)
+        g = np.zeros(self.n_dofs)
+        lib().orc_alg1_I(self._h, _d(_f64(q_a)), _d(_f64(q_b)), _d(I), _d(g), self.threads)
+        return I, g
+
+    def inertia_diag(self, q) -> np.ndarray:
+        h = np.zeros(self.n_dofs)
+        lib().orc_inertia_diag(self._h, _d(_f64(q)), _d(h), self.threads)
+        return h
+
+    def inertia_matrix(self, q):
+        """List of dense per-model joint-space inertia matrices at q."""
+        nd = np.diff(self.desc.dof_offset).astype(np.int64)
+        buf = np.zeros(int(np.sum(nd * nd)))
+        lib().orc_inertia_matrix(self._h, _d(_f64(q)), _d(buf), self.threads)
+        out, o = [], 0
+        for n in nd:
+            out.append(buf[o:o + n * n].reshape(n, n))
+            o += n * n
+        return out
+
+    def energy_report(self, q_prev, q_curr, dt) -> np.ndarray:
+        H = np.zeros(self.n_models)
+        lib().orc_energy_report(self._h, dt, _d(_f64(q_prev)), _d(_f64(q_curr)), _d(H), self.threads)
+        return H
+
+    # ------------------------------------------------------------------- step
+    def step(self, q_prev, q_curr, dt, tau=None, lbfgs_m=5, tol=1e-8, max_iter=500, max_ls=40,
+             eps_w=EPS64, order_K=2, precond=2):
+        opts = OrcOpts(dt, order_K, lbfgs_m, tol, max_iter, max_ls, eps_w, precond)
+        hist = _f64(np.concatenate([q_prev, q_curr]))
+        out = np.zeros(self.n_dofs)
+        stats = np.zeros(self.n_models, dtype=STATS_DTYPE)
+        tau = None if tau is None else _f64(tau)
+        rc = lib().orc_step(self._h, C.byref(opts), _d(hist), _d(tau), _d(out),
+                            stats.ctypes.data_as(C.c_void_p), self.threads)
+        if rc != 0:
+            raise ValueError(f"orc_step failed ({rc})")
+        return out, stats
+
+    def rollout(self, q0, steps, dt, q_init_prev=None, torque=None, **kw):
+        """States q_0..q_steps (zero initial velocity unless q_init_prev is given)."""
+        qs = [np.array(q0, dtype=np.float64)]
+        prev = qs[0].copy() if q_init_prev is None else np.array(q_init_prev, dtype=np.float64)
+        stats = []
+        for k in range(steps):
+            tau = None if torque is None else torque[k]
+            nxt, st = self.step(prev, qs[-1], dt, tau=tau, **kw)
+            prev = qs[-1]
+            qs.append(nxt)
+            stats.append(st)
+        return np.stack(qs), stats
+
+    # ---------------------------------------------------------------- helpers
+    def newton_polish(self, q, q_prev, q_curr, dt, tau=None, iters=8, h=1e-6):
+        """Newton on grad E = 0 with a central-difference Hessian of the Alg. 1
+        gradient, model by model.  Returns the polished q and the final |g| per model."""
+        q = _f64(q).copy()
+        do = self.desc.dof_offset
+        gnorm = np.zeros(self.n_models)
+        for _ in range(iters):
+            E, g, _ = self.objective_grad(q, q_prev, q_curr, dt, tau)
+            nmax = int(np.max(np.diff(do))) if self.n_models else 0
+            Hs = [np.zeros((do[i + 1] - do[i],) * 2) for i in range(self.n_models)]
+            for j in range(nmax):
+                qp, qm = q.copy(), q.copy()
+                idx = [do[i] + j for i in range(self.n_models) if do[i] + j < do[i + 1]]
+                qp[idx] += h
+                qm[idx] -= h
+                _, gp, _ = self.objective_grad(qp, q_prev, q_curr, dt, tau)
+                _, gm, _ = self.objective_grad(qm, q_prev, q_curr, dt, tau)
+                col = (gp - gm) / (2 * h)
+                for i in range(self.n_models):
+                    if do[i] + j < do[i + 1]:
+                        Hs[i][:, j] = col[do[i]:do[i + 1]]
+            for i in range(self.n_models):
+                sl = slice(do[i], do[i + 1])
+                if do[i + 1] == do[i]:
+                    continue
+                H = 0.5 * (Hs[i] + Hs[i].T)
+                q[sl] -= np.linalg.solve(H, g[sl])
+        _, g, _ = self.objective_grad(q, q_prev, q_curr, dt, tau)
+        for i in range(self.n_models):
+            gnorm[i] = np.linalg.norm(g[do[i]:do[i + 1]])
+        return q, gnorm
