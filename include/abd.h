@@ -1,0 +1,140 @@
+/*
+ * abd.h -- C ABI of the MI355X (gfx950) library for position-based articulated
+ * dynamics (Pan & Manocha, "Time Integrating Articulated Body Dynamics Using
+ * Position-Based Collocation Methods").
+ *
+ * One time step of a batch of articulated models solves, per model,
+ *     q_{k+1} = argmin_q  E(q)                                  (Sec. 4, Eq. EQ)
+ *     E(q) = sum_l 1/2 tr(D_l M_l D_l^T) - dt^2 sum_l g^T A_l(q) M_l e4 - dt^2 tau.q
+ *     D_l  = A_l(q) - 2 A_l(q_k) + A_l(q_{k-1})
+ * i.e. dt^2 times the paper's energy: the kinetic term of the second-order
+ * position-based discretisation integrated exactly over each body through its
+ * mass moment tensor M_l = int rho (p;1)(p;1)^T dp (Eq. ATOM), plus gravity and
+ * an optional generalized joint force tau.  A_l = [R_l | t_l] is the world pose
+ * of link l (forward kinematics, Alg. 1 forward pass).  The minimizer satisfies
+ * the stationarity condition Eq. PBAD.  The solver is a quasi-Newton method
+ * (L-BFGS, Sec. 5) whose gradient is the adjoint backward pass of Alg. 1.
+ *
+ * Conventions common to every call
+ * - All pointers passed to abd_step / abd_objective_grad are DEVICE pointers on
+ *   the device the model was created on; the caller owns them.  Work is enqueued
+ *   on `stream` (a hipStream_t; NULL = the default stream) and the call returns
+ *   after enqueueing; results are valid once the stream reaches that point.
+ * - DOF vectors are float64 [n_dofs] in the model's DOF order (link-major, the
+ *   DOFs of link l in the order of its axes).
+ * - Return value: ABD_OK, or a negative code; abd_last_error() then describes it.
+ *   Argument errors are detected on the host before anything is enqueued.
+ *   Per-model numerical outcomes are reported in abd_step_stats.flag, never in
+ *   the return code.
+ * - Concurrent calls on one model from several host threads are not supported:
+ *   a model owns per-step scratch memory.
+ */
+#ifndef ABD_H
+#define ABD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ABD_OK 0
+#define ABD_EINVAL (-1)   /* invalid argument */
+#define ABD_ENOMEM (-2)   /* device allocation failed */
+#define ABD_EDEVICE (-3)  /* HIP runtime error */
+#define ABD_ENOTSUP (-4)  /* valid input that this build does not handle */
+
+#define ABD_FP64 0        /* every operation in double precision */
+#define ABD_MIXED 1       /* kinematics and energy terms in float32 until the
+                             line search reaches float32 rounding, then double */
+
+#define ABD_PRECOND_IDENTITY 0 /* L-BFGS initial inverse Hessian gamma*I */
+#define ABD_PRECOND_INERTIA 2  /* initial inverse Hessian = inverse joint-space
+                                  inertia at the warm start */
+
+/* per-model outcome flags */
+#define ABD_FLAG_CONVERGED 1   /* |g| <= tol * |g(q0)| */
+#define ABD_FLAG_LS_FLOOR 2    /* no step accepted by the line search */
+#define ABD_FLAG_MAX_ITER 4    /* max_iter iterations done */
+#define ABD_FLAG_NONFINITE 8   /* objective or gradient not finite at the warm start */
+
+typedef struct abd_model abd_model;
+
+/* Host-side description of a batch of models (copied by abd_create_model). */
+typedef struct {
+  int n_models;
+  const int* link_offset;     /* [n_models+1], link_offset[0]=0; links of model i are
+                                 link_offset[i] .. link_offset[i+1]-1 */
+  const int* parent;          /* [n_links] parent link index within the model, -1 =
+                                 fixed world frame; a parent precedes its children */
+  const int* dofs_per_link;   /* [n_links] 1..3 consecutive hinges per joint */
+  const double* axis;         /* [3*n_dofs] unit hinge axis of each DOF, expressed in the
+                                 frame it rotates (link-major DOF order) */
+  const double* offset;       /* [3*n_links] joint origin in the parent link frame */
+  const double* mass_moment;  /* [10*n_links] upper triangle (row-major) of the symmetric
+                                 positive semi-definite 4x4 M_l with M_l[3][3] = mass > 0 */
+  double gravity[3];          /* gravitational acceleration (world frame) */
+} abd_model_desc;
+
+typedef struct {
+  double dt;         /* time step > 0 */
+  int order_K;       /* collocation order; this build: 2 */
+  int lbfgs_m;       /* L-BFGS history length, 1..10 */
+  double tol;        /* stop when |grad| <= tol * |grad at the warm start| */
+  int max_iter;      /* L-BFGS iterations per step, >= 0 */
+  int max_ls;        /* line-search halvings per iteration, 1..60 */
+  int precision;     /* ABD_FP64 or ABD_MIXED */
+  int precond;       /* ABD_PRECOND_IDENTITY or ABD_PRECOND_INERTIA */
+} abd_step_opts;
+
+typedef struct {
+  int iterations;    /* accepted L-BFGS iterations */
+  int evaluations;   /* objective+gradient evaluations (incl. the warm start) */
+  int flag;          /* ABD_FLAG_* */
+  int f32_iterations;/* iterations whose evaluations ran in float32 (ABD_MIXED) */
+  double grad_norm;  /* |grad| at the returned q */
+  double energy;     /* E at the returned q */
+} abd_step_stats;
+
+/* Validate a description and upload it to the current HIP device.  Checks
+ * topology, finite values, unit axes, positive mass and positive semi-definite
+ * moment tensors (ABD_EINVAL).  Synchronous.  *out receives the handle. */
+int abd_create_model(const abd_model_desc* desc, abd_model** out);
+
+/* Release the model's device memory (synchronizes the device first). */
+void abd_destroy_model(abd_model* model);
+
+/* Sizes of a created model (any pointer may be NULL). */
+int abd_model_info(const abd_model* model, int* n_models, int* n_links, int* n_dofs);
+
+/* One time step for every model (Sec. 4 and 5): warm start 2 q_k - q_{k-1},
+ * then preconditioned L-BFGS with a backtracking line search on E.
+ *   q_hist : [2*n_dofs] = q_{k-1} followed by q_k
+ *   tau    : [n_dofs] generalized joint forces held over the step, or NULL
+ *   q_out  : [n_dofs] receives q_{k+1}; must not overlap q_hist
+ *   stats  : [n_models] per-model outcome, or NULL */
+int abd_step(abd_model* model, const abd_step_opts* opts, const double* q_hist,
+             const double* tau, double* q_out, abd_step_stats* stats, void* stream);
+
+/* Objective and gradient without optimization (Eq. EQ scaled by dt^2; gradient by
+ * the adjoint backward pass of Alg. 1).
+ *   q      : [n_dofs] configuration to evaluate
+ *   q_hist : [2*n_dofs] = q_{k-1} followed by q_k
+ *   tau    : [n_dofs] or NULL
+ *   E      : [n_models] objective per model
+ *   grad   : [n_dofs] gradient, or NULL
+ * opts->precision selects float64 or float32 kinematics; other fields but dt
+ * are ignored. */
+int abd_objective_grad(abd_model* model, const abd_step_opts* opts, const double* q,
+                       const double* q_hist, const double* tau, double* E, double* grad,
+                       void* stream);
+
+/* World poses [R|t] (3x4 row-major, 12 doubles per link) of every link at q
+ * (forward kinematics of Alg. 1).  poses: device [12*n_links]. */
+int abd_poses(abd_model* model, const double* q, double* poses, void* stream);
+
+/* Text of the last error raised on the calling host thread ("" if none). */
+const char* abd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -657,6 +657,10 @@ static void step_model(const orc_model* m, int i, const orc_opts* o, const doubl
       apply_H0(mode, P, L, nd, 1.0, d);
       for (int j = 0; j < nd; ++j) d[j] = -d[j];
       gd = dotv(g, d, nd);
+      if (!(gd < 0.0)) { /* H0 not positive definite along g: give up */
+        s.flag = 2;
+        break;
+      }
     }
     /* backtracking line search */
     double alpha = 1.0, Et = 0.0, St = 0.0;

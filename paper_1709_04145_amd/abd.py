@@ -1,0 +1,221 @@
+"""Python binding of the C ABI in include/abd.h (ctypes; argument marshalling only).
+
+Every step of the computation runs in the HIP library ``libabd.so`` built from
+``csrc/abd.hip``.  PyTorch is used for device memory and streams.  There is no
+fallback: if the library is missing, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libabd.so")
+
+ABD_OK, ABD_EINVAL, ABD_ENOMEM, ABD_EDEVICE, ABD_ENOTSUP = 0, -1, -2, -3, -4
+FP64, MIXED = 0, 1
+PRECOND_IDENTITY, PRECOND_INERTIA = 0, 2
+FLAG_CONVERGED, FLAG_LS_FLOOR, FLAG_MAX_ITER, FLAG_NONFINITE = 1, 2, 4, 8
+
+
+class ModelDescC(C.Structure):
+    _fields_ = [("n_models", C.c_int),
+                ("link_offset", C.POINTER(C.c_int)),
+                ("parent", C.POINTER(C.c_int)),
+                ("dofs_per_link", C.POINTER(C.c_int)),
+                ("axis", C.POINTER(C.c_double)),
+                ("offset", C.POINTER(C.c_double)),
+                ("mass_moment", C.POINTER(C.c_double)),
+                ("gravity", C.c_double * 3)]
+
+
+class StepOptsC(C.Structure):
+    _fields_ = [("dt", C.c_double), ("order_K", C.c_int), ("lbfgs_m", C.c_int),
+                ("tol", C.c_double), ("max_iter", C.c_int), ("max_ls", C.c_int),
+                ("precision", C.c_int), ("precond", C.c_int)]
+
+
+STATS_DTYPE = np.dtype([("iterations", np.int32), ("evaluations", np.int32), ("flag", np.int32),
+                        ("f32_iterations", np.int32), ("grad_norm", np.float64),
+                        ("energy", np.float64)])
+assert STATS_DTYPE.itemsize == 32
+
+# every exported entry point and its prototype
+_PROTOS = {
+    "abd_create_model": (C.c_int, [C.POINTER(ModelDescC), C.POINTER(C.c_void_p)]),
+    "abd_destroy_model": (None, [C.c_void_p]),
+    "abd_model_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "abd_step": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
+                           C.c_void_p, C.c_void_p]),
+    "abd_objective_grad": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "abd_poses": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "abd_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libabd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(there is no non-HIP fallback)")
+    lib = C.CDLL(path)
+    for name, (res, args) in _PROTOS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class AbdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"abd error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int):
+    if rc != ABD_OK:
+        raise AbdError(rc, load().abd_last_error().decode())
+
+
+@dataclass
+class StepOptions:
+    dt: float
+    order_K: int = 2
+    lbfgs_m: int = 5
+    tol: float = 1e-8
+    max_iter: int = 500
+    max_ls: int = 40
+    precision: int = FP64
+    precond: int = PRECOND_INERTIA
+
+    def c(self) -> StepOptsC:
+        return StepOptsC(self.dt, self.order_K, self.lbfgs_m, self.tol, self.max_iter, self.max_ls,
+                         self.precision, self.precond)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, n, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, has {t.numel()}")
+    return t
+
+
+class Model:
+    """A batch of articulated models resident on the current HIP device."""
+
+    def __init__(self, desc):
+        lib = load()
+        self.desc = desc
+        self._keep = [np.ascontiguousarray(desc.link_offset, dtype=np.int32),
+                      np.ascontiguousarray(desc.parent, dtype=np.int32),
+                      np.ascontiguousarray(desc.dofs_per_link, dtype=np.int32),
+                      np.ascontiguousarray(desc.axis, dtype=np.float64),
+                      np.ascontiguousarray(desc.offset, dtype=np.float64),
+                      np.ascontiguousarray(desc.mass_moment, dtype=np.float64)]
+        k = self._keep
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int))
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        cd = ModelDescC(int(desc.n_models), ip(k[0]), ip(k[1]), ip(k[2]), dp(k[3]), dp(k[4]), dp(k[5]),
+                        (C.c_double * 3)(*[float(x) for x in desc.gravity]))
+        h = C.c_void_p()
+        _check(lib.abd_create_model(C.byref(cd), C.byref(h)))
+        self._h = h
+        nm, nl, nd = C.c_int(), C.c_int(), C.c_int()
+        _check(lib.abd_model_info(h, C.byref(nm), C.byref(nl), C.byref(nd)))
+        self.n_models, self.n_links, self.n_dofs = nm.value, nl.value, nd.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().abd_destroy_model(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------- calls
+    def step(self, q_hist: torch.Tensor, q_out: torch.Tensor, opts: StepOptions,
+             tau: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None, stream=None):
+        """Enqueue one time step.  q_hist = [q_{k-1}; q_k] (2*n_dofs contiguous)."""
+        _dev_f64(q_hist, 2 * self.n_dofs, "q_hist")
+        _dev_f64(q_out, self.n_dofs, "q_out")
+        if tau is not None:
+            _dev_f64(tau, self.n_dofs, "tau")
+        if stats is not None and (not stats.is_cuda or stats.numel() * stats.element_size() < 32 * self.n_models):
+            raise ValueError("stats must be a CUDA buffer of 32 bytes per model")
+        o = opts.c()
+        _check(load().abd_step(self._h, C.byref(o), _ptr(q_hist), _ptr(tau), _ptr(q_out), _ptr(stats),
+                               _stream(stream)))
+
+    def new_stats(self) -> torch.Tensor:
+        return torch.zeros((max(1, self.n_models), 4), dtype=torch.float64, device="cuda")
+
+    @staticmethod
+    def read_stats(stats: torch.Tensor, n_models: int) -> np.ndarray:
+        raw = stats.detach().cpu().numpy().reshape(-1).view(np.uint8)[:32 * n_models]
+        return raw.view(STATS_DTYPE).copy()
+
+    def objective_grad(self, q, q_hist, dt, tau=None, precision=FP64, stream=None):
+        _dev_f64(q, self.n_dofs, "q")
+        _dev_f64(q_hist, 2 * self.n_dofs, "q_hist")
+        if tau is not None:
+            _dev_f64(tau, self.n_dofs, "tau")
+        E = torch.zeros(max(1, self.n_models), dtype=torch.float64, device="cuda")
+        g = torch.zeros(max(1, self.n_dofs), dtype=torch.float64, device="cuda")
+        o = StepOptions(dt=dt, precision=precision).c()
+        _check(load().abd_objective_grad(self._h, C.byref(o), _ptr(q), _ptr(q_hist), _ptr(tau), _ptr(E),
+                                         _ptr(g), _stream(stream)))
+        return E[:self.n_models], g[:self.n_dofs]
+
+    def poses(self, q, stream=None):
+        _dev_f64(q, self.n_dofs, "q")
+        out = torch.zeros((max(1, self.n_links), 3, 4), dtype=torch.float64, device="cuda")
+        _check(load().abd_poses(self._h, _ptr(q), _ptr(out), _stream(stream)))
+        return out[:self.n_links]
+
+    def rollout(self, q0: torch.Tensor, steps: int, opts: StepOptions, q_init_prev=None, torque=None,
+                collect_stats: bool = True):
+        """States [steps+1, n_dofs] from q0 (zero initial velocity unless q_init_prev is given).
+
+        The trajectory buffer holds [q_{-1}, q_0, q_1, ...] so that every step reads
+        its history [q_{k-1}; q_k] in place and writes q_{k+1} after it."""
+        n = self.n_dofs
+        buf = torch.empty((steps + 2, n), dtype=torch.float64, device="cuda")
+        buf[1] = q0
+        buf[0] = q0 if q_init_prev is None else q_init_prev
+        stats = []
+        for k in range(steps):
+            st = self.new_stats() if collect_stats else None
+            tau = None if torque is None else torque[k]
+            self.step(buf[k:k + 2].reshape(-1), buf[k + 2], opts, tau=tau, stats=st)
+            if collect_stats:
+                stats.append(st)
+        out = buf[1:]
+        if collect_stats:
+            torch.cuda.synchronize()
+            stats = [self.read_stats(s, self.n_models) for s in stats]
+        return out, stats

@@ -1,0 +1,1097 @@
+// abd.hip -- MI355X (gfx950) implementation of the C ABI in include/abd.h.
+//
+// Position-based articulated dynamics (Pan & Manocha): every time step solves
+// q_{k+1} = argmin E(q) (Sec. 4, Eq. EQ, scaled by dt^2) with a quasi-Newton
+// method (Sec. 5).  Per evaluation the hot path is
+//   1. forward kinematics A_l = A_parent T_l(q_l)      (Alg. 1 forward pass)
+//   2. per-link energy terms and the seed dE/dA_l      (Eq. EQ with Eq. ATOM)
+//   3. the adjoint backward pass giving dE/dq          (Alg. 1 backward pass)
+// and per iteration the two-loop L-BFGS direction and a backtracking line search.
+//
+// Layout on the GPU.  A model is a serial chain of elementary hinge "frames"
+// (one per DOF; a ball joint is three consecutive hinges with massless
+// intermediate frames).  One wavefront owns one model and lane j owns frame j:
+//   * FK is an inclusive prefix scan of 3x4 rigid transforms over the lanes
+//     (DPP row shifts + row broadcasts: 6 levels for 64 lanes);
+//   * the adjoint backward pass is evaluated in the world frame: with
+//     G_l = dE/dA_l, k_l = sum_c R_l[:,c] x G_l[:,c] + t_l x G_l[:,3] and
+//     f_l = G_l[:,3], the derivative is g_n = w_n . (K_n - p_n x F_n) where
+//     (K_n, F_n) are suffix sums over the frames below n, w_n the world hinge
+//     axis and p_n the world joint point.  This is the same quantity as the
+//     4x4 body-frame recursion of Alg. 1 (A <- (A + dI/dT) t^T), rewritten as
+//     a plain sum so that it becomes a float64 suffix scan;
+//   * L-BFGS dot products are float64 wave reductions.
+// The initial inverse Hessian of L-BFGS is the inverse joint-space inertia at
+// the warm start, applied in O(n) by the two sweeps of the articulated-body
+// recursion.  Those sweeps are sequential along the chain, so they run with
+// one lane per model: G models share one workgroup, and wave 0 sweeps all G of
+// them at once from per-frame tables held in LDS.
+//
+// No MFMA: nothing on this path is a dense contraction.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/abd.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(ABD_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kWave = 64;
+constexpr int kMaxFrames = 64;  // frames (DOFs) per model handled by one wavefront
+constexpr int kG = 8;           // models per workgroup in the step kernel
+constexpr int kMaxHist = 10;    // longest L-BFGS history
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// ------------------------------------------------------------------ DPP --
+// update_dpp keeps `old` in lanes whose source is out of the row (bound_ctrl
+// off) or whose row is masked off.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp(float old, float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp(double old, double v) {
+  const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(x & 0xffffffffll), CTRL,
+                                             ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double readlane(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Keep a wave-uniform double in scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Inclusive prefix sum over the 64 lanes (row shifts 1,2,4,8, then the
+// row-15 and row-31 broadcasts).  Every lane ends with its inclusive prefix.
+__device__ __forceinline__ double wave_prefix_sum(double v) {
+  v += dpp<0x111, 0xF>(0.0, v);
+  v += dpp<0x112, 0xF>(0.0, v);
+  v += dpp<0x114, 0xF>(0.0, v);
+  v += dpp<0x118, 0xF>(0.0, v);
+  v += dpp<0x142, 0xA>(0.0, v);
+  v += dpp<0x143, 0xC>(0.0, v);
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) { return readlane(wave_prefix_sum(v), 63); }
+
+// Two independent sums in one pass (interleaved for latency hiding).
+__device__ __forceinline__ void wave_sum2(double& a, double& b) {
+  a += dpp<0x111, 0xF>(0.0, a); b += dpp<0x111, 0xF>(0.0, b);
+  a += dpp<0x112, 0xF>(0.0, a); b += dpp<0x112, 0xF>(0.0, b);
+  a += dpp<0x114, 0xF>(0.0, a); b += dpp<0x114, 0xF>(0.0, b);
+  a += dpp<0x118, 0xF>(0.0, a); b += dpp<0x118, 0xF>(0.0, b);
+  a += dpp<0x142, 0xA>(0.0, a); b += dpp<0x142, 0xA>(0.0, b);
+  a += dpp<0x143, 0xC>(0.0, a); b += dpp<0x143, 0xC>(0.0, b);
+  a = readlane(a, 63);
+  b = readlane(b, 63);
+}
+
+// ------------------------------------------------------------ transforms --
+// 3x4 rigid transform [R|t], row-major: m[4r+c].
+template <typename R>
+struct Xf {
+  R m[12];
+};
+
+template <typename R>
+__device__ __forceinline__ Xf<R> compose(const Xf<R>& a, const Xf<R>& b) {
+  Xf<R> c;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      c.m[4 * r + k] = a.m[4 * r] * b.m[k] + a.m[4 * r + 1] * b.m[4 + k] + a.m[4 * r + 2] * b.m[8 + k];
+    c.m[4 * r + 3] = a.m[4 * r] * b.m[3] + a.m[4 * r + 1] * b.m[7] + a.m[4 * r + 2] * b.m[11] + a.m[4 * r + 3];
+  }
+  return c;
+}
+
+template <typename R, int CTRL, int ROW_MASK>
+__device__ __forceinline__ Xf<R> dpp_xf(const Xf<R>& x) {
+  Xf<R> y;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const R id = (k == 0 || k == 5 || k == 10) ? R(1) : R(0);
+    y.m[k] = dpp<CTRL, ROW_MASK>(id, x.m[k]);
+  }
+  return y;
+}
+
+// A_j = T_0 T_1 ... T_j over the lanes (Alg. 1 forward pass as a scan; the
+// identity fills lanes whose source is outside the wave).
+template <typename R>
+__device__ __forceinline__ Xf<R> wave_prefix_compose(Xf<R> x) {
+  x = compose(dpp_xf<R, 0x111, 0xF>(x), x);
+  x = compose(dpp_xf<R, 0x112, 0xF>(x), x);
+  x = compose(dpp_xf<R, 0x114, 0xF>(x), x);
+  x = compose(dpp_xf<R, 0x118, 0xF>(x), x);
+  x = compose(dpp_xf<R, 0x142, 0xA>(x), x);
+  x = compose(dpp_xf<R, 0x143, 0xC>(x), x);
+  return x;
+}
+
+// sin and cos of half the joint angle.  float32: reduce modulo 2 pi in float64
+// first so that large angles keep their accuracy.
+__device__ __forceinline__ void half_sincos(double q, double& s, double& c) { sincos(0.5 * q, &s, &c); }
+__device__ __forceinline__ void half_sincos(double q, float& s, float& c) {
+  const double r = q - kTwoPi * rint(q * (1.0 / kTwoPi));
+  sincosf((float)(0.5 * r), &s, &c);
+}
+
+// Local transform of a hinge frame: [Rot(a, q) | o], Rot = cI + s[a]x + (1-c) a a^T
+// with s = 2 sh ch, 1-c = 2 sh^2 (half-angle form keeps 1-c accurate).
+template <typename R>
+__device__ __forceinline__ Xf<R> hinge_transform(const R a[3], const R o[3], double q) {
+  R sh, ch;
+  half_sincos(q, sh, ch);
+  const R s = R(2) * sh * ch, omc = R(2) * sh * sh, c = R(1) - omc;
+  Xf<R> T;
+  T.m[0] = c + omc * a[0] * a[0];
+  T.m[1] = omc * a[0] * a[1] - s * a[2];
+  T.m[2] = omc * a[0] * a[2] + s * a[1];
+  T.m[4] = omc * a[0] * a[1] + s * a[2];
+  T.m[5] = c + omc * a[1] * a[1];
+  T.m[6] = omc * a[1] * a[2] - s * a[0];
+  T.m[8] = omc * a[0] * a[2] - s * a[1];
+  T.m[9] = omc * a[1] * a[2] + s * a[0];
+  T.m[10] = c + omc * a[2] * a[2];
+  T.m[3] = o[0];
+  T.m[7] = o[1];
+  T.m[11] = o[2];
+  return T;
+}
+
+// index of M[x][y] in the 10-entry upper triangle
+__device__ __forceinline__ constexpr int sym4(int x, int y) {
+  return x <= y ? (x == 0 ? y : x == 1 ? 3 + y : x == 2 ? 5 + y : 9) : sym4(y, x);
+}
+
+// ------------------------------------------------------------- model data --
+struct DevModel {
+  int n_models, n_dofs;
+  const int* f0;            // [n_models+1] first frame (= DOF) of every model
+  // per-frame records (array of structures: one pointer per lane, immediate offsets)
+  //   fr: axis (3), joint offset (3, nonzero only on a link's first frame),
+  //       mass moment upper triangle (10, nonzero only on a link's last frame)
+  const double* fr64;       // [n_dofs][16]
+  const float* fr32;        // [n_dofs][16]
+  const int* pose_link;     // [n_dofs] link whose pose frame this is, -1 otherwise
+  double* B64;              // [n_dofs][12] per-step constant -2 A(q_k) + A(q_{k-1})
+  float* B32;               // [n_dofs][12]
+  double* inert;            // [n_dofs][10] world spatial inertia of each frame (per step)
+  double* hist;             // [n_dofs][2*kMaxHist] L-BFGS pairs s (ring) then y (ring)
+  double gx, gy, gz;
+};
+
+template <typename R>
+struct Arr;
+template <>
+struct Arr<double> {
+  static __device__ __forceinline__ const double* fr(const DevModel& d) { return d.fr64; }
+  static __device__ __forceinline__ const double* B(const DevModel& d) { return d.B64; }
+};
+template <>
+struct Arr<float> {
+  static __device__ __forceinline__ const float* fr(const DevModel& d) { return d.fr32; }
+  static __device__ __forceinline__ const float* B(const DevModel& d) { return d.B32; }
+};
+
+template <typename R>
+__device__ __forceinline__ void load_frame(const DevModel& d, int f, bool valid, R a[3], R o[3]) {
+  const R* rec = Arr<R>::fr(d) + (size_t)f * 16;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a[k] = valid ? rec[k] : R(0);
+    o[k] = valid ? rec[3 + k] : R(0);
+  }
+}
+
+// World poses of the frames of this wave's model at q (float64 or float32).
+template <typename R>
+__device__ __forceinline__ Xf<R> forward_kinematics(const DevModel& d, int f, bool valid, double q) {
+  R a[3], o[3];
+  load_frame(d, f, valid, a, o);
+  Xf<R> T = hinge_transform(a, o, valid ? q : 0.0);
+  return wave_prefix_compose(T);
+}
+
+struct EvalResult {
+  double E;  // objective of the model (wave-uniform)
+  double S;  // sum of |per-frame terms| (rounding scale of E; wave-uniform)
+  double g;  // dE/dq of this lane's DOF (0 on lanes without a frame)
+};
+
+// One objective + gradient evaluation for the model of this wave.
+template <typename R>
+__device__ EvalResult evaluate(const DevModel& d, int f, bool valid, double q, double tau, double dt2) {
+  // keep the per-frame loads inside the evaluation (no hoisting across calls,
+  // which would pin them in registers for the whole solve)
+  asm volatile("" ::: "memory");
+  R a[3], o[3];
+  load_frame(d, f, valid, a, o);
+  const Xf<R> A = wave_prefix_compose(hinge_transform(a, o, valid ? q : 0.0));
+
+  R M[10];
+  const R* rec = Arr<R>::fr(d) + (size_t)f * 16;
+  const R* Bp = Arr<R>::B(d) + (size_t)f * 12;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) M[k] = valid ? rec[6 + k] : R(0);
+
+  // Row r of D = A + B (= A(q) - 2A(q_k) + A(q_{k-1})), of D M and of the seed
+  // G = dE/dA = D M - dt^2 g (M e4)^T; e = 1/2 tr(D M D^T) - dt^2 g^T A M e4.
+  // The world-frame adjoint term k = sum_c R[:,c] x G[:,c] + t x G[:,3]
+  // is accumulated as each row of G appears (float64).
+  const R dt2r = R(dt2);
+  R e = R(0), pot = R(0);
+  double k0 = 0.0, k1 = 0.0, k2 = 0.0, fv[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const R gr = R(r == 0 ? d.gx : r == 1 ? d.gy : d.gz);
+    R D[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) D[c] = A.m[4 * r + c] + (valid ? Bp[4 * r + c] : R(0));
+    R AMe4 = R(0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      R dm = R(0);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) dm += D[x] * M[sym4(x, c)];
+      e += R(0.5) * dm * D[c];
+      AMe4 += A.m[4 * r + c] * M[sym4(c, 3)];
+      const double Grc = (double)(dm - dt2r * gr * M[sym4(c, 3)]);
+      // (u x w) with u = column c of A, w = column c of G; row r of w is Grc
+      const int r1 = (r + 1) % 3, r2 = (r + 2) % 3;
+      const double u1 = A.m[4 * r1 + c], u2 = A.m[4 * r2 + c];
+      // component r1 gets +u2*w_r, component r2 gets -u1*w_r
+      if (r == 0) { k1 += u2 * Grc; k2 -= u1 * Grc; }
+      if (r == 1) { k2 += u2 * Grc; k0 -= u1 * Grc; }
+      if (r == 2) { k0 += u2 * Grc; k1 -= u1 * Grc; }
+      if (c == 3) fv[r] = Grc;
+    }
+    pot -= gr * AMe4;
+  }
+  const double tq = dt2 * tau * q;
+  const double elane = (double)e + dt2 * (double)pot;
+  double Ev = elane - (valid ? tq : 0.0);
+  double Sv = fabs(elane) + (valid ? fabs(tq) : 0.0);
+
+  // suffix sums over the frames below: inclusive prefix, then total - prefix + own
+  const double v[6] = {k0, k1, k2, fv[0], fv[1], fv[2]};
+  double suf[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double pre = wave_prefix_sum(v[k]);
+    suf[k] = (readlane(pre, 63) - pre) + v[k];
+  }
+
+  // world axis w = R a, joint point p = t
+  const double w0 = (double)A.m[0] * a[0] + (double)A.m[1] * a[1] + (double)A.m[2] * a[2];
+  const double w1 = (double)A.m[4] * a[0] + (double)A.m[5] * a[1] + (double)A.m[6] * a[2];
+  const double w2 = (double)A.m[8] * a[0] + (double)A.m[9] * a[1] + (double)A.m[10] * a[2];
+  const double p0 = A.m[3], p1 = A.m[7], p2 = A.m[11];
+  const double m0 = suf[0] - (p1 * suf[5] - p2 * suf[4]);
+  const double m1 = suf[1] - (p2 * suf[3] - p0 * suf[5]);
+  const double m2 = suf[2] - (p0 * suf[4] - p1 * suf[3]);
+  EvalResult res;
+  res.g = valid ? (w0 * m0 + w1 * m1 + w2 * m2 - dt2 * tau) : 0.0;
+  wave_sum2(Ev, Sv);
+  res.E = Ev;
+  res.S = Sv;
+  return res;
+}
+
+__device__ __forceinline__ bool all_finite(double x) { return !__any(!isfinite(x)); }
+
+// ------------------------------------------------------------ step kernel --
+struct StepArgs {
+  DevModel d;
+  double dt2, tol;
+  int m, max_iter, max_ls, precond;
+  const double* q_prev;
+  const double* q_curr;
+  const double* tau;
+  double* q_out;
+  abd_step_stats* stats;
+};
+
+// Per-frame table of the articulated-body sweeps (LDS), per model slot:
+// s (6 = world hinge motion (w; p x w)), U (6 = I^A s), 1/D (1).
+template <int G>
+struct SweepLds {
+  double tab[13][kMaxFrames][G];
+  double xb[kMaxFrames][G];  // sweep input b, then u, then the output x
+  int nf[G];
+  int f0[G];
+  int req[G];
+};
+
+// Articulated inertias at the warm start (once per step), lane = model slot:
+//   I^A_f = I_f + P_{f+1},  U_f = I^A_f s_f,  D_f = s_f.U_f,
+//   P_f = I^A_f - U_f U_f^T / D_f  (passed to the parent frame).
+// The 6x6 symmetric I^A is held as ww (6), wv (3x3), vv (6).
+template <int G>
+__device__ void aba_setup(SweepLds<G>& L, const DevModel& d, int slot) {
+  const int nf = L.nf[slot], f0 = L.f0[slot];
+  // P holds the articulated inertia passed up from the child frame, then I^A in place:
+  // ww = P[0..5] (00 01 02 11 12 22), wv = P[6..14] (3x3 row-major), vv = P[15..20]
+  double P[21];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) P[k] = 0.0;
+  for (int f = nf - 1; f >= 0; --f) {
+    const double* in = d.inert + (size_t)(f0 + f) * 10;
+    // add I = [[J, [h]x], [[h]x^T, m 1]]
+#pragma unroll
+    for (int k = 0; k < 6; ++k) P[k] += in[k];
+    const double h0 = in[6], h1 = in[7], h2 = in[8];
+    const double ms = in[9];
+    P[7] -= h2; P[8] += h1; P[9] += h2; P[11] -= h0; P[12] -= h1; P[13] += h0;
+    P[15] += ms; P[18] += ms; P[20] += ms;
+    double s[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] = L.tab[k][f][slot];
+    double U[6];
+    U[0] = P[0] * s[0] + P[1] * s[1] + P[2] * s[2] + P[6] * s[3] + P[7] * s[4] + P[8] * s[5];
+    U[1] = P[1] * s[0] + P[3] * s[1] + P[4] * s[2] + P[9] * s[3] + P[10] * s[4] + P[11] * s[5];
+    U[2] = P[2] * s[0] + P[4] * s[1] + P[5] * s[2] + P[12] * s[3] + P[13] * s[4] + P[14] * s[5];
+    U[3] = P[6] * s[0] + P[9] * s[1] + P[12] * s[2] + P[15] * s[3] + P[16] * s[4] + P[17] * s[5];
+    U[4] = P[7] * s[0] + P[10] * s[1] + P[13] * s[2] + P[16] * s[3] + P[18] * s[4] + P[19] * s[5];
+    U[5] = P[8] * s[0] + P[11] * s[1] + P[14] * s[2] + P[17] * s[3] + P[19] * s[4] + P[20] * s[5];
+    const double D = s[0] * U[0] + s[1] * U[1] + s[2] * U[2] + s[3] * U[3] + s[4] * U[4] + s[5] * U[5];
+    const double iD = (D > 0.0) ? 1.0 / D : 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) L.tab[6 + k][f][slot] = U[k];
+    L.tab[12][f][slot] = iD;
+    // P <- I^A - U U^T / D  (the articulated inertia seen by the parent)
+    P[0] -= U[0] * U[0] * iD; P[1] -= U[0] * U[1] * iD; P[2] -= U[0] * U[2] * iD;
+    P[3] -= U[1] * U[1] * iD; P[4] -= U[1] * U[2] * iD; P[5] -= U[2] * U[2] * iD;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) P[6 + 3 * r + c] -= U[r] * U[3 + c] * iD;
+    P[15] -= U[3] * U[3] * iD; P[16] -= U[3] * U[4] * iD; P[17] -= U[3] * U[5] * iD;
+    P[18] -= U[4] * U[4] * iD; P[19] -= U[4] * U[5] * iD; P[20] -= U[5] * U[5] * iD;
+  }
+}
+
+// x = H^{-1} b in O(n): backward sweep u_f = b_f - s_f.p, p <- p + U_f u_f / D_f;
+// forward sweep x_f = (u_f - U_f.a) / D_f, a <- a + s_f x_f.  In place in xb.
+template <int G>
+__device__ void aba_solve(SweepLds<G>& L, int slot) {
+  const int nf = L.nf[slot];
+  double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p5 = 0;
+  for (int f = nf - 1; f >= 0; --f) {
+    const double u = L.xb[f][slot] - (L.tab[0][f][slot] * p0 + L.tab[1][f][slot] * p1 + L.tab[2][f][slot] * p2 +
+                                      L.tab[3][f][slot] * p3 + L.tab[4][f][slot] * p4 + L.tab[5][f][slot] * p5);
+    L.xb[f][slot] = u;
+    const double w = u * L.tab[12][f][slot];
+    p0 += L.tab[6][f][slot] * w;
+    p1 += L.tab[7][f][slot] * w;
+    p2 += L.tab[8][f][slot] * w;
+    p3 += L.tab[9][f][slot] * w;
+    p4 += L.tab[10][f][slot] * w;
+    p5 += L.tab[11][f][slot] * w;
+  }
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+  for (int f = 0; f < nf; ++f) {
+    const double x = (L.xb[f][slot] - (L.tab[6][f][slot] * a0 + L.tab[7][f][slot] * a1 + L.tab[8][f][slot] * a2 +
+                                       L.tab[9][f][slot] * a3 + L.tab[10][f][slot] * a4 +
+                                       L.tab[11][f][slot] * a5)) *
+                     L.tab[12][f][slot];
+    L.xb[f][slot] = x;
+    a0 += L.tab[0][f][slot] * x;
+    a1 += L.tab[1][f][slot] * x;
+    a2 += L.tab[2][f][slot] * x;
+    a3 += L.tab[3][f][slot] * x;
+    a4 += L.tab[4][f][slot] * x;
+    a5 += L.tab[5][f][slot] * x;
+  }
+}
+
+// Setup of one step for this wave's model (float64): the per-step constant
+// B = -2 A(q_k) + A(q_{k-1}) of every frame, and for the inertia preconditioner
+// the world spatial inertia (about the origin) and hinge motion at the warm start.
+template <int G>
+__device__ __forceinline__ void step_setup(const DevModel& d, SweepLds<G>& L, int f, bool valid, int wave, int lane,
+                                        double qkm1, double qk, double q0, bool use_aba) {
+  double* B64 = d.B64 + (size_t)f * 12;
+  float* B32 = d.B32 + (size_t)f * 12;
+  {
+    const Xf<double> Akm1 = forward_kinematics<double>(d, f, valid, qkm1);
+    if (valid)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) B64[k] = Akm1.m[k];
+  }
+  {
+    const Xf<double> Ak = forward_kinematics<double>(d, f, valid, qk);
+    if (valid)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const double b = B64[k] - 2.0 * Ak.m[k];
+        B64[k] = b;
+        B32[k] = (float)b;
+      }
+  }
+  if (!use_aba) return;
+  double a[3], o[3];
+  load_frame<double>(d, f, valid, a, o);
+  const Xf<double> A = forward_kinematics<double>(d, f, valid, q0);
+  double M[10];
+  const double* rec = d.fr64 + (size_t)f * 16;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) M[k] = valid ? rec[6 + k] : 0.0;
+  const double ms = M[9];
+  // world moment tensor: h = R (m c) + m t ; Sigma = R S R^T + R mc t^T + t (R mc)^T + m t t^T
+  double Rmc[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) Rmc[r] = A.m[4 * r] * M[3] + A.m[4 * r + 1] * M[6] + A.m[4 * r + 2] * M[8];
+  const double t[3] = {A.m[3], A.m[7], A.m[11]};
+  double Sw[6];  // 00 01 02 11 12 22
+  {
+    int k = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = r; c < 3; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+          const double RS = A.m[4 * r] * M[sym4(0, x)] + A.m[4 * r + 1] * M[sym4(1, x)] + A.m[4 * r + 2] * M[sym4(2, x)];
+          acc += RS * A.m[4 * c + x];
+        }
+        Sw[k++] = acc + Rmc[r] * t[c] + t[r] * Rmc[c] + ms * t[r] * t[c];
+      }
+  }
+  const double tr = Sw[0] + Sw[3] + Sw[5];
+  if (valid) {
+    double* in = d.inert + (size_t)f * 10;
+    in[0] = tr - Sw[0];
+    in[1] = -Sw[1];
+    in[2] = -Sw[2];
+    in[3] = tr - Sw[3];
+    in[4] = -Sw[4];
+    in[5] = tr - Sw[5];
+    in[6] = Rmc[0] + ms * t[0];
+    in[7] = Rmc[1] + ms * t[1];
+    in[8] = Rmc[2] + ms * t[2];
+    in[9] = ms;
+  }
+  const double w0 = A.m[0] * a[0] + A.m[1] * a[1] + A.m[2] * a[2];
+  const double w1 = A.m[4] * a[0] + A.m[5] * a[1] + A.m[6] * a[2];
+  const double w2 = A.m[8] * a[0] + A.m[9] * a[1] + A.m[10] * a[2];
+  L.tab[0][lane][wave] = valid ? w0 : 0.0;
+  L.tab[1][lane][wave] = valid ? w1 : 0.0;
+  L.tab[2][lane][wave] = valid ? w2 : 0.0;
+  L.tab[3][lane][wave] = valid ? t[1] * w2 - t[2] * w1 : 0.0;
+  L.tab[4][lane][wave] = valid ? t[2] * w0 - t[0] * w2 : 0.0;
+  L.tab[5][lane][wave] = valid ? t[0] * w1 - t[1] * w0 : 0.0;
+}
+
+// What the next evaluation of phase C is for.
+enum EvalPurpose { kTrial = 0, kRefresh = 1, kRefreshRetry = 2 };
+
+// One time step.  MIXED: float32 evaluations until the line search meets float32
+// rounding (or float32 claims convergence), then float64 to the end.
+template <int G, int MMAX, int PREC>
+__global__ void __launch_bounds__(G* kWave) k_step(StepArgs args) {
+  __shared__ SweepLds<G> L;
+  const DevModel& d = args.d;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int model = blockIdx.x * G + wave;
+  const bool has_model = model < d.n_models;
+  const int f0 = has_model ? d.f0[model] : 0;
+  const int nf = has_model ? d.f0[model + 1] - f0 : 0;
+  const bool valid = lane < nf;
+  const int f = f0 + (valid ? lane : 0);
+  const bool use_aba = args.precond == ABD_PRECOND_INERTIA;
+  if (lane == 0) {
+    L.nf[wave] = nf;
+    L.f0[wave] = f0;
+  }
+
+  const double qkm1 = valid ? args.q_prev[f] : 0.0;
+  const double qk = valid ? args.q_curr[f] : 0.0;
+  double q = valid ? 2.0 * qk - qkm1 : 0.0;  // warm start: constant-velocity extrapolation
+  const double tau = (valid && args.tau) ? args.tau[f] : 0.0;
+  if (nf > 0) step_setup<G>(d, L, f, valid, wave, lane, qkm1, qk, q, use_aba);
+  __syncthreads();
+  if (use_aba && wave == 0 && lane < G && L.nf[lane] > 0) aba_setup<G>(L, d, lane);
+  __syncthreads();
+
+  const double eps_w = PREC == ABD_MIXED ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
+  bool f32 = PREC == ABD_MIXED;
+  int iters = 0, evals = 0, flag = 0, f32_iters = 0;
+  double E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0;
+  bool active = nf > 0;
+  if (nf == 0 && has_model) flag = ABD_FLAG_CONVERGED;
+  if (active) {
+    const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(d, f, valid, q, tau, args.dt2)
+                                              : evaluate<double>(d, f, valid, q, tau, args.dt2);
+    ++evals;
+    E = r.E;
+    g = r.g;
+    if (!isfinite(E) || !all_finite(g)) {
+      flag = ABD_FLAG_NONFINITE;
+      active = false;
+    } else {
+      g0 = uniform(sqrt(wave_sum(g * g)));
+      gn = g0;
+      if (g0 == 0.0) {
+        flag = ABD_FLAG_CONVERGED;
+        active = false;
+      } else if (args.max_iter <= 0) {
+        flag = ABD_FLAG_MAX_ITER;
+        active = false;
+      }
+    }
+  }
+
+  // history: vectors in a per-frame ring buffer in device memory (slot `head` is
+  // the newest pair), scalars rho_i = 1/(s_i.y_i) newest-first in registers
+  double* hs = d.hist + (size_t)f * (2 * kMaxHist);
+  double rho[MMAX], alp[MMAX];
+#pragma unroll
+  for (int k = 0; k < MMAX; ++k) {
+    rho[k] = 0.0; alp[k] = 0.0;
+  }
+  double gam = 1.0;  // s^T y / y^T y of the newest pair (identity preconditioner)
+  int count = 0, head = 0;
+  bool reset = false;  // redo the direction with an empty history
+  double qv = 0.0;
+  const double c1 = 1e-4, dlt = 0.1;
+
+  for (;;) {
+    // phase A: first loop of the two-loop recursion (newest pair first)
+    if (active) {
+      if (reset) count = 0;
+      qv = g;
+#pragma unroll
+      for (int k = 0; k < MMAX; ++k)
+        if (k < count) {
+          const int slot = (head - k + args.m) % args.m;
+          const double sk = valid ? hs[slot] : 0.0, yk = valid ? hs[kMaxHist + slot] : 0.0;
+          alp[k] = uniform(rho[k] * wave_sum(sk * qv));
+          qv -= alp[k] * yk;
+        }
+      if (use_aba) L.xb[lane][wave] = valid ? qv : 0.0;
+    }
+    if (lane == 0) L.req[wave] = (active && use_aba) ? 1 : 0;
+    __syncthreads();
+    // phase B: apply the inverse joint-space inertia, one lane per model
+    if (wave == 0 && lane < G && L.req[lane]) aba_solve<G>(L, lane);
+    __syncthreads();
+    // phase C: second loop, line search, update
+    if (active) {
+      double r = use_aba ? L.xb[lane][wave] : (count > 0 ? gam : 1.0) * qv;
+#pragma unroll
+      for (int k = MMAX - 1; k >= 0; --k)
+        if (k < count) {
+          const int slot = (head - k + args.m) % args.m;
+          const double sk = valid ? hs[slot] : 0.0, yk = valid ? hs[kMaxHist + slot] : 0.0;
+          const double b = uniform(rho[k] * wave_sum(yk * r));
+          r += (alp[k] - b) * sk;
+        }
+      const double dir = valid ? -r : 0.0;
+      const double gd = uniform(wave_sum(g * dir));
+      if (!(gd < 0.0)) {
+        if (!reset) {
+          reset = true;
+        } else {
+          flag = ABD_FLAG_LS_FLOOR;
+          active = false;
+        }
+      } else {
+        reset = false;
+        double alpha = 1.0;
+        int ls = 0;
+        bool noisy = false;
+        int purpose = kTrial;
+        for (;;) {
+          const double x = purpose == kTrial ? q + alpha * dir : q;
+          EvalResult rt;
+          if (PREC == ABD_MIXED && f32)
+            rt = evaluate<float>(d, f, valid, x, tau, args.dt2);
+          else
+            rt = evaluate<double>(d, f, valid, x, tau, args.dt2);
+          ++evals;
+          if (purpose != kTrial) {
+            // float64 re-evaluation at q after leaving float32
+            E = rt.E;
+            g = rt.g;
+            gn = uniform(sqrt(wave_sum(g * g)));
+            if (purpose == kRefresh) {
+              if (gn <= args.tol * g0) {
+                flag = ABD_FLAG_CONVERGED;
+                active = false;
+              } else if (iters >= args.max_iter) {
+                flag = ABD_FLAG_MAX_ITER;
+                active = false;
+              }
+            }
+            break;
+          }
+          int ok = 0;
+          if (isfinite(rt.E) && all_finite(rt.g)) {
+            if (rt.E <= E + c1 * alpha * gd) {
+              ok = 1;
+            } else if (fabs(rt.E - E) <= 10.0 * eps_w * rt.S) {
+              noisy = true;
+              const double gtd = wave_sum(rt.g * dir);
+              if (gtd <= (2.0 * dlt - 1.0) * gd) ok = 1;
+            }
+          }
+          if (!ok) {
+            alpha *= 0.5;
+            if (++ls < args.max_ls) continue;
+            if (PREC == ABD_MIXED && f32) {
+              f32 = false;  // float32 rounding stalls the search: continue in float64 from q
+              purpose = kRefreshRetry;
+              continue;
+            }
+            flag = ABD_FLAG_LS_FLOOR;
+            active = false;
+            break;
+          }
+          // accepted: curvature pair and update
+          const double sv = alpha * dir;
+          const double y = rt.g - g;
+          double sy = sv * y, ss = sv * sv, yy = y * y, unused = 0.0;
+          wave_sum2(sy, ss);
+          wave_sum2(yy, unused);
+          if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
+#pragma unroll
+            for (int k = MMAX - 1; k > 0; --k) rho[k] = rho[k - 1];
+            rho[0] = uniform(1.0 / sy);
+            gam = uniform(sy / yy);
+            head = count == 0 ? 0 : (head + 1) % args.m;
+            if (valid) {
+              hs[head] = sv;
+              hs[kMaxHist + head] = y;
+            }
+            if (count < args.m) ++count;
+          }
+          q = x;
+          g = rt.g;
+          E = rt.E;
+          ++iters;
+          if (PREC == ABD_MIXED && f32) ++f32_iters;
+          gn = uniform(sqrt(wave_sum(g * g)));
+          const bool conv = gn <= args.tol * g0;
+          if (PREC == ABD_MIXED && f32 && (conv || noisy)) {
+            f32 = false;  // float32 has done what it can: confirm / continue in float64
+            purpose = kRefresh;
+            continue;
+          }
+          if (conv) {
+            flag = ABD_FLAG_CONVERGED;
+            active = false;
+          } else if (iters >= args.max_iter) {
+            flag = ABD_FLAG_MAX_ITER;
+            active = false;
+          }
+          break;
+        }
+      }
+    }
+    if (!__syncthreads_or(active ? 1 : 0)) break;
+  }
+
+  if (has_model) {
+    if (valid) args.q_out[f] = q;
+    if (args.stats && lane == 0) {
+      abd_step_stats st;
+      st.iterations = iters;
+      st.evaluations = evals;
+      st.flag = flag;
+      st.f32_iterations = f32_iters;
+      st.grad_norm = gn;
+      st.energy = E;
+      args.stats[model] = st;
+    }
+  }
+}
+
+// ---------------------------------------------------- objective / poses --
+struct EvalArgs {
+  DevModel d;
+  double dt2;
+  int precision;
+  const double* q;
+  const double* q_prev;
+  const double* q_curr;
+  const double* tau;
+  double* E;
+  double* grad;
+};
+
+__global__ void __launch_bounds__(kWave) k_objective_grad(EvalArgs a) {
+  const DevModel& d = a.d;
+  const int model = blockIdx.x, lane = threadIdx.x;
+  const int f0 = d.f0[model], nf = d.f0[model + 1] - f0;
+  const bool valid = lane < nf;
+  const int f = f0 + (valid ? lane : 0);
+  if (nf == 0) {
+    if (lane == 0) a.E[model] = 0.0;
+    return;
+  }
+  const double qkm1 = valid ? a.q_prev[f] : 0.0, qk = valid ? a.q_curr[f] : 0.0;
+  const Xf<double> Ak = forward_kinematics<double>(d, f, valid, qk);
+  const Xf<double> Akm1 = forward_kinematics<double>(d, f, valid, qkm1);
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double b = Akm1.m[k] - 2.0 * Ak.m[k];
+      d.B64[(size_t)f * 12 + k] = b;
+      d.B32[(size_t)f * 12 + k] = (float)b;
+    }
+  }
+  // the B rows of this lane were written by this lane: no barrier needed
+  const double q = valid ? a.q[f] : 0.0;
+  const double tau = (valid && a.tau) ? a.tau[f] : 0.0;
+  const EvalResult r = a.precision == ABD_MIXED ? evaluate<float>(d, f, valid, q, tau, a.dt2)
+                                                : evaluate<double>(d, f, valid, q, tau, a.dt2);
+  if (lane == 0) a.E[model] = r.E;
+  if (a.grad && valid) a.grad[f] = r.g;
+}
+
+__global__ void __launch_bounds__(kWave) k_poses(DevModel d, const double* q, double* poses) {
+  const int model = blockIdx.x, lane = threadIdx.x;
+  const int f0 = d.f0[model], nf = d.f0[model + 1] - f0;
+  if (nf == 0) return;
+  const bool valid = lane < nf;
+  const int f = f0 + (valid ? lane : 0);
+  const Xf<double> A = forward_kinematics<double>(d, f, valid, valid ? q[f] : 0.0);
+  if (valid) {
+    const int l = d.pose_link[f];
+    if (l >= 0)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) poses[12 * (size_t)l + k] = A.m[k];
+  }
+}
+
+}  // namespace
+
+// =================================================================== host ==
+struct abd_model {
+  int device = 0;
+  int n_models = 0, n_links = 0, n_dofs = 0;
+  double g[3] = {0, 0, 0};
+  // device buffers
+  int* f0 = nullptr;
+  int* pose_link = nullptr;
+  double* fr64 = nullptr;
+  float* fr32 = nullptr;
+  double* B64 = nullptr;
+  float* B32 = nullptr;
+  double* inert = nullptr;
+  double* hist = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+template <typename T>
+int upload(abd_model* m, T** dst, const std::vector<T>& src) {
+  size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(ABD_ENOMEM, "hipMalloc failed");
+  m->allocs.push_back(p);
+  if (!src.empty() && hipMemcpy(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(ABD_EDEVICE, "hipMemcpy to device failed");
+  *dst = static_cast<T*>(p);
+  return ABD_OK;
+}
+
+template <typename T>
+int alloc(abd_model* m, T** dst, size_t count) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(1, count) * sizeof(T)) != hipSuccess)
+    return fail(ABD_ENOMEM, "hipMalloc failed");
+  m->allocs.push_back(p);
+  *dst = static_cast<T*>(p);
+  return ABD_OK;
+}
+
+void free_model(abd_model* m) {
+  for (void* p : m->allocs) (void)hipFree(p);
+  m->allocs.clear();
+}
+
+bool psd4(const double* u) {
+  // symmetric 4x4 from the upper triangle; PSD test by pivoted LDL^T with tolerance
+  static const int idx[16] = {0, 1, 2, 3, 1, 4, 5, 6, 2, 5, 7, 8, 3, 6, 8, 9};
+  double A[4][4];
+  double scale = 0.0;
+  for (int i = 0; i < 16; ++i) {
+    A[i / 4][i % 4] = u[idx[i]];
+    scale = std::fmax(scale, std::fabs(u[idx[i]]));
+  }
+  const double tol = 1e-12 * (scale > 0 ? scale : 1.0);
+  for (int k = 0; k < 4; ++k) {
+    if (A[k][k] < -tol) return false;
+    if (A[k][k] <= tol) {
+      for (int j = k + 1; j < 4; ++j)
+        if (std::fabs(A[k][j]) > 1e-6 * std::sqrt(scale) * std::sqrt(std::fabs(A[j][j]) + tol)) return false;
+      continue;
+    }
+    for (int i = k + 1; i < 4; ++i) {
+      const double l = A[i][k] / A[k][k];
+      for (int j = k + 1; j < 4; ++j) A[i][j] -= l * A[k][j];
+    }
+  }
+  return true;
+}
+
+DevModel dev_view(const abd_model* m) {
+  DevModel d;
+  d.n_models = m->n_models;
+  d.n_dofs = m->n_dofs;
+  d.f0 = m->f0;
+  d.fr64 = m->fr64;
+  d.fr32 = m->fr32;
+  d.pose_link = m->pose_link;
+  d.B64 = m->B64; d.B32 = m->B32;
+  d.inert = m->inert;
+  d.hist = m->hist;
+  d.gx = m->g[0]; d.gy = m->g[1]; d.gz = m->g[2];
+  return d;
+}
+
+int check_device(const abd_model* m) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != m->device) return fail(ABD_EINVAL, "current HIP device differs from the model's device");
+  return ABD_OK;
+}
+
+int check_opts(const abd_step_opts* o, bool for_step) {
+  if (!o) return fail(ABD_EINVAL, "opts is NULL");
+  if (!(o->dt > 0.0) || !std::isfinite(o->dt)) return fail(ABD_EINVAL, "dt must be finite and > 0");
+  if (o->precision != ABD_FP64 && o->precision != ABD_MIXED)
+    return fail(ABD_EINVAL, "precision must be ABD_FP64 or ABD_MIXED");
+  if (!for_step) return ABD_OK;
+  if (o->order_K != 2) return fail(ABD_ENOTSUP, "order_K != 2 is not handled by this build");
+  if (o->lbfgs_m < 1 || o->lbfgs_m > 10) return fail(ABD_EINVAL, "lbfgs_m must be in 1..10");
+  if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(ABD_EINVAL, "tol must be finite and >= 0");
+  if (o->max_iter < 0) return fail(ABD_EINVAL, "max_iter must be >= 0");
+  if (o->max_ls < 1 || o->max_ls > 60) return fail(ABD_EINVAL, "max_ls must be in 1..60");
+  if (o->precond != ABD_PRECOND_IDENTITY && o->precond != ABD_PRECOND_INERTIA)
+    return fail(ABD_EINVAL, "precond must be ABD_PRECOND_IDENTITY or ABD_PRECOND_INERTIA");
+  return ABD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* abd_last_error(void) { return g_err.c_str(); }
+
+int abd_create_model(const abd_model_desc* desc, abd_model** out) {
+  g_err.clear();
+  if (!desc || !out) return fail(ABD_EINVAL, "desc and out must not be NULL");
+  *out = nullptr;
+  const int nm = desc->n_models;
+  if (nm < 0) return fail(ABD_EINVAL, "n_models < 0");
+  if (!desc->link_offset) return fail(ABD_EINVAL, "link_offset is NULL");
+  if (desc->link_offset[0] != 0) return fail(ABD_EINVAL, "link_offset[0] must be 0");
+  for (int i = 0; i < nm; ++i)
+    if (desc->link_offset[i + 1] < desc->link_offset[i]) return fail(ABD_EINVAL, "link_offset must be non-decreasing");
+  const int nl = desc->link_offset[nm];
+  if (nl > 0 && (!desc->parent || !desc->dofs_per_link || !desc->axis || !desc->offset || !desc->mass_moment))
+    return fail(ABD_EINVAL, "model arrays must not be NULL");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(desc->gravity[k])) return fail(ABD_EINVAL, "gravity must be finite");
+  long long nd_ll = 0;
+  for (int l = 0; l < nl; ++l) {
+    const int k = desc->dofs_per_link[l];
+    if (k < 1 || k > 3) return fail(ABD_EINVAL, "dofs_per_link must be in 1..3 (link " + std::to_string(l) + ")");
+    nd_ll += k;
+  }
+  if (nd_ll > (1ll << 30)) return fail(ABD_EINVAL, "too many DOFs");
+  const int nd = (int)nd_ll;
+
+  std::vector<int> f0(nm + 1, 0), pose_link(nd, -1), link_dof(nl + 1, 0);
+  for (int l = 0; l < nl; ++l) link_dof[l + 1] = link_dof[l] + desc->dofs_per_link[l];
+  for (int i = 0; i <= nm; ++i) f0[i] = link_dof[desc->link_offset[i]];
+  std::vector<double> fr64(16 * (size_t)nd, 0.0);
+  bool chain = true;
+  int max_frames = 0;
+  for (int i = 0; i < nm; ++i) {
+    const int lo = desc->link_offset[i], hi = desc->link_offset[i + 1];
+    max_frames = std::max(max_frames, f0[i + 1] - f0[i]);
+    for (int l = lo; l < hi; ++l) {
+      const int p = desc->parent[l];
+      if (p < -1 || p >= l - lo) return fail(ABD_EINVAL, "parent of link " + std::to_string(l) + " must precede it");
+      if (p != l - lo - 1) chain = false;
+      for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(desc->offset[3 * l + k])) return fail(ABD_EINVAL, "offset not finite");
+      const double* u = desc->mass_moment + 10 * (size_t)l;
+      for (int k = 0; k < 10; ++k)
+        if (!std::isfinite(u[k])) return fail(ABD_EINVAL, "mass_moment not finite");
+      if (!(u[9] > 0.0)) return fail(ABD_EINVAL, "mass of link " + std::to_string(l) + " must be > 0");
+      if (!psd4(u)) return fail(ABD_EINVAL, "mass_moment of link " + std::to_string(l) + " is not PSD");
+      const int d0 = link_dof[l], k = desc->dofs_per_link[l];
+      for (int j = 0; j < k; ++j) {
+        const double* a = desc->axis + 3 * (size_t)(d0 + j);
+        const double nrm = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        if (!std::isfinite(nrm) || std::fabs(nrm - 1.0) > 1e-9)
+          return fail(ABD_EINVAL, "axis of DOF " + std::to_string(d0 + j) + " must be a unit vector");
+        for (int c = 0; c < 3; ++c) fr64[16 * (size_t)(d0 + j) + c] = a[c];
+      }
+      for (int c = 0; c < 3; ++c) fr64[16 * (size_t)d0 + 3 + c] = desc->offset[3 * (size_t)l + c];
+      for (int c = 0; c < 10; ++c) fr64[16 * (size_t)(d0 + k - 1) + 6 + c] = u[c];
+      pose_link[d0 + k - 1] = l;
+    }
+  }
+  if (!chain) return fail(ABD_ENOTSUP, "branched trees are not handled by this build (serial chains only)");
+  if (max_frames > kMaxFrames)
+    return fail(ABD_ENOTSUP, "models with more than 64 DOFs are not handled by this build");
+
+  abd_model* m = new abd_model();
+  HIP_TRY(hipGetDevice(&m->device));
+  m->n_models = nm;
+  m->n_links = nl;
+  m->n_dofs = nd;
+  for (int k = 0; k < 3; ++k) m->g[k] = desc->gravity[k];
+  std::vector<float> fr32(fr64.begin(), fr64.end());
+  int rc = ABD_OK;
+  if ((rc = upload(m, &m->f0, f0)) || (rc = upload(m, &m->pose_link, pose_link)) ||
+      (rc = upload(m, &m->fr64, fr64)) || (rc = upload(m, &m->fr32, fr32)) ||
+      (rc = alloc(m, &m->B64, 12 * (size_t)nd)) || (rc = alloc(m, &m->B32, 12 * (size_t)nd)) ||
+      (rc = alloc(m, &m->inert, 10 * (size_t)nd)) || (rc = alloc(m, &m->hist, 2 * kMaxHist * (size_t)nd))) {
+    free_model(m);
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return ABD_OK;
+}
+
+void abd_destroy_model(abd_model* m) {
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  free_model(m);
+  delete m;
+}
+
+int abd_model_info(const abd_model* m, int* n_models, int* n_links, int* n_dofs) {
+  if (!m) return fail(ABD_EINVAL, "model is NULL");
+  if (n_models) *n_models = m->n_models;
+  if (n_links) *n_links = m->n_links;
+  if (n_dofs) *n_dofs = m->n_dofs;
+  return ABD_OK;
+}
+
+int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const double* tau, double* q_out,
+             abd_step_stats* stats, void* stream) {
+  g_err.clear();
+  if (!m) return fail(ABD_EINVAL, "model is NULL");
+  int rc = check_opts(o, true);
+  if (rc) return rc;
+  if (m->n_models == 0) return ABD_OK;
+  if (!q_hist || !q_out) return fail(ABD_EINVAL, "q_hist and q_out must not be NULL");
+  const double* q_prev = q_hist;
+  const double* q_curr = q_hist + m->n_dofs;
+  if (q_out < q_hist + 2 * (size_t)m->n_dofs && q_hist < q_out + m->n_dofs)
+    return fail(ABD_EINVAL, "q_out overlaps q_hist");
+  if ((rc = check_device(m))) return rc;
+  StepArgs a;
+  a.d = dev_view(m);
+  a.dt2 = o->dt * o->dt;
+  a.tol = o->tol;
+  a.m = o->lbfgs_m;
+  a.max_iter = o->max_iter;
+  a.max_ls = o->max_ls;
+  a.precond = o->precond;
+  a.q_prev = q_prev;
+  a.q_curr = q_curr;
+  a.tau = tau;
+  a.q_out = q_out;
+  a.stats = stats;
+  const int blocks = (m->n_models + kG - 1) / kG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const dim3 grid(blocks), block(kG * kWave);
+  if (o->precision == ABD_FP64) {
+    if (o->lbfgs_m <= 5)
+      hipLaunchKernelGGL((k_step<kG, 5, ABD_FP64>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_step<kG, 10, ABD_FP64>), grid, block, 0, s, a);
+  } else {
+    if (o->lbfgs_m <= 5)
+      hipLaunchKernelGGL((k_step<kG, 5, ABD_MIXED>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_step<kG, 10, ABD_MIXED>), grid, block, 0, s, a);
+  }
+  HIP_TRY(hipGetLastError());
+  return ABD_OK;
+}
+
+int abd_objective_grad(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,
+                       const double* tau, double* E, double* grad, void* stream) {
+  g_err.clear();
+  if (!m) return fail(ABD_EINVAL, "model is NULL");
+  int rc = check_opts(o, false);
+  if (rc) return rc;
+  if (m->n_models == 0) return ABD_OK;
+  if (!q || !q_hist || !E) return fail(ABD_EINVAL, "q, q_hist and E must not be NULL");
+  if ((rc = check_device(m))) return rc;
+  EvalArgs a;
+  a.d = dev_view(m);
+  a.dt2 = o->dt * o->dt;
+  a.precision = o->precision;
+  a.q = q;
+  a.q_prev = q_hist;
+  a.q_curr = q_hist + m->n_dofs;
+  a.tau = tau;
+  a.E = E;
+  a.grad = grad;
+  hipLaunchKernelGGL(k_objective_grad, dim3(m->n_models), dim3(kWave), 0, static_cast<hipStream_t>(stream), a);
+  HIP_TRY(hipGetLastError());
+  return ABD_OK;
+}
+
+int abd_poses(abd_model* m, const double* q, double* poses, void* stream) {
+  g_err.clear();
+  if (!m) return fail(ABD_EINVAL, "model is NULL");
+  if (m->n_models == 0) return ABD_OK;
+  if (!q || !poses) return fail(ABD_EINVAL, "q and poses must not be NULL");
+  int rc = check_device(m);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_poses, dim3(m->n_models), dim3(kWave), 0, static_cast<hipStream_t>(stream), dev_view(m), q,
+                     poses);
+  HIP_TRY(hipGetLastError());
+  return ABD_OK;
+}
+
+}  // extern "C"

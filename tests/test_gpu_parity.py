@@ -1,0 +1,286 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (stated per quantity):
+  * objective and gradient, float64 kernels: 1e-12 relative (objective relative
+    to the sum of the magnitudes of its terms, gradient relative to its largest
+    component);
+  * one time step, float64, teacher-forced (both sides step from the same
+    float64 (q_{k-1}, q_k)): 1e-10 relative in q (max |dq| / max(1, max |q|));
+  * one time step, mixed precision: 1e-5 relative pose error against the oracle
+    (max link-origin distance over the model's reach, max rotation Frobenius
+    distance).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.oracle import Oracle
+from paper_1709_04145_amd import abd
+from paper_1709_04145_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    abd.load()
+    yield
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def cu(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device="cuda")
+
+
+def rel_q(a, b):
+    return float(np.max(np.abs(a - b)) / max(1.0, float(np.max(np.abs(b))))) if a.size else 0.0
+
+
+def mixed_chains(n_models, seed, max_dofs=64):
+    """Serial chains mixing hinge and ball joints, ragged, up to max_dofs DOFs."""
+    models = []
+    for i in range(n_models):
+        rng = np.random.default_rng([seed, i])
+        target = int(rng.integers(1, max_dofs + 1))
+        dofs, axis, lengths = [], [], []
+        while sum(dofs) < target:
+            k = 3 if (rng.uniform() < 0.3 and sum(dofs) + 3 <= target) else 1
+            dofs.append(k)
+            if k == 3:
+                axis.extend(np.eye(3))
+            else:
+                v = rng.standard_normal(3)
+                axis.append(v / np.linalg.norm(v))
+            lengths.append(rng.uniform(0.2, 1.0))
+        n = len(dofs)
+        offset = np.zeros((n, 3))
+        for l in range(1, n):
+            offset[l] = [lengths[l - 1], 0.0, 0.0]
+        mm = np.stack([W.box_mass_moment(lengths[l], 0.1, rng.uniform(500, 2000)) for l in range(n)])
+        models.append(dict(parent=np.arange(-1, n - 1), dofs=np.array(dofs, np.int32), axis=np.array(axis),
+                           offset=offset, mm=mm))
+    return W._assemble(models)
+
+
+def pose_error(orc, desc, q, qref):
+    A = orc.poses(q)
+    Ar = orc.poses(qref)
+    lo = desc.link_offset
+    err_x, err_R = 0.0, 0.0
+    for i in range(desc.n_models):
+        sl = slice(lo[i], lo[i + 1])
+        reach = np.sum(np.linalg.norm(desc.offset[sl], axis=1)) + 2.0 * np.max(desc.mass_moment[sl, 3] / desc.mass_moment[sl, 9])
+        err_x = max(err_x, float(np.max(np.linalg.norm(A[sl, :, 3] - Ar[sl, :, 3], axis=1)) / reach))
+        err_R = max(err_R, float(np.max(np.linalg.norm(A[sl, :, :3] - Ar[sl, :, :3], axis=(1, 2)))))
+    return err_x, err_R
+
+
+# ------------------------------------------------------------ evaluation
+@pytest.mark.parametrize("seed", [1, 2])
+def test_objective_and_gradient_fp64(seed):
+    d = mixed_chains(40, seed)
+    say(f"objective_grad fp64 seed={seed} models={d.n_models} dofs={d.n_dofs}")
+    rng = np.random.default_rng(100 + seed)
+    q, qp, qc = (rng.uniform(-2, 2, d.n_dofs) for _ in range(3))
+    tau = rng.uniform(-1, 1, d.n_dofs)
+    dt = 0.05
+    E, g, S = Oracle(d).objective_grad(q, qp, qc, dt, tau)
+    m = abd.Model(d)
+    Eg, gg = m.objective_grad(cu(q), cu(np.concatenate([qp, qc])), dt, tau=cu(tau))
+    Eg, gg = Eg.cpu().numpy(), gg.cpu().numpy()
+    assert np.all(np.abs(Eg - E) <= 1e-12 * S)
+    do = d.dof_offset
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        scale = np.max(np.abs(g[sl]))
+        assert np.max(np.abs(gg[sl] - g[sl])) <= 1e-12 * scale, i
+
+
+def test_objective_mixed_is_close():
+    d = mixed_chains(20, 7)
+    rng = np.random.default_rng(5)
+    q, qp, qc = (rng.uniform(-1, 1, d.n_dofs) for _ in range(3))
+    say("objective_grad mixed")
+    E, g, S = Oracle(d).objective_grad(q, qp, qc, 0.03)
+    m = abd.Model(d)
+    Eg, gg = m.objective_grad(cu(q), cu(np.concatenate([qp, qc])), 0.03, precision=abd.MIXED)
+    assert np.all(np.abs(Eg.cpu().numpy() - E) <= 1e-5 * S)
+
+
+def test_poses_fp64():
+    d = mixed_chains(30, 3)
+    q = np.random.default_rng(6).uniform(-3, 3, d.n_dofs)
+    say("poses")
+    A = Oracle(d).poses(q)
+    Ag = abd.Model(d).poses(cu(q)).cpu().numpy()
+    assert np.max(np.abs(Ag - A)) <= 1e-13 * max(1.0, np.max(np.abs(A)))
+
+
+# ------------------------------------------------------------------ steps
+def _step_gpu(d, qp, qc, opts, tau=None):
+    m = abd.Model(d)
+    out = torch.zeros(d.n_dofs, dtype=torch.float64, device="cuda")
+    st = m.new_stats()
+    m.step(cu(np.concatenate([qp, qc])), out, opts, tau=None if tau is None else cu(tau), stats=st)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), m.read_stats(st, d.n_models)
+
+
+def _replicated(desc, k):
+    return desc.subset(np.tile(np.arange(desc.n_models), k))
+
+
+def test_config1_teacher_forced_fp64():
+    wl = W.config(1)
+    orc = Oracle(wl.model)
+    dt = wl.step.dt
+    qs, _ = orc.rollout(wl.q0, wl.step.steps, dt)
+    K = wl.step.steps
+    rep = _replicated(wl.model, K)
+    qp = np.concatenate([qs[max(k - 1, 0)] for k in range(K)])
+    qc = np.concatenate([qs[k] for k in range(K)])
+    say(f"config1 teacher-forced fp64, {K} steps in one batch")
+    ref, rst = Oracle(rep).step(qp, qc, dt)
+    out, st = _step_gpu(rep, qp, qc, abd.StepOptions(dt=dt))
+    assert rel_q(out, ref) <= 1e-10
+    assert np.all(st["flag"] == rst["flag"])
+    assert np.all(np.abs(st["iterations"] - rst["iterations"]) <= 1)
+
+
+@pytest.mark.parametrize("precision", [abd.FP64, abd.MIXED])
+def test_config2_subset_teacher_forced(precision):
+    wl = W.config(2, n_models=128)
+    orc = Oracle(wl.model)
+    dt = wl.step.dt
+    qs, _ = orc.rollout(wl.q0, 3, dt)
+    say(f"config2 subset teacher-forced precision={precision}")
+    for k in (0, 3):
+        qp, qc = qs[max(k - 1, 0)], qs[k]
+        ref, rst = orc.step(qp, qc, dt)
+        out, st = _step_gpu(wl.model, qp, qc, abd.StepOptions(dt=dt, precision=precision))
+        if precision == abd.FP64:
+            assert rel_q(out, ref) <= 1e-10, (k, rel_q(out, ref))
+            assert np.mean(st["iterations"] == rst["iterations"]) > 0.9
+        else:
+            ex, eR = pose_error(orc, wl.model, out, ref)
+            assert ex <= 1e-5 and eR <= 1e-5, (k, ex, eR)
+        assert np.all(st["flag"] == 1), np.unique(st["flag"], return_counts=True)
+
+
+def test_ragged_mixed_joint_chains_fp64():
+    d = mixed_chains(64, 11)
+    rng = np.random.default_rng(12)
+    qc = rng.uniform(-1, 1, d.n_dofs)
+    qp = qc - 0.02 * rng.uniform(-1, 1, d.n_dofs)
+    tau = rng.uniform(-1, 1, d.n_dofs)
+    say(f"ragged hinge/ball chains dofs={d.n_dofs}")
+    ref, rst = Oracle(d).step(qp, qc, 0.04, tau=tau)
+    out, st = _step_gpu(d, qp, qc, abd.StepOptions(dt=0.04), tau=tau)
+    assert rel_q(out, ref) <= 1e-10
+    assert np.all(st["flag"] == rst["flag"])
+
+
+def test_identity_preconditioner_fp64():
+    wl = W.config(1)
+    q = wl.q0
+    say("identity preconditioner")
+    ref, rst = Oracle(wl.model).step(q, q, wl.step.dt, precond=0, max_iter=2000)
+    out, st = _step_gpu(wl.model, q, q, abd.StepOptions(dt=wl.step.dt, precond=abd.PRECOND_IDENTITY,
+                                                         max_iter=2000))
+    assert st["flag"][0] == rst["flag"][0]
+    assert rel_q(out, ref) <= 1e-8
+
+
+def test_full_config2_sampled_fp64_and_mixed():
+    wl = W.config(2)
+    dt = wl.step.dt
+    say(f"config2 full size: {wl.model.n_models} models, {wl.model.n_dofs} dofs")
+    sample = np.arange(0, wl.model.n_models, 64)
+    sub = wl.model.subset(sample)
+    idx = wl.model.dof_subset_index(sample)
+    orc = Oracle(sub)
+    ref, rst = orc.step(wl.q0[idx], wl.q0[idx], dt)
+    for precision in (abd.FP64, abd.MIXED):
+        out, st = _step_gpu(wl.model, wl.q0, wl.q0, abd.StepOptions(dt=dt, precision=precision))
+        assert np.all(st["flag"] == 1), np.unique(st["flag"], return_counts=True)
+        if precision == abd.FP64:
+            assert rel_q(out[idx], ref) <= 1e-10
+        else:
+            ex, eR = pose_error(orc, sub, out[idx], ref)
+            assert ex <= 1e-5 and eR <= 1e-5
+
+
+# ------------------------------------------------------------- edge cases
+def test_empty_batch():
+    d = W.random_chain_models(0, 1)
+    m = abd.Model(d)
+    assert m.n_models == 0
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hist = torch.zeros(2, dtype=torch.float64, device="cuda")
+    # zero DOFs: the call is a no-op
+    abd.load().abd_step(m._h, abd.StepOptions(dt=0.1).c(), abd._ptr(hist), None, abd._ptr(out), None,
+                        abd._stream())
+
+
+def test_64_dofs_is_the_limit():
+    d = W.random_chain_models(2, 3, lo=64, hi=64)
+    abd.Model(d)
+    d65 = W.random_chain_models(1, 3, lo=65, hi=65)
+    with pytest.raises(abd.AbdError) as e:
+        abd.Model(d65)
+    assert e.value.code == abd.ABD_ENOTSUP
+
+
+def test_zero_gravity_rest_is_exact_fixed_point():
+    d = mixed_chains(16, 21)
+    d.gravity = np.zeros(3)
+    q = np.random.default_rng(3).uniform(-1, 1, d.n_dofs)
+    out, st = _step_gpu(d, q, q, abd.StepOptions(dt=0.1))
+    assert np.array_equal(out, q)
+    assert np.all(st["iterations"] == 0) and np.all(st["flag"] == 1)
+
+
+def test_nonfinite_model_is_isolated():
+    d = mixed_chains(8, 5)
+    q = np.random.default_rng(4).uniform(-1, 1, d.n_dofs)
+    qb = q.copy()
+    qb[d.dof_offset[3]] = np.nan
+    out, st = _step_gpu(d, q, qb, abd.StepOptions(dt=0.05))
+    assert st["flag"][3] == abd.FLAG_NONFINITE
+    others = [i for i in range(d.n_models) if i != 3]
+    assert np.all(st["flag"][others] == abd.FLAG_CONVERGED)
+
+
+def test_max_iter_zero_and_one():
+    wl = W.config(2, n_models=16)
+    q = wl.q0
+    out, st = _step_gpu(wl.model, q, q, abd.StepOptions(dt=wl.step.dt, max_iter=0))
+    assert np.all(st["flag"] == abd.FLAG_MAX_ITER) and np.all(st["iterations"] == 0)
+    assert np.array_equal(out, q)  # warm start with zero velocity is q itself
+    ref, rst = Oracle(wl.model).step(q, q, wl.step.dt, max_iter=1)
+    out, st = _step_gpu(wl.model, q, q, abd.StepOptions(dt=wl.step.dt, max_iter=1))
+    assert np.all(st["flag"] == rst["flag"])
+    assert rel_q(out, ref) <= 1e-10
+
+
+def test_invalid_options_rejected():
+    d = mixed_chains(2, 1)
+    m = abd.Model(d)
+    hist = torch.zeros(2 * d.n_dofs, dtype=torch.float64, device="cuda")
+    out = torch.zeros(d.n_dofs, dtype=torch.float64, device="cuda")
+    for bad in (dict(dt=0.0), dict(dt=0.1, lbfgs_m=11), dict(dt=0.1, max_ls=0), dict(dt=0.1, precision=7),
+                dict(dt=0.1, precond=1)):
+        with pytest.raises(abd.AbdError) as e:
+            m.step(hist, out, abd.StepOptions(**bad))
+        assert e.value.code == abd.ABD_EINVAL
+    with pytest.raises(abd.AbdError) as e:
+        m.step(hist, out, abd.StepOptions(dt=0.1, order_K=4))
+    assert e.value.code == abd.ABD_ENOTSUP
