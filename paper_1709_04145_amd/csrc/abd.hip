@@ -59,7 +59,6 @@ constexpr int kWave = 64;
 constexpr int kMaxFrames = 64;  // frames (DOFs) per model handled by one wavefront
 constexpr int kG = 8;           // models per workgroup in the step kernel
 constexpr int kMaxHist = 10;    // longest L-BFGS history
-constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 // ------------------------------------------------------------------ DPP --
 // update_dpp keeps `old` in lanes whose source is out of the row (bound_ctrl
@@ -162,12 +161,85 @@ __device__ __forceinline__ Xf<R> wave_prefix_compose(Xf<R> x) {
   return x;
 }
 
-// sin and cos of half the joint angle.  float32: reduce modulo 2 pi in float64
-// first so that large angles keep their accuracy.
-__device__ __forceinline__ void half_sincos(double q, double& s, double& c) { sincos(0.5 * q, &s, &c); }
-__device__ __forceinline__ void half_sincos(double q, float& s, float& c) {
-  const double r = q - kTwoPi * rint(q * (1.0 / kTwoPi));
-  sincosf((float)(0.5 * r), &s, &c);
+// sin and cos of half the joint angle without the math library's general
+// argument path: Cody-Waite reduction of x = q/2 by pi/2 (pi/2 split into a
+// 30-bit, a 30-bit and a 53-bit part, exact products for |k| < 2^23, i.e.
+// |q| < ~1e7 rad), then Taylor series of sin and cos on [-pi/4, pi/4]
+// (float64: through r^17 and r^16; float32: through r^11 and r^10, evaluated
+// in float32 after the float64 reduction).
+constexpr double kTwoOverPi = 0.6366197723675814;
+constexpr double kPio2Hi = 0x1.921fb54800000p+0;
+constexpr double kPio2Mid = -0x1.de973dc800000p-31;
+constexpr double kPio2Lo = -0x1.9d9cceba3f91fp-62;
+
+constexpr double inv_fact(int n) { return n <= 1 ? 1.0 : inv_fact(n - 1) / n; }
+// 1/n!, forced to compile-time constants
+template <int N>
+struct InvFact {
+  static constexpr double value = inv_fact(N);
+};
+
+__device__ __forceinline__ double reduce_pio2(double x, int& quadrant) {
+  const double k = rint(x * kTwoOverPi);
+  double r = fma(-k, kPio2Hi, x);
+  r = fma(-k, kPio2Mid, r);
+  r = fma(-k, kPio2Lo, r);
+  quadrant = ((int)k) & 3;
+  return r;
+}
+
+template <typename R>
+__device__ __forceinline__ void sincos_poly(R r, R& sr, R& cr);
+template <>
+__device__ __forceinline__ void sincos_poly<double>(double r, double& sr, double& cr) {
+  const double z = r * r;
+  double ps = -InvFact<17>::value;
+  ps = fma(ps, z, InvFact<15>::value);
+  ps = fma(ps, z, -InvFact<13>::value);
+  ps = fma(ps, z, InvFact<11>::value);
+  ps = fma(ps, z, -InvFact<9>::value);
+  ps = fma(ps, z, InvFact<7>::value);
+  ps = fma(ps, z, -InvFact<5>::value);
+  ps = fma(ps, z, InvFact<3>::value);
+  sr = fma(-r * z, ps, r);  // r - r^3/3! + ...
+  double pc = InvFact<16>::value;
+  pc = fma(pc, z, -InvFact<14>::value);
+  pc = fma(pc, z, InvFact<12>::value);
+  pc = fma(pc, z, -InvFact<10>::value);
+  pc = fma(pc, z, InvFact<8>::value);
+  pc = fma(pc, z, -InvFact<6>::value);
+  pc = fma(pc, z, InvFact<4>::value);
+  pc = fma(pc, z, -0.5);
+  cr = fma(z, pc, 1.0);
+}
+template <>
+__device__ __forceinline__ void sincos_poly<float>(float r, float& sr, float& cr) {
+  const float z = r * r;
+  float ps = -(float)InvFact<11>::value;
+  ps = fmaf(ps, z, (float)InvFact<9>::value);
+  ps = fmaf(ps, z, -(float)InvFact<7>::value);
+  ps = fmaf(ps, z, (float)InvFact<5>::value);
+  ps = fmaf(ps, z, -(float)InvFact<3>::value);
+  sr = fmaf(r * z, ps, r);
+  float pc = -(float)InvFact<10>::value;
+  pc = fmaf(pc, z, (float)InvFact<8>::value);
+  pc = fmaf(pc, z, -(float)InvFact<6>::value);
+  pc = fmaf(pc, z, (float)InvFact<4>::value);
+  pc = fmaf(pc, z, -0.5f);
+  cr = fmaf(z, pc, 1.0f);
+}
+
+template <typename R>
+__device__ __forceinline__ void half_sincos(double q, R& s, R& c) {
+  int quadrant;
+  const double r = reduce_pio2(0.5 * q, quadrant);
+  R sr, cr;
+  sincos_poly<R>((R)r, sr, cr);
+  // x = k pi/2 + r
+  const R s0 = (quadrant & 1) ? cr : sr;
+  const R c0 = (quadrant & 1) ? sr : cr;
+  s = (quadrant & 2) ? -s0 : s0;
+  c = ((quadrant + 1) & 2) ? -c0 : c0;
 }
 
 // Local transform of a hinge frame: [Rot(a, q) | o], Rot = cI + s[a]x + (1-c) a a^T
