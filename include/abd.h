@@ -114,6 +114,19 @@ int abd_model_info(const abd_model* model, int* n_models, int* n_links, int* n_d
 int abd_step(abd_model* model, const abd_step_opts* opts, const double* q_hist,
              const double* tau, double* q_out, abd_step_stats* stats, void* stream);
 
+/* n_steps consecutive time steps in one launch (a rollout).  Every model
+ * advances through the steps at its own pace, so a model whose step needs many
+ * iterations does not hold back the others between steps (the anti-starvation
+ * scheme of Sec. 5's GPU implementation: work is interleaved per iteration).
+ *   q_init : [2*n_dofs] = q_{-1} followed by q_0
+ *   tau    : [n_steps*n_dofs] joint forces of every step, or NULL
+ *   q_traj : [n_steps*n_dofs] receives q_1 .. q_{n_steps}; must not overlap q_init
+ *   stats  : [n_steps*n_models] per-step outcome, or NULL
+ * abd_step is the n_steps = 1 case. */
+int abd_rollout(abd_model* model, const abd_step_opts* opts, const double* q_init,
+                const double* tau, double* q_traj, abd_step_stats* stats, int n_steps,
+                void* stream);
+
 /* Objective and gradient without optimization (Eq. EQ scaled by dt^2; gradient by
  * the adjoint backward pass of Alg. 1).
  *   q      : [n_dofs] configuration to evaluate

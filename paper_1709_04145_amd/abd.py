@@ -52,6 +52,8 @@ _PROTOS = {
     "abd_model_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "abd_step": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
+    "abd_rollout": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_int, C.c_void_p]),
     "abd_objective_grad": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "abd_poses": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -197,25 +199,44 @@ class Model:
         _check(load().abd_poses(self._h, _ptr(q), _ptr(out), _stream(stream)))
         return out[:self.n_links]
 
-    def rollout(self, q0: torch.Tensor, steps: int, opts: StepOptions, q_init_prev=None, torque=None,
-                collect_stats: bool = True):
-        """States [steps+1, n_dofs] from q0 (zero initial velocity unless q_init_prev is given).
+    def rollout(self, q_init: torch.Tensor, steps: int, opts: StepOptions, torque=None,
+                q_traj: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None, stream=None):
+        """Enqueue `steps` time steps in one launch (abd_rollout).
 
-        The trajectory buffer holds [q_{-1}, q_0, q_1, ...] so that every step reads
-        its history [q_{k-1}; q_k] in place and writes q_{k+1} after it."""
+        q_init = [q_{-1}; q_0] (2*n_dofs); torque [steps, n_dofs] or None.
+        Returns (q_traj [steps, n_dofs] = q_1..q_steps, stats buffer [steps*n_models] or None)."""
+        n = self.n_dofs
+        _dev_f64(q_init, 2 * n, "q_init")
+        if q_traj is None:
+            q_traj = torch.empty((max(1, steps), n), dtype=torch.float64, device="cuda")
+        if torque is not None:
+            _dev_f64(torque, steps * n, "torque")
+        if stats is not None and stats.numel() * stats.element_size() < 32 * self.n_models * steps:
+            raise ValueError("stats must hold 32 bytes per model and step")
+        o = opts.c()
+        _check(load().abd_rollout(self._h, C.byref(o), _ptr(q_init), _ptr(torque), _ptr(q_traj), _ptr(stats),
+                                  int(steps), _stream(stream)))
+        return q_traj[:steps], stats
+
+    def new_rollout_stats(self, steps: int) -> torch.Tensor:
+        return torch.zeros((max(1, steps * self.n_models), 4), dtype=torch.float64, device="cuda")
+
+    def read_rollout_stats(self, stats: torch.Tensor, steps: int) -> np.ndarray:
+        return self.read_stats(stats, steps * self.n_models).reshape(steps, self.n_models)
+
+    def step_loop(self, q0: torch.Tensor, steps: int, opts: StepOptions, q_init_prev=None, torque=None):
+        """Trajectory q_0..q_steps from one abd_step call per step (zero initial velocity
+        unless q_init_prev is given); the buffer holds [q_{-1}, q_0, q_1, ...] so every
+        step reads [q_{k-1}; q_k] in place."""
         n = self.n_dofs
         buf = torch.empty((steps + 2, n), dtype=torch.float64, device="cuda")
         buf[1] = q0
         buf[0] = q0 if q_init_prev is None else q_init_prev
         stats = []
         for k in range(steps):
-            st = self.new_stats() if collect_stats else None
+            st = self.new_stats()
             tau = None if torque is None else torque[k]
             self.step(buf[k:k + 2].reshape(-1), buf[k + 2], opts, tau=tau, stats=st)
-            if collect_stats:
-                stats.append(st)
-        out = buf[1:]
-        if collect_stats:
-            torch.cuda.synchronize()
-            stats = [self.read_stats(s, self.n_models) for s in stats]
-        return out, stats
+            stats.append(st)
+        torch.cuda.synchronize()
+        return buf[1:], [self.read_stats(s, self.n_models) for s in stats]

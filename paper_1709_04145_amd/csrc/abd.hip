@@ -411,11 +411,12 @@ struct StepArgs {
   DevModel d;
   double dt2, tol;
   int m, max_iter, max_ls, precond;
-  const double* q_prev;
-  const double* q_curr;
-  const double* tau;
-  double* q_out;
-  abd_step_stats* stats;
+  int n_steps;                // time steps in this launch
+  const double* q_prev;       // q_{-1}
+  const double* q_curr;       // q_0
+  const double* tau;          // [n_steps][n_dofs] or NULL
+  double* q_out;              // [n_steps][n_dofs]: q_1 .. q_{n_steps}
+  abd_step_stats* stats;      // [n_steps][n_models] or NULL
 };
 
 // Per-frame table of the articulated-body sweeps (LDS), per model slot:
@@ -432,27 +433,38 @@ struct SweepLds {
 // Articulated inertias at the warm start (once per step), lane = model slot:
 //   I^A_f = I_f + P_{f+1},  U_f = I^A_f s_f,  D_f = s_f.U_f,
 //   P_f = I^A_f - U_f U_f^T / D_f  (passed to the parent frame).
-// The 6x6 symmetric I^A is held as ww (6), wv (3x3), vv (6).
+// The 6x6 symmetric I^A is held as ww (6), wv (3x3), vv (6).  The inputs of
+// frame f-1 are loaded while frame f is processed.
 template <int G>
 __device__ void aba_setup(SweepLds<G>& L, const DevModel& d, int slot) {
   const int nf = L.nf[slot], f0 = L.f0[slot];
+  if (nf <= 0) return;
   // P holds the articulated inertia passed up from the child frame, then I^A in place:
   // ww = P[0..5] (00 01 02 11 12 22), wv = P[6..14] (3x3 row-major), vv = P[15..20]
   double P[21];
 #pragma unroll
   for (int k = 0; k < 21; ++k) P[k] = 0.0;
+  double in[10], s[6];
+  {
+    const double* src = d.inert + (size_t)(f0 + nf - 1) * 10;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) in[k] = src[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] = L.tab[k][nf - 1][slot];
+  }
   for (int f = nf - 1; f >= 0; --f) {
-    const double* in = d.inert + (size_t)(f0 + f) * 10;
+    double inn[10], sn[6];
+    const int fn = f > 0 ? f - 1 : 0;
+    const double* src = d.inert + (size_t)(f0 + fn) * 10;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) inn[k] = src[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sn[k] = L.tab[k][fn][slot];
     // add I = [[J, [h]x], [[h]x^T, m 1]]
 #pragma unroll
     for (int k = 0; k < 6; ++k) P[k] += in[k];
-    const double h0 = in[6], h1 = in[7], h2 = in[8];
-    const double ms = in[9];
-    P[7] -= h2; P[8] += h1; P[9] += h2; P[11] -= h0; P[12] -= h1; P[13] += h0;
-    P[15] += ms; P[18] += ms; P[20] += ms;
-    double s[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) s[k] = L.tab[k][f][slot];
+    P[7] -= in[8]; P[8] += in[7]; P[9] += in[8]; P[11] -= in[6]; P[12] -= in[7]; P[13] += in[6];
+    P[15] += in[9]; P[18] += in[9]; P[20] += in[9];
     double U[6];
     U[0] = P[0] * s[0] + P[1] * s[1] + P[2] * s[2] + P[6] * s[3] + P[7] * s[4] + P[8] * s[5];
     U[1] = P[1] * s[0] + P[3] * s[1] + P[4] * s[2] + P[9] * s[3] + P[10] * s[4] + P[11] * s[5];
@@ -460,54 +472,74 @@ __device__ void aba_setup(SweepLds<G>& L, const DevModel& d, int slot) {
     U[3] = P[6] * s[0] + P[9] * s[1] + P[12] * s[2] + P[15] * s[3] + P[16] * s[4] + P[17] * s[5];
     U[4] = P[7] * s[0] + P[10] * s[1] + P[13] * s[2] + P[16] * s[3] + P[18] * s[4] + P[19] * s[5];
     U[5] = P[8] * s[0] + P[11] * s[1] + P[14] * s[2] + P[17] * s[3] + P[19] * s[4] + P[20] * s[5];
-    const double D = s[0] * U[0] + s[1] * U[1] + s[2] * U[2] + s[3] * U[3] + s[4] * U[4] + s[5] * U[5];
+    const double D = (s[0] * U[0] + s[1] * U[1]) + (s[2] * U[2] + s[3] * U[3]) + (s[4] * U[4] + s[5] * U[5]);
     const double iD = (D > 0.0) ? 1.0 / D : 0.0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) L.tab[6 + k][f][slot] = U[k];
     L.tab[12][f][slot] = iD;
     // P <- I^A - U U^T / D  (the articulated inertia seen by the parent)
-    P[0] -= U[0] * U[0] * iD; P[1] -= U[0] * U[1] * iD; P[2] -= U[0] * U[2] * iD;
-    P[3] -= U[1] * U[1] * iD; P[4] -= U[1] * U[2] * iD; P[5] -= U[2] * U[2] * iD;
+    double V[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) V[k] = U[k] * iD;
+    P[0] -= U[0] * V[0]; P[1] -= U[0] * V[1]; P[2] -= U[0] * V[2];
+    P[3] -= U[1] * V[1]; P[4] -= U[1] * V[2]; P[5] -= U[2] * V[2];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) P[6 + 3 * r + c] -= U[r] * U[3 + c] * iD;
-    P[15] -= U[3] * U[3] * iD; P[16] -= U[3] * U[4] * iD; P[17] -= U[3] * U[5] * iD;
-    P[18] -= U[4] * U[4] * iD; P[19] -= U[4] * U[5] * iD; P[20] -= U[5] * U[5] * iD;
+      for (int c = 0; c < 3; ++c) P[6 + 3 * r + c] -= U[r] * V[3 + c];
+    P[15] -= U[3] * V[3]; P[16] -= U[3] * V[4]; P[17] -= U[3] * V[5];
+    P[18] -= U[4] * V[4]; P[19] -= U[4] * V[5]; P[20] -= U[5] * V[5];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) in[k] = inn[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] = sn[k];
   }
 }
 
 // x = H^{-1} b in O(n): backward sweep u_f = b_f - s_f.p, p <- p + U_f u_f / D_f;
 // forward sweep x_f = (u_f - U_f.a) / D_f, a <- a + s_f x_f.  In place in xb.
+// The table entries of the next frame are read while the current one is used.
 template <int G>
 __device__ void aba_solve(SweepLds<G>& L, int slot) {
   const int nf = L.nf[slot];
-  double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p5 = 0;
+  if (nf <= 0) return;
+  double p[6] = {0, 0, 0, 0, 0, 0};
+  double t[14];
+#pragma unroll
+  for (int k = 0; k < 13; ++k) t[k] = L.tab[k][nf - 1][slot];
+  t[13] = L.xb[nf - 1][slot];
   for (int f = nf - 1; f >= 0; --f) {
-    const double u = L.xb[f][slot] - (L.tab[0][f][slot] * p0 + L.tab[1][f][slot] * p1 + L.tab[2][f][slot] * p2 +
-                                      L.tab[3][f][slot] * p3 + L.tab[4][f][slot] * p4 + L.tab[5][f][slot] * p5);
+    double tn[14];
+    const int fn = f > 0 ? f - 1 : 0;
+#pragma unroll
+    for (int k = 0; k < 13; ++k) tn[k] = L.tab[k][fn][slot];
+    tn[13] = L.xb[fn][slot];
+    const double sp = (t[0] * p[0] + t[1] * p[1]) + (t[2] * p[2] + t[3] * p[3]) + (t[4] * p[4] + t[5] * p[5]);
+    const double u = t[13] - sp;
     L.xb[f][slot] = u;
-    const double w = u * L.tab[12][f][slot];
-    p0 += L.tab[6][f][slot] * w;
-    p1 += L.tab[7][f][slot] * w;
-    p2 += L.tab[8][f][slot] * w;
-    p3 += L.tab[9][f][slot] * w;
-    p4 += L.tab[10][f][slot] * w;
-    p5 += L.tab[11][f][slot] * w;
+    const double w = u * t[12];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] += t[6 + k] * w;
+#pragma unroll
+    for (int k = 0; k < 14; ++k) t[k] = tn[k];
   }
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+  double a[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 13; ++k) t[k] = L.tab[k][0][slot];
+  t[13] = L.xb[0][slot];
   for (int f = 0; f < nf; ++f) {
-    const double x = (L.xb[f][slot] - (L.tab[6][f][slot] * a0 + L.tab[7][f][slot] * a1 + L.tab[8][f][slot] * a2 +
-                                       L.tab[9][f][slot] * a3 + L.tab[10][f][slot] * a4 +
-                                       L.tab[11][f][slot] * a5)) *
-                     L.tab[12][f][slot];
+    double tn[14];
+    const int fn = f + 1 < nf ? f + 1 : f;
+#pragma unroll
+    for (int k = 0; k < 13; ++k) tn[k] = L.tab[k][fn][slot];
+    tn[13] = L.xb[fn][slot];
+    const double Ua = (t[6] * a[0] + t[7] * a[1]) + (t[8] * a[2] + t[9] * a[3]) + (t[10] * a[4] + t[11] * a[5]);
+    const double x = (t[13] - Ua) * t[12];
     L.xb[f][slot] = x;
-    a0 += L.tab[0][f][slot] * x;
-    a1 += L.tab[1][f][slot] * x;
-    a2 += L.tab[2][f][slot] * x;
-    a3 += L.tab[3][f][slot] * x;
-    a4 += L.tab[4][f][slot] * x;
-    a5 += L.tab[5][f][slot] * x;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[k] += t[k] * x;
+#pragma unroll
+    for (int k = 0; k < 14; ++k) t[k] = tn[k];
   }
 }
 
@@ -592,13 +624,24 @@ __device__ __forceinline__ void step_setup(const DevModel& d, SweepLds<G>& L, in
 
 // What the next evaluation of phase C is for.
 enum EvalPurpose { kTrial = 0, kRefresh = 1, kRefreshRetry = 2 };
+// Per-model state of the rollout kernel.
+enum ModelState { kSetup = 0, kIterate = 1, kDone = 2 };
 
-// One time step.  MIXED: float32 evaluations until the line search meets float32
-// rounding (or float32 claims convergence), then float64 to the end.
+// A rollout of n_steps time steps.  Every model advances through the steps at
+// its own pace: a model whose step has converged starts its next step in the
+// following round while the other models of the workgroup keep iterating
+// (the per-iteration interleaving of Sec. 5's GPU scheme, inside one launch).
+// A round is: phase A (per model wave: step setup, or the first loop of the
+// two-loop recursion), barrier, phase B (wave 0: articulated-body recursion or
+// sweeps for every model slot that asks), barrier, phase C (per model wave:
+// first evaluation of a step, or second loop + line search + update).
+// MIXED: float32 evaluations until the line search meets float32 rounding (or
+// float32 claims convergence), then float64 to the end of the step.
 template <int G, int MMAX, int PREC>
-__global__ void __launch_bounds__(G* kWave) k_step(StepArgs args) {
+__global__ void __launch_bounds__(G* kWave) k_rollout(StepArgs args) {
   __shared__ SweepLds<G> L;
   const DevModel& d = args.d;
+  const int n = d.n_dofs;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int model = blockIdx.x * G + wave;
   const bool has_model = model < d.n_models;
@@ -611,61 +654,34 @@ __global__ void __launch_bounds__(G* kWave) k_step(StepArgs args) {
     L.nf[wave] = nf;
     L.f0[wave] = f0;
   }
-
-  const double qkm1 = valid ? args.q_prev[f] : 0.0;
-  const double qk = valid ? args.q_curr[f] : 0.0;
-  double q = valid ? 2.0 * qk - qkm1 : 0.0;  // warm start: constant-velocity extrapolation
-  const double tau = (valid && args.tau) ? args.tau[f] : 0.0;
-  if (nf > 0) step_setup<G>(d, L, f, valid, wave, lane, qkm1, qk, q, use_aba);
-  __syncthreads();
-  if (use_aba && wave == 0 && lane < G && L.nf[lane] > 0) aba_setup<G>(L, d, lane);
-  __syncthreads();
-
   const double eps_w = PREC == ABD_MIXED ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
-  bool f32 = PREC == ABD_MIXED;
-  int iters = 0, evals = 0, flag = 0, f32_iters = 0;
-  double E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0;
-  bool active = nf > 0;
-  if (nf == 0 && has_model) flag = ABD_FLAG_CONVERGED;
-  if (active) {
-    const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(d, f, valid, q, tau, args.dt2)
-                                              : evaluate<double>(d, f, valid, q, tau, args.dt2);
-    ++evals;
-    E = r.E;
-    g = r.g;
-    if (!isfinite(E) || !all_finite(g)) {
-      flag = ABD_FLAG_NONFINITE;
-      active = false;
-    } else {
-      g0 = uniform(sqrt(wave_sum(g * g)));
-      gn = g0;
-      if (g0 == 0.0) {
-        flag = ABD_FLAG_CONVERGED;
-        active = false;
-      } else if (args.max_iter <= 0) {
-        flag = ABD_FLAG_MAX_ITER;
-        active = false;
-      }
-    }
-  }
+  const double c1 = 1e-4, dlt = 0.1;
 
-  // history: vectors in a per-frame ring buffer in device memory (slot `head` is
-  // the newest pair), scalars rho_i = 1/(s_i.y_i) newest-first in registers
+  // history of the current step (registers), q_{k-1} and q_k
+  double qkm1 = valid ? args.q_prev[f] : 0.0;
+  double qk = valid ? args.q_curr[f] : 0.0;
+  int step = 0;
+  int state = has_model ? kSetup : kDone;
+  if (has_model && args.n_steps <= 0) state = kDone;
+
+  // per-step solver state
   double* hs = d.hist + (size_t)f * (2 * kMaxHist);
   double rho[MMAX], alp[MMAX];
 #pragma unroll
   for (int k = 0; k < MMAX; ++k) {
     rho[k] = 0.0; alp[k] = 0.0;
   }
-  double gam = 1.0;  // s^T y / y^T y of the newest pair (identity preconditioner)
-  int count = 0, head = 0;
-  bool reset = false;  // redo the direction with an empty history
-  double qv = 0.0;
-  const double c1 = 1e-4, dlt = 0.1;
+  bool f32 = false, reset = false;
+  int iters = 0, evals = 0, flag = 0, f32_iters = 0, count = 0, head = 0;
+  double q = 0.0, tau = 0.0, E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0, qv = 0.0;
 
   for (;;) {
-    // phase A: first loop of the two-loop recursion (newest pair first)
-    if (active) {
+    // ------------------------------------------------------------ phase A
+    if (state == kSetup) {
+      q = valid ? 2.0 * qk - qkm1 : 0.0;  // warm start: constant-velocity extrapolation
+      tau = (valid && args.tau) ? args.tau[(size_t)step * n + f] : 0.0;
+      if (nf > 0) step_setup<G>(d, L, f, valid, wave, lane, qkm1, qk, q, use_aba);
+    } else if (state == kIterate) {
       if (reset) count = 0;
       qv = g;
 #pragma unroll
@@ -678,13 +694,47 @@ __global__ void __launch_bounds__(G* kWave) k_step(StepArgs args) {
         }
       if (use_aba) L.xb[lane][wave] = valid ? qv : 0.0;
     }
-    if (lane == 0) L.req[wave] = (active && use_aba) ? 1 : 0;
+    if (lane == 0) L.req[wave] = (use_aba && nf > 0) ? (state == kSetup ? 2 : state == kIterate ? 1 : 0) : 0;
     __syncthreads();
-    // phase B: apply the inverse joint-space inertia, one lane per model
-    if (wave == 0 && lane < G && L.req[lane]) aba_solve<G>(L, lane);
+    // ------------------------------------------------------------ phase B
+    if (wave == 0 && lane < G) {
+      if (L.req[lane] == 2) aba_setup<G>(L, d, lane);
+      else if (L.req[lane] == 1) aba_solve<G>(L, lane);
+    }
     __syncthreads();
-    // phase C: second loop, line search, update
-    if (active) {
+    // ------------------------------------------------------------ phase C
+    bool step_done = false;
+    if (state == kSetup) {
+      f32 = PREC == ABD_MIXED;
+      iters = 0; evals = 0; flag = 0; f32_iters = 0; count = 0; head = 0; reset = false; gam = 1.0;
+      if (nf == 0) {
+        flag = ABD_FLAG_CONVERGED;
+        step_done = true;
+      } else {
+        const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(d, f, valid, q, tau, args.dt2)
+                                                  : evaluate<double>(d, f, valid, q, tau, args.dt2);
+        ++evals;
+        E = r.E;
+        g = r.g;
+        gn = 0.0;
+        if (!isfinite(E) || !all_finite(g)) {
+          flag = ABD_FLAG_NONFINITE;
+          step_done = true;
+        } else {
+          g0 = uniform(sqrt(wave_sum(g * g)));
+          gn = g0;
+          if (g0 == 0.0) {
+            flag = ABD_FLAG_CONVERGED;
+            step_done = true;
+          } else if (args.max_iter <= 0) {
+            flag = ABD_FLAG_MAX_ITER;
+            step_done = true;
+          } else {
+            state = kIterate;
+          }
+        }
+      }
+    } else if (state == kIterate) {
       double r = use_aba ? L.xb[lane][wave] : (count > 0 ? gam : 1.0) * qv;
 #pragma unroll
       for (int k = MMAX - 1; k >= 0; --k)
@@ -698,10 +748,10 @@ __global__ void __launch_bounds__(G* kWave) k_step(StepArgs args) {
       const double gd = uniform(wave_sum(g * dir));
       if (!(gd < 0.0)) {
         if (!reset) {
-          reset = true;
+          reset = true;  // redo the direction with an empty history
         } else {
           flag = ABD_FLAG_LS_FLOOR;
-          active = false;
+          step_done = true;
         }
       } else {
         reset = false;
@@ -725,10 +775,10 @@ __global__ void __launch_bounds__(G* kWave) k_step(StepArgs args) {
             if (purpose == kRefresh) {
               if (gn <= args.tol * g0) {
                 flag = ABD_FLAG_CONVERGED;
-                active = false;
+                step_done = true;
               } else if (iters >= args.max_iter) {
                 flag = ABD_FLAG_MAX_ITER;
-                active = false;
+                step_done = true;
               }
             }
             break;
@@ -752,7 +802,7 @@ __global__ void __launch_bounds__(G* kWave) k_step(StepArgs args) {
               continue;
             }
             flag = ABD_FLAG_LS_FLOOR;
-            active = false;
+            step_done = true;
             break;
           }
           // accepted: curvature pair and update
@@ -787,30 +837,33 @@ __global__ void __launch_bounds__(G* kWave) k_step(StepArgs args) {
           }
           if (conv) {
             flag = ABD_FLAG_CONVERGED;
-            active = false;
+            step_done = true;
           } else if (iters >= args.max_iter) {
             flag = ABD_FLAG_MAX_ITER;
-            active = false;
+            step_done = true;
           }
           break;
         }
       }
     }
-    if (!__syncthreads_or(active ? 1 : 0)) break;
-  }
-
-  if (has_model) {
-    if (valid) args.q_out[f] = q;
-    if (args.stats && lane == 0) {
-      abd_step_stats st;
-      st.iterations = iters;
-      st.evaluations = evals;
-      st.flag = flag;
-      st.f32_iterations = f32_iters;
-      st.grad_norm = gn;
-      st.energy = E;
-      args.stats[model] = st;
+    if (step_done) {
+      if (valid) args.q_out[(size_t)step * n + f] = q;
+      if (args.stats && lane == 0) {
+        abd_step_stats st;
+        st.iterations = iters;
+        st.evaluations = evals;
+        st.flag = flag;
+        st.f32_iterations = f32_iters;
+        st.grad_norm = gn;
+        st.energy = E;
+        args.stats[(size_t)step * d.n_models + model] = st;
+      }
+      qkm1 = qk;
+      qk = q;
+      ++step;
+      state = step < args.n_steps ? kSetup : kDone;
     }
+    if (!__syncthreads_or(state != kDone ? 1 : 0)) break;
   }
 }
 
@@ -1085,19 +1138,8 @@ int abd_model_info(const abd_model* m, int* n_models, int* n_links, int* n_dofs)
   return ABD_OK;
 }
 
-int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const double* tau, double* q_out,
-             abd_step_stats* stats, void* stream) {
-  g_err.clear();
-  if (!m) return fail(ABD_EINVAL, "model is NULL");
-  int rc = check_opts(o, true);
-  if (rc) return rc;
-  if (m->n_models == 0) return ABD_OK;
-  if (!q_hist || !q_out) return fail(ABD_EINVAL, "q_hist and q_out must not be NULL");
-  const double* q_prev = q_hist;
-  const double* q_curr = q_hist + m->n_dofs;
-  if (q_out < q_hist + 2 * (size_t)m->n_dofs && q_hist < q_out + m->n_dofs)
-    return fail(ABD_EINVAL, "q_out overlaps q_hist");
-  if ((rc = check_device(m))) return rc;
+static int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
+                          const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream) {
   StepArgs a;
   a.d = dev_view(m);
   a.dt2 = o->dt * o->dt;
@@ -1106,6 +1148,7 @@ int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const d
   a.max_iter = o->max_iter;
   a.max_ls = o->max_ls;
   a.precond = o->precond;
+  a.n_steps = n_steps;
   a.q_prev = q_prev;
   a.q_curr = q_curr;
   a.tau = tau;
@@ -1116,17 +1159,47 @@ int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const d
   const dim3 grid(blocks), block(kG * kWave);
   if (o->precision == ABD_FP64) {
     if (o->lbfgs_m <= 5)
-      hipLaunchKernelGGL((k_step<kG, 5, ABD_FP64>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_rollout<kG, 5, ABD_FP64>), grid, block, 0, s, a);
     else
-      hipLaunchKernelGGL((k_step<kG, 10, ABD_FP64>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_rollout<kG, 10, ABD_FP64>), grid, block, 0, s, a);
   } else {
     if (o->lbfgs_m <= 5)
-      hipLaunchKernelGGL((k_step<kG, 5, ABD_MIXED>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_rollout<kG, 5, ABD_MIXED>), grid, block, 0, s, a);
     else
-      hipLaunchKernelGGL((k_step<kG, 10, ABD_MIXED>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_rollout<kG, 10, ABD_MIXED>), grid, block, 0, s, a);
   }
   HIP_TRY(hipGetLastError());
   return ABD_OK;
+}
+
+int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const double* tau, double* q_out,
+             abd_step_stats* stats, void* stream) {
+  g_err.clear();
+  if (!m) return fail(ABD_EINVAL, "model is NULL");
+  int rc = check_opts(o, true);
+  if (rc) return rc;
+  if (m->n_models == 0) return ABD_OK;
+  if (!q_hist || !q_out) return fail(ABD_EINVAL, "q_hist and q_out must not be NULL");
+  if (q_out < q_hist + 2 * (size_t)m->n_dofs && q_hist < q_out + m->n_dofs)
+    return fail(ABD_EINVAL, "q_out overlaps q_hist");
+  if ((rc = check_device(m))) return rc;
+  return launch_rollout(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
+}
+
+int abd_rollout(abd_model* m, const abd_step_opts* o, const double* q_init, const double* tau, double* q_traj,
+                abd_step_stats* stats, int n_steps, void* stream) {
+  g_err.clear();
+  if (!m) return fail(ABD_EINVAL, "model is NULL");
+  int rc = check_opts(o, true);
+  if (rc) return rc;
+  if (n_steps < 0) return fail(ABD_EINVAL, "n_steps must be >= 0");
+  if (m->n_models == 0 || n_steps == 0) return ABD_OK;
+  if (!q_init || !q_traj) return fail(ABD_EINVAL, "q_init and q_traj must not be NULL");
+  const size_t nd = m->n_dofs;
+  if (q_traj < q_init + 2 * nd && q_init < q_traj + (size_t)n_steps * nd)
+    return fail(ABD_EINVAL, "q_traj overlaps q_init");
+  if ((rc = check_device(m))) return rc;
+  return launch_rollout(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
 }
 
 int abd_objective_grad(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,
