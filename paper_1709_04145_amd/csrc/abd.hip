@@ -60,6 +60,21 @@ constexpr int kMaxFrames = 64;  // frames (DOFs) per model handled by one wavefr
 constexpr int kG = 8;           // models per workgroup in the step kernel
 constexpr int kMaxHist = 10;    // longest L-BFGS history
 
+// Optional per-phase cycle counters (build with -DABD_PROFILE): lane 0 of every
+// model wave accumulates s_memtime deltas into abd_prof[model][slot].
+#ifdef ABD_PROFILE
+__device__ unsigned long long* abd_prof;
+#define PROF_T(var) unsigned long long var = __builtin_readcyclecounter()
+#define PROF_ADD(slot, t0)                                                          \
+  do {                                                                              \
+    if (lane == 0 && has_model)                                                     \
+      abd_prof[(size_t)model * 16 + (slot)] += __builtin_readcyclecounter() - (t0); \
+  } while (0)
+#else
+#define PROF_T(var)
+#define PROF_ADD(slot, t0)
+#endif
+
 // ------------------------------------------------------------------ DPP --
 // update_dpp keeps `old` in lanes whose source is out of the row (bound_ctrl
 // off) or whose row is masked off.
@@ -124,41 +139,67 @@ struct Xf {
   R m[12];
 };
 
+// Unit quaternion (w, x, y, z) of a rotation.
 template <typename R>
-__device__ __forceinline__ Xf<R> compose(const Xf<R>& a, const Xf<R>& b) {
-  Xf<R> c;
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-      c.m[4 * r + k] = a.m[4 * r] * b.m[k] + a.m[4 * r + 1] * b.m[4 + k] + a.m[4 * r + 2] * b.m[8 + k];
-    c.m[4 * r + 3] = a.m[4 * r] * b.m[3] + a.m[4 * r + 1] * b.m[7] + a.m[4 * r + 2] * b.m[11] + a.m[4 * r + 3];
-  }
+struct Quat {
+  R w, x, y, z;
+};
+
+// a (x) b : rotation b followed, in the frame of a, i.e. R(a) R(b)
+template <typename R>
+__device__ __forceinline__ Quat<R> qmul(const Quat<R>& a, const Quat<R>& b) {
+  Quat<R> c;
+  c.w = a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z;
+  c.x = a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y;
+  c.y = a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x;
+  c.z = a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w;
   return c;
 }
 
 template <typename R, int CTRL, int ROW_MASK>
-__device__ __forceinline__ Xf<R> dpp_xf(const Xf<R>& x) {
-  Xf<R> y;
-#pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    const R id = (k == 0 || k == 5 || k == 10) ? R(1) : R(0);
-    y.m[k] = dpp<CTRL, ROW_MASK>(id, x.m[k]);
-  }
+__device__ __forceinline__ Quat<R> dpp_quat(const Quat<R>& v) {
+  Quat<R> y;
+  y.w = dpp<CTRL, ROW_MASK>(R(1), v.w);
+  y.x = dpp<CTRL, ROW_MASK>(R(0), v.x);
+  y.y = dpp<CTRL, ROW_MASK>(R(0), v.y);
+  y.z = dpp<CTRL, ROW_MASK>(R(0), v.z);
   return y;
 }
 
-// A_j = T_0 T_1 ... T_j over the lanes (Alg. 1 forward pass as a scan; the
-// identity fills lanes whose source is outside the wave).
+// Q_j = r_0 (x) r_1 (x) ... (x) r_j over the lanes: the rotation part of Alg. 1's
+// forward pass T^j = T^{j-1} t_j as an inclusive prefix scan (row shifts 1,2,4,8,
+// then row broadcasts 15 and 31; the identity fills lanes without a source).
 template <typename R>
-__device__ __forceinline__ Xf<R> wave_prefix_compose(Xf<R> x) {
-  x = compose(dpp_xf<R, 0x111, 0xF>(x), x);
-  x = compose(dpp_xf<R, 0x112, 0xF>(x), x);
-  x = compose(dpp_xf<R, 0x114, 0xF>(x), x);
-  x = compose(dpp_xf<R, 0x118, 0xF>(x), x);
-  x = compose(dpp_xf<R, 0x142, 0xA>(x), x);
-  x = compose(dpp_xf<R, 0x143, 0xC>(x), x);
-  return x;
+__device__ __forceinline__ Quat<R> wave_prefix_quat(Quat<R> v) {
+  v = qmul(dpp_quat<R, 0x111, 0xF>(v), v);
+  v = qmul(dpp_quat<R, 0x112, 0xF>(v), v);
+  v = qmul(dpp_quat<R, 0x114, 0xF>(v), v);
+  v = qmul(dpp_quat<R, 0x118, 0xF>(v), v);
+  v = qmul(dpp_quat<R, 0x142, 0xA>(v), v);
+  v = qmul(dpp_quat<R, 0x143, 0xC>(v), v);
+  return v;
+}
+
+// Inclusive prefix sum in precision R (row shifts + row broadcasts).
+template <typename R>
+__device__ __forceinline__ R wave_prefix_sum_r(R v) {
+  v += dpp<0x111, 0xF>(R(0), v);
+  v += dpp<0x112, 0xF>(R(0), v);
+  v += dpp<0x114, 0xF>(R(0), v);
+  v += dpp<0x118, 0xF>(R(0), v);
+  v += dpp<0x142, 0xA>(R(0), v);
+  v += dpp<0x143, 0xC>(R(0), v);
+  return v;
+}
+
+// rotate v by the unit quaternion Q: v + 2w (u x v) + 2 u x (u x v), u = (x, y, z)
+template <typename R>
+__device__ __forceinline__ void qrotate(const Quat<R>& Q, const R v[3], R out[3]) {
+  const R c0 = Q.y * v[2] - Q.z * v[1], c1 = Q.z * v[0] - Q.x * v[2], c2 = Q.x * v[1] - Q.y * v[0];
+  const R d0 = Q.y * c2 - Q.z * c1, d1 = Q.z * c0 - Q.x * c2, d2 = Q.x * c1 - Q.y * c0;
+  out[0] = v[0] + R(2) * (Q.w * c0 + d0);
+  out[1] = v[1] + R(2) * (Q.w * c1 + d1);
+  out[2] = v[2] + R(2) * (Q.w * c2 + d2);
 }
 
 // sin and cos of half the joint angle without the math library's general
@@ -242,27 +283,22 @@ __device__ __forceinline__ void half_sincos(double q, R& s, R& c) {
   c = ((quadrant + 1) & 2) ? -c0 : c0;
 }
 
-// Local transform of a hinge frame: [Rot(a, q) | o], Rot = cI + s[a]x + (1-c) a a^T
-// with s = 2 sh ch, 1-c = 2 sh^2 (half-angle form keeps 1-c accurate).
+// Hinge rotation by q about the unit axis a: the quaternion (cos q/2, sin q/2 a).
 template <typename R>
-__device__ __forceinline__ Xf<R> hinge_transform(const R a[3], const R o[3], double q) {
+__device__ __forceinline__ Quat<R> hinge_quat(const R a[3], double q) {
   R sh, ch;
   half_sincos(q, sh, ch);
-  const R s = R(2) * sh * ch, omc = R(2) * sh * sh, c = R(1) - omc;
-  Xf<R> T;
-  T.m[0] = c + omc * a[0] * a[0];
-  T.m[1] = omc * a[0] * a[1] - s * a[2];
-  T.m[2] = omc * a[0] * a[2] + s * a[1];
-  T.m[4] = omc * a[0] * a[1] + s * a[2];
-  T.m[5] = c + omc * a[1] * a[1];
-  T.m[6] = omc * a[1] * a[2] - s * a[0];
-  T.m[8] = omc * a[0] * a[2] - s * a[1];
-  T.m[9] = omc * a[1] * a[2] + s * a[0];
-  T.m[10] = c + omc * a[2] * a[2];
-  T.m[3] = o[0];
-  T.m[7] = o[1];
-  T.m[11] = o[2];
-  return T;
+  Quat<R> r;
+  r.w = ch;
+  r.x = sh * a[0];
+  r.y = sh * a[1];
+  r.z = sh * a[2];
+  return r;
+}
+
+// index of S[x][y] in the 6-entry upper triangle of a symmetric 3x3 (00 01 02 11 12 22)
+__device__ __forceinline__ constexpr int sym3(int x, int y) {
+  return x <= y ? (x == 0 ? y : x == 1 ? 2 + y : 5) : sym3(y, x);
 }
 
 // index of M[x][y] in the 10-entry upper triangle
@@ -300,23 +336,57 @@ struct Arr<float> {
   static __device__ __forceinline__ const float* B(const DevModel& d) { return d.B32; }
 };
 
+// World pose A_j = [R_j | t_j] of every frame of this wave's model (Alg. 1
+// forward pass; frame j's joint is at its origin, offset o_j in the parent frame):
+//   R_j = R_{j-1} Rot(a_j, q_j)  -> prefix scan of hinge quaternions,
+//   t_j = t_{j-1} + R_{j-1} o_j  -> prefix sum of the parent-rotated offsets.
 template <typename R>
-__device__ __forceinline__ void load_frame(const DevModel& d, int f, bool valid, R a[3], R o[3]) {
-  const R* rec = Arr<R>::fr(d) + (size_t)f * 16;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    a[k] = valid ? rec[k] : R(0);
-    o[k] = valid ? rec[3 + k] : R(0);
-  }
+__device__ __forceinline__ Xf<R> forward_kinematics(const R a[3], const R o[3], bool valid, double q) {
+  Quat<R> Q = hinge_quat(a, valid ? q : 0.0);
+  if (!valid) Q = Quat<R>{R(1), R(0), R(0), R(0)};
+  Q = wave_prefix_quat(Q);
+  // parent rotation: the neighbour's prefix (identity for the root frame)
+  const Quat<R> Qp = dpp_quat<R, 0x138, 0xF>(Q);
+  R v[3];
+  qrotate(Qp, o, v);
+  Xf<R> A;
+  A.m[3] = wave_prefix_sum_r(v[0]);
+  A.m[7] = wave_prefix_sum_r(v[1]);
+  A.m[11] = wave_prefix_sum_r(v[2]);
+  const R xx = Q.x * Q.x, yy = Q.y * Q.y, zz = Q.z * Q.z;
+  const R xy = Q.x * Q.y, xz = Q.x * Q.z, yz = Q.y * Q.z;
+  const R wx = Q.w * Q.x, wy = Q.w * Q.y, wz = Q.w * Q.z;
+  A.m[0] = R(1) - R(2) * (yy + zz);
+  A.m[1] = R(2) * (xy - wz);
+  A.m[2] = R(2) * (xz + wy);
+  A.m[4] = R(2) * (xy + wz);
+  A.m[5] = R(1) - R(2) * (xx + zz);
+  A.m[6] = R(2) * (yz - wx);
+  A.m[8] = R(2) * (xz - wy);
+  A.m[9] = R(2) * (yz + wx);
+  A.m[10] = R(1) - R(2) * (xx + yy);
+  return A;
 }
 
-// World poses of the frames of this wave's model at q (float64 or float32).
+// axis and joint offset of this lane's frame (float64, kept in registers)
+struct FrameGeo {
+  double a[3], o[3];
+};
+__device__ __forceinline__ FrameGeo load_geo(const DevModel& d, int f, bool valid) {
+  FrameGeo g;
+  const double* rec = d.fr64 + (size_t)f * 16;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    g.a[k] = valid ? rec[k] : 0.0;
+    g.o[k] = valid ? rec[3 + k] : 0.0;
+  }
+  return g;
+}
 template <typename R>
-__device__ __forceinline__ Xf<R> forward_kinematics(const DevModel& d, int f, bool valid, double q) {
-  R a[3], o[3];
-  load_frame(d, f, valid, a, o);
-  Xf<R> T = hinge_transform(a, o, valid ? q : 0.0);
-  return wave_prefix_compose(T);
+__device__ __forceinline__ Xf<R> fk_geo(const FrameGeo& g, bool valid, double q) {
+  const R a[3] = {(R)g.a[0], (R)g.a[1], (R)g.a[2]};
+  const R o[3] = {(R)g.o[0], (R)g.o[1], (R)g.o[2]};
+  return forward_kinematics<R>(a, o, valid, q);
 }
 
 struct EvalResult {
@@ -327,19 +397,21 @@ struct EvalResult {
 
 // One objective + gradient evaluation for the model of this wave.
 template <typename R>
-__device__ EvalResult evaluate(const DevModel& d, int f, bool valid, double q, double tau, double dt2) {
+__device__ EvalResult evaluate(const DevModel& d, const FrameGeo& geo, int f, bool valid, double q, double tau,
+                               double dt2) {
   // keep the per-frame loads inside the evaluation (no hoisting across calls,
-  // which would pin them in registers for the whole solve)
+  // which would pin them in registers for the whole solve); they are issued
+  // first so that their latency overlaps the kinematics scan
   asm volatile("" ::: "memory");
-  R a[3], o[3];
-  load_frame(d, f, valid, a, o);
-  const Xf<R> A = wave_prefix_compose(hinge_transform(a, o, valid ? q : 0.0));
-
-  R M[10];
+  R M[10], Bn[4];
   const R* rec = Arr<R>::fr(d) + (size_t)f * 16;
   const R* Bp = Arr<R>::B(d) + (size_t)f * 12;
 #pragma unroll
   for (int k = 0; k < 10; ++k) M[k] = valid ? rec[6 + k] : R(0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Bn[k] = valid ? Bp[k] : R(0);
+  const Xf<R> A = fk_geo<R>(geo, valid, q);
+  const R a[3] = {(R)geo.a[0], (R)geo.a[1], (R)geo.a[2]};
 
   // Row r of D = A + B (= A(q) - 2A(q_k) + A(q_{k-1})), of D M and of the seed
   // G = dE/dA = D M - dt^2 g (M e4)^T; e = 1/2 tr(D M D^T) - dt^2 g^T A M e4.
@@ -353,7 +425,10 @@ __device__ EvalResult evaluate(const DevModel& d, int f, bool valid, double q, d
     const R gr = R(r == 0 ? d.gx : r == 1 ? d.gy : d.gz);
     R D[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) D[c] = A.m[4 * r + c] + (valid ? Bp[4 * r + c] : R(0));
+    for (int c = 0; c < 4; ++c) D[c] = A.m[4 * r + c] + Bn[c];
+    if (r < 2)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Bn[c] = valid ? Bp[4 * (r + 1) + c] : R(0);
     R AMe4 = R(0);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -425,6 +500,9 @@ template <int G>
 struct SweepLds {
   double tab[13][kMaxFrames][G];
   double xb[kMaxFrames][G];  // sweep input b, then u, then the output x
+  double P[21][G];           // articulated-inertia accumulator of the recursion
+  double rho[kMaxHist][G];   // 1/(s_i.y_i), newest first (per model slot)
+  double alp[kMaxHist][G];   // two-loop coefficients
   int nf[G];
   int f0[G];
   int req[G];
@@ -439,60 +517,55 @@ template <int G>
 __device__ void aba_setup(SweepLds<G>& L, const DevModel& d, int slot) {
   const int nf = L.nf[slot], f0 = L.f0[slot];
   if (nf <= 0) return;
-  // P holds the articulated inertia passed up from the child frame, then I^A in place:
-  // ww = P[0..5] (00 01 02 11 12 22), wv = P[6..14] (3x3 row-major), vv = P[15..20]
-  double P[21];
+  // L.P holds the articulated inertia passed up from the child frame, then I^A in
+  // place: ww = P[0..5] (00 01 02 11 12 22), wv = P[6..14] (3x3 row-major), vv = P[15..20]
 #pragma unroll
-  for (int k = 0; k < 21; ++k) P[k] = 0.0;
-  double in[10], s[6];
-  {
-    const double* src = d.inert + (size_t)(f0 + nf - 1) * 10;
-#pragma unroll
-    for (int k = 0; k < 10; ++k) in[k] = src[k];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) s[k] = L.tab[k][nf - 1][slot];
-  }
+  for (int k = 0; k < 21; ++k) L.P[k][slot] = 0.0;
   for (int f = nf - 1; f >= 0; --f) {
-    double inn[10], sn[6];
-    const int fn = f > 0 ? f - 1 : 0;
-    const double* src = d.inert + (size_t)(f0 + fn) * 10;
-#pragma unroll
-    for (int k = 0; k < 10; ++k) inn[k] = src[k];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) sn[k] = L.tab[k][fn][slot];
+    const double* in = d.inert + (size_t)(f0 + f) * 10;
     // add I = [[J, [h]x], [[h]x^T, m 1]]
 #pragma unroll
-    for (int k = 0; k < 6; ++k) P[k] += in[k];
-    P[7] -= in[8]; P[8] += in[7]; P[9] += in[8]; P[11] -= in[6]; P[12] -= in[7]; P[13] += in[6];
-    P[15] += in[9]; P[18] += in[9]; P[20] += in[9];
+    for (int k = 0; k < 6; ++k) L.P[k][slot] += in[k];
+    const double h0 = in[6], h1 = in[7], h2 = in[8], ms = in[9];
+    L.P[7][slot] -= h2; L.P[8][slot] += h1; L.P[9][slot] += h2;
+    L.P[11][slot] -= h0; L.P[12][slot] -= h1; L.P[13][slot] += h0;
+    L.P[15][slot] += ms; L.P[18][slot] += ms; L.P[20][slot] += ms;
+    double s[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] = L.tab[k][f][slot];
+    // U = I^A s, reading the symmetric blocks from P
     double U[6];
-    U[0] = P[0] * s[0] + P[1] * s[1] + P[2] * s[2] + P[6] * s[3] + P[7] * s[4] + P[8] * s[5];
-    U[1] = P[1] * s[0] + P[3] * s[1] + P[4] * s[2] + P[9] * s[3] + P[10] * s[4] + P[11] * s[5];
-    U[2] = P[2] * s[0] + P[4] * s[1] + P[5] * s[2] + P[12] * s[3] + P[13] * s[4] + P[14] * s[5];
-    U[3] = P[6] * s[0] + P[9] * s[1] + P[12] * s[2] + P[15] * s[3] + P[16] * s[4] + P[17] * s[5];
-    U[4] = P[7] * s[0] + P[10] * s[1] + P[13] * s[2] + P[16] * s[3] + P[18] * s[4] + P[19] * s[5];
-    U[5] = P[8] * s[0] + P[11] * s[1] + P[14] * s[2] + P[17] * s[3] + P[19] * s[4] + P[20] * s[5];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        int k;
+        if (r < 3 && c < 3) k = sym3(r, c);
+        else if (r < 3) k = 6 + 3 * r + (c - 3);
+        else if (c < 3) k = 6 + 3 * c + (r - 3);
+        else k = 15 + sym3(r - 3, c - 3);
+        acc += L.P[k][slot] * s[c];
+      }
+      U[r] = acc;
+    }
     const double D = (s[0] * U[0] + s[1] * U[1]) + (s[2] * U[2] + s[3] * U[3]) + (s[4] * U[4] + s[5] * U[5]);
     const double iD = (D > 0.0) ? 1.0 / D : 0.0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) L.tab[6 + k][f][slot] = U[k];
     L.tab[12][f][slot] = iD;
     // P <- I^A - U U^T / D  (the articulated inertia seen by the parent)
-    double V[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) V[k] = U[k] * iD;
-    P[0] -= U[0] * V[0]; P[1] -= U[0] * V[1]; P[2] -= U[0] * V[2];
-    P[3] -= U[1] * V[1]; P[4] -= U[1] * V[2]; P[5] -= U[2] * V[2];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) P[6 + 3 * r + c] -= U[r] * V[3 + c];
-    P[15] -= U[3] * V[3]; P[16] -= U[3] * V[4]; P[17] -= U[3] * V[5];
-    P[18] -= U[4] * V[4]; P[19] -= U[4] * V[5]; P[20] -= U[5] * V[5];
+      for (int c = r; c < 3; ++c) {
+        L.P[sym3(r, c)][slot] -= U[r] * U[c] * iD;
+        L.P[15 + sym3(r, c)][slot] -= U[3 + r] * U[3 + c] * iD;
+      }
 #pragma unroll
-    for (int k = 0; k < 10; ++k) in[k] = inn[k];
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int k = 0; k < 6; ++k) s[k] = sn[k];
+      for (int c = 0; c < 3; ++c) L.P[6 + 3 * r + c][slot] -= U[r] * U[3 + c] * iD;
   }
 }
 
@@ -547,18 +620,18 @@ __device__ void aba_solve(SweepLds<G>& L, int slot) {
 // B = -2 A(q_k) + A(q_{k-1}) of every frame, and for the inertia preconditioner
 // the world spatial inertia (about the origin) and hinge motion at the warm start.
 template <int G>
-__device__ __forceinline__ void step_setup(const DevModel& d, SweepLds<G>& L, int f, bool valid, int wave, int lane,
-                                        double qkm1, double qk, double q0, bool use_aba) {
+__device__ __forceinline__ void step_setup(const DevModel& d, SweepLds<G>& L, const FrameGeo& geo, int f, bool valid,
+                                        int wave, int lane, double qkm1, double qk, double q0, bool use_aba) {
   double* B64 = d.B64 + (size_t)f * 12;
   float* B32 = d.B32 + (size_t)f * 12;
   {
-    const Xf<double> Akm1 = forward_kinematics<double>(d, f, valid, qkm1);
+    const Xf<double> Akm1 = fk_geo<double>(geo, valid, qkm1);
     if (valid)
 #pragma unroll
       for (int k = 0; k < 12; ++k) B64[k] = Akm1.m[k];
   }
   {
-    const Xf<double> Ak = forward_kinematics<double>(d, f, valid, qk);
+    const Xf<double> Ak = fk_geo<double>(geo, valid, qk);
     if (valid)
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
@@ -568,9 +641,8 @@ __device__ __forceinline__ void step_setup(const DevModel& d, SweepLds<G>& L, in
       }
   }
   if (!use_aba) return;
-  double a[3], o[3];
-  load_frame<double>(d, f, valid, a, o);
-  const Xf<double> A = forward_kinematics<double>(d, f, valid, q0);
+  const double* a = geo.a;
+  const Xf<double> A = fk_geo<double>(geo, valid, q0);
   double M[10];
   const double* rec = d.fr64 + (size_t)f * 16;
 #pragma unroll
@@ -638,7 +710,10 @@ enum ModelState { kSetup = 0, kIterate = 1, kDone = 2 };
 // MIXED: float32 evaluations until the line search meets float32 rounding (or
 // float32 claims convergence), then float64 to the end of the step.
 template <int G, int MMAX, int PREC>
-__global__ void __launch_bounds__(G* kWave) k_rollout(StepArgs args) {
+#ifndef ABD_WAVES_PER_SIMD
+#define ABD_WAVES_PER_SIMD 2
+#endif
+__global__ void __launch_bounds__(G* kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs args) {
   __shared__ SweepLds<G> L;
   const DevModel& d = args.d;
   const int n = d.n_dofs;
@@ -654,6 +729,7 @@ __global__ void __launch_bounds__(G* kWave) k_rollout(StepArgs args) {
     L.nf[wave] = nf;
     L.f0[wave] = f0;
   }
+  const FrameGeo geo = load_geo(d, f, valid);
   const double eps_w = PREC == ABD_MIXED ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
   const double c1 = 1e-4, dlt = 0.1;
 
@@ -666,42 +742,48 @@ __global__ void __launch_bounds__(G* kWave) k_rollout(StepArgs args) {
 
   // per-step solver state
   double* hs = d.hist + (size_t)f * (2 * kMaxHist);
-  double rho[MMAX], alp[MMAX];
-#pragma unroll
-  for (int k = 0; k < MMAX; ++k) {
-    rho[k] = 0.0; alp[k] = 0.0;
-  }
   bool f32 = false, reset = false;
   int iters = 0, evals = 0, flag = 0, f32_iters = 0, count = 0, head = 0;
   double q = 0.0, tau = 0.0, E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0, qv = 0.0;
 
   for (;;) {
+    PROF_T(t_round);
     // ------------------------------------------------------------ phase A
     if (state == kSetup) {
       q = valid ? 2.0 * qk - qkm1 : 0.0;  // warm start: constant-velocity extrapolation
       tau = (valid && args.tau) ? args.tau[(size_t)step * n + f] : 0.0;
-      if (nf > 0) step_setup<G>(d, L, f, valid, wave, lane, qkm1, qk, q, use_aba);
+      if (nf > 0) step_setup<G>(d, L, geo, f, valid, wave, lane, qkm1, qk, q, use_aba);
     } else if (state == kIterate) {
       if (reset) count = 0;
       qv = g;
-#pragma unroll
-      for (int k = 0; k < MMAX; ++k)
-        if (k < count) {
-          const int slot = (head - k + args.m) % args.m;
-          const double sk = valid ? hs[slot] : 0.0, yk = valid ? hs[kMaxHist + slot] : 0.0;
-          alp[k] = uniform(rho[k] * wave_sum(sk * qv));
-          qv -= alp[k] * yk;
-        }
+      // newest pair first; the next pair is requested while the current one is used
+      double sk = (valid && count > 0) ? hs[head] : 0.0, yk = (valid && count > 0) ? hs[kMaxHist + head] : 0.0;
+      for (int k = 0; k < count; ++k) {
+        const int nxt = (head - k - 1 + args.m) % args.m;
+        const double sn = (valid && k + 1 < count) ? hs[nxt] : 0.0;
+        const double yn = (valid && k + 1 < count) ? hs[kMaxHist + nxt] : 0.0;
+        const double a_k = uniform(L.rho[k][wave] * wave_sum(sk * qv));
+        if (lane == 0) L.alp[k][wave] = a_k;
+        qv -= a_k * yk;
+        sk = sn;
+        yk = yn;
+      }
       if (use_aba) L.xb[lane][wave] = valid ? qv : 0.0;
     }
     if (lane == 0) L.req[wave] = (use_aba && nf > 0) ? (state == kSetup ? 2 : state == kIterate ? 1 : 0) : 0;
+    PROF_ADD(state == kSetup ? 0 : 1, t_round);
+    PROF_T(t_b0);
     __syncthreads();
+    PROF_ADD(2, t_b0);
     // ------------------------------------------------------------ phase B
+    PROF_T(t_b);
     if (wave == 0 && lane < G) {
       if (L.req[lane] == 2) aba_setup<G>(L, d, lane);
       else if (L.req[lane] == 1) aba_solve<G>(L, lane);
     }
     __syncthreads();
+    PROF_ADD(3, t_b);
+    PROF_T(t_c);
     // ------------------------------------------------------------ phase C
     bool step_done = false;
     if (state == kSetup) {
@@ -711,8 +793,8 @@ __global__ void __launch_bounds__(G* kWave) k_rollout(StepArgs args) {
         flag = ABD_FLAG_CONVERGED;
         step_done = true;
       } else {
-        const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(d, f, valid, q, tau, args.dt2)
-                                                  : evaluate<double>(d, f, valid, q, tau, args.dt2);
+        const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(d, geo, f, valid, q, tau, args.dt2)
+                                                  : evaluate<double>(d, geo, f, valid, q, tau, args.dt2);
         ++evals;
         E = r.E;
         g = r.g;
@@ -736,14 +818,21 @@ __global__ void __launch_bounds__(G* kWave) k_rollout(StepArgs args) {
       }
     } else if (state == kIterate) {
       double r = use_aba ? L.xb[lane][wave] : (count > 0 ? gam : 1.0) * qv;
-#pragma unroll
-      for (int k = MMAX - 1; k >= 0; --k)
-        if (k < count) {
-          const int slot = (head - k + args.m) % args.m;
-          const double sk = valid ? hs[slot] : 0.0, yk = valid ? hs[kMaxHist + slot] : 0.0;
-          const double b = uniform(rho[k] * wave_sum(yk * r));
-          r += (alp[k] - b) * sk;
+      // oldest pair first
+      {
+        int slot = (head - (count - 1) + args.m) % args.m;
+        double sk = (valid && count > 0) ? hs[slot] : 0.0, yk = (valid && count > 0) ? hs[kMaxHist + slot] : 0.0;
+        for (int k = count - 1; k >= 0; --k) {
+          const int nxt = (slot + 1) % args.m;
+          const double sn = (valid && k > 0) ? hs[nxt] : 0.0;
+          const double yn = (valid && k > 0) ? hs[kMaxHist + nxt] : 0.0;
+          const double b = uniform(L.rho[k][wave] * wave_sum(yk * r));
+          r += (L.alp[k][wave] - b) * sk;
+          sk = sn;
+          yk = yn;
+          slot = nxt;
         }
+      }
       const double dir = valid ? -r : 0.0;
       const double gd = uniform(wave_sum(g * dir));
       if (!(gd < 0.0)) {
@@ -762,10 +851,17 @@ __global__ void __launch_bounds__(G* kWave) k_rollout(StepArgs args) {
         for (;;) {
           const double x = purpose == kTrial ? q + alpha * dir : q;
           EvalResult rt;
+          PROF_T(t_e);
           if (PREC == ABD_MIXED && f32)
-            rt = evaluate<float>(d, f, valid, x, tau, args.dt2);
+            rt = evaluate<float>(d, geo, f, valid, x, tau, args.dt2);
           else
-            rt = evaluate<double>(d, f, valid, x, tau, args.dt2);
+            rt = evaluate<double>(d, geo, f, valid, x, tau, args.dt2);
+          PROF_ADD(6, t_e);
+          if (lane == 0 && has_model) {
+#ifdef ABD_PROFILE
+            abd_prof[(size_t)model * 16 + 7] += 1;
+#endif
+          }
           ++evals;
           if (purpose != kTrial) {
             // float64 re-evaluation at q after leaving float32
@@ -812,9 +908,10 @@ __global__ void __launch_bounds__(G* kWave) k_rollout(StepArgs args) {
           wave_sum2(sy, ss);
           wave_sum2(yy, unused);
           if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
-#pragma unroll
-            for (int k = MMAX - 1; k > 0; --k) rho[k] = rho[k - 1];
-            rho[0] = uniform(1.0 / sy);
+            if (lane == 0) {
+              for (int k = args.m - 1; k > 0; --k) L.rho[k][wave] = L.rho[k - 1][wave];
+              L.rho[0][wave] = 1.0 / sy;
+            }
             gam = uniform(sy / yy);
             head = count == 0 ? 0 : (head + 1) % args.m;
             if (valid) {
@@ -846,6 +943,7 @@ __global__ void __launch_bounds__(G* kWave) k_rollout(StepArgs args) {
         }
       }
     }
+    PROF_ADD(state == kSetup ? 4 : 5, t_c);
     if (step_done) {
       if (valid) args.q_out[(size_t)step * n + f] = q;
       if (args.stats && lane == 0) {
@@ -863,7 +961,15 @@ __global__ void __launch_bounds__(G* kWave) k_rollout(StepArgs args) {
       ++step;
       state = step < args.n_steps ? kSetup : kDone;
     }
-    if (!__syncthreads_or(state != kDone ? 1 : 0)) break;
+    PROF_T(t_end);
+    const bool more = __syncthreads_or(state != kDone ? 1 : 0);
+    PROF_ADD(8, t_end);
+    if (lane == 0 && has_model) {
+#ifdef ABD_PROFILE
+      abd_prof[(size_t)model * 16 + 9] += 1;
+#endif
+    }
+    if (!more) break;
   }
 }
 
@@ -891,8 +997,9 @@ __global__ void __launch_bounds__(kWave) k_objective_grad(EvalArgs a) {
     return;
   }
   const double qkm1 = valid ? a.q_prev[f] : 0.0, qk = valid ? a.q_curr[f] : 0.0;
-  const Xf<double> Ak = forward_kinematics<double>(d, f, valid, qk);
-  const Xf<double> Akm1 = forward_kinematics<double>(d, f, valid, qkm1);
+  const FrameGeo geo = load_geo(d, f, valid);
+  const Xf<double> Ak = fk_geo<double>(geo, valid, qk);
+  const Xf<double> Akm1 = fk_geo<double>(geo, valid, qkm1);
   if (valid) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -904,8 +1011,8 @@ __global__ void __launch_bounds__(kWave) k_objective_grad(EvalArgs a) {
   // the B rows of this lane were written by this lane: no barrier needed
   const double q = valid ? a.q[f] : 0.0;
   const double tau = (valid && a.tau) ? a.tau[f] : 0.0;
-  const EvalResult r = a.precision == ABD_MIXED ? evaluate<float>(d, f, valid, q, tau, a.dt2)
-                                                : evaluate<double>(d, f, valid, q, tau, a.dt2);
+  const EvalResult r = a.precision == ABD_MIXED ? evaluate<float>(d, geo, f, valid, q, tau, a.dt2)
+                                                : evaluate<double>(d, geo, f, valid, q, tau, a.dt2);
   if (lane == 0) a.E[model] = r.E;
   if (a.grad && valid) a.grad[f] = r.g;
 }
@@ -916,7 +1023,7 @@ __global__ void __launch_bounds__(kWave) k_poses(DevModel d, const double* q, do
   if (nf == 0) return;
   const bool valid = lane < nf;
   const int f = f0 + (valid ? lane : 0);
-  const Xf<double> A = forward_kinematics<double>(d, f, valid, valid ? q[f] : 0.0);
+  const Xf<double> A = fk_geo<double>(load_geo(d, f, valid), valid, valid ? q[f] : 0.0);
   if (valid) {
     const int l = d.pose_link[f];
     if (l >= 0)
@@ -1039,6 +1146,14 @@ int check_opts(const abd_step_opts* o, bool for_step) {
 }  // namespace
 
 extern "C" {
+
+#ifdef ABD_PROFILE
+// Profiling builds only: device buffer of 16 counters per model.
+int abd_debug_set_profile_buffer(unsigned long long* dev_ptr) {
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(abd_prof), &dev_ptr, sizeof(dev_ptr)));
+  return ABD_OK;
+}
+#endif
 
 const char* abd_last_error(void) { return g_err.c_str(); }
 
