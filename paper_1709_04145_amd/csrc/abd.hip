@@ -92,6 +92,20 @@ __device__ __forceinline__ double dpp(double old, double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Zero-filling row shift (all rows enabled): lanes whose source lies outside the
+// row read 0, so no "old" value has to be materialised.
+template <int CTRL>
+__device__ __forceinline__ float dpp0(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp0(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(x & 0xffffffffll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ double readlane(double v, int l) {
   const long long x = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), l);
@@ -110,10 +124,10 @@ __device__ __forceinline__ double uniform(double v) {
 // Inclusive prefix sum over the 64 lanes (row shifts 1,2,4,8, then the
 // row-15 and row-31 broadcasts).  Every lane ends with its inclusive prefix.
 __device__ __forceinline__ double wave_prefix_sum(double v) {
-  v += dpp<0x111, 0xF>(0.0, v);
-  v += dpp<0x112, 0xF>(0.0, v);
-  v += dpp<0x114, 0xF>(0.0, v);
-  v += dpp<0x118, 0xF>(0.0, v);
+  v += dpp0<0x111>(v);
+  v += dpp0<0x112>(v);
+  v += dpp0<0x114>(v);
+  v += dpp0<0x118>(v);
   v += dpp<0x142, 0xA>(0.0, v);
   v += dpp<0x143, 0xC>(0.0, v);
   return v;
@@ -122,10 +136,10 @@ __device__ __forceinline__ double wave_sum(double v) { return readlane(wave_pref
 
 // Two independent sums in one pass (interleaved for latency hiding).
 __device__ __forceinline__ void wave_sum2(double& a, double& b) {
-  a += dpp<0x111, 0xF>(0.0, a); b += dpp<0x111, 0xF>(0.0, b);
-  a += dpp<0x112, 0xF>(0.0, a); b += dpp<0x112, 0xF>(0.0, b);
-  a += dpp<0x114, 0xF>(0.0, a); b += dpp<0x114, 0xF>(0.0, b);
-  a += dpp<0x118, 0xF>(0.0, a); b += dpp<0x118, 0xF>(0.0, b);
+  a += dpp0<0x111>(a); b += dpp0<0x111>(b);
+  a += dpp0<0x112>(a); b += dpp0<0x112>(b);
+  a += dpp0<0x114>(a); b += dpp0<0x114>(b);
+  a += dpp0<0x118>(a); b += dpp0<0x118>(b);
   a += dpp<0x142, 0xA>(0.0, a); b += dpp<0x142, 0xA>(0.0, b);
   a += dpp<0x143, 0xC>(0.0, a); b += dpp<0x143, 0xC>(0.0, b);
   a = readlane(a, 63);
@@ -183,10 +197,10 @@ __device__ __forceinline__ Quat<R> wave_prefix_quat(Quat<R> v) {
 // Inclusive prefix sum in precision R (row shifts + row broadcasts).
 template <typename R>
 __device__ __forceinline__ R wave_prefix_sum_r(R v) {
-  v += dpp<0x111, 0xF>(R(0), v);
-  v += dpp<0x112, 0xF>(R(0), v);
-  v += dpp<0x114, 0xF>(R(0), v);
-  v += dpp<0x118, 0xF>(R(0), v);
+  v += dpp0<0x111>(v);
+  v += dpp0<0x112>(v);
+  v += dpp0<0x114>(v);
+  v += dpp0<0x118>(v);
   v += dpp<0x142, 0xA>(R(0), v);
   v += dpp<0x143, 0xC>(R(0), v);
   return v;
@@ -318,7 +332,6 @@ struct DevModel {
   const int* pose_link;     // [n_dofs] link whose pose frame this is, -1 otherwise
   double* B64;              // [n_dofs][12] per-step constant -2 A(q_k) + A(q_{k-1})
   float* B32;               // [n_dofs][12]
-  double* inert;            // [n_dofs][10] world spatial inertia of each frame (per step)
   double* hist;             // [n_dofs][2*kMaxHist] L-BFGS pairs s (ring) then y (ring)
   double gx, gy, gz;
 };
@@ -494,13 +507,15 @@ struct StepArgs {
   abd_step_stats* stats;      // [n_steps][n_models] or NULL
 };
 
-// Per-frame table of the articulated-body sweeps (LDS), per model slot:
-// s (6 = world hinge motion (w; p x w)), U (6 = I^A s), 1/D (1).
+// Per-frame tables of the articulated-body recursion and sweeps (LDS), one
+// 16-byte aligned record per (frame, model slot):
+//   tab: s (6 = world hinge motion (w; p x w)), U (6 = I^A s), 1/D, unused
+//   inert: world spatial inertia of the frame about the origin (J 6, h 3, m)
 template <int G>
 struct SweepLds {
-  double tab[13][kMaxFrames][G];
+  double tab[kMaxFrames][G][14];
+  double inert[kMaxFrames][G][10];
   double xb[kMaxFrames][G];  // sweep input b, then u, then the output x
-  double P[21][G];           // articulated-inertia accumulator of the recursion
   double rho[kMaxHist][G];   // 1/(s_i.y_i), newest first (per model slot)
   double alp[kMaxHist][G];   // two-loop coefficients
   int nf[G];
@@ -511,108 +526,109 @@ struct SweepLds {
 // Articulated inertias at the warm start (once per step), lane = model slot:
 //   I^A_f = I_f + P_{f+1},  U_f = I^A_f s_f,  D_f = s_f.U_f,
 //   P_f = I^A_f - U_f U_f^T / D_f  (passed to the parent frame).
-// The 6x6 symmetric I^A is held as ww (6), wv (3x3), vv (6).  The inputs of
-// frame f-1 are loaded while frame f is processed.
+// The 6x6 symmetric I^A is held as ww (6: 00 01 02 11 12 22), wv (3x3 row-major),
+// vv (6).  The LDS inputs of frame f-1 are read while frame f is processed.
 template <int G>
-__device__ void aba_setup(SweepLds<G>& L, const DevModel& d, int slot) {
-  const int nf = L.nf[slot], f0 = L.f0[slot];
+__device__ void aba_setup(SweepLds<G>& L, int slot) {
+  const int nf = L.nf[slot];
   if (nf <= 0) return;
-  // L.P holds the articulated inertia passed up from the child frame, then I^A in
-  // place: ww = P[0..5] (00 01 02 11 12 22), wv = P[6..14] (3x3 row-major), vv = P[15..20]
+  double P[21];
 #pragma unroll
-  for (int k = 0; k < 21; ++k) L.P[k][slot] = 0.0;
+  for (int k = 0; k < 21; ++k) P[k] = 0.0;
+  double in[10], s[6];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) in[k] = L.inert[nf - 1][slot][k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s[k] = L.tab[nf - 1][slot][k];
   for (int f = nf - 1; f >= 0; --f) {
-    const double* in = d.inert + (size_t)(f0 + f) * 10;
+    const int fn = f > 0 ? f - 1 : 0;
+    double inn[10], sn[6];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) inn[k] = L.inert[fn][slot][k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sn[k] = L.tab[fn][slot][k];
     // add I = [[J, [h]x], [[h]x^T, m 1]]
 #pragma unroll
-    for (int k = 0; k < 6; ++k) L.P[k][slot] += in[k];
-    const double h0 = in[6], h1 = in[7], h2 = in[8], ms = in[9];
-    L.P[7][slot] -= h2; L.P[8][slot] += h1; L.P[9][slot] += h2;
-    L.P[11][slot] -= h0; L.P[12][slot] -= h1; L.P[13][slot] += h0;
-    L.P[15][slot] += ms; L.P[18][slot] += ms; L.P[20][slot] += ms;
-    double s[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) s[k] = L.tab[k][f][slot];
-    // U = I^A s, reading the symmetric blocks from P
+    for (int k = 0; k < 6; ++k) P[k] += in[k];
+    P[7] -= in[8]; P[8] += in[7]; P[9] += in[8]; P[11] -= in[6]; P[12] -= in[7]; P[13] += in[6];
+    P[15] += in[9]; P[18] += in[9]; P[20] += in[9];
     double U[6];
-#pragma unroll
-    for (int r = 0; r < 6; ++r) {
-      double acc = 0.0;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        int k;
-        if (r < 3 && c < 3) k = sym3(r, c);
-        else if (r < 3) k = 6 + 3 * r + (c - 3);
-        else if (c < 3) k = 6 + 3 * c + (r - 3);
-        else k = 15 + sym3(r - 3, c - 3);
-        acc += L.P[k][slot] * s[c];
-      }
-      U[r] = acc;
-    }
+    U[0] = P[0] * s[0] + P[1] * s[1] + P[2] * s[2] + P[6] * s[3] + P[7] * s[4] + P[8] * s[5];
+    U[1] = P[1] * s[0] + P[3] * s[1] + P[4] * s[2] + P[9] * s[3] + P[10] * s[4] + P[11] * s[5];
+    U[2] = P[2] * s[0] + P[4] * s[1] + P[5] * s[2] + P[12] * s[3] + P[13] * s[4] + P[14] * s[5];
+    U[3] = P[6] * s[0] + P[9] * s[1] + P[12] * s[2] + P[15] * s[3] + P[16] * s[4] + P[17] * s[5];
+    U[4] = P[7] * s[0] + P[10] * s[1] + P[13] * s[2] + P[16] * s[3] + P[18] * s[4] + P[19] * s[5];
+    U[5] = P[8] * s[0] + P[11] * s[1] + P[14] * s[2] + P[17] * s[3] + P[19] * s[4] + P[20] * s[5];
     const double D = (s[0] * U[0] + s[1] * U[1]) + (s[2] * U[2] + s[3] * U[3]) + (s[4] * U[4] + s[5] * U[5]);
     const double iD = (D > 0.0) ? 1.0 / D : 0.0;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) L.tab[6 + k][f][slot] = U[k];
-    L.tab[12][f][slot] = iD;
+    for (int k = 0; k < 6; ++k) L.tab[f][slot][6 + k] = U[k];
+    L.tab[f][slot][12] = iD;
     // P <- I^A - U U^T / D  (the articulated inertia seen by the parent)
+    double V[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) V[k] = U[k] * iD;
+    P[0] -= U[0] * V[0]; P[1] -= U[0] * V[1]; P[2] -= U[0] * V[2];
+    P[3] -= U[1] * V[1]; P[4] -= U[1] * V[2]; P[5] -= U[2] * V[2];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = r; c < 3; ++c) {
-        L.P[sym3(r, c)][slot] -= U[r] * U[c] * iD;
-        L.P[15 + sym3(r, c)][slot] -= U[3 + r] * U[3 + c] * iD;
-      }
+      for (int c = 0; c < 3; ++c) P[6 + 3 * r + c] -= U[r] * V[3 + c];
+    P[15] -= U[3] * V[3]; P[16] -= U[3] * V[4]; P[17] -= U[3] * V[5];
+    P[18] -= U[4] * V[4]; P[19] -= U[4] * V[5]; P[20] -= U[5] * V[5];
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 10; ++k) in[k] = inn[k];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) L.P[6 + 3 * r + c][slot] -= U[r] * U[3 + c] * iD;
+    for (int k = 0; k < 6; ++k) s[k] = sn[k];
   }
 }
 
 // x = H^{-1} b in O(n): backward sweep u_f = b_f - s_f.p, p <- p + U_f u_f / D_f;
 // forward sweep x_f = (u_f - U_f.a) / D_f, a <- a + s_f x_f.  In place in xb.
-// The table entries of the next frame are read while the current one is used.
+// The record of the next frame is read while the current one is used.
 template <int G>
 __device__ void aba_solve(SweepLds<G>& L, int slot) {
   const int nf = L.nf[slot];
   if (nf <= 0) return;
   double p[6] = {0, 0, 0, 0, 0, 0};
-  double t[14];
+  double t[13], b;
 #pragma unroll
-  for (int k = 0; k < 13; ++k) t[k] = L.tab[k][nf - 1][slot];
-  t[13] = L.xb[nf - 1][slot];
+  for (int k = 0; k < 13; ++k) t[k] = L.tab[nf - 1][slot][k];
+  b = L.xb[nf - 1][slot];
   for (int f = nf - 1; f >= 0; --f) {
-    double tn[14];
     const int fn = f > 0 ? f - 1 : 0;
+    double tn[13];
 #pragma unroll
-    for (int k = 0; k < 13; ++k) tn[k] = L.tab[k][fn][slot];
-    tn[13] = L.xb[fn][slot];
+    for (int k = 0; k < 13; ++k) tn[k] = L.tab[fn][slot][k];
+    const double bn = L.xb[fn][slot];
     const double sp = (t[0] * p[0] + t[1] * p[1]) + (t[2] * p[2] + t[3] * p[3]) + (t[4] * p[4] + t[5] * p[5]);
-    const double u = t[13] - sp;
+    const double u = b - sp;
     L.xb[f][slot] = u;
     const double w = u * t[12];
 #pragma unroll
     for (int k = 0; k < 6; ++k) p[k] += t[6 + k] * w;
 #pragma unroll
-    for (int k = 0; k < 14; ++k) t[k] = tn[k];
+    for (int k = 0; k < 13; ++k) t[k] = tn[k];
+    b = bn;
   }
   double a[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-  for (int k = 0; k < 13; ++k) t[k] = L.tab[k][0][slot];
-  t[13] = L.xb[0][slot];
+  for (int k = 0; k < 13; ++k) t[k] = L.tab[0][slot][k];
+  b = L.xb[0][slot];
   for (int f = 0; f < nf; ++f) {
-    double tn[14];
     const int fn = f + 1 < nf ? f + 1 : f;
+    double tn[13];
 #pragma unroll
-    for (int k = 0; k < 13; ++k) tn[k] = L.tab[k][fn][slot];
-    tn[13] = L.xb[fn][slot];
+    for (int k = 0; k < 13; ++k) tn[k] = L.tab[fn][slot][k];
+    const double bn = L.xb[fn][slot];
     const double Ua = (t[6] * a[0] + t[7] * a[1]) + (t[8] * a[2] + t[9] * a[3]) + (t[10] * a[4] + t[11] * a[5]);
-    const double x = (t[13] - Ua) * t[12];
+    const double x = (b - Ua) * t[12];
     L.xb[f][slot] = x;
 #pragma unroll
     for (int k = 0; k < 6; ++k) a[k] += t[k] * x;
 #pragma unroll
-    for (int k = 0; k < 14; ++k) t[k] = tn[k];
+    for (int k = 0; k < 13; ++k) t[k] = tn[k];
+    b = bn;
   }
 }
 
@@ -670,28 +686,27 @@ __device__ __forceinline__ void step_setup(const DevModel& d, SweepLds<G>& L, co
       }
   }
   const double tr = Sw[0] + Sw[3] + Sw[5];
-  if (valid) {
-    double* in = d.inert + (size_t)f * 10;
-    in[0] = tr - Sw[0];
-    in[1] = -Sw[1];
-    in[2] = -Sw[2];
-    in[3] = tr - Sw[3];
-    in[4] = -Sw[4];
-    in[5] = tr - Sw[5];
-    in[6] = Rmc[0] + ms * t[0];
-    in[7] = Rmc[1] + ms * t[1];
-    in[8] = Rmc[2] + ms * t[2];
-    in[9] = ms;
-  }
+  double* in = L.inert[lane][wave];
+  in[0] = valid ? tr - Sw[0] : 0.0;
+  in[1] = valid ? -Sw[1] : 0.0;
+  in[2] = valid ? -Sw[2] : 0.0;
+  in[3] = valid ? tr - Sw[3] : 0.0;
+  in[4] = valid ? -Sw[4] : 0.0;
+  in[5] = valid ? tr - Sw[5] : 0.0;
+  in[6] = valid ? Rmc[0] + ms * t[0] : 0.0;
+  in[7] = valid ? Rmc[1] + ms * t[1] : 0.0;
+  in[8] = valid ? Rmc[2] + ms * t[2] : 0.0;
+  in[9] = valid ? ms : 0.0;
   const double w0 = A.m[0] * a[0] + A.m[1] * a[1] + A.m[2] * a[2];
   const double w1 = A.m[4] * a[0] + A.m[5] * a[1] + A.m[6] * a[2];
   const double w2 = A.m[8] * a[0] + A.m[9] * a[1] + A.m[10] * a[2];
-  L.tab[0][lane][wave] = valid ? w0 : 0.0;
-  L.tab[1][lane][wave] = valid ? w1 : 0.0;
-  L.tab[2][lane][wave] = valid ? w2 : 0.0;
-  L.tab[3][lane][wave] = valid ? t[1] * w2 - t[2] * w1 : 0.0;
-  L.tab[4][lane][wave] = valid ? t[2] * w0 - t[0] * w2 : 0.0;
-  L.tab[5][lane][wave] = valid ? t[0] * w1 - t[1] * w0 : 0.0;
+  double* ts = L.tab[lane][wave];
+  ts[0] = valid ? w0 : 0.0;
+  ts[1] = valid ? w1 : 0.0;
+  ts[2] = valid ? w2 : 0.0;
+  ts[3] = valid ? t[1] * w2 - t[2] * w1 : 0.0;
+  ts[4] = valid ? t[2] * w0 - t[0] * w2 : 0.0;
+  ts[5] = valid ? t[0] * w1 - t[1] * w0 : 0.0;
 }
 
 // What the next evaluation of phase C is for.
@@ -778,7 +793,7 @@ __global__ void __launch_bounds__(G* kWave, ABD_WAVES_PER_SIMD) k_rollout(StepAr
     // ------------------------------------------------------------ phase B
     PROF_T(t_b);
     if (wave == 0 && lane < G) {
-      if (L.req[lane] == 2) aba_setup<G>(L, d, lane);
+      if (L.req[lane] == 2) aba_setup<G>(L, lane);
       else if (L.req[lane] == 1) aba_solve<G>(L, lane);
     }
     __syncthreads();
@@ -1046,7 +1061,6 @@ struct abd_model {
   float* fr32 = nullptr;
   double* B64 = nullptr;
   float* B32 = nullptr;
-  double* inert = nullptr;
   double* hist = nullptr;
   std::vector<void*> allocs;
 };
@@ -1114,7 +1128,6 @@ DevModel dev_view(const abd_model* m) {
   d.fr32 = m->fr32;
   d.pose_link = m->pose_link;
   d.B64 = m->B64; d.B32 = m->B32;
-  d.inert = m->inert;
   d.hist = m->hist;
   d.gx = m->g[0]; d.gy = m->g[1]; d.gz = m->g[2];
   return d;
@@ -1229,7 +1242,7 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   if ((rc = upload(m, &m->f0, f0)) || (rc = upload(m, &m->pose_link, pose_link)) ||
       (rc = upload(m, &m->fr64, fr64)) || (rc = upload(m, &m->fr32, fr32)) ||
       (rc = alloc(m, &m->B64, 12 * (size_t)nd)) || (rc = alloc(m, &m->B32, 12 * (size_t)nd)) ||
-      (rc = alloc(m, &m->inert, 10 * (size_t)nd)) || (rc = alloc(m, &m->hist, 2 * kMaxHist * (size_t)nd))) {
+      (rc = alloc(m, &m->hist, 2 * kMaxHist * (size_t)nd))) {
     free_model(m);
     delete m;
     return rc;
