@@ -522,6 +522,154 @@ void orc_inertia_matrix(const orc_model* m, const double* q, double* H, int n_th
   free(off);
 }
 
+/* ------------------------------------------------ second derivatives -- */
+/* FK of model i at q (into w->T, w->tl) and the world derivative generator of
+ * every frame, W_n = T^{parent(n)} (dt_n/dq_n) (T^n)^{-1}, so that
+ * dT^f/dq_n = W_n T^f for every frame f below DOF n. */
+static void generators_model(const orc_model* m, int i, const double* q, eval_ws* w, double* Wb) {
+  int d0 = m->model_dof[i], nd = model_nd(m, i);
+  fk_model(m, i, q, w->T, w->tl);
+  double I4[16], dtl[16], tmp[16], Ti[16];
+  m4_eye(I4);
+  for (int j = 0; j < nd; ++j) {
+    int f = d0 + j, p = m->frame_parent[f];
+    local_dtf(m->axis + 3 * f, q[f], dtl);
+    m4_mul(p >= 0 ? w->T + 16 * (p - d0) : I4, dtl, tmp);
+    m4_rigid_inv(w->T + 16 * j, Ti);
+    m4_mul(tmp, Ti, Wb + 16 * j);
+  }
+}
+
+/* below[a*nd+b] = 1 when frame b is frame a or one of its descendants. */
+static void below_model(const orc_model* m, int i, char* below) {
+  int d0 = m->model_dof[i], nd = model_nd(m, i);
+  memset(below, 0, (size_t)nd * nd);
+  for (int b = 0; b < nd; ++b)
+    for (int a = b; a >= 0; a = m->frame_parent[d0 + a] >= 0 ? m->frame_parent[d0 + a] - d0 : -1)
+      below[(size_t)a * nd + b] = 1;
+}
+
+static size_t* block_offsets(const orc_model* m) {
+  size_t* off = (size_t*)malloc((m->n_models + 1) * sizeof(size_t));
+  off[0] = 0;
+  for (int i = 0; i < m->n_models; ++i) off[i + 1] = off[i] + (size_t)model_nd(m, i) * model_nd(m, i);
+  return off;
+}
+
+/* Hessian of the step objective of model i at q by its plain definition
+ *   d2E/dq_a dq_b = sum_l <dA_l/dq_a M_l, dA_l/dq_b> + <G_l, d2A_l/dq_a dq_b>,
+ * with dT^l/dq_n = W_n T^l and, for a an ancestor-or-self of b (both above l),
+ * d2T^l/dq_a dq_b = W_a W_b T^l;  G_l = D_l M_l - dt^2 g (M_l e4)^T is the
+ * derivative of E with respect to A_l (the seed of Alg. 1's backward pass).
+ * Only the three pose rows enter (the last row of every derivative is zero). */
+static void hessian_model(const orc_model* m, int i, double dt, const double* q, const double* qk,
+                          const double* qkm1, eval_ws* w, double* H, double* Wb, double* Gb, char* below) {
+  int d0 = m->model_dof[i], nd = model_nd(m, i);
+  double dt2 = dt * dt;
+  fk_model(m, i, qk, w->Tk, w->tl);
+  fk_model(m, i, qkm1, w->Tkm1, w->tl);
+  generators_model(m, i, q, w, Wb);
+  below_model(m, i, below);
+  memset(Gb, 0, (size_t)nd * 16 * sizeof(double));
+  for (int j = 0; j < nd; ++j) {
+    int l = m->frame_mass[d0 + j];
+    if (l < 0) continue;
+    double M[16];
+    mm_full(m->mm + 10 * l, M);
+    const double *A = w->T + 16 * j, *Ak = w->Tk + 16 * j, *Akm1 = w->Tkm1 + 16 * j;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 4; ++c) {
+        double dm = 0.0;
+        for (int k = 0; k < 4; ++k) dm += (A[4 * r + k] - 2.0 * Ak[4 * r + k] + Akm1[4 * r + k]) * M[4 * k + c];
+        Gb[16 * j + 4 * r + c] = dm - dt2 * m->g[r] * M[4 * c + 3];
+      }
+  }
+  memset(H, 0, (size_t)nd * nd * sizeof(double));
+  double dAa[16], dAb[16], dAaM[16], WW[16], d2A[16], M[16];
+  for (int a = 0; a < nd; ++a)
+    for (int b = a; b < nd; ++b) {
+      if (!below[(size_t)a * nd + b]) continue;
+      m4_mul(Wb + 16 * a, Wb + 16 * b, WW);
+      double v = 0.0;
+      for (int j = b; j < nd; ++j) {
+        int l = m->frame_mass[d0 + j];
+        if (l < 0 || !below[(size_t)b * nd + j]) continue;
+        mm_full(m->mm + 10 * l, M);
+        m4_mul(Wb + 16 * a, w->T + 16 * j, dAa);
+        m4_mul(Wb + 16 * b, w->T + 16 * j, dAb);
+        m4_mul(dAa, M, dAaM);
+        m4_mul(WW, w->T + 16 * j, d2A);
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 4; ++c) v += dAaM[4 * r + c] * dAb[4 * r + c] + Gb[16 * j + 4 * r + c] * d2A[4 * r + c];
+      }
+      H[(size_t)a * nd + b] = v;
+      H[(size_t)b * nd + a] = v;
+    }
+}
+
+void orc_hessian(const orc_model* m, double dt, const double* q, const double* q_hist, double* H,
+                 int n_threads) {
+  size_t* off = block_offsets(m);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int i = 0; i < m->n_models; ++i) {
+    int nd = model_nd(m, i), n1 = nd > 0 ? nd : 1;
+    eval_ws w;
+    ws_alloc(&w, nd);
+    double* Wb = (double*)malloc((size_t)n1 * 32 * sizeof(double));
+    char* below = (char*)malloc((size_t)n1 * n1);
+    hessian_model(m, i, dt, q, q_hist + m->n_dofs, q_hist, &w, H + off[i], Wb, Wb + 16 * (size_t)n1, below);
+    free(below);
+    free(Wb);
+    ws_free(&w);
+  }
+  free(off);
+}
+
+/* Mixed second derivative of a pairing  scale * sum_l <A_l(q) M_l, A_l(q_o)>
+ * (the form in which E depends on a past configuration: scale -2 for q_k,
+ * +1 for q_{k-1}):
+ *   C_ab = scale * sum_l <dA_l(q)/dq_a M_l, dA_l(q_o)/dq_o,b>  over links l
+ * below both DOFs.  C[a][b] row-major, one block per model. */
+void orc_cross_hessian(const orc_model* m, const double* q, const double* q_o, double scale, double* C,
+                       int n_threads) {
+  size_t* off = block_offsets(m);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int i = 0; i < m->n_models; ++i) {
+    int d0 = m->model_dof[i], nd = model_nd(m, i), n1 = nd > 0 ? nd : 1;
+    eval_ws w, wo;
+    ws_alloc(&w, nd);
+    ws_alloc(&wo, nd);
+    double* Wb = (double*)malloc((size_t)n1 * 32 * sizeof(double));
+    double* Wo = Wb + 16 * (size_t)n1;
+    char* below = (char*)malloc((size_t)n1 * n1);
+    generators_model(m, i, q, &w, Wb);
+    generators_model(m, i, q_o, &wo, Wo);
+    below_model(m, i, below);
+    double* Ci = C + off[i];
+    double dA[16], dAM[16], dAo[16], M[16];
+    for (int a = 0; a < nd; ++a)
+      for (int b = 0; b < nd; ++b) {
+        double v = 0.0;
+        for (int j = 0; j < nd; ++j) {
+          int l = m->frame_mass[d0 + j];
+          if (l < 0 || !below[(size_t)a * nd + j] || !below[(size_t)b * nd + j]) continue;
+          mm_full(m->mm + 10 * l, M);
+          m4_mul(Wb + 16 * a, w.T + 16 * j, dA);
+          m4_mul(dA, M, dAM);
+          m4_mul(Wo + 16 * b, wo.T + 16 * j, dAo);
+          for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 4; ++c) v += dAM[4 * r + c] * dAo[4 * r + c];
+        }
+        Ci[(size_t)a * nd + b] = scale * v;
+      }
+    free(below);
+    free(Wb);
+    ws_free(&wo);
+    ws_free(&w);
+  }
+  free(off);
+}
+
 /* Dense Cholesky H = L L^T in place (lower triangle); 0 on success. */
 static int cholesky(double* A, int n) {
   for (int j = 0; j < n; ++j) {

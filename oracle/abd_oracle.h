@@ -75,6 +75,18 @@ void orc_inertia_diag(const orc_model* m, const double* q, double* h, int n_thre
  * row-major block per model, packed model after model (sum of n_i^2 doubles). */
 void orc_inertia_matrix(const orc_model* m, const double* q, double* H, int n_threads);
 
+/* Hessian d2E/dq dq of the step objective at q (second derivatives of the
+ * poses written out), one dense row-major block per model, packed like
+ * orc_inertia_matrix.  q_hist = [q_{k-1}; q_k]. */
+void orc_hessian(const orc_model* m, double dt, const double* q, const double* q_hist, double* H,
+                 int n_threads);
+
+/* C_ab = scale * sum_l <dA_l(q)/dq_a M_l, dA_l(q_o)/dq_o,b>: the mixed second
+ * derivative of E with respect to q and a past configuration (scale -2 for q_k,
+ * +1 for q_{k-1}).  Packed dense blocks. */
+void orc_cross_hessian(const orc_model* m, const double* q, const double* q_o, double scale, double* C,
+                       int n_threads);
+
 /* One time step for every model: q_out = argmin of the step objective,
  * reached by preconditioned L-BFGS from the warm start 2 q_k - q_{k-1}. */
 int orc_step(const orc_model* m, const orc_opts* o, const double* q_hist, const double* tau,

@@ -70,6 +70,8 @@ def lib():
         _lib.orc_alg1_I.argtypes = [C.c_void_p, dp, dp, dp, dp, C.c_int]
         _lib.orc_inertia_diag.argtypes = [C.c_void_p, dp, dp, C.c_int]
         _lib.orc_inertia_matrix.argtypes = [C.c_void_p, dp, dp, C.c_int]
+        _lib.orc_hessian.argtypes = [C.c_void_p, C.c_double, dp, dp, dp, C.c_int]
+        _lib.orc_cross_hessian.argtypes = [C.c_void_p, dp, dp, C.c_double, dp, C.c_int]
         _lib.orc_step.argtypes = [C.c_void_p, C.POINTER(OrcOpts), dp, dp, dp, C.c_void_p, C.c_int]
         _lib.orc_step.restype = C.c_int
         _lib.orc_energy_report.argtypes = [C.c_void_p, C.c_double, dp, dp, dp, C.c_int]
@@ -159,6 +161,31 @@ class Oracle:
             o += n * n
         return out
 
+    def _blocks(self, buf):
+        nd = np.diff(self.desc.dof_offset).astype(np.int64)
+        out, o = [], 0
+        for n in nd:
+            out.append(buf[o:o + n * n].reshape(n, n))
+            o += n * n
+        return out
+
+    def _block_buffer(self):
+        nd = np.diff(self.desc.dof_offset).astype(np.int64)
+        return np.zeros(max(1, int(np.sum(nd * nd))))
+
+    def hessian(self, q, q_prev, q_curr, dt):
+        """List of dense per-model Hessians d2E/dq dq of the step objective at q."""
+        buf = self._block_buffer()
+        hist = _f64(np.concatenate([q_prev, q_curr]))
+        lib().orc_hessian(self._h, dt, _d(_f64(q)), _d(hist), _d(buf), self.threads)
+        return self._blocks(buf)
+
+    def cross_hessian(self, q, q_other, scale):
+        """List of per-model C[a][b] = scale sum_l <dA_l(q)/dq_a M_l, dA_l(q_o)/dq_o,b>."""
+        buf = self._block_buffer()
+        lib().orc_cross_hessian(self._h, _d(_f64(q)), _d(_f64(q_other)), scale, _d(buf), self.threads)
+        return self._blocks(buf)
+
     def energy_report(self, q_prev, q_curr, dt) -> np.ndarray:
         H = np.zeros(self.n_models)
         lib().orc_energy_report(self._h, dt, _d(_f64(q_prev)), _d(_f64(q_curr)), _d(H), self.threads)
@@ -190,6 +217,41 @@ class Oracle:
             qs.append(nxt)
             stats.append(st)
         return np.stack(qs), stats
+
+    def rollout_vjp(self, q_init_prev, q0, traj, dt, dL_dtraj):
+        """Reverse-mode derivative of a rollout by the implicit function theorem.
+
+        Step k defines q_{k+1} through the stationarity condition of its objective
+        (Eq. PBAD): g(q_{k+1}; q_k, q_{k-1}, tau_k) = 0.  Differentiating it,
+            H dq_{k+1} + C_k dq_k + C_{k-1} dq_{k-1} - dt^2 dtau_k = 0,
+        with H the Hessian at q_{k+1} and C_k, C_{k-1} the mixed second
+        derivatives (scales -2 and +1).  Given lambda = dL/dq_{k+1} (complete once
+        every later step has been processed), mu = H^{-1} lambda and
+            dL/dq_k += -C_k^T mu,  dL/dq_{k-1} += -C_{k-1}^T mu,  dL/dtau_k = dt^2 mu.
+        traj = [q_1..q_T] (T x n); dL_dtraj = dL/dq_1..q_T (T x n, the explicit
+        dependence of the loss).  Returns (dL/dq_{-1}, dL/dq_0, dL/dtau [T x n]).
+        Dense solves, model by model."""
+        traj = np.asarray(traj, dtype=np.float64)
+        T = traj.shape[0]
+        n = self.n_dofs
+        qs = [np.asarray(q_init_prev, np.float64), np.asarray(q0, np.float64)] + [traj[k] for k in range(T)]
+        lam = [np.zeros(n), np.zeros(n)] + [np.array(dL_dtraj[k], dtype=np.float64) for k in range(T)]
+        dtau = np.zeros((T, n))
+        do = self.desc.dof_offset
+        for k in range(T - 1, -1, -1):
+            q, qc, qp = qs[k + 2], qs[k + 1], qs[k]
+            H = self.hessian(q, qp, qc, dt)
+            Cc = self.cross_hessian(q, qc, -2.0)
+            Cp = self.cross_hessian(q, qp, 1.0)
+            for i in range(self.n_models):
+                sl = slice(do[i], do[i + 1])
+                if do[i + 1] == do[i]:
+                    continue
+                mu = np.linalg.solve(H[i], lam[k + 2][sl])
+                lam[k + 1][sl] -= Cc[i].T @ mu
+                lam[k][sl] -= Cp[i].T @ mu
+                dtau[k, sl] = dt * dt * mu
+        return lam[0], lam[1], dtau
 
     # ---------------------------------------------------------------- helpers
     def newton_polish(self, q, q_prev, q_curr, dt, tau=None, iters=8, h=1e-6):

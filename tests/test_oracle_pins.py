@@ -323,3 +323,95 @@ def test_empty_batch_and_max_iter_flag():
     qn, st = orc.step(wl.q0, wl.q0, wl.step.dt, max_iter=1)
     assert np.all(st["iterations"] <= 1)
     assert np.all((st["flag"] == 4) | (st["flag"] == 1))
+
+
+# ----------------------------------------------------- second derivatives
+def _fd_jacobian(fun, x, h=1e-5):
+    cols = []
+    for j in range(len(x)):
+        e = np.zeros_like(x)
+        e[j] = h
+        cols.append((fun(x + e) - fun(x - e)) / (2 * h))
+    return np.stack(cols, axis=1)
+
+
+def test_hessian_matches_fd_of_gradient():
+    """d2E/dq dq by the written-out second derivatives of the poses equals the
+    central difference of the Alg. 1 gradient (ball joints and branching)."""
+    d = _tree(3, seed=21, max_links=4)
+    rng = np.random.default_rng(22)
+    q, qp, qc = (rng.uniform(-1.5, 1.5, d.n_dofs) for _ in range(3))
+    dt = 0.05
+    orc = Oracle(d)
+    H = orc.hessian(q, qp, qc, dt)
+    Hfd = _fd_jacobian(lambda x: orc.objective_grad(x, qp, qc, dt)[1], q)
+    do = d.dof_offset
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        np.testing.assert_allclose(H[i], H[i].T, rtol=0, atol=1e-12 * np.abs(H[i]).max())
+        np.testing.assert_allclose(H[i], Hfd[sl, sl], rtol=0, atol=1e-7 * np.abs(H[i]).max())
+        # no coupling across models
+        off = np.delete(Hfd[sl], np.arange(do[i], do[i + 1]), axis=1)
+        assert np.abs(off).max(initial=0.0) == 0.0
+
+
+def test_cross_hessians_match_fd_of_gradient():
+    """The dependence of the gradient on q_k and q_{k-1}: scales -2 and +1."""
+    d = _tree(3, seed=23, max_links=4)
+    rng = np.random.default_rng(24)
+    q, qp, qc = (rng.uniform(-1.5, 1.5, d.n_dofs) for _ in range(3))
+    dt = 0.05
+    orc = Oracle(d)
+    Cc = orc.cross_hessian(q, qc, -2.0)
+    Cp = orc.cross_hessian(q, qp, 1.0)
+    Jc = _fd_jacobian(lambda x: orc.objective_grad(q, qp, x, dt)[1], qc)
+    Jp = _fd_jacobian(lambda x: orc.objective_grad(q, x, qc, dt)[1], qp)
+    do = d.dof_offset
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        np.testing.assert_allclose(Cc[i], Jc[sl, sl], rtol=0, atol=1e-7 * np.abs(Cc[i]).max())
+        np.testing.assert_allclose(Cp[i], Jp[sl, sl], rtol=0, atol=1e-7 * np.abs(Cp[i]).max())
+
+
+def _tight_rollout(orc, qm1, q0, tau, dt):
+    """Rollout whose every step is solved to the float64 floor (L-BFGS, then Newton)."""
+    qs = [qm1, q0]
+    for k in range(len(tau)):
+        qn, _ = orc.step(qs[-2], qs[-1], dt, tau=tau[k], tol=1e-12, max_iter=2000)
+        qn, _ = orc.newton_polish(qn, qs[-2], qs[-1], dt, tau=tau[k], iters=3)
+        qs.append(qn)
+    return np.stack(qs[2:])
+
+
+def test_rollout_vjp_matches_finite_differences():
+    """Implicit differentiation through the stationarity condition of every step
+    (Eq. PBAD) against central differences of whole rollouts, for the initial
+    configurations and the joint torques."""
+    d = W._assemble([W.chain_model([0.6, 0.9, 0.5], 0.1, [800.0, 1200.0, 1000.0],
+                                   [W._unit(np.array(a, float)) for a in ([1, 0, 0.3], [0, 1, 0], [0.2, 0.4, 1])])])
+    rng = np.random.default_rng(31)
+    n, T, dt = d.n_dofs, 4, 0.03
+    q0 = rng.uniform(-0.8, 0.8, n)
+    qm1 = q0 - 0.02 * rng.uniform(-1, 1, n)
+    tau = rng.uniform(-1, 1, (T, n))
+    w = rng.normal(size=(T, n))  # loss L = sum_k w_k . q_k
+    orc = Oracle(d, threads=1)
+    traj = _tight_rollout(orc, qm1, q0, tau, dt)
+    g_qm1, g_q0, g_tau = orc.rollout_vjp(qm1, q0, traj, dt, w)
+
+    def loss(a, b, t):
+        return float(np.sum(w * _tight_rollout(orc, a, b, t, dt)))
+
+    h = 1e-6
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = h
+        fd0 = (loss(qm1, q0 + e, tau) - loss(qm1, q0 - e, tau)) / (2 * h)
+        fdm = (loss(qm1 + e, q0, tau) - loss(qm1 - e, q0, tau)) / (2 * h)
+        assert abs(fd0 - g_q0[j]) <= 1e-6 * max(1.0, abs(fd0)), (j, fd0, g_q0[j])
+        assert abs(fdm - g_qm1[j]) <= 1e-6 * max(1.0, abs(fdm)), (j, fdm, g_qm1[j])
+    for k, j in ((0, 0), (1, 2), (3, 1)):
+        e = np.zeros((T, n))
+        e[k, j] = h
+        fd = (loss(qm1, q0, tau + e) - loss(qm1, q0, tau - e)) / (2 * h)
+        assert abs(fd - g_tau[k, j]) <= 1e-6 * max(1e-3, abs(fd)), (k, j, fd, g_tau[k, j])
