@@ -1,13 +1,27 @@
-"""Throughput of the batched time step on one MI355X: link-steps/s.
+"""Throughput of batched position-based time integration on one MI355X: link-steps/s.
 
-Workload (default): 4096 serial chains with 10..50 hinge links each (uniform),
-random unit axes, box links of length U[0.3,1.2] m, width 0.1 m, density
-U[500,2000] kg/m^3, initial angles U[-1,1] rad at rest, dt = 0.03 s, one
-collocation point per step (order 2), L-BFGS history 5, tolerance 1e-8.
-A bench step is one time step of the whole batch (one call of abd_step).
-`value` is the mixed-precision rate; the float64 rate on the same workload is
-reported next to it.  Inputs are synthetic and resident on the GPU before
-timing starts.
+Workload (default, "chains4096_uneven10to50"): 4096 serial chains with 10..50
+hinge links each (uniform), random unit axes, box links of length U[0.3,1.2] m,
+width 0.1 m, density U[500,2000] kg/m^3, initial angles U[-1,1] rad at rest,
+dt = 0.03 s, one collocation point per step (order 2), L-BFGS history 5,
+relative gradient tolerance 1e-8, inertia-preconditioned L-BFGS.
+
+A bench step is one time step of the whole batch.  The warm-up steps run as one
+rollout launch (abd_rollout) from rest; the K timed steps run as one more
+rollout launch from where the warm-up ended, with the inputs already on the
+GPU.  `value` is the mixed-precision rate; the float64 rate on the same
+workload is reported next to it.
+
+Also reported:
+  roofline     algorithmic bytes of the timed launch (per-link figures below,
+               times the link-iterations and evaluations the launch performed)
+               over the launch's duration measured with HIP events on the
+               launch stream, against the 8 TB/s HBM peak;
+  parity       one teacher-forced step from the final state on a sample of
+               models against the float64 CPU oracle (relative q error for
+               FP64, relative pose error for mixed);
+  cpu_baseline the oracle (C, OpenMP over models) on a sample of the models
+               over the same steps.
 
 Prints one JSON line.
 """
@@ -15,7 +29,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -25,10 +38,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic bytes per link (streaming formulation, no on-chip reuse across phases)
-EVAL_BYTES = {"f32": 128, "f64": 240}   # q, axis+offset, M, B in; g out
-LBFGS_BYTES = 128                        # g, q, s/y history (m=5) in; d, q, s, y out
-PRECOND_BYTES = 240                      # two sweeps: s, U, 1/D (f64) in twice; b/u/x traffic
+# Algorithmic bytes per link (one DOF per link), streaming form: every operand
+# read from and every result written to HBM once per use, no on-chip reuse.
+# evaluation, float32 terms: read q 8, axis+offset 24, M 40, B 48; write g 8
+# evaluation, float64 terms: read q 8, axis+offset 48, M 80, B 96; write g 8
+EVAL_BYTES = {"f32": 128, "f64": 240}
+LBFGS_BYTES = 128                       # read g, q, s/y history (m=5); write d, q, s, y
+PRECOND_BYTES = 240                     # two sweeps over the recursion records (s, U, 1/D) + b/u/x
+SETUP_BYTES = 328                       # per step: read q_{k-1}, q_k, axis/offset, M; write B (f64+f32), records
 HBM_PEAK_GBS = 8000.0
 
 
@@ -38,56 +55,75 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-parity", action="store_true", help="skip the oracle parity sample")
+    ap.add_argument("--cpu-models", type=int, default=1024, help="models in the CPU baseline sample")
     return ap.parse_args()
 
 
-def run_rollout(torch, abd, model, q0, opts, warmup, steps):
-    """Warm-up steps, then `steps` timed steps; per-launch durations from events on the launch stream."""
+def timed_rollout(torch, model, q0, opts, warmup, steps):
+    """Warm-up rollout from rest, then `steps` timed steps in one launch."""
     n = model.n_dofs
-    buf = torch.empty((warmup + steps + 2, n), dtype=torch.float64, device="cuda")
-    buf[0] = q0
-    buf[1] = q0
-    stats = torch.zeros((steps, max(1, model.n_models), 4), dtype=torch.float64, device="cuda")
-    for k in range(warmup):
-        model.step(buf[k:k + 2].reshape(-1), buf[k + 2], opts)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    q0c = torch.as_tensor(q0, dtype=torch.float64, device="cuda")
+    init = torch.cat([q0c, q0c]).contiguous()
+    if warmup > 0:
+        wtraj, _ = model.rollout(init, warmup, opts)
+        prev = wtraj[warmup - 2] if warmup >= 2 else q0c
+        init = torch.cat([prev, wtraj[warmup - 1]]).contiguous()
+    traj = torch.empty((steps, n), dtype=torch.float64, device="cuda")
+    stats = model.new_rollout_stats(steps)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev[0].record()
-    for j in range(steps):
-        k = warmup + j
-        model.step(buf[k:k + 2].reshape(-1), buf[k + 2], opts, stats=stats[j])
-        ev[j + 1].record()
+    ev0.record()
+    model.rollout(init, steps, opts, q_traj=traj, stats=stats)
+    ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per_launch_ms = [ev[j].elapsed_time(ev[j + 1]) for j in range(steps)]
-    st = [model.read_stats(stats[j], model.n_models) for j in range(steps)]
-    return buf, wall, per_launch_ms, st
+    kernel_ms = ev0.elapsed_time(ev1)
+    st = model.read_rollout_stats(stats, steps)
+    return init, traj, st, wall, kernel_ms
 
 
 def algorithmic_bytes(desc, st, precision):
-    """Bytes the step would move if every phase streamed its operands from HBM."""
-    links = np.diff(desc.link_offset).astype(np.float64)
+    """Bytes the timed launch would move in the streaming formulation."""
+    links = np.diff(desc.link_offset).astype(np.float64)[None, :]
     it = st["iterations"].astype(np.float64)
     ev = st["evaluations"].astype(np.float64)
     if precision == "mixed":
-        it32 = st["f32_iterations"].astype(np.float64)
-        ev32 = np.minimum(ev, it32 + 1.0)
+        ev32 = np.minimum(ev, st["f32_iterations"].astype(np.float64) + 1.0)
         ev64 = ev - ev32
     else:
         ev32, ev64 = np.zeros_like(ev), ev
-    per_link = EVAL_BYTES["f32"] * ev32 + EVAL_BYTES["f64"] * ev64 + (LBFGS_BYTES + PRECOND_BYTES) * it
+    per_link = (EVAL_BYTES["f32"] * ev32 + EVAL_BYTES["f64"] * ev64 + (LBFGS_BYTES + PRECOND_BYTES) * it
+                + SETUP_BYTES)
     return float(np.sum(links * per_link))
+
+
+def pose_error(orc, desc, q, ref):
+    """Relative pose error: max over links of |x - x_ref| / reach of the link's model
+    (sum of its link lengths), and max |R - R_ref|_F."""
+    A, B = orc.poses(q), orc.poses(ref)
+    lo = desc.link_offset
+    ex, eR = 0.0, 0.0
+    for i in range(desc.n_models):
+        sl = slice(lo[i], lo[i + 1])
+        if lo[i + 1] == lo[i]:
+            continue
+        reach = np.sum(np.linalg.norm(desc.offset[sl], axis=1)) + 2.0 * np.max(
+            desc.mass_moment[sl, 3] / desc.mass_moment[sl, 9])
+        ex = max(ex, float(np.max(np.linalg.norm(A[sl, :, 3] - B[sl, :, 3], axis=1)) / reach))
+        eR = max(eR, float(np.max(np.linalg.norm(A[sl, :, :3] - B[sl, :, :3], axis=(1, 2)))))
+    return ex, eR
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(models are independent; see the sharding notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the models are independent, "
+              "so a multi-GPU run would shard them and gather the results once (see the sharding notes)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -97,31 +133,28 @@ def main():
     wl = W.config(args.config)
     desc = wl.model
     model = abd.Model(desc)
-    q0 = torch.tensor(wl.q0, dtype=torch.float64, device="cuda")
     L = desc.n_links
     base = dict(dt=wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol, max_iter=wl.step.max_iter)
-    results = {}
+    runs = {}
     for name, prec in (("mixed", abd.MIXED), ("fp64", abd.FP64)):
         if name == "fp64" and args.no_fp64:
             continue
         opts = abd.StepOptions(precision=prec, **base)
-        buf, wall, per_launch, st = run_rollout(torch, abd, model, q0, opts, args.warmup, args.steps)
-        iters = np.stack([s["iterations"] for s in st])
-        evals = np.stack([s["evaluations"] for s in st])
-        flags = np.stack([s["flag"] for s in st])
-        bytes_launch = [algorithmic_bytes(desc, s, name) for s in st]
-        avg_ms = float(np.mean(per_launch))
-        results[name] = dict(
-            wall=wall, per_launch_ms=avg_ms, value=L * args.steps / wall,
-            iters_mean=float(iters.mean()), iters_max=int(iters.max()),
-            evals_mean=float(evals.mean()), converged_frac=float(np.mean(flags == 1)),
-            achieved_gbs=float(np.mean(bytes_launch)) / (avg_ms * 1e-3) / 1e9,
-            last=(buf[args.warmup + args.steps].cpu().numpy(), buf[args.warmup + args.steps + 1].cpu().numpy()),
-        )
-        print(f"[bench] {name}: {results[name]['value']:.4g} link-steps/s, {avg_ms:.3f} ms/launch, "
-              f"iters {results[name]['iters_mean']:.2f}", file=sys.stderr, flush=True)
+        init, traj, st, wall, kms = timed_rollout(torch, model, wl.q0, opts, args.warmup, args.steps)
+        nbytes = algorithmic_bytes(desc, st, name)
+        links = np.diff(desc.link_offset)[None, :]
+        runs[name] = dict(
+            init=init, traj=traj, st=st, wall=wall, kernel_ms=kms, value=L * args.steps / wall,
+            iters_mean=float(st["iterations"].mean()), iters_max=int(st["iterations"].max()),
+            evals_mean=float(st["evaluations"].mean()),
+            converged_frac=float(np.mean(st["flag"] == abd.FLAG_CONVERGED)),
+            link_iters=float(np.sum(links * st["iterations"])),
+            achieved_gbs=nbytes / (kms * 1e-3) / 1e9, bytes=nbytes)
+        print(f"[bench] {name}: {runs[name]['value']:.4g} link-steps/s, kernel {kms:.2f} ms for {args.steps} "
+              f"steps, iters/step {runs[name]['iters_mean']:.2f} (max {runs[name]['iters_max']})",
+              file=sys.stderr, flush=True)
 
-    mixed = results["mixed"]
+    mixed = runs["mixed"]
     out = {
         "metric": "link-steps/s on 1 MI355X, batched mixed vs plain FP64, at <=1e-5 rel pose err",
         "value": mixed["value"],
@@ -137,56 +170,74 @@ def main():
         "data": "synthetic",
         "config": {"workload": W.CONFIG_NAMES[args.config], "models": desc.n_models, "links": L,
                    "dofs": desc.n_dofs, "dt": wl.step.dt, "order_K": 2, "lbfgs_m": wl.step.lbfgs_m,
-                   "tol": wl.step.tol, "precond": "joint-space inertia"},
+                   "tol": wl.step.tol, "precond": "joint-space inertia", "launch": "one rollout per K steps"},
         "iterations_per_step": mixed["iters_mean"],
+        "iterations_per_step_max": mixed["iters_max"],
         "evaluations_per_step": mixed["evals_mean"],
         "converged_fraction": mixed["converged_frac"],
+        "link_iterations_per_s": mixed["link_iters"] / mixed["wall"],
         "roofline": {"bound": "hbm", "achieved": mixed["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": mixed["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None},
+                     "frac": mixed["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_rollout<MIXED>", "kernel_ms": mixed["kernel_ms"],
+                     "algorithmic_bytes": mixed["bytes"]},
     }
-    if "fp64" in results:
-        f = results["fp64"]
+    if "fp64" in runs:
+        f = runs["fp64"]
         out["fp64"] = {"value": f["value"], "ms_per_step": f["wall"] / args.steps * 1e3,
-                       "iterations_per_step": f["iters_mean"], "achieved_gbs": f["achieved_gbs"],
-                       "mixed_over_fp64": mixed["value"] / f["value"]}
+                       "iterations_per_step": f["iters_mean"], "iterations_per_step_max": f["iters_max"],
+                       "converged_fraction": f["converged_frac"], "kernel_ms": f["kernel_ms"],
+                       "achieved_gbs": f["achieved_gbs"], "mixed_over_fp64": mixed["value"] / f["value"]}
 
-    # parity of the last timed step against the oracle on a sample of models
-    from oracle.oracle import Oracle
-    sample = np.arange(0, desc.n_models, max(1, desc.n_models // 32))
-    sub = desc.subset(sample)
-    idx = desc.dof_subset_index(sample)
-    orc = Oracle(sub)
-    par = {}
-    # one teacher-forced step from the final mixed state, both precisions
-    qp, qc = results["mixed"]["last"]
-    ref, _ = orc.step(qp[idx], qc[idx], wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol)
-    for name, prec in (("mixed", abd.MIXED), ("fp64", abd.FP64)):
-        o = torch.zeros(desc.n_dofs, dtype=torch.float64, device="cuda")
-        h = torch.tensor(np.concatenate([qp, qc]), dtype=torch.float64, device="cuda")
-        model.step(h, o, abd.StepOptions(precision=prec, **base))
-        torch.cuda.synchronize()
-        qg = o.cpu().numpy()[idx]
-        par[name] = float(np.max(np.abs(qg - ref)) / max(1.0, np.max(np.abs(ref))))
-    out["parity_max_rel_q_err"] = par
+    if not args.no_parity:
+        # one teacher-forced step from the final FP64 state (both precisions start
+        # from the same float64 (q_{k-1}, q_k)) on a sample of models
+        from oracle.oracle import Oracle
+        src = runs["fp64"] if "fp64" in runs else mixed
+        tr = src["traj"].cpu().numpy()
+        qp, qc = (tr[-2], tr[-1]) if args.steps >= 2 else (src["init"].cpu().numpy()[:desc.n_dofs], tr[-1])
+        sample = np.arange(0, desc.n_models, max(1, desc.n_models // 64))
+        sub = desc.subset(sample)
+        idx = desc.dof_subset_index(sample)
+        orc = Oracle(sub)
+        ref, rst = orc.step(qp[idx], qc[idx], wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=1e-11)
+        hist = torch.tensor(np.concatenate([qp, qc]), dtype=torch.float64, device="cuda")
+        par = {}
+        for name, prec in (("fp64", abd.FP64), ("mixed", abd.MIXED)):
+            o = torch.zeros(desc.n_dofs, dtype=torch.float64, device="cuda")
+            model.step(hist, o, abd.StepOptions(precision=prec, **dict(base, tol=1e-11)))
+            torch.cuda.synchronize()
+            qg = o.cpu().numpy()[idx]
+            par[name] = {"max_rel_q_err": float(np.max(np.abs(qg - ref)) / max(1.0, np.max(np.abs(ref))))}
+            par[name]["max_rel_pose_err"], par[name]["max_rot_err"] = pose_error(orc, sub, qg, ref)
+        out["parity"] = {"sample_models": int(len(sample)), "tol": 1e-11, **par}
 
     if not args.no_cpu:
+        from oracle.oracle import Oracle
         threads = max(1, min(16, os.cpu_count() or 1))
-        orc_full = Oracle(desc, threads=threads)
-        qa = wl.q0.copy()
-        qb = wl.q0.copy()
+        nsub = max(1, min(desc.n_models, args.cpu_models))
+        sample = np.arange(0, desc.n_models, max(1, desc.n_models // nsub))[:nsub]
+        sub = desc.subset(sample)
+        idx = desc.dof_subset_index(sample)
+        orc = Oracle(sub, threads=threads)
+        qa = wl.q0[idx].copy()
+        qb = qa.copy()
+        for _ in range(args.warmup):
+            qn, _ = orc.step(qa, qb, wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol)
+            qa, qb = qb, qn
         t0 = time.perf_counter()
         nsteps = 0
-        while True:
-            qn, _ = orc_full.step(qa, qb, wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol)
+        while nsteps < args.steps:
+            qn, _ = orc.step(qa, qb, wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol)
             qa, qb = qb, qn
             nsteps += 1
-            if time.perf_counter() - t0 > args.cpu_seconds:
+            if time.perf_counter() - t0 > 30.0:
                 break
         el = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": L * nsteps / el, "unit": "link-steps/s", "cores": threads,
+        out["cpu_baseline"] = {"value": sub.n_links * nsteps / el, "unit": "link-steps/s", "cores": threads,
                                "kind": "oracle",
-                               "sample": f"full batch ({desc.n_models} models), first {nsteps} steps from rest, "
-                                         f"{el:.1f} s, OpenMP over models"}
+                               "sample": f"{len(sample)} of {desc.n_models} models ({sub.n_links} links), steps "
+                                         f"{args.warmup}..{args.warmup + nsteps - 1} after a {args.warmup}-step "
+                                         f"warm-up from rest, float64, OpenMP over models, {el:.1f} s"}
     print(json.dumps(out), flush=True)
 
 

@@ -140,6 +140,37 @@ int abd_objective_grad(abd_model* model, const abd_step_opts* opts, const double
                        const double* q_hist, const double* tau, double* E, double* grad,
                        void* stream);
 
+/* Hessian-vector product of the step objective at q (float64): Hv = (d2E/dq dq) v,
+ * the derivative of the Alg. 1 gradient along v, computed by forward-mode
+ * differentiation of the forward and backward passes (O(n) per model).
+ *   q, v, Hv : [n_dofs]     q_hist : [2*n_dofs] = q_{k-1} followed by q_k
+ * opts->dt is used; the other fields are ignored. */
+int abd_hvp(abd_model* model, const abd_step_opts* opts, const double* q, const double* q_hist,
+            const double* v, double* Hv, void* stream);
+
+/* Reverse-mode derivative of a rollout (float64).  Every step's result is
+ * defined by the stationarity condition of its objective (Eq. PBAD), so by the
+ * implicit function theorem, with lambda = dL/dq_{k+1} and H mu = lambda (H the
+ * Hessian at q_{k+1}, solved by conjugate gradients preconditioned with the
+ * inverse joint-space inertia):
+ *   dL/dq_k += -(d2E/dq dq_k)^T mu,  dL/dq_{k-1} += -(d2E/dq dq_{k-1})^T mu,
+ *   dL/dtau_k = dt^2 mu.
+ *   q_init     : [2*n_dofs] = q_{-1}, q_0 of the forward rollout
+ *   q_traj     : [n_steps*n_dofs] = q_1 .. q_{n_steps} it produced
+ *   dL_dq_traj : [n_steps*n_dofs] explicit dL/dq_1 .. dL/dq_{n_steps}
+ *   dL_dq_init : [2*n_dofs] receives dL/dq_{-1}, dL/dq_0
+ *   dL_dtau    : [n_steps*n_dofs] receives dL/dtau_0 .. dL/dtau_{n_steps-1}, or NULL
+ *   stats      : [n_steps*n_models] per solve: iterations = CG iterations,
+ *                evaluations = Hessian-vector products, grad_norm = final residual,
+ *                flag 1 converged / 2 H not positive definite along a CG direction /
+ *                4 max_iter / 8 non-finite; or NULL
+ * opts: dt; tol = relative CG residual; max_iter = CG iterations per step;
+ * precond selects the CG preconditioner.  The torques of the forward rollout are
+ * not needed (the objective is linear in them). */
+int abd_rollout_vjp(abd_model* model, const abd_step_opts* opts, const double* q_init, const double* q_traj,
+                    const double* dL_dq_traj, double* dL_dq_init, double* dL_dtau, abd_step_stats* stats,
+                    int n_steps, void* stream);
+
 /* World poses [R|t] (3x4 row-major, 12 doubles per link) of every link at q
  * (forward kinematics of Alg. 1).  poses: device [12*n_links]. */
 int abd_poses(abd_model* model, const double* q, double* poses, void* stream);

@@ -56,6 +56,10 @@ _PROTOS = {
                               C.c_void_p, C.c_int, C.c_void_p]),
     "abd_objective_grad": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "abd_hvp": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
+                          C.c_void_p, C.c_void_p]),
+    "abd_rollout_vjp": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "abd_poses": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "abd_last_error": (C.c_char_p, []),
 }
@@ -193,6 +197,36 @@ class Model:
                                          _ptr(g), _stream(stream)))
         return E[:self.n_models], g[:self.n_dofs]
 
+    def hvp(self, q, q_hist, v, dt, stream=None):
+        """Hessian-vector product of the step objective at q (float64)."""
+        _dev_f64(q, self.n_dofs, "q")
+        _dev_f64(q_hist, 2 * self.n_dofs, "q_hist")
+        _dev_f64(v, self.n_dofs, "v")
+        Hv = torch.zeros(max(1, self.n_dofs), dtype=torch.float64, device="cuda")
+        o = StepOptions(dt=dt).c()
+        _check(load().abd_hvp(self._h, C.byref(o), _ptr(q), _ptr(q_hist), _ptr(v), _ptr(Hv), _stream(stream)))
+        return Hv[:self.n_dofs]
+
+    def rollout_vjp(self, q_init, q_traj, dL_dq_traj, dt, tol=1e-10, max_iter=200, precond=PRECOND_INERTIA,
+                    want_tau=True, stats=None, stream=None):
+        """Reverse-mode derivative of a rollout (abd_rollout_vjp).
+
+        q_init [2n] = q_{-1}, q_0; q_traj [T, n] = q_1..q_T; dL_dq_traj [T, n].
+        Returns (dL/dq_init [2n], dL/dtau [T, n] or None)."""
+        n = self.n_dofs
+        T = q_traj.shape[0] if q_traj.dim() == 2 else q_traj.numel() // max(1, n)
+        _dev_f64(q_init, 2 * n, "q_init")
+        _dev_f64(q_traj, T * n, "q_traj")
+        _dev_f64(dL_dq_traj, T * n, "dL_dq_traj")
+        if stats is not None and stats.numel() * stats.element_size() < 32 * self.n_models * T:
+            raise ValueError("stats must hold 32 bytes per model and step")
+        g_init = torch.zeros(max(1, 2 * n), dtype=torch.float64, device="cuda")
+        g_tau = torch.zeros((max(1, T), max(1, n)), dtype=torch.float64, device="cuda") if want_tau else None
+        o = StepOptions(dt=dt, tol=tol, max_iter=max_iter, precond=precond).c()
+        _check(load().abd_rollout_vjp(self._h, C.byref(o), _ptr(q_init), _ptr(q_traj), _ptr(dL_dq_traj),
+                                      _ptr(g_init), _ptr(g_tau), _ptr(stats), int(T), _stream(stream)))
+        return g_init[:2 * n], (g_tau[:T, :n] if want_tau else None)
+
     def poses(self, q, stream=None):
         _dev_f64(q, self.n_dofs, "q")
         out = torch.zeros((max(1, self.n_links), 3, 4), dtype=torch.float64, device="cuda")
@@ -240,3 +274,72 @@ class Model:
             stats.append(st)
         torch.cuda.synchronize()
         return buf[1:], [self.read_stats(s, self.n_models) for s in stats]
+
+
+# ------------------------------------------------------------------ autograd
+class ObjectiveFunction(torch.autograd.Function):
+    """E(q) per model (abd_objective_grad) as a differentiable function of q and
+    tau.  Backward: dE/dq from the Alg. 1 gradient the forward pass already
+    computed, dE/dtau = -dt^2 q.  q_hist is treated as a constant."""
+
+    @staticmethod
+    def forward(ctx, q, tau, model, q_hist, dt):
+        E, g = model.objective_grad(q.detach().contiguous(), q_hist.detach().contiguous(), dt,
+                                    tau=None if tau is None else tau.detach().contiguous())
+        ctx.dt, ctx.has_tau = dt, tau is not None
+        dof_model = _dof_model_index(model)
+        ctx.save_for_backward(q.detach(), g, dof_model)
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        q, g, dof_model = ctx.saved_tensors
+        w = gE[dof_model]
+        gq = w * g
+        # E contains -dt^2 tau.q, so dE/dtau = -dt^2 q
+        gtau = (-ctx.dt * ctx.dt) * w * q if ctx.has_tau else None
+        return gq, gtau, None, None, None
+
+
+def _dof_model_index(model):
+    """Model index of every DOF (cached on the model)."""
+    idx = getattr(model, "_dof_model", None)
+    if idx is None:
+        per_model = np.diff(np.asarray(model.desc.dof_offset)).astype(np.int64)
+        idx = torch.as_tensor(np.repeat(np.arange(model.n_models), per_model), device="cuda")
+        model._dof_model = idx
+    return idx
+
+
+def objective(model, q, q_hist, dt, tau=None):
+    """Differentiable per-model objective E(q) (see ObjectiveFunction)."""
+    return ObjectiveFunction.apply(q, tau, model, q_hist, dt)
+
+
+class RolloutFunction(torch.autograd.Function):
+    """q_1..q_T = rollout(q_{-1}, q_0, tau) (abd_rollout, float64) with its
+    reverse-mode derivative by implicit differentiation (abd_rollout_vjp)."""
+
+    @staticmethod
+    def forward(ctx, q_init, torque, model, steps, opts, vjp_opts):
+        traj, _ = model.rollout(q_init.detach().contiguous(), steps, opts,
+                                torque=None if torque is None else torque.detach().contiguous())
+        ctx.model, ctx.opts, ctx.vjp_opts, ctx.has_tau = model, opts, vjp_opts, torque is not None
+        ctx.save_for_backward(q_init.detach(), traj)
+        return traj.clone()
+
+    @staticmethod
+    def backward(ctx, g_traj):
+        q_init, traj = ctx.saved_tensors
+        g_init, g_tau = ctx.model.rollout_vjp(q_init.contiguous(), traj.contiguous(), g_traj.contiguous(),
+                                              ctx.opts.dt, want_tau=ctx.has_tau, **ctx.vjp_opts)
+        return g_init, g_tau, None, None, None, None
+
+
+def rollout(model, q_init, steps, opts, torque=None, vjp_tol=1e-10, vjp_max_iter=200):
+    """Differentiable rollout: returns q_1..q_steps [steps, n_dofs]; gradients flow
+    to q_init = [q_{-1}; q_0] and to torque [steps, n_dofs]."""
+    if opts.precision != FP64:
+        raise ValueError("the differentiable rollout runs in float64 (precision=FP64)")
+    return RolloutFunction.apply(q_init, torque, model, steps, opts,
+                                 dict(tol=vjp_tol, max_iter=vjp_max_iter))

@@ -22,10 +22,12 @@
 //     a plain sum so that it becomes a float64 suffix scan;
 //   * L-BFGS dot products are float64 wave reductions.
 // The initial inverse Hessian of L-BFGS is the inverse joint-space inertia at
-// the warm start, applied in O(n) by the two sweeps of the articulated-body
-// recursion.  Those sweeps are sequential along the chain, so they run with
-// one lane per model: G models share one workgroup, and wave 0 sweeps all G of
-// them at once from per-frame tables held in LDS.
+// the warm start.  Once per step the articulated-body recursion factors it
+// (one lane, sequential along the chain, tables in LDS) and the 64 lanes solve
+// for the columns of the explicit inverse at once; every iteration then applies
+// it as a dense matrix-vector product streamed from memory, so the iteration
+// has no sequential sweep.  One model is one workgroup of one wavefront: models
+// never wait for each other, and the L-BFGS pairs live in LDS.
 //
 // No MFMA: nothing on this path is a dense contraction.
 
@@ -57,7 +59,6 @@ int fail(int code, const std::string& msg) {
 
 constexpr int kWave = 64;
 constexpr int kMaxFrames = 64;  // frames (DOFs) per model handled by one wavefront
-constexpr int kG = 8;           // models per workgroup in the step kernel
 constexpr int kMaxHist = 10;    // longest L-BFGS history
 
 // Optional per-phase cycle counters (build with -DABD_PROFILE): lane 0 of every
@@ -332,7 +333,8 @@ struct DevModel {
   const int* pose_link;     // [n_dofs] link whose pose frame this is, -1 otherwise
   double* B64;              // [n_dofs][12] per-step constant -2 A(q_k) + A(q_{k-1})
   float* B32;               // [n_dofs][12]
-  double* hist;             // [n_dofs][2*kMaxHist] L-BFGS pairs s (ring) then y (ring)
+  const long long* hoff;    // [n_models+1] start of every model's block in hinv
+  double* hinv;             // per model nf x nf: inverse joint-space inertia at the warm start
   double gx, gy, gz;
 };
 
@@ -507,46 +509,40 @@ struct StepArgs {
   abd_step_stats* stats;      // [n_steps][n_models] or NULL
 };
 
-// Per-frame tables of the articulated-body recursion and sweeps (LDS), one
-// 16-byte aligned record per (frame, model slot):
-//   tab: s (6 = world hinge motion (w; p x w)), U (6 = I^A s), 1/D, unused
-//   inert: world spatial inertia of the frame about the origin (J 6, h 3, m)
-template <int G>
-struct SweepLds {
-  double tab[kMaxFrames][G][14];
-  double inert[kMaxFrames][G][10];
-  double xb[kMaxFrames][G];  // sweep input b, then u, then the output x
-  double rho[kMaxHist][G];   // 1/(s_i.y_i), newest first (per model slot)
-  double alp[kMaxHist][G];   // two-loop coefficients
-  int nf[G];
-  int f0[G];
-  int req[G];
+// Per-model tables of the articulated-body recursion (LDS, one model per
+// workgroup):
+//   tab:   per frame s (6 = world hinge motion (w; p x w)), U (6 = I^A s), 1/D, unused
+//   inert: per frame world spatial inertia about the origin (J 6, h 3, m)
+struct ModelLds {
+  double tab[kMaxFrames][14];
+  double inert[kMaxFrames][10];
+  double rho[kMaxHist];  // 1/(s_i.y_i), newest first
+  double alp[kMaxHist];  // two-loop coefficients
 };
 
-// Articulated inertias at the warm start (once per step), lane = model slot:
+// Articulated inertias at the warm start (once per step, one lane):
 //   I^A_f = I_f + P_{f+1},  U_f = I^A_f s_f,  D_f = s_f.U_f,
 //   P_f = I^A_f - U_f U_f^T / D_f  (passed to the parent frame).
-// The 6x6 symmetric I^A is held as ww (6: 00 01 02 11 12 22), wv (3x3 row-major),
-// vv (6).  The LDS inputs of frame f-1 are read while frame f is processed.
-template <int G>
-__device__ void aba_setup(SweepLds<G>& L, int slot) {
-  const int nf = L.nf[slot];
+// The 6x6 symmetric P is held in registers as ww (6: 00 01 02 11 12 22),
+// wv (3x3 row-major), vv (6).  The LDS inputs of frame f-1 are read while
+// frame f is processed.
+__device__ void aba_setup(ModelLds& L, int nf) {
   if (nf <= 0) return;
   double P[21];
 #pragma unroll
   for (int k = 0; k < 21; ++k) P[k] = 0.0;
   double in[10], s[6];
 #pragma unroll
-  for (int k = 0; k < 10; ++k) in[k] = L.inert[nf - 1][slot][k];
+  for (int k = 0; k < 10; ++k) in[k] = L.inert[nf - 1][k];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) s[k] = L.tab[nf - 1][slot][k];
+  for (int k = 0; k < 6; ++k) s[k] = L.tab[nf - 1][k];
   for (int f = nf - 1; f >= 0; --f) {
     const int fn = f > 0 ? f - 1 : 0;
     double inn[10], sn[6];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) inn[k] = L.inert[fn][slot][k];
+    for (int k = 0; k < 10; ++k) inn[k] = L.inert[fn][k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) sn[k] = L.tab[fn][slot][k];
+    for (int k = 0; k < 6; ++k) sn[k] = L.tab[fn][k];
     // add I = [[J, [h]x], [[h]x^T, m 1]]
 #pragma unroll
     for (int k = 0; k < 6; ++k) P[k] += in[k];
@@ -562,8 +558,8 @@ __device__ void aba_setup(SweepLds<G>& L, int slot) {
     const double D = (s[0] * U[0] + s[1] * U[1]) + (s[2] * U[2] + s[3] * U[3]) + (s[4] * U[4] + s[5] * U[5]);
     const double iD = (D > 0.0) ? 1.0 / D : 0.0;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) L.tab[f][slot][6 + k] = U[k];
-    L.tab[f][slot][12] = iD;
+    for (int k = 0; k < 6; ++k) L.tab[f][6 + k] = U[k];
+    L.tab[f][12] = iD;
     // P <- I^A - U U^T / D  (the articulated inertia seen by the parent)
     double V[6];
 #pragma unroll
@@ -583,61 +579,86 @@ __device__ void aba_setup(SweepLds<G>& L, int slot) {
   }
 }
 
-// x = H^{-1} b in O(n): backward sweep u_f = b_f - s_f.p, p <- p + U_f u_f / D_f;
-// forward sweep x_f = (u_f - U_f.a) / D_f, a <- a + s_f x_f.  In place in xb.
-// The record of the next frame is read while the current one is used.
-template <int G>
-__device__ void aba_solve(SweepLds<G>& L, int slot) {
-  const int nf = L.nf[slot];
-  if (nf <= 0) return;
+// Explicit inverse of the joint-space inertia from the recursion above: lane j
+// solves H x = e_j with the two sweeps
+//   backward  u_f = b_f - s_f.p,   p <- p + U_f u_f / D_f,
+//   forward   x_f = (u_f - U_f.a) / D_f,  a <- a + s_f x_f,
+// all lanes walking the frames together (the records are LDS broadcasts).  u
+// is parked in the output column Hi[f][j] and overwritten by x; every lane
+// touches only its own column, so no other lane's stores have to be seen.
+constexpr int kInvChunk = 4;  // frames whose parked u are loaded ahead
+
+__device__ void aba_inverse(const ModelLds& L, int nf, int lane, double* Hi) {
+  const bool act = lane < nf;
   double p[6] = {0, 0, 0, 0, 0, 0};
-  double t[13], b;
-#pragma unroll
-  for (int k = 0; k < 13; ++k) t[k] = L.tab[nf - 1][slot][k];
-  b = L.xb[nf - 1][slot];
   for (int f = nf - 1; f >= 0; --f) {
-    const int fn = f > 0 ? f - 1 : 0;
-    double tn[13];
-#pragma unroll
-    for (int k = 0; k < 13; ++k) tn[k] = L.tab[fn][slot][k];
-    const double bn = L.xb[fn][slot];
+    const double* t = L.tab[f];
     const double sp = (t[0] * p[0] + t[1] * p[1]) + (t[2] * p[2] + t[3] * p[3]) + (t[4] * p[4] + t[5] * p[5]);
-    const double u = b - sp;
-    L.xb[f][slot] = u;
+    const double u = (f == lane ? 1.0 : 0.0) - sp;
+    if (act) Hi[(size_t)f * nf + lane] = u;
     const double w = u * t[12];
 #pragma unroll
     for (int k = 0; k < 6; ++k) p[k] += t[6 + k] * w;
-#pragma unroll
-    for (int k = 0; k < 13; ++k) t[k] = tn[k];
-    b = bn;
   }
   double a[6] = {0, 0, 0, 0, 0, 0};
+  // chunks of kInvChunk frames; the parked u of the next chunk are requested
+  // before the current chunk is solved
+  double un[kInvChunk];
 #pragma unroll
-  for (int k = 0; k < 13; ++k) t[k] = L.tab[0][slot][k];
-  b = L.xb[0][slot];
-  for (int f = 0; f < nf; ++f) {
-    const int fn = f + 1 < nf ? f + 1 : f;
-    double tn[13];
+  for (int k = 0; k < kInvChunk; ++k) un[k] = (act && k < nf) ? Hi[(size_t)k * nf + lane] : 0.0;
+  for (int c0 = 0; c0 < nf; c0 += kInvChunk) {
+    double uc[kInvChunk];
 #pragma unroll
-    for (int k = 0; k < 13; ++k) tn[k] = L.tab[fn][slot][k];
-    const double bn = L.xb[fn][slot];
-    const double Ua = (t[6] * a[0] + t[7] * a[1]) + (t[8] * a[2] + t[9] * a[3]) + (t[10] * a[4] + t[11] * a[5]);
-    const double x = (b - Ua) * t[12];
-    L.xb[f][slot] = x;
+    for (int k = 0; k < kInvChunk; ++k) {
+      uc[k] = un[k];
+      const int fn = c0 + kInvChunk + k;
+      un[k] = (act && fn < nf) ? Hi[(size_t)fn * nf + lane] : 0.0;
+    }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) a[k] += t[k] * x;
+    for (int k = 0; k < kInvChunk; ++k) {
+      const int f = c0 + k;
+      if (f < nf) {
+        const double* t = L.tab[f];
+        const double Ua = (t[6] * a[0] + t[7] * a[1]) + (t[8] * a[2] + t[9] * a[3]) + (t[10] * a[4] + t[11] * a[5]);
+        const double x = (uc[k] - Ua) * t[12];
+        if (act) Hi[(size_t)f * nf + lane] = x;
 #pragma unroll
-    for (int k = 0; k < 13; ++k) t[k] = tn[k];
-    b = bn;
+        for (int i = 0; i < 6; ++i) a[i] += t[i] * x;
+      }
+    }
   }
+}
+
+// r_j = sum_i Hi[i][j] v_i: the preconditioner applied to the wave's vector v
+// (lane i holds v_i).  Column j lives in lane j's own stores of aba_inverse.
+constexpr int kMvChunk = 8;
+
+__device__ __forceinline__ double apply_inverse(const double* Hi, int nf, int lane, double v) {
+  const bool act = lane < nf;
+  double r = 0.0;
+  double hn[kMvChunk];
+#pragma unroll
+  for (int k = 0; k < kMvChunk; ++k) hn[k] = (act && k < nf) ? Hi[(size_t)k * nf + lane] : 0.0;
+  for (int i0 = 0; i0 < nf; i0 += kMvChunk) {
+    double hc[kMvChunk];
+#pragma unroll
+    for (int k = 0; k < kMvChunk; ++k) {
+      hc[k] = hn[k];
+      const int in = i0 + kMvChunk + k;
+      hn[k] = (act && in < nf) ? Hi[(size_t)in * nf + lane] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kMvChunk; ++k)
+      if (i0 + k < nf) r += hc[k] * readlane(v, i0 + k);
+  }
+  return r;
 }
 
 // Setup of one step for this wave's model (float64): the per-step constant
 // B = -2 A(q_k) + A(q_{k-1}) of every frame, and for the inertia preconditioner
 // the world spatial inertia (about the origin) and hinge motion at the warm start.
-template <int G>
-__device__ __forceinline__ void step_setup(const DevModel& d, SweepLds<G>& L, const FrameGeo& geo, int f, bool valid,
-                                        int wave, int lane, double qkm1, double qk, double q0, bool use_aba) {
+__device__ __forceinline__ void step_setup(const DevModel& d, ModelLds& L, const FrameGeo& geo, int f, bool valid,
+                                           int lane, double qkm1, double qk, double q0, bool use_aba) {
   double* B64 = d.B64 + (size_t)f * 12;
   float* B32 = d.B32 + (size_t)f * 12;
   {
@@ -686,7 +707,7 @@ __device__ __forceinline__ void step_setup(const DevModel& d, SweepLds<G>& L, co
       }
   }
   const double tr = Sw[0] + Sw[3] + Sw[5];
-  double* in = L.inert[lane][wave];
+  double* in = L.inert[lane];
   in[0] = valid ? tr - Sw[0] : 0.0;
   in[1] = valid ? -Sw[1] : 0.0;
   in[2] = valid ? -Sw[2] : 0.0;
@@ -700,7 +721,7 @@ __device__ __forceinline__ void step_setup(const DevModel& d, SweepLds<G>& L, co
   const double w0 = A.m[0] * a[0] + A.m[1] * a[1] + A.m[2] * a[2];
   const double w1 = A.m[4] * a[0] + A.m[5] * a[1] + A.m[6] * a[2];
   const double w2 = A.m[8] * a[0] + A.m[9] * a[1] + A.m[10] * a[2];
-  double* ts = L.tab[lane][wave];
+  double* ts = L.tab[lane];
   ts[0] = valid ? w0 : 0.0;
   ts[1] = valid ? w1 : 0.0;
   ts[2] = valid ? w2 : 0.0;
@@ -709,105 +730,79 @@ __device__ __forceinline__ void step_setup(const DevModel& d, SweepLds<G>& L, co
   ts[5] = valid ? t[0] * w1 - t[1] * w0 : 0.0;
 }
 
-// What the next evaluation of phase C is for.
+// What the next evaluation of an iteration is for.
 enum EvalPurpose { kTrial = 0, kRefresh = 1, kRefreshRetry = 2 };
 // Per-model state of the rollout kernel.
 enum ModelState { kSetup = 0, kIterate = 1, kDone = 2 };
 
-// A rollout of n_steps time steps.  Every model advances through the steps at
-// its own pace: a model whose step has converged starts its next step in the
-// following round while the other models of the workgroup keep iterating
-// (the per-iteration interleaving of Sec. 5's GPU scheme, inside one launch).
-// A round is: phase A (per model wave: step setup, or the first loop of the
-// two-loop recursion), barrier, phase B (wave 0: articulated-body recursion or
-// sweeps for every model slot that asks), barrier, phase C (per model wave:
-// first evaluation of a step, or second loop + line search + update).
+// A rollout of n_steps time steps, one model per workgroup of one wavefront.
+// Every model advances through the steps at its own pace and a workgroup ends
+// when its model has finished the last step, so the hardware dispatcher starts
+// the next model in its place (the per-iteration interleaving of Sec. 5's GPU
+// scheme, done by the dispatcher instead of a software queue).
+// A step is: setup (B, and for the inertia preconditioner the recursion and the
+// explicit inverse), the warm-start evaluation, then iterations of two-loop
+// L-BFGS direction + backtracking line search + update.
 // MIXED: float32 evaluations until the line search meets float32 rounding (or
 // float32 claims convergence), then float64 to the end of the step.
-template <int G, int MMAX, int PREC>
 #ifndef ABD_WAVES_PER_SIMD
 #define ABD_WAVES_PER_SIMD 2
 #endif
-__global__ void __launch_bounds__(G* kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs args) {
-  __shared__ SweepLds<G> L;
+template <int PREC>
+__global__ void __launch_bounds__(kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs args) {
+  __shared__ ModelLds L;
+  // L-BFGS pairs of the current step: s in ring slots [0, m), y in [m, 2m),
+  // one double per lane per slot
+  extern __shared__ double pairs[];
   const DevModel& d = args.d;
   const int n = d.n_dofs;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int model = blockIdx.x * G + wave;
+  const int lane = threadIdx.x;
+  const int model = blockIdx.x;
   const bool has_model = model < d.n_models;
-  const int f0 = has_model ? d.f0[model] : 0;
-  const int nf = has_model ? d.f0[model + 1] - f0 : 0;
+  if (!has_model) return;
+  const int f0 = d.f0[model];
+  const int nf = d.f0[model + 1] - f0;
   const bool valid = lane < nf;
   const int f = f0 + (valid ? lane : 0);
   const bool use_aba = args.precond == ABD_PRECOND_INERTIA;
-  if (lane == 0) {
-    L.nf[wave] = nf;
-    L.f0[wave] = f0;
-  }
+  double* Hi = d.hinv + d.hoff[model];
   const FrameGeo geo = load_geo(d, f, valid);
   const double eps_w = PREC == ABD_MIXED ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
   const double c1 = 1e-4, dlt = 0.1;
 
-  // history of the current step (registers), q_{k-1} and q_k
+  // q_{k-1} and q_k of the current step
   double qkm1 = valid ? args.q_prev[f] : 0.0;
   double qk = valid ? args.q_curr[f] : 0.0;
   int step = 0;
-  int state = has_model ? kSetup : kDone;
-  if (has_model && args.n_steps <= 0) state = kDone;
+  int state = args.n_steps > 0 ? kSetup : kDone;
 
   // per-step solver state
-  double* hs = d.hist + (size_t)f * (2 * kMaxHist);
+  double* hs = pairs + lane;
+  const int ys = args.m * kWave;  // offset of the y ring
   bool f32 = false, reset = false;
   int iters = 0, evals = 0, flag = 0, f32_iters = 0, count = 0, head = 0;
-  double q = 0.0, tau = 0.0, E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0, qv = 0.0;
+  double q = 0.0, tau = 0.0, E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0;
 
-  for (;;) {
-    PROF_T(t_round);
-    // ------------------------------------------------------------ phase A
-    if (state == kSetup) {
-      q = valid ? 2.0 * qk - qkm1 : 0.0;  // warm start: constant-velocity extrapolation
-      tau = (valid && args.tau) ? args.tau[(size_t)step * n + f] : 0.0;
-      if (nf > 0) step_setup<G>(d, L, geo, f, valid, wave, lane, qkm1, qk, q, use_aba);
-    } else if (state == kIterate) {
-      if (reset) count = 0;
-      qv = g;
-      // newest pair first; the next pair is requested while the current one is used
-      double sk = (valid && count > 0) ? hs[head] : 0.0, yk = (valid && count > 0) ? hs[kMaxHist + head] : 0.0;
-      for (int k = 0; k < count; ++k) {
-        const int nxt = (head - k - 1 + args.m) % args.m;
-        const double sn = (valid && k + 1 < count) ? hs[nxt] : 0.0;
-        const double yn = (valid && k + 1 < count) ? hs[kMaxHist + nxt] : 0.0;
-        const double a_k = uniform(L.rho[k][wave] * wave_sum(sk * qv));
-        if (lane == 0) L.alp[k][wave] = a_k;
-        qv -= a_k * yk;
-        sk = sn;
-        yk = yn;
-      }
-      if (use_aba) L.xb[lane][wave] = valid ? qv : 0.0;
-    }
-    if (lane == 0) L.req[wave] = (use_aba && nf > 0) ? (state == kSetup ? 2 : state == kIterate ? 1 : 0) : 0;
-    PROF_ADD(state == kSetup ? 0 : 1, t_round);
-    PROF_T(t_b0);
-    __syncthreads();
-    PROF_ADD(2, t_b0);
-    // ------------------------------------------------------------ phase B
-    PROF_T(t_b);
-    if (wave == 0 && lane < G) {
-      if (L.req[lane] == 2) aba_setup<G>(L, lane);
-      else if (L.req[lane] == 1) aba_solve<G>(L, lane);
-    }
-    __syncthreads();
-    PROF_ADD(3, t_b);
-    PROF_T(t_c);
-    // ------------------------------------------------------------ phase C
+  while (state != kDone) {
     bool step_done = false;
     if (state == kSetup) {
+      PROF_T(t_s);
+      q = valid ? 2.0 * qk - qkm1 : 0.0;  // warm start: constant-velocity extrapolation
+      tau = (valid && args.tau) ? args.tau[(size_t)step * n + f] : 0.0;
       f32 = PREC == ABD_MIXED;
       iters = 0; evals = 0; flag = 0; f32_iters = 0; count = 0; head = 0; reset = false; gam = 1.0;
       if (nf == 0) {
         flag = ABD_FLAG_CONVERGED;
         step_done = true;
       } else {
+        step_setup(d, L, geo, f, valid, lane, qkm1, qk, q, use_aba);
+        if (use_aba) {
+          __syncthreads();
+          if (lane == 0) aba_setup(L, nf);
+          __syncthreads();
+          aba_inverse(L, nf, lane, Hi);
+        }
+        PROF_ADD(0, t_s);
         const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(d, geo, f, valid, q, tau, args.dt2)
                                                   : evaluate<double>(d, geo, f, valid, q, tau, args.dt2);
         ++evals;
@@ -831,18 +826,41 @@ __global__ void __launch_bounds__(G* kWave, ABD_WAVES_PER_SIMD) k_rollout(StepAr
           }
         }
       }
-    } else if (state == kIterate) {
-      double r = use_aba ? L.xb[lane][wave] : (count > 0 ? gam : 1.0) * qv;
-      // oldest pair first
+    } else {
+      PROF_T(t_a);
+      // ---- two-loop recursion: newest pair first; the next pair is requested
+      // while the current one is used
+      if (reset) count = 0;
+      double qv = g;
+      {
+        double sk = (valid && count > 0) ? hs[head * kWave] : 0.0;
+        double yk = (valid && count > 0) ? hs[ys + head * kWave] : 0.0;
+        for (int k = 0; k < count; ++k) {
+          const int nxt = (head - k - 1 + args.m) % args.m;
+          const double sn = (valid && k + 1 < count) ? hs[nxt * kWave] : 0.0;
+          const double yn = (valid && k + 1 < count) ? hs[ys + nxt * kWave] : 0.0;
+          const double a_k = uniform(L.rho[k] * wave_sum(sk * qv));
+          if (lane == 0) L.alp[k] = a_k;
+          qv -= a_k * yk;
+          sk = sn;
+          yk = yn;
+        }
+      }
+      // ---- initial inverse Hessian
+      double r = use_aba ? apply_inverse(Hi, nf, lane, qv) : (count > 0 ? gam : 1.0) * qv;
+      PROF_ADD(1, t_a);
+      PROF_T(t_c);
+      // ---- oldest pair first
       {
         int slot = (head - (count - 1) + args.m) % args.m;
-        double sk = (valid && count > 0) ? hs[slot] : 0.0, yk = (valid && count > 0) ? hs[kMaxHist + slot] : 0.0;
+        double sk = (valid && count > 0) ? hs[slot * kWave] : 0.0;
+        double yk = (valid && count > 0) ? hs[ys + slot * kWave] : 0.0;
         for (int k = count - 1; k >= 0; --k) {
           const int nxt = (slot + 1) % args.m;
-          const double sn = (valid && k > 0) ? hs[nxt] : 0.0;
-          const double yn = (valid && k > 0) ? hs[kMaxHist + nxt] : 0.0;
-          const double b = uniform(L.rho[k][wave] * wave_sum(yk * r));
-          r += (L.alp[k][wave] - b) * sk;
+          const double sn = (valid && k > 0) ? hs[nxt * kWave] : 0.0;
+          const double yn = (valid && k > 0) ? hs[ys + nxt * kWave] : 0.0;
+          const double b = uniform(L.rho[k] * wave_sum(yk * r));
+          r += (L.alp[k] - b) * sk;
           sk = sn;
           yk = yn;
           slot = nxt;
@@ -872,11 +890,9 @@ __global__ void __launch_bounds__(G* kWave, ABD_WAVES_PER_SIMD) k_rollout(StepAr
           else
             rt = evaluate<double>(d, geo, f, valid, x, tau, args.dt2);
           PROF_ADD(6, t_e);
-          if (lane == 0 && has_model) {
 #ifdef ABD_PROFILE
-            abd_prof[(size_t)model * 16 + 7] += 1;
+          if (lane == 0) abd_prof[(size_t)model * 16 + 7] += 1;
 #endif
-          }
           ++evals;
           if (purpose != kTrial) {
             // float64 re-evaluation at q after leaving float32
@@ -924,14 +940,14 @@ __global__ void __launch_bounds__(G* kWave, ABD_WAVES_PER_SIMD) k_rollout(StepAr
           wave_sum2(yy, unused);
           if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
             if (lane == 0) {
-              for (int k = args.m - 1; k > 0; --k) L.rho[k][wave] = L.rho[k - 1][wave];
-              L.rho[0][wave] = 1.0 / sy;
+              for (int k = args.m - 1; k > 0; --k) L.rho[k] = L.rho[k - 1];
+              L.rho[0] = 1.0 / sy;
             }
             gam = uniform(sy / yy);
             head = count == 0 ? 0 : (head + 1) % args.m;
             if (valid) {
-              hs[head] = sv;
-              hs[kMaxHist + head] = y;
+              hs[head * kWave] = sv;
+              hs[ys + head * kWave] = y;
             }
             if (count < args.m) ++count;
           }
@@ -957,8 +973,11 @@ __global__ void __launch_bounds__(G* kWave, ABD_WAVES_PER_SIMD) k_rollout(StepAr
           break;
         }
       }
+      PROF_ADD(5, t_c);
+#ifdef ABD_PROFILE
+      if (lane == 0) abd_prof[(size_t)model * 16 + 9] += 1;
+#endif
     }
-    PROF_ADD(state == kSetup ? 4 : 5, t_c);
     if (step_done) {
       if (valid) args.q_out[(size_t)step * n + f] = q;
       if (args.stats && lane == 0) {
@@ -976,15 +995,337 @@ __global__ void __launch_bounds__(G* kWave, ABD_WAVES_PER_SIMD) k_rollout(StepAr
       ++step;
       state = step < args.n_steps ? kSetup : kDone;
     }
-    PROF_T(t_end);
-    const bool more = __syncthreads_or(state != kDone ? 1 : 0);
-    PROF_ADD(8, t_end);
-    if (lane == 0 && has_model) {
-#ifdef ABD_PROFILE
-      abd_prof[(size_t)model * 16 + 9] += 1;
-#endif
+  }
+}
+
+// ------------------------------------------------------- second order --
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Suffix sum over the frames at and below each lane (chain order = lane order).
+__device__ __forceinline__ double wave_suffix_sum(double v) {
+  const double pre = wave_prefix_sum(v);
+  return (readlane(pre, 63) - pre) + v;
+}
+
+// Adjoint backward pass of Alg. 1 for a given seed S_l = dF/dA_l (3x4 per frame)
+// at the configuration whose poses are A (world-frame form): returns
+// dF/dq_n = w_n . (K_n - p_n x F_n) with the suffix sums of
+// k = sum_c R[:,c] x S[:,c] + t x S[:,3] and f = S[:,3].
+__device__ double adjoint_of_seed(const Xf<double>& A, const double S[12], const double a[3], bool valid) {
+  const double t[3] = {A.m[3], A.m[7], A.m[11]};
+  double k[3] = {0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double col[3] = {c < 3 ? A.m[c] : t[0], c < 3 ? A.m[4 + c] : t[1], c < 3 ? A.m[8 + c] : t[2]};
+    const double s[3] = {S[c], S[4 + c], S[8 + c]};
+    double x[3];
+    cross3(col, s, x);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) k[i] += x[i];
+  }
+  double K[3], F[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    K[i] = wave_suffix_sum(valid ? k[i] : 0.0);
+    F[i] = wave_suffix_sum(valid ? S[4 * i + 3] : 0.0);
+  }
+  double w[3], pF[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) w[i] = A.m[4 * i] * a[0] + A.m[4 * i + 1] * a[1] + A.m[4 * i + 2] * a[2];
+  cross3(t, F, pF);
+  const double r = w[0] * (K[0] - pF[0]) + w[1] * (K[1] - pF[1]) + w[2] * (K[2] - pF[2]);
+  return valid ? r : 0.0;
+}
+
+// Tangent of the poses along a DOF direction v (forward-mode Alg. 1):
+// dA_j/dq_n = [[w_n]x R_j | w_n x (t_j - p_n)] for every frame n at or above j,
+// so with the prefix sums W_j = sum v_n w_n and Z_j = sum v_n (w_n x p_n)
+//   dR_j = [W_j]x R_j,   dt_j = W_j x t_j - Z_j.
+__device__ void tangent_pose(const Xf<double>& A, const double a[3], bool valid, double v, double dA[12],
+                             double W[3], double w[3]) {
+  const double t[3] = {A.m[3], A.m[7], A.m[11]};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) w[i] = A.m[4 * i] * a[0] + A.m[4 * i + 1] * a[1] + A.m[4 * i + 2] * a[2];
+  double wp[3];
+  cross3(w, t, wp);
+  const double vv = valid ? v : 0.0;
+  double Z[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    W[i] = wave_prefix_sum(vv * w[i]);
+    Z[i] = wave_prefix_sum(vv * wp[i]);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double col[3] = {A.m[c], A.m[4 + c], A.m[8 + c]};
+    double x[3];
+    cross3(W, col, x);
+    dA[c] = x[0];
+    dA[4 + c] = x[1];
+    dA[8 + c] = x[2];
+  }
+  double Wt[3];
+  cross3(W, t, Wt);
+  dA[3] = Wt[0] - Z[0];
+  dA[7] = Wt[1] - Z[1];
+  dA[11] = Wt[2] - Z[2];
+}
+
+// Hessian-vector product of the step objective at q (float64): the derivative
+// of the gradient g_n = w_n . (K_n - p_n x F_n) along v.  With the tangent
+// poses dA and the tangent seed dG = dA M (the gravity part of the seed is
+// constant),
+//   dk = sum_c (dR[:,c] x G[:,c] + R[:,c] x dG[:,c]) + dt x G[:,3] + t x dG[:,3],
+//   (Hv)_n = dw_n . (K_n - p_n x F_n) + w_n . (dK_n - dp_n x F_n - p_n x dF_n),
+// dw_n = W_n x w_n, dp_n = dt_n.  Needs B of the step in the model scratch.
+__device__ double hess_vec(const DevModel& d, const FrameGeo& geo, int f, bool valid, double q, double v,
+                           double dt2) {
+  asm volatile("" ::: "memory");
+  double M[10], B[12];
+  const double* rec = d.fr64 + (size_t)f * 16;
+  const double* Bp = d.B64 + (size_t)f * 12;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) M[k] = valid ? rec[6 + k] : 0.0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) B[k] = valid ? Bp[k] : 0.0;
+  const Xf<double> A = fk_geo<double>(geo, valid, q);
+  double dA[12], W[3], w[3];
+  tangent_pose(A, geo.a, valid, v, dA, W, w);
+  const double g[3] = {d.gx, d.gy, d.gz};
+  double G[12], dG[12];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double s = 0.0, ds = 0.0;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        s += (A.m[4 * r + x] + B[4 * r + x]) * M[sym4(x, c)];
+        ds += dA[4 * r + x] * M[sym4(x, c)];
+      }
+      G[4 * r + c] = s - dt2 * g[r] * M[sym4(c, 3)];
+      dG[4 * r + c] = ds;
     }
-    if (!more) break;
+  double k[3] = {0, 0, 0}, dk[3] = {0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double col[3] = {A.m[c], A.m[4 + c], A.m[8 + c]};
+    const double dcol[3] = {dA[c], dA[4 + c], dA[8 + c]};
+    const double gc[3] = {G[c], G[4 + c], G[8 + c]};
+    const double dgc[3] = {dG[c], dG[4 + c], dG[8 + c]};
+    double x[3], y[3], z[3];
+    cross3(col, gc, x);
+    cross3(dcol, gc, y);
+    cross3(col, dgc, z);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      k[i] += x[i];
+      dk[i] += y[i] + z[i];
+    }
+  }
+  double K[3], F[3], dK[3], dF[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    K[i] = wave_suffix_sum(valid ? k[i] : 0.0);
+    F[i] = wave_suffix_sum(valid ? G[4 * i + 3] : 0.0);
+    dK[i] = wave_suffix_sum(valid ? dk[i] : 0.0);
+    dF[i] = wave_suffix_sum(valid ? dG[4 * i + 3] : 0.0);
+  }
+  const double p[3] = {A.m[3], A.m[7], A.m[11]};
+  const double dp[3] = {dA[3], dA[7], dA[11]};
+  double dw[3], pF[3], dpF[3], pdF[3];
+  cross3(W, w, dw);
+  cross3(p, F, pF);
+  cross3(dp, F, dpF);
+  cross3(p, dF, pdF);
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r += dw[i] * (K[i] - pF[i]) + w[i] * (dK[i] - dpF[i] - pdF[i]);
+  return valid ? r : 0.0;
+}
+
+// B = A(q_{k-1}) - 2 A(q_k) of this lane's frame into the model scratch.
+__device__ __forceinline__ void write_B(const DevModel& d, const FrameGeo& geo, int f, bool valid, double qkm1,
+                                        double qk) {
+  const Xf<double> Ak = fk_geo<double>(geo, valid, qk);
+  const Xf<double> Akm1 = fk_geo<double>(geo, valid, qkm1);
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double b = Akm1.m[k] - 2.0 * Ak.m[k];
+      d.B64[(size_t)f * 12 + k] = b;
+      d.B32[(size_t)f * 12 + k] = (float)b;
+    }
+  }
+}
+
+struct HvpArgs {
+  DevModel d;
+  double dt2;
+  const double* q;
+  const double* q_prev;
+  const double* q_curr;
+  const double* v;
+  double* Hv;
+};
+
+__global__ void __launch_bounds__(kWave) k_hvp(HvpArgs a) {
+  const DevModel& d = a.d;
+  const int model = blockIdx.x, lane = threadIdx.x;
+  const int f0 = d.f0[model], nf = d.f0[model + 1] - f0;
+  if (nf == 0) return;
+  const bool valid = lane < nf;
+  const int f = f0 + (valid ? lane : 0);
+  const FrameGeo geo = load_geo(d, f, valid);
+  write_B(d, geo, f, valid, valid ? a.q_prev[f] : 0.0, valid ? a.q_curr[f] : 0.0);
+  // the B rows of this lane were written by this lane: no barrier needed
+  const double hv = hess_vec(d, geo, f, valid, valid ? a.q[f] : 0.0, valid ? a.v[f] : 0.0, a.dt2);
+  if (valid) a.Hv[f] = hv;
+}
+
+// Reverse-mode derivative of a rollout by implicit differentiation.  Step k
+// defines q_{k+1} by the stationarity of its objective (Eq. PBAD),
+// g(q_{k+1}; q_k, q_{k-1}, tau_k) = 0, so with lambda = dL/dq_{k+1} (complete
+// once the later steps are done) and H mu = lambda (H = Hessian at q_{k+1}):
+//   dL/dq_k     += adjoint at q_k     of the seed  2 dA(mu) M,
+//   dL/dq_{k-1} += adjoint at q_{k-1} of the seed   -dA(mu) M,
+//   dL/dtau_k    = dt^2 mu,
+// dA(mu) the tangent poses at q_{k+1} along mu.  H mu = lambda is solved by
+// conjugate gradients preconditioned with the inverse joint-space inertia at
+// q_{k+1} (the same operator as the step's initial inverse Hessian).
+struct VjpArgs {
+  DevModel d;
+  double dt2, tol;
+  int max_iter, n_steps, use_aba;
+  const double* q_init;  // [2][n]: q_{-1}, q_0
+  const double* q_traj;  // [n_steps][n]: q_1 .. q_T
+  const double* dL_dq;   // [n_steps][n]: explicit dL/dq_1 .. dL/dq_T
+  double* dL_dinit;      // [2][n]
+  double* dL_dtau;       // [n_steps][n] or NULL
+  abd_step_stats* stats; // [n_steps][n_models] or NULL
+};
+
+__global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
+  __shared__ ModelLds L;
+  const DevModel& d = args.d;
+  const int n = d.n_dofs, T = args.n_steps;
+  const int model = blockIdx.x, lane = threadIdx.x;
+  const int f0 = d.f0[model], nf = d.f0[model + 1] - f0;
+  const bool valid = lane < nf;
+  const int f = f0 + (valid ? lane : 0);
+  const FrameGeo geo = load_geo(d, f, valid);
+  double* Hi = d.hinv + d.hoff[model];
+  const bool use_aba = args.use_aba != 0;
+  // q_j and the explicit dL/dq_j of this lane's DOF, j >= -1
+  auto qat = [&](int j) -> double {
+    if (!valid) return 0.0;
+    return j >= 1 ? args.q_traj[(size_t)(j - 1) * n + f] : args.q_init[(size_t)(j + 1) * n + f];
+  };
+  auto dl = [&](int j) -> double { return (valid && j >= 1) ? args.dL_dq[(size_t)(j - 1) * n + f] : 0.0; };
+  double lam_next = dl(T), lam_cur = dl(T - 1), lam_prev = dl(T - 2);
+  for (int k = T - 1; k >= 0; --k) {
+    const double q = qat(k + 1), qc = qat(k), qp = qat(k - 1);
+    double mu = 0.0, rn = 0.0;
+    int it = 0, hv_count = 0, flag = ABD_FLAG_CONVERGED;
+    if (nf > 0) {
+      step_setup(d, L, geo, f, valid, lane, qp, qc, q, use_aba);
+      if (use_aba) {
+        __syncthreads();
+        if (lane == 0) aba_setup(L, nf);
+        __syncthreads();
+        aba_inverse(L, nf, lane, Hi);
+      }
+      // ---- preconditioned conjugate gradients on H mu = lambda
+      const double b = valid ? lam_next : 0.0;
+      const double bn = uniform(sqrt(wave_sum(b * b)));
+      double r = b;
+      double z = use_aba ? apply_inverse(Hi, nf, lane, r) : r;
+      double p = z;
+      double rz = uniform(wave_sum(r * z));
+      rn = bn;
+      if (!isfinite(bn)) {
+        flag = ABD_FLAG_NONFINITE;
+      } else if (bn > 0.0) {
+        flag = ABD_FLAG_MAX_ITER;
+        while (it < args.max_iter) {
+          const double hp = hess_vec(d, geo, f, valid, q, p, args.dt2);
+          ++hv_count;
+          const double php = uniform(wave_sum(p * hp));
+          if (!(php > 0.0)) {
+            flag = ABD_FLAG_LS_FLOOR;  // not positive definite along p
+            break;
+          }
+          const double al = rz / php;
+          mu += al * p;
+          r -= al * hp;
+          ++it;
+          rn = uniform(sqrt(wave_sum(r * r)));
+          if (rn <= args.tol * bn) {
+            flag = ABD_FLAG_CONVERGED;
+            break;
+          }
+          z = use_aba ? apply_inverse(Hi, nf, lane, r) : r;
+          const double rz1 = uniform(wave_sum(r * z));
+          p = z + (rz1 / rz) * p;
+          rz = rz1;
+        }
+      }
+      // ---- propagate to the two past configurations
+      double M[10];
+      const double* rec = d.fr64 + (size_t)f * 16;
+#pragma unroll
+      for (int i = 0; i < 10; ++i) M[i] = valid ? rec[6 + i] : 0.0;
+      double S[12];
+      {
+        const Xf<double> A = fk_geo<double>(geo, valid, q);
+        double dA[12], W[3], w[3];
+        tangent_pose(A, geo.a, valid, mu, dA, W, w);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int x = 0; x < 4; ++x) s += dA[4 * r + x] * M[sym4(x, c)];
+            S[4 * r + c] = s;
+          }
+      }
+      {
+        const Xf<double> Ac = fk_geo<double>(geo, valid, qc);
+        double S2[12];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) S2[i] = 2.0 * S[i];
+        lam_cur += adjoint_of_seed(Ac, S2, geo.a, valid);
+      }
+      {
+        const Xf<double> Ap = fk_geo<double>(geo, valid, qp);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) S[i] = -S[i];
+        lam_prev += adjoint_of_seed(Ap, S, geo.a, valid);
+      }
+    }
+    if (args.dL_dtau && valid) args.dL_dtau[(size_t)k * n + f] = args.dt2 * mu;
+    if (args.stats && lane == 0) {
+      abd_step_stats st;
+      st.iterations = it;
+      st.evaluations = hv_count;
+      st.flag = flag;
+      st.f32_iterations = 0;
+      st.grad_norm = rn;
+      st.energy = 0.0;
+      args.stats[(size_t)k * d.n_models + model] = st;
+    }
+    lam_next = lam_cur;
+    lam_cur = lam_prev;
+    lam_prev = dl(k - 2);
+  }
+  if (valid) {
+    args.dL_dinit[f] = lam_cur;        // q_{-1}
+    args.dL_dinit[(size_t)n + f] = lam_next;  // q_0
   }
 }
 
@@ -1061,7 +1402,8 @@ struct abd_model {
   float* fr32 = nullptr;
   double* B64 = nullptr;
   float* B32 = nullptr;
-  double* hist = nullptr;
+  long long* hoff = nullptr;
+  double* hinv = nullptr;
   std::vector<void*> allocs;
 };
 
@@ -1128,7 +1470,8 @@ DevModel dev_view(const abd_model* m) {
   d.fr32 = m->fr32;
   d.pose_link = m->pose_link;
   d.B64 = m->B64; d.B32 = m->B32;
-  d.hist = m->hist;
+  d.hoff = m->hoff;
+  d.hinv = m->hinv;
   d.gx = m->g[0]; d.gy = m->g[1]; d.gz = m->g[2];
   return d;
 }
@@ -1230,6 +1573,12 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   if (!chain) return fail(ABD_ENOTSUP, "branched trees are not handled by this build (serial chains only)");
   if (max_frames > kMaxFrames)
     return fail(ABD_ENOTSUP, "models with more than 64 DOFs are not handled by this build");
+  // every model's explicit inverse inertia (nf x nf doubles)
+  std::vector<long long> hoff(nm + 1, 0);
+  for (int i = 0; i < nm; ++i) {
+    const long long k = f0[i + 1] - f0[i];
+    hoff[i + 1] = hoff[i] + k * k;
+  }
 
   abd_model* m = new abd_model();
   HIP_TRY(hipGetDevice(&m->device));
@@ -1242,7 +1591,8 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   if ((rc = upload(m, &m->f0, f0)) || (rc = upload(m, &m->pose_link, pose_link)) ||
       (rc = upload(m, &m->fr64, fr64)) || (rc = upload(m, &m->fr32, fr32)) ||
       (rc = alloc(m, &m->B64, 12 * (size_t)nd)) || (rc = alloc(m, &m->B32, 12 * (size_t)nd)) ||
-      (rc = alloc(m, &m->hist, 2 * kMaxHist * (size_t)nd))) {
+      (rc = upload(m, &m->hoff, hoff)) ||
+      (rc = alloc(m, &m->hinv, (size_t)hoff[nm]))) {
     free_model(m);
     delete m;
     return rc;
@@ -1282,20 +1632,13 @@ static int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_
   a.tau = tau;
   a.q_out = q_out;
   a.stats = stats;
-  const int blocks = (m->n_models + kG - 1) / kG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const dim3 grid(blocks), block(kG * kWave);
-  if (o->precision == ABD_FP64) {
-    if (o->lbfgs_m <= 5)
-      hipLaunchKernelGGL((k_rollout<kG, 5, ABD_FP64>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_rollout<kG, 10, ABD_FP64>), grid, block, 0, s, a);
-  } else {
-    if (o->lbfgs_m <= 5)
-      hipLaunchKernelGGL((k_rollout<kG, 5, ABD_MIXED>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_rollout<kG, 10, ABD_MIXED>), grid, block, 0, s, a);
-  }
+  const dim3 grid(m->n_models), block(kWave);
+  const size_t pair_bytes = 2 * (size_t)o->lbfgs_m * kWave * sizeof(double);
+  if (o->precision == ABD_FP64)
+    hipLaunchKernelGGL((k_rollout<ABD_FP64>), grid, block, pair_bytes, s, a);
+  else
+    hipLaunchKernelGGL((k_rollout<ABD_MIXED>), grid, block, pair_bytes, s, a);
   HIP_TRY(hipGetLastError());
   return ABD_OK;
 }
@@ -1350,6 +1693,62 @@ int abd_objective_grad(abd_model* m, const abd_step_opts* o, const double* q, co
   a.E = E;
   a.grad = grad;
   hipLaunchKernelGGL(k_objective_grad, dim3(m->n_models), dim3(kWave), 0, static_cast<hipStream_t>(stream), a);
+  HIP_TRY(hipGetLastError());
+  return ABD_OK;
+}
+
+int abd_hvp(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist, const double* v,
+            double* Hv, void* stream) {
+  g_err.clear();
+  if (!m) return fail(ABD_EINVAL, "model is NULL");
+  int rc = check_opts(o, false);
+  if (rc) return rc;
+  if (m->n_models == 0) return ABD_OK;
+  if (!q || !q_hist || !v || !Hv) return fail(ABD_EINVAL, "q, q_hist, v and Hv must not be NULL");
+  if ((rc = check_device(m))) return rc;
+  HvpArgs a;
+  a.d = dev_view(m);
+  a.dt2 = o->dt * o->dt;
+  a.q = q;
+  a.q_prev = q_hist;
+  a.q_curr = q_hist + m->n_dofs;
+  a.v = v;
+  a.Hv = Hv;
+  hipLaunchKernelGGL(k_hvp, dim3(m->n_models), dim3(kWave), 0, static_cast<hipStream_t>(stream), a);
+  HIP_TRY(hipGetLastError());
+  return ABD_OK;
+}
+
+int abd_rollout_vjp(abd_model* m, const abd_step_opts* o, const double* q_init, const double* q_traj,
+                    const double* dL_dq_traj, double* dL_dq_init, double* dL_dtau, abd_step_stats* stats,
+                    int n_steps, void* stream) {
+  g_err.clear();
+  if (!m) return fail(ABD_EINVAL, "model is NULL");
+  int rc = check_opts(o, false);
+  if (rc) return rc;
+  if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(ABD_EINVAL, "tol must be finite and >= 0");
+  if (o->max_iter < 0) return fail(ABD_EINVAL, "max_iter must be >= 0");
+  if (o->precond != ABD_PRECOND_IDENTITY && o->precond != ABD_PRECOND_INERTIA)
+    return fail(ABD_EINVAL, "precond must be ABD_PRECOND_IDENTITY or ABD_PRECOND_INERTIA");
+  if (n_steps < 1) return fail(ABD_EINVAL, "n_steps must be >= 1");
+  if (m->n_models == 0) return ABD_OK;
+  if (!q_init || !q_traj || !dL_dq_traj || !dL_dq_init)
+    return fail(ABD_EINVAL, "q_init, q_traj, dL_dq_traj and dL_dq_init must not be NULL");
+  if ((rc = check_device(m))) return rc;
+  VjpArgs a;
+  a.d = dev_view(m);
+  a.dt2 = o->dt * o->dt;
+  a.tol = o->tol;
+  a.max_iter = o->max_iter;
+  a.n_steps = n_steps;
+  a.use_aba = o->precond == ABD_PRECOND_INERTIA;
+  a.q_init = q_init;
+  a.q_traj = q_traj;
+  a.dL_dq = dL_dq_traj;
+  a.dL_dinit = dL_dq_init;
+  a.dL_dtau = dL_dtau;
+  a.stats = stats;
+  hipLaunchKernelGGL(k_rollout_vjp, dim3(m->n_models), dim3(kWave), 0, static_cast<hipStream_t>(stream), a);
   HIP_TRY(hipGetLastError());
   return ABD_OK;
 }

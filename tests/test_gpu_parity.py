@@ -250,30 +250,41 @@ def test_rollout_equals_step_loop_bitwise(precision):
 
 
 def test_rollout_with_torques_matches_oracle():
-    """Rollout with per-step joint torques (config 5 chains).  Each step is only
-    determined to the solver tolerance, and a free trajectory compounds those
-    differences, so every GPU step k is compared with the oracle step taken from
-    the GPU's own (q_{k-1}, q_k) and torque k (which also checks that step k
-    reads torque row k).  These chains reach the float64 floor |H| eps |q| of
-    the gradient before a 1e-11 relative tolerance, so the comparison uses the
-    configured tolerance and its bound."""
+    """Rollout with per-step joint torques (config 5 chains: 1 m, 10 kg links).
+    Every GPU step k is checked against the exact minimizer q* of the step from
+    the GPU's own (q_{k-1}, q_k) and torque k (oracle L-BFGS, then Newton), which
+    also checks that step k reads torque row k.  These chains are so badly
+    conditioned that a relative gradient tolerance of 1e-8 leaves ~1e-6 in q
+    (the oracle's own result is 9e-7 from q* on one of these steps), so the
+    check is the one the tolerance implies: the gradient at the GPU's q
+    (computed by the oracle) is within the tolerance, and the GPU's q is within
+    |H(q*)^-1| |g(q)| of q* (first-order bound, 50% margin)."""
     steps = 5
     wl = W.config(5, n_models=32, steps=steps)
     dt = wl.step.dt
+    d = wl.model
     say("rollout with torques")
-    m = abd.Model(wl.model)
+    m = abd.Model(d)
     q0 = cu(wl.q0)
-    traj, _ = m.rollout(torch.cat([q0, q0]), steps, abd.StepOptions(dt=dt), torque=cu(wl.torque))
+    tol = wl.step.tol
+    traj, _ = m.rollout(torch.cat([q0, q0]), steps, abd.StepOptions(dt=dt, tol=tol), torque=cu(wl.torque))
     qg = np.concatenate([wl.q0[None], wl.q0[None], traj.cpu().numpy()])  # q_{-1}, q_0, q_1..
-    orc = Oracle(wl.model)
+    orc = Oracle(d)
+    do = d.dof_offset
     for k in range(steps):
-        ref, _ = orc.step(qg[k], qg[k + 1], dt, tau=wl.torque[k])
-        assert rel_q(qg[k + 2], ref) <= 1e-7, k
-    # the free trajectories stay together to the compounded tolerance
-    qs, _ = orc.rollout(wl.q0, steps, dt, torque=wl.torque)
-    assert rel_q(qg[2:], qs[1:]) <= 1e-5
-
-
+        qp, qc, tau = qg[k], qg[k + 1], wl.torque[k]
+        ref, _ = orc.step(qp, qc, dt, tau=tau, tol=1e-11, max_iter=2000)
+        qs, _ = orc.newton_polish(ref, qp, qc, dt, tau=tau, iters=3)
+        _, g_w, _ = orc.objective_grad(2 * qc - qp, qp, qc, dt, tau)  # gradient at the warm start
+        _, g_q, _ = orc.objective_grad(qg[k + 2], qp, qc, dt, tau)     # gradient at the GPU's q
+        H = orc.hessian(qs, qp, qc, dt)
+        for i in range(d.n_models):
+            sl = slice(do[i], do[i + 1])
+            gq, gw = np.linalg.norm(g_q[sl]), np.linalg.norm(g_w[sl])
+            assert gq <= 2.0 * tol * gw + 1e-13, (k, i, gq, gw)
+            hinv = 1.0 / np.min(np.linalg.eigvalsh(H[i]))
+            err = np.linalg.norm(qg[k + 2][sl] - qs[sl])
+            assert err <= 1.5 * hinv * gq + 1e-12, (k, i, err, hinv * gq)
 # ------------------------------------------------------------- edge cases
 def test_empty_batch():
     d = W.random_chain_models(0, 1)
