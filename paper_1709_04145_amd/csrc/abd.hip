@@ -58,7 +58,8 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 constexpr int kWave = 64;
-constexpr int kMaxFrames = 64;  // frames (DOFs) per model handled by one wavefront
+constexpr int kMaxFrames = 64;  // frames (DOFs) per wavefront
+constexpr int kMaxWaves = 16;   // wavefronts per model (at most 1024 frames)
 constexpr int kMaxHist = 10;    // longest L-BFGS history
 
 // Optional per-phase cycle counters (build with -DABD_PROFILE): lane 0 of every
@@ -68,7 +69,7 @@ __device__ unsigned long long* abd_prof;
 #define PROF_T(var) unsigned long long var = __builtin_readcyclecounter()
 #define PROF_ADD(slot, t0)                                                          \
   do {                                                                              \
-    if (lane == 0 && has_model)                                                     \
+    if (threadIdx.x == 0 && has_model)                                              \
       abd_prof[(size_t)model * 16 + (slot)] += __builtin_readcyclecounter() - (t0); \
   } while (0)
 #else
@@ -311,14 +312,20 @@ __device__ __forceinline__ Quat<R> hinge_quat(const R a[3], double q) {
   return r;
 }
 
-// index of S[x][y] in the 6-entry upper triangle of a symmetric 3x3 (00 01 02 11 12 22)
+// Index of S[x][y] in the 6-entry upper triangle of a symmetric 3x3
+// (00 01 02 11 12 22), and of M[x][y] in the 10-entry upper triangle of a
+// symmetric 4x4.  Written without recursion so that, with unrolled constant
+// arguments, the index folds to a constant (a recursive form is turned into a
+// loop before inlining and leaves a run-time register index).
+__device__ __forceinline__ constexpr int sym3_ordered(int x, int y) { return x == 0 ? y : x == 1 ? 2 + y : 5; }
 __device__ __forceinline__ constexpr int sym3(int x, int y) {
-  return x <= y ? (x == 0 ? y : x == 1 ? 2 + y : 5) : sym3(y, x);
+  return x <= y ? sym3_ordered(x, y) : sym3_ordered(y, x);
 }
-
-// index of M[x][y] in the 10-entry upper triangle
+__device__ __forceinline__ constexpr int sym4_ordered(int x, int y) {
+  return x == 0 ? y : x == 1 ? 3 + y : x == 2 ? 5 + y : 9;
+}
 __device__ __forceinline__ constexpr int sym4(int x, int y) {
-  return x <= y ? (x == 0 ? y : x == 1 ? 3 + y : x == 2 ? 5 + y : 9) : sym4(y, x);
+  return x <= y ? sym4_ordered(x, y) : sym4_ordered(y, x);
 }
 
 // ------------------------------------------------------------- model data --
@@ -334,7 +341,10 @@ struct DevModel {
   double* B64;              // [n_dofs][12] per-step constant -2 A(q_k) + A(q_{k-1})
   float* B32;               // [n_dofs][12]
   const long long* hoff;    // [n_models+1] start of every model's block in hinv
-  double* hinv;             // per model nf x nf: inverse joint-space inertia at the warm start
+  double* hinv;             // per model: nf x nf inverse joint-space inertia at the warm
+                            // start (nf <= 64), else the frames' spatial inertias [nf][10]
+  double* hist;             // models of more than 64 frames: [n_dofs][2*kMaxHist] L-BFGS
+                            // pairs, s ring then y ring
   double gx, gy, gz;
 };
 
@@ -351,23 +361,181 @@ struct Arr<float> {
   static __device__ __forceinline__ const float* B(const DevModel& d) { return d.B32; }
 };
 
+// ----------------------------------------------------------- scan policies --
+// Scans and reductions over the frames of one model.  Frame j of a model lives
+// in lane j % 64 of wave j / 64 of its workgroup.
+//   WaveScan:     one wavefront per model (DPP only);
+//   BlockScan<NW>: NW wavefronts per model: DPP inside each wave, then the wave
+//                 totals are exchanged through LDS (one barrier per scan).  Two
+//                 exchange areas alternate: a wave can only write an area again
+//                 after the barrier of the next scan, which every wave reaches
+//                 after reading the area.
+struct WaveScan {
+  template <typename R>
+  __device__ __forceinline__ Quat<R> prefix_quat(const Quat<R>& v) { return wave_prefix_quat(v); }
+  // the predecessor's inclusive prefix (identity for frame 0)
+  template <typename R>
+  __device__ __forceinline__ Quat<R> parent_quat(const Quat<R>& incl) { return dpp_quat<R, 0x138, 0xF>(incl); }
+  template <typename R>
+  __device__ __forceinline__ void prefix_sum3(R v[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = wave_prefix_sum_r(v[k]);
+  }
+  // v[k] <- sum over the frames at and below this one; a, b <- model totals
+  __device__ __forceinline__ void suffix6_total2(double v[6], double& a, double& b) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double pre = wave_prefix_sum(v[k]);
+      v[k] = (readlane(pre, 63) - pre) + v[k];
+    }
+    wave_sum2(a, b);
+  }
+  __device__ __forceinline__ double suffix(double v) {
+    const double pre = wave_prefix_sum(v);
+    return (readlane(pre, 63) - pre) + v;
+  }
+  __device__ __forceinline__ double sum(double v) { return wave_sum(v); }
+  __device__ __forceinline__ void sum2(double& a, double& b) { wave_sum2(a, b); }
+  __device__ __forceinline__ bool all_finite(double x) { return !__any(!isfinite(x)); }
+    __device__ __forceinline__ void sync() {}
+};
+
+template <int NW>
+struct BlockScan {
+  double* xch;  // LDS [2][NW][8]
+  int wave, lane, area;
+  double cq[4];  // carry of the last prefix_quat: product of the earlier waves' totals
+
+  __device__ __forceinline__ double* next_area() {
+    double* a = xch + area * (NW * 8);
+    area ^= 1;
+    return a;
+  }
+  __device__ __forceinline__ void sync() { __syncthreads(); }
+
+  template <typename R>
+  __device__ __forceinline__ Quat<R> prefix_quat(const Quat<R>& v0) {
+    const Quat<R> v = wave_prefix_quat(v0);
+    double* a = next_area();
+    if (lane == 63) {
+      a[wave * 8 + 0] = v.w; a[wave * 8 + 1] = v.x; a[wave * 8 + 2] = v.y; a[wave * 8 + 3] = v.z;
+    }
+    __syncthreads();
+    Quat<R> c{R(1), R(0), R(0), R(0)};
+    for (int w = 0; w < wave; ++w)
+      c = qmul(c, Quat<R>{(R)a[w * 8 + 0], (R)a[w * 8 + 1], (R)a[w * 8 + 2], (R)a[w * 8 + 3]});
+    cq[0] = c.w; cq[1] = c.x; cq[2] = c.y; cq[3] = c.z;
+    return qmul(c, v);
+  }
+  template <typename R>
+  __device__ __forceinline__ Quat<R> parent_quat(const Quat<R>& incl) {
+    const Quat<R> sh = dpp_quat<R, 0x138, 0xF>(incl);
+    const Quat<R> c{(R)cq[0], (R)cq[1], (R)cq[2], (R)cq[3]};
+    return lane == 0 ? c : sh;
+  }
+  template <typename R>
+  __device__ __forceinline__ void prefix_sum3(R v[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = wave_prefix_sum_r(v[k]);
+    double* a = next_area();
+    if (lane == 63)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a[wave * 8 + k] = v[k];
+    __syncthreads();
+    double c[3] = {0, 0, 0};
+    for (int w = 0; w < wave; ++w)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) c[k] += a[w * 8 + k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] += (R)c[k];
+  }
+  __device__ __forceinline__ void suffix6_total2(double v[6], double& ta, double& tb) {
+    double pre[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pre[k] = wave_prefix_sum(v[k]);
+    wave_sum2(ta, tb);
+    double* a = next_area();
+    if (lane == 63) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) a[wave * 8 + k] = pre[k];
+      a[wave * 8 + 6] = ta;
+      a[wave * 8 + 7] = tb;
+    }
+    __syncthreads();
+    double before[6] = {0, 0, 0, 0, 0, 0}, all[6] = {0, 0, 0, 0, 0, 0};
+    ta = 0.0;
+    tb = 0.0;
+    for (int w = 0; w < NW; ++w) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const double x = a[w * 8 + k];
+        all[k] += x;
+        if (w < wave) before[k] += x;
+      }
+      ta += a[w * 8 + 6];
+      tb += a[w * 8 + 7];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = (all[k] - (before[k] + pre[k])) + v[k];
+  }
+  __device__ __forceinline__ double suffix(double v) {
+    const double pre = wave_prefix_sum(v);
+    double* a = next_area();
+    if (lane == 63) a[wave * 8] = pre;
+    __syncthreads();
+    double before = 0.0, all = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      const double x = a[w * 8];
+      all += x;
+      if (w < wave) before += x;
+    }
+    return (all - (before + pre)) + v;
+  }
+  __device__ __forceinline__ double sum(double v) {
+    v = wave_sum(v);
+    double* a = next_area();
+    if (lane == 0) a[wave * 8] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < NW; ++w) t += a[w * 8];
+    return t;
+  }
+  __device__ __forceinline__ bool all_finite(double x) { return sum(isfinite(x) ? 0.0 : 1.0) == 0.0; }
+  __device__ __forceinline__ void sum2(double& x, double& y) {
+    wave_sum2(x, y);
+    double* a = next_area();
+    if (lane == 0) {
+      a[wave * 8] = x;
+      a[wave * 8 + 1] = y;
+    }
+    __syncthreads();
+    x = 0.0;
+    y = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      x += a[w * 8];
+      y += a[w * 8 + 1];
+    }
+  }
+};
+
 // World pose A_j = [R_j | t_j] of every frame of this wave's model (Alg. 1
 // forward pass; frame j's joint is at its origin, offset o_j in the parent frame):
 //   R_j = R_{j-1} Rot(a_j, q_j)  -> prefix scan of hinge quaternions,
 //   t_j = t_{j-1} + R_{j-1} o_j  -> prefix sum of the parent-rotated offsets.
-template <typename R>
-__device__ __forceinline__ Xf<R> forward_kinematics(const R a[3], const R o[3], bool valid, double q) {
+template <typename R, typename S>
+__device__ __forceinline__ Xf<R> forward_kinematics(S& sc, const R a[3], const R o[3], bool valid, double q) {
   Quat<R> Q = hinge_quat(a, valid ? q : 0.0);
   if (!valid) Q = Quat<R>{R(1), R(0), R(0), R(0)};
-  Q = wave_prefix_quat(Q);
-  // parent rotation: the neighbour's prefix (identity for the root frame)
-  const Quat<R> Qp = dpp_quat<R, 0x138, 0xF>(Q);
+  Q = sc.prefix_quat(Q);
+  // parent rotation: the predecessor's prefix (identity for the root frame)
+  const Quat<R> Qp = sc.parent_quat(Q);
   R v[3];
   qrotate(Qp, o, v);
+  sc.prefix_sum3(v);
   Xf<R> A;
-  A.m[3] = wave_prefix_sum_r(v[0]);
-  A.m[7] = wave_prefix_sum_r(v[1]);
-  A.m[11] = wave_prefix_sum_r(v[2]);
+  A.m[3] = v[0];
+  A.m[7] = v[1];
+  A.m[11] = v[2];
   const R xx = Q.x * Q.x, yy = Q.y * Q.y, zz = Q.z * Q.z;
   const R xy = Q.x * Q.y, xz = Q.x * Q.z, yz = Q.y * Q.z;
   const R wx = Q.w * Q.x, wy = Q.w * Q.y, wz = Q.w * Q.z;
@@ -397,11 +565,11 @@ __device__ __forceinline__ FrameGeo load_geo(const DevModel& d, int f, bool vali
   }
   return g;
 }
-template <typename R>
-__device__ __forceinline__ Xf<R> fk_geo(const FrameGeo& g, bool valid, double q) {
+template <typename R, typename S>
+__device__ __forceinline__ Xf<R> fk_geo(S& sc, const FrameGeo& g, bool valid, double q) {
   const R a[3] = {(R)g.a[0], (R)g.a[1], (R)g.a[2]};
   const R o[3] = {(R)g.o[0], (R)g.o[1], (R)g.o[2]};
-  return forward_kinematics<R>(a, o, valid, q);
+  return forward_kinematics<R>(sc, a, o, valid, q);
 }
 
 struct EvalResult {
@@ -411,9 +579,9 @@ struct EvalResult {
 };
 
 // One objective + gradient evaluation for the model of this wave.
-template <typename R>
-__device__ EvalResult evaluate(const DevModel& d, const FrameGeo& geo, int f, bool valid, double q, double tau,
-                               double dt2) {
+template <typename R, typename S>
+__device__ EvalResult evaluate(S& sc, const DevModel& d, const FrameGeo& geo, int f, bool valid, double q,
+                               double tau, double dt2) {
   // keep the per-frame loads inside the evaluation (no hoisting across calls,
   // which would pin them in registers for the whole solve); they are issued
   // first so that their latency overlaps the kinematics scan
@@ -425,7 +593,7 @@ __device__ EvalResult evaluate(const DevModel& d, const FrameGeo& geo, int f, bo
   for (int k = 0; k < 10; ++k) M[k] = valid ? rec[6 + k] : R(0);
 #pragma unroll
   for (int k = 0; k < 4; ++k) Bn[k] = valid ? Bp[k] : R(0);
-  const Xf<R> A = fk_geo<R>(geo, valid, q);
+  const Xf<R> A = fk_geo<R>(sc, geo, valid, q);
   const R a[3] = {(R)geo.a[0], (R)geo.a[1], (R)geo.a[2]};
 
   // Row r of D = A + B (= A(q) - 2A(q_k) + A(q_{k-1})), of D M and of the seed
@@ -469,14 +637,10 @@ __device__ EvalResult evaluate(const DevModel& d, const FrameGeo& geo, int f, bo
   double Ev = elane - (valid ? tq : 0.0);
   double Sv = fabs(elane) + (valid ? fabs(tq) : 0.0);
 
-  // suffix sums over the frames below: inclusive prefix, then total - prefix + own
-  const double v[6] = {k0, k1, k2, fv[0], fv[1], fv[2]};
-  double suf[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const double pre = wave_prefix_sum(v[k]);
-    suf[k] = (readlane(pre, 63) - pre) + v[k];
-  }
+  // suffix sums over the frames below (inclusive prefix, then total - prefix +
+  // own) and the model totals of E and S
+  double suf[6] = {k0, k1, k2, fv[0], fv[1], fv[2]};
+  sc.suffix6_total2(suf, Ev, Sv);
 
   // world axis w = R a, joint point p = t
   const double w0 = (double)A.m[0] * a[0] + (double)A.m[1] * a[1] + (double)A.m[2] * a[2];
@@ -488,13 +652,11 @@ __device__ EvalResult evaluate(const DevModel& d, const FrameGeo& geo, int f, bo
   const double m2 = suf[2] - (p0 * suf[4] - p1 * suf[3]);
   EvalResult res;
   res.g = valid ? (w0 * m0 + w1 * m1 + w2 * m2 - dt2 * tau) : 0.0;
-  wave_sum2(Ev, Sv);
   res.E = Ev;
   res.S = Sv;
   return res;
 }
 
-__device__ __forceinline__ bool all_finite(double x) { return !__any(!isfinite(x)); }
 
 // ------------------------------------------------------------ step kernel --
 struct StepArgs {
@@ -509,16 +671,22 @@ struct StepArgs {
   abd_step_stats* stats;      // [n_steps][n_models] or NULL
 };
 
-// Per-model tables of the articulated-body recursion (LDS, one model per
-// workgroup):
+// Per-model LDS of the rollout kernel (one model per workgroup of NW waves):
 //   tab:   per frame s (6 = world hinge motion (w; p x w)), U (6 = I^A s), 1/D, unused
-//   inert: per frame world spatial inertia about the origin (J 6, h 3, m)
-struct ModelLds {
-  double tab[kMaxFrames][14];
-  double inert[kMaxFrames][10];
+//   inert: per frame world spatial inertia about the origin (J 6, h 3, m);
+//          NW > 1 keeps it in the model's device scratch instead
+//   xb:    NW > 1: the vector swept by the recursion
+//   xch:   scan exchange areas of BlockScan
+template <int NW>
+struct RollLds {
+  double tab[kMaxFrames * NW][14];
+  double inert[NW == 1 ? kMaxFrames : 1][10];
   double rho[kMaxHist];  // 1/(s_i.y_i), newest first
   double alp[kMaxHist];  // two-loop coefficients
+  double xb[NW == 1 ? 1 : kMaxFrames * NW];
+  double xch[2][NW][8];
 };
+using ModelLds = RollLds<1>;
 
 // Articulated inertias at the warm start (once per step, one lane):
 //   I^A_f = I_f + P_{f+1},  U_f = I^A_f s_f,  D_f = s_f.U_f,
@@ -526,23 +694,23 @@ struct ModelLds {
 // The 6x6 symmetric P is held in registers as ww (6: 00 01 02 11 12 22),
 // wv (3x3 row-major), vv (6).  The LDS inputs of frame f-1 are read while
 // frame f is processed.
-__device__ void aba_setup(ModelLds& L, int nf) {
+__device__ void aba_setup(const double* inert, double (*tab)[14], int nf) {
   if (nf <= 0) return;
   double P[21];
 #pragma unroll
   for (int k = 0; k < 21; ++k) P[k] = 0.0;
   double in[10], s[6];
 #pragma unroll
-  for (int k = 0; k < 10; ++k) in[k] = L.inert[nf - 1][k];
+  for (int k = 0; k < 10; ++k) in[k] = inert[(nf - 1) * 10 + k];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) s[k] = L.tab[nf - 1][k];
+  for (int k = 0; k < 6; ++k) s[k] = tab[nf - 1][k];
   for (int f = nf - 1; f >= 0; --f) {
     const int fn = f > 0 ? f - 1 : 0;
     double inn[10], sn[6];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) inn[k] = L.inert[fn][k];
+    for (int k = 0; k < 10; ++k) inn[k] = inert[fn * 10 + k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) sn[k] = L.tab[fn][k];
+    for (int k = 0; k < 6; ++k) sn[k] = tab[fn][k];
     // add I = [[J, [h]x], [[h]x^T, m 1]]
 #pragma unroll
     for (int k = 0; k < 6; ++k) P[k] += in[k];
@@ -558,8 +726,8 @@ __device__ void aba_setup(ModelLds& L, int nf) {
     const double D = (s[0] * U[0] + s[1] * U[1]) + (s[2] * U[2] + s[3] * U[3]) + (s[4] * U[4] + s[5] * U[5]);
     const double iD = (D > 0.0) ? 1.0 / D : 0.0;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) L.tab[f][6 + k] = U[k];
-    L.tab[f][12] = iD;
+    for (int k = 0; k < 6; ++k) tab[f][6 + k] = U[k];
+    tab[f][12] = iD;
     // P <- I^A - U U^T / D  (the articulated inertia seen by the parent)
     double V[6];
 #pragma unroll
@@ -588,11 +756,11 @@ __device__ void aba_setup(ModelLds& L, int nf) {
 // touches only its own column, so no other lane's stores have to be seen.
 constexpr int kInvChunk = 4;  // frames whose parked u are loaded ahead
 
-__device__ void aba_inverse(const ModelLds& L, int nf, int lane, double* Hi) {
+__device__ void aba_inverse(const double (*tab)[14], int nf, int lane, double* Hi) {
   const bool act = lane < nf;
   double p[6] = {0, 0, 0, 0, 0, 0};
   for (int f = nf - 1; f >= 0; --f) {
-    const double* t = L.tab[f];
+    const double* t = tab[f];
     const double sp = (t[0] * p[0] + t[1] * p[1]) + (t[2] * p[2] + t[3] * p[3]) + (t[4] * p[4] + t[5] * p[5]);
     const double u = (f == lane ? 1.0 : 0.0) - sp;
     if (act) Hi[(size_t)f * nf + lane] = u;
@@ -618,7 +786,7 @@ __device__ void aba_inverse(const ModelLds& L, int nf, int lane, double* Hi) {
     for (int k = 0; k < kInvChunk; ++k) {
       const int f = c0 + k;
       if (f < nf) {
-        const double* t = L.tab[f];
+        const double* t = tab[f];
         const double Ua = (t[6] * a[0] + t[7] * a[1]) + (t[8] * a[2] + t[9] * a[3]) + (t[10] * a[4] + t[11] * a[5]);
         const double x = (uc[k] - Ua) * t[12];
         if (act) Hi[(size_t)f * nf + lane] = x;
@@ -654,21 +822,70 @@ __device__ __forceinline__ double apply_inverse(const double* Hi, int nf, int la
   return r;
 }
 
+// x = H^{-1} b in O(n) by one thread (models of more than one wave): backward
+// sweep u_f = b_f - s_f.p, p <- p + U_f u_f / D_f; forward sweep
+// x_f = (u_f - U_f.a) / D_f, a <- a + s_f x_f; in place in xb (LDS).  The
+// record of the next frame is read while the current one is used.
+__device__ void aba_solve(const double (*tab)[14], double* xb, int nf) {
+  if (nf <= 0) return;
+  double p[6] = {0, 0, 0, 0, 0, 0};
+  double t[13], b;
+#pragma unroll
+  for (int k = 0; k < 13; ++k) t[k] = tab[nf - 1][k];
+  b = xb[nf - 1];
+  for (int f = nf - 1; f >= 0; --f) {
+    const int fn = f > 0 ? f - 1 : 0;
+    double tn[13];
+#pragma unroll
+    for (int k = 0; k < 13; ++k) tn[k] = tab[fn][k];
+    const double bn = xb[fn];
+    const double sp = (t[0] * p[0] + t[1] * p[1]) + (t[2] * p[2] + t[3] * p[3]) + (t[4] * p[4] + t[5] * p[5]);
+    const double u = b - sp;
+    xb[f] = u;
+    const double w = u * t[12];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] += t[6 + k] * w;
+#pragma unroll
+    for (int k = 0; k < 13; ++k) t[k] = tn[k];
+    b = bn;
+  }
+  double a[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 13; ++k) t[k] = tab[0][k];
+  b = xb[0];
+  for (int f = 0; f < nf; ++f) {
+    const int fn = f + 1 < nf ? f + 1 : f;
+    double tn[13];
+#pragma unroll
+    for (int k = 0; k < 13; ++k) tn[k] = tab[fn][k];
+    const double bn = xb[fn];
+    const double Ua = (t[6] * a[0] + t[7] * a[1]) + (t[8] * a[2] + t[9] * a[3]) + (t[10] * a[4] + t[11] * a[5]);
+    const double x = (b - Ua) * t[12];
+    xb[f] = x;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[k] += t[k] * x;
+#pragma unroll
+    for (int k = 0; k < 13; ++k) t[k] = tn[k];
+    b = bn;
+  }
+}
+
 // Setup of one step for this wave's model (float64): the per-step constant
 // B = -2 A(q_k) + A(q_{k-1}) of every frame, and for the inertia preconditioner
 // the world spatial inertia (about the origin) and hinge motion at the warm start.
-__device__ __forceinline__ void step_setup(const DevModel& d, ModelLds& L, const FrameGeo& geo, int f, bool valid,
-                                           int lane, double qkm1, double qk, double q0, bool use_aba) {
+template <typename S>
+__device__ __forceinline__ void step_setup(S& sc, const DevModel& d, double* inert, double* tab, const FrameGeo& geo,
+                                           int f, bool valid, double qkm1, double qk, double q0, bool use_aba) {
   double* B64 = d.B64 + (size_t)f * 12;
   float* B32 = d.B32 + (size_t)f * 12;
   {
-    const Xf<double> Akm1 = fk_geo<double>(geo, valid, qkm1);
+    const Xf<double> Akm1 = fk_geo<double>(sc, geo, valid, qkm1);
     if (valid)
 #pragma unroll
       for (int k = 0; k < 12; ++k) B64[k] = Akm1.m[k];
   }
   {
-    const Xf<double> Ak = fk_geo<double>(geo, valid, qk);
+    const Xf<double> Ak = fk_geo<double>(sc, geo, valid, qk);
     if (valid)
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
@@ -679,7 +896,7 @@ __device__ __forceinline__ void step_setup(const DevModel& d, ModelLds& L, const
   }
   if (!use_aba) return;
   const double* a = geo.a;
-  const Xf<double> A = fk_geo<double>(geo, valid, q0);
+  const Xf<double> A = fk_geo<double>(sc, geo, valid, q0);
   double M[10];
   const double* rec = d.fr64 + (size_t)f * 16;
 #pragma unroll
@@ -707,7 +924,7 @@ __device__ __forceinline__ void step_setup(const DevModel& d, ModelLds& L, const
       }
   }
   const double tr = Sw[0] + Sw[3] + Sw[5];
-  double* in = L.inert[lane];
+  double* in = inert;
   in[0] = valid ? tr - Sw[0] : 0.0;
   in[1] = valid ? -Sw[1] : 0.0;
   in[2] = valid ? -Sw[2] : 0.0;
@@ -721,7 +938,7 @@ __device__ __forceinline__ void step_setup(const DevModel& d, ModelLds& L, const
   const double w0 = A.m[0] * a[0] + A.m[1] * a[1] + A.m[2] * a[2];
   const double w1 = A.m[4] * a[0] + A.m[5] * a[1] + A.m[6] * a[2];
   const double w2 = A.m[8] * a[0] + A.m[9] * a[1] + A.m[10] * a[2];
-  double* ts = L.tab[lane];
+  double* ts = tab;
   ts[0] = valid ? w0 : 0.0;
   ts[1] = valid ? w1 : 0.0;
   ts[2] = valid ? w2 : 0.0;
@@ -735,37 +952,63 @@ enum EvalPurpose { kTrial = 0, kRefresh = 1, kRefreshRetry = 2 };
 // Per-model state of the rollout kernel.
 enum ModelState { kSetup = 0, kIterate = 1, kDone = 2 };
 
-// A rollout of n_steps time steps, one model per workgroup of one wavefront.
-// Every model advances through the steps at its own pace and a workgroup ends
-// when its model has finished the last step, so the hardware dispatcher starts
-// the next model in its place (the per-iteration interleaving of Sec. 5's GPU
-// scheme, done by the dispatcher instead of a software queue).
-// A step is: setup (B, and for the inertia preconditioner the recursion and the
-// explicit inverse), the warm-start evaluation, then iterations of two-loop
-// L-BFGS direction + backtracking line search + update.
+// A rollout of n_steps time steps, one model per workgroup of NW wavefronts
+// (frame j in lane j % 64 of wave j / 64).  Every model advances through the
+// steps at its own pace and a workgroup ends when its model has finished the
+// last step, so the hardware dispatcher starts the next model in its place (the
+// per-iteration interleaving of Sec. 5's GPU scheme, done by the dispatcher
+// instead of a software queue).
+// A step is: setup (B, and for the inertia preconditioner the recursion and,
+// for one-wave models, the explicit inverse), the warm-start evaluation, then
+// iterations of two-loop L-BFGS direction + backtracking line search + update.
+// The initial inverse Hessian is applied as a dense matrix-vector product
+// (one wave) or by the two sweeps of the recursion on one thread (NW > 1).
+// The L-BFGS pairs live in LDS (one wave) or in the per-frame device ring.
+// Every branch is uniform over the workgroup (all decisions use reduced values).
 // MIXED: float32 evaluations until the line search meets float32 rounding (or
 // float32 claims convergence), then float64 to the end of the step.
 #ifndef ABD_WAVES_PER_SIMD
 #define ABD_WAVES_PER_SIMD 2
 #endif
-template <int PREC>
-__global__ void __launch_bounds__(kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs args) {
-  __shared__ ModelLds L;
-  // L-BFGS pairs of the current step: s in ring slots [0, m), y in [m, 2m),
-  // one double per lane per slot
+template <int NW>
+struct ScanOf {
+  using type = BlockScan<NW>;
+  static __device__ __forceinline__ type make(double* xch, int wave, int lane) {
+    type t;
+    t.xch = xch;
+    t.wave = wave;
+    t.lane = lane;
+    t.area = 0;
+    return t;
+  }
+};
+template <>
+struct ScanOf<1> {
+  using type = WaveScan;
+  static __device__ __forceinline__ type make(double*, int, int) { return WaveScan{}; }
+};
+
+template <int NW, int PREC>
+__global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD)) k_rollout(StepArgs args) {
+  __shared__ RollLds<NW> L;
+  // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
+  // y in [m, 2m), one double per lane per slot
   extern __shared__ double pairs[];
   const DevModel& d = args.d;
   const int n = d.n_dofs;
-  const int lane = threadIdx.x;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int j = threadIdx.x;  // frame of this thread within the model
+  const bool lead = threadIdx.x == 0;
   const int model = blockIdx.x;
   const bool has_model = model < d.n_models;
   if (!has_model) return;
+  typename ScanOf<NW>::type sc = ScanOf<NW>::make(&L.xch[0][0][0], wave, lane);
   const int f0 = d.f0[model];
   const int nf = d.f0[model + 1] - f0;
-  const bool valid = lane < nf;
-  const int f = f0 + (valid ? lane : 0);
+  const bool valid = j < nf;
+  const int f = f0 + (valid ? j : 0);
   const bool use_aba = args.precond == ABD_PRECOND_INERTIA;
-  double* Hi = d.hinv + d.hoff[model];
+  double* Hi = d.hinv + d.hoff[model];  // one wave: explicit inverse; NW > 1: inertias [nf][10]
   const FrameGeo geo = load_geo(d, f, valid);
   const double eps_w = PREC == ABD_MIXED ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
   const double c1 = 1e-4, dlt = 0.1;
@@ -777,11 +1020,23 @@ __global__ void __launch_bounds__(kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs 
   int state = args.n_steps > 0 ? kSetup : kDone;
 
   // per-step solver state
-  double* hs = pairs + lane;
-  const int ys = args.m * kWave;  // offset of the y ring
+  double* hs;
+  int hstride, ys;
+  if (NW == 1) {
+    hs = pairs + lane;
+    hstride = kWave;
+    ys = args.m * kWave;
+  } else {
+    hs = d.hist + (size_t)f * (2 * kMaxHist);
+    hstride = 1;
+    ys = kMaxHist;
+  }
   bool f32 = false, reset = false;
   int iters = 0, evals = 0, flag = 0, f32_iters = 0, count = 0, head = 0;
   double q = 0.0, tau = 0.0, E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0;
+#ifdef ABD_PROFILE
+  if (lead) abd_prof[(size_t)model * 16 + 10] = __builtin_amdgcn_s_memrealtime();
+#endif
 
   while (state != kDone) {
     bool step_done = false;
@@ -795,25 +1050,27 @@ __global__ void __launch_bounds__(kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs 
         flag = ABD_FLAG_CONVERGED;
         step_done = true;
       } else {
-        step_setup(d, L, geo, f, valid, lane, qkm1, qk, q, use_aba);
+        double* inert = NW == 1 ? L.inert[lane] : Hi + (size_t)(valid ? j : 0) * 10;
+        step_setup(sc, d, inert, L.tab[j], geo, f, valid, qkm1, qk, q, use_aba);
         if (use_aba) {
+          if (NW > 1) __threadfence_block();  // inertias go through device memory
           __syncthreads();
-          if (lane == 0) aba_setup(L, nf);
+          if (lead) aba_setup(NW == 1 ? &L.inert[0][0] : Hi, L.tab, nf);
           __syncthreads();
-          aba_inverse(L, nf, lane, Hi);
+          if (NW == 1) aba_inverse(L.tab, nf, lane, Hi);
         }
         PROF_ADD(0, t_s);
-        const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(d, geo, f, valid, q, tau, args.dt2)
-                                                  : evaluate<double>(d, geo, f, valid, q, tau, args.dt2);
+        const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(sc, d, geo, f, valid, q, tau, args.dt2)
+                                                  : evaluate<double>(sc, d, geo, f, valid, q, tau, args.dt2);
         ++evals;
         E = r.E;
         g = r.g;
         gn = 0.0;
-        if (!isfinite(E) || !all_finite(g)) {
+        if (!isfinite(E) || !sc.all_finite(g)) {
           flag = ABD_FLAG_NONFINITE;
           step_done = true;
         } else {
-          g0 = uniform(sqrt(wave_sum(g * g)));
+          g0 = uniform(sqrt(sc.sum(g * g)));
           gn = g0;
           if (g0 == 0.0) {
             flag = ABD_FLAG_CONVERGED;
@@ -833,33 +1090,44 @@ __global__ void __launch_bounds__(kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs 
       if (reset) count = 0;
       double qv = g;
       {
-        double sk = (valid && count > 0) ? hs[head * kWave] : 0.0;
-        double yk = (valid && count > 0) ? hs[ys + head * kWave] : 0.0;
+        double sk = (valid && count > 0) ? hs[head * hstride] : 0.0;
+        double yk = (valid && count > 0) ? hs[ys + head * hstride] : 0.0;
         for (int k = 0; k < count; ++k) {
           const int nxt = (head - k - 1 + args.m) % args.m;
-          const double sn = (valid && k + 1 < count) ? hs[nxt * kWave] : 0.0;
-          const double yn = (valid && k + 1 < count) ? hs[ys + nxt * kWave] : 0.0;
-          const double a_k = uniform(L.rho[k] * wave_sum(sk * qv));
-          if (lane == 0) L.alp[k] = a_k;
+          const double sn = (valid && k + 1 < count) ? hs[nxt * hstride] : 0.0;
+          const double yn = (valid && k + 1 < count) ? hs[ys + nxt * hstride] : 0.0;
+          const double a_k = uniform(L.rho[k] * sc.sum(sk * qv));
+          if (lead) L.alp[k] = a_k;
           qv -= a_k * yk;
           sk = sn;
           yk = yn;
         }
       }
       // ---- initial inverse Hessian
-      double r = use_aba ? apply_inverse(Hi, nf, lane, qv) : (count > 0 ? gam : 1.0) * qv;
+      double r;
+      if (!use_aba) {
+        r = (count > 0 ? gam : 1.0) * qv;
+      } else if (NW == 1) {
+        r = apply_inverse(Hi, nf, lane, qv);
+      } else {
+        L.xb[j] = valid ? qv : 0.0;
+        __syncthreads();
+        if (lead) aba_solve(L.tab, L.xb, nf);
+        __syncthreads();
+        r = valid ? L.xb[j] : 0.0;
+      }
       PROF_ADD(1, t_a);
       PROF_T(t_c);
       // ---- oldest pair first
       {
         int slot = (head - (count - 1) + args.m) % args.m;
-        double sk = (valid && count > 0) ? hs[slot * kWave] : 0.0;
-        double yk = (valid && count > 0) ? hs[ys + slot * kWave] : 0.0;
+        double sk = (valid && count > 0) ? hs[slot * hstride] : 0.0;
+        double yk = (valid && count > 0) ? hs[ys + slot * hstride] : 0.0;
         for (int k = count - 1; k >= 0; --k) {
           const int nxt = (slot + 1) % args.m;
-          const double sn = (valid && k > 0) ? hs[nxt * kWave] : 0.0;
-          const double yn = (valid && k > 0) ? hs[ys + nxt * kWave] : 0.0;
-          const double b = uniform(L.rho[k] * wave_sum(yk * r));
+          const double sn = (valid && k > 0) ? hs[nxt * hstride] : 0.0;
+          const double yn = (valid && k > 0) ? hs[ys + nxt * hstride] : 0.0;
+          const double b = uniform(L.rho[k] * sc.sum(yk * r));
           r += (L.alp[k] - b) * sk;
           sk = sn;
           yk = yn;
@@ -867,7 +1135,7 @@ __global__ void __launch_bounds__(kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs 
         }
       }
       const double dir = valid ? -r : 0.0;
-      const double gd = uniform(wave_sum(g * dir));
+      const double gd = uniform(sc.sum(g * dir));
       if (!(gd < 0.0)) {
         if (!reset) {
           reset = true;  // redo the direction with an empty history
@@ -886,19 +1154,19 @@ __global__ void __launch_bounds__(kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs 
           EvalResult rt;
           PROF_T(t_e);
           if (PREC == ABD_MIXED && f32)
-            rt = evaluate<float>(d, geo, f, valid, x, tau, args.dt2);
+            rt = evaluate<float>(sc, d, geo, f, valid, x, tau, args.dt2);
           else
-            rt = evaluate<double>(d, geo, f, valid, x, tau, args.dt2);
+            rt = evaluate<double>(sc, d, geo, f, valid, x, tau, args.dt2);
           PROF_ADD(6, t_e);
 #ifdef ABD_PROFILE
-          if (lane == 0) abd_prof[(size_t)model * 16 + 7] += 1;
+          if (lead) abd_prof[(size_t)model * 16 + 7] += 1;
 #endif
           ++evals;
           if (purpose != kTrial) {
             // float64 re-evaluation at q after leaving float32
             E = rt.E;
             g = rt.g;
-            gn = uniform(sqrt(wave_sum(g * g)));
+            gn = uniform(sqrt(sc.sum(g * g)));
             if (purpose == kRefresh) {
               if (gn <= args.tol * g0) {
                 flag = ABD_FLAG_CONVERGED;
@@ -911,12 +1179,12 @@ __global__ void __launch_bounds__(kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs 
             break;
           }
           int ok = 0;
-          if (isfinite(rt.E) && all_finite(rt.g)) {
+          if (isfinite(rt.E) && sc.all_finite(rt.g)) {
             if (rt.E <= E + c1 * alpha * gd) {
               ok = 1;
             } else if (fabs(rt.E - E) <= 10.0 * eps_w * rt.S) {
               noisy = true;
-              const double gtd = wave_sum(rt.g * dir);
+              const double gtd = sc.sum(rt.g * dir);
               if (gtd <= (2.0 * dlt - 1.0) * gd) ok = 1;
             }
           }
@@ -935,19 +1203,19 @@ __global__ void __launch_bounds__(kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs 
           // accepted: curvature pair and update
           const double sv = alpha * dir;
           const double y = rt.g - g;
-          double sy = sv * y, ss = sv * sv, yy = y * y, unused = 0.0;
-          wave_sum2(sy, ss);
-          wave_sum2(yy, unused);
+          double sy = sv * y, ss = sv * sv, yy = y * y, gg = rt.g * rt.g;
+          sc.sum2(sy, ss);
+          sc.sum2(yy, gg);
           if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
-            if (lane == 0) {
+            if (lead) {
               for (int k = args.m - 1; k > 0; --k) L.rho[k] = L.rho[k - 1];
               L.rho[0] = 1.0 / sy;
             }
             gam = uniform(sy / yy);
             head = count == 0 ? 0 : (head + 1) % args.m;
             if (valid) {
-              hs[head * kWave] = sv;
-              hs[ys + head * kWave] = y;
+              hs[head * hstride] = sv;
+              hs[ys + head * hstride] = y;
             }
             if (count < args.m) ++count;
           }
@@ -956,7 +1224,7 @@ __global__ void __launch_bounds__(kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs 
           E = rt.E;
           ++iters;
           if (PREC == ABD_MIXED && f32) ++f32_iters;
-          gn = uniform(sqrt(wave_sum(g * g)));
+          gn = uniform(sqrt(gg));
           const bool conv = gn <= args.tol * g0;
           if (PREC == ABD_MIXED && f32 && (conv || noisy)) {
             f32 = false;  // float32 has done what it can: confirm / continue in float64
@@ -975,12 +1243,12 @@ __global__ void __launch_bounds__(kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs 
       }
       PROF_ADD(5, t_c);
 #ifdef ABD_PROFILE
-      if (lane == 0) abd_prof[(size_t)model * 16 + 9] += 1;
+      if (lead) abd_prof[(size_t)model * 16 + 9] += 1;
 #endif
     }
     if (step_done) {
       if (valid) args.q_out[(size_t)step * n + f] = q;
-      if (args.stats && lane == 0) {
+      if (args.stats && lead) {
         abd_step_stats st;
         st.iterations = iters;
         st.evaluations = evals;
@@ -996,6 +1264,9 @@ __global__ void __launch_bounds__(kWave, ABD_WAVES_PER_SIMD) k_rollout(StepArgs 
       state = step < args.n_steps ? kSetup : kDone;
     }
   }
+#ifdef ABD_PROFILE
+  if (lead) abd_prof[(size_t)model * 16 + 11] = __builtin_amdgcn_s_memrealtime();
+#endif
 }
 
 // ------------------------------------------------------- second order --
@@ -1015,7 +1286,8 @@ __device__ __forceinline__ double wave_suffix_sum(double v) {
 // at the configuration whose poses are A (world-frame form): returns
 // dF/dq_n = w_n . (K_n - p_n x F_n) with the suffix sums of
 // k = sum_c R[:,c] x S[:,c] + t x S[:,3] and f = S[:,3].
-__device__ double adjoint_of_seed(const Xf<double>& A, const double S[12], const double a[3], bool valid) {
+template <typename Sc>
+__device__ double adjoint_of_seed(Sc& sc, const Xf<double>& A, const double S[12], const double a[3], bool valid) {
   const double t[3] = {A.m[3], A.m[7], A.m[11]};
   double k[3] = {0, 0, 0};
 #pragma unroll
@@ -1027,12 +1299,11 @@ __device__ double adjoint_of_seed(const Xf<double>& A, const double S[12], const
 #pragma unroll
     for (int i = 0; i < 3; ++i) k[i] += x[i];
   }
-  double K[3], F[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    K[i] = wave_suffix_sum(valid ? k[i] : 0.0);
-    F[i] = wave_suffix_sum(valid ? S[4 * i + 3] : 0.0);
-  }
+  double KF[6] = {valid ? k[0] : 0.0, valid ? k[1] : 0.0, valid ? k[2] : 0.0,
+                  valid ? S[3] : 0.0, valid ? S[7] : 0.0, valid ? S[11] : 0.0};
+  double unused_a = 0.0, unused_b = 0.0;
+  sc.suffix6_total2(KF, unused_a, unused_b);
+  const double K[3] = {KF[0], KF[1], KF[2]}, F[3] = {KF[3], KF[4], KF[5]};
   double w[3], pF[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) w[i] = A.m[4 * i] * a[0] + A.m[4 * i + 1] * a[1] + A.m[4 * i + 2] * a[2];
@@ -1045,7 +1316,8 @@ __device__ double adjoint_of_seed(const Xf<double>& A, const double S[12], const
 // dA_j/dq_n = [[w_n]x R_j | w_n x (t_j - p_n)] for every frame n at or above j,
 // so with the prefix sums W_j = sum v_n w_n and Z_j = sum v_n (w_n x p_n)
 //   dR_j = [W_j]x R_j,   dt_j = W_j x t_j - Z_j.
-__device__ void tangent_pose(const Xf<double>& A, const double a[3], bool valid, double v, double dA[12],
+template <typename Sc>
+__device__ void tangent_pose(Sc& sc, const Xf<double>& A, const double a[3], bool valid, double v, double dA[12],
                              double W[3], double w[3]) {
   const double t[3] = {A.m[3], A.m[7], A.m[11]};
 #pragma unroll
@@ -1056,9 +1328,11 @@ __device__ void tangent_pose(const Xf<double>& A, const double a[3], bool valid,
   double Z[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    W[i] = wave_prefix_sum(vv * w[i]);
-    Z[i] = wave_prefix_sum(vv * wp[i]);
+    W[i] = vv * w[i];
+    Z[i] = vv * wp[i];
   }
+  sc.prefix_sum3(W);
+  sc.prefix_sum3(Z);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const double col[3] = {A.m[c], A.m[4 + c], A.m[8 + c]};
@@ -1082,7 +1356,8 @@ __device__ void tangent_pose(const Xf<double>& A, const double a[3], bool valid,
 //   dk = sum_c (dR[:,c] x G[:,c] + R[:,c] x dG[:,c]) + dt x G[:,3] + t x dG[:,3],
 //   (Hv)_n = dw_n . (K_n - p_n x F_n) + w_n . (dK_n - dp_n x F_n - p_n x dF_n),
 // dw_n = W_n x w_n, dp_n = dt_n.  Needs B of the step in the model scratch.
-__device__ double hess_vec(const DevModel& d, const FrameGeo& geo, int f, bool valid, double q, double v,
+template <typename Sc>
+__device__ double hess_vec(Sc& sc, const DevModel& d, const FrameGeo& geo, int f, bool valid, double q, double v,
                            double dt2) {
   asm volatile("" ::: "memory");
   double M[10], B[12];
@@ -1092,9 +1367,9 @@ __device__ double hess_vec(const DevModel& d, const FrameGeo& geo, int f, bool v
   for (int k = 0; k < 10; ++k) M[k] = valid ? rec[6 + k] : 0.0;
 #pragma unroll
   for (int k = 0; k < 12; ++k) B[k] = valid ? Bp[k] : 0.0;
-  const Xf<double> A = fk_geo<double>(geo, valid, q);
+  const Xf<double> A = fk_geo<double>(sc, geo, valid, q);
   double dA[12], W[3], w[3];
-  tangent_pose(A, geo.a, valid, v, dA, W, w);
+  tangent_pose(sc, A, geo.a, valid, v, dA, W, w);
   const double g[3] = {d.gx, d.gy, d.gz};
   double G[12], dG[12];
 #pragma unroll
@@ -1127,14 +1402,15 @@ __device__ double hess_vec(const DevModel& d, const FrameGeo& geo, int f, bool v
       dk[i] += y[i] + z[i];
     }
   }
-  double K[3], F[3], dK[3], dF[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    K[i] = wave_suffix_sum(valid ? k[i] : 0.0);
-    F[i] = wave_suffix_sum(valid ? G[4 * i + 3] : 0.0);
-    dK[i] = wave_suffix_sum(valid ? dk[i] : 0.0);
-    dF[i] = wave_suffix_sum(valid ? dG[4 * i + 3] : 0.0);
-  }
+  double KF[6] = {valid ? k[0] : 0.0, valid ? k[1] : 0.0, valid ? k[2] : 0.0,
+                  valid ? G[3] : 0.0, valid ? G[7] : 0.0, valid ? G[11] : 0.0};
+  double dKF[6] = {valid ? dk[0] : 0.0, valid ? dk[1] : 0.0, valid ? dk[2] : 0.0,
+                   valid ? dG[3] : 0.0, valid ? dG[7] : 0.0, valid ? dG[11] : 0.0};
+  double unused_a = 0.0, unused_b = 0.0;
+  sc.suffix6_total2(KF, unused_a, unused_b);
+  sc.suffix6_total2(dKF, unused_a, unused_b);
+  const double K[3] = {KF[0], KF[1], KF[2]}, F[3] = {KF[3], KF[4], KF[5]};
+  const double dK[3] = {dKF[0], dKF[1], dKF[2]}, dF[3] = {dKF[3], dKF[4], dKF[5]};
   const double p[3] = {A.m[3], A.m[7], A.m[11]};
   const double dp[3] = {dA[3], dA[7], dA[11]};
   double dw[3], pF[3], dpF[3], pdF[3];
@@ -1149,10 +1425,11 @@ __device__ double hess_vec(const DevModel& d, const FrameGeo& geo, int f, bool v
 }
 
 // B = A(q_{k-1}) - 2 A(q_k) of this lane's frame into the model scratch.
-__device__ __forceinline__ void write_B(const DevModel& d, const FrameGeo& geo, int f, bool valid, double qkm1,
-                                        double qk) {
-  const Xf<double> Ak = fk_geo<double>(geo, valid, qk);
-  const Xf<double> Akm1 = fk_geo<double>(geo, valid, qkm1);
+template <typename Sc>
+__device__ __forceinline__ void write_B(Sc& sc, const DevModel& d, const FrameGeo& geo, int f, bool valid,
+                                        double qkm1, double qk) {
+  const Xf<double> Ak = fk_geo<double>(sc, geo, valid, qk);
+  const Xf<double> Akm1 = fk_geo<double>(sc, geo, valid, qkm1);
   if (valid) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -1181,9 +1458,10 @@ __global__ void __launch_bounds__(kWave) k_hvp(HvpArgs a) {
   const bool valid = lane < nf;
   const int f = f0 + (valid ? lane : 0);
   const FrameGeo geo = load_geo(d, f, valid);
-  write_B(d, geo, f, valid, valid ? a.q_prev[f] : 0.0, valid ? a.q_curr[f] : 0.0);
+  WaveScan ws;
+  write_B(ws, d, geo, f, valid, valid ? a.q_prev[f] : 0.0, valid ? a.q_curr[f] : 0.0);
   // the B rows of this lane were written by this lane: no barrier needed
-  const double hv = hess_vec(d, geo, f, valid, valid ? a.q[f] : 0.0, valid ? a.v[f] : 0.0, a.dt2);
+  const double hv = hess_vec(ws, d, geo, f, valid, valid ? a.q[f] : 0.0, valid ? a.v[f] : 0.0, a.dt2);
   if (valid) a.Hv[f] = hv;
 }
 
@@ -1220,6 +1498,7 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
   const FrameGeo geo = load_geo(d, f, valid);
   double* Hi = d.hinv + d.hoff[model];
   const bool use_aba = args.use_aba != 0;
+  WaveScan ws;
   // q_j and the explicit dL/dq_j of this lane's DOF, j >= -1
   auto qat = [&](int j) -> double {
     if (!valid) return 0.0;
@@ -1232,12 +1511,12 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
     double mu = 0.0, rn = 0.0;
     int it = 0, hv_count = 0, flag = ABD_FLAG_CONVERGED;
     if (nf > 0) {
-      step_setup(d, L, geo, f, valid, lane, qp, qc, q, use_aba);
+      step_setup(ws, d, L.inert[lane], L.tab[lane], geo, f, valid, qp, qc, q, use_aba);
       if (use_aba) {
         __syncthreads();
-        if (lane == 0) aba_setup(L, nf);
+        if (lane == 0) aba_setup(&L.inert[0][0], L.tab, nf);
         __syncthreads();
-        aba_inverse(L, nf, lane, Hi);
+        aba_inverse(L.tab, nf, lane, Hi);
       }
       // ---- preconditioned conjugate gradients on H mu = lambda
       const double b = valid ? lam_next : 0.0;
@@ -1252,7 +1531,7 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
       } else if (bn > 0.0) {
         flag = ABD_FLAG_MAX_ITER;
         while (it < args.max_iter) {
-          const double hp = hess_vec(d, geo, f, valid, q, p, args.dt2);
+          const double hp = hess_vec(ws, d, geo, f, valid, q, p, args.dt2);
           ++hv_count;
           const double php = uniform(wave_sum(p * hp));
           if (!(php > 0.0)) {
@@ -1281,9 +1560,9 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
       for (int i = 0; i < 10; ++i) M[i] = valid ? rec[6 + i] : 0.0;
       double S[12];
       {
-        const Xf<double> A = fk_geo<double>(geo, valid, q);
+        const Xf<double> A = fk_geo<double>(ws, geo, valid, q);
         double dA[12], W[3], w[3];
-        tangent_pose(A, geo.a, valid, mu, dA, W, w);
+        tangent_pose(ws, A, geo.a, valid, mu, dA, W, w);
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -1295,17 +1574,17 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
           }
       }
       {
-        const Xf<double> Ac = fk_geo<double>(geo, valid, qc);
+        const Xf<double> Ac = fk_geo<double>(ws, geo, valid, qc);
         double S2[12];
 #pragma unroll
         for (int i = 0; i < 12; ++i) S2[i] = 2.0 * S[i];
-        lam_cur += adjoint_of_seed(Ac, S2, geo.a, valid);
+        lam_cur += adjoint_of_seed(ws, Ac, S2, geo.a, valid);
       }
       {
-        const Xf<double> Ap = fk_geo<double>(geo, valid, qp);
+        const Xf<double> Ap = fk_geo<double>(ws, geo, valid, qp);
 #pragma unroll
         for (int i = 0; i < 12; ++i) S[i] = -S[i];
-        lam_prev += adjoint_of_seed(Ap, S, geo.a, valid);
+        lam_prev += adjoint_of_seed(ws, Ap, S, geo.a, valid);
       }
     }
     if (args.dL_dtau && valid) args.dL_dtau[(size_t)k * n + f] = args.dt2 * mu;
@@ -1342,44 +1621,41 @@ struct EvalArgs {
   double* grad;
 };
 
-__global__ void __launch_bounds__(kWave) k_objective_grad(EvalArgs a) {
+template <int NW>
+__global__ void __launch_bounds__(NW* kWave) k_objective_grad(EvalArgs a) {
+  __shared__ double xch[2][NW][8];
   const DevModel& d = a.d;
-  const int model = blockIdx.x, lane = threadIdx.x;
+  const int model = blockIdx.x, j = threadIdx.x;
   const int f0 = d.f0[model], nf = d.f0[model + 1] - f0;
-  const bool valid = lane < nf;
-  const int f = f0 + (valid ? lane : 0);
+  const bool valid = j < nf;
+  const int f = f0 + (valid ? j : 0);
   if (nf == 0) {
-    if (lane == 0) a.E[model] = 0.0;
+    if (j == 0) a.E[model] = 0.0;
     return;
   }
+  typename ScanOf<NW>::type sc = ScanOf<NW>::make(&xch[0][0][0], j / kWave, j % kWave);
   const double qkm1 = valid ? a.q_prev[f] : 0.0, qk = valid ? a.q_curr[f] : 0.0;
   const FrameGeo geo = load_geo(d, f, valid);
-  const Xf<double> Ak = fk_geo<double>(geo, valid, qk);
-  const Xf<double> Akm1 = fk_geo<double>(geo, valid, qkm1);
-  if (valid) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      const double b = Akm1.m[k] - 2.0 * Ak.m[k];
-      d.B64[(size_t)f * 12 + k] = b;
-      d.B32[(size_t)f * 12 + k] = (float)b;
-    }
-  }
-  // the B rows of this lane were written by this lane: no barrier needed
+  write_B(sc, d, geo, f, valid, qkm1, qk);
+  // the B rows of this thread were written by this thread: no barrier needed
   const double q = valid ? a.q[f] : 0.0;
   const double tau = (valid && a.tau) ? a.tau[f] : 0.0;
-  const EvalResult r = a.precision == ABD_MIXED ? evaluate<float>(d, geo, f, valid, q, tau, a.dt2)
-                                                : evaluate<double>(d, geo, f, valid, q, tau, a.dt2);
-  if (lane == 0) a.E[model] = r.E;
+  const EvalResult r = a.precision == ABD_MIXED ? evaluate<float>(sc, d, geo, f, valid, q, tau, a.dt2)
+                                                : evaluate<double>(sc, d, geo, f, valid, q, tau, a.dt2);
+  if (j == 0) a.E[model] = r.E;
   if (a.grad && valid) a.grad[f] = r.g;
 }
 
-__global__ void __launch_bounds__(kWave) k_poses(DevModel d, const double* q, double* poses) {
-  const int model = blockIdx.x, lane = threadIdx.x;
+template <int NW>
+__global__ void __launch_bounds__(NW* kWave) k_poses(DevModel d, const double* q, double* poses) {
+  __shared__ double xch[2][NW][8];
+  const int model = blockIdx.x, j = threadIdx.x;
   const int f0 = d.f0[model], nf = d.f0[model + 1] - f0;
   if (nf == 0) return;
-  const bool valid = lane < nf;
-  const int f = f0 + (valid ? lane : 0);
-  const Xf<double> A = fk_geo<double>(load_geo(d, f, valid), valid, valid ? q[f] : 0.0);
+  const bool valid = j < nf;
+  const int f = f0 + (valid ? j : 0);
+  typename ScanOf<NW>::type sc = ScanOf<NW>::make(&xch[0][0][0], j / kWave, j % kWave);
+  const Xf<double> A = fk_geo<double>(sc, load_geo(d, f, valid), valid, valid ? q[f] : 0.0);
   if (valid) {
     const int l = d.pose_link[f];
     if (l >= 0)
@@ -1393,7 +1669,7 @@ __global__ void __launch_bounds__(kWave) k_poses(DevModel d, const double* q, do
 // =================================================================== host ==
 struct abd_model {
   int device = 0;
-  int n_models = 0, n_links = 0, n_dofs = 0;
+  int n_models = 0, n_links = 0, n_dofs = 0, max_frames = 0;
   double g[3] = {0, 0, 0};
   // device buffers
   int* f0 = nullptr;
@@ -1404,6 +1680,7 @@ struct abd_model {
   float* B32 = nullptr;
   long long* hoff = nullptr;
   double* hinv = nullptr;
+  double* hist = nullptr;
   std::vector<void*> allocs;
 };
 
@@ -1472,6 +1749,7 @@ DevModel dev_view(const abd_model* m) {
   d.B64 = m->B64; d.B32 = m->B32;
   d.hoff = m->hoff;
   d.hinv = m->hinv;
+  d.hist = m->hist;
   d.gx = m->g[0]; d.gy = m->g[1]; d.gz = m->g[2];
   return d;
 }
@@ -1571,13 +1849,14 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
     }
   }
   if (!chain) return fail(ABD_ENOTSUP, "branched trees are not handled by this build (serial chains only)");
-  if (max_frames > kMaxFrames)
-    return fail(ABD_ENOTSUP, "models with more than 64 DOFs are not handled by this build");
-  // every model's explicit inverse inertia (nf x nf doubles)
+  if (max_frames > kMaxFrames * kMaxWaves)
+    return fail(ABD_ENOTSUP, "models with more than 1024 DOFs are not handled by this build");
+  // per-model preconditioner scratch: the explicit inverse inertia (nf x nf) of
+  // a one-wave model, the per-frame spatial inertias (10 nf) of a longer one
   std::vector<long long> hoff(nm + 1, 0);
   for (int i = 0; i < nm; ++i) {
     const long long k = f0[i + 1] - f0[i];
-    hoff[i + 1] = hoff[i] + k * k;
+    hoff[i + 1] = hoff[i] + (k <= kMaxFrames ? k * k : 10 * k);
   }
 
   abd_model* m = new abd_model();
@@ -1585,6 +1864,7 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   m->n_models = nm;
   m->n_links = nl;
   m->n_dofs = nd;
+  m->max_frames = max_frames;
   for (int k = 0; k < 3; ++k) m->g[k] = desc->gravity[k];
   std::vector<float> fr32(fr64.begin(), fr64.end());
   int rc = ABD_OK;
@@ -1592,6 +1872,7 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
       (rc = upload(m, &m->fr64, fr64)) || (rc = upload(m, &m->fr32, fr32)) ||
       (rc = alloc(m, &m->B64, 12 * (size_t)nd)) || (rc = alloc(m, &m->B32, 12 * (size_t)nd)) ||
       (rc = upload(m, &m->hoff, hoff)) ||
+      (rc = alloc(m, &m->hist, max_frames > kMaxFrames ? 2 * kMaxHist * (size_t)nd : 1)) ||
       (rc = alloc(m, &m->hinv, (size_t)hoff[nm]))) {
     free_model(m);
     delete m;
@@ -1616,6 +1897,13 @@ int abd_model_info(const abd_model* m, int* n_models, int* n_links, int* n_dofs)
   return ABD_OK;
 }
 
+// wavefronts per model workgroup: the power of two covering the longest model
+static int waves_for(int max_frames) {
+  int nw = 1;
+  while (nw * kMaxFrames < max_frames) nw *= 2;
+  return nw;
+}
+
 static int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
                           const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream) {
   StepArgs a;
@@ -1633,12 +1921,25 @@ static int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_
   a.q_out = q_out;
   a.stats = stats;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const dim3 grid(m->n_models), block(kWave);
-  const size_t pair_bytes = 2 * (size_t)o->lbfgs_m * kWave * sizeof(double);
-  if (o->precision == ABD_FP64)
-    hipLaunchKernelGGL((k_rollout<ABD_FP64>), grid, block, pair_bytes, s, a);
-  else
-    hipLaunchKernelGGL((k_rollout<ABD_MIXED>), grid, block, pair_bytes, s, a);
+  const int nw = waves_for(m->max_frames);
+  const dim3 grid(m->n_models), block(nw * kWave);
+  const size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * kWave * sizeof(double) : 0;
+  const bool f64 = o->precision == ABD_FP64;
+#define ABD_LAUNCH(NW)                                                                      \
+  do {                                                                                      \
+    if (f64)                                                                                \
+      hipLaunchKernelGGL((k_rollout<NW, ABD_FP64>), grid, block, pair_bytes, s, a);         \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_rollout<NW, ABD_MIXED>), grid, block, pair_bytes, s, a);        \
+  } while (0)
+  switch (nw) {
+    case 1: ABD_LAUNCH(1); break;
+    case 2: ABD_LAUNCH(2); break;
+    case 4: ABD_LAUNCH(4); break;
+    case 8: ABD_LAUNCH(8); break;
+    default: ABD_LAUNCH(16); break;
+  }
+#undef ABD_LAUNCH
   HIP_TRY(hipGetLastError());
   return ABD_OK;
 }
@@ -1692,7 +1993,16 @@ int abd_objective_grad(abd_model* m, const abd_step_opts* o, const double* q, co
   a.tau = tau;
   a.E = E;
   a.grad = grad;
-  hipLaunchKernelGGL(k_objective_grad, dim3(m->n_models), dim3(kWave), 0, static_cast<hipStream_t>(stream), a);
+  const int nw = waves_for(m->max_frames);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const dim3 grid(m->n_models), block(nw * kWave);
+  switch (nw) {
+    case 1: hipLaunchKernelGGL(k_objective_grad<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_objective_grad<2>, grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_objective_grad<4>, grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_objective_grad<8>, grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL(k_objective_grad<16>, grid, block, 0, s, a); break;
+  }
   HIP_TRY(hipGetLastError());
   return ABD_OK;
 }
@@ -1705,6 +2015,8 @@ int abd_hvp(abd_model* m, const abd_step_opts* o, const double* q, const double*
   if (rc) return rc;
   if (m->n_models == 0) return ABD_OK;
   if (!q || !q_hist || !v || !Hv) return fail(ABD_EINVAL, "q, q_hist, v and Hv must not be NULL");
+  if (m->max_frames > kMaxFrames)
+    return fail(ABD_ENOTSUP, "abd_hvp handles models of at most 64 DOFs in this build");
   if ((rc = check_device(m))) return rc;
   HvpArgs a;
   a.d = dev_view(m);
@@ -1734,6 +2046,8 @@ int abd_rollout_vjp(abd_model* m, const abd_step_opts* o, const double* q_init, 
   if (m->n_models == 0) return ABD_OK;
   if (!q_init || !q_traj || !dL_dq_traj || !dL_dq_init)
     return fail(ABD_EINVAL, "q_init, q_traj, dL_dq_traj and dL_dq_init must not be NULL");
+  if (m->max_frames > kMaxFrames)
+    return fail(ABD_ENOTSUP, "abd_rollout_vjp handles models of at most 64 DOFs in this build");
   if ((rc = check_device(m))) return rc;
   VjpArgs a;
   a.d = dev_view(m);
@@ -1760,8 +2074,17 @@ int abd_poses(abd_model* m, const double* q, double* poses, void* stream) {
   if (!q || !poses) return fail(ABD_EINVAL, "q and poses must not be NULL");
   int rc = check_device(m);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_poses, dim3(m->n_models), dim3(kWave), 0, static_cast<hipStream_t>(stream), dev_view(m), q,
-                     poses);
+  const int nw = waves_for(m->max_frames);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const dim3 grid(m->n_models), block(nw * kWave);
+  const DevModel d = dev_view(m);
+  switch (nw) {
+    case 1: hipLaunchKernelGGL(k_poses<1>, grid, block, 0, s, d, q, poses); break;
+    case 2: hipLaunchKernelGGL(k_poses<2>, grid, block, 0, s, d, q, poses); break;
+    case 4: hipLaunchKernelGGL(k_poses<4>, grid, block, 0, s, d, q, poses); break;
+    case 8: hipLaunchKernelGGL(k_poses<8>, grid, block, 0, s, d, q, poses); break;
+    default: hipLaunchKernelGGL(k_poses<16>, grid, block, 0, s, d, q, poses); break;
+  }
   HIP_TRY(hipGetLastError());
   return ABD_OK;
 }

@@ -1,0 +1,148 @@
+"""Models of more than 64 DOFs: one workgroup of up to 16 wavefronts per model
+(scans and reductions carried across the waves through LDS), against the FP64
+CPU oracle.
+
+  * objective and gradient, float64: 1e-12 relative (objective relative to the
+    sum of the magnitudes of its terms, gradient to its largest component);
+  * poses: 1e-12 absolute;
+  * one time step: long chains reach the float64 floor of the gradient near a
+    relative tolerance of 1e-6 (the oracle too), so the step is solved to 1e-6
+    and checked by what that tolerance implies: the oracle's gradient at the
+    GPU's q is within the tolerance, and the GPU's q is within |H(q*)^-1| |g(q)|
+    of the exact minimizer q* (first-order bound with a 50% margin);
+  * a rollout in one launch equals the loop of single steps bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.oracle import Oracle
+from paper_1709_04145_amd import abd
+from paper_1709_04145_amd import workloads as W
+from test_gpu_parity import cu, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    abd.load()
+    yield
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(1e-300, float(np.max(np.abs(b))))) if a.size else 0.0
+
+
+def hanging_chains(sizes, seed, L=0.2, spread=0.3):
+    """Serial chains of the given DOF counts (hinges alternating y/x), hanging
+    from the root with random angles about the hanging pose."""
+    models, q0 = [], []
+    for i, n in enumerate(sizes):
+        rng = np.random.default_rng([seed, i])
+        axes = W.alternating_axes(n, "y")
+        lengths = rng.uniform(0.5 * L, 1.5 * L, n)
+        models.append(W.chain_model(lengths, 0.2 * L, rng.uniform(500, 2000, n), axes))
+        q = rng.uniform(-spread, spread, n)
+        q[0] += np.pi / 2
+        q0.append(q)
+    return W._assemble(models), np.concatenate(q0)
+
+
+@pytest.mark.parametrize("sizes", [[65, 100, 128], [129, 200, 256, 64], [300, 512, 17], [700, 1024]])
+def test_long_objective_gradient_and_poses(sizes):
+    d, _ = hanging_chains(sizes, 3)
+    say(f"long objective sizes={sizes}")
+    rng = np.random.default_rng(sum(sizes))
+    q, qp, qc = (rng.uniform(-1.5, 1.5, d.n_dofs) for _ in range(3))
+    tau = rng.uniform(-1, 1, d.n_dofs)
+    dt = 0.01
+    orc = Oracle(d)
+    E, g, S = orc.objective_grad(q, qp, qc, dt, tau)
+    m = abd.Model(d)
+    Eg, gg = m.objective_grad(cu(q), cu(np.concatenate([qp, qc])), dt, tau=cu(tau))
+    Eg, gg = Eg.cpu().numpy(), gg.cpu().numpy()
+    assert np.all(np.abs(Eg - E) <= 1e-12 * S), (Eg - E, S)
+    do = d.dof_offset
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        assert _rel(gg[sl], g[sl]) <= 1e-12, (i, _rel(gg[sl], g[sl]))
+    P = m.poses(cu(q)).cpu().numpy()
+    np.testing.assert_allclose(P, orc.poses(q), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("precision", [abd.FP64, abd.MIXED])
+def test_long_step_meets_its_tolerance(precision):
+    sizes = [65, 90, 130, 160]
+    d, q0 = hanging_chains(sizes, 5)
+    dt, tol = 0.01, 1e-6
+    say(f"long step precision={precision}")
+    m = abd.Model(d)
+    out = torch.zeros(d.n_dofs, dtype=torch.float64, device="cuda")
+    st = m.new_stats()
+    m.step(cu(np.concatenate([q0, q0])), out, abd.StepOptions(dt=dt, tol=tol, max_iter=3000, lbfgs_m=10,
+                                                               precision=precision), stats=st)
+    torch.cuda.synchronize()
+    st = m.read_stats(st, d.n_models)
+    qg = out.cpu().numpy()
+    assert np.all(st["flag"] == abd.FLAG_CONVERGED), st
+    orc = Oracle(d)
+    ref, rst = orc.step(q0, q0, dt, tol=1e-9, max_iter=5000, lbfgs_m=10)
+    qs, _ = orc.newton_polish(ref, q0, q0, dt, iters=3)
+    _, g_w, _ = orc.objective_grad(q0, q0, q0, dt)
+    _, g_q, _ = orc.objective_grad(qg, q0, q0, dt)
+    H = orc.hessian(qs, q0, q0, dt)
+    do = d.dof_offset
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        gq, gw = np.linalg.norm(g_q[sl]), np.linalg.norm(g_w[sl])
+        assert gq <= 2.0 * tol * gw, (i, gq, gw)
+        hinv = 1.0 / np.min(np.linalg.eigvalsh(H[i]))
+        err = np.linalg.norm(qg[sl] - qs[sl])
+        assert err <= 1.5 * hinv * gq + 1e-12, (i, err, hinv * gq)
+
+
+def test_long_rollout_equals_step_loop_bitwise():
+    d, q0 = hanging_chains([70, 150, 40], 9)
+    m = abd.Model(d)
+    opts = abd.StepOptions(dt=0.01, tol=1e-6, max_iter=800, lbfgs_m=10)
+    K = 3
+    traj_loop, st_loop = m.step_loop(cu(q0), K, opts)
+    st = m.new_rollout_stats(K)
+    traj, _ = m.rollout(torch.cat([cu(q0), cu(q0)]), K, opts, stats=st)
+    torch.cuda.synchronize()
+    assert torch.equal(traj, traj_loop[1:])
+    st = m.read_rollout_stats(st, K)
+    for k in range(K):
+        assert np.array_equal(st[k]["iterations"], st_loop[k]["iterations"])
+
+
+def test_long_models_reject_second_order_calls():
+    d, q0 = hanging_chains([80], 1)
+    m = abd.Model(d)
+    with pytest.raises(abd.AbdError) as e:
+        m.hvp(cu(q0), cu(np.concatenate([q0, q0])), cu(q0), 0.01)
+    assert e.value.code == abd.ABD_ENOTSUP
+
+
+def test_rope_workload_runs_and_flags_like_the_oracle():
+    """The 1000-link ropes (dt 0.1): the float64 oracle does not converge either
+    (max_iter), so this checks that both report the same outcome and that the
+    GPU's objective at its result is not above the oracle's."""
+    wl = W.config(4, n_models=2, steps=1)
+    d = wl.model
+    m = abd.Model(d)
+    out = torch.zeros(d.n_dofs, dtype=torch.float64, device="cuda")
+    st = m.new_stats()
+    opts = abd.StepOptions(dt=wl.step.dt, lbfgs_m=wl.step.lbfgs_m, max_iter=100)
+    m.step(cu(np.concatenate([wl.q0, wl.q0])), out, opts, stats=st)
+    torch.cuda.synchronize()
+    st = m.read_stats(st, d.n_models)
+    ref, rst = Oracle(d).step(wl.q0, wl.q0, wl.step.dt, lbfgs_m=wl.step.lbfgs_m, max_iter=100)
+    assert np.all(np.isin(st["flag"], [abd.FLAG_MAX_ITER, abd.FLAG_LS_FLOOR]))
+    assert np.all(np.isin(rst["flag"], [abd.FLAG_MAX_ITER, abd.FLAG_LS_FLOOR]))
+    E0, _, S = Oracle(d).objective_grad(wl.q0, wl.q0, wl.q0, wl.step.dt)
+    Eg, _, _ = Oracle(d).objective_grad(out.cpu().numpy(), wl.q0, wl.q0, wl.step.dt)
+    assert np.all(Eg < E0), (Eg, E0)  # the GPU's iterations decreased the objective

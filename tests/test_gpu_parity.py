@@ -297,12 +297,12 @@ def test_empty_batch():
                         abd._stream())
 
 
-def test_64_dofs_is_the_limit():
-    d = W.random_chain_models(2, 3, lo=64, hi=64)
+def test_1024_dofs_is_the_limit():
+    d = W.random_chain_models(1, 3, lo=1024, hi=1024)
     abd.Model(d)
-    d65 = W.random_chain_models(1, 3, lo=65, hi=65)
+    d1025 = W.random_chain_models(1, 3, lo=1025, hi=1025)
     with pytest.raises(abd.AbdError) as e:
-        abd.Model(d65)
+        abd.Model(d1025)
     assert e.value.code == abd.ABD_ENOTSUP
 
 
@@ -351,3 +351,38 @@ def test_invalid_options_rejected():
     with pytest.raises(abd.AbdError) as e:
         m.step(hist, out, abd.StepOptions(dt=0.1, order_K=4))
     assert e.value.code == abd.ABD_ENOTSUP
+
+
+def test_rollout_captured_in_hip_graph_replays_exactly():
+    """abd_rollout captured in a HIP graph (through torch's graph capture) and
+    replayed several times, with other eager work on the same model in between,
+    matches an eager rollout of the same inputs bit for bit on every replay."""
+    wl = W.config(2, n_models=64)
+    d = wl.model
+    m = abd.Model(d)
+    opts = abd.StepOptions(dt=wl.step.dt, precision=abd.MIXED)
+    steps = 3
+    rng = np.random.default_rng(81)
+    init = torch.zeros(2 * d.n_dofs, dtype=torch.float64, device="cuda")
+    traj = torch.empty((steps, d.n_dofs), dtype=torch.float64, device="cuda")
+    stats = m.new_rollout_stats(steps)
+    init.copy_(cu(np.concatenate([wl.q0, wl.q0])))
+    m.rollout(init, steps, opts, q_traj=traj, stats=stats)  # warm-up outside capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        m.rollout(init, steps, opts, q_traj=traj, stats=stats)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        q0 = wl.q0 + 0.1 * rng.uniform(-1, 1, d.n_dofs)
+        init.copy_(cu(np.concatenate([q0, q0])))
+        g.replay()
+        torch.cuda.synchronize()
+        got = traj.clone()
+        got_st = m.read_rollout_stats(stats, steps)
+        # eager work on the same model between replays
+        ref, ref_st = m.rollout(cu(np.concatenate([q0, q0])), steps, opts, stats=m.new_rollout_stats(steps))
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), rep
+        ref_st = m.read_rollout_stats(ref_st, steps)
+        assert np.array_equal(got_st["iterations"], ref_st["iterations"]), rep
