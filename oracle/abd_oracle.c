@@ -907,3 +907,468 @@ int orc_step(const orc_model* m, const orc_opts* o, const double* q_hist, const 
   free(scratch);
   return 0;
 }
+
+/* ------------------------------------------ high-order collocation (K>2) -- */
+/* Sec. 4, Eq. HOC / Eq. EQHOC.  Collocation points of order K: alpha_1 < ... <
+ * alpha_{K-2} are the roots of the Legendre polynomial L_{K-2}(2 alpha - 1) and
+ * alpha_{K-1} = 1.  The K+1 points of one step, in units of dt from t_k, are
+ *   tau = (alpha_{K-2} - 1, 0, alpha_1, ..., alpha_{K-1})
+ * (the first is the previous step's alpha_{K-2} point; alpha_0 = 0 for K = 2).
+ * Every body point follows the polynomial through its positions at these
+ * points, so dt^2 Pddot(tau_i) = sum_j w_ij P_j with w_ij = L_j''(tau_i) for the
+ * Lagrange basis L_j through the points. */
+#define ORC_KMAX 8
+
+/* Legendre polynomial P_n(x) and its derivative by the three-term recurrence. */
+static double legendre(int n, double x, double* dp) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) {
+    *dp = 0.0;
+    return 1.0;
+  }
+  for (int k = 2; k <= n; ++k) {
+    double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  *dp = n * (x * p1 - p0) / (x * x - 1.0);
+  return p1;
+}
+
+int orc_collocation(int K, double* tau, double* w) {
+  if (K < 2 || K > ORC_KMAX) return -1;
+  int n = K - 2;
+  double alpha[ORC_KMAX + 1];
+  /* roots of P_n by Newton from the usual cosine guesses, ascending in alpha */
+  for (int r = 0; r < n; ++r) {
+    double x = cos(acos(-1.0) * (r + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double dp, p = legendre(n, x, &dp);
+      double dx = p / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    alpha[n - r] = 0.5 * (x + 1.0); /* index 1..n ascending */
+  }
+  alpha[0] = 0.0;
+  alpha[K - 1] = 1.0;
+  tau[0] = alpha[K - 2] - 1.0;
+  tau[1] = 0.0;
+  for (int u = 1; u <= K - 1; ++u) tau[1 + u] = alpha[u];
+  /* w[u][j] = L_j''(tau_{1+u}), u = 0..K-2 (the unknown points), j = 0..K */
+  int np = K + 1;
+  for (int u = 0; u < K - 1; ++u) {
+    double x = tau[2 + u];
+    for (int j = 0; j < np; ++j) {
+      double den = 1.0;
+      for (int a = 0; a < np; ++a)
+        if (a != j) den *= tau[j] - tau[a];
+      double num = 0.0;
+      for (int a = 0; a < np; ++a) {
+        if (a == j) continue;
+        for (int b = 0; b < np; ++b) {
+          if (b == j || b == a) continue;
+          double prod = 1.0;
+          for (int c = 0; c < np; ++c)
+            if (c != j && c != a && c != b) prod *= x - tau[c];
+          num += prod;
+        }
+      }
+      w[u * np + j] = num / den;
+    }
+  }
+  return 0;
+}
+
+/* Per-model work space of the EQHOC evaluation: poses T (and local transforms
+ * tl) of all K+1 points, derivative generators of the K-1 unknown points, the
+ * seeds and residuals of the unknown points. */
+typedef struct {
+  int K, nd;
+  double *T, *tl, *Wg, *G, *res, *Adj, *blk;
+  char* below;
+} hoc_ws;
+
+static void hoc_alloc(hoc_ws* h, int K, int nd) {
+  int n1 = nd > 0 ? nd : 1;
+  h->K = K;
+  h->nd = nd;
+  h->T = (double*)malloc((size_t)(K + 1) * n1 * 16 * sizeof(double));
+  h->tl = (double*)malloc((size_t)(K + 1) * n1 * 16 * sizeof(double));
+  h->Wg = (double*)malloc((size_t)(K + 1) * n1 * 16 * sizeof(double));
+  h->G = (double*)malloc((size_t)(K - 1) * n1 * 16 * sizeof(double));
+  h->res = (double*)malloc((size_t)(K - 1) * n1 * sizeof(double));
+  h->Adj = (double*)malloc((size_t)n1 * 16 * sizeof(double));
+  h->blk = (double*)malloc((size_t)n1 * n1 * sizeof(double));
+  h->below = (char*)malloc((size_t)n1 * n1);
+}
+static void hoc_free(hoc_ws* h) {
+  free(h->T); free(h->tl); free(h->Wg); free(h->G); free(h->res); free(h->Adj); free(h->blk);
+  free(h->below);
+}
+
+/* EQHOC objective of model i and its gradient with respect to the K-1 unknown
+ * configurations.  pts[p] (p = 0..K) are full-length DOF vectors: the two known
+ * points and the unknowns.  Per unknown u (point p = 2+u):
+ *   dt^2 r_u = sum_p w_up dI(q_u, q_p)/dq_u - dt^2 dV/dq... as the Alg. 1
+ *   backward pass at q_u of the seed G_u = sum_p w_up A(q_p) M - dt^2 g (M e4)^T,
+ *   minus dt^2 tau (generalized force);
+ *   E = sum_u |dt^2 r_u|^2.
+ * Gradient dE/dq_a = 2 sum_u J_ua^T (dt^2 r_u) with the blocks
+ *   J_uu = S(q_u; G_u) + w_u,(2+u) C(q_u, q_u),   J_ua = w_u,(2+a) C(q_u, q_a),
+ *   S(q; G)_bc = sum_l <G_l, d2A_l(q)/dq_b dq_c>,
+ *   C(q, q')_bc = sum_l <dA_l(q)/dq_b M_l, dA_l(q')/dq'_c>,
+ * written out from the pose derivatives (dT/dq_n = W_n T, d2T/dq_b dq_c = W_b W_c T).
+ * grad (may be NULL) receives [K-1][nd] local values. */
+static double hoc_eval_model(const orc_model* m, int i, int K, const double* w, double dt,
+                             const double* const* pts, const double* tau, hoc_ws* h, double* grad) {
+  const int d0 = m->model_dof[i], nd = model_nd(m, i), np = K + 1, U = K - 1;
+  const double dt2 = dt * dt;
+  eval_ws ew;
+  ws_alloc(&ew, nd);
+  for (int p = 0; p < np; ++p) {
+    if (p >= 2) {
+      generators_model(m, i, pts[p], &ew, h->Wg + (size_t)p * nd * 16);
+    } else {
+      fk_model(m, i, pts[p], ew.T, ew.tl);
+    }
+    memcpy(h->T + (size_t)p * nd * 16, ew.T, (size_t)nd * 16 * sizeof(double));
+    memcpy(h->tl + (size_t)p * nd * 16, ew.tl, (size_t)nd * 16 * sizeof(double));
+  }
+  below_model(m, i, h->below);
+  double E = 0.0;
+  for (int u = 0; u < U; ++u) {
+    double* G = h->G + (size_t)u * nd * 16;
+    memset(G, 0, (size_t)nd * 16 * sizeof(double));
+    for (int j = 0; j < nd; ++j) {
+      int l = m->frame_mass[d0 + j];
+      if (l < 0) continue;
+      double M[16], TM[16];
+      mm_full(m->mm + 10 * l, M);
+      for (int p = 0; p < np; ++p) {
+        m4_mul(h->T + ((size_t)p * nd + j) * 16, M, TM);
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 4; ++c) G[16 * j + 4 * r + c] += w[u * np + p] * TM[4 * r + c];
+      }
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 4; ++c) G[16 * j + 4 * r + c] -= dt2 * m->g[r] * M[4 * c + 3];
+    }
+    /* residual: Alg. 1 backward pass at q_u with the seed G_u */
+    memcpy(h->Adj, G, (size_t)nd * 16 * sizeof(double));
+    double* r = h->res + (size_t)u * nd;
+    double* gfull = (double*)calloc((size_t)m->n_dofs > 0 ? m->n_dofs : 1, sizeof(double));
+    alg1_backward(m, i, h->T + (size_t)(2 + u) * nd * 16, h->tl + (size_t)(2 + u) * nd * 16, h->Adj,
+                  pts[2 + u], gfull);
+    for (int j = 0; j < nd; ++j) r[j] = gfull[d0 + j] - (tau ? dt2 * tau[d0 + j] : 0.0);
+    free(gfull);
+    for (int j = 0; j < nd; ++j) E += r[j] * r[j];
+  }
+  if (grad) {
+    memset(grad, 0, (size_t)U * nd * sizeof(double));
+    double WW[16], d2A[16], dA[16], dAM[16], dAo[16], M[16];
+    for (int u = 0; u < U; ++u) {
+      const double* Tu = h->T + (size_t)(2 + u) * nd * 16;
+      const double* Wu = h->Wg + (size_t)(2 + u) * nd * 16;
+      const double* G = h->G + (size_t)u * nd * 16;
+      const double* r = h->res + (size_t)u * nd;
+      for (int a = 0; a < U; ++a) {
+        const double* Ta = h->T + (size_t)(2 + a) * nd * 16;
+        const double* Wa = h->Wg + (size_t)(2 + a) * nd * 16;
+        const double wua = w[u * np + 2 + a];
+        /* block J_ua (rows: residual components b, columns: DOFs c of q_a) */
+        for (int b = 0; b < nd; ++b)
+          for (int c = 0; c < nd; ++c) {
+            double v = 0.0;
+            if (a == u) {
+              /* S(q_u; G_u)_bc, b or c the ancestor */
+              int lo = b < c ? b : c, hi = b < c ? c : b;
+              if (h->below[(size_t)lo * nd + hi]) {
+                m4_mul(Wu + 16 * lo, Wu + 16 * hi, WW);
+                for (int j = hi; j < nd; ++j) {
+                  if (m->frame_mass[d0 + j] < 0 || !h->below[(size_t)hi * nd + j]) continue;
+                  m4_mul(WW, Tu + 16 * j, d2A);
+                  for (int x = 0; x < 12; ++x) v += G[16 * j + x] * d2A[x];
+                }
+              }
+            }
+            if (wua != 0.0) {
+              double cv = 0.0;
+              for (int j = 0; j < nd; ++j) {
+                int l = m->frame_mass[d0 + j];
+                if (l < 0 || !h->below[(size_t)b * nd + j] || !h->below[(size_t)c * nd + j]) continue;
+                mm_full(m->mm + 10 * l, M);
+                m4_mul(Wu + 16 * b, Tu + 16 * j, dA);
+                m4_mul(dA, M, dAM);
+                m4_mul(Wa + 16 * c, Ta + 16 * j, dAo);
+                for (int x = 0; x < 12; ++x) cv += dAM[x] * dAo[x];
+              }
+              v += wua * cv;
+            }
+            h->blk[(size_t)b * nd + c] = v;
+          }
+        for (int c = 0; c < nd; ++c) {
+          double s = 0.0;
+          for (int b = 0; b < nd; ++b) s += h->blk[(size_t)b * nd + c] * r[b];
+          grad[(size_t)a * nd + c] += 2.0 * s;
+        }
+      }
+    }
+  }
+  ws_free(&ew);
+  return E;
+}
+
+void orc_eqhoc_objective_grad(const orc_model* m, int K, double dt, const double* q_known,
+                              const double* q_unknown, const double* tau, double* E, double* grad,
+                              int n_threads) {
+  double tauv[ORC_KMAX + 1], w[(ORC_KMAX - 1) * (ORC_KMAX + 1)];
+  orc_collocation(K, tauv, w);
+  const int n = m->n_dofs, U = K - 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int i = 0; i < m->n_models; ++i) {
+    int nd = model_nd(m, i), d0 = m->model_dof[i];
+    const double* pts[ORC_KMAX + 1];
+    pts[0] = q_known;
+    pts[1] = q_known + n;
+    for (int u = 0; u < U; ++u) pts[2 + u] = q_unknown + (size_t)u * n;
+    hoc_ws h;
+    hoc_alloc(&h, K, nd);
+    double* g = grad ? (double*)malloc((size_t)U * (nd > 0 ? nd : 1) * sizeof(double)) : NULL;
+    E[i] = hoc_eval_model(m, i, K, w, dt, pts, tau, &h, g);
+    if (grad)
+      for (int u = 0; u < U; ++u)
+        for (int j = 0; j < nd; ++j) grad[(size_t)u * n + d0 + j] = g[(size_t)u * nd + j];
+    free(g);
+    hoc_free(&h);
+  }
+}
+
+/* Dense inverse of a small matrix by Gauss-Jordan with partial pivoting; 0 on success. */
+static int small_inverse(const double* A, int n, double* X) {
+  double a[ORC_KMAX * ORC_KMAX * 2];
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < 2 * n; ++c) a[r * 2 * n + c] = c < n ? A[r * n + c] : (c - n == r ? 1.0 : 0.0);
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(a[r * 2 * n + c]) > fabs(a[p * 2 * n + c])) p = r;
+    if (a[p * 2 * n + c] == 0.0) return -1;
+    for (int k = 0; k < 2 * n; ++k) {
+      double t = a[c * 2 * n + k];
+      a[c * 2 * n + k] = a[p * 2 * n + k];
+      a[p * 2 * n + k] = t;
+    }
+    double piv = a[c * 2 * n + c];
+    for (int k = 0; k < 2 * n; ++k) a[c * 2 * n + k] /= piv;
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = a[r * 2 * n + c];
+      for (int k = 0; k < 2 * n; ++k) a[r * 2 * n + k] -= f * a[c * 2 * n + k];
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) X[r * n + c] = a[r * 2 * n + n + c];
+  return 0;
+}
+
+/* One EQHOC step of model i (Sec. 4-5): L-BFGS over the K-1 unknown
+ * configurations with the same line search and termination as the K = 2 step.
+ * Warm start: constant velocity from the two known points,
+ * q_u = q_k + alpha_u (q_k - q_prev) / (1 - alpha_{K-2}).  Initial inverse
+ * Hessian (precond 2): E is a sum of squares whose Jacobian is close to
+ * W_uu (x) H_q (W_uu: weights among the unknown points, H_q: joint-space
+ * inertia at q_k), so H0 = (W_uu^T W_uu)^-1 (x) H_q^-2; precond 0: gamma I. */
+static void step_model_hoc(const orc_model* m, int i, const orc_opts* o, const double* qprev, const double* qk,
+                           const double* tau, double* qunk_full, double* q_out, orc_stats* st) {
+  const int K = o->order_K, U = K - 1, np = K + 1, n = m->n_dofs;
+  const int d0 = m->model_dof[i], nd = model_nd(m, i), N = U * nd, Mh = o->lbfgs_m > 0 ? o->lbfgs_m : 1;
+  orc_stats s = {0, 0, 0, 0, 0.0, 0.0};
+  if (nd == 0) {
+    s.flag = 1;
+    *st = s;
+    return;
+  }
+  double tauv[ORC_KMAX + 1], w[(ORC_KMAX - 1) * (ORC_KMAX + 1)];
+  orc_collocation(K, tauv, w);
+  int mode = o->precond == 2 ? 2 : 0;
+  double* buf = (double*)calloc((size_t)N * (6 + 2 * Mh) + 3 * Mh, sizeof(double));
+  double *q = buf, *g = q + N, *d = g + N, *qt = d + N, *gt = qt + N, *tmp = gt + N;
+  double *Sv = tmp + N, *Yv = Sv + (size_t)Mh * N, *rho = Yv + (size_t)Mh * N, *alp = rho + Mh, *gam = alp + Mh;
+  double* L = NULL;
+  double Minv[ORC_KMAX * ORC_KMAX];
+  hoc_ws h;
+  hoc_alloc(&h, K, nd);
+  const double* pts[ORC_KMAX + 1];
+  pts[0] = qprev;
+  pts[1] = qk;
+  for (int u = 0; u < U; ++u) pts[2 + u] = qunk_full + (size_t)u * n;
+
+  const double vscale = 1.0 / (tauv[1] - tauv[0]);
+  for (int u = 0; u < U; ++u)
+    for (int j = 0; j < nd; ++j)
+      q[u * nd + j] = qk[d0 + j] + tauv[2 + u] * vscale * (qk[d0 + j] - qprev[d0 + j]);
+  if (mode == 2) {
+    double Wuu[ORC_KMAX * ORC_KMAX], WtW[ORC_KMAX * ORC_KMAX];
+    for (int u = 0; u < U; ++u)
+      for (int a = 0; a < U; ++a) Wuu[u * U + a] = w[u * np + 2 + a];
+    for (int a = 0; a < U; ++a)
+      for (int b = 0; b < U; ++b) {
+        double t = 0.0;
+        for (int u = 0; u < U; ++u) t += Wuu[u * U + a] * Wuu[u * U + b];
+        WtW[a * U + b] = t;
+      }
+    eval_ws ew;
+    ws_alloc(&ew, nd);
+    L = (double*)malloc(((size_t)nd * nd + 32 * (size_t)nd) * sizeof(double));
+    inertia_matrix_model(m, i, qk, &ew, L, L + (size_t)nd * nd, L + (size_t)nd * nd + 16 * nd);
+    ws_free(&ew);
+    if (cholesky(L, nd) != 0 || small_inverse(WtW, U, Minv) != 0) mode = 0;
+  }
+#define HOC_EVAL(X, GRAD, EOUT)                                                     \
+  do {                                                                              \
+    for (int u_ = 0; u_ < U; ++u_)                                                  \
+      for (int j_ = 0; j_ < nd; ++j_) qunk_full[(size_t)u_ * n + d0 + j_] = (X)[u_ * nd + j_]; \
+    EOUT = hoc_eval_model(m, i, K, w, o->dt, pts, tau, &h, GRAD);                   \
+  } while (0)
+  double E;
+  HOC_EVAL(q, g, E);
+  s.evaluations = 1;
+  if (!isfinite(E) || !finitev(g, N)) {
+    s.flag = 8;
+    s.energy = E;
+    s.grad_norm = NAN;
+    goto done;
+  }
+  double g0 = sqrt(dotv(g, g, N)), gn = g0;
+  if (g0 == 0.0) {
+    s.flag = 1;
+    goto finish;
+  }
+  int head = 0, count = 0;
+  const double c1 = 1e-4, dlt = 0.1;
+  for (int it = 0; it < o->max_iter; ++it) {
+    for (int j = 0; j < N; ++j) d[j] = g[j];
+    for (int t = 0; t < count; ++t) {
+      int k = (head + count - 1 - t) % Mh;
+      alp[k] = rho[k] * dotv(Sv + (size_t)k * N, d, N);
+      for (int j = 0; j < N; ++j) d[j] -= alp[k] * Yv[(size_t)k * N + j];
+    }
+    /* initial inverse Hessian */
+    if (mode == 2) {
+      for (int u = 0; u < U; ++u) {
+        chol_solve(L, nd, d + (size_t)u * nd);
+        chol_solve(L, nd, d + (size_t)u * nd);
+      }
+      for (int u = 0; u < U; ++u)
+        for (int j = 0; j < nd; ++j) {
+          double t = 0.0;
+          for (int a = 0; a < U; ++a) t += Minv[u * U + a] * d[(size_t)a * nd + j];
+          tmp[(size_t)u * nd + j] = t;
+        }
+      memcpy(d, tmp, (size_t)N * sizeof(double));
+    } else {
+      double gamma = count > 0 ? gam[(head + count - 1) % Mh] : 1.0;
+      for (int j = 0; j < N; ++j) d[j] *= gamma;
+    }
+    for (int t = count - 1; t >= 0; --t) {
+      int k = (head + count - 1 - t) % Mh;
+      double b = rho[k] * dotv(Yv + (size_t)k * N, d, N);
+      for (int j = 0; j < N; ++j) d[j] += (alp[k] - b) * Sv[(size_t)k * N + j];
+    }
+    for (int j = 0; j < N; ++j) d[j] = -d[j];
+    double gd = dotv(g, d, N);
+    if (!(gd < 0.0)) {
+      if (count > 0) {
+        count = 0;
+        --it;
+        continue; /* redo the direction with an empty history */
+      }
+      s.flag = 2;
+      break;
+    }
+    double alpha = 1.0, Et = 0.0;
+    int ok = 0;
+    for (int ls = 0; ls < o->max_ls; ++ls) {
+      for (int j = 0; j < N; ++j) qt[j] = q[j] + alpha * d[j];
+      HOC_EVAL(qt, gt, Et);
+      s.evaluations++;
+      if (isfinite(Et) && finitev(gt, N)) {
+        if (Et <= E + c1 * alpha * gd)
+          ok = 1;
+        else if (fabs(Et - E) <= 10.0 * o->eps_w * Et) {
+          double gtd = dotv(gt, d, N);
+          if (gtd <= (2.0 * dlt - 1.0) * gd) ok = 1;
+        }
+      }
+      if (ok) break;
+      alpha *= 0.5;
+    }
+    if (!ok) {
+      s.flag = 2;
+      break;
+    }
+    double sy = 0.0, ss = 0.0, yy = 0.0;
+    for (int j = 0; j < N; ++j) {
+      double sj = qt[j] - q[j], yj = gt[j] - g[j];
+      sy += sj * yj;
+      ss += sj * sj;
+      yy += yj * yj;
+    }
+    if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
+      int k;
+      if (count < Mh) {
+        k = (head + count) % Mh;
+        count++;
+      } else {
+        k = head;
+        head = (head + 1) % Mh;
+      }
+      for (int j = 0; j < N; ++j) {
+        Sv[(size_t)k * N + j] = qt[j] - q[j];
+        Yv[(size_t)k * N + j] = gt[j] - g[j];
+      }
+      rho[k] = 1.0 / sy;
+      gam[k] = sy / yy;
+    }
+    memcpy(q, qt, (size_t)N * sizeof(double));
+    memcpy(g, gt, (size_t)N * sizeof(double));
+    E = Et;
+    s.iterations++;
+    gn = sqrt(dotv(g, g, N));
+    if (gn <= o->tol * g0) {
+      s.flag = 1;
+      break;
+    }
+  }
+  if (s.flag == 0) s.flag = 4;
+finish:
+  s.grad_norm = gn;
+  s.energy = E;
+done:
+  for (int u = 0; u < U; ++u)
+    for (int j = 0; j < nd; ++j) q_out[(size_t)u * n + d0 + j] = q[u * nd + j];
+  *st = s;
+#undef HOC_EVAL
+  free(L);
+  free(buf);
+  hoc_free(&h);
+}
+
+int orc_step_hoc(const orc_model* m, const orc_opts* o, const double* q_known, const double* tau,
+                 double* q_out, orc_stats* stats, int n_threads) {
+  if (o->order_K < 3 || o->order_K > ORC_KMAX) return -1;
+  const int n = m->n_dofs > 0 ? m->n_dofs : 1, U = o->order_K - 1;
+  int nt = n_threads > 0 ? n_threads : 1;
+  double* scratch = (double*)malloc((size_t)nt * U * n * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  for (int i = 0; i < m->n_models; ++i) {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    double* qunk = scratch + (size_t)tid * U * n;
+    step_model_hoc(m, i, o, q_known, q_known + m->n_dofs, tau, qunk, q_out, stats + i);
+  }
+  free(scratch);
+  return 0;
+}

@@ -87,10 +87,30 @@ void orc_hessian(const orc_model* m, double dt, const double* q, const double* q
 void orc_cross_hessian(const orc_model* m, const double* q, const double* q_o, double scale, double* C,
                        int n_threads);
 
+/* Collocation of order K (2..8) for Eq. HOC: tau[K+1] = the points of one step
+ * in units of dt from t_k (alpha_{K-2}-1, 0, alpha_1..alpha_{K-1}), and
+ * w[(K-1)*(K+1)] = second derivatives of the Lagrange basis at the K-1 unknown
+ * points (dt^2 Pddot(tau_{2+u}) = sum_j w[u][j] P_j).  Returns 0, or -1 for K
+ * out of range. */
+int orc_collocation(int K, double* tau, double* w);
+
+/* Eq. EQHOC objective per model and its gradient ([K-1][n_dofs]) with respect to
+ * the K-1 unknown configurations q_unknown ([K-1][n_dofs]), given the two known
+ * configurations q_known = [q_{k-1+alpha_{K-2}}; q_k].  tau may be NULL. */
+void orc_eqhoc_objective_grad(const orc_model* m, int K, double dt, const double* q_known,
+                              const double* q_unknown, const double* tau, double* E, double* grad,
+                              int n_threads);
+
 /* One time step for every model: q_out = argmin of the step objective,
  * reached by preconditioned L-BFGS from the warm start 2 q_k - q_{k-1}. */
 int orc_step(const orc_model* m, const orc_opts* o, const double* q_hist, const double* tau,
              double* q_out, orc_stats* stats, int n_threads);
+
+/* One Eq. EQHOC step (order_K = 3..8) for every model: q_known = [q_{k-1+alpha_{K-2}};
+ * q_k] ([2][n_dofs]), q_out receives the K-1 unknown configurations ([K-1][n_dofs],
+ * the last one is q_{k+1}).  Returns 0, or -1 for an order out of range. */
+int orc_step_hoc(const orc_model* m, const orc_opts* o, const double* q_known, const double* tau,
+                 double* q_out, orc_stats* stats, int n_threads);
 
 /* Reported total energy at step k: (1/2dt^2) sum tr(dA M dA^T) + V(q_k),
  * dA = A(q_k) - A(q_{k-1}). */

@@ -71,6 +71,11 @@ def lib():
         _lib.orc_inertia_diag.argtypes = [C.c_void_p, dp, dp, C.c_int]
         _lib.orc_inertia_matrix.argtypes = [C.c_void_p, dp, dp, C.c_int]
         _lib.orc_hessian.argtypes = [C.c_void_p, C.c_double, dp, dp, dp, C.c_int]
+        _lib.orc_collocation.argtypes = [C.c_int, dp, dp]
+        _lib.orc_collocation.restype = C.c_int
+        _lib.orc_eqhoc_objective_grad.argtypes = [C.c_void_p, C.c_int, C.c_double, dp, dp, dp, dp, dp, C.c_int]
+        _lib.orc_step_hoc.argtypes = [C.c_void_p, C.POINTER(OrcOpts), dp, dp, dp, C.c_void_p, C.c_int]
+        _lib.orc_step_hoc.restype = C.c_int
         _lib.orc_cross_hessian.argtypes = [C.c_void_p, dp, dp, C.c_double, dp, C.c_int]
         _lib.orc_step.argtypes = [C.c_void_p, C.POINTER(OrcOpts), dp, dp, dp, C.c_void_p, C.c_int]
         _lib.orc_step.restype = C.c_int
@@ -92,6 +97,15 @@ def _f64(a):
 
 def default_threads() -> int:
     return max(1, min(16, os.cpu_count() or 1))
+
+
+def collocation(K: int):
+    """(tau [K+1], w [K-1, K+1]) of the order-K position-based collocation (Eq. HOC)."""
+    tau = np.zeros(K + 1)
+    w = np.zeros((K - 1) * (K + 1))
+    if lib().orc_collocation(K, _d(tau), _d(w)) != 0:
+        raise ValueError(f"order {K} out of range")
+    return tau, w.reshape(K - 1, K + 1)
 
 
 class Oracle:
@@ -215,6 +229,44 @@ class Oracle:
             nxt, st = self.step(prev, qs[-1], dt, tau=tau, **kw)
             prev = qs[-1]
             qs.append(nxt)
+            stats.append(st)
+        return np.stack(qs), stats
+
+    def eqhoc_objective_grad(self, K, dt, q_prev, q_curr, q_unknown, tau=None):
+        """Eq. EQHOC per model and its gradient [K-1, n] w.r.t. the unknown points."""
+        E = np.zeros(self.n_models)
+        g = np.zeros((K - 1) * self.n_dofs)
+        known = _f64(np.concatenate([q_prev, q_curr]))
+        unk = _f64(np.asarray(q_unknown).reshape(-1))
+        tau = None if tau is None else _f64(tau)
+        lib().orc_eqhoc_objective_grad(self._h, K, dt, _d(known), _d(unk), _d(tau), _d(E), _d(g), self.threads)
+        return E, g.reshape(K - 1, self.n_dofs)
+
+    def step_hoc(self, K, q_prev, q_curr, dt, tau=None, lbfgs_m=5, tol=1e-8, max_iter=500, max_ls=40,
+                 eps_w=EPS64, precond=2):
+        """One Eq. EQHOC step: returns the K-1 unknown configurations [K-1, n] and stats.
+        q_prev is the previous step's alpha_{K-2} point, q_curr = q_k."""
+        opts = OrcOpts(dt, K, lbfgs_m, tol, max_iter, max_ls, eps_w, precond)
+        known = _f64(np.concatenate([q_prev, q_curr]))
+        out = np.zeros((K - 1) * self.n_dofs)
+        stats = np.zeros(self.n_models, dtype=STATS_DTYPE)
+        tau = None if tau is None else _f64(tau)
+        rc = lib().orc_step_hoc(self._h, C.byref(opts), _d(known), _d(tau), _d(out),
+                                stats.ctypes.data_as(C.c_void_p), self.threads)
+        if rc != 0:
+            raise ValueError(f"orc_step_hoc failed ({rc})")
+        return out.reshape(K - 1, self.n_dofs), stats
+
+    def rollout_hoc(self, K, q_prev, q0, steps, dt, **kw):
+        """Order-K rollout from the known points (q_{-1+alpha_{K-2}}, q_0): returns
+        q_0..q_steps at whole steps and the per-step stats."""
+        qs = [np.array(q0, dtype=np.float64)]
+        prev = np.array(q_prev, dtype=np.float64)
+        stats = []
+        for _ in range(steps):
+            pts, st = self.step_hoc(K, prev, qs[-1], dt, **kw)
+            prev = pts[K - 3] if K >= 3 else qs[-1]
+            qs.append(pts[K - 2].copy())
             stats.append(st)
         return np.stack(qs), stats
 

@@ -415,3 +415,91 @@ def test_rollout_vjp_matches_finite_differences():
         e[k, j] = h
         fd = (loss(qm1, q0, tau + e) - loss(qm1, q0, tau - e)) / (2 * h)
         assert abs(fd - g_tau[k, j]) <= 1e-6 * max(1e-3, abs(fd)), (k, j, fd, g_tau[k, j])
+
+
+# ------------------------------------------------- high-order collocation
+def test_collocation_points_and_weights():
+    """Eq. HOC: the interior points are the roots of L_{K-2}(2 alpha - 1); the
+    weights are second derivatives of the Lagrange basis, so they reproduce the
+    second derivative of every polynomial of degree <= K exactly."""
+    from oracle.oracle import collocation
+    tau, w = collocation(2)
+    np.testing.assert_allclose(tau, [-1, 0, 1], atol=1e-15)
+    np.testing.assert_allclose(w, [[1, -2, 1]], atol=1e-12)
+    tau, w = collocation(3)
+    np.testing.assert_allclose(tau, [-0.5, 0, 0.5, 1], atol=1e-15)
+    np.testing.assert_allclose(w, [[0, 4, -8, 4], [-4, 16, -20, 8]], atol=1e-12)
+    tau, w = collocation(4)
+    a1, a2 = (1 - 1 / math.sqrt(3)) / 2, (1 + 1 / math.sqrt(3)) / 2
+    np.testing.assert_allclose(tau, [a2 - 1, 0, a1, a2, 1], atol=1e-15)
+    for K in (2, 3, 4, 5, 6):
+        tau, w = collocation(K)
+        for p in range(K + 1):
+            exact = p * (p - 1) * tau[2:] ** (p - 2) if p >= 2 else np.zeros(K - 1)
+            np.testing.assert_allclose(w @ tau ** p, exact, atol=1e-9 * (1 + np.abs(exact).max()))
+
+
+def test_eqhoc_at_order_two_is_the_squared_eq_gradient():
+    """At K = 2 the collocation residual is the gradient of Eq. EQ, so
+    Eq. EQHOC = |grad E|^2 and both have the same minimizer."""
+    d = _tree(3, seed=41)
+    rng = np.random.default_rng(42)
+    q, qp, qc = (rng.uniform(-1, 1, d.n_dofs) for _ in range(3))
+    tau = rng.uniform(-1, 1, d.n_dofs)
+    dt = 0.04
+    orc = Oracle(d)
+    _, g, _ = orc.objective_grad(q, qp, qc, dt, tau)
+    E, _ = orc.eqhoc_objective_grad(2, dt, qp, qc, q[None], tau)
+    do = d.dof_offset
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        assert abs(E[i] - g[sl] @ g[sl]) <= 1e-12 * max(1e-30, g[sl] @ g[sl])
+
+
+@pytest.mark.parametrize("K", [3, 4])
+def test_eqhoc_gradient_matches_central_differences(K):
+    d = _tree(2, seed=43 + K, max_links=3)
+    rng = np.random.default_rng(44 + K)
+    qp, qc = (rng.uniform(-1, 1, d.n_dofs) for _ in range(2))
+    qu = rng.uniform(-1, 1, (K - 1, d.n_dofs))
+    dt = 0.05
+    orc = Oracle(d)
+    E, g = orc.eqhoc_objective_grad(K, dt, qp, qc, qu)
+    h = 1e-6
+    for u in range(K - 1):
+        for j in range(d.n_dofs):
+            e = np.zeros_like(qu)
+            e[u, j] = h
+            Ep, _ = orc.eqhoc_objective_grad(K, dt, qp, qc, qu + e)
+            Em, _ = orc.eqhoc_objective_grad(K, dt, qp, qc, qu - e)
+            fd = (Ep.sum() - Em.sum()) / (2 * h)
+            assert abs(fd - g[u, j]) <= 1e-6 * max(1.0, np.abs(g).max()), (u, j, fd, g[u, j])
+
+
+@pytest.mark.slow
+def test_higher_orders_converge_faster_to_the_lagrangian_reference():
+    """The order-K method tracks the continuous equations (RK4 reference) with
+    error O(dt^(K-1)): order ~2 for K = 3, and at a fixed dt the errors fall by
+    orders of magnitude from K = 2 to 3 to 4.  Started from the exact solution's
+    known points (motion from rest is time-symmetric: q(-s) = q(s))."""
+    from oracle.oracle import collocation
+    d = W._assemble([W.chain_model([1.0, 0.8, 0.6], 0.1, [1000.0] * 3, W.alternating_axes(3, "y"))])
+    q0 = np.array([0.4, -0.3, 0.2])
+    T = 0.2
+    ref = refkin.rk4_reference(d, q0, T, 0.001)
+    orc = Oracle(d, threads=1)
+
+    def err(K, dt):
+        if K == 2:
+            qs, _ = orc.rollout(q0, int(round(T / dt)), dt, tol=1e-12)
+        else:
+            tau, _ = collocation(K)
+            s = -tau[0] * dt
+            qprev = refkin.rk4_reference(d, q0, s, s / max(1, int(round(s / 0.0005))))
+            qs, _ = orc.rollout_hoc(K, qprev, q0, int(round(T / dt)), dt, tol=1e-12, max_iter=5000)
+        return float(np.max(np.abs(qs[-1] - ref)))
+
+    e3 = [err(3, dt) for dt in (0.01, 0.005)]
+    assert 1.7 < math.log2(e3[0] / e3[1]) < 2.4, e3
+    e2, e4 = err(2, 0.01), err(4, 0.01)
+    assert e4 < 1e-2 * e3[0] < 1e-3 * e2, (e2, e3[0], e4)
