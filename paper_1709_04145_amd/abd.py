@@ -166,9 +166,11 @@ class Model:
     # ----------------------------------------------------------------- calls
     def step(self, q_hist: torch.Tensor, q_out: torch.Tensor, opts: StepOptions,
              tau: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None, stream=None):
-        """Enqueue one time step.  q_hist = [q_{k-1}; q_k] (2*n_dofs contiguous)."""
+        """Enqueue one time step.  q_hist = [q_{k-1}; q_k] (2*n_dofs contiguous); for
+        order_K > 2, q_hist = [q_{k-1+alpha_{K-2}}; q_k] and q_out receives the K-1
+        unknown configurations ([K-1, n_dofs], the last one is q_{k+1})."""
         _dev_f64(q_hist, 2 * self.n_dofs, "q_hist")
-        _dev_f64(q_out, self.n_dofs, "q_out")
+        _dev_f64(q_out, (opts.order_K - 1) * self.n_dofs, "q_out")
         if tau is not None:
             _dev_f64(tau, self.n_dofs, "tau")
         if stats is not None and (not stats.is_cuda or stats.numel() * stats.element_size() < 32 * self.n_models):
@@ -185,17 +187,21 @@ class Model:
         raw = stats.detach().cpu().numpy().reshape(-1).view(np.uint8)[:32 * n_models]
         return raw.view(STATS_DTYPE).copy()
 
-    def objective_grad(self, q, q_hist, dt, tau=None, precision=FP64, stream=None):
-        _dev_f64(q, self.n_dofs, "q")
+    def objective_grad(self, q, q_hist, dt, tau=None, precision=FP64, order_K=2, stream=None):
+        """Objective per model and gradient.  order_K > 2: Eq. EQHOC with q the K-1
+        unknown configurations ([K-1, n_dofs]); the gradient has the same shape."""
+        U = order_K - 1
+        _dev_f64(q, U * self.n_dofs, "q")
         _dev_f64(q_hist, 2 * self.n_dofs, "q_hist")
         if tau is not None:
             _dev_f64(tau, self.n_dofs, "tau")
         E = torch.zeros(max(1, self.n_models), dtype=torch.float64, device="cuda")
-        g = torch.zeros(max(1, self.n_dofs), dtype=torch.float64, device="cuda")
-        o = StepOptions(dt=dt, precision=precision).c()
+        g = torch.zeros(max(1, U * self.n_dofs), dtype=torch.float64, device="cuda")
+        o = StepOptions(dt=dt, precision=precision, order_K=order_K).c()
         _check(load().abd_objective_grad(self._h, C.byref(o), _ptr(q), _ptr(q_hist), _ptr(tau), _ptr(E),
                                          _ptr(g), _stream(stream)))
-        return E[:self.n_models], g[:self.n_dofs]
+        g = g[:U * self.n_dofs]
+        return E[:self.n_models], (g if order_K == 2 else g.view(U, self.n_dofs))
 
     def hvp(self, q, q_hist, v, dt, stream=None):
         """Hessian-vector product of the step objective at q (float64)."""
@@ -238,11 +244,16 @@ class Model:
         """Enqueue `steps` time steps in one launch (abd_rollout).
 
         q_init = [q_{-1}; q_0] (2*n_dofs); torque [steps, n_dofs] or None.
-        Returns (q_traj [steps, n_dofs] = q_1..q_steps, stats buffer [steps*n_models] or None)."""
+        Returns (q_traj [steps, n_dofs] = q_1..q_steps, stats buffer [steps*n_models] or None).
+        order_K > 2: q_init = [q_{-1+alpha_{K-2}}; q_0] and q_traj is [steps, K-1, n_dofs]
+        (every step's unknown configurations)."""
         n = self.n_dofs
+        U = opts.order_K - 1
         _dev_f64(q_init, 2 * n, "q_init")
         if q_traj is None:
-            q_traj = torch.empty((max(1, steps), n), dtype=torch.float64, device="cuda")
+            shape = (max(1, steps), n) if U == 1 else (max(1, steps), U, n)
+            q_traj = torch.empty(shape, dtype=torch.float64, device="cuda")
+        _dev_f64(q_traj, max(1, steps) * U * n, "q_traj")
         if torque is not None:
             _dev_f64(torque, steps * n, "torque")
         if stats is not None and stats.numel() * stats.element_size() < 32 * self.n_models * steps:

@@ -1608,6 +1608,438 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
   }
 }
 
+// ------------------------------------------ high-order collocation (K>2) --
+// Sec. 4, Eq. HOC / Eq. EQHOC for one-wave models.  The K-1 unknown
+// configurations q_u of a step sit in registers of the lane that owns the frame
+// (U = K-1 values per lane).  With the known seed part
+// Bk_u = w_u0 A(q_prev) + w_u1 A(q_k) (per step) and the poses A_a = A(q_a):
+//   seed      G_u = (Bk_u + sum_a w_u,2+a A_a) M - dt^2 g (M e4)^T
+//   residual  rho_u = adjoint of G_u at q_u (- dt^2 tau)          [= dt^2 r_u]
+//   objective E = sum_u |rho_u|^2
+//   gradient  dE/dq_a = 2 (T_a + C_a), where, with dA_u the tangent poses at
+//             q_u along rho_u,
+//             T_a = derivative of the adjoint of the FIXED seed G_a at q_a along
+//                   rho_a (the second derivatives of the poses, S(q_a; G_a) rho_a),
+//             C_a = adjoint at q_a of the seed sum_u w_u,2+a dA_u M
+//                   (the mixed second derivatives, C(q_u, q_a)^T rho_u).
+template <int U>
+struct HocArgs {
+  DevModel d;
+  double dt2, tol;
+  int m, max_iter, max_ls, precond, n_steps;
+  double w[U][U + 2];   // dt^2 Pddot(tau_{2+u}) = sum_p w[u][p] P_p over the K+1 points
+  double vscale;        // 1 / (tau_1 - tau_0): warm-start velocity from the known points
+  double tau_u[U];      // the unknown points (units of dt from t_k)
+  double minv[U][U];    // (W_uu^T W_uu)^-1, W_uu = weights among the unknown points
+  const double* q_prev; // q_{-1+alpha_{K-2}}
+  const double* q_curr; // q_0
+  const double* tau;    // [n_steps][n_dofs] or NULL
+  double* q_out;        // [n_steps][U][n_dofs]
+  abd_step_stats* stats;
+  double* Bk;           // scratch [n_dofs][U][12]
+};
+
+// Derivative along a tangent (dA, W) of the adjoint pass at poses A with a FIXED
+// seed G (K, F = its suffix sums at these poses):
+//   dk = sum_c dR[:,c] x G[:,c] + dt x G[:,3],  dF = 0,
+//   result_n = dw_n . (K_n - p_n x F_n) + w_n . (dK_n - dp_n x F_n).
+template <typename Sc>
+__device__ double adjoint_fixed_seed_tangent(Sc& sc, const Xf<double>& A, const double dA[12], const double W[3],
+                                             const double w[3], const double G[12], const double K[3],
+                                             const double F[3], bool valid) {
+  double dk[3] = {0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double dcol[3] = {dA[c], dA[4 + c], dA[8 + c]};
+    const double gc[3] = {G[c], G[4 + c], G[8 + c]};
+    double x[3];
+    cross3(dcol, gc, x);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dk[i] += x[i];
+  }
+  double dK6[6] = {valid ? dk[0] : 0.0, valid ? dk[1] : 0.0, valid ? dk[2] : 0.0, 0.0, 0.0, 0.0};
+  double ua = 0.0, ub = 0.0;
+  sc.suffix6_total2(dK6, ua, ub);
+  const double p[3] = {A.m[3], A.m[7], A.m[11]};
+  const double dp[3] = {dA[3], dA[7], dA[11]};
+  double dw[3], pF[3], dpF[3];
+  cross3(W, w, dw);
+  cross3(p, F, pF);
+  cross3(dp, F, dpF);
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r += dw[i] * (K[i] - pF[i]) + w[i] * (dK6[i] - dpF[i]);
+  return valid ? r : 0.0;
+}
+
+// One EQHOC evaluation (float64): E (wave-uniform) and the gradient g[U] of this lane.
+template <int U, typename Sc>
+__device__ double hoc_evaluate(Sc& sc, const HocArgs<U>& args, const FrameGeo& geo, int f, bool valid,
+                               const double q[U], double tau, double g[U]) {
+  const DevModel& d = args.d;
+  asm volatile("" ::: "memory");
+  double M[10];
+  const double* rec = d.fr64 + (size_t)f * 16;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) M[k] = valid ? rec[6 + k] : 0.0;
+  const double* Bk = args.Bk + (size_t)f * (12 * U);
+  const double gv[3] = {d.gx, d.gy, d.gz};
+  Xf<double> A[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) A[u] = fk_geo<double>(sc, geo, valid, q[u]);
+  // seeds, residuals and their suffix sums
+  double rho[U], KF[U][6];
+  double E = 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    double G[12];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          double bx = valid ? Bk[12 * u + 4 * r + x] : 0.0;
+#pragma unroll
+          for (int a = 0; a < U; ++a) bx += args.w[u][2 + a] * A[a].m[4 * r + x];
+          s += bx * M[sym4(x, c)];
+        }
+        G[4 * r + c] = s - args.dt2 * gv[r] * M[sym4(c, 3)];
+      }
+    double k[3] = {0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double col[3] = {A[u].m[c], A[u].m[4 + c], A[u].m[8 + c]};
+      const double gc[3] = {G[c], G[4 + c], G[8 + c]};
+      double x[3];
+      cross3(col, gc, x);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) k[i] += x[i];
+    }
+    KF[u][0] = valid ? k[0] : 0.0; KF[u][1] = valid ? k[1] : 0.0; KF[u][2] = valid ? k[2] : 0.0;
+    KF[u][3] = valid ? G[3] : 0.0; KF[u][4] = valid ? G[7] : 0.0; KF[u][5] = valid ? G[11] : 0.0;
+    double ua = 0.0, ub = 0.0;
+    sc.suffix6_total2(KF[u], ua, ub);
+    double w[3], pF[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) w[i] = A[u].m[4 * i] * geo.a[0] + A[u].m[4 * i + 1] * geo.a[1] + A[u].m[4 * i + 2] * geo.a[2];
+    const double p[3] = {A[u].m[3], A[u].m[7], A[u].m[11]};
+    const double F[3] = {KF[u][3], KF[u][4], KF[u][5]};
+    cross3(p, F, pF);
+    const double r = w[0] * (KF[u][0] - pF[0]) + w[1] * (KF[u][1] - pF[1]) + w[2] * (KF[u][2] - pF[2]);
+    rho[u] = valid ? r - args.dt2 * tau : 0.0;
+    E += rho[u] * rho[u];
+  }
+  E = sc.sum(E);
+  // tangents along the residuals; fixed-seed terms; mixed-seed accumulation
+  double S[U][12];
+#pragma unroll
+  for (int a = 0; a < U; ++a)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) S[a][i] = 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    double dA[12], W[3], w[3];
+    tangent_pose(sc, A[u], geo.a, valid, rho[u], dA, W, w);
+    double G[12];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          double bx = valid ? Bk[12 * u + 4 * r + x] : 0.0;
+#pragma unroll
+          for (int a = 0; a < U; ++a) bx += args.w[u][2 + a] * A[a].m[4 * r + x];
+          s += bx * M[sym4(x, c)];
+        }
+        G[4 * r + c] = s - args.dt2 * gv[r] * M[sym4(c, 3)];
+      }
+    const double K3[3] = {KF[u][0], KF[u][1], KF[u][2]}, F3[3] = {KF[u][3], KF[u][4], KF[u][5]};
+    g[u] = adjoint_fixed_seed_tangent(sc, A[u], dA, W, w, G, K3, F3, valid);
+    // dA_u M, accumulated into the mixed seeds of every unknown a
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) s += dA[4 * r + x] * M[sym4(x, c)];
+#pragma unroll
+        for (int a = 0; a < U; ++a) S[a][4 * r + c] += args.w[u][2 + a] * s;
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < U; ++a) g[a] = 2.0 * (g[a] + adjoint_of_seed(sc, A[a], S[a], geo.a, valid));
+  return E;
+}
+
+template <int U>
+__global__ void __launch_bounds__(kWave, 1) k_rollout_hoc(HocArgs<U> args) {
+  __shared__ ModelLds L;
+  extern __shared__ double pairs[];  // s ring [m][U][64], then y ring
+  const DevModel& d = args.d;
+  const int n = d.n_dofs;
+  const int lane = threadIdx.x;
+  const int model = blockIdx.x;
+  if (model >= d.n_models) return;
+  WaveScan ws;
+  const int f0 = d.f0[model];
+  const int nf = d.f0[model + 1] - f0;
+  const bool valid = lane < nf;
+  const int f = f0 + (valid ? lane : 0);
+  const bool use_aba = args.precond == ABD_PRECOND_INERTIA;
+  double* Hi = d.hinv + d.hoff[model];
+  const FrameGeo geo = load_geo(d, f, valid);
+  const double eps_w = 1.1102230246251565e-16;
+  const double c1 = 1e-4, dlt = 0.1;
+  double qprev = valid ? args.q_prev[f] : 0.0;
+  double qk = valid ? args.q_curr[f] : 0.0;
+  double* sp = pairs + lane;                   // s of slot k, unknown u: sp[(k * U + u) * kWave]
+  double* yp = pairs + args.m * U * kWave + lane;
+  for (int step = 0; step < args.n_steps; ++step) {
+    double q[U], g[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u] = valid ? qk + args.tau_u[u] * args.vscale * (qk - qprev) : 0.0;
+    const double tau = (valid && args.tau) ? args.tau[(size_t)step * n + f] : 0.0;
+    int iters = 0, evals = 0, flag = 0, count = 0, head = 0;
+    double E = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0;
+    bool reset = false;
+    if (nf == 0) {
+      flag = ABD_FLAG_CONVERGED;
+    } else {
+      // known seed parts and the preconditioner at q_k
+      {
+        const Xf<double> Ap = fk_geo<double>(ws, geo, valid, qprev);
+        const Xf<double> Ak = fk_geo<double>(ws, geo, valid, qk);
+        if (valid)
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+              args.Bk[(size_t)f * (12 * U) + 12 * u + k] = args.w[u][0] * Ap.m[k] + args.w[u][1] * Ak.m[k];
+      }
+      if (use_aba) {
+        step_setup(ws, d, L.inert[lane], L.tab[lane], geo, f, valid, qprev, qk, qk, true);
+        __syncthreads();
+        if (lane == 0) aba_setup(&L.inert[0][0], L.tab, nf);
+        __syncthreads();
+        aba_inverse(L.tab, nf, lane, Hi);
+      }
+      E = hoc_evaluate<U>(ws, args, geo, f, valid, q, tau, g);
+      ++evals;
+      bool fin = isfinite(E);
+#pragma unroll
+      for (int u = 0; u < U; ++u) fin = fin && ws.all_finite(g[u]);
+      if (!fin) {
+        flag = ABD_FLAG_NONFINITE;
+      } else {
+        double gg = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) gg += g[u] * g[u];
+        g0 = uniform(sqrt(ws.sum(gg)));
+        gn = g0;
+        if (g0 == 0.0) flag = ABD_FLAG_CONVERGED;
+        else if (args.max_iter <= 0) flag = ABD_FLAG_MAX_ITER;
+      }
+      while (flag == 0) {
+        if (reset) count = 0;
+        // ---- two-loop recursion, newest pair first
+        double qv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) qv[u] = g[u];
+        for (int k = 0; k < count; ++k) {
+          const int slot = (head - k + args.m) % args.m;
+          double sq = 0.0;
+#pragma unroll
+          for (int u = 0; u < U; ++u) sq += (valid ? sp[(slot * U + u) * kWave] : 0.0) * qv[u];
+          const double a_k = uniform(L.rho[k] * ws.sum(sq));
+          if (lane == 0) L.alp[k] = a_k;
+#pragma unroll
+          for (int u = 0; u < U; ++u) qv[u] -= a_k * (valid ? yp[(slot * U + u) * kWave] : 0.0);
+        }
+        // ---- initial inverse Hessian: (W^T W)^-1 (x) H_q^-2, or gamma I
+        double r[U];
+        if (use_aba) {
+          double y[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) y[u] = apply_inverse(Hi, nf, lane, apply_inverse(Hi, nf, lane, qv[u]));
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            double t = 0.0;
+#pragma unroll
+            for (int a = 0; a < U; ++a) t += args.minv[u][a] * y[a];
+            r[u] = t;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; ++u) r[u] = (count > 0 ? gam : 1.0) * qv[u];
+        }
+        // ---- oldest pair first
+        for (int k = count - 1; k >= 0; --k) {
+          const int slot = (head - k + args.m) % args.m;
+          double yr = 0.0;
+#pragma unroll
+          for (int u = 0; u < U; ++u) yr += (valid ? yp[(slot * U + u) * kWave] : 0.0) * r[u];
+          const double b = uniform(L.rho[k] * ws.sum(yr));
+#pragma unroll
+          for (int u = 0; u < U; ++u) r[u] += (L.alp[k] - b) * (valid ? sp[(slot * U + u) * kWave] : 0.0);
+        }
+        double dir[U], gdl = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          dir[u] = valid ? -r[u] : 0.0;
+          gdl += g[u] * dir[u];
+        }
+        const double gd = uniform(ws.sum(gdl));
+        if (!(gd < 0.0)) {
+          if (!reset && count > 0) {
+            reset = true;
+            continue;
+          }
+          flag = ABD_FLAG_LS_FLOOR;
+          break;
+        }
+        reset = false;
+        double alpha = 1.0, Et = 0.0, qt[U], gt[U];
+        bool ok = false;
+        for (int ls = 0; ls < args.max_ls; ++ls) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) qt[u] = q[u] + alpha * dir[u];
+          Et = hoc_evaluate<U>(ws, args, geo, f, valid, qt, tau, gt);
+          ++evals;
+          bool fin = isfinite(Et);
+#pragma unroll
+          for (int u = 0; u < U; ++u) fin = fin && ws.all_finite(gt[u]);
+          if (fin) {
+            if (Et <= E + c1 * alpha * gd) {
+              ok = true;
+            } else if (fabs(Et - E) <= 10.0 * eps_w * Et) {
+              double gtdl = 0.0;
+#pragma unroll
+              for (int u = 0; u < U; ++u) gtdl += gt[u] * dir[u];
+              if (ws.sum(gtdl) <= (2.0 * dlt - 1.0) * gd) ok = true;
+            }
+          }
+          if (ok) break;
+          alpha *= 0.5;
+        }
+        if (!ok) {
+          flag = ABD_FLAG_LS_FLOOR;
+          break;
+        }
+        double syl = 0.0, ssl = 0.0, yyl = 0.0, ggl = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double sv = qt[u] - q[u], yv = gt[u] - g[u];
+          syl += sv * yv;
+          ssl += sv * sv;
+          yyl += yv * yv;
+          ggl += gt[u] * gt[u];
+        }
+        ws.sum2(syl, ssl);
+        ws.sum2(yyl, ggl);
+        if (syl > 1e-12 * sqrt(ssl) * sqrt(yyl)) {
+          if (lane == 0) {
+            for (int k = args.m - 1; k > 0; --k) L.rho[k] = L.rho[k - 1];
+            L.rho[0] = 1.0 / syl;
+          }
+          gam = uniform(syl / yyl);
+          head = count == 0 ? 0 : (head + 1) % args.m;
+          if (valid)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              sp[(head * U + u) * kWave] = qt[u] - q[u];
+              yp[(head * U + u) * kWave] = gt[u] - g[u];
+            }
+          if (count < args.m) ++count;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          q[u] = qt[u];
+          g[u] = gt[u];
+        }
+        E = Et;
+        ++iters;
+        gn = uniform(sqrt(ggl));
+        if (gn <= args.tol * g0) flag = ABD_FLAG_CONVERGED;
+        else if (iters >= args.max_iter) flag = ABD_FLAG_MAX_ITER;
+      }
+    }
+    if (valid)
+#pragma unroll
+      for (int u = 0; u < U; ++u) args.q_out[((size_t)step * U + u) * n + f] = q[u];
+    if (args.stats && lane == 0) {
+      abd_step_stats st;
+      st.iterations = iters;
+      st.evaluations = evals;
+      st.flag = flag;
+      st.f32_iterations = 0;
+      st.grad_norm = gn;
+      st.energy = E;
+      args.stats[(size_t)step * d.n_models + model] = st;
+    }
+    qprev = valid ? q[U - 2] : 0.0;
+    qk = valid ? q[U - 1] : 0.0;
+  }
+}
+
+struct HocObjArgs {
+  DevModel d;
+  double dt2;
+  double w[3][5];
+  const double* q_prev;
+  const double* q_curr;
+  const double* q;     // [U][n]
+  const double* tau;
+  double* E;
+  double* grad;        // [U][n] or NULL
+  double* Bk;
+};
+
+template <int U>
+__global__ void __launch_bounds__(kWave) k_hoc_objective(HocObjArgs a) {
+  const DevModel& d = a.d;
+  const int model = blockIdx.x, lane = threadIdx.x;
+  const int f0 = d.f0[model], nf = d.f0[model + 1] - f0;
+  if (nf == 0) {
+    if (lane == 0) a.E[model] = 0.0;
+    return;
+  }
+  const bool valid = lane < nf;
+  const int f = f0 + (valid ? lane : 0);
+  const int n = d.n_dofs;
+  WaveScan ws;
+  const FrameGeo geo = load_geo(d, f, valid);
+  HocArgs<U> h;
+  h.d = d;
+  h.dt2 = a.dt2;
+  for (int u = 0; u < U; ++u)
+    for (int p = 0; p < U + 2; ++p) h.w[u][p] = a.w[u][p];
+  h.Bk = a.Bk;
+  {
+    const Xf<double> Ap = fk_geo<double>(ws, geo, valid, valid ? a.q_prev[f] : 0.0);
+    const Xf<double> Ak = fk_geo<double>(ws, geo, valid, valid ? a.q_curr[f] : 0.0);
+    if (valid)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+          a.Bk[(size_t)f * (12 * U) + 12 * u + k] = h.w[u][0] * Ap.m[k] + h.w[u][1] * Ak.m[k];
+  }
+  double q[U], g[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) q[u] = valid ? a.q[(size_t)u * n + f] : 0.0;
+  const double tau = (valid && a.tau) ? a.tau[f] : 0.0;
+  const double E = hoc_evaluate<U>(ws, h, geo, f, valid, q, tau, g);
+  if (lane == 0) a.E[model] = E;
+  if (a.grad && valid)
+#pragma unroll
+    for (int u = 0; u < U; ++u) a.grad[(size_t)u * n + f] = g[u];
+}
+
 // ---------------------------------------------------- objective / poses --
 struct EvalArgs {
   DevModel d;
@@ -1681,6 +2113,7 @@ struct abd_model {
   long long* hoff = nullptr;
   double* hinv = nullptr;
   double* hist = nullptr;
+  double* Bk = nullptr;  // known seed parts of order-K steps, allocated on first use
   std::vector<void*> allocs;
 };
 
@@ -1767,7 +2200,8 @@ int check_opts(const abd_step_opts* o, bool for_step) {
   if (o->precision != ABD_FP64 && o->precision != ABD_MIXED)
     return fail(ABD_EINVAL, "precision must be ABD_FP64 or ABD_MIXED");
   if (!for_step) return ABD_OK;
-  if (o->order_K != 2) return fail(ABD_ENOTSUP, "order_K != 2 is not handled by this build");
+  if (o->order_K < 2) return fail(ABD_EINVAL, "order_K must be >= 2");
+  if (o->order_K > 4) return fail(ABD_ENOTSUP, "order_K > 4 is not handled by this build");
   if (o->lbfgs_m < 1 || o->lbfgs_m > 10) return fail(ABD_EINVAL, "lbfgs_m must be in 1..10");
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(ABD_EINVAL, "tol must be finite and >= 0");
   if (o->max_iter < 0) return fail(ABD_EINVAL, "max_iter must be >= 0");
@@ -1897,6 +2331,127 @@ int abd_model_info(const abd_model* m, int* n_models, int* n_links, int* n_dofs)
   return ABD_OK;
 }
 
+extern "C++" {
+// Collocation of order K = 3, 4 (Eq. HOC): the interior points are the roots of
+// the Legendre polynomial L_{K-2}(2 alpha - 1) (closed forms for K <= 4) and
+// alpha_{K-1} = 1; the K+1 points of a step are tau = (alpha_{K-2} - 1, 0,
+// alpha_1, ..., alpha_{K-1}).  The weights of the second derivative at an
+// unknown point x solve the moment conditions sum_j w_j tau_j^p = p (p-1) x^(p-2),
+// p = 0..K (exact for polynomials of degree <= K), by Gaussian elimination.
+static void hoc_collocation(int K, double* tau, double* w) {
+  double alpha[4] = {0, 0, 0, 0};
+  if (K == 3) {
+    alpha[1] = 0.5;
+  } else {
+    alpha[1] = 0.5 * (1.0 - 1.0 / std::sqrt(3.0));
+    alpha[2] = 0.5 * (1.0 + 1.0 / std::sqrt(3.0));
+  }
+  alpha[K - 1] = 1.0;
+  tau[0] = alpha[K - 2] - 1.0;
+  tau[1] = 0.0;
+  for (int u = 1; u <= K - 1; ++u) tau[1 + u] = alpha[u];
+  const int np = K + 1;
+  for (int u = 0; u < K - 1; ++u) {
+    const double x = tau[2 + u];
+    double a[5][6];
+    for (int p = 0; p < np; ++p) {
+      for (int j = 0; j < np; ++j) a[p][j] = std::pow(tau[j], p);
+      a[p][np] = p >= 2 ? p * (p - 1) * std::pow(x, p - 2) : 0.0;
+    }
+    for (int c = 0; c < np; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < np; ++r)
+        if (std::fabs(a[r][c]) > std::fabs(a[piv][c])) piv = r;
+      for (int k = 0; k <= np; ++k) std::swap(a[c][k], a[piv][k]);
+      for (int r = 0; r < np; ++r) {
+        if (r == c) continue;
+        const double fct = a[r][c] / a[c][c];
+        for (int k = c; k <= np; ++k) a[r][k] -= fct * a[c][k];
+      }
+    }
+    for (int j = 0; j < np; ++j) w[u * np + j] = a[j][np] / a[j][j];
+  }
+}
+
+template <int U>
+static int fill_hoc_args(abd_model* m, const abd_step_opts* o, HocArgs<U>& a) {
+  const int K = U + 1, np = K + 1;
+  double tau[5], w[3 * 5];
+  hoc_collocation(K, tau, w);
+  a.d = dev_view(m);
+  a.dt2 = o->dt * o->dt;
+  a.tol = o->tol;
+  a.m = o->lbfgs_m;
+  a.max_iter = o->max_iter;
+  a.max_ls = o->max_ls;
+  a.precond = o->precond;
+  for (int u = 0; u < U; ++u) {
+    for (int p = 0; p < np; ++p) a.w[u][p] = w[u * np + p];
+    a.tau_u[u] = tau[2 + u];
+  }
+  a.vscale = 1.0 / (tau[1] - tau[0]);
+  // (W_uu^T W_uu)^-1 by Gauss-Jordan
+  double g[U][2 * U];
+  for (int r = 0; r < U; ++r)
+    for (int c = 0; c < U; ++c) {
+      double t = 0.0;
+      for (int k = 0; k < U; ++k) t += w[k * np + 2 + r] * w[k * np + 2 + c];
+      g[r][c] = t;
+      g[r][U + c] = r == c ? 1.0 : 0.0;
+    }
+  for (int c = 0; c < U; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < U; ++r)
+      if (std::fabs(g[r][c]) > std::fabs(g[piv][c])) piv = r;
+    for (int k = 0; k < 2 * U; ++k) std::swap(g[c][k], g[piv][k]);
+    const double d = g[c][c];
+    for (int k = 0; k < 2 * U; ++k) g[c][k] /= d;
+    for (int r = 0; r < U; ++r) {
+      if (r == c) continue;
+      const double fct = g[r][c];
+      for (int k = 0; k < 2 * U; ++k) g[r][k] -= fct * g[c][k];
+    }
+  }
+  for (int r = 0; r < U; ++r)
+    for (int c = 0; c < U; ++c) a.minv[r][c] = g[r][U + c];
+  if (!m->Bk) {
+    int rc = alloc(m, &m->Bk, 36 * (size_t)m->n_dofs);
+    if (rc) return rc;
+  }
+  a.Bk = m->Bk;
+  return ABD_OK;
+}
+
+static int check_hoc(const abd_model* m, const abd_step_opts* o) {
+  if (m->max_frames > kMaxFrames)
+    return fail(ABD_ENOTSUP, "order_K > 2 handles models of at most 64 DOFs in this build");
+  if (o->precision != ABD_FP64) return fail(ABD_ENOTSUP, "order_K > 2 runs in ABD_FP64 only in this build");
+  return ABD_OK;
+}
+
+static int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
+                      const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream) {
+  int rc = check_hoc(m, o);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int U = o->order_K - 1;
+  const size_t pair_bytes = 2 * (size_t)o->lbfgs_m * U * kWave * sizeof(double);
+  if (U == 2) {
+    HocArgs<2> a;
+    if ((rc = fill_hoc_args<2>(m, o, a))) return rc;
+    a.n_steps = n_steps; a.q_prev = q_prev; a.q_curr = q_curr; a.tau = tau; a.q_out = q_out; a.stats = stats;
+    hipLaunchKernelGGL(k_rollout_hoc<2>, dim3(m->n_models), dim3(kWave), pair_bytes, s, a);
+  } else {
+    HocArgs<3> a;
+    if ((rc = fill_hoc_args<3>(m, o, a))) return rc;
+    a.n_steps = n_steps; a.q_prev = q_prev; a.q_curr = q_curr; a.tau = tau; a.q_out = q_out; a.stats = stats;
+    hipLaunchKernelGGL(k_rollout_hoc<3>, dim3(m->n_models), dim3(kWave), pair_bytes, s, a);
+  }
+  HIP_TRY(hipGetLastError());
+  return ABD_OK;
+}
+}  // extern "C++"
+
 // wavefronts per model workgroup: the power of two covering the longest model
 static int waves_for(int max_frames) {
   int nw = 1;
@@ -1952,9 +2507,11 @@ int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const d
   if (rc) return rc;
   if (m->n_models == 0) return ABD_OK;
   if (!q_hist || !q_out) return fail(ABD_EINVAL, "q_hist and q_out must not be NULL");
-  if (q_out < q_hist + 2 * (size_t)m->n_dofs && q_hist < q_out + m->n_dofs)
+  const size_t out_len = (size_t)(o->order_K - 1) * m->n_dofs;
+  if (q_out < q_hist + 2 * (size_t)m->n_dofs && q_hist < q_out + out_len)
     return fail(ABD_EINVAL, "q_out overlaps q_hist");
   if ((rc = check_device(m))) return rc;
+  if (o->order_K > 2) return launch_hoc(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
   return launch_rollout(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
 }
 
@@ -1968,9 +2525,10 @@ int abd_rollout(abd_model* m, const abd_step_opts* o, const double* q_init, cons
   if (m->n_models == 0 || n_steps == 0) return ABD_OK;
   if (!q_init || !q_traj) return fail(ABD_EINVAL, "q_init and q_traj must not be NULL");
   const size_t nd = m->n_dofs;
-  if (q_traj < q_init + 2 * nd && q_init < q_traj + (size_t)n_steps * nd)
+  if (q_traj < q_init + 2 * nd && q_init < q_traj + (size_t)n_steps * (o->order_K - 1) * nd)
     return fail(ABD_EINVAL, "q_traj overlaps q_init");
   if ((rc = check_device(m))) return rc;
+  if (o->order_K > 2) return launch_hoc(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
   return launch_rollout(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
 }
 
@@ -1983,6 +2541,35 @@ int abd_objective_grad(abd_model* m, const abd_step_opts* o, const double* q, co
   if (m->n_models == 0) return ABD_OK;
   if (!q || !q_hist || !E) return fail(ABD_EINVAL, "q, q_hist and E must not be NULL");
   if ((rc = check_device(m))) return rc;
+  if (o->order_K < 2) return fail(ABD_EINVAL, "order_K must be >= 2");
+  if (o->order_K > 4) return fail(ABD_ENOTSUP, "order_K > 4 is not handled by this build");
+  if (o->order_K > 2) {
+    if ((rc = check_hoc(m, o))) return rc;
+    const int U = o->order_K - 1;
+    HocObjArgs h;
+    HocArgs<3> tmp;
+    if ((rc = fill_hoc_args<3>(m, o, tmp))) return rc;  // allocates the scratch
+    double tau_pts[5], w[15];
+    hoc_collocation(o->order_K, tau_pts, w);
+    h.d = dev_view(m);
+    h.dt2 = o->dt * o->dt;
+    for (int u = 0; u < 3; ++u)
+      for (int p = 0; p < 5; ++p) h.w[u][p] = (u < U && p < U + 2) ? w[u * (U + 2) + p] : 0.0;
+    h.q_prev = q_hist;
+    h.q_curr = q_hist + m->n_dofs;
+    h.q = q;
+    h.tau = tau;
+    h.E = E;
+    h.grad = grad;
+    h.Bk = m->Bk;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (U == 2)
+      hipLaunchKernelGGL(k_hoc_objective<2>, dim3(m->n_models), dim3(kWave), 0, s, h);
+    else
+      hipLaunchKernelGGL(k_hoc_objective<3>, dim3(m->n_models), dim3(kWave), 0, s, h);
+    HIP_TRY(hipGetLastError());
+    return ABD_OK;
+  }
   EvalArgs a;
   a.d = dev_view(m);
   a.dt2 = o->dt * o->dt;

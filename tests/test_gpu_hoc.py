@@ -1,0 +1,106 @@
+"""High-order position-based collocation (Eq. HOC / Eq. EQHOC, K = 3, 4) on the
+GPU against the FP64 CPU oracle.
+
+  * objective and gradient: E is a sum of squared residuals that are themselves
+    cancelling sums, so E is compared to 1e-10 relative and the gradient to 1e-9
+    relative to its largest component;
+  * one step: both sides solve to a relative gradient tolerance of 1e-10; the
+    oracle's own results at 1e-10 and at its float64 floor differ by up to
+    1.3e-8 on these chains (the squared residual makes the problem worse
+    conditioned than Eq. EQ), so the bound is 1e-7 on all K-1 configurations;
+  * a rollout in one launch equals the loop of single steps bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.oracle import Oracle
+from paper_1709_04145_amd import abd
+from paper_1709_04145_amd import workloads as W
+from test_gpu_parity import cu, mixed_chains, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    abd.load()
+    yield
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(1e-300, float(np.max(np.abs(b))))) if a.size else 0.0
+
+
+@pytest.mark.parametrize("K", [3, 4])
+def test_eqhoc_objective_and_gradient(K):
+    d = mixed_chains(16, 30 + K, max_dofs=20)
+    say(f"eqhoc objective K={K} dofs={d.n_dofs}")
+    rng = np.random.default_rng(90 + K)
+    qp, qc = (rng.uniform(-1, 1, d.n_dofs) for _ in range(2))
+    qu = rng.uniform(-1, 1, (K - 1, d.n_dofs))
+    tau = rng.uniform(-1, 1, d.n_dofs)
+    dt = 0.03
+    E, g = Oracle(d).eqhoc_objective_grad(K, dt, qp, qc, qu, tau)
+    m = abd.Model(d)
+    Eg, gg = m.objective_grad(cu(qu.reshape(-1)), cu(np.concatenate([qp, qc])), dt, tau=cu(tau), order_K=K)
+    Eg, gg = Eg.cpu().numpy(), gg.cpu().numpy()
+    np.testing.assert_allclose(Eg, E, rtol=1e-10, atol=0)
+    do = d.dof_offset
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        assert _rel(gg[:, sl], g[:, sl]) <= 1e-9, (i, _rel(gg[:, sl], g[:, sl]))
+
+
+@pytest.mark.parametrize("K", [3, 4])
+def test_eqhoc_step_matches_oracle(K):
+    d = W.random_chain_models(8, 11, lo=4, hi=12)
+    rng = np.random.default_rng(5)
+    q0 = rng.uniform(-0.5, 0.5, d.n_dofs)
+    dt, tol = 0.01, 1e-10
+    say(f"eqhoc step K={K}")
+    ref, rst = Oracle(d).step_hoc(K, q0, q0, dt, tol=tol, max_iter=3000)
+    m = abd.Model(d)
+    out = torch.zeros((K - 1, d.n_dofs), dtype=torch.float64, device="cuda")
+    st = m.new_stats()
+    m.step(cu(np.concatenate([q0, q0])), out, abd.StepOptions(dt=dt, order_K=K, tol=tol, max_iter=3000), stats=st)
+    torch.cuda.synchronize()
+    st = m.read_stats(st, d.n_models)
+    assert np.all(st["flag"] == abd.FLAG_CONVERGED), st["flag"]
+    assert np.all(rst["flag"] == 1)
+    got = out.cpu().numpy()
+    err = float(np.max(np.abs(got - ref))) / max(1.0, float(np.max(np.abs(ref))))
+    assert err <= 1e-7, err
+
+
+def test_eqhoc_rollout_equals_step_loop_bitwise():
+    K = 4
+    d = W.random_chain_models(6, 12, lo=3, hi=10)
+    q0 = np.random.default_rng(6).uniform(-0.5, 0.5, d.n_dofs)
+    m = abd.Model(d)
+    opts = abd.StepOptions(dt=0.01, order_K=K, tol=1e-9, max_iter=2000)
+    steps = 3
+    traj, _ = m.rollout(torch.cat([cu(q0), cu(q0)]), steps, opts)
+    known = torch.cat([cu(q0), cu(q0)])
+    for k in range(steps):
+        out = torch.zeros((K - 1, d.n_dofs), dtype=torch.float64, device="cuda")
+        m.step(known, out, opts)
+        torch.cuda.synchronize()
+        assert torch.equal(out, traj[k]), k
+        known = torch.cat([out[K - 3], out[K - 2]]).contiguous()
+
+
+def test_eqhoc_unsupported_cases_are_rejected():
+    d = W.random_chain_models(2, 13, lo=3, hi=6)
+    m = abd.Model(d)
+    q = cu(np.zeros(d.n_dofs))
+    out = torch.zeros((3, d.n_dofs), dtype=torch.float64, device="cuda")
+    with pytest.raises(abd.AbdError) as e:
+        m.step(torch.cat([q, q]), out, abd.StepOptions(dt=0.01, order_K=4, precision=abd.MIXED))
+    assert e.value.code == abd.ABD_ENOTSUP
+    out5 = torch.zeros((4, d.n_dofs), dtype=torch.float64, device="cuda")
+    with pytest.raises(abd.AbdError) as e:
+        m.step(torch.cat([q, q]), out5, abd.StepOptions(dt=0.01, order_K=5))
+    assert e.value.code == abd.ABD_ENOTSUP

@@ -348,9 +348,15 @@ def test_invalid_options_rejected():
         with pytest.raises(abd.AbdError) as e:
             m.step(hist, out, abd.StepOptions(**bad))
         assert e.value.code == abd.ABD_EINVAL
+    out5 = torch.zeros(4 * d.n_dofs, dtype=torch.float64, device="cuda")
     with pytest.raises(abd.AbdError) as e:
-        m.step(hist, out, abd.StepOptions(dt=0.1, order_K=4))
+        m.step(hist, out5, abd.StepOptions(dt=0.1, order_K=5))
     assert e.value.code == abd.ABD_ENOTSUP
+    import ctypes
+    o1 = abd.StepOptions(dt=0.1, order_K=1).c()
+    rc = abd.load().abd_step(m._h, ctypes.byref(o1), ctypes.c_void_p(hist.data_ptr()), None,
+                             ctypes.c_void_p(out.data_ptr()), None, None)
+    assert rc == abd.ABD_EINVAL
 
 
 def test_rollout_captured_in_hip_graph_replays_exactly():
