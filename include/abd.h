@@ -76,7 +76,10 @@ typedef struct {
 
 typedef struct {
   double dt;         /* time step > 0 */
-  int order_K;       /* collocation order; this build: 2 */
+  int order_K;       /* collocation order K: 2 = Eq. EQ (one unknown configuration per
+                        step); 3, 4 = Eq. EQHOC with K-1 unknown configurations per
+                        step (float64 only, models of <= 64 DOFs); other values are
+                        rejected (EINVAL below 2, ENOTSUP above 4) */
   int lbfgs_m;       /* L-BFGS history length, 1..10 */
   double tol;        /* stop when |grad| <= tol * |grad at the warm start| */
   int max_iter;      /* L-BFGS iterations per step, >= 0 */
@@ -110,7 +113,15 @@ int abd_model_info(const abd_model* model, int* n_models, int* n_links, int* n_d
  *   q_hist : [2*n_dofs] = q_{k-1} followed by q_k
  *   tau    : [n_dofs] generalized joint forces held over the step, or NULL
  *   q_out  : [n_dofs] receives q_{k+1}; must not overlap q_hist
- *   stats  : [n_models] per-model outcome, or NULL */
+ *   stats  : [n_models] per-model outcome, or NULL
+ * Order K > 2 (Eq. HOC): the step has K-1 unknown configurations at the
+ * collocation points t_k + alpha_u dt (alpha_1..alpha_{K-2} the roots of the
+ * Legendre polynomial L_{K-2}(2 alpha - 1), alpha_{K-1} = 1).  Then q_hist =
+ * q_{k-1+alpha_{K-2}} followed by q_k, q_out is [(K-1)*n_dofs] (all unknown
+ * configurations, the last one is q_{k+1}), the objective is Eq. EQHOC (sum of
+ * squared residuals, each scaled by dt^2), the warm start extrapolates the known
+ * points at constant velocity, and the initial inverse Hessian is
+ * (W^T W)^-1 (x) H_q(q_k)^-2 (W: collocation weights among the unknown points). */
 int abd_step(abd_model* model, const abd_step_opts* opts, const double* q_hist,
              const double* tau, double* q_out, abd_step_stats* stats, void* stream);
 
@@ -122,7 +133,9 @@ int abd_step(abd_model* model, const abd_step_opts* opts, const double* q_hist,
  *   tau    : [n_steps*n_dofs] joint forces of every step, or NULL
  *   q_traj : [n_steps*n_dofs] receives q_1 .. q_{n_steps}; must not overlap q_init
  *   stats  : [n_steps*n_models] per-step outcome, or NULL
- * abd_step is the n_steps = 1 case. */
+ * abd_step is the n_steps = 1 case.  Order K > 2: q_init = q_{-1+alpha_{K-2}}
+ * followed by q_0, and q_traj is [n_steps][K-1][n_dofs] (every step's unknown
+ * configurations). */
 int abd_rollout(abd_model* model, const abd_step_opts* opts, const double* q_init,
                 const double* tau, double* q_traj, abd_step_stats* stats, int n_steps,
                 void* stream);
@@ -134,8 +147,10 @@ int abd_rollout(abd_model* model, const abd_step_opts* opts, const double* q_ini
  *   tau    : [n_dofs] or NULL
  *   E      : [n_models] objective per model
  *   grad   : [n_dofs] gradient, or NULL
- * opts->precision selects float64 or float32 kinematics; other fields but dt
- * are ignored. */
+ * opts->precision selects float64 or float32 kinematics; opts->order_K > 2
+ * evaluates Eq. EQHOC with q and grad of [(K-1)*n_dofs] (the unknown
+ * configurations) and q_hist = q_{k-1+alpha_{K-2}}, q_k; other fields but dt are
+ * ignored. */
 int abd_objective_grad(abd_model* model, const abd_step_opts* opts, const double* q,
                        const double* q_hist, const double* tau, double* E, double* grad,
                        void* stream);
