@@ -37,6 +37,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/abd.h"
@@ -345,6 +346,11 @@ struct DevModel {
                             // start (nf <= 64), else the frames' spatial inertias [nf][10]
   double* hist;             // models of more than 64 frames: [n_dofs][2*kMaxHist] L-BFGS
                             // pairs, s ring then y ring
+  // frames are stored in depth-first preorder of the links (the identity for chains)
+  const int* uidx;          // [n_dofs] index of the frame's DOF in the caller's vectors
+  const int* fpar;          // [n_dofs] parent frame within the model, -1 = world
+  const int* fend;          // [n_dofs] last frame below this one (within the model)
+  int jump_rounds;          // ceil(log2(deepest frame path)) of the batch
   double gx, gy, gz;
 };
 
@@ -518,6 +524,107 @@ struct BlockScan {
   }
 };
 
+// TreeScan<NW>: branched models.  Frames are stored in depth-first preorder,
+// so the frames below frame j form the contiguous range [j, end_j].
+//   * prefixes along the ancestor path (the rotation and translation parts of
+//     Alg. 1's forward pass) by pointer jumping through LDS: every frame keeps
+//     the partial result over its path up to a current ancestor and replaces it
+//     by the ancestor's partial result composed with its own, then jumps to the
+//     ancestor's ancestor (`rounds` = ceil(log2(depth)) rounds);
+//   * sums over the frames below (the adjoint pass) as differences of the
+//     preorder prefix sum: P(end_j) - P(j - 1);
+//   * model-wide reductions as in BlockScan.
+template <int NW>
+struct TreeScan : BlockScan<NW> {
+  double (*tq)[4];  // LDS [64 NW][4]: partial rotations, then prefix sums
+  double (*tv)[6];  // LDS [64 NW][6]
+  int* tanc;        // LDS [64 NW]: current ancestor
+  int j, parent, send, rounds;
+
+  template <typename R>
+  __device__ __forceinline__ Quat<R> prefix_quat(const Quat<R>& r) {
+    Quat<R> x = r;
+    int a = parent;
+    for (int k = 0; k < rounds; ++k) {
+      tq[j][0] = x.w; tq[j][1] = x.x; tq[j][2] = x.y; tq[j][3] = x.z;
+      tanc[j] = a;
+      __syncthreads();
+      if (a >= 0) {
+        const Quat<R> y{(R)tq[a][0], (R)tq[a][1], (R)tq[a][2], (R)tq[a][3]};
+        const int aa = tanc[a];
+        x = qmul(y, x);
+        a = aa;
+      }
+      __syncthreads();
+    }
+    return x;
+  }
+  template <typename R>
+  __device__ __forceinline__ Quat<R> parent_quat(const Quat<R>& incl) {
+    tq[j][0] = incl.w; tq[j][1] = incl.x; tq[j][2] = incl.y; tq[j][3] = incl.z;
+    __syncthreads();
+    Quat<R> p{R(1), R(0), R(0), R(0)};
+    if (parent >= 0) p = Quat<R>{(R)tq[parent][0], (R)tq[parent][1], (R)tq[parent][2], (R)tq[parent][3]};
+    __syncthreads();
+    return p;
+  }
+  template <typename R>
+  __device__ __forceinline__ void prefix_sum3(R v[3]) {
+    double x[3] = {v[0], v[1], v[2]};
+    int a = parent;
+    for (int k = 0; k < rounds; ++k) {
+      tv[j][0] = x[0]; tv[j][1] = x[1]; tv[j][2] = x[2];
+      tanc[j] = a;
+      __syncthreads();
+      if (a >= 0) {
+        const int aa = tanc[a];
+        x[0] += tv[a][0]; x[1] += tv[a][1]; x[2] += tv[a][2];
+        a = aa;
+      }
+      __syncthreads();
+    }
+    v[0] = (R)x[0]; v[1] = (R)x[1]; v[2] = (R)x[2];
+  }
+  __device__ __forceinline__ void suffix6_total2(double v[6], double& ta, double& tb) {
+    // inclusive preorder prefix of the 6 values (waves + carries), model totals of ta, tb
+    double pre[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pre[k] = wave_prefix_sum(v[k]);
+    wave_sum2(ta, tb);
+    double* a = this->next_area();
+    if (this->lane == 63) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) a[this->wave * 8 + k] = pre[k];
+      a[this->wave * 8 + 6] = ta;
+      a[this->wave * 8 + 7] = tb;
+    }
+    __syncthreads();
+    double before[6] = {0, 0, 0, 0, 0, 0};
+    ta = 0.0;
+    tb = 0.0;
+    for (int w = 0; w < NW; ++w) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (w < this->wave) before[k] += a[w * 8 + k];
+      ta += a[w * 8 + 6];
+      tb += a[w * 8 + 7];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tv[j][k] = before[k] + pre[k];
+    __syncthreads();
+    // sum over [j, end_j] = P(end_j) - P(j) + own
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = (tv[send][k] - tv[j][k]) + v[k];
+    __syncthreads();
+  }
+  __device__ __forceinline__ double suffix(double v) {
+    double w6[6] = {v, 0, 0, 0, 0, 0};
+    double ua = 0.0, ub = 0.0;
+    suffix6_total2(w6, ua, ub);
+    return w6[0];
+  }
+};
+
 // World pose A_j = [R_j | t_j] of every frame of this wave's model (Alg. 1
 // forward pass; frame j's joint is at its origin, offset o_j in the parent frame):
 //   R_j = R_{j-1} Rot(a_j, q_j)  -> prefix scan of hinge quaternions,
@@ -677,16 +784,23 @@ struct StepArgs {
 //          NW > 1 keeps it in the model's device scratch instead
 //   xb:    NW > 1: the vector swept by the recursion
 //   xch:   scan exchange areas of BlockScan
-template <int NW>
+//   branched models (TREE): pointer-jumping buffers of TreeScan (tq, tv, tanc),
+//   frame parents (tpar) and the sweep accumulators (acc)
+template <int NW, bool TREE = false>
 struct RollLds {
   double tab[kMaxFrames * NW][14];
   double inert[NW == 1 ? kMaxFrames : 1][10];
   double rho[kMaxHist];  // 1/(s_i.y_i), newest first
   double alp[kMaxHist];  // two-loop coefficients
-  double xb[NW == 1 ? 1 : kMaxFrames * NW];
+  double xb[(NW == 1 && !TREE) ? 1 : kMaxFrames * NW];
   double xch[2][NW][8];
+  double tq[TREE ? kMaxFrames * NW : 1][4];
+  double tv[TREE ? kMaxFrames * NW : 1][6];
+  double acc[TREE ? kMaxFrames * NW : 1][6];
+  int tanc[TREE ? kMaxFrames * NW : 1];
+  int tpar[TREE ? kMaxFrames * NW : 1];
 };
-using ModelLds = RollLds<1>;
+using ModelLds = RollLds<1, false>;
 
 // Articulated inertias at the warm start (once per step, one lane):
 //   I^A_f = I_f + P_{f+1},  U_f = I^A_f s_f,  D_f = s_f.U_f,
@@ -870,6 +984,93 @@ __device__ void aba_solve(const double (*tab)[14], double* xb, int nf) {
   }
 }
 
+// Branched models (one thread, frames in depth-first preorder, parent[f] < f):
+// the articulated inertias accumulate the children's P_c into the parent,
+//   I^A_f = I_f + sum_children P_c,  U_f = I^A_f s_f,  D_f = s_f.U_f,
+//   P_f = I^A_f - U_f U_f^T / D_f;
+// pacc [nf][21] (device scratch) holds the accumulated children's P.
+__device__ void aba_setup_tree(const double* inert, double (*tab)[14], const int* parent, double* pacc, int nf) {
+  for (int f = 0; f < nf; ++f)
+    for (int k = 0; k < 21; ++k) pacc[f * 21 + k] = 0.0;
+  for (int f = nf - 1; f >= 0; --f) {
+    double P[21], s[6], in[10];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) P[k] = pacc[f * 21 + k];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) in[k] = inert[f * 10 + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] = tab[f][k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) P[k] += in[k];
+    P[7] -= in[8]; P[8] += in[7]; P[9] += in[8]; P[11] -= in[6]; P[12] -= in[7]; P[13] += in[6];
+    P[15] += in[9]; P[18] += in[9]; P[20] += in[9];
+    double U[6];
+    U[0] = P[0] * s[0] + P[1] * s[1] + P[2] * s[2] + P[6] * s[3] + P[7] * s[4] + P[8] * s[5];
+    U[1] = P[1] * s[0] + P[3] * s[1] + P[4] * s[2] + P[9] * s[3] + P[10] * s[4] + P[11] * s[5];
+    U[2] = P[2] * s[0] + P[4] * s[1] + P[5] * s[2] + P[12] * s[3] + P[13] * s[4] + P[14] * s[5];
+    U[3] = P[6] * s[0] + P[9] * s[1] + P[12] * s[2] + P[15] * s[3] + P[16] * s[4] + P[17] * s[5];
+    U[4] = P[7] * s[0] + P[10] * s[1] + P[13] * s[2] + P[16] * s[3] + P[18] * s[4] + P[19] * s[5];
+    U[5] = P[8] * s[0] + P[11] * s[1] + P[14] * s[2] + P[17] * s[3] + P[19] * s[4] + P[20] * s[5];
+    const double D = (s[0] * U[0] + s[1] * U[1]) + (s[2] * U[2] + s[3] * U[3]) + (s[4] * U[4] + s[5] * U[5]);
+    const double iD = (D > 0.0) ? 1.0 / D : 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tab[f][6 + k] = U[k];
+    tab[f][12] = iD;
+    const int p = parent[f];
+    if (p >= 0) {
+      double V[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) V[k] = U[k] * iD;
+      P[0] -= U[0] * V[0]; P[1] -= U[0] * V[1]; P[2] -= U[0] * V[2];
+      P[3] -= U[1] * V[1]; P[4] -= U[1] * V[2]; P[5] -= U[2] * V[2];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) P[6 + 3 * r + c] -= U[r] * V[3 + c];
+      P[15] -= U[3] * V[3]; P[16] -= U[3] * V[4]; P[17] -= U[3] * V[5];
+      P[18] -= U[4] * V[4]; P[19] -= U[4] * V[5]; P[20] -= U[5] * V[5];
+#pragma unroll
+      for (int k = 0; k < 21; ++k) pacc[p * 21 + k] += P[k];
+    }
+  }
+}
+
+// x = H^{-1} b on a branched model (one thread, in place in xb): backward sweep
+// in reverse preorder u_f = b_f - s_f.p_f, p_parent += p_f + U_f u_f / D_f;
+// forward sweep in preorder x_f = (u_f - U_f.a_parent) / D_f, a_f = a_parent + s_f x_f.
+// acc [nf][6] (LDS) holds p, then a.
+__device__ void aba_solve_tree(const double (*tab)[14], double* xb, const int* parent, double (*acc)[6], int nf) {
+  for (int f = 0; f < nf; ++f)
+    for (int k = 0; k < 6; ++k) acc[f][k] = 0.0;
+  for (int f = nf - 1; f >= 0; --f) {
+    const double* t = tab[f];
+    double p[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] = acc[f][k];
+    const double sp = (t[0] * p[0] + t[1] * p[1]) + (t[2] * p[2] + t[3] * p[3]) + (t[4] * p[4] + t[5] * p[5]);
+    const double u = xb[f] - sp;
+    xb[f] = u;
+    const double w = u * t[12];
+    const int pa = parent[f];
+    if (pa >= 0)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[pa][k] += p[k] + t[6 + k] * w;
+  }
+  for (int f = 0; f < nf; ++f) {
+    const double* t = tab[f];
+    const int pa = parent[f];
+    double a[6] = {0, 0, 0, 0, 0, 0};
+    if (pa >= 0)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) a[k] = acc[pa][k];
+    const double Ua = (t[6] * a[0] + t[7] * a[1]) + (t[8] * a[2] + t[9] * a[3]) + (t[10] * a[4] + t[11] * a[5]);
+    const double x = (xb[f] - Ua) * t[12];
+    xb[f] = x;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[f][k] = a[k] + t[k] * x;
+  }
+}
+
 // Setup of one step for this wave's model (float64): the per-step constant
 // B = -2 A(q_k) + A(q_{k-1}) of every frame, and for the inertia preconditioner
 // the world spatial inertia (about the origin) and hinge motion at the warm start.
@@ -988,9 +1189,53 @@ struct ScanOf<1> {
   static __device__ __forceinline__ type make(double*, int, int) { return WaveScan{}; }
 };
 
-template <int NW, int PREC>
+// LDS of the kernels that only evaluate (objective, poses): the scan buffers.
+template <int NW, bool TREE>
+struct ScanLds {
+  double xch[2][NW][8];
+  double tq[TREE ? kMaxFrames * NW : 1][4];
+  double tv[TREE ? kMaxFrames * NW : 1][6];
+  int tanc[TREE ? kMaxFrames * NW : 1];
+  int tpar[TREE ? kMaxFrames * NW : 1];
+};
+
+// The scan policy of a model workgroup: DPP (+ LDS carries) for chains,
+// pointer jumping and preorder ranges for branched models.
+template <int NW, bool TREE>
+struct ModelScan {
+  using type = typename ScanOf<NW>::type;
+  template <typename Lds>
+  static __device__ __forceinline__ type make(Lds& L, const DevModel&, int wave, int lane, int, int, bool) {
+    return ScanOf<NW>::make(&L.xch[0][0][0], wave, lane);
+  }
+};
+template <int NW>
+struct ModelScan<NW, true> {
+  using type = TreeScan<NW>;
+  template <typename Lds>
+  static __device__ __forceinline__ type make(Lds& L, const DevModel& d, int wave, int lane, int j, int f,
+                                              bool valid) {
+    type t;
+    t.xch = &L.xch[0][0][0];
+    t.wave = wave;
+    t.lane = lane;
+    t.area = 0;
+    t.tq = L.tq;
+    t.tv = L.tv;
+    t.tanc = L.tanc;
+    t.j = j;
+    t.parent = valid ? d.fpar[f] : -1;
+    t.send = valid ? d.fend[f] : j;
+    t.rounds = d.jump_rounds;
+    L.tpar[j] = t.parent;
+    __syncthreads();
+    return t;
+  }
+};
+
+template <int NW, int PREC, bool TREE>
 __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD)) k_rollout(StepArgs args) {
-  __shared__ RollLds<NW> L;
+  __shared__ RollLds<NW, TREE> L;
   // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
   // y in [m, 2m), one double per lane per slot
   extern __shared__ double pairs[];
@@ -1002,20 +1247,23 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
   const int model = blockIdx.x;
   const bool has_model = model < d.n_models;
   if (!has_model) return;
-  typename ScanOf<NW>::type sc = ScanOf<NW>::make(&L.xch[0][0][0], wave, lane);
   const int f0 = d.f0[model];
   const int nf = d.f0[model + 1] - f0;
   const bool valid = j < nf;
   const int f = f0 + (valid ? j : 0);
+  typename ModelScan<NW, TREE>::type sc = ModelScan<NW, TREE>::make(L, d, wave, lane, j, f, valid);
+  const int io = TREE ? (valid ? d.uidx[f] : 0) : f;  // index of this frame's DOF in the caller's vectors
   const bool use_aba = args.precond == ABD_PRECOND_INERTIA;
-  double* Hi = d.hinv + d.hoff[model];  // one wave: explicit inverse; NW > 1: inertias [nf][10]
+  // one-wave chains: explicit inverse; otherwise inertias [nf][10] (then, for
+  // branched models, the recursion's accumulators [nf][21])
+  double* Hi = d.hinv + d.hoff[model];
   const FrameGeo geo = load_geo(d, f, valid);
   const double eps_w = PREC == ABD_MIXED ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
   const double c1 = 1e-4, dlt = 0.1;
 
   // q_{k-1} and q_k of the current step
-  double qkm1 = valid ? args.q_prev[f] : 0.0;
-  double qk = valid ? args.q_curr[f] : 0.0;
+  double qkm1 = valid ? args.q_prev[io] : 0.0;
+  double qk = valid ? args.q_curr[io] : 0.0;
   int step = 0;
   int state = args.n_steps > 0 ? kSetup : kDone;
 
@@ -1043,7 +1291,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
     if (state == kSetup) {
       PROF_T(t_s);
       q = valid ? 2.0 * qk - qkm1 : 0.0;  // warm start: constant-velocity extrapolation
-      tau = (valid && args.tau) ? args.tau[(size_t)step * n + f] : 0.0;
+      tau = (valid && args.tau) ? args.tau[(size_t)step * n + io] : 0.0;
       f32 = PREC == ABD_MIXED;
       iters = 0; evals = 0; flag = 0; f32_iters = 0; count = 0; head = 0; reset = false; gam = 1.0;
       if (nf == 0) {
@@ -1055,9 +1303,14 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
         if (use_aba) {
           if (NW > 1) __threadfence_block();  // inertias go through device memory
           __syncthreads();
-          if (lead) aba_setup(NW == 1 ? &L.inert[0][0] : Hi, L.tab, nf);
+          if (lead) {
+            if (TREE)
+              aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
+            else
+              aba_setup(NW == 1 ? &L.inert[0][0] : Hi, L.tab, nf);
+          }
           __syncthreads();
-          if (NW == 1) aba_inverse(L.tab, nf, lane, Hi);
+          if (NW == 1 && !TREE) aba_inverse(L.tab, nf, lane, Hi);
         }
         PROF_ADD(0, t_s);
         const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(sc, d, geo, f, valid, q, tau, args.dt2)
@@ -1107,12 +1360,17 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
       double r;
       if (!use_aba) {
         r = (count > 0 ? gam : 1.0) * qv;
-      } else if (NW == 1) {
+      } else if (NW == 1 && !TREE) {
         r = apply_inverse(Hi, nf, lane, qv);
       } else {
         L.xb[j] = valid ? qv : 0.0;
         __syncthreads();
-        if (lead) aba_solve(L.tab, L.xb, nf);
+        if (lead) {
+          if (TREE)
+            aba_solve_tree(L.tab, L.xb, L.tpar, L.acc, nf);
+          else
+            aba_solve(L.tab, L.xb, nf);
+        }
         __syncthreads();
         r = valid ? L.xb[j] : 0.0;
       }
@@ -1247,7 +1505,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
 #endif
     }
     if (step_done) {
-      if (valid) args.q_out[(size_t)step * n + f] = q;
+      if (valid) args.q_out[(size_t)step * n + io] = q;
       if (args.stats && lead) {
         abd_step_stats st;
         st.iterations = iters;
@@ -2053,9 +2311,9 @@ struct EvalArgs {
   double* grad;
 };
 
-template <int NW>
+template <int NW, bool TREE>
 __global__ void __launch_bounds__(NW* kWave) k_objective_grad(EvalArgs a) {
-  __shared__ double xch[2][NW][8];
+  __shared__ ScanLds<NW, TREE> L;
   const DevModel& d = a.d;
   const int model = blockIdx.x, j = threadIdx.x;
   const int f0 = d.f0[model], nf = d.f0[model + 1] - f0;
@@ -2065,29 +2323,31 @@ __global__ void __launch_bounds__(NW* kWave) k_objective_grad(EvalArgs a) {
     if (j == 0) a.E[model] = 0.0;
     return;
   }
-  typename ScanOf<NW>::type sc = ScanOf<NW>::make(&xch[0][0][0], j / kWave, j % kWave);
-  const double qkm1 = valid ? a.q_prev[f] : 0.0, qk = valid ? a.q_curr[f] : 0.0;
+  typename ModelScan<NW, TREE>::type sc = ModelScan<NW, TREE>::make(L, d, j / kWave, j % kWave, j, f, valid);
+  const int io = TREE ? (valid ? d.uidx[f] : 0) : f;
+  const double qkm1 = valid ? a.q_prev[io] : 0.0, qk = valid ? a.q_curr[io] : 0.0;
   const FrameGeo geo = load_geo(d, f, valid);
   write_B(sc, d, geo, f, valid, qkm1, qk);
   // the B rows of this thread were written by this thread: no barrier needed
-  const double q = valid ? a.q[f] : 0.0;
-  const double tau = (valid && a.tau) ? a.tau[f] : 0.0;
+  const double q = valid ? a.q[io] : 0.0;
+  const double tau = (valid && a.tau) ? a.tau[io] : 0.0;
   const EvalResult r = a.precision == ABD_MIXED ? evaluate<float>(sc, d, geo, f, valid, q, tau, a.dt2)
                                                 : evaluate<double>(sc, d, geo, f, valid, q, tau, a.dt2);
   if (j == 0) a.E[model] = r.E;
-  if (a.grad && valid) a.grad[f] = r.g;
+  if (a.grad && valid) a.grad[io] = r.g;
 }
 
-template <int NW>
+template <int NW, bool TREE>
 __global__ void __launch_bounds__(NW* kWave) k_poses(DevModel d, const double* q, double* poses) {
-  __shared__ double xch[2][NW][8];
+  __shared__ ScanLds<NW, TREE> L;
   const int model = blockIdx.x, j = threadIdx.x;
   const int f0 = d.f0[model], nf = d.f0[model + 1] - f0;
   if (nf == 0) return;
   const bool valid = j < nf;
   const int f = f0 + (valid ? j : 0);
-  typename ScanOf<NW>::type sc = ScanOf<NW>::make(&xch[0][0][0], j / kWave, j % kWave);
-  const Xf<double> A = fk_geo<double>(sc, load_geo(d, f, valid), valid, valid ? q[f] : 0.0);
+  typename ModelScan<NW, TREE>::type sc = ModelScan<NW, TREE>::make(L, d, j / kWave, j % kWave, j, f, valid);
+  const int io = TREE ? (valid ? d.uidx[f] : 0) : f;
+  const Xf<double> A = fk_geo<double>(sc, load_geo(d, f, valid), valid, valid ? q[io] : 0.0);
   if (valid) {
     const int l = d.pose_link[f];
     if (l >= 0)
@@ -2101,7 +2361,8 @@ __global__ void __launch_bounds__(NW* kWave) k_poses(DevModel d, const double* q
 // =================================================================== host ==
 struct abd_model {
   int device = 0;
-  int n_models = 0, n_links = 0, n_dofs = 0, max_frames = 0;
+  int n_models = 0, n_links = 0, n_dofs = 0, max_frames = 0, jump_rounds = 0;
+  bool tree = false;
   double g[3] = {0, 0, 0};
   // device buffers
   int* f0 = nullptr;
@@ -2114,6 +2375,9 @@ struct abd_model {
   double* hinv = nullptr;
   double* hist = nullptr;
   double* Bk = nullptr;  // known seed parts of order-K steps, allocated on first use
+  int* uidx = nullptr;
+  int* fpar = nullptr;
+  int* fend = nullptr;
   std::vector<void*> allocs;
 };
 
@@ -2183,6 +2447,10 @@ DevModel dev_view(const abd_model* m) {
   d.hoff = m->hoff;
   d.hinv = m->hinv;
   d.hist = m->hist;
+  d.uidx = m->uidx;
+  d.fpar = m->fpar;
+  d.fend = m->fend;
+  d.jump_rounds = m->jump_rounds;
   d.gx = m->g[0]; d.gy = m->g[1]; d.gz = m->g[2];
   return d;
 }
@@ -2282,15 +2550,71 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
       pose_link[d0 + k - 1] = l;
     }
   }
-  if (!chain) return fail(ABD_ENOTSUP, "branched trees are not handled by this build (serial chains only)");
   if (max_frames > kMaxFrames * kMaxWaves)
     return fail(ABD_ENOTSUP, "models with more than 1024 DOFs are not handled by this build");
+  if (!chain && max_frames > 4 * kMaxFrames)
+    return fail(ABD_ENOTSUP, "branched models of more than 256 DOFs are not handled by this build");
+  // Internal frame order: depth-first preorder of each model's links (children
+  // in index order), the frames of a link consecutive, so that the frames below
+  // any frame form a contiguous range.  For chains this is the caller's order.
+  std::vector<int> uidx(nd), fpar(nd), fend(nd), fdepth(nd, 0);
+  int max_depth = 1;
+  for (int i = 0; i < nm; ++i) {
+    const int lo = desc->link_offset[i], hi = desc->link_offset[i + 1], nlk = hi - lo;
+    std::vector<std::vector<int>> kids(nlk);
+    std::vector<int> stack, first(nlk), last(nlk), subend(nlk);
+    for (int l = nlk - 1; l >= 0; --l) {
+      const int p = desc->parent[lo + l];
+      if (p < 0) stack.push_back(l);
+      else kids[p].push_back(l);
+    }
+    for (auto& k : kids) std::reverse(k.begin(), k.end());  // pushed in reverse: pop in index order
+    std::vector<int> order;
+    while (!stack.empty()) {
+      const int l = stack.back();
+      stack.pop_back();
+      order.push_back(l);
+      for (int c : kids[l]) stack.push_back(c);
+    }
+    int pos = f0[i];
+    for (int l : order) {
+      const int k = desc->dofs_per_link[lo + l], p = desc->parent[lo + l];
+      first[l] = pos;
+      for (int jj = 0; jj < k; ++jj, ++pos) {
+        uidx[pos] = link_dof[lo + l] + jj;
+        fpar[pos] = jj > 0 ? pos - 1 - f0[i] : (p < 0 ? -1 : last[p] - f0[i]);
+        fdepth[pos] = (fpar[pos] < 0 ? 0 : fdepth[f0[i] + fpar[pos]]) + 1;
+        max_depth = std::max(max_depth, fdepth[pos]);
+      }
+      last[l] = pos - 1;
+    }
+    for (int t = (int)order.size() - 1; t >= 0; --t) {
+      const int l = order[t];
+      subend[l] = last[l];
+      for (int c : kids[l]) subend[l] = std::max(subend[l], subend[c]);
+      for (int fr = first[l]; fr <= last[l]; ++fr) fend[fr] = subend[l] - f0[i];
+    }
+  }
+  int jump_rounds = 0;
+  while ((1 << jump_rounds) < max_depth) ++jump_rounds;
+  // per-frame records in internal order
+  {
+    std::vector<double> r(fr64.size());
+    std::vector<int> pl(nd);
+    for (int fr = 0; fr < nd; ++fr) {
+      std::copy(fr64.begin() + 16 * (size_t)uidx[fr], fr64.begin() + 16 * (size_t)uidx[fr] + 16, r.begin() + 16 * (size_t)fr);
+      pl[fr] = pose_link[uidx[fr]];
+    }
+    fr64.swap(r);
+    pose_link.swap(pl);
+  }
   // per-model preconditioner scratch: the explicit inverse inertia (nf x nf) of
-  // a one-wave model, the per-frame spatial inertias (10 nf) of a longer one
+  // a one-wave chain, the per-frame spatial inertias (10 nf) of a longer chain,
+  // inertias and recursion accumulators (31 nf) of a branched model
   std::vector<long long> hoff(nm + 1, 0);
   for (int i = 0; i < nm; ++i) {
     const long long k = f0[i + 1] - f0[i];
-    hoff[i + 1] = hoff[i] + (k <= kMaxFrames ? k * k : 10 * k);
+    hoff[i + 1] = hoff[i] + (!chain ? 31 * k : k <= kMaxFrames ? k * k : 10 * k);
   }
 
   abd_model* m = new abd_model();
@@ -2299,13 +2623,16 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   m->n_links = nl;
   m->n_dofs = nd;
   m->max_frames = max_frames;
+  m->tree = !chain;
+  m->jump_rounds = jump_rounds;
   for (int k = 0; k < 3; ++k) m->g[k] = desc->gravity[k];
   std::vector<float> fr32(fr64.begin(), fr64.end());
   int rc = ABD_OK;
   if ((rc = upload(m, &m->f0, f0)) || (rc = upload(m, &m->pose_link, pose_link)) ||
       (rc = upload(m, &m->fr64, fr64)) || (rc = upload(m, &m->fr32, fr32)) ||
       (rc = alloc(m, &m->B64, 12 * (size_t)nd)) || (rc = alloc(m, &m->B32, 12 * (size_t)nd)) ||
-      (rc = upload(m, &m->hoff, hoff)) ||
+      (rc = upload(m, &m->hoff, hoff)) || (rc = upload(m, &m->uidx, uidx)) ||
+      (rc = upload(m, &m->fpar, fpar)) || (rc = upload(m, &m->fend, fend)) ||
       (rc = alloc(m, &m->hist, max_frames > kMaxFrames ? 2 * kMaxHist * (size_t)nd : 1)) ||
       (rc = alloc(m, &m->hinv, (size_t)hoff[nm]))) {
     free_model(m);
@@ -2423,8 +2750,8 @@ static int fill_hoc_args(abd_model* m, const abd_step_opts* o, HocArgs<U>& a) {
 }
 
 static int check_hoc(const abd_model* m, const abd_step_opts* o) {
-  if (m->max_frames > kMaxFrames)
-    return fail(ABD_ENOTSUP, "order_K > 2 handles models of at most 64 DOFs in this build");
+  if (m->max_frames > kMaxFrames || m->tree)
+    return fail(ABD_ENOTSUP, "order_K > 2 handles serial chains of at most 64 DOFs in this build");
   if (o->precision != ABD_FP64) return fail(ABD_ENOTSUP, "order_K > 2 runs in ABD_FP64 only in this build");
   return ABD_OK;
 }
@@ -2480,19 +2807,27 @@ static int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_
   const dim3 grid(m->n_models), block(nw * kWave);
   const size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * kWave * sizeof(double) : 0;
   const bool f64 = o->precision == ABD_FP64;
-#define ABD_LAUNCH(NW)                                                                      \
+#define ABD_LAUNCH(NW, TREE)                                                                \
   do {                                                                                      \
     if (f64)                                                                                \
-      hipLaunchKernelGGL((k_rollout<NW, ABD_FP64>), grid, block, pair_bytes, s, a);         \
+      hipLaunchKernelGGL((k_rollout<NW, ABD_FP64, TREE>), grid, block, pair_bytes, s, a);   \
     else                                                                                    \
-      hipLaunchKernelGGL((k_rollout<NW, ABD_MIXED>), grid, block, pair_bytes, s, a);        \
+      hipLaunchKernelGGL((k_rollout<NW, ABD_MIXED, TREE>), grid, block, pair_bytes, s, a);  \
   } while (0)
-  switch (nw) {
-    case 1: ABD_LAUNCH(1); break;
-    case 2: ABD_LAUNCH(2); break;
-    case 4: ABD_LAUNCH(4); break;
-    case 8: ABD_LAUNCH(8); break;
-    default: ABD_LAUNCH(16); break;
+  if (m->tree) {
+    switch (nw) {
+      case 1: ABD_LAUNCH(1, true); break;
+      case 2: ABD_LAUNCH(2, true); break;
+      default: ABD_LAUNCH(4, true); break;
+    }
+  } else {
+    switch (nw) {
+      case 1: ABD_LAUNCH(1, false); break;
+      case 2: ABD_LAUNCH(2, false); break;
+      case 4: ABD_LAUNCH(4, false); break;
+      case 8: ABD_LAUNCH(8, false); break;
+      default: ABD_LAUNCH(16, false); break;
+    }
   }
 #undef ABD_LAUNCH
   HIP_TRY(hipGetLastError());
@@ -2583,12 +2918,20 @@ int abd_objective_grad(abd_model* m, const abd_step_opts* o, const double* q, co
   const int nw = waves_for(m->max_frames);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 grid(m->n_models), block(nw * kWave);
-  switch (nw) {
-    case 1: hipLaunchKernelGGL(k_objective_grad<1>, grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_objective_grad<2>, grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL(k_objective_grad<4>, grid, block, 0, s, a); break;
-    case 8: hipLaunchKernelGGL(k_objective_grad<8>, grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL(k_objective_grad<16>, grid, block, 0, s, a); break;
+  if (m->tree) {
+    switch (nw) {
+      case 1: hipLaunchKernelGGL((k_objective_grad<1, true>), grid, block, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_objective_grad<2, true>), grid, block, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_objective_grad<4, true>), grid, block, 0, s, a); break;
+    }
+  } else {
+    switch (nw) {
+      case 1: hipLaunchKernelGGL((k_objective_grad<1, false>), grid, block, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_objective_grad<2, false>), grid, block, 0, s, a); break;
+      case 4: hipLaunchKernelGGL((k_objective_grad<4, false>), grid, block, 0, s, a); break;
+      case 8: hipLaunchKernelGGL((k_objective_grad<8, false>), grid, block, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_objective_grad<16, false>), grid, block, 0, s, a); break;
+    }
   }
   HIP_TRY(hipGetLastError());
   return ABD_OK;
@@ -2602,8 +2945,8 @@ int abd_hvp(abd_model* m, const abd_step_opts* o, const double* q, const double*
   if (rc) return rc;
   if (m->n_models == 0) return ABD_OK;
   if (!q || !q_hist || !v || !Hv) return fail(ABD_EINVAL, "q, q_hist, v and Hv must not be NULL");
-  if (m->max_frames > kMaxFrames)
-    return fail(ABD_ENOTSUP, "abd_hvp handles models of at most 64 DOFs in this build");
+  if (m->max_frames > kMaxFrames || m->tree)
+    return fail(ABD_ENOTSUP, "abd_hvp handles serial chains of at most 64 DOFs in this build");
   if ((rc = check_device(m))) return rc;
   HvpArgs a;
   a.d = dev_view(m);
@@ -2633,8 +2976,8 @@ int abd_rollout_vjp(abd_model* m, const abd_step_opts* o, const double* q_init, 
   if (m->n_models == 0) return ABD_OK;
   if (!q_init || !q_traj || !dL_dq_traj || !dL_dq_init)
     return fail(ABD_EINVAL, "q_init, q_traj, dL_dq_traj and dL_dq_init must not be NULL");
-  if (m->max_frames > kMaxFrames)
-    return fail(ABD_ENOTSUP, "abd_rollout_vjp handles models of at most 64 DOFs in this build");
+  if (m->max_frames > kMaxFrames || m->tree)
+    return fail(ABD_ENOTSUP, "abd_rollout_vjp handles serial chains of at most 64 DOFs in this build");
   if ((rc = check_device(m))) return rc;
   VjpArgs a;
   a.d = dev_view(m);
@@ -2665,12 +3008,20 @@ int abd_poses(abd_model* m, const double* q, double* poses, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 grid(m->n_models), block(nw * kWave);
   const DevModel d = dev_view(m);
-  switch (nw) {
-    case 1: hipLaunchKernelGGL(k_poses<1>, grid, block, 0, s, d, q, poses); break;
-    case 2: hipLaunchKernelGGL(k_poses<2>, grid, block, 0, s, d, q, poses); break;
-    case 4: hipLaunchKernelGGL(k_poses<4>, grid, block, 0, s, d, q, poses); break;
-    case 8: hipLaunchKernelGGL(k_poses<8>, grid, block, 0, s, d, q, poses); break;
-    default: hipLaunchKernelGGL(k_poses<16>, grid, block, 0, s, d, q, poses); break;
+  if (m->tree) {
+    switch (nw) {
+      case 1: hipLaunchKernelGGL((k_poses<1, true>), grid, block, 0, s, d, q, poses); break;
+      case 2: hipLaunchKernelGGL((k_poses<2, true>), grid, block, 0, s, d, q, poses); break;
+      default: hipLaunchKernelGGL((k_poses<4, true>), grid, block, 0, s, d, q, poses); break;
+    }
+  } else {
+    switch (nw) {
+      case 1: hipLaunchKernelGGL((k_poses<1, false>), grid, block, 0, s, d, q, poses); break;
+      case 2: hipLaunchKernelGGL((k_poses<2, false>), grid, block, 0, s, d, q, poses); break;
+      case 4: hipLaunchKernelGGL((k_poses<4, false>), grid, block, 0, s, d, q, poses); break;
+      case 8: hipLaunchKernelGGL((k_poses<8, false>), grid, block, 0, s, d, q, poses); break;
+      default: hipLaunchKernelGGL((k_poses<16, false>), grid, block, 0, s, d, q, poses); break;
+    }
   }
   HIP_TRY(hipGetLastError());
   return ABD_OK;
