@@ -1895,6 +1895,7 @@ struct HocArgs {
   double* q_out;        // [n_steps][U][n_dofs]
   abd_step_stats* stats;
   double* Bk;           // scratch [n_dofs][U][12]
+  double* hist3;        // models of more than 64 DOFs: L-BFGS pairs [n_dofs][2][kMaxHist][3]
 };
 
 // Derivative along a tangent (dA, W) of the adjoint pass at poses A with a FIXED
@@ -2034,34 +2035,48 @@ __device__ double hoc_evaluate(Sc& sc, const HocArgs<U>& args, const FrameGeo& g
   return E;
 }
 
-template <int U>
-__global__ void __launch_bounds__(kWave, 1) k_rollout_hoc(HocArgs<U> args) {
-  __shared__ ModelLds L;
-  extern __shared__ double pairs[];  // s ring [m][U][64], then y ring
+template <int NW, bool TREE, int U>
+__global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
+  __shared__ RollLds<NW, TREE> L;
+  extern __shared__ double pairs[];  // one-wave chains: s ring [m][U][64], then y ring
   const DevModel& d = args.d;
   const int n = d.n_dofs;
-  const int lane = threadIdx.x;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int j = threadIdx.x;
+  const bool lead = threadIdx.x == 0;
   const int model = blockIdx.x;
   if (model >= d.n_models) return;
-  WaveScan ws;
   const int f0 = d.f0[model];
   const int nf = d.f0[model + 1] - f0;
-  const bool valid = lane < nf;
-  const int f = f0 + (valid ? lane : 0);
+  const bool valid = j < nf;
+  const int f = f0 + (valid ? j : 0);
+  typename ModelScan<NW, TREE>::type ws = ModelScan<NW, TREE>::make(L, d, wave, lane, j, f, valid);
+  const int io = TREE ? (valid ? d.uidx[f] : 0) : f;
   const bool use_aba = args.precond == ABD_PRECOND_INERTIA;
+  const bool explicit_inverse = NW == 1 && !TREE;
   double* Hi = d.hinv + d.hoff[model];
   const FrameGeo geo = load_geo(d, f, valid);
   const double eps_w = 1.1102230246251565e-16;
   const double c1 = 1e-4, dlt = 0.1;
-  double qprev = valid ? args.q_prev[f] : 0.0;
-  double qk = valid ? args.q_curr[f] : 0.0;
-  double* sp = pairs + lane;                   // s of slot k, unknown u: sp[(k * U + u) * kWave]
-  double* yp = pairs + args.m * U * kWave + lane;
+  double qprev = valid ? args.q_prev[io] : 0.0;
+  double qk = valid ? args.q_curr[io] : 0.0;
+  // pairs: s of slot k, unknown u at sp[(k * U + u) * stride], y likewise at yp
+  double *sp, *yp;
+  int stride;
+  if (NW == 1) {
+    sp = pairs + lane;
+    yp = pairs + args.m * U * kWave + lane;
+    stride = kWave;
+  } else {
+    sp = args.hist3 + (size_t)f * (2 * kMaxHist * 3);
+    yp = sp + kMaxHist * 3;
+    stride = 1;
+  }
   for (int step = 0; step < args.n_steps; ++step) {
     double q[U], g[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) q[u] = valid ? qk + args.tau_u[u] * args.vscale * (qk - qprev) : 0.0;
-    const double tau = (valid && args.tau) ? args.tau[(size_t)step * n + f] : 0.0;
+    const double tau = (valid && args.tau) ? args.tau[(size_t)step * n + io] : 0.0;
     int iters = 0, evals = 0, flag = 0, count = 0, head = 0;
     double E = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0;
     bool reset = false;
@@ -2080,11 +2095,18 @@ __global__ void __launch_bounds__(kWave, 1) k_rollout_hoc(HocArgs<U> args) {
               args.Bk[(size_t)f * (12 * U) + 12 * u + k] = args.w[u][0] * Ap.m[k] + args.w[u][1] * Ak.m[k];
       }
       if (use_aba) {
-        step_setup(ws, d, L.inert[lane], L.tab[lane], geo, f, valid, qprev, qk, qk, true);
+        double* inert = NW == 1 ? L.inert[lane] : Hi + (size_t)(valid ? j : 0) * 10;
+        step_setup(ws, d, inert, L.tab[j], geo, f, valid, qprev, qk, qk, true);
+        if (NW > 1) __threadfence_block();
         __syncthreads();
-        if (lane == 0) aba_setup(&L.inert[0][0], L.tab, nf);
+        if (lead) {
+          if (TREE)
+            aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
+          else
+            aba_setup(NW == 1 ? &L.inert[0][0] : Hi, L.tab, nf);
+        }
         __syncthreads();
-        aba_inverse(L.tab, nf, lane, Hi);
+        if (explicit_inverse) aba_inverse(L.tab, nf, lane, Hi);
       }
       E = hoc_evaluate<U>(ws, args, geo, f, valid, q, tau, g);
       ++evals;
@@ -2112,18 +2134,37 @@ __global__ void __launch_bounds__(kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           const int slot = (head - k + args.m) % args.m;
           double sq = 0.0;
 #pragma unroll
-          for (int u = 0; u < U; ++u) sq += (valid ? sp[(slot * U + u) * kWave] : 0.0) * qv[u];
+          for (int u = 0; u < U; ++u) sq += (valid ? sp[(slot * U + u) * stride] : 0.0) * qv[u];
           const double a_k = uniform(L.rho[k] * ws.sum(sq));
-          if (lane == 0) L.alp[k] = a_k;
+          if (lead) L.alp[k] = a_k;
 #pragma unroll
-          for (int u = 0; u < U; ++u) qv[u] -= a_k * (valid ? yp[(slot * U + u) * kWave] : 0.0);
+          for (int u = 0; u < U; ++u) qv[u] -= a_k * (valid ? yp[(slot * U + u) * stride] : 0.0);
         }
         // ---- initial inverse Hessian: (W^T W)^-1 (x) H_q^-2, or gamma I
         double r[U];
         if (use_aba) {
           double y[U];
+          if (explicit_inverse) {
 #pragma unroll
-          for (int u = 0; u < U; ++u) y[u] = apply_inverse(Hi, nf, lane, apply_inverse(Hi, nf, lane, qv[u]));
+            for (int u = 0; u < U; ++u) y[u] = apply_inverse(Hi, nf, lane, apply_inverse(Hi, nf, lane, qv[u]));
+          } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              L.xb[j] = valid ? qv[u] : 0.0;
+              __syncthreads();
+              if (lead) {
+                for (int rep = 0; rep < 2; ++rep) {
+                  if (TREE)
+                    aba_solve_tree(L.tab, L.xb, L.tpar, L.acc, nf);
+                  else
+                    aba_solve(L.tab, L.xb, nf);
+                }
+              }
+              __syncthreads();
+              y[u] = valid ? L.xb[j] : 0.0;
+              __syncthreads();
+            }
+          }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             double t = 0.0;
@@ -2140,10 +2181,10 @@ __global__ void __launch_bounds__(kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           const int slot = (head - k + args.m) % args.m;
           double yr = 0.0;
 #pragma unroll
-          for (int u = 0; u < U; ++u) yr += (valid ? yp[(slot * U + u) * kWave] : 0.0) * r[u];
+          for (int u = 0; u < U; ++u) yr += (valid ? yp[(slot * U + u) * stride] : 0.0) * r[u];
           const double b = uniform(L.rho[k] * ws.sum(yr));
 #pragma unroll
-          for (int u = 0; u < U; ++u) r[u] += (L.alp[k] - b) * (valid ? sp[(slot * U + u) * kWave] : 0.0);
+          for (int u = 0; u < U; ++u) r[u] += (L.alp[k] - b) * (valid ? sp[(slot * U + u) * stride] : 0.0);
         }
         double dir[U], gdl = 0.0;
 #pragma unroll
@@ -2200,7 +2241,7 @@ __global__ void __launch_bounds__(kWave, 1) k_rollout_hoc(HocArgs<U> args) {
         ws.sum2(syl, ssl);
         ws.sum2(yyl, ggl);
         if (syl > 1e-12 * sqrt(ssl) * sqrt(yyl)) {
-          if (lane == 0) {
+          if (lead) {
             for (int k = args.m - 1; k > 0; --k) L.rho[k] = L.rho[k - 1];
             L.rho[0] = 1.0 / syl;
           }
@@ -2209,8 +2250,8 @@ __global__ void __launch_bounds__(kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           if (valid)
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-              sp[(head * U + u) * kWave] = qt[u] - q[u];
-              yp[(head * U + u) * kWave] = gt[u] - g[u];
+              sp[(head * U + u) * stride] = qt[u] - q[u];
+              yp[(head * U + u) * stride] = gt[u] - g[u];
             }
           if (count < args.m) ++count;
         }
@@ -2228,8 +2269,8 @@ __global__ void __launch_bounds__(kWave, 1) k_rollout_hoc(HocArgs<U> args) {
     }
     if (valid)
 #pragma unroll
-      for (int u = 0; u < U; ++u) args.q_out[((size_t)step * U + u) * n + f] = q[u];
-    if (args.stats && lane == 0) {
+      for (int u = 0; u < U; ++u) args.q_out[((size_t)step * U + u) * n + io] = q[u];
+    if (args.stats && lead) {
       abd_step_stats st;
       st.iterations = iters;
       st.evaluations = evals;
@@ -2257,19 +2298,21 @@ struct HocObjArgs {
   double* Bk;
 };
 
-template <int U>
-__global__ void __launch_bounds__(kWave) k_hoc_objective(HocObjArgs a) {
+template <int NW, bool TREE, int U>
+__global__ void __launch_bounds__(NW* kWave) k_hoc_objective(HocObjArgs a) {
+  __shared__ ScanLds<NW, TREE> L;
   const DevModel& d = a.d;
-  const int model = blockIdx.x, lane = threadIdx.x;
+  const int model = blockIdx.x, j = threadIdx.x;
   const int f0 = d.f0[model], nf = d.f0[model + 1] - f0;
   if (nf == 0) {
-    if (lane == 0) a.E[model] = 0.0;
+    if (j == 0) a.E[model] = 0.0;
     return;
   }
-  const bool valid = lane < nf;
-  const int f = f0 + (valid ? lane : 0);
+  const bool valid = j < nf;
+  const int f = f0 + (valid ? j : 0);
   const int n = d.n_dofs;
-  WaveScan ws;
+  typename ModelScan<NW, TREE>::type ws = ModelScan<NW, TREE>::make(L, d, j / kWave, j % kWave, j, f, valid);
+  const int io = TREE ? (valid ? d.uidx[f] : 0) : f;
   const FrameGeo geo = load_geo(d, f, valid);
   HocArgs<U> h;
   h.d = d;
@@ -2278,8 +2321,8 @@ __global__ void __launch_bounds__(kWave) k_hoc_objective(HocObjArgs a) {
     for (int p = 0; p < U + 2; ++p) h.w[u][p] = a.w[u][p];
   h.Bk = a.Bk;
   {
-    const Xf<double> Ap = fk_geo<double>(ws, geo, valid, valid ? a.q_prev[f] : 0.0);
-    const Xf<double> Ak = fk_geo<double>(ws, geo, valid, valid ? a.q_curr[f] : 0.0);
+    const Xf<double> Ap = fk_geo<double>(ws, geo, valid, valid ? a.q_prev[io] : 0.0);
+    const Xf<double> Ak = fk_geo<double>(ws, geo, valid, valid ? a.q_curr[io] : 0.0);
     if (valid)
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -2289,13 +2332,13 @@ __global__ void __launch_bounds__(kWave) k_hoc_objective(HocObjArgs a) {
   }
   double q[U], g[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) q[u] = valid ? a.q[(size_t)u * n + f] : 0.0;
-  const double tau = (valid && a.tau) ? a.tau[f] : 0.0;
+  for (int u = 0; u < U; ++u) q[u] = valid ? a.q[(size_t)u * n + io] : 0.0;
+  const double tau = (valid && a.tau) ? a.tau[io] : 0.0;
   const double E = hoc_evaluate<U>(ws, h, geo, f, valid, q, tau, g);
-  if (lane == 0) a.E[model] = E;
+  if (j == 0) a.E[model] = E;
   if (a.grad && valid)
 #pragma unroll
-    for (int u = 0; u < U; ++u) a.grad[(size_t)u * n + f] = g[u];
+    for (int u = 0; u < U; ++u) a.grad[(size_t)u * n + io] = g[u];
 }
 
 // ---------------------------------------------------- objective / poses --
@@ -2375,6 +2418,7 @@ struct abd_model {
   double* hinv = nullptr;
   double* hist = nullptr;
   double* Bk = nullptr;  // known seed parts of order-K steps, allocated on first use
+  double* hist3 = nullptr;  // order-K pairs of models of more than 64 DOFs, on first use
   int* uidx = nullptr;
   int* fpar = nullptr;
   int* fend = nullptr;
@@ -2658,6 +2702,13 @@ int abd_model_info(const abd_model* m, int* n_models, int* n_links, int* n_dofs)
   return ABD_OK;
 }
 
+// wavefronts per model workgroup: the power of two covering the longest model
+static int waves_for(int max_frames) {
+  int nw = 1;
+  while (nw * kMaxFrames < max_frames) nw *= 2;
+  return nw;
+}
+
 extern "C++" {
 // Collocation of order K = 3, 4 (Eq. HOC): the interior points are the roots of
 // the Legendre polynomial L_{K-2}(2 alpha - 1) (closed forms for K <= 4) and
@@ -2745,13 +2796,18 @@ static int fill_hoc_args(abd_model* m, const abd_step_opts* o, HocArgs<U>& a) {
     int rc = alloc(m, &m->Bk, 36 * (size_t)m->n_dofs);
     if (rc) return rc;
   }
+  if (!m->hist3 && m->max_frames > kMaxFrames) {
+    int rc = alloc(m, &m->hist3, 2 * kMaxHist * 3 * (size_t)m->n_dofs);
+    if (rc) return rc;
+  }
   a.Bk = m->Bk;
+  a.hist3 = m->hist3;
   return ABD_OK;
 }
 
 static int check_hoc(const abd_model* m, const abd_step_opts* o) {
-  if (m->max_frames > kMaxFrames || m->tree)
-    return fail(ABD_ENOTSUP, "order_K > 2 handles serial chains of at most 64 DOFs in this build");
+  if (m->max_frames > 4 * kMaxFrames)
+    return fail(ABD_ENOTSUP, "order_K > 2 handles models of at most 256 DOFs in this build");
   if (o->precision != ABD_FP64) return fail(ABD_ENOTSUP, "order_K > 2 runs in ABD_FP64 only in this build");
   return ABD_OK;
 }
@@ -2762,29 +2818,40 @@ static int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int U = o->order_K - 1;
-  const size_t pair_bytes = 2 * (size_t)o->lbfgs_m * U * kWave * sizeof(double);
-  if (U == 2) {
-    HocArgs<2> a;
-    if ((rc = fill_hoc_args<2>(m, o, a))) return rc;
-    a.n_steps = n_steps; a.q_prev = q_prev; a.q_curr = q_curr; a.tau = tau; a.q_out = q_out; a.stats = stats;
-    hipLaunchKernelGGL(k_rollout_hoc<2>, dim3(m->n_models), dim3(kWave), pair_bytes, s, a);
+  const int nw = waves_for(m->max_frames);
+  const size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * U * kWave * sizeof(double) : 0;
+  const dim3 grid(m->n_models), block(nw * kWave);
+#define ABD_HOC(NW, TREE, UU)                                                                  \
+  do {                                                                                         \
+    HocArgs<UU> a;                                                                             \
+    if ((rc = fill_hoc_args<UU>(m, o, a))) return rc;                                          \
+    a.n_steps = n_steps; a.q_prev = q_prev; a.q_curr = q_curr; a.tau = tau; a.q_out = q_out;   \
+    a.stats = stats;                                                                           \
+    hipLaunchKernelGGL((k_rollout_hoc<NW, TREE, UU>), grid, block, pair_bytes, s, a);          \
+  } while (0)
+#define ABD_HOC_U(NW, TREE) \
+  do {                      \
+    if (U == 2)             \
+      ABD_HOC(NW, TREE, 2); \
+    else                    \
+      ABD_HOC(NW, TREE, 3); \
+  } while (0)
+  if (m->tree) {
+    if (nw == 1) ABD_HOC_U(1, true);
+    else if (nw == 2) ABD_HOC_U(2, true);
+    else ABD_HOC_U(4, true);
   } else {
-    HocArgs<3> a;
-    if ((rc = fill_hoc_args<3>(m, o, a))) return rc;
-    a.n_steps = n_steps; a.q_prev = q_prev; a.q_curr = q_curr; a.tau = tau; a.q_out = q_out; a.stats = stats;
-    hipLaunchKernelGGL(k_rollout_hoc<3>, dim3(m->n_models), dim3(kWave), pair_bytes, s, a);
+    if (nw == 1) ABD_HOC_U(1, false);
+    else if (nw == 2) ABD_HOC_U(2, false);
+    else ABD_HOC_U(4, false);
   }
+#undef ABD_HOC_U
+#undef ABD_HOC
   HIP_TRY(hipGetLastError());
   return ABD_OK;
 }
 }  // extern "C++"
 
-// wavefronts per model workgroup: the power of two covering the longest model
-static int waves_for(int max_frames) {
-  int nw = 1;
-  while (nw * kMaxFrames < max_frames) nw *= 2;
-  return nw;
-}
 
 static int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
                           const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream) {
@@ -2898,10 +2965,25 @@ int abd_objective_grad(abd_model* m, const abd_step_opts* o, const double* q, co
     h.grad = grad;
     h.Bk = m->Bk;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (U == 2)
-      hipLaunchKernelGGL(k_hoc_objective<2>, dim3(m->n_models), dim3(kWave), 0, s, h);
-    else
-      hipLaunchKernelGGL(k_hoc_objective<3>, dim3(m->n_models), dim3(kWave), 0, s, h);
+    const int nw = waves_for(m->max_frames);
+    const dim3 grid(m->n_models), block(nw * kWave);
+#define ABD_HOCOBJ(NW, TREE)                                                              \
+  do {                                                                                    \
+    if (U == 2)                                                                           \
+      hipLaunchKernelGGL((k_hoc_objective<NW, TREE, 2>), grid, block, 0, s, h);           \
+    else                                                                                  \
+      hipLaunchKernelGGL((k_hoc_objective<NW, TREE, 3>), grid, block, 0, s, h);           \
+  } while (0)
+    if (m->tree) {
+      if (nw == 1) ABD_HOCOBJ(1, true);
+      else if (nw == 2) ABD_HOCOBJ(2, true);
+      else ABD_HOCOBJ(4, true);
+    } else {
+      if (nw == 1) ABD_HOCOBJ(1, false);
+      else if (nw == 2) ABD_HOCOBJ(2, false);
+      else ABD_HOCOBJ(4, false);
+    }
+#undef ABD_HOCOBJ
     HIP_TRY(hipGetLastError());
     return ABD_OK;
   }

@@ -104,3 +104,44 @@ def test_eqhoc_unsupported_cases_are_rejected():
     with pytest.raises(abd.AbdError) as e:
         m.step(torch.cat([q, q]), out5, abd.StepOptions(dt=0.01, order_K=5))
     assert e.value.code == abd.ABD_ENOTSUP
+
+
+@pytest.mark.parametrize("which", ["small", "workload"])
+def test_eqhoc_tree_objective_and_gradient(which):
+    """Branched models (preorder frames, pointer-jumping forward pass), order 4;
+    the workload trees have 90..180 DOFs (several waves per model)."""
+    K = 4
+    d = W.random_tree_models(12, 61, max_links=8, ball_prob=0.4) if which == "small" else W.config_models(3, 3)
+    say(f"eqhoc tree objective {which} dofs={d.n_dofs}")
+    rng = np.random.default_rng(62)
+    qp, qc = (rng.uniform(-0.5, 0.5, d.n_dofs) for _ in range(2))
+    qu = rng.uniform(-0.5, 0.5, (K - 1, d.n_dofs))
+    dt = 0.05
+    E, g = Oracle(d).eqhoc_objective_grad(K, dt, qp, qc, qu)
+    m = abd.Model(d)
+    Eg, gg = m.objective_grad(cu(qu.reshape(-1)), cu(np.concatenate([qp, qc])), dt, order_K=K)
+    Eg, gg = Eg.cpu().numpy(), gg.cpu().numpy()
+    np.testing.assert_allclose(Eg, E, rtol=1e-10, atol=0)
+    do = d.dof_offset
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        assert _rel(gg[:, sl], g[:, sl]) <= 1e-9, (i, _rel(gg[:, sl], g[:, sl]))
+
+
+def test_eqhoc_tree_step_matches_oracle():
+    K = 4
+    d = W.random_tree_models(8, 61, max_links=6, ball_prob=0.4)
+    q0 = np.random.default_rng(2).uniform(-0.5, 0.5, d.n_dofs)
+    dt, tol = 0.01, 1e-10
+    say("eqhoc tree step")
+    ref, rst = Oracle(d).step_hoc(K, q0, q0, dt, tol=tol, max_iter=3000)
+    m = abd.Model(d)
+    out = torch.zeros((K - 1, d.n_dofs), dtype=torch.float64, device="cuda")
+    st = m.new_stats()
+    m.step(cu(np.concatenate([q0, q0])), out, abd.StepOptions(dt=dt, order_K=K, tol=tol, max_iter=3000), stats=st)
+    torch.cuda.synchronize()
+    st = m.read_stats(st, d.n_models)
+    assert np.all(st["flag"] == abd.FLAG_CONVERGED), st["flag"]
+    got = out.cpu().numpy()
+    err = float(np.max(np.abs(got - ref))) / max(1.0, float(np.max(np.abs(ref))))
+    assert err <= 1e-7, err
