@@ -99,7 +99,11 @@ typedef struct {
 
 /* Validate a description and upload it to the current HIP device.  Checks
  * topology, finite values, unit axes, positive mass and positive semi-definite
- * moment tensors (ABD_EINVAL).  Synchronous.  *out receives the handle. */
+ * moment tensors (ABD_EINVAL).  Synchronous.  *out receives the handle.
+ * Limits of this build (ABD_ENOTSUP): serial chains of up to 1024 DOFs per
+ * model, branched models (trees) of up to 256 DOFs per model.  abd_hvp and
+ * abd_rollout_vjp take serial chains of up to 64 DOFs; order_K > 2 takes models
+ * of up to 256 DOFs. */
 int abd_create_model(const abd_model_desc* desc, abd_model** out);
 
 /* Release the model's device memory (synchronizes the device first). */
