@@ -712,6 +712,18 @@ static int finitev(const double* a, int n) {
   return 1;
 }
 
+/* Next trial step after a rejected one (backtracking with quadratic
+ * interpolation, Nocedal & Wright Sec. 3.5): the minimizer of the parabola
+ * through E(0), E'(0) = gd and E(alpha), kept within [0.1, 0.5] alpha; plain
+ * halving when E(alpha) is not finite or the parabola has no interior minimum. */
+static double next_alpha(double alpha, double E, double Et, double gd) {
+  if (!isfinite(Et)) return 0.5 * alpha;
+  double den = 2.0 * (Et - E - gd * alpha);
+  if (!(den > 0.0)) return 0.5 * alpha;
+  double aq = -gd * alpha * alpha / den;
+  return aq < 0.1 * alpha ? 0.1 * alpha : (aq > 0.5 * alpha ? 0.5 * alpha : aq);
+}
+
 /* v <- gamma * H0 v for the chosen initial inverse Hessian. */
 static void apply_H0(int mode, const double* P, const double* L, int nd, double gamma, double* v) {
   if (mode == 2) {
@@ -829,7 +841,7 @@ static void step_model(const orc_model* m, int i, const orc_opts* o, const doubl
         }
       }
       if (ok) break;
-      alpha *= 0.5;
+      alpha = next_alpha(alpha, E, Et, gd);
     }
     if (!ok) {
       s.flag = 2;
@@ -1301,7 +1313,7 @@ static void step_model_hoc(const orc_model* m, int i, const orc_opts* o, const d
         }
       }
       if (ok) break;
-      alpha *= 0.5;
+      alpha = next_alpha(alpha, E, Et, gd);
     }
     if (!ok) {
       s.flag = 2;

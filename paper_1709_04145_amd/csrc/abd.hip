@@ -1148,6 +1148,18 @@ __device__ __forceinline__ void step_setup(S& sc, const DevModel& d, double* ine
   ts[5] = valid ? t[0] * w1 - t[1] * w0 : 0.0;
 }
 
+// Next trial step after a rejected one: backtracking with quadratic
+// interpolation (the minimizer of the parabola through E(0), E'(0) = gd and
+// E(alpha)), kept within [0.1, 0.5] alpha; halving when E(alpha) is not finite
+// or the parabola has no interior minimum.  All values are wave-uniform.
+__device__ __forceinline__ double next_alpha(double alpha, double E, double Et, double gd) {
+  if (!isfinite(Et)) return 0.5 * alpha;
+  const double den = 2.0 * (Et - E - gd * alpha);
+  if (!(den > 0.0)) return 0.5 * alpha;
+  const double aq = -gd * alpha * alpha / den;
+  return aq < 0.1 * alpha ? 0.1 * alpha : (aq > 0.5 * alpha ? 0.5 * alpha : aq);
+}
+
 // What the next evaluation of an iteration is for.
 enum EvalPurpose { kTrial = 0, kRefresh = 1, kRefreshRetry = 2 };
 // Per-model state of the rollout kernel.
@@ -1447,7 +1459,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
             }
           }
           if (!ok) {
-            alpha *= 0.5;
+            alpha = next_alpha(alpha, E, rt.E, gd);
             if (++ls < args.max_ls) continue;
             if (PREC == ABD_MIXED && f32) {
               f32 = false;  // float32 rounding stalls the search: continue in float64 from q
@@ -2223,7 +2235,7 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
             }
           }
           if (ok) break;
-          alpha *= 0.5;
+          alpha = next_alpha(alpha, E, Et, gd);
         }
         if (!ok) {
           flag = ABD_FLAG_LS_FLOOR;

@@ -127,7 +127,7 @@ def test_tree_rollout_equals_step_loop_bitwise():
 
 
 def test_tree_second_order_calls_rejected():
-    d = W.random_tree_models(2, 57, max_links=5)
+    d = W._assemble([W.tree_model(np.array([-1, 0, 0, 1]), 0.5, 0.1, 1000.0)])  # branched
     m = abd.Model(d)
     q = cu(np.zeros(d.n_dofs))
     with pytest.raises(abd.AbdError) as e:
