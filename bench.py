@@ -18,8 +18,13 @@ Also reported:
                over the launch's duration measured with HIP events on the
                launch stream, against the 8 TB/s HBM peak;
   parity       one teacher-forced step from the final state on a sample of
-               models against the float64 CPU oracle (relative q error for
-               FP64, relative pose error for mixed);
+               models against the float64 CPU oracle, both solved to a 1e-11
+               relative gradient: q and pose errors over the models where both
+               sides converge to the same minimum (equal objective to 1e-9 of
+               its scale); the step objective is non-convex on this workload,
+               so models where the two reach different local minima, and
+               models where either side stops at the iteration cap, are
+               counted separately;
   cpu_baseline the oracle (C, OpenMP over models) on a sample of the models
                over the same steps.
 
@@ -47,6 +52,29 @@ LBFGS_BYTES = 128                       # read g, q, s/y history (m=5); write d,
 PRECOND_BYTES = 240                     # two sweeps over the recursion records (s, U, 1/D) + b/u/x
 SETUP_BYTES = 328                       # per step: read q_{k-1}, q_k, axis/offset, M; write B (f64+f32), records
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_rollout_chains4096_hbm_traffic.md")
+
+
+def measured_traffic(workload, precision, warmup, steps):
+    """HBM bytes of the timed launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, if it was taken on this kernel source and this launch; else None."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    kv = {}
+    for line in text.splitlines():
+        if ": " in line and not line.startswith(("|", "#", " ")):
+            k, v = line.split(": ", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_1709_04145_amd", "csrc", "abd.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    want = {"source_sha256": digest, "workload": workload, "precision": precision,
+            "warmup": str(warmup), "steps": str(steps)}
+    if any(kv.get(k) != v for k, v in want.items()) or "traffic_bytes" not in kv:
+        return None
+    return float(kv["traffic_bytes"])
 
 
 def parse():
@@ -65,13 +93,17 @@ def parse():
 def timed_rollout(torch, model, q0, opts, warmup, steps):
     """Warm-up rollout from rest, then `steps` timed steps in one launch."""
     n = model.n_dofs
+    K = opts.order_K
     q0c = torch.as_tensor(q0, dtype=torch.float64, device="cuda")
     init = torch.cat([q0c, q0c]).contiguous()
     if warmup > 0:
         wtraj, _ = model.rollout(init, warmup, opts)
-        prev = wtraj[warmup - 2] if warmup >= 2 else q0c
-        init = torch.cat([prev, wtraj[warmup - 1]]).contiguous()
-    traj = torch.empty((steps, n), dtype=torch.float64, device="cuda")
+        if K == 2:
+            prev = wtraj[warmup - 2] if warmup >= 2 else q0c
+            init = torch.cat([prev, wtraj[warmup - 1]]).contiguous()
+        else:  # known points of the next step: the last step's alpha_{K-2} point and q_{k+1}
+            init = torch.cat([wtraj[warmup - 1, K - 3], wtraj[warmup - 1, K - 2]]).contiguous()
+    traj = torch.empty((steps, n) if K == 2 else (steps, K - 1, n), dtype=torch.float64, device="cuda")
     stats = model.new_rollout_stats(steps)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -134,11 +166,14 @@ def main():
     desc = wl.model
     model = abd.Model(desc)
     L = desc.n_links
-    base = dict(dt=wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol, max_iter=wl.step.max_iter)
+    K = wl.step.order_K
+    base = dict(dt=wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol, max_iter=wl.step.max_iter, order_K=K)
     runs = {}
     for name, prec in (("mixed", abd.MIXED), ("fp64", abd.FP64)):
-        if name == "fp64" and args.no_fp64:
+        if name == "fp64" and args.no_fp64 and K == 2:
             continue
+        if name == "mixed" and K > 2:
+            continue  # order K > 2 runs in float64 only
         opts = abd.StepOptions(precision=prec, **base)
         init, traj, st, wall, kms = timed_rollout(torch, model, wl.q0, opts, args.warmup, args.steps)
         nbytes = algorithmic_bytes(desc, st, name)
@@ -154,7 +189,7 @@ def main():
               f"steps, iters/step {runs[name]['iters_mean']:.2f} (max {runs[name]['iters_max']})",
               file=sys.stderr, flush=True)
 
-    mixed = runs["mixed"]
+    mixed = runs["mixed"] if "mixed" in runs else runs["fp64"]
     out = {
         "metric": "link-steps/s on 1 MI355X, batched mixed vs plain FP64, at <=1e-5 rel pose err",
         "value": mixed["value"],
@@ -166,10 +201,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f32+f64" if "mixed" in runs else "f64",
         "data": "synthetic",
         "config": {"workload": W.CONFIG_NAMES[args.config], "models": desc.n_models, "links": L,
-                   "dofs": desc.n_dofs, "dt": wl.step.dt, "order_K": 2, "lbfgs_m": wl.step.lbfgs_m,
+                   "dofs": desc.n_dofs, "dt": wl.step.dt, "order_K": K, "lbfgs_m": wl.step.lbfgs_m,
                    "tol": wl.step.tol, "precond": "joint-space inertia", "launch": "one rollout per K steps"},
         "iterations_per_step": mixed["iters_mean"],
         "iterations_per_step_max": mixed["iters_max"],
@@ -177,18 +212,22 @@ def main():
         "converged_fraction": mixed["converged_frac"],
         "link_iterations_per_s": mixed["link_iters"] / mixed["wall"],
         "roofline": {"bound": "hbm", "achieved": mixed["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": mixed["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_rollout<MIXED>", "kernel_ms": mixed["kernel_ms"],
+                     "frac": mixed["achieved_gbs"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(W.CONFIG_NAMES[args.config], "mixed" if "mixed" in runs else "fp64",
+                                                 args.warmup, args.steps),
+                     "kernel": "k_rollout<MIXED>" if "mixed" in runs else ("k_rollout<FP64>" if K == 2 else
+                                                                             "k_rollout_hoc"),
+                     "kernel_ms": mixed["kernel_ms"],
                      "algorithmic_bytes": mixed["bytes"]},
     }
-    if "fp64" in runs:
+    if "fp64" in runs and "mixed" in runs:
         f = runs["fp64"]
         out["fp64"] = {"value": f["value"], "ms_per_step": f["wall"] / args.steps * 1e3,
                        "iterations_per_step": f["iters_mean"], "iterations_per_step_max": f["iters_max"],
                        "converged_fraction": f["converged_frac"], "kernel_ms": f["kernel_ms"],
                        "achieved_gbs": f["achieved_gbs"], "mixed_over_fp64": mixed["value"] / f["value"]}
 
-    if not args.no_parity:
+    if not args.no_parity and K == 2:
         # one teacher-forced step from the final FP64 state (both precisions start
         # from the same float64 (q_{k-1}, q_k)) on a sample of models
         from oracle.oracle import Oracle
@@ -199,19 +238,38 @@ def main():
         sub = desc.subset(sample)
         idx = desc.dof_subset_index(sample)
         orc = Oracle(sub)
-        ref, rst = orc.step(qp[idx], qc[idx], wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=1e-11)
+        ref, rst = orc.step(qp[idx], qc[idx], wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=1e-11,
+                            max_iter=wl.step.max_iter)
         hist = torch.tensor(np.concatenate([qp, qc]), dtype=torch.float64, device="cuda")
+        E_ref, _, S_ref = orc.objective_grad(ref, qp[idx], qc[idx], wl.step.dt)
+        do = sub.dof_offset
         par = {}
         for name, prec in (("fp64", abd.FP64), ("mixed", abd.MIXED)):
             o = torch.zeros(desc.n_dofs, dtype=torch.float64, device="cuda")
-            model.step(hist, o, abd.StepOptions(precision=prec, **dict(base, tol=1e-11)))
+            st = model.new_stats()
+            model.step(hist, o, abd.StepOptions(precision=prec, **dict(base, tol=1e-11)), stats=st)
             torch.cuda.synchronize()
+            gst = model.read_stats(st, desc.n_models)[sample]
             qg = o.cpu().numpy()[idx]
-            par[name] = {"max_rel_q_err": float(np.max(np.abs(qg - ref)) / max(1.0, np.max(np.abs(ref))))}
-            par[name]["max_rel_pose_err"], par[name]["max_rot_err"] = pose_error(orc, sub, qg, ref)
+            E_g, _, _ = orc.objective_grad(qg, qp[idx], qc[idx], wl.step.dt)
+            conv = (gst["flag"] == abd.FLAG_CONVERGED) & (rst["flag"] == 1)
+            same = conv & (np.abs(E_g - E_ref) <= 1e-9 * S_ref)
+            qerr, perr = 0.0, 0.0
+            keep = np.nonzero(same)[0]
+            if len(keep):
+                sd = sub.subset(keep)
+                si = sub.dof_subset_index(keep)
+                qerr = float(np.max(np.abs(qg[si] - ref[si])) / max(1.0, np.max(np.abs(ref[si]))))
+                perr = pose_error(Oracle(sd), sd, qg[si], ref[si])[0]
+            distinct = conv & ~same
+            par[name] = {"models_same_minimum": int(same.sum()), "max_rel_q_err": qerr, "max_rel_pose_err": perr,
+                         "models_distinct_minima": int(distinct.sum()),
+                         "max_rel_objective_gap_distinct": float(np.max(np.abs(E_g - E_ref)[distinct] / S_ref[distinct]))
+                         if distinct.any() else 0.0,
+                         "models_not_converged": int((~conv).sum())}
         out["parity"] = {"sample_models": int(len(sample)), "tol": 1e-11, **par}
 
-    if not args.no_cpu:
+    if not args.no_cpu and K == 2:
         from oracle.oracle import Oracle
         threads = max(1, min(16, os.cpu_count() or 1))
         nsub = max(1, min(desc.n_models, args.cpu_models))
