@@ -149,6 +149,15 @@ __device__ __forceinline__ void wave_sum2(double& a, double& b) {
   b = readlane(b, 63);
 }
 
+// Load *p on every lane and keep it where c holds (0 elsewhere).  The address
+// must be valid on every lane (callers clamp indices to the model's frames), so
+// the load is unconditional and needs no execution-mask branch.
+template <typename T>
+__device__ __forceinline__ T ld_if(const T* p, bool c) {
+  const T x = *p;
+  return c ? x : T(0);
+}
+
 // ------------------------------------------------------------ transforms --
 // 3x4 rigid transform [R|t], row-major: m[4r+c].
 template <typename R>
@@ -667,8 +676,8 @@ __device__ __forceinline__ FrameGeo load_geo(const DevModel& d, int f, bool vali
   const double* rec = d.fr64 + (size_t)f * 16;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    g.a[k] = valid ? rec[k] : 0.0;
-    g.o[k] = valid ? rec[3 + k] : 0.0;
+    g.a[k] = ld_if(rec + k, valid);
+    g.o[k] = ld_if(rec + 3 + k, valid);
   }
   return g;
 }
@@ -697,9 +706,9 @@ __device__ EvalResult evaluate(S& sc, const DevModel& d, const FrameGeo& geo, in
   const R* rec = Arr<R>::fr(d) + (size_t)f * 16;
   const R* Bp = Arr<R>::B(d) + (size_t)f * 12;
 #pragma unroll
-  for (int k = 0; k < 10; ++k) M[k] = valid ? rec[6 + k] : R(0);
+  for (int k = 0; k < 10; ++k) M[k] = ld_if(rec + 6 + k, valid);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) Bn[k] = valid ? Bp[k] : R(0);
+  for (int k = 0; k < 4; ++k) Bn[k] = ld_if(Bp + k, valid);
   const Xf<R> A = fk_geo<R>(sc, geo, valid, q);
   const R a[3] = {(R)geo.a[0], (R)geo.a[1], (R)geo.a[2]};
 
@@ -718,7 +727,7 @@ __device__ EvalResult evaluate(S& sc, const DevModel& d, const FrameGeo& geo, in
     for (int c = 0; c < 4; ++c) D[c] = A.m[4 * r + c] + Bn[c];
     if (r < 2)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Bn[c] = valid ? Bp[4 * (r + 1) + c] : R(0);
+      for (int c = 0; c < 4; ++c) Bn[c] = ld_if(Bp + 4 * (r + 1) + c, valid);
     R AMe4 = R(0);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -886,15 +895,16 @@ __device__ void aba_inverse(const double (*tab)[14], int nf, int lane, double* H
   // chunks of kInvChunk frames; the parked u of the next chunk are requested
   // before the current chunk is solved
   double un[kInvChunk];
+  const int col = lane < nf ? lane : nf - 1;  // clamped: every lane loads inside the block
 #pragma unroll
-  for (int k = 0; k < kInvChunk; ++k) un[k] = (act && k < nf) ? Hi[(size_t)k * nf + lane] : 0.0;
+  for (int k = 0; k < kInvChunk; ++k) un[k] = ld_if(Hi + (size_t)(k < nf ? k : nf - 1) * nf + col, act && k < nf);
   for (int c0 = 0; c0 < nf; c0 += kInvChunk) {
     double uc[kInvChunk];
 #pragma unroll
     for (int k = 0; k < kInvChunk; ++k) {
       uc[k] = un[k];
       const int fn = c0 + kInvChunk + k;
-      un[k] = (act && fn < nf) ? Hi[(size_t)fn * nf + lane] : 0.0;
+      un[k] = ld_if(Hi + (size_t)(fn < nf ? fn : nf - 1) * nf + col, act && fn < nf);
     }
 #pragma unroll
     for (int k = 0; k < kInvChunk; ++k) {
@@ -919,21 +929,31 @@ __device__ __forceinline__ double apply_inverse(const double* Hi, int nf, int la
   const bool act = lane < nf;
   double r = 0.0;
   double hn[kMvChunk];
+  const int col = lane < nf ? lane : nf - 1;  // clamped: every lane loads inside the block
 #pragma unroll
-  for (int k = 0; k < kMvChunk; ++k) hn[k] = (act && k < nf) ? Hi[(size_t)k * nf + lane] : 0.0;
+  for (int k = 0; k < kMvChunk; ++k) hn[k] = ld_if(Hi + (size_t)(k < nf ? k : nf - 1) * nf + col, act && k < nf);
   for (int i0 = 0; i0 < nf; i0 += kMvChunk) {
     double hc[kMvChunk];
 #pragma unroll
     for (int k = 0; k < kMvChunk; ++k) {
       hc[k] = hn[k];
       const int in = i0 + kMvChunk + k;
-      hn[k] = (act && in < nf) ? Hi[(size_t)in * nf + lane] : 0.0;
+      hn[k] = ld_if(Hi + (size_t)(in < nf ? in : nf - 1) * nf + col, act && in < nf);
     }
 #pragma unroll
     for (int k = 0; k < kMvChunk; ++k)
       if (i0 + k < nf) r += hc[k] * readlane(v, i0 + k);
   }
   return r;
+}
+
+// The same product from a float32 copy of the explicit inverse kept in LDS
+// (Hl[i * 64 + j] = H^{-1}[i][j]; lane j only reads its own column), with
+// float64 accumulation.
+__device__ __forceinline__ double apply_inverse_lds(const float* Hl, int nf, int lane, double v) {
+  double r = 0.0;
+  for (int i = 0; i < nf; ++i) r += (double)Hl[i * kWave + lane] * readlane(v, i);
+  return lane < nf ? r : 0.0;
 }
 
 // x = H^{-1} b in O(n) by one thread (models of more than one wave): backward
@@ -1101,7 +1121,7 @@ __device__ __forceinline__ void step_setup(S& sc, const DevModel& d, double* ine
   double M[10];
   const double* rec = d.fr64 + (size_t)f * 16;
 #pragma unroll
-  for (int k = 0; k < 10; ++k) M[k] = valid ? rec[6 + k] : 0.0;
+  for (int k = 0; k < 10; ++k) M[k] = ld_if(rec + 6 + k, valid);
   const double ms = M[9];
   // world moment tensor: h = R (m c) + m t ; Sigma = R S R^T + R mc t^T + t (R mc)^T + m t t^T
   double Rmc[3];
@@ -1183,6 +1203,9 @@ enum ModelState { kSetup = 0, kIterate = 1, kDone = 2 };
 #ifndef ABD_WAVES_PER_SIMD
 #define ABD_WAVES_PER_SIMD 2
 #endif
+#ifndef ABD_HINV_LDS
+#define ABD_HINV_LDS 0
+#endif
 template <int NW>
 struct ScanOf {
   using type = BlockScan<NW>;
@@ -1249,8 +1272,12 @@ template <int NW, int PREC, bool TREE>
 __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD)) k_rollout(StepArgs args) {
   __shared__ RollLds<NW, TREE> L;
   // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
-  // y in [m, 2m), one double per lane per slot
+  // y in [m, 2m), one double per lane per slot (then, with ABD_HINV_LDS, the
+  // float32 copy of the explicit inverse)
   extern __shared__ double pairs[];
+#if ABD_HINV_LDS
+  float* hlds = reinterpret_cast<float*>(pairs + 2 * args.m * kWave);
+#endif
   const DevModel& d = args.d;
   const int n = d.n_dofs;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -1261,8 +1288,16 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
   if (!has_model) return;
   const int f0 = d.f0[model];
   const int nf = d.f0[model + 1] - f0;
+  if (nf == 0) {  // a model without frames: every step is trivially converged
+    if (lead && args.stats)
+      for (int k = 0; k < args.n_steps; ++k) {
+        abd_step_stats st = {0, 0, ABD_FLAG_CONVERGED, 0, 0.0, 0.0};
+        args.stats[(size_t)k * d.n_models + model] = st;
+      }
+    return;
+  }
   const bool valid = j < nf;
-  const int f = f0 + (valid ? j : 0);
+  const int f = f0 + (valid ? j : 0);  // invalid lanes alias frame 0 of the model (loads stay in bounds)
   typename ModelScan<NW, TREE>::type sc = ModelScan<NW, TREE>::make(L, d, wave, lane, j, f, valid);
   const int io = TREE ? (valid ? d.uidx[f] : 0) : f;  // index of this frame's DOF in the caller's vectors
   const bool use_aba = args.precond == ABD_PRECOND_INERTIA;
@@ -1274,8 +1309,8 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
   const double c1 = 1e-4, dlt = 0.1;
 
   // q_{k-1} and q_k of the current step
-  double qkm1 = valid ? args.q_prev[io] : 0.0;
-  double qk = valid ? args.q_curr[io] : 0.0;
+  double qkm1 = ld_if(args.q_prev + io, valid);
+  double qk = ld_if(args.q_curr + io, valid);
   int step = 0;
   int state = args.n_steps > 0 ? kSetup : kDone;
 
@@ -1322,7 +1357,13 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
               aba_setup(NW == 1 ? &L.inert[0][0] : Hi, L.tab, nf);
           }
           __syncthreads();
-          if (NW == 1 && !TREE) aba_inverse(L.tab, nf, lane, Hi);
+          if (NW == 1 && !TREE) {
+            aba_inverse(L.tab, nf, lane, Hi);
+#if ABD_HINV_LDS
+            if (lane < nf)
+              for (int i = 0; i < nf; ++i) hlds[i * kWave + lane] = (float)Hi[(size_t)i * nf + lane];
+#endif
+          }
         }
         PROF_ADD(0, t_s);
         const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(sc, d, geo, f, valid, q, tau, args.dt2)
@@ -1355,12 +1396,12 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
       if (reset) count = 0;
       double qv = g;
       {
-        double sk = (valid && count > 0) ? hs[head * hstride] : 0.0;
-        double yk = (valid && count > 0) ? hs[ys + head * hstride] : 0.0;
+        double sk = ld_if(hs + head * hstride, valid && count > 0);
+        double yk = ld_if(hs + ys + head * hstride, valid && count > 0);
         for (int k = 0; k < count; ++k) {
           const int nxt = (head - k - 1 + args.m) % args.m;
-          const double sn = (valid && k + 1 < count) ? hs[nxt * hstride] : 0.0;
-          const double yn = (valid && k + 1 < count) ? hs[ys + nxt * hstride] : 0.0;
+          const double sn = ld_if(hs + nxt * hstride, valid && k + 1 < count);
+          const double yn = ld_if(hs + ys + nxt * hstride, valid && k + 1 < count);
           const double a_k = uniform(L.rho[k] * sc.sum(sk * qv));
           if (lead) L.alp[k] = a_k;
           qv -= a_k * yk;
@@ -1373,7 +1414,11 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
       if (!use_aba) {
         r = (count > 0 ? gam : 1.0) * qv;
       } else if (NW == 1 && !TREE) {
+#if ABD_HINV_LDS
+        r = apply_inverse_lds(hlds, nf, lane, qv);
+#else
         r = apply_inverse(Hi, nf, lane, qv);
+#endif
       } else {
         L.xb[j] = valid ? qv : 0.0;
         __syncthreads();
@@ -1384,19 +1429,19 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
             aba_solve(L.tab, L.xb, nf);
         }
         __syncthreads();
-        r = valid ? L.xb[j] : 0.0;
+        r = ld_if(&L.xb[j], valid);
       }
       PROF_ADD(1, t_a);
       PROF_T(t_c);
       // ---- oldest pair first
       {
         int slot = (head - (count - 1) + args.m) % args.m;
-        double sk = (valid && count > 0) ? hs[slot * hstride] : 0.0;
-        double yk = (valid && count > 0) ? hs[ys + slot * hstride] : 0.0;
+        double sk = ld_if(hs + slot * hstride, valid && count > 0);
+        double yk = ld_if(hs + ys + slot * hstride, valid && count > 0);
         for (int k = count - 1; k >= 0; --k) {
           const int nxt = (slot + 1) % args.m;
-          const double sn = (valid && k > 0) ? hs[nxt * hstride] : 0.0;
-          const double yn = (valid && k > 0) ? hs[ys + nxt * hstride] : 0.0;
+          const double sn = ld_if(hs + nxt * hstride, valid && k > 0);
+          const double yn = ld_if(hs + ys + nxt * hstride, valid && k > 0);
           const double b = uniform(L.rho[k] * sc.sum(yk * r));
           r += (L.alp[k] - b) * sk;
           sk = sn;
@@ -1634,9 +1679,9 @@ __device__ double hess_vec(Sc& sc, const DevModel& d, const FrameGeo& geo, int f
   const double* rec = d.fr64 + (size_t)f * 16;
   const double* Bp = d.B64 + (size_t)f * 12;
 #pragma unroll
-  for (int k = 0; k < 10; ++k) M[k] = valid ? rec[6 + k] : 0.0;
+  for (int k = 0; k < 10; ++k) M[k] = ld_if(rec + 6 + k, valid);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) B[k] = valid ? Bp[k] : 0.0;
+  for (int k = 0; k < 12; ++k) B[k] = ld_if(Bp + k, valid);
   const Xf<double> A = fk_geo<double>(sc, geo, valid, q);
   double dA[12], W[3], w[3];
   tangent_pose(sc, A, geo.a, valid, v, dA, W, w);
@@ -1763,6 +1808,14 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
   const int n = d.n_dofs, T = args.n_steps;
   const int model = blockIdx.x, lane = threadIdx.x;
   const int f0 = d.f0[model], nf = d.f0[model + 1] - f0;
+  if (nf == 0) {
+    if (lane == 0 && args.stats)
+      for (int k = 0; k < T; ++k) {
+        abd_step_stats st = {0, 0, ABD_FLAG_CONVERGED, 0, 0.0, 0.0};
+        args.stats[(size_t)k * d.n_models + model] = st;
+      }
+    return;
+  }
   const bool valid = lane < nf;
   const int f = f0 + (valid ? lane : 0);
   const FrameGeo geo = load_geo(d, f, valid);
@@ -1952,7 +2005,7 @@ __device__ double hoc_evaluate(Sc& sc, const HocArgs<U>& args, const FrameGeo& g
   double M[10];
   const double* rec = d.fr64 + (size_t)f * 16;
 #pragma unroll
-  for (int k = 0; k < 10; ++k) M[k] = valid ? rec[6 + k] : 0.0;
+  for (int k = 0; k < 10; ++k) M[k] = ld_if(rec + 6 + k, valid);
   const double* Bk = args.Bk + (size_t)f * (12 * U);
   const double gv[3] = {d.gx, d.gy, d.gz};
   Xf<double> A[U];
@@ -1971,7 +2024,7 @@ __device__ double hoc_evaluate(Sc& sc, const HocArgs<U>& args, const FrameGeo& g
         double s = 0.0;
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-          double bx = valid ? Bk[12 * u + 4 * r + x] : 0.0;
+          double bx = ld_if(Bk + 12 * u + 4 * r + x, valid);
 #pragma unroll
           for (int a = 0; a < U; ++a) bx += args.w[u][2 + a] * A[a].m[4 * r + x];
           s += bx * M[sym4(x, c)];
@@ -2021,7 +2074,7 @@ __device__ double hoc_evaluate(Sc& sc, const HocArgs<U>& args, const FrameGeo& g
         double s = 0.0;
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-          double bx = valid ? Bk[12 * u + 4 * r + x] : 0.0;
+          double bx = ld_if(Bk + 12 * u + 4 * r + x, valid);
 #pragma unroll
           for (int a = 0; a < U; ++a) bx += args.w[u][2 + a] * A[a].m[4 * r + x];
           s += bx * M[sym4(x, c)];
@@ -2060,6 +2113,14 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
   if (model >= d.n_models) return;
   const int f0 = d.f0[model];
   const int nf = d.f0[model + 1] - f0;
+  if (nf == 0) {
+    if (lead && args.stats)
+      for (int k = 0; k < args.n_steps; ++k) {
+        abd_step_stats st = {0, 0, ABD_FLAG_CONVERGED, 0, 0.0, 0.0};
+        args.stats[(size_t)k * d.n_models + model] = st;
+      }
+    return;
+  }
   const bool valid = j < nf;
   const int f = f0 + (valid ? j : 0);
   typename ModelScan<NW, TREE>::type ws = ModelScan<NW, TREE>::make(L, d, wave, lane, j, f, valid);
@@ -2146,11 +2207,11 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           const int slot = (head - k + args.m) % args.m;
           double sq = 0.0;
 #pragma unroll
-          for (int u = 0; u < U; ++u) sq += (valid ? sp[(slot * U + u) * stride] : 0.0) * qv[u];
+          for (int u = 0; u < U; ++u) sq += ld_if(sp + (slot * U + u) * stride, valid) * qv[u];
           const double a_k = uniform(L.rho[k] * ws.sum(sq));
           if (lead) L.alp[k] = a_k;
 #pragma unroll
-          for (int u = 0; u < U; ++u) qv[u] -= a_k * (valid ? yp[(slot * U + u) * stride] : 0.0);
+          for (int u = 0; u < U; ++u) qv[u] -= a_k * ld_if(yp + (slot * U + u) * stride, valid);
         }
         // ---- initial inverse Hessian: (W^T W)^-1 (x) H_q^-2, or gamma I
         double r[U];
@@ -2193,10 +2254,10 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           const int slot = (head - k + args.m) % args.m;
           double yr = 0.0;
 #pragma unroll
-          for (int u = 0; u < U; ++u) yr += (valid ? yp[(slot * U + u) * stride] : 0.0) * r[u];
+          for (int u = 0; u < U; ++u) yr += ld_if(yp + (slot * U + u) * stride, valid) * r[u];
           const double b = uniform(L.rho[k] * ws.sum(yr));
 #pragma unroll
-          for (int u = 0; u < U; ++u) r[u] += (L.alp[k] - b) * (valid ? sp[(slot * U + u) * stride] : 0.0);
+          for (int u = 0; u < U; ++u) r[u] += (L.alp[k] - b) * ld_if(sp + (slot * U + u) * stride, valid);
         }
         double dir[U], gdl = 0.0;
 #pragma unroll
@@ -2884,7 +2945,10 @@ static int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nw = waves_for(m->max_frames);
   const dim3 grid(m->n_models), block(nw * kWave);
-  const size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * kWave * sizeof(double) : 0;
+  size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * kWave * sizeof(double) : 0;
+#if ABD_HINV_LDS
+  if (nw == 1 && !m->tree) pair_bytes += (size_t)m->max_frames * kWave * sizeof(float);
+#endif
   const bool f64 = o->precision == ABD_FP64;
 #define ABD_LAUNCH(NW, TREE)                                                                \
   do {                                                                                      \
