@@ -87,7 +87,21 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the oracle parity sample")
     ap.add_argument("--cpu-models", type=int, default=1024, help="models in the CPU baseline sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB of float64 device to device three times (the known-size kernel "
+                         "that calibrates rocprofv3's FETCH_SIZE and WRITE_SIZE counters), then exit")
     return ap.parse_args()
+
+
+def copy_probe(torch):
+    n = (1 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(f"copied {x.numel() * 8} bytes three times", flush=True)
 
 
 def timed_rollout(torch, model, q0, opts, warmup, steps):
@@ -158,6 +172,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if args.copy_probe:
+        copy_probe(torch)
+        return
 
     from paper_1709_04145_amd import abd
     from paper_1709_04145_amd import workloads as W

@@ -54,8 +54,10 @@ int fail(int code, const std::string& msg) {
 #define HIP_TRY(expr)                                                              \
   do {                                                                             \
     hipError_t e_ = (expr);                                                        \
-    if (e_ != hipSuccess)                                                          \
+    if (e_ != hipSuccess) {                                                        \
+      (void)hipGetLastError(); /* reported here: do not leave it for the caller */ \
       return fail(ABD_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+    }                                                                              \
   } while (0)
 
 constexpr int kWave = 64;
@@ -708,7 +710,7 @@ __device__ EvalResult evaluate(S& sc, const DevModel& d, const FrameGeo& geo, in
 #pragma unroll
   for (int k = 0; k < 10; ++k) M[k] = ld_if(rec + 6 + k, valid);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) Bn[k] = ld_if(Bp + k, valid);
+  for (int k = 0; k < 4; ++k) Bn[k] = Bp[k];  // lanes without a frame: M = 0 zeroes every term
   const Xf<R> A = fk_geo<R>(sc, geo, valid, q);
   const R a[3] = {(R)geo.a[0], (R)geo.a[1], (R)geo.a[2]};
 
@@ -727,7 +729,7 @@ __device__ EvalResult evaluate(S& sc, const DevModel& d, const FrameGeo& geo, in
     for (int c = 0; c < 4; ++c) D[c] = A.m[4 * r + c] + Bn[c];
     if (r < 2)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Bn[c] = ld_if(Bp + 4 * (r + 1) + c, valid);
+      for (int c = 0; c < 4; ++c) Bn[c] = Bp[4 * (r + 1) + c];
     R AMe4 = R(0);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -945,15 +947,6 @@ __device__ __forceinline__ double apply_inverse(const double* Hi, int nf, int la
       if (i0 + k < nf) r += hc[k] * readlane(v, i0 + k);
   }
   return r;
-}
-
-// The same product from a float32 copy of the explicit inverse kept in LDS
-// (Hl[i * 64 + j] = H^{-1}[i][j]; lane j only reads its own column), with
-// float64 accumulation.
-__device__ __forceinline__ double apply_inverse_lds(const float* Hl, int nf, int lane, double v) {
-  double r = 0.0;
-  for (int i = 0; i < nf; ++i) r += (double)Hl[i * kWave + lane] * readlane(v, i);
-  return lane < nf ? r : 0.0;
 }
 
 // x = H^{-1} b in O(n) by one thread (models of more than one wave): backward
@@ -1203,9 +1196,6 @@ enum ModelState { kSetup = 0, kIterate = 1, kDone = 2 };
 #ifndef ABD_WAVES_PER_SIMD
 #define ABD_WAVES_PER_SIMD 2
 #endif
-#ifndef ABD_HINV_LDS
-#define ABD_HINV_LDS 0
-#endif
 template <int NW>
 struct ScanOf {
   using type = BlockScan<NW>;
@@ -1272,12 +1262,8 @@ template <int NW, int PREC, bool TREE>
 __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD)) k_rollout(StepArgs args) {
   __shared__ RollLds<NW, TREE> L;
   // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
-  // y in [m, 2m), one double per lane per slot (then, with ABD_HINV_LDS, the
-  // float32 copy of the explicit inverse)
+  // y in [m, 2m), one double per lane per slot
   extern __shared__ double pairs[];
-#if ABD_HINV_LDS
-  float* hlds = reinterpret_cast<float*>(pairs + 2 * args.m * kWave);
-#endif
   const DevModel& d = args.d;
   const int n = d.n_dofs;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -1357,13 +1343,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
               aba_setup(NW == 1 ? &L.inert[0][0] : Hi, L.tab, nf);
           }
           __syncthreads();
-          if (NW == 1 && !TREE) {
-            aba_inverse(L.tab, nf, lane, Hi);
-#if ABD_HINV_LDS
-            if (lane < nf)
-              for (int i = 0; i < nf; ++i) hlds[i * kWave + lane] = (float)Hi[(size_t)i * nf + lane];
-#endif
-          }
+          if (NW == 1 && !TREE) aba_inverse(L.tab, nf, lane, Hi);
         }
         PROF_ADD(0, t_s);
         const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(sc, d, geo, f, valid, q, tau, args.dt2)
@@ -1414,11 +1394,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
       if (!use_aba) {
         r = (count > 0 ? gam : 1.0) * qv;
       } else if (NW == 1 && !TREE) {
-#if ABD_HINV_LDS
-        r = apply_inverse_lds(hlds, nf, lane, qv);
-#else
         r = apply_inverse(Hi, nf, lane, qv);
-#endif
       } else {
         L.xb[j] = valid ? qv : 0.0;
         __syncthreads();
@@ -2504,10 +2480,15 @@ template <typename T>
 int upload(abd_model* m, T** dst, const std::vector<T>& src) {
   size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return fail(ABD_ENOMEM, "hipMalloc failed");
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ABD_ENOMEM, "hipMalloc failed");
+  }
   m->allocs.push_back(p);
-  if (!src.empty() && hipMemcpy(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+  if (!src.empty() && hipMemcpy(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
     return fail(ABD_EDEVICE, "hipMemcpy to device failed");
+  }
   *dst = static_cast<T*>(p);
   return ABD_OK;
 }
@@ -2515,8 +2496,10 @@ int upload(abd_model* m, T** dst, const std::vector<T>& src) {
 template <typename T>
 int alloc(abd_model* m, T** dst, size_t count) {
   void* p = nullptr;
-  if (hipMalloc(&p, std::max<size_t>(1, count) * sizeof(T)) != hipSuccess)
+  if (hipMalloc(&p, std::max<size_t>(1, count) * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
     return fail(ABD_ENOMEM, "hipMalloc failed");
+  }
   m->allocs.push_back(p);
   *dst = static_cast<T*>(p);
   return ABD_OK;
@@ -2756,6 +2739,15 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
     delete m;
     return rc;
   }
+  // lanes without a frame read frame 0's B of their model (times a zero mass
+  // moment): keep the buffers finite from the start
+  if (nd > 0 && (hipMemset(m->B64, 0, 12 * (size_t)nd * sizeof(double)) != hipSuccess ||
+                 hipMemset(m->B32, 0, 12 * (size_t)nd * sizeof(float)) != hipSuccess)) {
+    (void)hipGetLastError();
+    free_model(m);
+    delete m;
+    return fail(ABD_EDEVICE, "hipMemset failed");
+  }
   *out = m;
   return ABD_OK;
 }
@@ -2945,10 +2937,7 @@ static int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nw = waves_for(m->max_frames);
   const dim3 grid(m->n_models), block(nw * kWave);
-  size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * kWave * sizeof(double) : 0;
-#if ABD_HINV_LDS
-  if (nw == 1 && !m->tree) pair_bytes += (size_t)m->max_frames * kWave * sizeof(float);
-#endif
+  const size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * kWave * sizeof(double) : 0;
   const bool f64 = o->precision == ABD_FP64;
 #define ABD_LAUNCH(NW, TREE)                                                                \
   do {                                                                                      \
