@@ -86,6 +86,10 @@ typedef struct {
   int max_ls;        /* line-search halvings per iteration, 1..60 */
   int precision;     /* ABD_FP64 or ABD_MIXED */
   int precond;       /* ABD_PRECOND_IDENTITY or ABD_PRECOND_INERTIA */
+  int refresh;       /* ABD_PRECOND_INERTIA, order_K = 2: every `refresh` accepted
+                        iterations of a step, re-form the preconditioner at the
+                        current iterate and drop the L-BFGS pairs; 0 = keep the
+                        warm start's for the whole step.  >= 0 (EINVAL otherwise) */
 } abd_step_opts;
 
 typedef struct {

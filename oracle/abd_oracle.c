@@ -795,6 +795,17 @@ static void step_model(const orc_model* m, int i, const orc_opts* o, const doubl
   int head = 0, count = 0;
   const double c1 = 1e-4, dlt = 0.1;
   for (int it = 0; it < o->max_iter; ++it) {
+    if (mode == 2 && o->refresh > 0 && it > 0 && it % o->refresh == 0) {
+      /* H_q of the warm start no longer describes the iterate: re-form it at q
+       * (qfull holds q after an accepted step) and restart the history */
+      inertia_matrix_model(m, i, qfull, &w, L, L + (size_t)nd * nd, L + (size_t)nd * nd + 16 * nd);
+      if (cholesky(L, nd) != 0) {
+        s.flag = 2;
+        break;
+      }
+      count = 0;
+      head = 0;
+    }
     /* two-loop recursion, newest pair first */
     for (int j = 0; j < nd; ++j) d[j] = g[j];
     for (int t = 0; t < count; ++t) {

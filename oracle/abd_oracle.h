@@ -33,6 +33,8 @@ typedef struct {
   double eps_w;    /* working-precision epsilon used by the noise test */
   int precond;     /* initial inverse Hessian H0: 0 gamma*I, 1 gamma*diag(H_q)^-1,
                       2 H_q^-1 (joint-space inertia at the warm start) */
+  int refresh;     /* precond 2, K = 2: every `refresh` iterations re-form H_q at the
+                      current iterate and drop the curvature pairs (0 = never) */
 } orc_opts;
 
 typedef struct {

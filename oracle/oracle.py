@@ -26,12 +26,15 @@ _LIB = os.path.join(_HERE, "liborc.so")
 FLAG_CONVERGED, FLAG_LS_FLOOR, FLAG_MAX_ITER, FLAG_NONFINITE = 1, 2, 4, 8
 EPS64 = 2.0 ** -53
 EPS32 = 2.0 ** -24
+# default period (accepted iterations) at which a step re-forms H_q at the
+# current iterate (the value the GPU library's step options default to)
+REFRESH = 10
 
 
 class OrcOpts(C.Structure):
     _fields_ = [("dt", C.c_double), ("order_K", C.c_int), ("lbfgs_m", C.c_int),
                 ("tol", C.c_double), ("max_iter", C.c_int), ("max_ls", C.c_int),
-                ("eps_w", C.c_double), ("precond", C.c_int)]
+                ("eps_w", C.c_double), ("precond", C.c_int), ("refresh", C.c_int)]
 
 
 class OrcStats(C.Structure):
@@ -207,8 +210,8 @@ class Oracle:
 
     # ------------------------------------------------------------------- step
     def step(self, q_prev, q_curr, dt, tau=None, lbfgs_m=5, tol=1e-8, max_iter=500, max_ls=40,
-             eps_w=EPS64, order_K=2, precond=2):
-        opts = OrcOpts(dt, order_K, lbfgs_m, tol, max_iter, max_ls, eps_w, precond)
+             eps_w=EPS64, order_K=2, precond=2, refresh=REFRESH):
+        opts = OrcOpts(dt, order_K, lbfgs_m, tol, max_iter, max_ls, eps_w, precond, refresh)
         hist = _f64(np.concatenate([q_prev, q_curr]))
         out = np.zeros(self.n_dofs)
         stats = np.zeros(self.n_models, dtype=STATS_DTYPE)
@@ -246,7 +249,7 @@ class Oracle:
                  eps_w=EPS64, precond=2):
         """One Eq. EQHOC step: returns the K-1 unknown configurations [K-1, n] and stats.
         q_prev is the previous step's alpha_{K-2} point, q_curr = q_k."""
-        opts = OrcOpts(dt, K, lbfgs_m, tol, max_iter, max_ls, eps_w, precond)
+        opts = OrcOpts(dt, K, lbfgs_m, tol, max_iter, max_ls, eps_w, precond, 0)
         known = _f64(np.concatenate([q_prev, q_curr]))
         out = np.zeros((K - 1) * self.n_dofs)
         stats = np.zeros(self.n_models, dtype=STATS_DTYPE)

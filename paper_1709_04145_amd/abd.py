@@ -20,6 +20,9 @@ LIB_PATH = os.path.join(HERE, "libabd.so")
 ABD_OK, ABD_EINVAL, ABD_ENOMEM, ABD_EDEVICE, ABD_ENOTSUP = 0, -1, -2, -3, -4
 FP64, MIXED = 0, 1
 PRECOND_IDENTITY, PRECOND_INERTIA = 0, 2
+# default period (accepted iterations) at which a step re-forms its inertia
+# preconditioner at the current iterate
+REFRESH = 10
 FLAG_CONVERGED, FLAG_LS_FLOOR, FLAG_MAX_ITER, FLAG_NONFINITE = 1, 2, 4, 8
 
 
@@ -37,7 +40,7 @@ class ModelDescC(C.Structure):
 class StepOptsC(C.Structure):
     _fields_ = [("dt", C.c_double), ("order_K", C.c_int), ("lbfgs_m", C.c_int),
                 ("tol", C.c_double), ("max_iter", C.c_int), ("max_ls", C.c_int),
-                ("precision", C.c_int), ("precond", C.c_int)]
+                ("precision", C.c_int), ("precond", C.c_int), ("refresh", C.c_int)]
 
 
 STATS_DTYPE = np.dtype([("iterations", np.int32), ("evaluations", np.int32), ("flag", np.int32),
@@ -105,10 +108,11 @@ class StepOptions:
     max_ls: int = 40
     precision: int = FP64
     precond: int = PRECOND_INERTIA
+    refresh: int = REFRESH
 
     def c(self) -> StepOptsC:
         return StepOptsC(self.dt, self.order_K, self.lbfgs_m, self.tol, self.max_iter, self.max_ls,
-                         self.precision, self.precond)
+                         self.precision, self.precond, self.refresh)
 
 
 def _ptr(t: Optional[torch.Tensor]):

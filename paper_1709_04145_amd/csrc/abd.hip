@@ -781,6 +781,7 @@ struct StepArgs {
   DevModel d;
   double dt2, tol;
   int m, max_iter, max_ls, precond;
+  int refresh;                // re-form the inertia preconditioner every `refresh` iterations (0: never)
   int n_steps;                // time steps in this launch
   const double* q_prev;       // q_{-1}
   const double* q_curr;       // q_0
@@ -1084,9 +1085,15 @@ __device__ void aba_solve_tree(const double (*tab)[14], double* xb, const int* p
   }
 }
 
+// Inputs of the inertia preconditioner at configuration q (float64): this
+// frame's world spatial inertia about the origin and its hinge motion.
+template <typename S>
+__device__ __forceinline__ void precond_frame(S& sc, const DevModel& d, double* inert, double* tab,
+                                              const FrameGeo& geo, int f, bool valid, double q0);
+
 // Setup of one step for this wave's model (float64): the per-step constant
 // B = -2 A(q_k) + A(q_{k-1}) of every frame, and for the inertia preconditioner
-// the world spatial inertia (about the origin) and hinge motion at the warm start.
+// its inputs at the warm start.
 template <typename S>
 __device__ __forceinline__ void step_setup(S& sc, const DevModel& d, double* inert, double* tab, const FrameGeo& geo,
                                            int f, bool valid, double qkm1, double qk, double q0, bool use_aba) {
@@ -1108,7 +1115,12 @@ __device__ __forceinline__ void step_setup(S& sc, const DevModel& d, double* ine
         B32[k] = (float)b;
       }
   }
-  if (!use_aba) return;
+  if (use_aba) precond_frame(sc, d, inert, tab, geo, f, valid, q0);
+}
+
+template <typename S>
+__device__ __forceinline__ void precond_frame(S& sc, const DevModel& d, double* inert, double* tab,
+                                              const FrameGeo& geo, int f, bool valid, double q0) {
   const double* a = geo.a;
   const Xf<double> A = fk_geo<double>(sc, geo, valid, q0);
   double M[10];
@@ -1313,11 +1325,30 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
     ys = kMaxHist;
   }
   bool f32 = false, reset = false;
-  int iters = 0, evals = 0, flag = 0, f32_iters = 0, count = 0, head = 0;
+  int iters = 0, evals = 0, flag = 0, f32_iters = 0, count = 0, head = 0, refreshed = 0;
   double q = 0.0, tau = 0.0, E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0;
 #ifdef ABD_PROFILE
   if (lead) abd_prof[(size_t)model * 16 + 10] = __builtin_amdgcn_s_memrealtime();
 #endif
+  // the recursion's tables (and, for one-wave chains, the explicit inverse) once
+  // every frame has written its inputs
+  auto factor_precond = [&]() {
+    if (NW > 1) __threadfence_block();  // inertias go through device memory
+    __syncthreads();
+    PROF_T(t_r);
+    if (lead) {
+      if (TREE)
+        aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
+      else
+        aba_setup(NW == 1 ? &L.inert[0][0] : Hi, L.tab, nf);
+    }
+    __syncthreads();
+    PROF_ADD(2, t_r);
+    PROF_T(t_i);
+    if (NW == 1 && !TREE) aba_inverse(L.tab, nf, lane, Hi);
+    PROF_ADD(3, t_i);
+  };
+  double* const inert = NW == 1 ? L.inert[lane] : Hi + (size_t)(valid ? j : 0) * 10;
 
   while (state != kDone) {
     bool step_done = false;
@@ -1326,25 +1357,13 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
       q = valid ? 2.0 * qk - qkm1 : 0.0;  // warm start: constant-velocity extrapolation
       tau = (valid && args.tau) ? args.tau[(size_t)step * n + io] : 0.0;
       f32 = PREC == ABD_MIXED;
-      iters = 0; evals = 0; flag = 0; f32_iters = 0; count = 0; head = 0; reset = false; gam = 1.0;
+      iters = 0; evals = 0; flag = 0; f32_iters = 0; count = 0; head = 0; refreshed = 0; reset = false; gam = 1.0;
       if (nf == 0) {
         flag = ABD_FLAG_CONVERGED;
         step_done = true;
       } else {
-        double* inert = NW == 1 ? L.inert[lane] : Hi + (size_t)(valid ? j : 0) * 10;
         step_setup(sc, d, inert, L.tab[j], geo, f, valid, qkm1, qk, q, use_aba);
-        if (use_aba) {
-          if (NW > 1) __threadfence_block();  // inertias go through device memory
-          __syncthreads();
-          if (lead) {
-            if (TREE)
-              aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
-            else
-              aba_setup(NW == 1 ? &L.inert[0][0] : Hi, L.tab, nf);
-          }
-          __syncthreads();
-          if (NW == 1 && !TREE) aba_inverse(L.tab, nf, lane, Hi);
-        }
+        if (use_aba) factor_precond();
         PROF_ADD(0, t_s);
         const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(sc, d, geo, f, valid, q, tau, args.dt2)
                                                   : evaluate<double>(sc, d, geo, f, valid, q, tau, args.dt2);
@@ -1370,6 +1389,20 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
         }
       }
     } else {
+      if (use_aba && args.refresh > 0 && iters > 0 && iters % args.refresh == 0 && iters != refreshed) {
+        // the inertia of the warm start no longer describes the iterate: re-form
+        // the preconditioner at q and restart the curvature history
+        refreshed = iters;
+        PROF_T(t_f);
+        precond_frame(sc, d, inert, L.tab[j], geo, f, valid, q);
+        factor_precond();
+        count = 0;
+        head = 0;
+        PROF_ADD(4, t_f);
+#ifdef ABD_PROFILE
+        if (lead) abd_prof[(size_t)model * 16 + 8] += 1;
+#endif
+      }
       PROF_T(t_a);
       // ---- two-loop recursion: newest pair first; the next pair is requested
       // while the current one is used
@@ -2576,6 +2609,7 @@ int check_opts(const abd_step_opts* o, bool for_step) {
   if (o->max_ls < 1 || o->max_ls > 60) return fail(ABD_EINVAL, "max_ls must be in 1..60");
   if (o->precond != ABD_PRECOND_IDENTITY && o->precond != ABD_PRECOND_INERTIA)
     return fail(ABD_EINVAL, "precond must be ABD_PRECOND_IDENTITY or ABD_PRECOND_INERTIA");
+  if (o->refresh < 0) return fail(ABD_EINVAL, "refresh must be >= 0");
   return ABD_OK;
 }
 
@@ -2928,6 +2962,7 @@ static int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_
   a.max_iter = o->max_iter;
   a.max_ls = o->max_ls;
   a.precond = o->precond;
+  a.refresh = o->refresh;
   a.n_steps = n_steps;
   a.q_prev = q_prev;
   a.q_curr = q_curr;
