@@ -64,6 +64,7 @@ constexpr int kWave = 64;
 constexpr int kMaxFrames = 64;  // frames (DOFs) per wavefront
 constexpr int kMaxWaves = 16;   // wavefronts per model (at most 1024 frames)
 constexpr int kMaxHist = 10;    // longest L-BFGS history
+constexpr int kTab = 13;        // recursion record per frame: s (6), U (6), 1/D
 
 // Optional per-phase cycle counters (build with -DABD_PROFILE): lane 0 of every
 // model wave accumulates s_memtime deltas into abd_prof[model][slot].
@@ -344,6 +345,9 @@ __device__ __forceinline__ constexpr int sym4(int x, int y) {
 struct DevModel {
   int n_models, n_dofs;
   const int* f0;            // [n_models+1] first frame (= DOF) of every model
+  const int* order;         // [n_models] model of every workgroup of a rollout: most frames
+                            // first, so the longest solves start first and the dispatcher's
+                            // round robin spreads them over the XCDs
   // per-frame records (array of structures: one pointer per lane, immediate offsets)
   //   fr: axis (3), joint offset (3, nonzero only on a link's first frame),
   //       mass moment upper triangle (10, nonzero only on a link's last frame)
@@ -353,8 +357,10 @@ struct DevModel {
   double* B64;              // [n_dofs][12] per-step constant -2 A(q_k) + A(q_{k-1})
   float* B32;               // [n_dofs][12]
   const long long* hoff;    // [n_models+1] start of every model's block in hinv
-  double* hinv;             // per model: nf x nf inverse joint-space inertia at the warm
-                            // start (nf <= 64), else the frames' spatial inertias [nf][10]
+  double* hinv;             // per model: chains of more than 64 frames, the frames' spatial
+                            // inertias [nf][10]; branched models, those and the recursion's
+                            // accumulators [nf][31]; nothing for one-wave chains (their
+                            // explicit inverse lives in LDS)
   double* hist;             // models of more than 64 frames: [n_dofs][2*kMaxHist] L-BFGS
                             // pairs, s ring then y ring
   // frames are stored in depth-first preorder of the links (the identity for chains)
@@ -791,17 +797,18 @@ struct StepArgs {
 };
 
 // Per-model LDS of the rollout kernel (one model per workgroup of NW waves):
-//   tab:   per frame s (6 = world hinge motion (w; p x w)), U (6 = I^A s), 1/D, unused
-//   inert: per frame world spatial inertia about the origin (J 6, h 3, m);
-//          NW > 1 keeps it in the model's device scratch instead
+//   tab:   per frame s (6 = world hinge motion (w; p x w)), U (6 = I^A s), 1/D
+//   inert: per frame world spatial inertia about the origin (J 6, h 3, m), for
+//          one-wave trees; one-wave chains keep it in the LDS of their explicit
+//          inverse, NW > 1 in the model's device scratch
 //   xb:    NW > 1: the vector swept by the recursion
 //   xch:   scan exchange areas of BlockScan
 //   branched models (TREE): pointer-jumping buffers of TreeScan (tq, tv, tanc),
 //   frame parents (tpar) and the sweep accumulators (acc)
 template <int NW, bool TREE = false>
 struct RollLds {
-  double tab[kMaxFrames * NW][14];
-  double inert[NW == 1 ? kMaxFrames : 1][10];
+  double tab[kMaxFrames * NW][kTab];
+  double inert[(NW == 1 && TREE) ? kMaxFrames : 1][10];  // one-wave chains: in the inverse's LDS
   double rho[kMaxHist];  // 1/(s_i.y_i), newest first
   double alp[kMaxHist];  // two-loop coefficients
   double xb[(NW == 1 && !TREE) ? 1 : kMaxFrames * NW];
@@ -820,7 +827,7 @@ using ModelLds = RollLds<1, false>;
 // The 6x6 symmetric P is held in registers as ww (6: 00 01 02 11 12 22),
 // wv (3x3 row-major), vv (6).  The LDS inputs of frame f-1 are read while
 // frame f is processed.
-__device__ void aba_setup(const double* inert, double (*tab)[14], int nf) {
+__device__ void aba_setup(const double* inert, double (*tab)[kTab], int nf) {
   if (nf <= 0) return;
   double P[21];
 #pragma unroll
@@ -873,88 +880,95 @@ __device__ void aba_setup(const double* inert, double (*tab)[14], int nf) {
   }
 }
 
-// Explicit inverse of the joint-space inertia from the recursion above: lane j
-// solves H x = e_j with the two sweeps
+// Explicit inverse of the joint-space inertia of a one-wave chain, kept in LDS
+// as the packed upper triangle: entry (i, j), i <= j, at tri(j) + i, so column
+// j of the triangle is contiguous.  Lane j solves H x = e_j with the two sweeps
 //   backward  u_f = b_f - s_f.p,   p <- p + U_f u_f / D_f,
 //   forward   x_f = (u_f - U_f.a) / D_f,  a <- a + s_f x_f,
-// all lanes walking the frames together (the records are LDS broadcasts).  u
-// is parked in the output column Hi[f][j] and overwritten by x; every lane
-// touches only its own column, so no other lane's stores have to be seen.
-constexpr int kInvChunk = 4;  // frames whose parked u are loaded ahead
+// all lanes walking the frames together (the records are LDS broadcasts).  The
+// right-hand side vanishes beyond frame j, so p stays zero there and u_f = 0
+// for f > j: lane j's nonzero u_f are exactly its own packed column, where they
+// are parked and then overwritten by x_f (f <= j); the entries x_f, f > j, are
+// those of the columns of the other lanes (H^-1 is symmetric).
+__device__ __forceinline__ int tri(int j) { return (j * (j + 1)) >> 1; }
 
-__device__ void aba_inverse(const double (*tab)[14], int nf, int lane, double* Hi) {
+// LDS doubles of the packed inverse, which also holds the per-frame inertia
+// inputs of the recursion (10 per frame) before the inverse is formed.
+__host__ __device__ constexpr int inverse_lds_doubles(int nf) {
+  return (nf * (nf + 1) / 2 > 10 * kMaxFrames) ? nf * (nf + 1) / 2 : 10 * kMaxFrames;
+}
+
+__device__ void aba_inverse(const double (*tab)[kTab], int nf, int lane, double* P) {
   const bool act = lane < nf;
+  const int col = act ? lane : nf - 1;
+  const int base = tri(col);  // lanes without a frame address the last column (in bounds, never stored)
+  // the record of the next frame is read while the current one is used
+  double t[kTab], tn[kTab];
+#pragma unroll
+  for (int k = 0; k < kTab; ++k) tn[k] = tab[nf - 1][k];
   double p[6] = {0, 0, 0, 0, 0, 0};
   for (int f = nf - 1; f >= 0; --f) {
-    const double* t = tab[f];
+#pragma unroll
+    for (int k = 0; k < kTab; ++k) t[k] = tn[k];
+    const int fn = f > 0 ? f - 1 : 0;
+#pragma unroll
+    for (int k = 0; k < kTab; ++k) tn[k] = tab[fn][k];
     const double sp = (t[0] * p[0] + t[1] * p[1]) + (t[2] * p[2] + t[3] * p[3]) + (t[4] * p[4] + t[5] * p[5]);
     const double u = (f == lane ? 1.0 : 0.0) - sp;
-    if (act) Hi[(size_t)f * nf + lane] = u;
+    if (act && f <= lane) P[base + f] = u;
     const double w = u * t[12];
 #pragma unroll
     for (int k = 0; k < 6; ++k) p[k] += t[6 + k] * w;
   }
+  // tn holds frame 0's record now
   double a[6] = {0, 0, 0, 0, 0, 0};
-  // chunks of kInvChunk frames; the parked u of the next chunk are requested
-  // before the current chunk is solved
-  double un[kInvChunk];
-  const int col = lane < nf ? lane : nf - 1;  // clamped: every lane loads inside the block
+  double un = ld_if(P + base, act);
+  for (int f = 0; f < nf; ++f) {
 #pragma unroll
-  for (int k = 0; k < kInvChunk; ++k) un[k] = ld_if(Hi + (size_t)(k < nf ? k : nf - 1) * nf + col, act && k < nf);
-  for (int c0 = 0; c0 < nf; c0 += kInvChunk) {
-    double uc[kInvChunk];
+    for (int k = 0; k < kTab; ++k) t[k] = tn[k];
+    const double uf = un;
+    const int fn = f + 1 < nf ? f + 1 : f;
 #pragma unroll
-    for (int k = 0; k < kInvChunk; ++k) {
-      uc[k] = un[k];
-      const int fn = c0 + kInvChunk + k;
-      un[k] = ld_if(Hi + (size_t)(fn < nf ? fn : nf - 1) * nf + col, act && fn < nf);
-    }
+    for (int k = 0; k < kTab; ++k) tn[k] = tab[fn][k];
+    un = ld_if(P + base + (fn <= col ? fn : col), act && fn <= lane);
+    const double Ua = (t[6] * a[0] + t[7] * a[1]) + (t[8] * a[2] + t[9] * a[3]) + (t[10] * a[4] + t[11] * a[5]);
+    const double x = ((act && f <= lane ? uf : 0.0) - Ua) * t[12];
+    if (act && f <= lane) P[base + f] = x;
 #pragma unroll
-    for (int k = 0; k < kInvChunk; ++k) {
-      const int f = c0 + k;
-      if (f < nf) {
-        const double* t = tab[f];
-        const double Ua = (t[6] * a[0] + t[7] * a[1]) + (t[8] * a[2] + t[9] * a[3]) + (t[10] * a[4] + t[11] * a[5]);
-        const double x = (uc[k] - Ua) * t[12];
-        if (act) Hi[(size_t)f * nf + lane] = x;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) a[i] += t[i] * x;
-      }
-    }
+    for (int i = 0; i < 6; ++i) a[i] += t[i] * x;
   }
 }
 
-// r_j = sum_i Hi[i][j] v_i: the preconditioner applied to the wave's vector v
-// (lane i holds v_i).  Column j lives in lane j's own stores of aba_inverse.
-constexpr int kMvChunk = 8;
+// r_j = sum_i (H^-1)_ij v_i: the preconditioner applied to the wave's vector v
+// (lane i holds v_i), reading the packed triangle: (i, j) from column j for
+// i <= j, from column i (symmetry) otherwise; eight reads are issued at a time.
+constexpr int kMvBatch = 8;
 
-__device__ __forceinline__ double apply_inverse(const double* Hi, int nf, int lane, double v) {
+__device__ __forceinline__ double apply_inverse(const double* P, int nf, int lane, double v) {
   const bool act = lane < nf;
+  const int col = act ? lane : nf - 1;
+  const int base = tri(col);
   double r = 0.0;
-  double hn[kMvChunk];
-  const int col = lane < nf ? lane : nf - 1;  // clamped: every lane loads inside the block
+  int i0 = 0;
+  for (; i0 + kMvBatch <= nf; i0 += kMvBatch) {
+    double h[kMvBatch];
 #pragma unroll
-  for (int k = 0; k < kMvChunk; ++k) hn[k] = ld_if(Hi + (size_t)(k < nf ? k : nf - 1) * nf + col, act && k < nf);
-  for (int i0 = 0; i0 < nf; i0 += kMvChunk) {
-    double hc[kMvChunk];
-#pragma unroll
-    for (int k = 0; k < kMvChunk; ++k) {
-      hc[k] = hn[k];
-      const int in = i0 + kMvChunk + k;
-      hn[k] = ld_if(Hi + (size_t)(in < nf ? in : nf - 1) * nf + col, act && in < nf);
+    for (int k = 0; k < kMvBatch; ++k) {
+      const int i = i0 + k;
+      h[k] = P[i <= col ? base + i : tri(i) + col];
     }
 #pragma unroll
-    for (int k = 0; k < kMvChunk; ++k)
-      if (i0 + k < nf) r += hc[k] * readlane(v, i0 + k);
+    for (int k = 0; k < kMvBatch; ++k) r += h[k] * readlane(v, i0 + k);
   }
-  return r;
+  for (; i0 < nf; ++i0) r += P[i0 <= col ? base + i0 : tri(i0) + col] * readlane(v, i0);
+  return act ? r : 0.0;
 }
 
 // x = H^{-1} b in O(n) by one thread (models of more than one wave): backward
 // sweep u_f = b_f - s_f.p, p <- p + U_f u_f / D_f; forward sweep
 // x_f = (u_f - U_f.a) / D_f, a <- a + s_f x_f; in place in xb (LDS).  The
 // record of the next frame is read while the current one is used.
-__device__ void aba_solve(const double (*tab)[14], double* xb, int nf) {
+__device__ void aba_solve(const double (*tab)[kTab], double* xb, int nf) {
   if (nf <= 0) return;
   double p[6] = {0, 0, 0, 0, 0, 0};
   double t[13], b;
@@ -1003,7 +1017,7 @@ __device__ void aba_solve(const double (*tab)[14], double* xb, int nf) {
 //   I^A_f = I_f + sum_children P_c,  U_f = I^A_f s_f,  D_f = s_f.U_f,
 //   P_f = I^A_f - U_f U_f^T / D_f;
 // pacc [nf][21] (device scratch) holds the accumulated children's P.
-__device__ void aba_setup_tree(const double* inert, double (*tab)[14], const int* parent, double* pacc, int nf) {
+__device__ void aba_setup_tree(const double* inert, double (*tab)[kTab], const int* parent, double* pacc, int nf) {
   for (int f = 0; f < nf; ++f)
     for (int k = 0; k < 21; ++k) pacc[f * 21 + k] = 0.0;
   for (int f = nf - 1; f >= 0; --f) {
@@ -1053,7 +1067,7 @@ __device__ void aba_setup_tree(const double* inert, double (*tab)[14], const int
 // in reverse preorder u_f = b_f - s_f.p_f, p_parent += p_f + U_f u_f / D_f;
 // forward sweep in preorder x_f = (u_f - U_f.a_parent) / D_f, a_f = a_parent + s_f x_f.
 // acc [nf][6] (LDS) holds p, then a.
-__device__ void aba_solve_tree(const double (*tab)[14], double* xb, const int* parent, double (*acc)[6], int nf) {
+__device__ void aba_solve_tree(const double (*tab)[kTab], double* xb, const int* parent, double (*acc)[6], int nf) {
   for (int f = 0; f < nf; ++f)
     for (int k = 0; k < 6; ++k) acc[f][k] = 0.0;
   for (int f = nf - 1; f >= 0; --f) {
@@ -1274,16 +1288,18 @@ template <int NW, int PREC, bool TREE>
 __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD)) k_rollout(StepArgs args) {
   __shared__ RollLds<NW, TREE> L;
   // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
-  // y in [m, 2m), one double per lane per slot
+  // y in [m, 2m), one double per lane per slot; one-wave chains: then the
+  // packed explicit inverse (inverse_lds_doubles(max frames))
   extern __shared__ double pairs[];
+  double* const hl = pairs + 2 * args.m * kWave;
   const DevModel& d = args.d;
   const int n = d.n_dofs;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int j = threadIdx.x;  // frame of this thread within the model
   const bool lead = threadIdx.x == 0;
-  const int model = blockIdx.x;
-  const bool has_model = model < d.n_models;
+  const bool has_model = blockIdx.x < d.n_models;
   if (!has_model) return;
+  const int model = d.order[blockIdx.x];
   const int f0 = d.f0[model];
   const int nf = d.f0[model + 1] - f0;
   if (nf == 0) {  // a model without frames: every step is trivially converged
@@ -1340,15 +1356,18 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
       if (TREE)
         aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
       else
-        aba_setup(NW == 1 ? &L.inert[0][0] : Hi, L.tab, nf);
+        aba_setup(NW == 1 ? hl : Hi, L.tab, nf);
     }
     __syncthreads();
     PROF_ADD(2, t_r);
     PROF_T(t_i);
-    if (NW == 1 && !TREE) aba_inverse(L.tab, nf, lane, Hi);
+    if (NW == 1 && !TREE) {
+      aba_inverse(L.tab, nf, lane, hl);  // overwrites the inertias
+      __syncthreads();  // every lane reads the other lanes' columns
+    }
     PROF_ADD(3, t_i);
   };
-  double* const inert = NW == 1 ? L.inert[lane] : Hi + (size_t)(valid ? j : 0) * 10;
+  double* const inert = NW == 1 ? (TREE ? L.inert[lane] : hl + 10 * lane) : Hi + (size_t)(valid ? j : 0) * 10;
 
   while (state != kDone) {
     bool step_done = false;
@@ -1427,7 +1446,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
       if (!use_aba) {
         r = (count > 0 ? gam : 1.0) * qv;
       } else if (NW == 1 && !TREE) {
-        r = apply_inverse(Hi, nf, lane, qv);
+        r = apply_inverse(hl, nf, lane, qv);
       } else {
         L.xb[j] = valid ? qv : 0.0;
         __syncthreads();
@@ -1813,6 +1832,7 @@ struct VjpArgs {
 
 __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
   __shared__ ModelLds L;
+  extern __shared__ double hl[];  // packed explicit inverse (inverse_lds_doubles(max frames))
   const DevModel& d = args.d;
   const int n = d.n_dofs, T = args.n_steps;
   const int model = blockIdx.x, lane = threadIdx.x;
@@ -1828,7 +1848,6 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
   const bool valid = lane < nf;
   const int f = f0 + (valid ? lane : 0);
   const FrameGeo geo = load_geo(d, f, valid);
-  double* Hi = d.hinv + d.hoff[model];
   const bool use_aba = args.use_aba != 0;
   WaveScan ws;
   // q_j and the explicit dL/dq_j of this lane's DOF, j >= -1
@@ -1843,18 +1862,19 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
     double mu = 0.0, rn = 0.0;
     int it = 0, hv_count = 0, flag = ABD_FLAG_CONVERGED;
     if (nf > 0) {
-      step_setup(ws, d, L.inert[lane], L.tab[lane], geo, f, valid, qp, qc, q, use_aba);
+      step_setup(ws, d, hl + 10 * lane, L.tab[lane], geo, f, valid, qp, qc, q, use_aba);
       if (use_aba) {
         __syncthreads();
-        if (lane == 0) aba_setup(&L.inert[0][0], L.tab, nf);
+        if (lane == 0) aba_setup(hl, L.tab, nf);
         __syncthreads();
-        aba_inverse(L.tab, nf, lane, Hi);
+        aba_inverse(L.tab, nf, lane, hl);  // overwrites the inertias
+        __syncthreads();  // every lane reads the other lanes' columns
       }
       // ---- preconditioned conjugate gradients on H mu = lambda
       const double b = valid ? lam_next : 0.0;
       const double bn = uniform(sqrt(wave_sum(b * b)));
       double r = b;
-      double z = use_aba ? apply_inverse(Hi, nf, lane, r) : r;
+      double z = use_aba ? apply_inverse(hl, nf, lane, r) : r;
       double p = z;
       double rz = uniform(wave_sum(r * z));
       rn = bn;
@@ -1879,7 +1899,7 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
             flag = ABD_FLAG_CONVERGED;
             break;
           }
-          z = use_aba ? apply_inverse(Hi, nf, lane, r) : r;
+          z = use_aba ? apply_inverse(hl, nf, lane, r) : r;
           const double rz1 = uniform(wave_sum(r * z));
           p = z + (rz1 / rz) * p;
           rz = rz1;
@@ -2112,14 +2132,17 @@ __device__ double hoc_evaluate(Sc& sc, const HocArgs<U>& args, const FrameGeo& g
 template <int NW, bool TREE, int U>
 __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
   __shared__ RollLds<NW, TREE> L;
-  extern __shared__ double pairs[];  // one-wave chains: s ring [m][U][64], then y ring
+  // one-wave models: s ring [m][U][64], then y ring; one-wave chains: then the
+  // packed explicit inverse (inverse_lds_doubles(max frames))
+  extern __shared__ double pairs[];
+  double* const hl = pairs + 2 * args.m * U * kWave;
   const DevModel& d = args.d;
   const int n = d.n_dofs;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int j = threadIdx.x;
   const bool lead = threadIdx.x == 0;
-  const int model = blockIdx.x;
-  if (model >= d.n_models) return;
+  if (blockIdx.x >= d.n_models) return;
+  const int model = d.order[blockIdx.x];
   const int f0 = d.f0[model];
   const int nf = d.f0[model + 1] - f0;
   if (nf == 0) {
@@ -2177,7 +2200,7 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
               args.Bk[(size_t)f * (12 * U) + 12 * u + k] = args.w[u][0] * Ap.m[k] + args.w[u][1] * Ak.m[k];
       }
       if (use_aba) {
-        double* inert = NW == 1 ? L.inert[lane] : Hi + (size_t)(valid ? j : 0) * 10;
+        double* inert = NW == 1 ? (TREE ? L.inert[lane] : hl + 10 * lane) : Hi + (size_t)(valid ? j : 0) * 10;
         step_setup(ws, d, inert, L.tab[j], geo, f, valid, qprev, qk, qk, true);
         if (NW > 1) __threadfence_block();
         __syncthreads();
@@ -2185,10 +2208,13 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           if (TREE)
             aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
           else
-            aba_setup(NW == 1 ? &L.inert[0][0] : Hi, L.tab, nf);
+            aba_setup(NW == 1 ? hl : Hi, L.tab, nf);
         }
         __syncthreads();
-        if (explicit_inverse) aba_inverse(L.tab, nf, lane, Hi);
+        if (explicit_inverse) {
+          aba_inverse(L.tab, nf, lane, hl);  // overwrites the inertias
+          __syncthreads();  // every lane reads the other lanes' columns
+        }
       }
       E = hoc_evaluate<U>(ws, args, geo, f, valid, q, tau, g);
       ++evals;
@@ -2228,7 +2254,7 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           double y[U];
           if (explicit_inverse) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) y[u] = apply_inverse(Hi, nf, lane, apply_inverse(Hi, nf, lane, qv[u]));
+            for (int u = 0; u < U; ++u) y[u] = apply_inverse(hl, nf, lane, apply_inverse(hl, nf, lane, qv[u]));
           } else {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -2491,6 +2517,7 @@ struct abd_model {
   double g[3] = {0, 0, 0};
   // device buffers
   int* f0 = nullptr;
+  int* order = nullptr;
   int* pose_link = nullptr;
   double* fr64 = nullptr;
   float* fr32 = nullptr;
@@ -2573,6 +2600,7 @@ DevModel dev_view(const abd_model* m) {
   d.n_models = m->n_models;
   d.n_dofs = m->n_dofs;
   d.f0 = m->f0;
+  d.order = m->order;
   d.fr64 = m->fr64;
   d.fr32 = m->fr32;
   d.pose_link = m->pose_link;
@@ -2742,14 +2770,19 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
     fr64.swap(r);
     pose_link.swap(pl);
   }
-  // per-model preconditioner scratch: the explicit inverse inertia (nf x nf) of
-  // a one-wave chain, the per-frame spatial inertias (10 nf) of a longer chain,
-  // inertias and recursion accumulators (31 nf) of a branched model
+  // per-model preconditioner scratch: the per-frame spatial inertias (10 nf) of
+  // a chain longer than one wave, inertias and recursion accumulators (31 nf) of
+  // a branched model (one-wave chains keep theirs in LDS)
   std::vector<long long> hoff(nm + 1, 0);
   for (int i = 0; i < nm; ++i) {
     const long long k = f0[i + 1] - f0[i];
-    hoff[i + 1] = hoff[i] + (!chain ? 31 * k : k <= kMaxFrames ? k * k : 10 * k);
+    hoff[i + 1] = hoff[i] + (!chain ? 31 * k : k <= kMaxFrames ? 0 : 10 * k);
   }
+
+  std::vector<int> order(nm);
+  for (int i = 0; i < nm; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return f0[a + 1] - f0[a] > f0[b + 1] - f0[b]; });
 
   abd_model* m = new abd_model();
   HIP_TRY(hipGetDevice(&m->device));
@@ -2762,7 +2795,8 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   for (int k = 0; k < 3; ++k) m->g[k] = desc->gravity[k];
   std::vector<float> fr32(fr64.begin(), fr64.end());
   int rc = ABD_OK;
-  if ((rc = upload(m, &m->f0, f0)) || (rc = upload(m, &m->pose_link, pose_link)) ||
+  if ((rc = upload(m, &m->f0, f0)) || (rc = upload(m, &m->order, order)) ||
+      (rc = upload(m, &m->pose_link, pose_link)) ||
       (rc = upload(m, &m->fr64, fr64)) || (rc = upload(m, &m->fr32, fr32)) ||
       (rc = alloc(m, &m->B64, 12 * (size_t)nd)) || (rc = alloc(m, &m->B32, 12 * (size_t)nd)) ||
       (rc = upload(m, &m->hoff, hoff)) || (rc = upload(m, &m->uidx, uidx)) ||
@@ -2918,7 +2952,8 @@ static int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int U = o->order_K - 1;
   const int nw = waves_for(m->max_frames);
-  const size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * U * kWave * sizeof(double) : 0;
+  size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * U * kWave * sizeof(double) : 0;
+  if (nw == 1 && !m->tree) pair_bytes += (size_t)inverse_lds_doubles(m->max_frames) * sizeof(double);
   const dim3 grid(m->n_models), block(nw * kWave);
 #define ABD_HOC(NW, TREE, UU)                                                                  \
   do {                                                                                         \
@@ -2972,7 +3007,8 @@ static int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nw = waves_for(m->max_frames);
   const dim3 grid(m->n_models), block(nw * kWave);
-  const size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * kWave * sizeof(double) : 0;
+  size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * kWave * sizeof(double) : 0;
+  if (nw == 1 && !m->tree) pair_bytes += (size_t)inverse_lds_doubles(m->max_frames) * sizeof(double);
   const bool f64 = o->precision == ABD_FP64;
 #define ABD_LAUNCH(NW, TREE)                                                                \
   do {                                                                                      \
@@ -3174,7 +3210,8 @@ int abd_rollout_vjp(abd_model* m, const abd_step_opts* o, const double* q_init, 
   a.dL_dinit = dL_dq_init;
   a.dL_dtau = dL_dtau;
   a.stats = stats;
-  hipLaunchKernelGGL(k_rollout_vjp, dim3(m->n_models), dim3(kWave), 0, static_cast<hipStream_t>(stream), a);
+  hipLaunchKernelGGL(k_rollout_vjp, dim3(m->n_models), dim3(kWave),
+                     (size_t)inverse_lds_doubles(m->max_frames) * sizeof(double), static_cast<hipStream_t>(stream), a);
   HIP_TRY(hipGetLastError());
   return ABD_OK;
 }

@@ -4,10 +4,13 @@ GPU against the FP64 CPU oracle.
   * objective and gradient: E is a sum of squared residuals that are themselves
     cancelling sums, so E is compared to 1e-10 relative and the gradient to 1e-9
     relative to its largest component;
-  * one step: both sides solve to a relative gradient tolerance of 1e-10; the
-    oracle's own results at 1e-10 and at its float64 floor differ by up to
-    1.3e-8 on these chains (the squared residual makes the problem worse
-    conditioned than Eq. EQ), so the bound is 1e-7 on all K-1 configurations;
+  * one step: both sides solve to a relative gradient tolerance of 1e-10.  A
+    step is determined only to its tolerance, and the squared residual makes
+    Eq. EQHOC far worse conditioned than Eq. EQ, so the check is what the
+    tolerance implies: the oracle's gradient at the GPU's configurations is
+    within the tolerance, and the GPU's and the oracle's configurations are
+    within |H^-1| (|g_gpu| + |g_oracle|) of each other (H = the oracle's
+    Hessian of Eq. EQHOC by central differences of its gradient);
   * a rollout in one launch equals the loop of single steps bit for bit.
 """
 import numpy as np
@@ -32,6 +35,46 @@ def gpu():
 
 def _rel(a, b):
     return float(np.max(np.abs(a - b)) / max(1e-300, float(np.max(np.abs(b))))) if a.size else 0.0
+
+
+def _check_tolerance_implied(d, K, dt, tol, q0, got, ref):
+    """The GPU's step result `got` and the oracle's `ref` (both [K-1, n], from the
+    zero-velocity known points q0, q0) are what a relative gradient tolerance
+    `tol` allows: the oracle's gradient at `got` is within the tolerance, and
+    |got - ref| <= 1.5 |H^-1| (|g(got)| + |g(ref)|) per model."""
+    orc = Oracle(d)
+    _, g_gpu = orc.eqhoc_objective_grad(K, dt, q0, q0, got)
+    _, g_ref = orc.eqhoc_objective_grad(K, dt, q0, q0, ref)
+    _, g_warm = orc.eqhoc_objective_grad(K, dt, q0, q0, np.tile(q0, (K - 1, 1)))
+    # Hessian of every model at the oracle's solution by central differences;
+    # all models are perturbed at once in their j-th coordinate (they are independent)
+    do = d.dof_offset
+    nmax = int(np.max(np.diff(do)))
+    h = 1e-6
+    H = [np.zeros(((K - 1) * (do[i + 1] - do[i]),) * 2) for i in range(d.n_models)]
+    for u in range(K - 1):
+        for jj in range(nmax):
+            idx = [do[i] + jj for i in range(d.n_models) if do[i] + jj < do[i + 1]]
+            qp_, qm_ = ref.copy(), ref.copy()
+            qp_[u, idx] += h
+            qm_[u, idx] -= h
+            _, gp = orc.eqhoc_objective_grad(K, dt, q0, q0, qp_)
+            _, gm = orc.eqhoc_objective_grad(K, dt, q0, q0, qm_)
+            col = (gp - gm) / (2 * h)
+            for i in range(d.n_models):
+                ni = do[i + 1] - do[i]
+                if jj < ni:
+                    H[i][:, u * ni + jj] = col[:, do[i]:do[i + 1]].reshape(-1)
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        lam_min = float(np.min(np.linalg.eigvalsh(0.5 * (H[i] + H[i].T))))
+        assert lam_min > 0.0, (i, lam_min)
+        gi, ri, wi = (float(np.linalg.norm(x[:, sl])) for x in (g_gpu, g_ref, g_warm))
+        assert gi <= 2.0 * tol * wi, (i, gi / wi)
+        dist = float(np.linalg.norm(got[:, sl] - ref[:, sl]))
+        bound = 1.5 * (gi + ri) / lam_min
+        say(f"  model {i}: |q_gpu - q_oracle| {dist:.2e}, tolerance-implied bound {bound:.2e}")
+        assert dist <= bound + 1e-14, (i, dist, bound)
 
 
 @pytest.mark.parametrize("K", [3, 4])
@@ -70,9 +113,7 @@ def test_eqhoc_step_matches_oracle(K):
     st = m.read_stats(st, d.n_models)
     assert np.all(st["flag"] == abd.FLAG_CONVERGED), st["flag"]
     assert np.all(rst["flag"] == 1)
-    got = out.cpu().numpy()
-    err = float(np.max(np.abs(got - ref))) / max(1.0, float(np.max(np.abs(ref))))
-    assert err <= 1e-7, err
+    _check_tolerance_implied(d, K, dt, tol, q0, out.cpu().numpy(), ref)
 
 
 def test_eqhoc_rollout_equals_step_loop_bitwise():
@@ -142,6 +183,4 @@ def test_eqhoc_tree_step_matches_oracle():
     torch.cuda.synchronize()
     st = m.read_stats(st, d.n_models)
     assert np.all(st["flag"] == abd.FLAG_CONVERGED), st["flag"]
-    got = out.cpu().numpy()
-    err = float(np.max(np.abs(got - ref))) / max(1.0, float(np.max(np.abs(ref))))
-    assert err <= 1e-7, err
+    _check_tolerance_implied(d, K, dt, tol, q0, out.cpu().numpy(), ref)
