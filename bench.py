@@ -18,8 +18,8 @@ Also reported:
                over the launch's duration measured with HIP events on the
                launch stream, against the 8 TB/s HBM peak;
   parity       one teacher-forced step from the final state on a sample of
-               models against the float64 CPU oracle, both solved to a 1e-11
-               relative gradient: q and pose errors over the models where both
+               models against the float64 CPU oracle, both solved to a 1e-12
+               relative gradient (at most 2000 iterations): q and pose errors over the models where both
                sides converge to the same minimum (equal objective to 1e-9 of
                its scale); the step objective is non-convex on this workload,
                so models where the two reach different local minima, and
@@ -54,6 +54,11 @@ SETUP_BYTES = 328                       # per step: read q_{k-1}, q_k, axis/offs
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_rollout_chains4096_hbm_traffic.md")
 
+
+# tolerance of the parity sample: at 1e-12 a step's result is implied to ~3e-11
+# (the oracle's own results at 1e-12 and 1e-13 differ by that), at 1e-11 only to ~1e-9
+PARITY_TOL = 1e-12
+PARITY_MAX_ITER = 2000
 
 def measured_traffic(workload, precision, warmup, steps):
     """HBM bytes of the timed launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
@@ -256,8 +261,8 @@ def main():
         sub = desc.subset(sample)
         idx = desc.dof_subset_index(sample)
         orc = Oracle(sub)
-        ref, rst = orc.step(qp[idx], qc[idx], wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=1e-11,
-                            max_iter=wl.step.max_iter)
+        ref, rst = orc.step(qp[idx], qc[idx], wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=PARITY_TOL,
+                            max_iter=PARITY_MAX_ITER)
         hist = torch.tensor(np.concatenate([qp, qc]), dtype=torch.float64, device="cuda")
         E_ref, _, S_ref = orc.objective_grad(ref, qp[idx], qc[idx], wl.step.dt)
         do = sub.dof_offset
@@ -265,7 +270,8 @@ def main():
         for name, prec in (("fp64", abd.FP64), ("mixed", abd.MIXED)):
             o = torch.zeros(desc.n_dofs, dtype=torch.float64, device="cuda")
             st = model.new_stats()
-            model.step(hist, o, abd.StepOptions(precision=prec, **dict(base, tol=1e-11)), stats=st)
+            model.step(hist, o, abd.StepOptions(precision=prec, **dict(base, tol=PARITY_TOL, max_iter=PARITY_MAX_ITER)),
+                       stats=st)
             torch.cuda.synchronize()
             gst = model.read_stats(st, desc.n_models)[sample]
             qg = o.cpu().numpy()[idx]
@@ -285,7 +291,7 @@ def main():
                          "max_rel_objective_gap_distinct": float(np.max(np.abs(E_g - E_ref)[distinct] / S_ref[distinct]))
                          if distinct.any() else 0.0,
                          "models_not_converged": int((~conv).sum())}
-        out["parity"] = {"sample_models": int(len(sample)), "tol": 1e-11, **par}
+        out["parity"] = {"sample_models": int(len(sample)), "tol": PARITY_TOL, **par}
 
     if not args.no_cpu and K == 2:
         from oracle.oracle import Oracle

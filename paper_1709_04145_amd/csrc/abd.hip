@@ -809,7 +809,7 @@ template <int NW, bool TREE = false>
 struct RollLds {
   double tab[kMaxFrames * NW][kTab];
   double inert[(NW == 1 && TREE) ? kMaxFrames : 1][10];  // one-wave chains: in the inverse's LDS
-  double rho[kMaxHist];  // 1/(s_i.y_i), newest first
+  double rho[kMaxHist];  // 1/(s_i.y_i): k_rollout by ring slot of the pair, others newest first
   double alp[kMaxHist];  // two-loop coefficients
   double xb[(NW == 1 && !TREE) ? 1 : kMaxFrames * NW];
   double xch[2][NW][8];
@@ -821,62 +821,81 @@ struct RollLds {
 };
 using ModelLds = RollLds<1, false>;
 
-// Articulated inertias at the warm start (once per step, one lane):
+// 1/x for x > 0 from the hardware reciprocal and one Newton step (a few ulp;
+// used where the value only shapes a preconditioner).
+__device__ __forceinline__ double recip(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return y;
+}
+
+// Articulated inertias of a chain at the configuration of the preconditioner,
+// tip to root:
 //   I^A_f = I_f + P_{f+1},  U_f = I^A_f s_f,  D_f = s_f.U_f,
-//   P_f = I^A_f - U_f U_f^T / D_f  (passed to the parent frame).
-// The 6x6 symmetric P is held in registers as ww (6: 00 01 02 11 12 22),
-// wv (3x3 row-major), vv (6).  The LDS inputs of frame f-1 are read while
-// frame f is processed.
-__device__ void aba_setup(const double* inert, double (*tab)[kTab], int nf) {
+//   P_f = I^A_f - U_f U_f^T / D_f  (passed to the parent frame),
+// with the 6x6 algebra spread over lanes: lane
+// r < 6 holds row r of P (full rows), computes U_r = P_r . s, the six U_r are
+// broadcast through scalar registers, D and 1/D are formed on every lane, and
+// each lane updates its row, P_rc <- P_rc - U_r U_c / D.  Entry c of row r of
+// the frame inertia [[J, [h]x], [[h]x^T, m 1]] is a signed pick from the
+// 10-entry record (J 00 01 02 11 12 22, h, m).  The whole wave runs; lanes >= 6
+// shadow row 5 and store nothing.  The next frame's inputs are read while the
+// current one is processed.
+__device__ void aba_setup_rows(const double* inert, double (*tab)[kTab], int nf, int lane) {
   if (nf <= 0) return;
-  double P[21];
+  const int r = lane < 6 ? lane : 5;
+  int idx[6];
+  float sgn[6];  // -1, 0, +1
 #pragma unroll
-  for (int k = 0; k < 21; ++k) P[k] = 0.0;
-  double in[10], s[6];
+  for (int c = 0; c < 6; ++c) {
+    const int a = r < 3 ? r : c, b = r < 3 ? c : r;  // (3x3 block row, column) of the pick
+    if (r < 3 && c < 3) {  // J
+      const int lo = a < b ? a : b, hi = a < b ? b : a;
+      idx[c] = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+      sgn[c] = 1.0f;
+    } else if (r >= 3 && c >= 3) {  // m 1
+      idx[c] = 9;
+      sgn[c] = (r == c) ? 1.0f : 0.0f;
+    } else {  // [h]x (row block 0) or its transpose (row block 1): ([h]x)_{a, b - 3}
+      const int ra = a, cb = b - 3;
+      if (ra == cb) {
+        idx[c] = 9;
+        sgn[c] = 0.0f;
+      } else {
+        idx[c] = 6 + (3 - ra - cb);                 // the remaining component of h
+        sgn[c] = (cb == (ra + 2) % 3) ? 1.0f : -1.0f;  // (0,2) (1,0) (2,1) positive
+      }
+    }
+  }
+  double P[6] = {0, 0, 0, 0, 0, 0};
+  double in[6], s[6], inn[6], sn[6];
 #pragma unroll
-  for (int k = 0; k < 10; ++k) in[k] = inert[(nf - 1) * 10 + k];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) s[k] = tab[nf - 1][k];
+  for (int c = 0; c < 6; ++c) {
+    inn[c] = (double)sgn[c] * inert[(nf - 1) * 10 + idx[c]];
+    sn[c] = tab[nf - 1][c];
+  }
   for (int f = nf - 1; f >= 0; --f) {
     const int fn = f > 0 ? f - 1 : 0;
-    double inn[10], sn[6];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) inn[k] = inert[fn * 10 + k];
+    for (int c = 0; c < 6; ++c) {
+      in[c] = inn[c];
+      s[c] = sn[c];
+      inn[c] = (double)sgn[c] * inert[fn * 10 + idx[c]];
+      sn[c] = tab[fn][c];
+    }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) sn[k] = tab[fn][k];
-    // add I = [[J, [h]x], [[h]x^T, m 1]]
+    for (int c = 0; c < 6; ++c) P[c] += in[c];
+    const double U = (P[0] * s[0] + P[1] * s[1]) + (P[2] * s[2] + P[3] * s[3]) + (P[4] * s[4] + P[5] * s[5]);
+    double Uc[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) P[k] += in[k];
-    P[7] -= in[8]; P[8] += in[7]; P[9] += in[8]; P[11] -= in[6]; P[12] -= in[7]; P[13] += in[6];
-    P[15] += in[9]; P[18] += in[9]; P[20] += in[9];
-    double U[6];
-    U[0] = P[0] * s[0] + P[1] * s[1] + P[2] * s[2] + P[6] * s[3] + P[7] * s[4] + P[8] * s[5];
-    U[1] = P[1] * s[0] + P[3] * s[1] + P[4] * s[2] + P[9] * s[3] + P[10] * s[4] + P[11] * s[5];
-    U[2] = P[2] * s[0] + P[4] * s[1] + P[5] * s[2] + P[12] * s[3] + P[13] * s[4] + P[14] * s[5];
-    U[3] = P[6] * s[0] + P[9] * s[1] + P[12] * s[2] + P[15] * s[3] + P[16] * s[4] + P[17] * s[5];
-    U[4] = P[7] * s[0] + P[10] * s[1] + P[13] * s[2] + P[16] * s[3] + P[18] * s[4] + P[19] * s[5];
-    U[5] = P[8] * s[0] + P[11] * s[1] + P[14] * s[2] + P[17] * s[3] + P[19] * s[4] + P[20] * s[5];
-    const double D = (s[0] * U[0] + s[1] * U[1]) + (s[2] * U[2] + s[3] * U[3]) + (s[4] * U[4] + s[5] * U[5]);
-    const double iD = (D > 0.0) ? 1.0 / D : 0.0;
+    for (int c = 0; c < 6; ++c) Uc[c] = readlane(U, c);
+    const double D = (s[0] * Uc[0] + s[1] * Uc[1]) + (s[2] * Uc[2] + s[3] * Uc[3]) + (s[4] * Uc[4] + s[5] * Uc[5]);
+    const double iD = (D > 0.0) ? recip(D) : 0.0;
+    if (lane < 6) tab[f][6 + lane] = U;
+    if (lane == 0) tab[f][12] = iD;
+    const double V = U * iD;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) tab[f][6 + k] = U[k];
-    tab[f][12] = iD;
-    // P <- I^A - U U^T / D  (the articulated inertia seen by the parent)
-    double V[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) V[k] = U[k] * iD;
-    P[0] -= U[0] * V[0]; P[1] -= U[0] * V[1]; P[2] -= U[0] * V[2];
-    P[3] -= U[1] * V[1]; P[4] -= U[1] * V[2]; P[5] -= U[2] * V[2];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) P[6 + 3 * r + c] -= U[r] * V[3 + c];
-    P[15] -= U[3] * V[3]; P[16] -= U[3] * V[4]; P[17] -= U[3] * V[5];
-    P[18] -= U[4] * V[4]; P[19] -= U[4] * V[5]; P[20] -= U[5] * V[5];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) in[k] = inn[k];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) s[k] = sn[k];
+    for (int c = 0; c < 6; ++c) P[c] -= V * Uc[c];
   }
 }
 
@@ -1352,11 +1371,10 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
     if (NW > 1) __threadfence_block();  // inertias go through device memory
     __syncthreads();
     PROF_T(t_r);
-    if (lead) {
-      if (TREE)
-        aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
-      else
-        aba_setup(NW == 1 ? hl : Hi, L.tab, nf);
+    if (TREE) {
+      if (lead) aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
+    } else if (wave == 0) {
+      aba_setup_rows(NW == 1 ? hl : Hi, L.tab, nf, lane);
     }
     __syncthreads();
     PROF_ADD(2, t_r);
@@ -1434,7 +1452,10 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
           const int nxt = (head - k - 1 + args.m) % args.m;
           const double sn = ld_if(hs + nxt * hstride, valid && k + 1 < count);
           const double yn = ld_if(hs + ys + nxt * hstride, valid && k + 1 < count);
-          const double a_k = uniform(L.rho[k] * sc.sum(sk * qv));
+          // the reduction (a barrier for several waves) before the LDS read of
+          // rho, which the lead lane writes when the pair is accepted
+          const double sq = sc.sum(sk * qv);
+          const double a_k = uniform(L.rho[(head - k + args.m) % args.m] * sq);
           if (lead) L.alp[k] = a_k;
           qv -= a_k * yk;
           sk = sn;
@@ -1461,6 +1482,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
       }
       PROF_ADD(1, t_a);
       PROF_T(t_c);
+      PROF_T(t_l);
       // ---- oldest pair first
       {
         int slot = (head - (count - 1) + args.m) % args.m;
@@ -1470,7 +1492,8 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
           const int nxt = (slot + 1) % args.m;
           const double sn = ld_if(hs + nxt * hstride, valid && k > 0);
           const double yn = ld_if(hs + ys + nxt * hstride, valid && k > 0);
-          const double b = uniform(L.rho[k] * sc.sum(yk * r));
+          const double yr = sc.sum(yk * r);
+          const double b = uniform(L.rho[slot] * yr);
           r += (L.alp[k] - b) * sk;
           sk = sn;
           yk = yn;
@@ -1479,6 +1502,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
       }
       const double dir = valid ? -r : 0.0;
       const double gd = uniform(sc.sum(g * dir));
+      PROF_ADD(12, t_l);
       if (!(gd < 0.0)) {
         if (!reset) {
           reset = true;  // redo the direction with an empty history
@@ -1544,18 +1568,16 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
             break;
           }
           // accepted: curvature pair and update
+          PROF_T(t_u);
           const double sv = alpha * dir;
           const double y = rt.g - g;
           double sy = sv * y, ss = sv * sv, yy = y * y, gg = rt.g * rt.g;
           sc.sum2(sy, ss);
           sc.sum2(yy, gg);
           if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
-            if (lead) {
-              for (int k = args.m - 1; k > 0; --k) L.rho[k] = L.rho[k - 1];
-              L.rho[0] = 1.0 / sy;
-            }
             gam = uniform(sy / yy);
             head = count == 0 ? 0 : (head + 1) % args.m;
+            if (lead) L.rho[head] = 1.0 / sy;  // rho lives in the ring slot of its pair
             if (valid) {
               hs[head * hstride] = sv;
               hs[ys + head * hstride] = y;
@@ -1568,6 +1590,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
           ++iters;
           if (PREC == ABD_MIXED && f32) ++f32_iters;
           gn = uniform(sqrt(gg));
+          PROF_ADD(13, t_u);
           const bool conv = gn <= args.tol * g0;
           if (PREC == ABD_MIXED && f32 && (conv || noisy)) {
             f32 = false;  // float32 has done what it can: confirm / continue in float64
@@ -1865,7 +1888,7 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
       step_setup(ws, d, hl + 10 * lane, L.tab[lane], geo, f, valid, qp, qc, q, use_aba);
       if (use_aba) {
         __syncthreads();
-        if (lane == 0) aba_setup(hl, L.tab, nf);
+        aba_setup_rows(hl, L.tab, nf, lane);
         __syncthreads();
         aba_inverse(L.tab, nf, lane, hl);  // overwrites the inertias
         __syncthreads();  // every lane reads the other lanes' columns
@@ -2204,11 +2227,10 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
         step_setup(ws, d, inert, L.tab[j], geo, f, valid, qprev, qk, qk, true);
         if (NW > 1) __threadfence_block();
         __syncthreads();
-        if (lead) {
-          if (TREE)
-            aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
-          else
-            aba_setup(NW == 1 ? hl : Hi, L.tab, nf);
+        if (TREE) {
+          if (lead) aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
+        } else if (wave == 0) {
+          aba_setup_rows(NW == 1 ? hl : Hi, L.tab, nf, lane);
         }
         __syncthreads();
         if (explicit_inverse) {
@@ -2243,7 +2265,8 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           double sq = 0.0;
 #pragma unroll
           for (int u = 0; u < U; ++u) sq += ld_if(sp + (slot * U + u) * stride, valid) * qv[u];
-          const double a_k = uniform(L.rho[k] * ws.sum(sq));
+          const double sqs = ws.sum(sq);  // reduction (a barrier for several waves) before the rho read
+          const double a_k = uniform(L.rho[k] * sqs);
           if (lead) L.alp[k] = a_k;
 #pragma unroll
           for (int u = 0; u < U; ++u) qv[u] -= a_k * ld_if(yp + (slot * U + u) * stride, valid);
@@ -2290,7 +2313,8 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           double yr = 0.0;
 #pragma unroll
           for (int u = 0; u < U; ++u) yr += ld_if(yp + (slot * U + u) * stride, valid) * r[u];
-          const double b = uniform(L.rho[k] * ws.sum(yr));
+          const double yrs = ws.sum(yr);
+          const double b = uniform(L.rho[k] * yrs);
 #pragma unroll
           for (int u = 0; u < U; ++u) r[u] += (L.alp[k] - b) * ld_if(sp + (slot * U + u) * stride, valid);
         }

@@ -6,11 +6,12 @@ Tolerances (stated per quantity):
     component);
   * one time step, float64, teacher-forced (both sides step from the same
     float64 (q_{k-1}, q_k)): 1e-10 relative in q (max |dq| / max(1, max |q|))
-    when both sides converge to a relative gradient tolerance of 1e-11, i.e.
-    both results are the minimizer to well below 1e-10.  At the configured
-    tolerance (1e-8) two correct L-BFGS runs stop at different points inside
-    the tolerance, measured at ~2e-8 from the exact minimizer, so there the
-    bound is 1e-7;
+    when both sides converge to a relative gradient tolerance of 1e-12: the
+    oracle's own results at 1e-12 and 1e-13 differ by at most 3e-11 on these
+    cases, while at 1e-11 they differ by up to 1.2e-9, so 1e-12 is the
+    tolerance at which 1e-10 is implied rather than a matter of both sides
+    taking the same path.  At the configured tolerance (1e-8) the bound is
+    1e-7 (two runs of the same method from the same start);
   * one time step, mixed precision: 1e-5 relative pose error against the oracle
     (max link-origin distance over the model's reach, max rotation Frobenius
     distance).
@@ -170,7 +171,7 @@ def test_config2_subset_teacher_forced(precision):
     for k in (0, 3):
         qp, qc = qs[max(k - 1, 0)], qs[k]
         if precision == abd.FP64:
-            for tol, bound in ((1e-11, 1e-10), (1e-8, 1e-7)):
+            for tol, bound in ((1e-12, 1e-10), (1e-8, 1e-7)):
                 ref, rst = orc.step(qp, qc, dt, tol=tol)
                 out, st = _step_gpu(wl.model, qp, qc, abd.StepOptions(dt=dt, tol=tol))
                 assert rel_q(out, ref) <= bound, (k, tol, rel_q(out, ref))
@@ -189,8 +190,8 @@ def test_ragged_mixed_joint_chains_fp64():
     qc = rng.uniform(-1, 1, d.n_dofs)
     tau = rng.uniform(-1, 1, d.n_dofs)
     say(f"ragged hinge/ball chains dofs={d.n_dofs}")
-    ref, rst = Oracle(d).step(qc, qc, 0.01, tau=tau, tol=1e-11)
-    out, st = _step_gpu(d, qc, qc, abd.StepOptions(dt=0.01, tol=1e-11), tau=tau)
+    ref, rst = Oracle(d).step(qc, qc, 0.01, tau=tau, tol=1e-12)
+    out, st = _step_gpu(d, qc, qc, abd.StepOptions(dt=0.01, tol=1e-12), tau=tau)
     both = (st["flag"] == 1) & (rst["flag"] == 1)
     assert np.mean(both) > 0.9, (np.unique(st["flag"], return_counts=True), np.unique(rst["flag"], return_counts=True))
     do = d.dof_offset
@@ -218,7 +219,7 @@ def test_full_config2_sampled_fp64_and_mixed():
     sub = wl.model.subset(sample)
     idx = wl.model.dof_subset_index(sample)
     orc = Oracle(sub)
-    for precision, tol in ((abd.FP64, 1e-11), (abd.MIXED, 1e-8)):
+    for precision, tol in ((abd.FP64, 1e-12), (abd.MIXED, 1e-8)):
         ref, rst = orc.step(wl.q0[idx], wl.q0[idx], dt, tol=tol)
         out, st = _step_gpu(wl.model, wl.q0, wl.q0, abd.StepOptions(dt=dt, precision=precision, tol=tol))
         assert np.all(st["flag"] == 1), np.unique(st["flag"], return_counts=True)
