@@ -59,6 +59,10 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_rollout_chains4096_hbm_traff
 # (the oracle's own results at 1e-12 and 1e-13 differ by that), at 1e-11 only to ~1e-9
 PARITY_TOL = 1e-12
 PARITY_MAX_ITER = 2000
+# CG of the rollout derivative; iteration cap of the order-K oracle sample
+VJP_TOL = 1e-10
+VJP_MAX_ITER = 200
+HOC_CPU_ITERS = 20
 
 def measured_traffic(workload, precision, warmup, steps):
     """HBM bytes of the timed launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
@@ -92,6 +96,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the oracle parity sample")
     ap.add_argument("--cpu-models", type=int, default=1024, help="models in the CPU baseline sample")
+    ap.add_argument("--vjp", action="store_true",
+                    help="also time the rollout's reverse-mode derivative (abd_rollout_vjp; on for configuration 5)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB of float64 device to device three times (the known-size kernel "
                          "that calibrates rocprofv3's FETCH_SIZE and WRITE_SIZE counters), then exit")
@@ -109,14 +115,19 @@ def copy_probe(torch):
     print(f"copied {x.numel() * 8} bytes three times", flush=True)
 
 
-def timed_rollout(torch, model, q0, opts, warmup, steps):
-    """Warm-up rollout from rest, then `steps` timed steps in one launch."""
+def timed_rollout(torch, model, q0, opts, warmup, steps, torque=None):
+    """Warm-up rollout from rest, then `steps` timed steps in one launch
+    (torque: [warmup + steps, n_dofs] joint forces, or None)."""
     n = model.n_dofs
     K = opts.order_K
     q0c = torch.as_tensor(q0, dtype=torch.float64, device="cuda")
     init = torch.cat([q0c, q0c]).contiguous()
+    tw = tt = None
+    if torque is not None:
+        tq = torch.as_tensor(torque, dtype=torch.float64, device="cuda")
+        tw, tt = tq[:warmup].contiguous(), tq[warmup:warmup + steps].contiguous()
     if warmup > 0:
-        wtraj, _ = model.rollout(init, warmup, opts)
+        wtraj, _ = model.rollout(init, warmup, opts, torque=tw)
         if K == 2:
             prev = wtraj[warmup - 2] if warmup >= 2 else q0c
             init = torch.cat([prev, wtraj[warmup - 1]]).contiguous()
@@ -128,7 +139,7 @@ def timed_rollout(torch, model, q0, opts, warmup, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
-    model.rollout(init, steps, opts, q_traj=traj, stats=stats)
+    model.rollout(init, steps, opts, torque=tt, q_traj=traj, stats=stats)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -187,6 +198,10 @@ def main():
 
     wl = W.config(args.config)
     desc = wl.model
+    if wl.torque is not None and args.warmup + args.steps > wl.torque.shape[0]:
+        print(f"configuration {args.config} defines joint forces for {wl.torque.shape[0]} steps: "
+              f"--warmup + --steps must not exceed that", file=sys.stderr)
+        sys.exit(2)
     model = abd.Model(desc)
     L = desc.n_links
     K = wl.step.order_K
@@ -198,7 +213,7 @@ def main():
         if name == "mixed" and K > 2:
             continue  # order K > 2 runs in float64 only
         opts = abd.StepOptions(precision=prec, **base)
-        init, traj, st, wall, kms = timed_rollout(torch, model, wl.q0, opts, args.warmup, args.steps)
+        init, traj, st, wall, kms = timed_rollout(torch, model, wl.q0, opts, args.warmup, args.steps, wl.torque)
         nbytes = algorithmic_bytes(desc, st, name)
         links = np.diff(desc.link_offset)[None, :]
         runs[name] = dict(
@@ -249,6 +264,9 @@ def main():
                        "iterations_per_step": f["iters_mean"], "iterations_per_step_max": f["iters_max"],
                        "converged_fraction": f["converged_frac"], "kernel_ms": f["kernel_ms"],
                        "achieved_gbs": f["achieved_gbs"], "mixed_over_fp64": mixed["value"] / f["value"]}
+
+    if (args.vjp or args.config == 5) and K == 2 and "fp64" in runs:
+        out["vjp"] = time_vjp(torch, abd, model, desc, wl, runs["fp64"], args)
 
     if not args.no_parity and K == 2:
         # one teacher-forced step from the final FP64 state (both precisions start
@@ -320,7 +338,77 @@ def main():
                                "sample": f"{len(sample)} of {desc.n_models} models ({sub.n_links} links), steps "
                                          f"{args.warmup}..{args.warmup + nsteps - 1} after a {args.warmup}-step "
                                          f"warm-up from rest, float64, OpenMP over models, {el:.1f} s"}
+    if not args.no_cpu and K > 2:
+        out["cpu_baseline"] = hoc_cpu_baseline(desc, wl, runs["fp64"], K)
     print(json.dumps(out), flush=True)
+
+
+def time_vjp(torch, abd, model, desc, wl, run, args):
+    """The rollout's reverse-mode derivative for a seed on the last configuration
+    (implicit differentiation, abd_rollout_vjp), timed with HIP events on the
+    launch stream after one untimed call; the oracle's dense implicit
+    differentiation of the same trajectory timed on a sample of models."""
+    n, T = desc.n_dofs, args.steps
+    seed = np.zeros((T, n))
+    seed[-1] = np.random.default_rng(7).standard_normal(n)
+    dl = torch.as_tensor(seed, dtype=torch.float64, device="cuda")
+    st = model.new_rollout_stats(T)
+    kw = dict(tol=VJP_TOL, max_iter=VJP_MAX_ITER)
+    model.rollout_vjp(run["init"], run["traj"], dl, wl.step.dt, stats=st, **kw)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    model.rollout_vjp(run["init"], run["traj"], dl, wl.step.dt, stats=st, **kw)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    s = model.read_rollout_stats(st, T)
+    res = {"value": desc.n_links * T / (ms * 1e-3), "unit": "link-steps/s", "kernel": "k_rollout_vjp",
+           "kernel_ms": ms, "cg_iterations_per_step": float(s["iterations"].mean()),
+           "cg_iterations_max": int(s["iterations"].max()),
+           "converged_fraction": float(np.mean(s["flag"] == abd.FLAG_CONVERGED)), "cg_tol": VJP_TOL}
+    if not args.no_cpu:
+        from oracle.oracle import Oracle
+        nsub = min(desc.n_models, 64)
+        sample = np.arange(0, desc.n_models, max(1, desc.n_models // nsub))[:nsub]
+        sub = desc.subset(sample)
+        idx = desc.dof_subset_index(sample)
+        qi = run["init"].cpu().numpy()
+        tr = run["traj"].cpu().numpy()[:, idx]
+        threads = max(1, min(16, os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        Oracle(sub, threads=threads).rollout_vjp(qi[:n][idx], qi[n:][idx], tr, wl.step.dt, seed[:, idx])
+        el = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": sub.n_links * T / el, "unit": "link-steps/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{nsub} of {desc.n_models} models ({sub.n_links} links), the same {T} "
+                                         f"steps, dense Hessians and solves, {el:.1f} s"}
+    return res
+
+
+def hoc_cpu_baseline(desc, wl, run, K):
+    """The oracle's order-K step on a bounded sample: one step of a few models from
+    the GPU's timed starting state with the iterations capped, as link-iterations/s
+    (the steps of this workload do not converge within the cap in either
+    implementation, so link-steps/s would only measure the cap)."""
+    from oracle.oracle import Oracle
+    n = desc.n_dofs
+    threads = max(1, min(16, os.cpu_count() or 1))
+    nsub = min(desc.n_models, threads)
+    sample = np.arange(0, desc.n_models, max(1, desc.n_models // nsub))[:nsub]
+    sub = desc.subset(sample)
+    idx = desc.dof_subset_index(sample)
+    init = run["init"].cpu().numpy()
+    t0 = time.perf_counter()
+    _, st = Oracle(sub, threads=threads).step_hoc(K, init[:n][idx], init[n:][idx], wl.step.dt,
+                                                  lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol,
+                                                  max_iter=HOC_CPU_ITERS)
+    el = time.perf_counter() - t0
+    li = float(np.sum(np.diff(sub.link_offset) * st["iterations"]))
+    return {"value": li / el, "unit": "link-iterations/s", "cores": threads, "kind": "oracle",
+            "sample": f"one step of {nsub} of {desc.n_models} models ({sub.n_links} links) from the timed "
+                      f"launch's starting state, at most {HOC_CPU_ITERS} iterations, float64, {el:.1f} s; "
+                      f"compare with link_iterations_per_s"}
 
 
 if __name__ == "__main__":

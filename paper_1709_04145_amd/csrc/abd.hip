@@ -67,13 +67,14 @@ constexpr int kMaxHist = 10;    // longest L-BFGS history
 constexpr int kTab = 13;        // recursion record per frame: s (6), U (6), 1/D
 
 // Optional per-phase cycle counters (build with -DABD_PROFILE): lane 0 of every
-// model wave accumulates s_memtime deltas into abd_prof[model][slot].
+// model wave accumulates s_memtime deltas into abd_prof[model][slot]; nothing is
+// recorded while no buffer is set (abd_prof null).
 #ifdef ABD_PROFILE
 __device__ unsigned long long* abd_prof;
 #define PROF_T(var) unsigned long long var = __builtin_readcyclecounter()
 #define PROF_ADD(slot, t0)                                                          \
   do {                                                                              \
-    if (threadIdx.x == 0 && has_model)                                              \
+    if (threadIdx.x == 0 && has_model && abd_prof)                                  \
       abd_prof[(size_t)model * 16 + (slot)] += __builtin_readcyclecounter() - (t0); \
   } while (0)
 #else
@@ -1363,7 +1364,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
   int iters = 0, evals = 0, flag = 0, f32_iters = 0, count = 0, head = 0, refreshed = 0;
   double q = 0.0, tau = 0.0, E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0;
 #ifdef ABD_PROFILE
-  if (lead) abd_prof[(size_t)model * 16 + 10] = __builtin_amdgcn_s_memrealtime();
+  if (lead && abd_prof) abd_prof[(size_t)model * 16 + 10] = __builtin_amdgcn_s_memrealtime();
 #endif
   // the recursion's tables (and, for one-wave chains, the explicit inverse) once
   // every frame has written its inputs
@@ -1437,7 +1438,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
         head = 0;
         PROF_ADD(4, t_f);
 #ifdef ABD_PROFILE
-        if (lead) abd_prof[(size_t)model * 16 + 8] += 1;
+        if (lead && abd_prof) abd_prof[(size_t)model * 16 + 8] += 1;
 #endif
       }
       PROF_T(t_a);
@@ -1467,7 +1468,9 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
       if (!use_aba) {
         r = (count > 0 ? gam : 1.0) * qv;
       } else if (NW == 1 && !TREE) {
+        PROF_T(t_h);
         r = apply_inverse(hl, nf, lane, qv);
+        PROF_ADD(14, t_h);
       } else {
         L.xb[j] = valid ? qv : 0.0;
         __syncthreads();
@@ -1526,7 +1529,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
             rt = evaluate<double>(sc, d, geo, f, valid, x, tau, args.dt2);
           PROF_ADD(6, t_e);
 #ifdef ABD_PROFILE
-          if (lead) abd_prof[(size_t)model * 16 + 7] += 1;
+          if (lead && abd_prof) abd_prof[(size_t)model * 16 + 7] += 1;
 #endif
           ++evals;
           if (purpose != kTrial) {
@@ -1609,7 +1612,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
       }
       PROF_ADD(5, t_c);
 #ifdef ABD_PROFILE
-      if (lead) abd_prof[(size_t)model * 16 + 9] += 1;
+      if (lead && abd_prof) abd_prof[(size_t)model * 16 + 9] += 1;
 #endif
     }
     if (step_done) {
@@ -1631,7 +1634,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
     }
   }
 #ifdef ABD_PROFILE
-  if (lead) abd_prof[(size_t)model * 16 + 11] = __builtin_amdgcn_s_memrealtime();
+  if (lead && abd_prof) abd_prof[(size_t)model * 16 + 11] = __builtin_amdgcn_s_memrealtime();
 #endif
 }
 
