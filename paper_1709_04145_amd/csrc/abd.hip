@@ -961,13 +961,17 @@ __device__ void aba_inverse(const double (*tab)[kTab], int nf, int lane, double*
 
 // r_j = sum_i (H^-1)_ij v_i: the preconditioner applied to the wave's vector v
 // (lane i holds v_i), reading the packed triangle: (i, j) from column j for
-// i <= j, from column i (symmetry) otherwise; eight reads are issued at a time.
+// i <= j, from column i (symmetry) otherwise.  v goes through LDS (vb, 64
+// doubles) and is read back as broadcasts, two entries per read; eight matrix
+// entries are requested at a time.  One wave per workgroup.
 constexpr int kMvBatch = 8;
 
-__device__ __forceinline__ double apply_inverse(const double* P, int nf, int lane, double v) {
+__device__ __forceinline__ double apply_inverse(const double* P, double* vb, int nf, int lane, double v) {
   const bool act = lane < nf;
   const int col = act ? lane : nf - 1;
   const int base = tri(col);
+  vb[lane] = act ? v : 0.0;
+  __syncthreads();
   double r = 0.0;
   int i0 = 0;
   for (; i0 + kMvBatch <= nf; i0 += kMvBatch) {
@@ -978,9 +982,10 @@ __device__ __forceinline__ double apply_inverse(const double* P, int nf, int lan
       h[k] = P[i <= col ? base + i : tri(i) + col];
     }
 #pragma unroll
-    for (int k = 0; k < kMvBatch; ++k) r += h[k] * readlane(v, i0 + k);
+    for (int k = 0; k < kMvBatch; ++k) r += h[k] * vb[i0 + k];
   }
-  for (; i0 < nf; ++i0) r += P[i0 <= col ? base + i0 : tri(i0) + col] * readlane(v, i0);
+  for (; i0 < nf; ++i0) r += P[i0 <= col ? base + i0 : tri(i0) + col] * vb[i0];
+  __syncthreads();  // vb is reused by the next product
   return act ? r : 0.0;
 }
 
@@ -1469,7 +1474,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD))
         r = (count > 0 ? gam : 1.0) * qv;
       } else if (NW == 1 && !TREE) {
         PROF_T(t_h);
-        r = apply_inverse(hl, nf, lane, qv);
+        r = apply_inverse(hl, &L.tab[0][0], nf, lane, qv);  // the recursion's table is free between formations
         PROF_ADD(14, t_h);
       } else {
         L.xb[j] = valid ? qv : 0.0;
@@ -1900,7 +1905,7 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
       const double b = valid ? lam_next : 0.0;
       const double bn = uniform(sqrt(wave_sum(b * b)));
       double r = b;
-      double z = use_aba ? apply_inverse(hl, nf, lane, r) : r;
+      double z = use_aba ? apply_inverse(hl, &L.tab[0][0], nf, lane, r) : r;
       double p = z;
       double rz = uniform(wave_sum(r * z));
       rn = bn;
@@ -1925,7 +1930,7 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
             flag = ABD_FLAG_CONVERGED;
             break;
           }
-          z = use_aba ? apply_inverse(hl, nf, lane, r) : r;
+          z = use_aba ? apply_inverse(hl, &L.tab[0][0], nf, lane, r) : r;
           const double rz1 = uniform(wave_sum(r * z));
           p = z + (rz1 / rz) * p;
           rz = rz1;
@@ -2280,7 +2285,8 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           double y[U];
           if (explicit_inverse) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) y[u] = apply_inverse(hl, nf, lane, apply_inverse(hl, nf, lane, qv[u]));
+            for (int u = 0; u < U; ++u)
+              y[u] = apply_inverse(hl, &L.tab[0][0], nf, lane, apply_inverse(hl, &L.tab[0][0], nf, lane, qv[u]));
           } else {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
