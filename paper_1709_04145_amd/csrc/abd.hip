@@ -842,7 +842,8 @@ __device__ __forceinline__ double recip(double x) {
 // 10-entry record (J 00 01 02 11 12 22, h, m).  The whole wave runs; lanes >= 6
 // shadow row 5 and store nothing.  The next frame's inputs are read while the
 // current one is processed.
-__device__ void aba_setup_rows(const double* inert, double (*tab)[kTab], int nf, int lane) {
+__device__ void aba_setup_rows(const double* inert, double (*tab)[kTab], int nf_in, int lane) {
+  const int nf = __builtin_amdgcn_readfirstlane(nf_in);  // wave-uniform frame loop
   if (nf <= 0) return;
   const int r = lane < 6 ? lane : 5;
   int idx[6];
@@ -918,7 +919,8 @@ __host__ __device__ constexpr int inverse_lds_doubles(int nf) {
   return (nf * (nf + 1) / 2 > 10 * kMaxFrames) ? nf * (nf + 1) / 2 : 10 * kMaxFrames;
 }
 
-__device__ void aba_inverse(const double (*tab)[kTab], int nf, int lane, double* P) {
+__device__ void aba_inverse(const double (*tab)[kTab], int nf_in, int lane, double* P) {
+  const int nf = __builtin_amdgcn_readfirstlane(nf_in);  // wave-uniform frame loops
   const bool act = lane < nf;
   const int col = act ? lane : nf - 1;
   const int base = tri(col);  // lanes without a frame address the last column (in bounds, never stored)
@@ -962,31 +964,39 @@ __device__ void aba_inverse(const double (*tab)[kTab], int nf, int lane, double*
 // r_j = sum_i (H^-1)_ij v_i: the preconditioner applied to the wave's vector v
 // (lane i holds v_i), reading the packed triangle: (i, j) from column j for
 // i <= j, from column i (symmetry) otherwise.  v goes through LDS (vb, 64
-// doubles) and is read back as broadcasts, two entries per read; eight matrix
-// entries are requested at a time.  One wave per workgroup.
+// doubles) and is read back as broadcasts; eight matrix entries are requested
+// at a time.  The row index is wave-uniform (scalar registers), so each entry
+// costs a select between two precomputed indices and no branch; rows past the
+// model's last (the batch tail) re-read its last row with weight zero.  One
+// wave per workgroup.
 constexpr int kMvBatch = 8;
 
-__device__ __forceinline__ double apply_inverse(const double* P, double* vb, int nf, int lane, double v) {
+__device__ __forceinline__ double apply_inverse(const double* P, double* vb, int nf_in, int lane, double v) {
+  const int nf = __builtin_amdgcn_readfirstlane(nf_in);
   const bool act = lane < nf;
   const int col = act ? lane : nf - 1;
   const int base = tri(col);
   vb[lane] = act ? v : 0.0;
   __syncthreads();
-  double r = 0.0;
-  int i0 = 0;
-  for (; i0 + kMvBatch <= nf; i0 += kMvBatch) {
-    double h[kMvBatch];
+  double r0 = 0.0, r1 = 0.0;
+  for (int i0 = 0; i0 < nf; i0 += kMvBatch) {
+    double h[kMvBatch], x[kMvBatch];
 #pragma unroll
     for (int k = 0; k < kMvBatch; ++k) {
-      const int i = i0 + k;
-      h[k] = P[i <= col ? base + i : tri(i) + col];
+      const int i = i0 + k < nf ? i0 + k : nf - 1;
+      const int upper = base + i, lower = tri(i) + col;
+      h[k] = P[i <= col ? upper : lower];
+      const double xv = vb[i];
+      x[k] = i0 + k < nf ? xv : 0.0;
     }
 #pragma unroll
-    for (int k = 0; k < kMvBatch; ++k) r += h[k] * vb[i0 + k];
+    for (int k = 0; k < kMvBatch; k += 2) {
+      r0 += h[k] * x[k];
+      r1 += h[k + 1] * x[k + 1];
+    }
   }
-  for (; i0 < nf; ++i0) r += P[i0 <= col ? base + i0 : tri(i0) + col] * vb[i0];
   __syncthreads();  // vb is reused by the next product
-  return act ? r : 0.0;
+  return act ? r0 + r1 : 0.0;
 }
 
 // x = H^{-1} b in O(n) by one thread (models of more than one wave): backward

@@ -184,6 +184,20 @@ def test_config2_subset_teacher_forced(precision):
             assert np.all(st["flag"] == 1), np.unique(st["flag"], return_counts=True)
 
 
+def test_frozen_preconditioner_matches_oracle():
+    """refresh = 0 (H_q of the warm start for the whole step) on both sides:
+    float64 to 1e-10 at a 1e-12 tolerance, like the default path."""
+    wl = W.config(2, n_models=128)
+    orc = Oracle(wl.model)
+    dt = wl.step.dt
+    qs, _ = orc.rollout(wl.q0, 3, dt)
+    say("config2 subset, frozen preconditioner")
+    ref, rst = orc.step(qs[-2], qs[-1], dt, tol=1e-12, refresh=0, max_iter=2000)
+    out, st = _step_gpu(wl.model, qs[-2], qs[-1], abd.StepOptions(dt=dt, tol=1e-12, refresh=0, max_iter=2000))
+    assert np.all(st["flag"] == 1) and np.all(rst["flag"] == 1)
+    assert rel_q(out, ref) <= 1e-10, rel_q(out, ref)
+
+
 def test_ragged_mixed_joint_chains_fp64():
     d = mixed_chains(64, 11, max_dofs=40)
     rng = np.random.default_rng(12)
@@ -345,7 +359,7 @@ def test_invalid_options_rejected():
     hist = torch.zeros(2 * d.n_dofs, dtype=torch.float64, device="cuda")
     out = torch.zeros(d.n_dofs, dtype=torch.float64, device="cuda")
     for bad in (dict(dt=0.0), dict(dt=0.1, lbfgs_m=11), dict(dt=0.1, max_ls=0), dict(dt=0.1, precision=7),
-                dict(dt=0.1, precond=1)):
+                dict(dt=0.1, precond=1), dict(dt=0.1, refresh=-1)):
         with pytest.raises(abd.AbdError) as e:
             m.step(hist, out, abd.StepOptions(**bad))
         assert e.value.code == abd.ABD_EINVAL
