@@ -986,13 +986,15 @@ __device__ __forceinline__ double apply_inverse(const double* P, double* vb, int
       const int i = i0 + k < nf ? i0 + k : nf - 1;
       const int upper = base + i, lower = tri(i) + col;
       h[k] = P[i <= col ? upper : lower];
-      const double xv = vb[i];
-      x[k] = i0 + k < nf ? xv : 0.0;
+      x[k] = vb[i];
     }
+    // all reads of the batch are issued before the first is used (otherwise
+    // the scheduler pairs each read with its use and waits for every pair)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < kMvBatch; k += 2) {
-      r0 += h[k] * x[k];
-      r1 += h[k + 1] * x[k + 1];
+      r0 += h[k] * (i0 + k < nf ? x[k] : 0.0);
+      r1 += h[k + 1] * (i0 + k + 1 < nf ? x[k + 1] : 0.0);
     }
   }
   __syncthreads();  // vb is reused by the next product
