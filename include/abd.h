@@ -48,7 +48,8 @@ extern "C" {
 
 #define ABD_PRECOND_IDENTITY 0 /* L-BFGS initial inverse Hessian gamma*I */
 #define ABD_PRECOND_INERTIA 2  /* initial inverse Hessian = inverse joint-space
-                                  inertia at the warm start */
+                                  inertia, formed at the warm start and re-formed
+                                  at the iterate every opts->refresh iterations */
 
 /* per-model outcome flags */
 #define ABD_FLAG_CONVERGED 1   /* |g| <= tol * |g(q0)| */
@@ -117,7 +118,9 @@ void abd_destroy_model(abd_model* model);
 int abd_model_info(const abd_model* model, int* n_models, int* n_links, int* n_dofs);
 
 /* One time step for every model (Sec. 4 and 5): warm start 2 q_k - q_{k-1},
- * then preconditioned L-BFGS with a backtracking line search on E.
+ * then preconditioned L-BFGS with a backtracking line search on E.  Results do
+ * not depend on the order of the models in the batch (each model is solved on
+ * its own; workgroups take the models with the most frames first).
  *   q_hist : [2*n_dofs] = q_{k-1} followed by q_k
  *   tau    : [n_dofs] generalized joint forces held over the step, or NULL
  *   q_out  : [n_dofs] receives q_{k+1}; must not overlap q_hist
