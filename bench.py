@@ -17,16 +17,17 @@ Also reported:
                times the link-iterations and evaluations the launch performed)
                over the launch's duration measured with HIP events on the
                launch stream, against the 8 TB/s HBM peak;
-  parity       one teacher-forced step from the final state on a sample of
-               models against the float64 CPU oracle, both solved to a 1e-12
-               relative gradient (at most 2000 iterations): q and pose errors over the models where both
-               sides converge to the same minimum (equal objective to 1e-9 of
-               its scale); the step objective is non-convex on this workload,
-               so models where the two reach different local minima, and
-               models where either side stops at the iteration cap, are
-               counted separately;
   cpu_baseline the oracle (C, OpenMP over models) on a sample of the models
-               over the same steps.
+               over the same steps, and (cpu_baseline.parity) the oracle's
+               solution of one teacher-forced step from the final state on a
+               sample of models next to the GPU's (both precisions, both solved
+               to a 1e-12 relative gradient, at most 2000 iterations): q and
+               pose errors over the models where both sides converge to the
+               same minimum (equal objective to 1e-9 of its scale); the step
+               objective is non-convex on this workload, so models where the two
+               reach different local minima, and models where either side stops
+               at the iteration cap, are counted separately.  The oracle runs in
+               this leg only (--no-cpu skips it).
 
 Prints one JSON line.
 """
@@ -94,7 +95,7 @@ def parse():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-parity", action="store_true", help="skip the oracle parity sample")
+    ap.add_argument("--no-parity", action="store_true", help="skip the teacher-forced parity sample")
     ap.add_argument("--cpu-models", type=int, default=1024, help="models in the CPU baseline sample")
     ap.add_argument("--vjp", action="store_true",
                     help="also time the rollout's reverse-mode derivative (abd_rollout_vjp; on for configuration 5)")
@@ -268,48 +269,13 @@ def main():
     if (args.vjp or args.config == 5) and K == 2 and "fp64" in runs:
         out["vjp"] = time_vjp(torch, abd, model, desc, wl, runs["fp64"], args)
 
-    if not args.no_parity and K == 2:
-        # one teacher-forced step from the final FP64 state (both precisions start
-        # from the same float64 (q_{k-1}, q_k)) on a sample of models
-        from oracle.oracle import Oracle
-        src = runs["fp64"] if "fp64" in runs else mixed
-        tr = src["traj"].cpu().numpy()
-        qp, qc = (tr[-2], tr[-1]) if args.steps >= 2 else (src["init"].cpu().numpy()[:desc.n_dofs], tr[-1])
-        sample = np.arange(0, desc.n_models, max(1, desc.n_models // 64))
-        sub = desc.subset(sample)
-        idx = desc.dof_subset_index(sample)
-        orc = Oracle(sub)
-        ref, rst = orc.step(qp[idx], qc[idx], wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=PARITY_TOL,
-                            max_iter=PARITY_MAX_ITER)
-        hist = torch.tensor(np.concatenate([qp, qc]), dtype=torch.float64, device="cuda")
-        E_ref, _, S_ref = orc.objective_grad(ref, qp[idx], qc[idx], wl.step.dt)
-        do = sub.dof_offset
-        par = {}
-        for name, prec in (("fp64", abd.FP64), ("mixed", abd.MIXED)):
-            o = torch.zeros(desc.n_dofs, dtype=torch.float64, device="cuda")
-            st = model.new_stats()
-            model.step(hist, o, abd.StepOptions(precision=prec, **dict(base, tol=PARITY_TOL, max_iter=PARITY_MAX_ITER)),
-                       stats=st)
-            torch.cuda.synchronize()
-            gst = model.read_stats(st, desc.n_models)[sample]
-            qg = o.cpu().numpy()[idx]
-            E_g, _, _ = orc.objective_grad(qg, qp[idx], qc[idx], wl.step.dt)
-            conv = (gst["flag"] == abd.FLAG_CONVERGED) & (rst["flag"] == 1)
-            same = conv & (np.abs(E_g - E_ref) <= 1e-9 * S_ref)
-            qerr, perr = 0.0, 0.0
-            keep = np.nonzero(same)[0]
-            if len(keep):
-                sd = sub.subset(keep)
-                si = sub.dof_subset_index(keep)
-                qerr = float(np.max(np.abs(qg[si] - ref[si])) / max(1.0, np.max(np.abs(ref[si]))))
-                perr = pose_error(Oracle(sd), sd, qg[si], ref[si])[0]
-            distinct = conv & ~same
-            par[name] = {"models_same_minimum": int(same.sum()), "max_rel_q_err": qerr, "max_rel_pose_err": perr,
-                         "models_distinct_minima": int(distinct.sum()),
-                         "max_rel_objective_gap_distinct": float(np.max(np.abs(E_g - E_ref)[distinct] / S_ref[distinct]))
-                         if distinct.any() else 0.0,
-                         "models_not_converged": int((~conv).sum())}
-        out["parity"] = {"sample_models": int(len(sample)), "tol": PARITY_TOL, **par}
+    if K == 2:
+        src = runs["fp64"] if "fp64" in runs else runs["mixed"]
+        out["energy"] = energy_drift(torch, model, desc, wl, src, args)
+
+    tf = None
+    if not args.no_parity and not args.no_cpu and K == 2:
+        tf = teacher_forced_gpu(torch, abd, model, desc, wl, runs, base, args)
 
     if not args.no_cpu and K == 2:
         from oracle.oracle import Oracle
@@ -338,9 +304,97 @@ def main():
                                "sample": f"{len(sample)} of {desc.n_models} models ({sub.n_links} links), steps "
                                          f"{args.warmup}..{args.warmup + nsteps - 1} after a {args.warmup}-step "
                                          f"warm-up from rest, float64, OpenMP over models, {el:.1f} s"}
+        if tf is not None:
+            out["cpu_baseline"]["parity"] = parity_vs_oracle(abd, desc, wl, tf)
     if not args.no_cpu and K > 2:
         out["cpu_baseline"] = hoc_cpu_baseline(desc, wl, runs["fp64"], K)
     print(json.dumps(out), flush=True)
+
+
+def model_energy(poses, prev_poses, desc, dt):
+    """Reported energy per model: (1/2 dt^2) sum_l tr(dA_l M_l dA_l^T) + V(q_k),
+    dA = A(q_k) - A(q_{k-1}), V = -sum_l g^T A_l M_l e4, from world poses
+    [n_links, 3, 4] (host arithmetic on the GPU's forward kinematics)."""
+    mm = desc.mass_moment
+    M = np.zeros((desc.n_links, 4, 4))
+    iu = np.triu_indices(4)
+    M[:, iu[0], iu[1]] = mm
+    M[:, iu[1], iu[0]] = mm
+    dA = poses - prev_poses
+    ke = 0.5 * np.einsum("lij,ljk,lik->l", dA, M, dA) / (dt * dt)
+    pot = -np.einsum("i,lij,lj->l", desc.gravity, poses, M[:, :, 3])
+    lo = desc.link_offset
+    return np.add.reduceat(ke + pot, lo[:-1]) if desc.n_links else np.zeros(desc.n_models)
+
+
+def energy_drift(torch, model, desc, wl, run, args):
+    """Energy at the start and at the end of the timed launch (float64 run)."""
+    n = desc.n_dofs
+    init = run["init"]
+    tr = run["traj"]
+    P = lambda q: model.poses(q.contiguous()).cpu().numpy().reshape(desc.n_links, 3, 4)
+    h0 = model_energy(P(init[n:]), P(init[:n]), desc, wl.step.dt)
+    last_prev = tr[-2] if args.steps >= 2 else init[n:]
+    h1 = model_energy(P(tr[-1]), P(last_prev), desc, wl.step.dt)
+    ok = np.nonzero(np.diff(desc.link_offset) > 0)[0]
+    rel = (h1[ok] - h0[ok]) / np.maximum(np.abs(h0[ok]), 1e-300)
+    return {"definition": "(1/2dt^2) sum tr(dA M dA^T) + V(q_k), per model, float64 run",
+            "mean_J_start": float(np.mean(h0[ok])), "mean_J_end": float(np.mean(h1[ok])),
+            "mean_rel_change": float(np.mean(rel)), "models_losing_energy": float(np.mean(h1[ok] < h0[ok]))}
+
+
+def teacher_forced_gpu(torch, abd, model, desc, wl, runs, base, args):
+    """One step of every model from the final float64 state (both precisions
+    start from the same float64 (q_{k-1}, q_k)), solved to PARITY_TOL on the GPU."""
+    src = runs["fp64"] if "fp64" in runs else runs["mixed"]
+    tr = src["traj"].cpu().numpy()
+    qp, qc = (tr[-2], tr[-1]) if args.steps >= 2 else (src["init"].cpu().numpy()[:desc.n_dofs], tr[-1])
+    hist = torch.tensor(np.concatenate([qp, qc]), dtype=torch.float64, device="cuda")
+    res = {"qp": qp, "qc": qc}
+    for name, prec in (("fp64", abd.FP64), ("mixed", abd.MIXED)):
+        o = torch.zeros(desc.n_dofs, dtype=torch.float64, device="cuda")
+        st = model.new_stats()
+        model.step(hist, o, abd.StepOptions(precision=prec, **dict(base, tol=PARITY_TOL, max_iter=PARITY_MAX_ITER)),
+                   stats=st)
+        torch.cuda.synchronize()
+        res[name] = (o.cpu().numpy(), model.read_stats(st, desc.n_models))
+    return res
+
+
+def parity_vs_oracle(abd, desc, wl, tf):
+    """The oracle's solution of the same teacher-forced step on a sample of models
+    next to the GPU's (part of the CPU-baseline leg)."""
+    from oracle.oracle import Oracle
+    qp, qc = tf["qp"], tf["qc"]
+    sample = np.arange(0, desc.n_models, max(1, desc.n_models // 64))
+    sub = desc.subset(sample)
+    idx = desc.dof_subset_index(sample)
+    orc = Oracle(sub)
+    ref, rst = orc.step(qp[idx], qc[idx], wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=PARITY_TOL,
+                        max_iter=PARITY_MAX_ITER)
+    E_ref, _, S_ref = orc.objective_grad(ref, qp[idx], qc[idx], wl.step.dt)
+    par = {}
+    for name in ("fp64", "mixed"):
+        qfull, st = tf[name]
+        gst = st[sample]
+        qg = qfull[idx]
+        E_g, _, _ = orc.objective_grad(qg, qp[idx], qc[idx], wl.step.dt)
+        conv = (gst["flag"] == abd.FLAG_CONVERGED) & (rst["flag"] == 1)
+        same = conv & (np.abs(E_g - E_ref) <= 1e-9 * S_ref)
+        qerr, perr = 0.0, 0.0
+        keep = np.nonzero(same)[0]
+        if len(keep):
+            sd = sub.subset(keep)
+            si = sub.dof_subset_index(keep)
+            qerr = float(np.max(np.abs(qg[si] - ref[si])) / max(1.0, np.max(np.abs(ref[si]))))
+            perr = pose_error(Oracle(sd), sd, qg[si], ref[si])[0]
+        distinct = conv & ~same
+        par[name] = {"models_same_minimum": int(same.sum()), "max_rel_q_err": qerr, "max_rel_pose_err": perr,
+                     "models_distinct_minima": int(distinct.sum()),
+                     "max_rel_objective_gap_distinct": float(np.max(np.abs(E_g - E_ref)[distinct] / S_ref[distinct]))
+                     if distinct.any() else 0.0,
+                     "models_not_converged": int((~conv).sum())}
+    return {"sample_models": int(len(sample)), "tol": PARITY_TOL, **par}
 
 
 def time_vjp(torch, abd, model, desc, wl, run, args):
