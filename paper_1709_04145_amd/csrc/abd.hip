@@ -8,9 +8,10 @@
 //   3. the adjoint backward pass giving dE/dq          (Alg. 1 backward pass)
 // and per iteration the two-loop L-BFGS direction and a backtracking line search.
 //
-// Layout on the GPU.  A model is a serial chain of elementary hinge "frames"
-// (one per DOF; a ball joint is three consecutive hinges with massless
-// intermediate frames).  One wavefront owns one model and lane j owns frame j:
+// Layout on the GPU.  A model is a tree (usually a serial chain) of elementary
+// hinge "frames" (one per DOF; a ball joint is three consecutive hinges with
+// massless intermediate frames).  One workgroup owns one model (one wavefront
+// up to 64 frames, 2..16 beyond) and lane j owns frame j:
 //   * FK is an inclusive prefix scan of 3x4 rigid transforms over the lanes
 //     (DPP row shifts + row broadcasts: 6 levels for 64 lanes);
 //   * the adjoint backward pass is evaluated in the world frame: with
@@ -21,13 +22,14 @@
 //     4x4 body-frame recursion of Alg. 1 (A <- (A + dI/dT) t^T), rewritten as
 //     a plain sum so that it becomes a float64 suffix scan;
 //   * L-BFGS dot products are float64 wave reductions.
-// The initial inverse Hessian of L-BFGS is the inverse joint-space inertia at
-// the warm start.  Once per step the articulated-body recursion factors it
-// (one lane, sequential along the chain, tables in LDS) and the 64 lanes solve
-// for the columns of the explicit inverse at once; every iteration then applies
-// it as a dense matrix-vector product streamed from memory, so the iteration
-// has no sequential sweep.  One model is one workgroup of one wavefront: models
-// never wait for each other, and the L-BFGS pairs live in LDS.
+// The initial inverse Hessian of L-BFGS is the inverse joint-space inertia,
+// formed at the warm start and again at the iterate every `refresh` iterations.
+// The articulated-body recursion factors it (sequential along the chain, its
+// 6x6 algebra spread over six lanes, tables in LDS) and, for one-wave chains,
+// the 64 lanes solve for the columns of the explicit inverse at once and keep
+// it in LDS as a packed triangle; every iteration then applies it as a
+// matrix-vector product, so the iteration has no sequential sweep.  Models never
+// wait for each other, and the L-BFGS pairs live in LDS.
 //
 // No MFMA: nothing on this path is a dense contraction.
 
@@ -1248,17 +1250,20 @@ enum ModelState { kSetup = 0, kIterate = 1, kDone = 2 };
 // per-iteration interleaving of Sec. 5's GPU scheme, done by the dispatcher
 // instead of a software queue).
 // A step is: setup (B, and for the inertia preconditioner the recursion and,
-// for one-wave models, the explicit inverse), the warm-start evaluation, then
-// iterations of two-loop L-BFGS direction + backtracking line search + update.
-// The initial inverse Hessian is applied as a dense matrix-vector product
-// (one wave) or by the two sweeps of the recursion on one thread (NW > 1).
+// for one-wave chains, the explicit inverse in LDS), the warm-start evaluation,
+// then iterations of two-loop L-BFGS direction + backtracking line search +
+// update; every `refresh` accepted iterations the preconditioner is formed again
+// at the iterate and the pairs are dropped.  The initial inverse Hessian is
+// applied as a matrix-vector product from the packed inverse (one-wave chains)
+// or by the two sweeps of the recursion on one thread (longer chains, trees).
 // The L-BFGS pairs live in LDS (one wave) or in the per-frame device ring.
+// Workgroup b takes the b-th model in descending frame count (d.order).
 // Every branch is uniform over the workgroup (all decisions use reduced values).
 // MIXED: float32 evaluations until the line search meets float32 rounding (or
 // float32 claims convergence), then float64 to the end of the step.
-#ifndef ABD_WAVES_PER_SIMD
-#define ABD_WAVES_PER_SIMD 2
-#endif
+// Two waves per SIMD: one-wave workgroups use up to 256 VGPRs (3 per SIMD
+// needed <= 168 and spilled, and was slower).
+constexpr int kWavesPerSimd = 2;
 template <int NW>
 struct ScanOf {
   using type = BlockScan<NW>;
@@ -1322,7 +1327,7 @@ struct ModelScan<NW, true> {
 };
 
 template <int NW, int PREC, bool TREE>
-__global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : ABD_WAVES_PER_SIMD)) k_rollout(StepArgs args) {
+__global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_rollout(StepArgs args) {
   __shared__ RollLds<NW, TREE> L;
   // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
   // y in [m, 2m), one double per lane per slot; one-wave chains: then the
