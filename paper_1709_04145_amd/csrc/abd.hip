@@ -192,9 +192,17 @@ template <typename R, int CTRL, int ROW_MASK>
 __device__ __forceinline__ Quat<R> dpp_quat(const Quat<R>& v) {
   Quat<R> y;
   y.w = dpp<CTRL, ROW_MASK>(R(1), v.w);
-  y.x = dpp<CTRL, ROW_MASK>(R(0), v.x);
-  y.y = dpp<CTRL, ROW_MASK>(R(0), v.y);
-  y.z = dpp<CTRL, ROW_MASK>(R(0), v.z);
+  if constexpr (ROW_MASK == 0xF) {
+    // every row enabled: only lanes without a source take the identity, whose
+    // vector part the zero fill supplies without a materialised old value
+    y.x = dpp0<CTRL>(v.x);
+    y.y = dpp0<CTRL>(v.y);
+    y.z = dpp0<CTRL>(v.z);
+  } else {
+    y.x = dpp<CTRL, ROW_MASK>(R(0), v.x);
+    y.y = dpp<CTRL, ROW_MASK>(R(0), v.y);
+    y.z = dpp<CTRL, ROW_MASK>(R(0), v.z);
+  }
   return y;
 }
 
