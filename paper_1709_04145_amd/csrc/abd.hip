@@ -27,8 +27,9 @@
 // The articulated-body recursion factors it (sequential along the chain, its
 // 6x6 algebra spread over six lanes, tables in LDS) and, for one-wave chains,
 // the 64 lanes solve for the columns of the explicit inverse at once and keep
-// it in LDS as a packed triangle; every iteration then applies it as a
-// matrix-vector product, so the iteration has no sequential sweep.  Models never
+// it in LDS (a packed float64 triangle; the full matrix in float32 for mixed
+// precision); every iteration then applies it as a matrix-vector product, so
+// the iteration has no sequential sweep.  Models never
 // wait for each other, and the L-BFGS pairs live in LDS.
 //
 // No MFMA: nothing on this path is a dense contraction.
@@ -1011,6 +1012,93 @@ __device__ __forceinline__ double apply_inverse(const double* P, double* vb, int
   return act ? r0 + r1 : 0.0;
 }
 
+// The same inverse as aba_inverse (float64 sweeps), stored for the mixed
+// kernel as the full symmetric matrix in float32, row-major with row stride nf:
+// entry (f, j) at F[f * nf + j].  Lane j's u_f (f <= j) are parked at its own
+// entries of rows f and read back, then overwritten by x_f, by the same lane
+// (no other lane touches column j), so the sweeps need no barrier; u_f = 0 for
+// f > j is not stored.  The matrix is only a preconditioner: float32 rounding
+// of u and of the entries changes the search directions, not the solution the
+// iteration converges to.  nf^2 floats fit in the packed triangle's tri(nf)
+// doubles.
+// The float32 inverse is formed while the recursion's pivots D_f span at most
+// kInv32MaxRatio: uneven chains of 10..50 box links span up to ~1e4, and there
+// the eigenvalues of (float32 inverse) x H stay within [0.97, 1.04]; chains
+// whose pivots span 1e6 and more can leave it a poor or indefinite
+// preconditioner, and they keep the packed float64 inverse.
+constexpr float kInv32MaxRatio = 1e5f;
+
+__device__ void aba_inverse_f32(const double (*tab)[kTab], int nf_in, int lane, float* F) {
+  const int nf = __builtin_amdgcn_readfirstlane(nf_in);
+  const bool act = lane < nf;
+  const int col = act ? lane : nf - 1;
+  double t[kTab], tn[kTab];
+#pragma unroll
+  for (int k = 0; k < kTab; ++k) tn[k] = tab[nf - 1][k];
+  double p[6] = {0, 0, 0, 0, 0, 0};
+  for (int f = nf - 1; f >= 0; --f) {
+#pragma unroll
+    for (int k = 0; k < kTab; ++k) t[k] = tn[k];
+    const int fn = f > 0 ? f - 1 : 0;
+#pragma unroll
+    for (int k = 0; k < kTab; ++k) tn[k] = tab[fn][k];
+    const double sp = (t[0] * p[0] + t[1] * p[1]) + (t[2] * p[2] + t[3] * p[3]) + (t[4] * p[4] + t[5] * p[5]);
+    const double u = (f == lane ? 1.0 : 0.0) - sp;
+    if (act && f <= lane) F[f * nf + col] = (float)u;
+    const double w = u * t[12];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] += t[6 + k] * w;
+  }
+  double a[6] = {0, 0, 0, 0, 0, 0};
+  float un = ld_if(F + col, act);
+  for (int f = 0; f < nf; ++f) {
+#pragma unroll
+    for (int k = 0; k < kTab; ++k) t[k] = tn[k];
+    const float uf = un;
+    const int fn = f + 1 < nf ? f + 1 : f;
+#pragma unroll
+    for (int k = 0; k < kTab; ++k) tn[k] = tab[fn][k];
+    un = ld_if(F + fn * nf + col, act && fn <= lane);
+    const double Ua = (t[6] * a[0] + t[7] * a[1]) + (t[8] * a[2] + t[9] * a[3]) + (t[10] * a[4] + t[11] * a[5]);
+    const double x = ((act && f <= lane ? (double)uf : 0.0) - Ua) * t[12];
+    if (act) F[f * nf + col] = (float)x;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) a[i] += t[i] * x;
+  }
+}
+
+// r_j = sum_i F_ij v_i with the float32 full inverse of aba_inverse_f32: row i
+// is read by the wave as one contiguous run (lane j takes entry (i, j)), v goes
+// through LDS as float32 (vb, 64 floats, zero past the model's last frame) and
+// is read back as broadcasts, products and sums in float32.  Rows past the last
+// (the batch tail) re-read the last row with weight zero.  One wave per
+// workgroup.
+__device__ __forceinline__ double apply_inverse_f32(const float* F, float* vb, int nf_in, int lane, double v) {
+  const int nf = __builtin_amdgcn_readfirstlane(nf_in);
+  const bool act = lane < nf;
+  const float* Fc = F + (act ? lane : nf - 1);
+  vb[lane] = act ? (float)v : 0.0f;
+  __syncthreads();
+  float r0 = 0.0f, r1 = 0.0f;
+  for (int i0 = 0; i0 < nf; i0 += kMvBatch) {
+    float h[kMvBatch], x[kMvBatch];
+#pragma unroll
+    for (int k = 0; k < kMvBatch; ++k) {
+      const int i = i0 + k < nf ? i0 + k : nf - 1;
+      h[k] = Fc[i * nf];
+      x[k] = vb[i0 + k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < kMvBatch; k += 2) {
+      r0 = fmaf(h[k], x[k], r0);
+      r1 = fmaf(h[k + 1], x[k + 1], r1);
+    }
+  }
+  __syncthreads();  // vb is reused by the next product
+  return act ? (double)(r0 + r1) : 0.0;
+}
+
 // x = H^{-1} b in O(n) by one thread (models of more than one wave): backward
 // sweep u_f = b_f - s_f.p, p <- p + U_f u_f / D_f; forward sweep
 // x_f = (u_f - U_f.a) / D_f, a <- a + s_f x_f; in place in xb (LDS).  The
@@ -1262,7 +1350,7 @@ enum ModelState { kSetup = 0, kIterate = 1, kDone = 2 };
 // then iterations of two-loop L-BFGS direction + backtracking line search +
 // update; every `refresh` accepted iterations the preconditioner is formed again
 // at the iterate and the pairs are dropped.  The initial inverse Hessian is
-// applied as a matrix-vector product from the packed inverse (one-wave chains)
+// applied as a matrix-vector product from the explicit inverse (one-wave chains)
 // or by the two sweeps of the recursion on one thread (longer chains, trees).
 // The L-BFGS pairs live in LDS (one wave) or in the per-frame device ring.
 // Workgroup b takes the b-th model in descending frame count (d.order).
@@ -1339,7 +1427,8 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   __shared__ RollLds<NW, TREE> L;
   // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
   // y in [m, 2m), one double per lane per slot; one-wave chains: then the
-  // packed explicit inverse (inverse_lds_doubles(max frames))
+  // explicit inverse (inverse_lds_doubles(max frames); packed float64, or the
+  // full float32 matrix for MIXED)
   extern __shared__ double pairs[];
   double* const hl = pairs + 2 * args.m * kWave;
   const DevModel& d = args.d;
@@ -1391,6 +1480,9 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
     ys = kMaxHist;
   }
   bool f32 = false, reset = false;
+  // the float32 inverse is no descent preconditioner at this iterate, so the
+  // step continues with H0 = gamma I until the next formation
+  bool h0_plain = false;
   int iters = 0, evals = 0, flag = 0, f32_iters = 0, count = 0, head = 0, refreshed = 0;
   double q = 0.0, tau = 0.0, E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0;
 #ifdef ABD_PROFILE
@@ -1398,6 +1490,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
 #endif
   // the recursion's tables (and, for one-wave chains, the explicit inverse) once
   // every frame has written its inputs
+  bool inv32 = false;  // MIXED, one-wave chains: the explicit inverse is the float32 matrix
   auto factor_precond = [&]() {
     if (NW > 1) __threadfence_block();  // inertias go through device memory
     __syncthreads();
@@ -1411,7 +1504,21 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
     PROF_ADD(2, t_r);
     PROF_T(t_i);
     if (NW == 1 && !TREE) {
-      aba_inverse(L.tab, nf, lane, hl);  // overwrites the inertias
+      if (PREC == ABD_MIXED) {
+        // float32 inverse only while the pivots D_f span at most kInv32MaxRatio
+        float lo = (float)L.tab[lane < nf ? lane : 0][12], hi = lo;  // 1/D_f
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          lo = fminf(lo, __shfl_xor(lo, o));
+          hi = fmaxf(hi, __shfl_xor(hi, o));
+        }
+        inv32 = __builtin_amdgcn_readfirstlane((int)(hi <= kInv32MaxRatio * lo)) != 0;
+      }
+      // overwrites the inertias
+      if (inv32)
+        aba_inverse_f32(L.tab, nf, lane, reinterpret_cast<float*>(hl));
+      else
+        aba_inverse(L.tab, nf, lane, hl);
       __syncthreads();  // every lane reads the other lanes' columns
     }
     PROF_ADD(3, t_i);
@@ -1426,6 +1533,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
       tau = (valid && args.tau) ? args.tau[(size_t)step * n + io] : 0.0;
       f32 = PREC == ABD_MIXED;
       iters = 0; evals = 0; flag = 0; f32_iters = 0; count = 0; head = 0; refreshed = 0; reset = false; gam = 1.0;
+      h0_plain = false;
       if (nf == 0) {
         flag = ABD_FLAG_CONVERGED;
         step_done = true;
@@ -1466,6 +1574,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         factor_precond();
         count = 0;
         head = 0;
+        h0_plain = false;
         PROF_ADD(4, t_f);
 #ifdef ABD_PROFILE
         if (lead && abd_prof) abd_prof[(size_t)model * 16 + 8] += 1;
@@ -1495,11 +1604,13 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
       }
       // ---- initial inverse Hessian
       double r;
-      if (!use_aba) {
+      if (!use_aba || h0_plain) {
         r = (count > 0 ? gam : 1.0) * qv;
       } else if (NW == 1 && !TREE) {
         PROF_T(t_h);
-        r = apply_inverse(hl, &L.tab[0][0], nf, lane, qv);  // the recursion's table is free between formations
+        // the recursion's table is free between formations
+        r = inv32 ? apply_inverse_f32(reinterpret_cast<const float*>(hl), reinterpret_cast<float*>(&L.tab[0][0]), nf, lane, qv)
+                  : apply_inverse(hl, &L.tab[0][0], nf, lane, qv);
         PROF_ADD(14, t_h);
       } else {
         L.xb[j] = valid ? qv : 0.0;
@@ -1539,6 +1650,8 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
       if (!(gd < 0.0)) {
         if (!reset) {
           reset = true;  // redo the direction with an empty history
+        } else if (inv32 && !h0_plain) {
+          h0_plain = true;  // -H0 g is no descent direction either
         } else {
           flag = ABD_FLAG_LS_FLOOR;
           step_done = true;

@@ -244,6 +244,47 @@ def test_identity_preconditioner_fp64():
     assert rel_q(out, ref) <= 1e-6
 
 
+def _ill_conditioned_chains(n_models, seed):
+    """Hinge chains with link lengths log-uniform in [0.02, 2] m and densities
+    log-uniform in [1e-2, 1e5] kg/m^3: joint-space inertias of condition 1e9..1e17."""
+    models = []
+    for i in range(n_models):
+        rng = np.random.default_rng([seed, i])
+        n = int(rng.integers(20, 64))
+        axis = rng.standard_normal((n, 3))
+        axis /= np.linalg.norm(axis, axis=1, keepdims=True)
+        L = np.exp(rng.uniform(np.log(0.02), np.log(2.0), n))
+        offset = np.zeros((n, 3))
+        offset[1:, 0] = L[:-1]
+        mm = np.stack([W.box_mass_moment(L[l], 0.1 * min(1.0, L[l]), np.exp(rng.uniform(np.log(1e-2), np.log(1e5))))
+                       for l in range(n)])
+        models.append(dict(parent=np.arange(-1, n - 1), dofs=np.ones(n, np.int32), axis=axis, offset=offset, mm=mm))
+    return W._assemble(models)
+
+
+def test_mixed_ill_conditioned_chains_converge():
+    """Mixed precision keeps a one-wave chain's explicit inverse in float32 only
+    while the recursion's pivots span at most 1e5; these chains (pivots spanning
+    up to 1e14) must keep the float64 inverse where float32 rounding would make
+    it a poor or indefinite preconditioner.  Every step must converge, to a point
+    where the oracle's float64 gradient meets the tolerance too."""
+    d = _ill_conditioned_chains(32, 77)
+    rng = np.random.default_rng(78)
+    q = rng.uniform(-1, 1, d.n_dofs)
+    dt, tol = 0.03, 1e-8
+    say("mixed ill-conditioned chains")
+    orc = Oracle(d)
+    out, st = _step_gpu(d, q, q, abd.StepOptions(dt=dt, tol=tol, max_iter=5000, precision=abd.MIXED))
+    say(f"  flags {np.unique(st['flag'], return_counts=True)}, iterations max {st['iterations'].max()}")
+    assert np.all(st["flag"] == abd.FLAG_CONVERGED), st["flag"]
+    _, g, _ = orc.objective_grad(out, q, q, dt)
+    _, g0, _ = orc.objective_grad(q, q, q, dt)  # warm start 2 q_k - q_{k-1} = q
+    do = d.dof_offset
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        assert np.linalg.norm(g[sl]) <= 1.1 * tol * np.linalg.norm(g0[sl]), (i, np.linalg.norm(g[sl]) / np.linalg.norm(g0[sl]))
+
+
 def test_full_config2_sampled_fp64_and_mixed():
     wl = W.config(2)
     dt = wl.step.dt
