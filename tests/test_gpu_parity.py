@@ -233,6 +233,30 @@ def test_ragged_mixed_joint_chains_fp64():
         assert rel_q(out[sl], ref[sl]) <= 1e-10, i
 
 
+def test_ragged_mixed_joint_chains_mixed():
+    """Mixed precision on ragged hinge/ball chains of 1..64 DOFs (the one-wave
+    limit, where the float32 inverse fills its whole LDS region): every step
+    converges, and its poses are within 1e-5 relative pose error of the oracle's
+    float64 solution."""
+    d = mixed_chains(64, 13, max_dofs=64)
+    n = np.diff(d.dof_offset)
+    assert n.min() == 1 and n.max() == 64
+    rng = np.random.default_rng(14)
+    qc = rng.uniform(-1, 1, d.n_dofs)
+    say(f"ragged hinge/ball chains, mixed, dofs={d.n_dofs}")
+    orc = Oracle(d)
+    ref, rst = orc.step(qc, qc, 0.01, tol=1e-12, max_iter=3000)
+    out, st = _step_gpu(d, qc, qc, abd.StepOptions(dt=0.01, precision=abd.MIXED))
+    assert np.all(st["flag"] == abd.FLAG_CONVERGED), np.unique(st["flag"], return_counts=True)
+    ok = rst["flag"] == 1
+    assert np.mean(ok) > 0.9
+    keep = np.nonzero(ok)[0]
+    sub = d.subset(keep)
+    idx = d.dof_subset_index(keep)
+    ex, eR = pose_error(Oracle(sub), sub, out[idx], ref[idx])
+    assert ex <= 1e-5 and eR <= 1e-5, (ex, eR)
+
+
 def test_identity_preconditioner_fp64():
     wl = W.config(1)
     q = wl.q0
