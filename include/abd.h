@@ -53,7 +53,9 @@ extern "C" {
 
 /* per-model outcome flags */
 #define ABD_FLAG_CONVERGED 1   /* |g| <= tol * |g(q0)| */
-#define ABD_FLAG_LS_FLOOR 2    /* no step accepted by the line search */
+#define ABD_FLAG_LS_FLOOR 2    /* no step accepted by the line search, or the accepted point
+                                  equals the iterate in every coordinate (no progress possible
+                                  at float64 precision) */
 #define ABD_FLAG_MAX_ITER 4    /* max_iter iterations done */
 #define ABD_FLAG_NONFINITE 8   /* objective or gradient not finite at the warm start */
 

@@ -858,6 +858,14 @@ static void step_model(const orc_model* m, int i, const orc_opts* o, const doubl
       s.flag = 2;
       break;
     }
+    /* an accepted point equal to q in every coordinate is no progress: the
+     * iteration cannot move at this precision */
+    int moved = 0;
+    for (int j = 0; j < nd; ++j) moved |= qt[j] != q[j];
+    if (!moved) {
+      s.flag = 2;
+      break;
+    }
     /* curvature pair */
     for (int j = 0; j < nd; ++j) qt[j] -= q[j]; /* s = accepted point - q */
     double sy = 0.0, ss = 0.0, yy = 0.0, yPy = 0.0;

@@ -1713,9 +1713,21 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
             step_done = true;
             break;
           }
-          // accepted: curvature pair and update
+          // an accepted trial point that equals q in every coordinate is no
+          // progress: at this precision the iteration cannot move any more
+          if (uniform(sc.sum(valid && x != q ? 1.0 : 0.0)) == 0.0) {
+            if (PREC == ABD_MIXED && f32) {
+              f32 = false;
+              purpose = kRefreshRetry;
+              continue;
+            }
+            flag = ABD_FLAG_LS_FLOOR;
+            step_done = true;
+            break;
+          }
+          // accepted: curvature pair (the step actually taken) and update
           PROF_T(t_u);
-          const double sv = alpha * dir;
+          const double sv = x - q;
           const double y = rt.g - g;
           double sy = sv * y, ss = sv * sv, yy = y * y, gg = rt.g * rt.g;
           sc.sum2(sy, ss);
