@@ -1338,6 +1338,12 @@ static void step_model_hoc(const orc_model* m, int i, const orc_opts* o, const d
       s.flag = 2;
       break;
     }
+    int moved = 0; /* an accepted point equal to q is no progress (as for order 2) */
+    for (int j = 0; j < N; ++j) moved |= qt[j] != q[j];
+    if (!moved) {
+      s.flag = 2;
+      break;
+    }
     double sy = 0.0, ss = 0.0, yy = 0.0;
     for (int j = 0; j < N; ++j) {
       double sj = qt[j] - q[j], yj = gt[j] - g[j];

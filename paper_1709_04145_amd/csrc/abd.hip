@@ -2520,6 +2520,16 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           flag = ABD_FLAG_LS_FLOOR;
           break;
         }
+        {
+          // an accepted point equal to q in every coordinate is no progress
+          double mv = 0.0;
+#pragma unroll
+          for (int u = 0; u < U; ++u) mv += (valid && qt[u] != q[u]) ? 1.0 : 0.0;
+          if (uniform(ws.sum(mv)) == 0.0) {
+            flag = ABD_FLAG_LS_FLOOR;
+            break;
+          }
+        }
         double syl = 0.0, ssl = 0.0, yyl = 0.0, ggl = 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
