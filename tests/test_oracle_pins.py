@@ -317,6 +317,26 @@ def test_refreshed_and_frozen_preconditioner_reach_the_same_minimizer():
     assert np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b))) <= 1e-10
 
 
+def test_no_progress_stop_returns_the_minimizer():
+    """With an unreachable tolerance (0) a step can only end at the iteration cap
+    or by the line search: every model that stops with flag 2 before the cap
+    (no accepted step, or an accepted point equal to the iterate) holds the same
+    minimizer as a converged solve at 1e-12, to 1e-10 relative, and so does every
+    model at the cap."""
+    wl = W.config(2, n_models=32)
+    orc = Oracle(wl.model)
+    q = wl.q0
+    out, st = orc.step(q, q, wl.step.dt, tol=0.0, max_iter=2000)
+    ref, rst = orc.step(q, q, wl.step.dt, tol=1e-12, max_iter=2000)
+    assert np.all(rst["flag"] == 1)
+    assert np.all(np.isin(st["flag"], [2, 4]))
+    assert np.any(st["flag"] == 2) and np.all(st["iterations"][st["flag"] == 2] < 2000)
+    do = wl.model.dof_offset
+    for i in range(wl.model.n_models):
+        sl = slice(do[i], do[i + 1])
+        assert np.max(np.abs(out[sl] - ref[sl])) / max(1.0, np.max(np.abs(ref[sl]))) <= 1e-10, i
+
+
 def test_refresh_converges_where_the_warm_start_preconditioner_stalls():
     """A hard step of the 4096-chain workload (chain 1681 after 32 steps from
     rest with the frozen preconditioner): H_q of the warm start for the whole
