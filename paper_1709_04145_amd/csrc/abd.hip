@@ -1480,17 +1480,17 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
     ys = kMaxHist;
   }
   bool f32 = false, reset = false;
-  // the float32 inverse is no descent preconditioner at this iterate, so the
-  // step continues with H0 = gamma I until the next formation
+  // set when the float32 inverse is no descent preconditioner at the iterate:
+  // the step then continues with H0 = gamma I until the next formation
   bool h0_plain = false;
   int iters = 0, evals = 0, flag = 0, f32_iters = 0, count = 0, head = 0, refreshed = 0;
   double q = 0.0, tau = 0.0, E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0;
 #ifdef ABD_PROFILE
   if (lead && abd_prof) abd_prof[(size_t)model * 16 + 10] = __builtin_amdgcn_s_memrealtime();
 #endif
+  bool inv32 = false;  // MIXED, one-wave chains: the explicit inverse is the float32 matrix
   // the recursion's tables (and, for one-wave chains, the explicit inverse) once
   // every frame has written its inputs
-  bool inv32 = false;  // MIXED, one-wave chains: the explicit inverse is the float32 matrix
   auto factor_precond = [&]() {
     if (NW > 1) __threadfence_block();  // inertias go through device memory
     __syncthreads();
