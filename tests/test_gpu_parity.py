@@ -437,6 +437,24 @@ def test_max_iter_zero_and_one():
     assert rel_q(out, ref) <= 1e-10
 
 
+@pytest.mark.parametrize("precision", [abd.FP64, abd.MIXED])
+def test_unreachable_tolerance_stops_at_the_minimizer(precision):
+    """tol = 0 can never be met: every step must end by the line search (flag 2,
+    which includes an accepted point equal to the iterate) or at the cap, and
+    hold the oracle's minimizer of a 1e-12 solve to 1e-10 relative."""
+    wl = W.config(2, n_models=32)
+    q = wl.q0
+    say(f"unreachable tolerance precision={precision}")
+    ref, rst = Oracle(wl.model).step(q, q, wl.step.dt, tol=1e-12, max_iter=2000)
+    out, st = _step_gpu(wl.model, q, q, abd.StepOptions(dt=wl.step.dt, tol=0.0, max_iter=2000, precision=precision))
+    assert np.all(rst["flag"] == 1)
+    assert np.all(np.isin(st["flag"], [abd.FLAG_LS_FLOOR, abd.FLAG_MAX_ITER])), np.unique(st["flag"])
+    do = wl.model.dof_offset
+    for i in range(wl.model.n_models):
+        sl = slice(do[i], do[i + 1])
+        assert np.max(np.abs(out[sl] - ref[sl])) / max(1.0, np.max(np.abs(ref[sl]))) <= 1e-10, i
+
+
 def test_invalid_options_rejected():
     d = mixed_chains(2, 1)
     m = abd.Model(d)
