@@ -287,15 +287,18 @@ def main():
         orc = Oracle(sub, threads=threads)
         qa = wl.q0[idx].copy()
         qb = qa.copy()
-        for _ in range(args.warmup):
+        for k in range(args.warmup):
             qn, _ = orc.step(qa, qb, wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol)
             qa, qb = qb, qn
+            print(f"[bench] cpu baseline: warm-up step {k} done", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         nsteps = 0
         while nsteps < args.steps:
             qn, _ = orc.step(qa, qb, wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol)
             qa, qb = qb, qn
             nsteps += 1
+            if nsteps % 10 == 0 or time.perf_counter() - t0 > 30.0:
+                print(f"[bench] cpu baseline: {nsteps} timed steps done", file=sys.stderr, flush=True)
             if time.perf_counter() - t0 > 30.0:
                 break
         el = time.perf_counter() - t0
@@ -305,6 +308,7 @@ def main():
                                          f"{args.warmup}..{args.warmup + nsteps - 1} after a {args.warmup}-step "
                                          f"warm-up from rest, float64, OpenMP over models, {el:.1f} s"}
         if tf is not None:
+            print("[bench] parity: oracle solving the teacher-forced step", file=sys.stderr, flush=True)
             out["cpu_baseline"]["parity"] = parity_vs_oracle(abd, desc, wl, tf)
     if not args.no_cpu and K > 2:
         out["cpu_baseline"] = hoc_cpu_baseline(desc, wl, runs["fp64"], K)
