@@ -44,7 +44,9 @@ extern "C" {
 
 #define ABD_FP64 0        /* every operation in double precision */
 #define ABD_MIXED 1       /* kinematics and energy terms in float32 until the
-                             line search reaches float32 rounding, then double;
+                             line search reaches float32 rounding (at most until
+                             the step's first preconditioner re-formation), then
+                             double;
                              for one-wave chains whose articulated pivots span at
                              most 1e5, the inertia preconditioner's explicit
                              inverse is kept in float32 (it shapes the search

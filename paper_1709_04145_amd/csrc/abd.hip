@@ -1355,8 +1355,10 @@ enum ModelState { kSetup = 0, kIterate = 1, kDone = 2 };
 // The L-BFGS pairs live in LDS (one wave) or in the per-frame device ring.
 // Workgroup b takes the b-th model in descending frame count (d.order).
 // Every branch is uniform over the workgroup (all decisions use reduced values).
-// MIXED: float32 evaluations until the line search meets float32 rounding (or
-// float32 claims convergence), then float64 to the end of the step.
+// MIXED: float32 evaluations until the line search meets float32 rounding,
+// float32 claims convergence or the step's first preconditioner re-formation
+// comes (a long float32 phase can leave a hard step far slower to finish in
+// float64), then float64 to the end of the step.
 // Two waves per SIMD: one-wave workgroups use up to 256 VGPRs (3 per SIMD
 // needed <= 168 and spilled, and was slower).
 constexpr int kWavesPerSimd = 2;
@@ -1483,6 +1485,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   // set when the float32 inverse is no descent preconditioner at the iterate:
   // the step then continues with H0 = gamma I until the next formation
   bool h0_plain = false;
+  bool leave32 = false;  // MIXED: the float32 phase ends at the step's first re-formation
   int iters = 0, evals = 0, flag = 0, f32_iters = 0, count = 0, head = 0, refreshed = 0;
   double q = 0.0, tau = 0.0, E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0;
 #ifdef ABD_PROFILE
@@ -1534,6 +1537,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
       f32 = PREC == ABD_MIXED;
       iters = 0; evals = 0; flag = 0; f32_iters = 0; count = 0; head = 0; refreshed = 0; reset = false; gam = 1.0;
       h0_plain = false;
+      leave32 = false;
       if (nf == 0) {
         flag = ABD_FLAG_CONVERGED;
         step_done = true;
@@ -1575,6 +1579,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         count = 0;
         head = 0;
         h0_plain = false;
+        if (PREC == ABD_MIXED && f32) leave32 = true;
         PROF_ADD(4, t_f);
 #ifdef ABD_PROFILE
         if (lead && abd_prof) abd_prof[(size_t)model * 16 + 8] += 1;
@@ -1663,6 +1668,11 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         bool noisy = false;
         int purpose = kTrial;
         for (;;) {
+          if (PREC == ABD_MIXED && leave32) {
+            leave32 = false;
+            f32 = false;  // continue in float64 from q
+            purpose = kRefresh;
+          }
           const double x = purpose == kTrial ? q + alpha * dir : q;
           EvalResult rt;
           PROF_T(t_e);
