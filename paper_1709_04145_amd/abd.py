@@ -1,7 +1,7 @@
 """Python binding of the C ABI in include/abd.h (ctypes; argument marshalling only).
 
 Every step of the computation runs in the HIP library ``libabd.so`` built from
-``csrc/abd.hip``.  PyTorch is used for device memory and streams.  There is no
+the sources under ``csrc/``.  PyTorch is used for device memory and streams.  There is no
 fallback: if the library is missing, loading fails with an error.
 """
 from __future__ import annotations

@@ -1,0 +1,71 @@
+// abd_internal.h -- declarations shared by the translation units of the library:
+// the model handle behind the opaque abd_model of include/abd.h, error reporting
+// and the kernel launches each unit provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/abd.h"
+
+struct abd_model {
+  int device = 0;
+  int n_models = 0, n_links = 0, n_dofs = 0, max_frames = 0, jump_rounds = 0;
+  bool tree = false;
+  double g[3] = {0, 0, 0};
+  // device buffers
+  int* f0 = nullptr;
+  int* order = nullptr;
+  int* pose_link = nullptr;
+  double* fr64 = nullptr;
+  float* fr32 = nullptr;
+  double* B64 = nullptr;
+  float* B32 = nullptr;
+  long long* hoff = nullptr;
+  double* hinv = nullptr;
+  double* hist = nullptr;
+  double* Bk = nullptr;  // known seed parts of order-K steps, allocated on first use
+  double* hist3 = nullptr;  // order-K pairs of models of more than 64 DOFs, on first use
+  int* uidx = nullptr;
+  int* fpar = nullptr;
+  int* fend = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace abd_impl {
+
+// Record msg as the calling thread's last error and return code.
+int fail(int code, const std::string& msg);
+
+// Device allocation owned by the model (freed with it); ABD_ENOMEM on failure.
+int model_alloc(abd_model* m, void** dst, size_t bytes);
+
+// Kernel launches (stream-ordered; arguments already validated by the caller).
+int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
+                   const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream);
+int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
+               const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream);
+int launch_hoc_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,
+                         const double* tau, double* E, double* grad, void* stream);
+int launch_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,
+                     const double* tau, double* E, double* grad, void* stream);
+int launch_poses(abd_model* m, const double* q, double* poses, void* stream);
+int launch_hvp(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist, const double* v,
+               double* Hv, void* stream);
+int launch_rollout_vjp(abd_model* m, const abd_step_opts* o, const double* q_init, const double* q_traj,
+                       const double* dL_dq_traj, double* dL_dq_init, double* dL_dtau, abd_step_stats* stats,
+                       int n_steps, void* stream);
+int check_hoc(const abd_model* m, const abd_step_opts* o);
+
+}  // namespace abd_impl
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      (void)hipGetLastError(); /* reported here: do not leave it for the caller */ \
+      return abd_impl::fail(ABD_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+    }                                                                              \
+  } while (0)

@@ -1,0 +1,447 @@
+// rollout.hip -- the order-2 step kernel (Sec. 4 Eq. EQ, Sec. 5 L-BFGS) and its launch.
+#include "abd_device.h"
+
+namespace {
+
+template <int NW, int PREC, bool TREE>
+__global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_rollout(StepArgs args) {
+  __shared__ RollLds<NW, TREE> L;
+  // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
+  // y in [m, 2m), one double per lane per slot; one-wave chains: then the
+  // explicit inverse (inverse_lds_doubles(max frames); packed float64, or the
+  // full float32 matrix for MIXED)
+  extern __shared__ double pairs[];
+  double* const hl = pairs + 2 * args.m * kWave;
+  const DevModel& d = args.d;
+  const int n = d.n_dofs;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int j = threadIdx.x;  // frame of this thread within the model
+  const bool lead = threadIdx.x == 0;
+  const bool has_model = blockIdx.x < d.n_models;
+  if (!has_model) return;
+  const int model = d.order[blockIdx.x];
+  const int f0 = d.f0[model];
+  const int nf = d.f0[model + 1] - f0;
+  if (nf == 0) {  // a model without frames: every step is trivially converged
+    if (lead && args.stats)
+      for (int k = 0; k < args.n_steps; ++k) {
+        abd_step_stats st = {0, 0, ABD_FLAG_CONVERGED, 0, 0.0, 0.0};
+        args.stats[(size_t)k * d.n_models + model] = st;
+      }
+    return;
+  }
+  const bool valid = j < nf;
+  const int f = f0 + (valid ? j : 0);  // invalid lanes alias frame 0 of the model (loads stay in bounds)
+  typename ModelScan<NW, TREE>::type sc = ModelScan<NW, TREE>::make(L, d, wave, lane, j, f, valid);
+  const int io = TREE ? (valid ? d.uidx[f] : 0) : f;  // index of this frame's DOF in the caller's vectors
+  const bool use_aba = args.precond == ABD_PRECOND_INERTIA;
+  // one-wave chains: explicit inverse; otherwise inertias [nf][10] (then, for
+  // branched models, the recursion's accumulators [nf][21])
+  double* Hi = d.hinv + d.hoff[model];
+  const FrameGeo geo = load_geo(d, f, valid);
+  const double eps_w = PREC == ABD_MIXED ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
+  const double c1 = 1e-4, dlt = 0.1;
+
+  // q_{k-1} and q_k of the current step
+  double qkm1 = ld_if(args.q_prev + io, valid);
+  double qk = ld_if(args.q_curr + io, valid);
+  int step = 0;
+  int state = args.n_steps > 0 ? kSetup : kDone;
+
+  // per-step solver state
+  double* hs;
+  int hstride, ys;
+  if (NW == 1) {
+    hs = pairs + lane;
+    hstride = kWave;
+    ys = args.m * kWave;
+  } else {
+    hs = d.hist + (size_t)f * (2 * kMaxHist);
+    hstride = 1;
+    ys = kMaxHist;
+  }
+  bool f32 = false, reset = false;
+  // set when the float32 inverse is no descent preconditioner at the iterate:
+  // the step then continues with H0 = gamma I until the next formation
+  bool h0_plain = false;
+  bool leave32 = false;  // MIXED: the float32 phase ends at the step's first re-formation
+  int iters = 0, evals = 0, flag = 0, f32_iters = 0, count = 0, head = 0, refreshed = 0;
+  double q = 0.0, tau = 0.0, E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0;
+#ifdef ABD_PROFILE
+  if (lead && abd_prof) abd_prof[(size_t)model * 16 + 10] = __builtin_amdgcn_s_memrealtime();
+#endif
+  bool inv32 = false;  // MIXED, one-wave chains: the explicit inverse is the float32 matrix
+  // the recursion's tables (and, for one-wave chains, the explicit inverse) once
+  // every frame has written its inputs
+  auto factor_precond = [&]() {
+    if (NW > 1) __threadfence_block();  // inertias go through device memory
+    __syncthreads();
+    PROF_T(t_r);
+    if (TREE) {
+      if (lead) aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
+    } else if (wave == 0) {
+      aba_setup_rows(NW == 1 ? hl : Hi, L.tab, nf, lane);
+    }
+    __syncthreads();
+    PROF_ADD(2, t_r);
+    PROF_T(t_i);
+    if (NW == 1 && !TREE) {
+      if (PREC == ABD_MIXED) {
+        // float32 inverse only while the pivots D_f span at most kInv32MaxRatio
+        float lo = (float)L.tab[lane < nf ? lane : 0][12], hi = lo;  // 1/D_f
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          lo = fminf(lo, __shfl_xor(lo, o));
+          hi = fmaxf(hi, __shfl_xor(hi, o));
+        }
+        inv32 = __builtin_amdgcn_readfirstlane((int)(hi <= kInv32MaxRatio * lo)) != 0;
+      }
+      // overwrites the inertias
+      if (inv32)
+        aba_inverse_f32(L.tab, nf, lane, reinterpret_cast<float*>(hl));
+      else
+        aba_inverse(L.tab, nf, lane, hl);
+      __syncthreads();  // every lane reads the other lanes' columns
+    }
+    PROF_ADD(3, t_i);
+  };
+  double* const inert = NW == 1 ? (TREE ? L.inert[lane] : hl + 10 * lane) : Hi + (size_t)(valid ? j : 0) * 10;
+
+  while (state != kDone) {
+    bool step_done = false;
+    if (state == kSetup) {
+      PROF_T(t_s);
+      q = valid ? 2.0 * qk - qkm1 : 0.0;  // warm start: constant-velocity extrapolation
+      tau = (valid && args.tau) ? args.tau[(size_t)step * n + io] : 0.0;
+      f32 = PREC == ABD_MIXED;
+      iters = 0; evals = 0; flag = 0; f32_iters = 0; count = 0; head = 0; refreshed = 0; reset = false; gam = 1.0;
+      h0_plain = false;
+      leave32 = false;
+      if (nf == 0) {
+        flag = ABD_FLAG_CONVERGED;
+        step_done = true;
+      } else {
+        step_setup(sc, d, inert, L.tab[j], geo, f, valid, qkm1, qk, q, use_aba);
+        if (use_aba) factor_precond();
+        PROF_ADD(0, t_s);
+        const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(sc, d, geo, f, valid, q, tau, args.dt2)
+                                                  : evaluate<double>(sc, d, geo, f, valid, q, tau, args.dt2);
+        ++evals;
+        E = r.E;
+        g = r.g;
+        gn = 0.0;
+        if (!isfinite(E) || !sc.all_finite(g)) {
+          flag = ABD_FLAG_NONFINITE;
+          step_done = true;
+        } else {
+          g0 = uniform(sqrt(sc.sum(g * g)));
+          gn = g0;
+          if (g0 == 0.0) {
+            flag = ABD_FLAG_CONVERGED;
+            step_done = true;
+          } else if (args.max_iter <= 0) {
+            flag = ABD_FLAG_MAX_ITER;
+            step_done = true;
+          } else {
+            state = kIterate;
+          }
+        }
+      }
+    } else {
+      if (use_aba && args.refresh > 0 && iters > 0 && iters % args.refresh == 0 && iters != refreshed) {
+        // the inertia of the warm start no longer describes the iterate: re-form
+        // the preconditioner at q and restart the curvature history
+        refreshed = iters;
+        PROF_T(t_f);
+        precond_frame(sc, d, inert, L.tab[j], geo, f, valid, q);
+        factor_precond();
+        count = 0;
+        head = 0;
+        h0_plain = false;
+        if (PREC == ABD_MIXED && f32) leave32 = true;
+        PROF_ADD(4, t_f);
+#ifdef ABD_PROFILE
+        if (lead && abd_prof) abd_prof[(size_t)model * 16 + 8] += 1;
+#endif
+      }
+      PROF_T(t_a);
+      // ---- two-loop recursion: newest pair first; the next pair is requested
+      // while the current one is used
+      if (reset) count = 0;
+      double qv = g;
+      {
+        double sk = ld_if(hs + head * hstride, valid && count > 0);
+        double yk = ld_if(hs + ys + head * hstride, valid && count > 0);
+        for (int k = 0; k < count; ++k) {
+          const int nxt = (head - k - 1 + args.m) % args.m;
+          const double sn = ld_if(hs + nxt * hstride, valid && k + 1 < count);
+          const double yn = ld_if(hs + ys + nxt * hstride, valid && k + 1 < count);
+          // the reduction (a barrier for several waves) before the LDS read of
+          // rho, which the lead lane writes when the pair is accepted
+          const double sq = sc.sum(sk * qv);
+          const double a_k = uniform(L.rho[(head - k + args.m) % args.m] * sq);
+          if (lead) L.alp[k] = a_k;
+          qv -= a_k * yk;
+          sk = sn;
+          yk = yn;
+        }
+      }
+      // ---- initial inverse Hessian
+      double r;
+      if (!use_aba || h0_plain) {
+        r = (count > 0 ? gam : 1.0) * qv;
+      } else if (NW == 1 && !TREE) {
+        PROF_T(t_h);
+        // the recursion's table is free between formations
+        r = inv32 ? apply_inverse_f32(reinterpret_cast<const float*>(hl), reinterpret_cast<float*>(&L.tab[0][0]), nf, lane, qv)
+                  : apply_inverse(hl, &L.tab[0][0], nf, lane, qv);
+        PROF_ADD(14, t_h);
+      } else {
+        L.xb[j] = valid ? qv : 0.0;
+        __syncthreads();
+        if (lead) {
+          if (TREE)
+            aba_solve_tree(L.tab, L.xb, L.tpar, L.acc, nf);
+          else
+            aba_solve(L.tab, L.xb, nf);
+        }
+        __syncthreads();
+        r = ld_if(&L.xb[j], valid);
+      }
+      PROF_ADD(1, t_a);
+      PROF_T(t_c);
+      PROF_T(t_l);
+      // ---- oldest pair first
+      {
+        int slot = (head - (count - 1) + args.m) % args.m;
+        double sk = ld_if(hs + slot * hstride, valid && count > 0);
+        double yk = ld_if(hs + ys + slot * hstride, valid && count > 0);
+        for (int k = count - 1; k >= 0; --k) {
+          const int nxt = (slot + 1) % args.m;
+          const double sn = ld_if(hs + nxt * hstride, valid && k > 0);
+          const double yn = ld_if(hs + ys + nxt * hstride, valid && k > 0);
+          const double yr = sc.sum(yk * r);
+          const double b = uniform(L.rho[slot] * yr);
+          r += (L.alp[k] - b) * sk;
+          sk = sn;
+          yk = yn;
+          slot = nxt;
+        }
+      }
+      const double dir = valid ? -r : 0.0;
+      const double gd = uniform(sc.sum(g * dir));
+      PROF_ADD(12, t_l);
+      if (!(gd < 0.0)) {
+        if (!reset) {
+          reset = true;  // redo the direction with an empty history
+        } else if (inv32 && !h0_plain) {
+          h0_plain = true;  // -H0 g is no descent direction either
+        } else {
+          flag = ABD_FLAG_LS_FLOOR;
+          step_done = true;
+        }
+      } else {
+        reset = false;
+        double alpha = 1.0;
+        int ls = 0;
+        bool noisy = false;
+        int purpose = kTrial;
+        for (;;) {
+          if (PREC == ABD_MIXED && leave32) {
+            leave32 = false;
+            f32 = false;  // continue in float64 from q
+            purpose = kRefresh;
+          }
+          const double x = purpose == kTrial ? q + alpha * dir : q;
+          EvalResult rt;
+          PROF_T(t_e);
+          if (PREC == ABD_MIXED && f32)
+            rt = evaluate<float>(sc, d, geo, f, valid, x, tau, args.dt2);
+          else
+            rt = evaluate<double>(sc, d, geo, f, valid, x, tau, args.dt2);
+          PROF_ADD(6, t_e);
+#ifdef ABD_PROFILE
+          if (lead && abd_prof) abd_prof[(size_t)model * 16 + 7] += 1;
+#endif
+          ++evals;
+          if (purpose != kTrial) {
+            // float64 re-evaluation at q after leaving float32
+            E = rt.E;
+            g = rt.g;
+            gn = uniform(sqrt(sc.sum(g * g)));
+            if (purpose == kRefresh) {
+              if (gn <= args.tol * g0) {
+                flag = ABD_FLAG_CONVERGED;
+                step_done = true;
+              } else if (iters >= args.max_iter) {
+                flag = ABD_FLAG_MAX_ITER;
+                step_done = true;
+              }
+            }
+            break;
+          }
+          int ok = 0;
+          if (isfinite(rt.E) && sc.all_finite(rt.g)) {
+            if (rt.E <= E + c1 * alpha * gd) {
+              ok = 1;
+            } else if (fabs(rt.E - E) <= 10.0 * eps_w * rt.S) {
+              noisy = true;
+              const double gtd = sc.sum(rt.g * dir);
+              if (gtd <= (2.0 * dlt - 1.0) * gd) ok = 1;
+            }
+          }
+          if (!ok) {
+            alpha = next_alpha(alpha, E, rt.E, gd);
+            if (++ls < args.max_ls) continue;
+            if (PREC == ABD_MIXED && f32) {
+              f32 = false;  // float32 rounding stalls the search: continue in float64 from q
+              purpose = kRefreshRetry;
+              continue;
+            }
+            flag = ABD_FLAG_LS_FLOOR;
+            step_done = true;
+            break;
+          }
+          // an accepted trial point that equals q in every coordinate is no
+          // progress: at this precision the iteration cannot move any more
+          if (uniform(sc.sum(valid && x != q ? 1.0 : 0.0)) == 0.0) {
+            if (PREC == ABD_MIXED && f32) {
+              f32 = false;
+              purpose = kRefreshRetry;
+              continue;
+            }
+            flag = ABD_FLAG_LS_FLOOR;
+            step_done = true;
+            break;
+          }
+          // accepted: curvature pair (the step actually taken) and update
+          PROF_T(t_u);
+          const double sv = x - q;
+          const double y = rt.g - g;
+          double sy = sv * y, ss = sv * sv, yy = y * y, gg = rt.g * rt.g;
+          sc.sum2(sy, ss);
+          sc.sum2(yy, gg);
+          if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
+            gam = uniform(sy / yy);
+            head = count == 0 ? 0 : (head + 1) % args.m;
+            if (lead) L.rho[head] = 1.0 / sy;  // rho lives in the ring slot of its pair
+            if (valid) {
+              hs[head * hstride] = sv;
+              hs[ys + head * hstride] = y;
+            }
+            if (count < args.m) ++count;
+          }
+          q = x;
+          g = rt.g;
+          E = rt.E;
+          ++iters;
+          if (PREC == ABD_MIXED && f32) ++f32_iters;
+          gn = uniform(sqrt(gg));
+          PROF_ADD(13, t_u);
+          const bool conv = gn <= args.tol * g0;
+          if (PREC == ABD_MIXED && f32 && (conv || noisy)) {
+            f32 = false;  // float32 has done what it can: confirm / continue in float64
+            purpose = kRefresh;
+            continue;
+          }
+          if (conv) {
+            flag = ABD_FLAG_CONVERGED;
+            step_done = true;
+          } else if (iters >= args.max_iter) {
+            flag = ABD_FLAG_MAX_ITER;
+            step_done = true;
+          }
+          break;
+        }
+      }
+      PROF_ADD(5, t_c);
+#ifdef ABD_PROFILE
+      if (lead && abd_prof) abd_prof[(size_t)model * 16 + 9] += 1;
+#endif
+    }
+    if (step_done) {
+      if (valid) args.q_out[(size_t)step * n + io] = q;
+      if (args.stats && lead) {
+        abd_step_stats st;
+        st.iterations = iters;
+        st.evaluations = evals;
+        st.flag = flag;
+        st.f32_iterations = f32_iters;
+        st.grad_norm = gn;
+        st.energy = E;
+        args.stats[(size_t)step * d.n_models + model] = st;
+      }
+      qkm1 = qk;
+      qk = q;
+      ++step;
+      state = step < args.n_steps ? kSetup : kDone;
+    }
+  }
+#ifdef ABD_PROFILE
+  if (lead && abd_prof) abd_prof[(size_t)model * 16 + 11] = __builtin_amdgcn_s_memrealtime();
+#endif
+}
+
+}  // namespace
+
+namespace abd_impl {
+
+int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
+                          const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream) {
+  StepArgs a;
+  a.d = dev_view(m);
+  a.dt2 = o->dt * o->dt;
+  a.tol = o->tol;
+  a.m = o->lbfgs_m;
+  a.max_iter = o->max_iter;
+  a.max_ls = o->max_ls;
+  a.precond = o->precond;
+  a.refresh = o->refresh;
+  a.n_steps = n_steps;
+  a.q_prev = q_prev;
+  a.q_curr = q_curr;
+  a.tau = tau;
+  a.q_out = q_out;
+  a.stats = stats;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nw = waves_for(m->max_frames);
+  const dim3 grid(m->n_models), block(nw * kWave);
+  size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * kWave * sizeof(double) : 0;
+  if (nw == 1 && !m->tree) pair_bytes += (size_t)inverse_lds_doubles(m->max_frames) * sizeof(double);
+  const bool f64 = o->precision == ABD_FP64;
+#define ABD_LAUNCH(NW, TREE)                                                                \
+  do {                                                                                      \
+    if (f64)                                                                                \
+      hipLaunchKernelGGL((k_rollout<NW, ABD_FP64, TREE>), grid, block, pair_bytes, s, a);   \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_rollout<NW, ABD_MIXED, TREE>), grid, block, pair_bytes, s, a);  \
+  } while (0)
+  if (m->tree) {
+    switch (nw) {
+      case 1: ABD_LAUNCH(1, true); break;
+      case 2: ABD_LAUNCH(2, true); break;
+      default: ABD_LAUNCH(4, true); break;
+    }
+  } else {
+    switch (nw) {
+      case 1: ABD_LAUNCH(1, false); break;
+      case 2: ABD_LAUNCH(2, false); break;
+      case 4: ABD_LAUNCH(4, false); break;
+      case 8: ABD_LAUNCH(8, false); break;
+      default: ABD_LAUNCH(16, false); break;
+    }
+  }
+#undef ABD_LAUNCH
+  HIP_TRY(hipGetLastError());
+  return ABD_OK;
+}
+
+}  // namespace abd_impl
+
+#ifdef ABD_PROFILE
+// Profiling builds only: device buffer of 16 counters per model.
+extern "C" int abd_debug_set_profile_buffer(unsigned long long* dev_ptr) {
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(abd_prof), &dev_ptr, sizeof(dev_ptr)));
+  return ABD_OK;
+}
+#endif
