@@ -14,9 +14,11 @@ workload is reported next to it.
 
 Also reported:
   roofline     algorithmic bytes of the timed launch (per-link figures below,
-               times the link-iterations and evaluations the launch performed)
-               over the launch's duration measured with HIP events on the
-               launch stream, against the 8 TB/s HBM peak;
+               times the float32 and float64 evaluations and the iterations the
+               launch performed, as counted by the kernel) over the launch's
+               duration measured with HIP events on the launch stream, against
+               the 8 TB/s HBM peak; the preconditioner's and the step setup's
+               bytes are reported beside it (extra_bytes), not in it;
   cpu_baseline the oracle (C, OpenMP over models) on a sample of the models
                over the same steps, and (cpu_baseline.parity) the oracle's
                solution of one teacher-forced step from the final state on a
@@ -48,9 +50,12 @@ sys.path.insert(0, ROOT)
 # read from and every result written to HBM once per use, no on-chip reuse.
 # evaluation, float32 terms: read q 8, axis+offset 24, M 40, B 48; write g 8
 # evaluation, float64 terms: read q 8, axis+offset 48, M 80, B 96; write g 8
+# These and the L-BFGS figure are the method's work per link-iteration; the
+# roofline fraction counts them only.
 EVAL_BYTES = {"f32": 128, "f64": 240}
 LBFGS_BYTES = 128                       # read g, q, s/y history (m=5); write d, q, s, y
-PRECOND_BYTES = 240                     # two sweeps over the recursion records (s, U, 1/D) + b/u/x
+# Work of this implementation's choices, reported separately (extra_bytes):
+PRECOND_BYTES = 240                     # per iteration: two sweeps over the recursion records (s, U, 1/D) + b/u/x
 SETUP_BYTES = 328                       # per step: read q_{k-1}, q_k, axis/offset, M; write B (f64+f32), records
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_rollout_chains4096_hbm_traffic.md")
@@ -65,6 +70,17 @@ VJP_TOL = 1e-10
 VJP_MAX_ITER = 200
 HOC_CPU_ITERS = 20
 
+def kernel_source_digest():
+    """sha256 over the library's sources (csrc/*.hip and *.h in name order)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1709_04145_amd", "csrc", "*"))):
+        if p.endswith((".hip", ".h")):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload, precision, warmup, steps):
     """HBM bytes of the timed launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary, if it was taken on this kernel source and this launch; else None."""
@@ -78,8 +94,7 @@ def measured_traffic(workload, precision, warmup, steps):
         if ": " in line and not line.startswith(("|", "#", " ")):
             k, v = line.split(": ", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_1709_04145_amd", "csrc", "abd.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    digest = kernel_source_digest()
     want = {"source_sha256": digest, "workload": workload, "precision": precision,
             "warmup": str(warmup), "steps": str(steps)}
     if any(kv.get(k) != v for k, v in want.items()) or "traffic_bytes" not in kv:
@@ -149,19 +164,19 @@ def timed_rollout(torch, model, q0, opts, warmup, steps, torque=None):
     return init, traj, st, wall, kernel_ms
 
 
-def algorithmic_bytes(desc, st, precision):
-    """Bytes the timed launch would move in the streaming formulation."""
+def algorithmic_bytes(desc, st):
+    """Bytes the timed launch would move in the streaming formulation of the
+    method: per link, EVAL_BYTES per evaluation (float32 or float64, as the
+    kernel counted them) and LBFGS_BYTES per iteration.  Returns (bytes,
+    extra_bytes), extra_bytes being the preconditioner's and the step setup's."""
     links = np.diff(desc.link_offset).astype(np.float64)[None, :]
     it = st["iterations"].astype(np.float64)
     ev = st["evaluations"].astype(np.float64)
-    if precision == "mixed":
-        ev32 = np.minimum(ev, st["f32_iterations"].astype(np.float64) + 1.0)
-        ev64 = ev - ev32
-    else:
-        ev32, ev64 = np.zeros_like(ev), ev
-    per_link = (EVAL_BYTES["f32"] * ev32 + EVAL_BYTES["f64"] * ev64 + (LBFGS_BYTES + PRECOND_BYTES) * it
-                + SETUP_BYTES)
-    return float(np.sum(links * per_link))
+    ev32 = st["f32_evaluations"].astype(np.float64)
+    ev64 = ev - ev32
+    per_link = EVAL_BYTES["f32"] * ev32 + EVAL_BYTES["f64"] * ev64 + LBFGS_BYTES * it
+    extra = PRECOND_BYTES * it + SETUP_BYTES
+    return float(np.sum(links * per_link)), float(np.sum(links * extra))
 
 
 def pose_error(orc, desc, q, ref):
@@ -215,15 +230,16 @@ def main():
             continue  # order K > 2 runs in float64 only
         opts = abd.StepOptions(precision=prec, **base)
         init, traj, st, wall, kms = timed_rollout(torch, model, wl.q0, opts, args.warmup, args.steps, wl.torque)
-        nbytes = algorithmic_bytes(desc, st, name)
+        nbytes, xbytes = algorithmic_bytes(desc, st)
         links = np.diff(desc.link_offset)[None, :]
         runs[name] = dict(
             init=init, traj=traj, st=st, wall=wall, kernel_ms=kms, value=L * args.steps / wall,
             iters_mean=float(st["iterations"].mean()), iters_max=int(st["iterations"].max()),
             evals_mean=float(st["evaluations"].mean()),
+            f32_eval_share=float(np.sum(links * st["f32_evaluations"]) / max(1, np.sum(links * st["evaluations"]))),
             converged_frac=float(np.mean(st["flag"] == abd.FLAG_CONVERGED)),
             link_iters=float(np.sum(links * st["iterations"])),
-            achieved_gbs=nbytes / (kms * 1e-3) / 1e9, bytes=nbytes)
+            achieved_gbs=nbytes / (kms * 1e-3) / 1e9, bytes=nbytes, extra_bytes=xbytes)
         print(f"[bench] {name}: {runs[name]['value']:.4g} link-steps/s, kernel {kms:.2f} ms for {args.steps} "
               f"steps, iters/step {runs[name]['iters_mean']:.2f} (max {runs[name]['iters_max']})",
               file=sys.stderr, flush=True)
@@ -257,7 +273,11 @@ def main():
                      "kernel": "k_rollout<MIXED>" if "mixed" in runs else ("k_rollout<FP64>" if K == 2 else
                                                                              "k_rollout_hoc"),
                      "kernel_ms": mixed["kernel_ms"],
-                     "algorithmic_bytes": mixed["bytes"]},
+                     "algorithmic_bytes": mixed["bytes"],
+                     "extra_bytes": mixed["extra_bytes"],
+                     "bytes_per_link": {"eval_f32": EVAL_BYTES["f32"], "eval_f64": EVAL_BYTES["f64"],
+                                        "lbfgs_iteration": LBFGS_BYTES}},
+        "float32_evaluation_share": mixed["f32_eval_share"],
     }
     if "fp64" in runs and "mixed" in runs:
         f = runs["fp64"]
@@ -303,10 +323,32 @@ def main():
                 break
         el = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": sub.n_links * nsteps / el, "unit": "link-steps/s", "cores": threads,
-                               "kind": "oracle",
+                               "kind": "oracle", "host_cores": os.cpu_count(),
                                "sample": f"{len(sample)} of {desc.n_models} models ({sub.n_links} links), steps "
                                          f"{args.warmup}..{args.warmup + nsteps - 1} after a {args.warmup}-step "
                                          f"warm-up from rest, float64, OpenMP over models, {el:.1f} s"}
+        # one core: the same steps on the first 64 models of the sample
+        n1 = min(64, len(sample))
+        sub1 = sub.subset(np.arange(n1))
+        idx1 = sub.dof_subset_index(np.arange(n1))
+        orc1 = Oracle(sub1, threads=1)
+        qa1 = wl.q0[idx][idx1].copy()
+        qb1 = qa1.copy()
+        for k in range(args.warmup):
+            qn, _ = orc1.step(qa1, qb1, wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol)
+            qa1, qb1 = qb1, qn
+        t0 = time.perf_counter()
+        n1steps = 0
+        while n1steps < args.steps and time.perf_counter() - t0 < 15.0:
+            qn, _ = orc1.step(qa1, qb1, wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol)
+            qa1, qb1 = qb1, qn
+            n1steps += 1
+        el1 = time.perf_counter() - t0
+        out["cpu_baseline"]["single_core"] = {
+            "value": sub1.n_links * n1steps / el1, "unit": "link-steps/s", "cores": 1,
+            "sample": f"{n1} models ({sub1.n_links} links), steps {args.warmup}..{args.warmup + n1steps - 1}, "
+                      f"{el1:.1f} s"}
+        print(f"[bench] cpu baseline: single core done ({n1steps} steps)", file=sys.stderr, flush=True)
         if tf is not None:
             print("[bench] parity: oracle solving the teacher-forced step", file=sys.stderr, flush=True)
             out["cpu_baseline"]["parity"] = parity_vs_oracle(abd, desc, wl, tf)

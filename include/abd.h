@@ -52,6 +52,16 @@ extern "C" {
                              inverse is kept in float32 (it shapes the search
                              directions only, not the converged solution) */
 
+/* schedules (abd_step_opts.schedule): how models are mapped onto the GPU */
+#define ABD_SCHEDULE_AUTO 0 /* the library picks (currently ABD_SCHEDULE_WAVE) */
+#define ABD_SCHEDULE_WAVE 1 /* one model per workgroup of the fewest wavefronts (64
+                               frames each) that hold the batch's longest model,
+                               models dispatched longest first (Sec. 5 "GPU
+                               Parallelization": one workgroup per trajectory) */
+
+/* optimizers (abd_step_opts.solver), Sec. 5 "Optimization Algorithm" */
+#define ABD_SOLVER_LBFGS 0  /* L-BFGS (two-loop recursion) with a backtracking line search */
+
 #define ABD_PRECOND_IDENTITY 0 /* L-BFGS initial inverse Hessian gamma*I */
 #define ABD_PRECOND_INERTIA 2  /* initial inverse Hessian = inverse joint-space
                                   inertia, formed at the warm start and re-formed
@@ -87,7 +97,7 @@ typedef struct {
   double dt;         /* time step > 0 */
   int order_K;       /* collocation order K: 2 = Eq. EQ (one unknown configuration per
                         step); 3, 4 = Eq. EQHOC with K-1 unknown configurations per
-                        step (float64 only, models of <= 64 DOFs); other values are
+                        step (float64 only, models of <= 256 DOFs); other values are
                         rejected (EINVAL below 2, ENOTSUP above 4) */
   int lbfgs_m;       /* L-BFGS history length, 1..10 */
   double tol;        /* stop when |grad| <= tol * |grad at the warm start| */
@@ -99,18 +109,26 @@ typedef struct {
                         iterations of a step, re-form the preconditioner at the
                         current iterate and drop the L-BFGS pairs; 0 = keep the
                         warm start's for the whole step.  >= 0 (EINVAL otherwise) */
+  int schedule;      /* ABD_SCHEDULE_* (EINVAL for other values) */
+  int solver;        /* ABD_SOLVER_* (EINVAL for other values) */
 } abd_step_opts;
 
 typedef struct {
-  int iterations;    /* accepted L-BFGS iterations */
+  int iterations;    /* accepted iterations */
   int evaluations;   /* objective+gradient evaluations (incl. the warm start) */
   int flag;          /* ABD_FLAG_* */
   int f32_iterations;/* iterations whose evaluations ran in float32 (ABD_MIXED) */
+  int f32_evaluations;/* evaluations that ran in float32 (ABD_MIXED) */
+  int reserved;      /* 0 */
   double grad_norm;  /* |grad| at the returned q */
   double energy;     /* E at the returned q */
-} abd_step_stats;
+} abd_step_stats;    /* 40 bytes */
 
-/* Validate a description and upload it to the current HIP device.  Checks
+/* Validate a description and upload it to the current HIP device.  The
+ * description is the model of Sec. 5: bodies with a parent relation, joint axes
+ * and offsets, and the precomputed per-body integrals of Eq. ATOM (mass_moment:
+ * int rho (p;1)(p;1)^T dp over the body, in its own frame), which turn every
+ * body integral of Eq. EQ into a contraction with the pose.  Checks
  * topology, finite values, unit axes, positive mass and positive semi-definite
  * moment tensors (ABD_EINVAL).  Synchronous.  *out receives the handle.
  * Limits of this build (ABD_ENOTSUP): serial chains of up to 1024 DOFs per
@@ -161,18 +179,21 @@ int abd_rollout(abd_model* model, const abd_step_opts* opts, const double* q_ini
 
 /* Objective and gradient without optimization (Eq. EQ scaled by dt^2; gradient by
  * the adjoint backward pass of Alg. 1).
- *   q      : [n_dofs] configuration to evaluate
- *   q_hist : [2*n_dofs] = q_{k-1} followed by q_k
- *   tau    : [n_dofs] or NULL
- *   E      : [n_models] objective per model
- *   grad   : [n_dofs] gradient, or NULL
+ *   q        : [n_dofs] configuration to evaluate
+ *   q_hist   : [2*n_dofs] = q_{k-1} followed by q_k
+ *   tau      : [n_dofs] or NULL
+ *   E        : [n_models] objective per model
+ *   grad     : [n_dofs] gradient dE/dq, or NULL
+ *   grad_tau : [n_dofs] dE/dtau (= -dt^2 q for order 2; for order K > 2 the
+ *              derivative of Eq. EQHOC with respect to the joint forces held over
+ *              the step, -2 dt^2 sum_u rho_u), or NULL
  * opts->precision selects float64 or float32 kinematics; opts->order_K > 2
  * evaluates Eq. EQHOC with q and grad of [(K-1)*n_dofs] (the unknown
  * configurations) and q_hist = q_{k-1+alpha_{K-2}}, q_k; other fields but dt are
  * ignored. */
 int abd_objective_grad(abd_model* model, const abd_step_opts* opts, const double* q,
                        const double* q_hist, const double* tau, double* E, double* grad,
-                       void* stream);
+                       double* grad_tau, void* stream);
 
 /* Hessian-vector product of the step objective at q (float64): Hv = (d2E/dq dq) v,
  * the derivative of the Alg. 1 gradient along v, computed by forward-mode

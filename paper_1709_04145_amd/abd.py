@@ -24,6 +24,8 @@ PRECOND_IDENTITY, PRECOND_INERTIA = 0, 2
 # preconditioner at the current iterate
 REFRESH = 10
 FLAG_CONVERGED, FLAG_LS_FLOOR, FLAG_MAX_ITER, FLAG_NONFINITE = 1, 2, 4, 8
+SCHEDULE_AUTO, SCHEDULE_WAVE = 0, 1
+SOLVER_LBFGS = 0
 
 
 class ModelDescC(C.Structure):
@@ -40,13 +42,15 @@ class ModelDescC(C.Structure):
 class StepOptsC(C.Structure):
     _fields_ = [("dt", C.c_double), ("order_K", C.c_int), ("lbfgs_m", C.c_int),
                 ("tol", C.c_double), ("max_iter", C.c_int), ("max_ls", C.c_int),
-                ("precision", C.c_int), ("precond", C.c_int), ("refresh", C.c_int)]
+                ("precision", C.c_int), ("precond", C.c_int), ("refresh", C.c_int),
+                ("schedule", C.c_int), ("solver", C.c_int)]
 
 
 STATS_DTYPE = np.dtype([("iterations", np.int32), ("evaluations", np.int32), ("flag", np.int32),
-                        ("f32_iterations", np.int32), ("grad_norm", np.float64),
-                        ("energy", np.float64)])
-assert STATS_DTYPE.itemsize == 32
+                        ("f32_iterations", np.int32), ("f32_evaluations", np.int32), ("reserved", np.int32),
+                        ("grad_norm", np.float64), ("energy", np.float64)])
+STATS_BYTES = 40
+assert STATS_DTYPE.itemsize == STATS_BYTES
 
 # every exported entry point and its prototype
 _PROTOS = {
@@ -58,7 +62,7 @@ _PROTOS = {
     "abd_rollout": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_int, C.c_void_p]),
     "abd_objective_grad": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p,
-                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "abd_hvp": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
                           C.c_void_p, C.c_void_p]),
     "abd_rollout_vjp": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
@@ -109,10 +113,12 @@ class StepOptions:
     precision: int = FP64
     precond: int = PRECOND_INERTIA
     refresh: int = REFRESH
+    schedule: int = SCHEDULE_AUTO
+    solver: int = SOLVER_LBFGS
 
     def c(self) -> StepOptsC:
         return StepOptsC(self.dt, self.order_K, self.lbfgs_m, self.tol, self.max_iter, self.max_ls,
-                         self.precision, self.precond, self.refresh)
+                         self.precision, self.precond, self.refresh, self.schedule, self.solver)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -177,23 +183,25 @@ class Model:
         _dev_f64(q_out, (opts.order_K - 1) * self.n_dofs, "q_out")
         if tau is not None:
             _dev_f64(tau, self.n_dofs, "tau")
-        if stats is not None and (not stats.is_cuda or stats.numel() * stats.element_size() < 32 * self.n_models):
-            raise ValueError("stats must be a CUDA buffer of 32 bytes per model")
+        if stats is not None and (not stats.is_cuda or stats.numel() * stats.element_size() < STATS_BYTES * self.n_models):
+            raise ValueError(f"stats must be a CUDA buffer of {STATS_BYTES} bytes per model")
         o = opts.c()
         _check(load().abd_step(self._h, C.byref(o), _ptr(q_hist), _ptr(tau), _ptr(q_out), _ptr(stats),
                                _stream(stream)))
 
     def new_stats(self) -> torch.Tensor:
-        return torch.zeros((max(1, self.n_models), 4), dtype=torch.float64, device="cuda")
+        return torch.zeros((max(1, self.n_models), STATS_BYTES // 8), dtype=torch.float64, device="cuda")
 
     @staticmethod
     def read_stats(stats: torch.Tensor, n_models: int) -> np.ndarray:
-        raw = stats.detach().cpu().numpy().reshape(-1).view(np.uint8)[:32 * n_models]
+        raw = stats.detach().cpu().numpy().reshape(-1).view(np.uint8)[:STATS_BYTES * n_models]
         return raw.view(STATS_DTYPE).copy()
 
-    def objective_grad(self, q, q_hist, dt, tau=None, precision=FP64, order_K=2, stream=None):
+    def objective_grad(self, q, q_hist, dt, tau=None, precision=FP64, order_K=2, want_tau_grad=False,
+                       stream=None):
         """Objective per model and gradient.  order_K > 2: Eq. EQHOC with q the K-1
-        unknown configurations ([K-1, n_dofs]); the gradient has the same shape."""
+        unknown configurations ([K-1, n_dofs]); the gradient has the same shape.
+        With want_tau_grad, also returns dE/dtau [n_dofs] (computed by the library)."""
         U = order_K - 1
         _dev_f64(q, U * self.n_dofs, "q")
         _dev_f64(q_hist, 2 * self.n_dofs, "q_hist")
@@ -201,11 +209,13 @@ class Model:
             _dev_f64(tau, self.n_dofs, "tau")
         E = torch.zeros(max(1, self.n_models), dtype=torch.float64, device="cuda")
         g = torch.zeros(max(1, U * self.n_dofs), dtype=torch.float64, device="cuda")
+        gt = torch.zeros(max(1, self.n_dofs), dtype=torch.float64, device="cuda") if want_tau_grad else None
         o = StepOptions(dt=dt, precision=precision, order_K=order_K).c()
         _check(load().abd_objective_grad(self._h, C.byref(o), _ptr(q), _ptr(q_hist), _ptr(tau), _ptr(E),
-                                         _ptr(g), _stream(stream)))
+                                         _ptr(g), _ptr(gt), _stream(stream)))
         g = g[:U * self.n_dofs]
-        return E[:self.n_models], (g if order_K == 2 else g.view(U, self.n_dofs))
+        out = (E[:self.n_models], (g if order_K == 2 else g.view(U, self.n_dofs)))
+        return out + (gt[:self.n_dofs],) if want_tau_grad else out
 
     def hvp(self, q, q_hist, v, dt, stream=None):
         """Hessian-vector product of the step objective at q (float64)."""
@@ -228,8 +238,8 @@ class Model:
         _dev_f64(q_init, 2 * n, "q_init")
         _dev_f64(q_traj, T * n, "q_traj")
         _dev_f64(dL_dq_traj, T * n, "dL_dq_traj")
-        if stats is not None and stats.numel() * stats.element_size() < 32 * self.n_models * T:
-            raise ValueError("stats must hold 32 bytes per model and step")
+        if stats is not None and stats.numel() * stats.element_size() < STATS_BYTES * self.n_models * T:
+            raise ValueError(f"stats must hold {STATS_BYTES} bytes per model and step")
         g_init = torch.zeros(max(1, 2 * n), dtype=torch.float64, device="cuda")
         g_tau = torch.zeros((max(1, T), max(1, n)), dtype=torch.float64, device="cuda") if want_tau else None
         o = StepOptions(dt=dt, tol=tol, max_iter=max_iter, precond=precond).c()
@@ -260,15 +270,15 @@ class Model:
         _dev_f64(q_traj, max(1, steps) * U * n, "q_traj")
         if torque is not None:
             _dev_f64(torque, steps * n, "torque")
-        if stats is not None and stats.numel() * stats.element_size() < 32 * self.n_models * steps:
-            raise ValueError("stats must hold 32 bytes per model and step")
+        if stats is not None and stats.numel() * stats.element_size() < STATS_BYTES * self.n_models * steps:
+            raise ValueError(f"stats must hold {STATS_BYTES} bytes per model and step")
         o = opts.c()
         _check(load().abd_rollout(self._h, C.byref(o), _ptr(q_init), _ptr(torque), _ptr(q_traj), _ptr(stats),
                                   int(steps), _stream(stream)))
         return q_traj[:steps], stats
 
     def new_rollout_stats(self, steps: int) -> torch.Tensor:
-        return torch.zeros((max(1, steps * self.n_models), 4), dtype=torch.float64, device="cuda")
+        return torch.zeros((max(1, steps * self.n_models), STATS_BYTES // 8), dtype=torch.float64, device="cuda")
 
     def read_rollout_stats(self, stats: torch.Tensor, steps: int) -> np.ndarray:
         return self.read_stats(stats, steps * self.n_models).reshape(steps, self.n_models)
@@ -294,26 +304,25 @@ class Model:
 # ------------------------------------------------------------------ autograd
 class ObjectiveFunction(torch.autograd.Function):
     """E(q) per model (abd_objective_grad) as a differentiable function of q and
-    tau.  Backward: dE/dq from the Alg. 1 gradient the forward pass already
-    computed, dE/dtau = -dt^2 q.  q_hist is treated as a constant."""
+    tau.  Backward: dE/dq (the Alg. 1 gradient) and dE/dtau, both computed by
+    the library in the forward call; the backward only scales them by the
+    incoming per-model weights.  q_hist is treated as a constant."""
 
     @staticmethod
     def forward(ctx, q, tau, model, q_hist, dt):
-        E, g = model.objective_grad(q.detach().contiguous(), q_hist.detach().contiguous(), dt,
-                                    tau=None if tau is None else tau.detach().contiguous())
-        ctx.dt, ctx.has_tau = dt, tau is not None
+        E, g, gt = model.objective_grad(q.detach().contiguous(), q_hist.detach().contiguous(), dt,
+                                        tau=None if tau is None else tau.detach().contiguous(),
+                                        want_tau_grad=True)
+        ctx.has_tau = tau is not None
         dof_model = _dof_model_index(model)
-        ctx.save_for_backward(q.detach(), g, dof_model)
+        ctx.save_for_backward(g, gt, dof_model)
         return E
 
     @staticmethod
     def backward(ctx, gE):
-        q, g, dof_model = ctx.saved_tensors
+        g, gt, dof_model = ctx.saved_tensors
         w = gE[dof_model]
-        gq = w * g
-        # E contains -dt^2 tau.q, so dE/dtau = -dt^2 q
-        gtau = (-ctx.dt * ctx.dt) * w * q if ctx.has_tau else None
-        return gq, gtau, None, None, None
+        return w * g, (w * gt if ctx.has_tau else None), None, None, None
 
 
 def _dof_model_index(model):
@@ -356,5 +365,8 @@ def rollout(model, q_init, steps, opts, torque=None, vjp_tol=1e-10, vjp_max_iter
     to q_init = [q_{-1}; q_0] and to torque [steps, n_dofs]."""
     if opts.precision != FP64:
         raise ValueError("the differentiable rollout runs in float64 (precision=FP64)")
+    if opts.order_K != 2:
+        raise ValueError("the differentiable rollout is defined for order_K = 2 (Eq. EQ); "
+                         "abd_rollout_vjp has no order-K derivative")
     return RolloutFunction.apply(q_init, torque, model, steps, opts,
                                  dict(tol=vjp_tol, max_iter=vjp_max_iter))

@@ -1341,8 +1341,6 @@ __device__ __forceinline__ double next_alpha(double alpha, double E, double Et, 
   return aq < 0.1 * alpha ? 0.1 * alpha : (aq > 0.5 * alpha ? 0.5 * alpha : aq);
 }
 
-// What the next evaluation of an iteration is for.
-enum EvalPurpose { kTrial = 0, kRefresh = 1, kRefreshRetry = 2 };
 // Per-model state of the rollout kernel.
 enum ModelState { kSetup = 0, kIterate = 1, kDone = 2 };
 

@@ -48,9 +48,9 @@ int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, c
 int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
                const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream);
 int launch_hoc_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,
-                         const double* tau, double* E, double* grad, void* stream);
+                         const double* tau, double* E, double* grad, double* grad_tau, void* stream);
 int launch_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,
-                     const double* tau, double* E, double* grad, void* stream);
+                     const double* tau, double* E, double* grad, double* grad_tau, void* stream);
 int launch_poses(abd_model* m, const double* q, double* poses, void* stream);
 int launch_hvp(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist, const double* v,
                double* Hv, void* stream);

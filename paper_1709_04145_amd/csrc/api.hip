@@ -115,6 +115,9 @@ int check_opts(const abd_step_opts* o, bool for_step) {
   if (o->precond != ABD_PRECOND_IDENTITY && o->precond != ABD_PRECOND_INERTIA)
     return fail(ABD_EINVAL, "precond must be ABD_PRECOND_IDENTITY or ABD_PRECOND_INERTIA");
   if (o->refresh < 0) return fail(ABD_EINVAL, "refresh must be >= 0");
+  if (o->schedule != ABD_SCHEDULE_AUTO && o->schedule != ABD_SCHEDULE_WAVE)
+    return fail(ABD_EINVAL, "schedule must be ABD_SCHEDULE_AUTO or ABD_SCHEDULE_WAVE");
+  if (o->solver != ABD_SOLVER_LBFGS) return fail(ABD_EINVAL, "solver must be ABD_SOLVER_LBFGS");
   return ABD_OK;
 }
 
@@ -310,9 +313,9 @@ int abd_model_info(const abd_model* m, int* n_models, int* n_links, int* n_dofs)
 int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const double* tau, double* q_out,
              abd_step_stats* stats, void* stream) {
   g_err.clear();
-  if (!m) return fail(ABD_EINVAL, "model is NULL");
-  int rc = check_opts(o, true);
+  int rc = check_opts(o, true);  // options first: they are checked without a device
   if (rc) return rc;
+  if (!m) return fail(ABD_EINVAL, "model is NULL");
   if (m->n_models == 0) return ABD_OK;
   if (!q_hist || !q_out) return fail(ABD_EINVAL, "q_hist and q_out must not be NULL");
   const size_t out_len = (size_t)(o->order_K - 1) * m->n_dofs;
@@ -326,9 +329,9 @@ int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const d
 int abd_rollout(abd_model* m, const abd_step_opts* o, const double* q_init, const double* tau, double* q_traj,
                 abd_step_stats* stats, int n_steps, void* stream) {
   g_err.clear();
-  if (!m) return fail(ABD_EINVAL, "model is NULL");
-  int rc = check_opts(o, true);
+  int rc = check_opts(o, true);  // options first: they are checked without a device
   if (rc) return rc;
+  if (!m) return fail(ABD_EINVAL, "model is NULL");
   if (n_steps < 0) return fail(ABD_EINVAL, "n_steps must be >= 0");
   if (m->n_models == 0 || n_steps == 0) return ABD_OK;
   if (!q_init || !q_traj) return fail(ABD_EINVAL, "q_init and q_traj must not be NULL");
@@ -341,7 +344,7 @@ int abd_rollout(abd_model* m, const abd_step_opts* o, const double* q_init, cons
 }
 
 int abd_objective_grad(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,
-                       const double* tau, double* E, double* grad, void* stream) {
+                       const double* tau, double* E, double* grad, double* grad_tau, void* stream) {
   g_err.clear();
   if (!m) return fail(ABD_EINVAL, "model is NULL");
   int rc = check_opts(o, false);
@@ -351,8 +354,8 @@ int abd_objective_grad(abd_model* m, const abd_step_opts* o, const double* q, co
   if ((rc = check_device(m))) return rc;
   if (o->order_K < 2) return fail(ABD_EINVAL, "order_K must be >= 2");
   if (o->order_K > 4) return fail(ABD_ENOTSUP, "order_K > 4 is not handled by this build");
-  if (o->order_K > 2) return abd_impl::launch_hoc_objective(m, o, q, q_hist, tau, E, grad, stream);
-  return abd_impl::launch_objective(m, o, q, q_hist, tau, E, grad, stream);
+  if (o->order_K > 2) return abd_impl::launch_hoc_objective(m, o, q, q_hist, tau, E, grad, grad_tau, stream);
+  return abd_impl::launch_objective(m, o, q, q_hist, tau, E, grad, grad_tau, stream);
 }
 
 int abd_hvp(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist, const double* v,

@@ -14,6 +14,7 @@ struct EvalArgs {
   const double* tau;
   double* E;
   double* grad;
+  double* grad_tau;
 };
 
 template <int NW, bool TREE>
@@ -40,6 +41,8 @@ __global__ void __launch_bounds__(NW* kWave) k_objective_grad(EvalArgs a) {
                                                 : evaluate<double>(sc, d, geo, f, valid, q, tau, a.dt2);
   if (j == 0) a.E[model] = r.E;
   if (a.grad && valid) a.grad[io] = r.g;
+  // E contains -dt^2 tau.q
+  if (a.grad_tau && valid) a.grad_tau[io] = -a.dt2 * q;
 }
 
 template <int NW, bool TREE>
@@ -66,7 +69,7 @@ __global__ void __launch_bounds__(NW* kWave) k_poses(DevModel d, const double* q
 namespace abd_impl {
 
 int launch_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,
-                     const double* tau, double* E, double* grad, void* stream) {
+                     const double* tau, double* E, double* grad, double* grad_tau, void* stream) {
   EvalArgs a;
   a.d = dev_view(m);
   a.dt2 = o->dt * o->dt;
@@ -77,6 +80,7 @@ int launch_objective(abd_model* m, const abd_step_opts* o, const double* q, cons
   a.tau = tau;
   a.E = E;
   a.grad = grad;
+  a.grad_tau = grad_tau;
   const int nw = waves_for(m->max_frames);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 grid(m->n_models), block(nw * kWave);

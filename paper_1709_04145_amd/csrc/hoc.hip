@@ -71,7 +71,7 @@ __device__ double adjoint_fixed_seed_tangent(Sc& sc, const Xf<double>& A, const 
 // One EQHOC evaluation (float64): E (wave-uniform) and the gradient g[U] of this lane.
 template <int U, typename Sc>
 __device__ double hoc_evaluate(Sc& sc, const HocArgs<U>& args, const FrameGeo& geo, int f, bool valid,
-                               const double q[U], double tau, double g[U]) {
+                               const double q[U], double tau, double g[U], double* rho_sum = nullptr) {
   const DevModel& d = args.d;
   asm volatile("" ::: "memory");
   double M[10];
@@ -126,6 +126,12 @@ __device__ double hoc_evaluate(Sc& sc, const HocArgs<U>& args, const FrameGeo& g
     const double r = w[0] * (KF[u][0] - pF[0]) + w[1] * (KF[u][1] - pF[1]) + w[2] * (KF[u][2] - pF[2]);
     rho[u] = valid ? r - args.dt2 * tau : 0.0;
     E += rho[u] * rho[u];
+  }
+  if (rho_sum) {
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) t += rho[u];
+    *rho_sum = t;
   }
   E = sc.sum(E);
   // tangents along the residuals; fixed-seed terms; mixed-seed accumulation
@@ -191,7 +197,7 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
   if (nf == 0) {
     if (lead && args.stats)
       for (int k = 0; k < args.n_steps; ++k) {
-        abd_step_stats st = {0, 0, ABD_FLAG_CONVERGED, 0, 0.0, 0.0};
+        abd_step_stats st = {0, 0, ABD_FLAG_CONVERGED, 0, 0, 0, 0.0, 0.0};
         args.stats[(size_t)k * d.n_models + model] = st;
       }
     return;
@@ -439,6 +445,8 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
       st.evaluations = evals;
       st.flag = flag;
       st.f32_iterations = 0;
+      st.f32_evaluations = 0;
+      st.reserved = 0;
       st.grad_norm = gn;
       st.energy = E;
       args.stats[(size_t)step * d.n_models + model] = st;
@@ -458,6 +466,7 @@ struct HocObjArgs {
   const double* tau;
   double* E;
   double* grad;        // [U][n] or NULL
+  double* grad_tau;    // [n] or NULL
   double* Bk;
 };
 
@@ -497,8 +506,11 @@ __global__ void __launch_bounds__(NW* kWave) k_hoc_objective(HocObjArgs a) {
 #pragma unroll
   for (int u = 0; u < U; ++u) q[u] = valid ? a.q[(size_t)u * n + io] : 0.0;
   const double tau = (valid && a.tau) ? a.tau[io] : 0.0;
-  const double E = hoc_evaluate<U>(ws, h, geo, f, valid, q, tau, g);
+  double rsum = 0.0;
+  const double E = hoc_evaluate<U>(ws, h, geo, f, valid, q, tau, g, &rsum);
   if (j == 0) a.E[model] = E;
+  // rho_u = (adjoint term) - dt^2 tau, so dE/dtau = -2 dt^2 sum_u rho_u
+  if (a.grad_tau && valid) a.grad_tau[io] = -2.0 * a.dt2 * rsum;
   if (a.grad && valid)
 #pragma unroll
     for (int u = 0; u < U; ++u) a.grad[(size_t)u * n + io] = g[u];
@@ -651,7 +663,7 @@ int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const
 }
 
 int launch_hoc_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,
-                         const double* tau, double* E, double* grad, void* stream) {
+                         const double* tau, double* E, double* grad, double* grad_tau, void* stream) {
   int rc = check_hoc(m, o);
   if (rc) return rc;
   const int U = o->order_K - 1;
@@ -670,6 +682,7 @@ int launch_hoc_objective(abd_model* m, const abd_step_opts* o, const double* q, 
   h.tau = tau;
   h.E = E;
   h.grad = grad;
+  h.grad_tau = grad_tau;
   h.Bk = m->Bk;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nw = waves_for(m->max_frames);

@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   if (nf == 0) {  // a model without frames: every step is trivially converged
     if (lead && args.stats)
       for (int k = 0; k < args.n_steps; ++k) {
-        abd_step_stats st = {0, 0, ABD_FLAG_CONVERGED, 0, 0.0, 0.0};
+        abd_step_stats st = {0, 0, ABD_FLAG_CONVERGED, 0, 0, 0, 0.0, 0.0};
         args.stats[(size_t)k * d.n_models + model] = st;
       }
     return;
@@ -64,8 +64,10 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   // set when the float32 inverse is no descent preconditioner at the iterate:
   // the step then continues with H0 = gamma I until the next formation
   bool h0_plain = false;
-  bool leave32 = false;  // MIXED: the float32 phase ends at the step's first re-formation
-  int iters = 0, evals = 0, flag = 0, f32_iters = 0, count = 0, head = 0, refreshed = 0;
+  // MIXED: re-evaluate at the iterate in float64 before the next direction (set
+  // when float32 has done what it can, and at the step's first re-formation)
+  bool to64 = false;
+  int iters = 0, evals = 0, flag = 0, f32_iters = 0, f32_evals = 0, count = 0, head = 0, refreshed = 0;
   double q = 0.0, tau = 0.0, E = 0.0, g = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0;
 #ifdef ABD_PROFILE
   if (lead && abd_prof) abd_prof[(size_t)model * 16 + 10] = __builtin_amdgcn_s_memrealtime();
@@ -114,9 +116,10 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
       q = valid ? 2.0 * qk - qkm1 : 0.0;  // warm start: constant-velocity extrapolation
       tau = (valid && args.tau) ? args.tau[(size_t)step * n + io] : 0.0;
       f32 = PREC == ABD_MIXED;
-      iters = 0; evals = 0; flag = 0; f32_iters = 0; count = 0; head = 0; refreshed = 0; reset = false; gam = 1.0;
+      iters = 0; evals = 0; flag = 0; f32_iters = 0; f32_evals = 0; count = 0; head = 0; refreshed = 0;
+      reset = false; gam = 1.0;
       h0_plain = false;
-      leave32 = false;
+      to64 = false;
       if (nf == 0) {
         flag = ABD_FLAG_CONVERGED;
         step_done = true;
@@ -127,6 +130,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(sc, d, geo, f, valid, q, tau, args.dt2)
                                                   : evaluate<double>(sc, d, geo, f, valid, q, tau, args.dt2);
         ++evals;
+        if (PREC == ABD_MIXED) ++f32_evals;
         E = r.E;
         g = r.g;
         gn = 0.0;
@@ -158,200 +162,201 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         count = 0;
         head = 0;
         h0_plain = false;
-        if (PREC == ABD_MIXED && f32) leave32 = true;
+        if (PREC == ABD_MIXED && f32) to64 = true;
         PROF_ADD(4, t_f);
 #ifdef ABD_PROFILE
         if (lead && abd_prof) abd_prof[(size_t)model * 16 + 8] += 1;
 #endif
       }
-      PROF_T(t_a);
-      // ---- two-loop recursion: newest pair first; the next pair is requested
-      // while the current one is used
-      if (reset) count = 0;
-      double qv = g;
-      {
-        double sk = ld_if(hs + head * hstride, valid && count > 0);
-        double yk = ld_if(hs + ys + head * hstride, valid && count > 0);
-        for (int k = 0; k < count; ++k) {
-          const int nxt = (head - k - 1 + args.m) % args.m;
-          const double sn = ld_if(hs + nxt * hstride, valid && k + 1 < count);
-          const double yn = ld_if(hs + ys + nxt * hstride, valid && k + 1 < count);
-          // the reduction (a barrier for several waves) before the LDS read of
-          // rho, which the lead lane writes when the pair is accepted
-          const double sq = sc.sum(sk * qv);
-          const double a_k = uniform(L.rho[(head - k + args.m) % args.m] * sq);
-          if (lead) L.alp[k] = a_k;
-          qv -= a_k * yk;
-          sk = sn;
-          yk = yn;
-        }
-      }
-      // ---- initial inverse Hessian
-      double r;
-      if (!use_aba || h0_plain) {
-        r = (count > 0 ? gam : 1.0) * qv;
-      } else if (NW == 1 && !TREE) {
-        PROF_T(t_h);
-        // the recursion's table is free between formations
-        r = inv32 ? apply_inverse_f32(reinterpret_cast<const float*>(hl), reinterpret_cast<float*>(&L.tab[0][0]), nf, lane, qv)
-                  : apply_inverse(hl, &L.tab[0][0], nf, lane, qv);
-        PROF_ADD(14, t_h);
-      } else {
-        L.xb[j] = valid ? qv : 0.0;
-        __syncthreads();
-        if (lead) {
-          if (TREE)
-            aba_solve_tree(L.tab, L.xb, L.tpar, L.acc, nf);
-          else
-            aba_solve(L.tab, L.xb, nf);
-        }
-        __syncthreads();
-        r = ld_if(&L.xb[j], valid);
-      }
-      PROF_ADD(1, t_a);
-      PROF_T(t_c);
-      PROF_T(t_l);
-      // ---- oldest pair first
-      {
-        int slot = (head - (count - 1) + args.m) % args.m;
-        double sk = ld_if(hs + slot * hstride, valid && count > 0);
-        double yk = ld_if(hs + ys + slot * hstride, valid && count > 0);
-        for (int k = count - 1; k >= 0; --k) {
-          const int nxt = (slot + 1) % args.m;
-          const double sn = ld_if(hs + nxt * hstride, valid && k > 0);
-          const double yn = ld_if(hs + ys + nxt * hstride, valid && k > 0);
-          const double yr = sc.sum(yk * r);
-          const double b = uniform(L.rho[slot] * yr);
-          r += (L.alp[k] - b) * sk;
-          sk = sn;
-          yk = yn;
-          slot = nxt;
-        }
-      }
-      const double dir = valid ? -r : 0.0;
-      const double gd = uniform(sc.sum(g * dir));
-      PROF_ADD(12, t_l);
-      if (!(gd < 0.0)) {
-        if (!reset) {
-          reset = true;  // redo the direction with an empty history
-        } else if (inv32 && !h0_plain) {
-          h0_plain = true;  // -H0 g is no descent direction either
-        } else {
-          flag = ABD_FLAG_LS_FLOOR;
+      if (PREC == ABD_MIXED && to64) {
+        // leave float32: re-evaluate at q in float64 (right after a re-formation,
+        // or where float32 converged, met its rounding or stalled the search)
+        to64 = false;
+        f32 = false;
+        const EvalResult r = evaluate<double>(sc, d, geo, f, valid, q, tau, args.dt2);
+        ++evals;
+        E = r.E;
+        g = r.g;
+        gn = uniform(sqrt(sc.sum(g * g)));
+        if (gn <= args.tol * g0) {
+          flag = ABD_FLAG_CONVERGED;
+          step_done = true;
+        } else if (iters >= args.max_iter) {
+          flag = ABD_FLAG_MAX_ITER;
           step_done = true;
         }
-      } else {
-        reset = false;
-        double alpha = 1.0;
-        int ls = 0;
-        bool noisy = false;
-        int purpose = kTrial;
-        for (;;) {
-          if (PREC == ABD_MIXED && leave32) {
-            leave32 = false;
-            f32 = false;  // continue in float64 from q
-            purpose = kRefresh;
+      }
+      PROF_T(t_a);
+      if (!step_done) {
+        // ---- two-loop recursion: newest pair first; the next pair is requested
+        // while the current one is used
+        if (reset) count = 0;
+        double qv = g;
+        {
+          double sk = ld_if(hs + head * hstride, valid && count > 0);
+          double yk = ld_if(hs + ys + head * hstride, valid && count > 0);
+          for (int k = 0; k < count; ++k) {
+            const int nxt = (head - k - 1 + args.m) % args.m;
+            const double sn = ld_if(hs + nxt * hstride, valid && k + 1 < count);
+            const double yn = ld_if(hs + ys + nxt * hstride, valid && k + 1 < count);
+            // the reduction (a barrier for several waves) before the LDS read of
+            // rho, which the lead lane writes when the pair is accepted
+            const double sq = sc.sum(sk * qv);
+            const double a_k = uniform(L.rho[(head - k + args.m) % args.m] * sq);
+            if (lead) L.alp[k] = a_k;
+            qv -= a_k * yk;
+            sk = sn;
+            yk = yn;
           }
-          const double x = purpose == kTrial ? q + alpha * dir : q;
-          EvalResult rt;
-          PROF_T(t_e);
-          if (PREC == ABD_MIXED && f32)
-            rt = evaluate<float>(sc, d, geo, f, valid, x, tau, args.dt2);
-          else
-            rt = evaluate<double>(sc, d, geo, f, valid, x, tau, args.dt2);
-          PROF_ADD(6, t_e);
-#ifdef ABD_PROFILE
-          if (lead && abd_prof) abd_prof[(size_t)model * 16 + 7] += 1;
-#endif
-          ++evals;
-          if (purpose != kTrial) {
-            // float64 re-evaluation at q after leaving float32
-            E = rt.E;
-            g = rt.g;
-            gn = uniform(sqrt(sc.sum(g * g)));
-            if (purpose == kRefresh) {
-              if (gn <= args.tol * g0) {
-                flag = ABD_FLAG_CONVERGED;
-                step_done = true;
-              } else if (iters >= args.max_iter) {
-                flag = ABD_FLAG_MAX_ITER;
-                step_done = true;
+        }
+        // ---- initial inverse Hessian
+        double r;
+        if (!use_aba || h0_plain) {
+          r = (count > 0 ? gam : 1.0) * qv;
+        } else if (NW == 1 && !TREE) {
+          PROF_T(t_h);
+          // the recursion's table is free between formations
+          r = inv32 ? apply_inverse_f32(reinterpret_cast<const float*>(hl), reinterpret_cast<float*>(&L.tab[0][0]), nf, lane, qv)
+                    : apply_inverse(hl, &L.tab[0][0], nf, lane, qv);
+          PROF_ADD(14, t_h);
+        } else {
+          L.xb[j] = valid ? qv : 0.0;
+          __syncthreads();
+          if (lead) {
+            if (TREE)
+              aba_solve_tree(L.tab, L.xb, L.tpar, L.acc, nf);
+            else
+              aba_solve(L.tab, L.xb, nf);
+          }
+          __syncthreads();
+          r = ld_if(&L.xb[j], valid);
+        }
+        PROF_ADD(1, t_a);
+        PROF_T(t_c);
+        PROF_T(t_l);
+        // ---- oldest pair first
+        {
+          int slot = (head - (count - 1) + args.m) % args.m;
+          double sk = ld_if(hs + slot * hstride, valid && count > 0);
+          double yk = ld_if(hs + ys + slot * hstride, valid && count > 0);
+          for (int k = count - 1; k >= 0; --k) {
+            const int nxt = (slot + 1) % args.m;
+            const double sn = ld_if(hs + nxt * hstride, valid && k > 0);
+            const double yn = ld_if(hs + ys + nxt * hstride, valid && k > 0);
+            const double yr = sc.sum(yk * r);
+            const double b = uniform(L.rho[slot] * yr);
+            r += (L.alp[k] - b) * sk;
+            sk = sn;
+            yk = yn;
+            slot = nxt;
+          }
+        }
+        const double dir = valid ? -r : 0.0;
+        const double gd = uniform(sc.sum(g * dir));
+        PROF_ADD(12, t_l);
+        if (!(gd < 0.0)) {
+          if (!reset) {
+            reset = true;  // redo the direction with an empty history
+          } else if (inv32 && !h0_plain) {
+            h0_plain = true;  // -H0 g is no descent direction either
+          } else if (PREC == ABD_MIXED && f32) {
+            to64 = true;  // the float32 gradient gives no descent direction: go on in float64
+            reset = false;
+            h0_plain = false;
+          } else {
+            flag = ABD_FLAG_LS_FLOOR;
+            step_done = true;
+          }
+        } else {
+          reset = false;
+          double alpha = 1.0;
+          int ls = 0;
+          bool noisy = false;
+          for (;;) {
+            const double x = q + alpha * dir;
+            EvalResult rt;
+            PROF_T(t_e);
+            if (PREC == ABD_MIXED && f32) {
+              rt = evaluate<float>(sc, d, geo, f, valid, x, tau, args.dt2);
+              ++f32_evals;
+            } else {
+              rt = evaluate<double>(sc, d, geo, f, valid, x, tau, args.dt2);
+            }
+            PROF_ADD(6, t_e);
+  #ifdef ABD_PROFILE
+            if (lead && abd_prof) abd_prof[(size_t)model * 16 + 7] += 1;
+  #endif
+            ++evals;
+            int ok = 0;
+            if (isfinite(rt.E) && sc.all_finite(rt.g)) {
+              if (rt.E <= E + c1 * alpha * gd) {
+                ok = 1;
+              } else if (fabs(rt.E - E) <= 10.0 * eps_w * rt.S) {
+                noisy = true;
+                const double gtd = sc.sum(rt.g * dir);
+                if (gtd <= (2.0 * dlt - 1.0) * gd) ok = 1;
               }
             }
+            if (!ok) {
+              alpha = next_alpha(alpha, E, rt.E, gd);
+              if (++ls < args.max_ls) continue;
+              if (PREC == ABD_MIXED && f32) {
+                to64 = true;  // float32 rounding stalls the search: continue in float64 from q
+                break;
+              }
+              flag = ABD_FLAG_LS_FLOOR;
+              step_done = true;
+              break;
+            }
+            // an accepted trial point that equals q in every coordinate is no
+            // progress: at this precision the iteration cannot move any more
+            if (uniform(sc.sum(valid && x != q ? 1.0 : 0.0)) == 0.0) {
+              if (PREC == ABD_MIXED && f32) {
+                to64 = true;
+                break;
+              }
+              flag = ABD_FLAG_LS_FLOOR;
+              step_done = true;
+              break;
+            }
+            // accepted: curvature pair (the step actually taken) and update
+            PROF_T(t_u);
+            const double sv = x - q;
+            const double y = rt.g - g;
+            double sy = sv * y, ss = sv * sv, yy = y * y, gg = rt.g * rt.g;
+            sc.sum2(sy, ss);
+            sc.sum2(yy, gg);
+            if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
+              gam = uniform(sy / yy);
+              head = count == 0 ? 0 : (head + 1) % args.m;
+              if (lead) L.rho[head] = 1.0 / sy;  // rho lives in the ring slot of its pair
+              if (valid) {
+                hs[head * hstride] = sv;
+                hs[ys + head * hstride] = y;
+              }
+              if (count < args.m) ++count;
+            }
+            q = x;
+            g = rt.g;
+            E = rt.E;
+            ++iters;
+            if (PREC == ABD_MIXED && f32) ++f32_iters;
+            gn = uniform(sqrt(gg));
+            PROF_ADD(13, t_u);
+            const bool conv = gn <= args.tol * g0;
+            if (PREC == ABD_MIXED && f32 && (conv || noisy)) {
+              to64 = true;  // float32 has done what it can: confirm / continue in float64
+              break;
+            }
+            if (conv) {
+              flag = ABD_FLAG_CONVERGED;
+              step_done = true;
+            } else if (iters >= args.max_iter) {
+              flag = ABD_FLAG_MAX_ITER;
+              step_done = true;
+            }
             break;
           }
-          int ok = 0;
-          if (isfinite(rt.E) && sc.all_finite(rt.g)) {
-            if (rt.E <= E + c1 * alpha * gd) {
-              ok = 1;
-            } else if (fabs(rt.E - E) <= 10.0 * eps_w * rt.S) {
-              noisy = true;
-              const double gtd = sc.sum(rt.g * dir);
-              if (gtd <= (2.0 * dlt - 1.0) * gd) ok = 1;
-            }
-          }
-          if (!ok) {
-            alpha = next_alpha(alpha, E, rt.E, gd);
-            if (++ls < args.max_ls) continue;
-            if (PREC == ABD_MIXED && f32) {
-              f32 = false;  // float32 rounding stalls the search: continue in float64 from q
-              purpose = kRefreshRetry;
-              continue;
-            }
-            flag = ABD_FLAG_LS_FLOOR;
-            step_done = true;
-            break;
-          }
-          // an accepted trial point that equals q in every coordinate is no
-          // progress: at this precision the iteration cannot move any more
-          if (uniform(sc.sum(valid && x != q ? 1.0 : 0.0)) == 0.0) {
-            if (PREC == ABD_MIXED && f32) {
-              f32 = false;
-              purpose = kRefreshRetry;
-              continue;
-            }
-            flag = ABD_FLAG_LS_FLOOR;
-            step_done = true;
-            break;
-          }
-          // accepted: curvature pair (the step actually taken) and update
-          PROF_T(t_u);
-          const double sv = x - q;
-          const double y = rt.g - g;
-          double sy = sv * y, ss = sv * sv, yy = y * y, gg = rt.g * rt.g;
-          sc.sum2(sy, ss);
-          sc.sum2(yy, gg);
-          if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
-            gam = uniform(sy / yy);
-            head = count == 0 ? 0 : (head + 1) % args.m;
-            if (lead) L.rho[head] = 1.0 / sy;  // rho lives in the ring slot of its pair
-            if (valid) {
-              hs[head * hstride] = sv;
-              hs[ys + head * hstride] = y;
-            }
-            if (count < args.m) ++count;
-          }
-          q = x;
-          g = rt.g;
-          E = rt.E;
-          ++iters;
-          if (PREC == ABD_MIXED && f32) ++f32_iters;
-          gn = uniform(sqrt(gg));
-          PROF_ADD(13, t_u);
-          const bool conv = gn <= args.tol * g0;
-          if (PREC == ABD_MIXED && f32 && (conv || noisy)) {
-            f32 = false;  // float32 has done what it can: confirm / continue in float64
-            purpose = kRefresh;
-            continue;
-          }
-          if (conv) {
-            flag = ABD_FLAG_CONVERGED;
-            step_done = true;
-          } else if (iters >= args.max_iter) {
-            flag = ABD_FLAG_MAX_ITER;
-            step_done = true;
-          }
-          break;
         }
       }
       PROF_ADD(5, t_c);
@@ -367,6 +372,8 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         st.evaluations = evals;
         st.flag = flag;
         st.f32_iterations = f32_iters;
+        st.f32_evaluations = f32_evals;
+        st.reserved = 0;
         st.grad_norm = gn;
         st.energy = E;
         args.stats[(size_t)step * d.n_models + model] = st;

@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
   if (nf == 0) {
     if (lane == 0 && args.stats)
       for (int k = 0; k < T; ++k) {
-        abd_step_stats st = {0, 0, ABD_FLAG_CONVERGED, 0, 0.0, 0.0};
+        abd_step_stats st = {0, 0, ABD_FLAG_CONVERGED, 0, 0, 0, 0.0, 0.0};
         args.stats[(size_t)k * d.n_models + model] = st;
       }
     return;
@@ -167,6 +167,8 @@ __global__ void __launch_bounds__(kWave) k_rollout_vjp(VjpArgs args) {
       st.evaluations = hv_count;
       st.flag = flag;
       st.f32_iterations = 0;
+      st.f32_evaluations = 0;
+      st.reserved = 0;
       st.grad_norm = rn;
       st.energy = 0.0;
       args.stats[(size_t)k * d.n_models + model] = st;

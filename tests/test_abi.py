@@ -77,4 +77,48 @@ def test_invalid_descriptions_are_rejected_on_the_host(lib, mutate, needle):
 def test_null_arguments_are_rejected(lib):
     assert lib.abd_create_model(None, None) == abd.ABD_EINVAL
     assert lib.abd_step(None, None, None, None, None, None, None) == abd.ABD_EINVAL
-    assert lib.abd_objective_grad(None, None, None, None, None, None, None, None) == abd.ABD_EINVAL
+    assert lib.abd_objective_grad(None, None, None, None, None, None, None, None, None) == abd.ABD_EINVAL
+
+
+def test_struct_layouts_match_the_header():
+    """The binding's ctypes structures have the sizes the header's comments state."""
+    assert C.sizeof(abd.StepOptsC) == 56
+    assert abd.STATS_DTYPE.itemsize == abd.STATS_BYTES == 40
+    text = open(os.path.join(ROOT, "include", "abd.h")).read()
+    for field in ("schedule", "solver", "f32_evaluations"):
+        assert field in text
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("schedule", 7, "schedule"),
+    ("schedule", -1, "schedule"),
+    ("solver", 9, "solver"),
+    ("order_K", 1, "order_K"),
+    ("lbfgs_m", 0, "lbfgs_m"),
+    ("refresh", -2, "refresh"),
+])
+def test_step_options_are_validated_before_the_device(lib, field, value, needle):
+    """abd_step and abd_rollout check their options on the host, before the
+    model handle and before anything is enqueued."""
+    o = abd.StepOptions(dt=0.01)
+    setattr(o, field, value)
+    oc = o.c()
+    assert lib.abd_step(None, C.byref(oc), None, None, None, None, None) == abd.ABD_EINVAL
+    assert needle in lib.abd_last_error().decode()
+    assert lib.abd_rollout(None, C.byref(oc), None, None, None, None, 1, None) == abd.ABD_EINVAL
+    assert needle in lib.abd_last_error().decode()
+
+
+def test_valid_schedules_pass_the_option_check(lib):
+    """A valid option set reaches the next check (the NULL model)."""
+    for sched in (abd.SCHEDULE_AUTO, abd.SCHEDULE_WAVE):
+        oc = abd.StepOptions(dt=0.01, schedule=sched).c()
+        assert lib.abd_step(None, C.byref(oc), None, None, None, None, None) == abd.ABD_EINVAL
+        assert "model is NULL" in lib.abd_last_error().decode()
+
+
+def test_differentiable_rollout_rejects_higher_orders():
+    """abd_rollout_vjp has no order-K derivative: the autograd rollout refuses
+    order_K != 2 instead of flattening the K-1 configurations of a step."""
+    with pytest.raises(ValueError, match="order_K"):
+        abd.rollout(None, None, 3, abd.StepOptions(dt=0.01, order_K=3))

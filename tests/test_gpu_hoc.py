@@ -100,6 +100,49 @@ def test_eqhoc_objective_and_gradient(K):
         assert _rel(gg[:, sl], g[:, sl]) <= 1e-9, (i, _rel(gg[:, sl], g[:, sl]))
 
 
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_torque_derivative_from_the_library(K):
+    """abd_objective_grad's dE/dtau against central differences of the oracle's
+    objective in tau (E is quadratic in tau, so the differences are exact up to
+    rounding); every model's j-th joint force is perturbed at once."""
+    d = mixed_chains(12, 40 + K, max_dofs=16)
+    rng = np.random.default_rng(110 + K)
+    qp, qc = (rng.uniform(-1, 1, d.n_dofs) for _ in range(2))
+    tau = rng.uniform(-1, 1, d.n_dofs)
+    dt = 0.03
+    orc = Oracle(d)
+    qu = rng.uniform(-1, 1, ((K - 1), d.n_dofs))
+    m = abd.Model(d)
+    say(f"torque derivative K={K}")
+    _, _, gt = m.objective_grad(cu(qu.reshape(-1)), cu(np.concatenate([qp, qc])), dt, tau=cu(tau), order_K=K,
+                                want_tau_grad=True)
+    gt = gt.cpu().numpy()
+
+    def E(t):
+        if K == 2:
+            return orc.objective_grad(qu[0], qp, qc, dt, t)[0]
+        return orc.eqhoc_objective_grad(K, dt, qp, qc, qu, t)[0]
+
+    do = d.dof_offset
+    nmax = int(np.max(np.diff(do)))
+    fd = np.zeros(d.n_dofs)
+    h = 1e-3
+    for jj in range(nmax):
+        idx = [do[i] + jj for i in range(d.n_models) if do[i] + jj < do[i + 1]]
+        tp, tm = tau.copy(), tau.copy()
+        tp[idx] += h
+        tm[idx] -= h
+        dE = (E(tp) - E(tm)) / (2 * h)
+        for i in range(d.n_models):
+            if do[i] + jj < do[i + 1]:
+                fd[do[i] + jj] = dE[i]
+    if K == 2:
+        assert np.array_equal(gt, -dt * dt * qu[0])
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        assert _rel(gt[sl], fd[sl]) <= 1e-7, (i, _rel(gt[sl], fd[sl]))
+
+
 @pytest.mark.parametrize("K", [3, 4])
 def test_eqhoc_step_matches_oracle(K):
     d = W.random_chain_models(8, 11, lo=4, hi=12)

@@ -182,6 +182,16 @@ def test_config2_subset_teacher_forced(precision):
             ex, eR = pose_error(orc, wl.model, out, ref)
             assert ex <= 1e-5 and eR <= 1e-5, (k, ex, eR)
             assert np.all(st["flag"] == 1), np.unique(st["flag"], return_counts=True)
+            _check_float32_phase(st, abd.REFRESH)
+
+
+def _check_float32_phase(st, refresh):
+    """Mixed steps: the float32 phase ends at the step's first re-formation of the
+    preconditioner (so at most `refresh` float32 iterations), the warm start is
+    evaluated in float32, and float32 evaluations are a subset of all of them."""
+    assert np.all(st["f32_iterations"] <= refresh), int(st["f32_iterations"].max())
+    assert np.all(st["f32_evaluations"] >= st["f32_iterations"] + 1), "float32 evaluations undercounted"
+    assert np.all(st["f32_evaluations"] <= st["evaluations"])
 
 
 def test_frozen_preconditioner_matches_oracle():
@@ -384,6 +394,35 @@ def test_rollout_with_torques_matches_oracle():
             hinv = 1.0 / np.min(np.linalg.eigvalsh(H[i]))
             err = np.linalg.norm(qg[k + 2][sl] - qs[sl])
             assert err <= 1.5 * hinv * gq + 1e-12, (k, i, err, hinv * gq)
+def test_mixed_rollout_with_torques_bounded_float32_phase():
+    """Mixed-precision rollout on the torque workload's chains (1 m, 10 kg links,
+    joint forces per step): each step's float32 phase stays within the first
+    re-formation interval, and every step's result is within 1e-5 relative pose
+    error of the oracle's minimizer of the same step (teacher-forced from the
+    GPU's own float64 history, oracle solved to 1e-11 and Newton-polished)."""
+    steps = 5
+    wl = W.config(5, n_models=32, steps=steps)
+    dt = wl.step.dt
+    d = wl.model
+    say("mixed rollout with torques")
+    m = abd.Model(d)
+    q0 = cu(wl.q0)
+    st = m.new_rollout_stats(steps)
+    traj, _ = m.rollout(torch.cat([q0, q0]), steps, abd.StepOptions(dt=dt, precision=abd.MIXED),
+                        torque=cu(wl.torque), stats=st)
+    st = m.read_rollout_stats(st, steps)
+    qg = np.concatenate([wl.q0[None], wl.q0[None], traj.cpu().numpy()])
+    orc = Oracle(d)
+    for k in range(steps):
+        _check_float32_phase(st[k], abd.REFRESH)
+        assert np.all(st[k]["flag"] == abd.FLAG_CONVERGED), (k, np.unique(st[k]["flag"]))
+        qp, qc, tau = qg[k], qg[k + 1], wl.torque[k]
+        ref, _ = orc.step(qp, qc, dt, tau=tau, tol=1e-11, max_iter=2000)
+        qs, _ = orc.newton_polish(ref, qp, qc, dt, tau=tau, iters=3)
+        ex, eR = pose_error(orc, d, qg[k + 2], qs)
+        assert ex <= 1e-5 and eR <= 1e-5, (k, ex, eR)
+
+
 # ------------------------------------------------------------- edge cases
 def test_empty_batch():
     d = W.random_chain_models(0, 1)
