@@ -209,6 +209,7 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
   const bool use_aba = args.precond == ABD_PRECOND_INERTIA;
   const bool explicit_inverse = NW == 1 && !TREE;
   double* Hi = d.hinv + d.hoff[model];
+  __shared__ double inert_sink[10];  // written by lanes without a frame, never read
   const FrameGeo geo = load_geo(d, f, valid);
   const double eps_w = 1.1102230246251565e-16;
   const double c1 = 1e-4, dlt = 0.1;
@@ -249,7 +250,8 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
               args.Bk[(size_t)f * (12 * U) + 12 * u + k] = args.w[u][0] * Ap.m[k] + args.w[u][1] * Ak.m[k];
       }
       if (use_aba) {
-        double* inert = NW == 1 ? (TREE ? L.inert[lane] : hl + 10 * lane) : Hi + (size_t)(valid ? j : 0) * 10;
+        // lanes without a frame of a multi-wave model: a sink, not frame 0's slot
+        double* inert = NW == 1 ? (TREE ? L.inert[lane] : hl + 10 * lane) : (valid ? Hi + (size_t)j * 10 : inert_sink);
         step_setup(ws, d, inert, L.tab[j], geo, f, valid, qprev, qk, qk, true);
         if (NW > 1) __threadfence_block();
         __syncthreads();

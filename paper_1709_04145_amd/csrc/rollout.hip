@@ -107,7 +107,10 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
     }
     PROF_ADD(3, t_i);
   };
-  double* const inert = NW == 1 ? (TREE ? L.inert[lane] : hl + 10 * lane) : Hi + (size_t)(valid ? j : 0) * 10;
+  // frames' inertias: lanes without a frame of a multi-wave model write their
+  // (zero) record to a sink, never to frame 0's slot, which lane 0 fills
+  __shared__ double inert_sink[10];
+  double* const inert = NW == 1 ? (TREE ? L.inert[lane] : hl + 10 * lane) : (valid ? Hi + (size_t)j * 10 : inert_sink);
 
   while (state != kDone) {
     bool step_done = false;

@@ -102,9 +102,11 @@ def test_eqhoc_objective_and_gradient(K):
 
 @pytest.mark.parametrize("K", [2, 3, 4])
 def test_torque_derivative_from_the_library(K):
-    """abd_objective_grad's dE/dtau against central differences of the oracle's
-    objective in tau (E is quadratic in tau, so the differences are exact up to
-    rounding); every model's j-th joint force is perturbed at once."""
+    """abd_objective_grad's dE/dtau against the oracle: for order K > 2 against
+    -2 dt^2 sum_u (dt^2 r_u) from the oracle's residuals, and for every order
+    against central differences of the oracle's objective in tau (E is quadratic
+    in tau, so the differences are exact up to rounding, which a wide step keeps
+    small); every model's j-th joint force is perturbed at once."""
     d = mixed_chains(12, 40 + K, max_dofs=16)
     rng = np.random.default_rng(110 + K)
     qp, qc = (rng.uniform(-1, 1, d.n_dofs) for _ in range(2))
@@ -126,7 +128,7 @@ def test_torque_derivative_from_the_library(K):
     do = d.dof_offset
     nmax = int(np.max(np.diff(do)))
     fd = np.zeros(d.n_dofs)
-    h = 1e-3
+    h = 1.0
     for jj in range(nmax):
         idx = [do[i] + jj for i in range(d.n_models) if do[i] + jj < do[i + 1]]
         tp, tm = tau.copy(), tau.copy()
@@ -138,6 +140,12 @@ def test_torque_derivative_from_the_library(K):
                 fd[do[i] + jj] = dE[i]
     if K == 2:
         assert np.array_equal(gt, -dt * dt * qu[0])
+    else:
+        R, _ = orc.eqhoc_residual_jacobian(K, dt, qp, qc, qu, tau, jacobian=False)
+        exact = -2.0 * dt * dt * R.sum(axis=0)
+        for i in range(d.n_models):
+            sl = slice(do[i], do[i + 1])
+            assert _rel(gt[sl], exact[sl]) <= 1e-11, (i, _rel(gt[sl], exact[sl]))
     for i in range(d.n_models):
         sl = slice(do[i], do[i + 1])
         assert _rel(gt[sl], fd[sl]) <= 1e-7, (i, _rel(gt[sl], fd[sl]))
