@@ -1050,9 +1050,12 @@ static void hoc_free(hoc_ws* h) {
  *   S(q; G)_bc = sum_l <G_l, d2A_l(q)/dq_b dq_c>,
  *   C(q, q')_bc = sum_l <dA_l(q)/dq_b M_l, dA_l(q')/dq'_c>,
  * written out from the pose derivatives (dT/dq_n = W_n T, d2T/dq_b dq_c = W_b W_c T).
- * grad (may be NULL) receives [K-1][nd] local values. */
+ * grad (may be NULL) receives [K-1][nd] local values; res_out (may be NULL) the
+ * scaled residuals dt^2 r_u ([K-1][nd]); jac_out (may be NULL) the Jacobian of
+ * those residuals, row (u, b), column (a, c), row-major [(K-1) nd]^2. */
 static double hoc_eval_model(const orc_model* m, int i, int K, const double* w, double dt,
-                             const double* const* pts, const double* tau, hoc_ws* h, double* grad) {
+                             const double* const* pts, const double* tau, hoc_ws* h, double* grad,
+                             double* res_out, double* jac_out) {
   const int d0 = m->model_dof[i], nd = model_nd(m, i), np = K + 1, U = K - 1;
   const double dt2 = dt * dt;
   eval_ws ew;
@@ -1094,8 +1097,9 @@ static double hoc_eval_model(const orc_model* m, int i, int K, const double* w, 
     free(gfull);
     for (int j = 0; j < nd; ++j) E += r[j] * r[j];
   }
-  if (grad) {
-    memset(grad, 0, (size_t)U * nd * sizeof(double));
+  if (res_out) memcpy(res_out, h->res, (size_t)U * nd * sizeof(double));
+  if (grad || jac_out) {
+    if (grad) memset(grad, 0, (size_t)U * nd * sizeof(double));
     double WW[16], d2A[16], dA[16], dAM[16], dAo[16], M[16];
     for (int u = 0; u < U; ++u) {
       const double* Tu = h->T + (size_t)(2 + u) * nd * 16;
@@ -1137,11 +1141,16 @@ static double hoc_eval_model(const orc_model* m, int i, int K, const double* w, 
             }
             h->blk[(size_t)b * nd + c] = v;
           }
-        for (int c = 0; c < nd; ++c) {
-          double s = 0.0;
-          for (int b = 0; b < nd; ++b) s += h->blk[(size_t)b * nd + c] * r[b];
-          grad[(size_t)a * nd + c] += 2.0 * s;
-        }
+        if (jac_out)
+          for (int b = 0; b < nd; ++b)
+            memcpy(jac_out + ((size_t)u * nd + b) * U * nd + (size_t)a * nd, h->blk + (size_t)b * nd,
+                   (size_t)nd * sizeof(double));
+        if (grad)
+          for (int c = 0; c < nd; ++c) {
+            double s = 0.0;
+            for (int b = 0; b < nd; ++b) s += h->blk[(size_t)b * nd + c] * r[b];
+            grad[(size_t)a * nd + c] += 2.0 * s;
+          }
       }
     }
   }
@@ -1165,13 +1174,48 @@ void orc_eqhoc_objective_grad(const orc_model* m, int K, double dt, const double
     hoc_ws h;
     hoc_alloc(&h, K, nd);
     double* g = grad ? (double*)malloc((size_t)U * (nd > 0 ? nd : 1) * sizeof(double)) : NULL;
-    E[i] = hoc_eval_model(m, i, K, w, dt, pts, tau, &h, g);
+    E[i] = hoc_eval_model(m, i, K, w, dt, pts, tau, &h, g, NULL, NULL);
     if (grad)
       for (int u = 0; u < U; ++u)
         for (int j = 0; j < nd; ++j) grad[(size_t)u * n + d0 + j] = g[(size_t)u * nd + j];
     free(g);
     hoc_free(&h);
   }
+}
+
+/* Residuals dt^2 r_u of Eq. HOC at the K-1 unknown configurations ([K-1][n_dofs],
+ * global DOF order) and, if J is not NULL, their Jacobian with respect to the
+ * unknowns: one dense row-major block of ((K-1) nd)^2 doubles per model, packed
+ * model after model, row (u, b) and column (a, c) in unknown-major order. */
+void orc_eqhoc_residual_jacobian(const orc_model* m, int K, double dt, const double* q_known,
+                                 const double* q_unknown, const double* tau, double* R, double* J,
+                                 int n_threads) {
+  double tauv[ORC_KMAX + 1], w[(ORC_KMAX - 1) * (ORC_KMAX + 1)];
+  orc_collocation(K, tauv, w);
+  const int n = m->n_dofs, U = K - 1;
+  size_t* joff = (size_t*)malloc(((size_t)m->n_models + 1) * sizeof(size_t));
+  joff[0] = 0;
+  for (int i = 0; i < m->n_models; ++i) {
+    size_t N = (size_t)U * model_nd(m, i);
+    joff[i + 1] = joff[i] + N * N;
+  }
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+  for (int i = 0; i < m->n_models; ++i) {
+    int nd = model_nd(m, i), d0 = m->model_dof[i];
+    const double* pts[ORC_KMAX + 1];
+    pts[0] = q_known;
+    pts[1] = q_known + n;
+    for (int u = 0; u < U; ++u) pts[2 + u] = q_unknown + (size_t)u * n;
+    hoc_ws h;
+    hoc_alloc(&h, K, nd);
+    double* r = (double*)malloc((size_t)U * (nd > 0 ? nd : 1) * sizeof(double));
+    hoc_eval_model(m, i, K, w, dt, pts, tau, &h, NULL, r, J ? J + joff[i] : NULL);
+    for (int u = 0; u < U; ++u)
+      for (int j = 0; j < nd; ++j) R[(size_t)u * n + d0 + j] = r[(size_t)u * nd + j];
+    free(r);
+    hoc_free(&h);
+  }
+  free(joff);
 }
 
 /* Dense inverse of a small matrix by Gauss-Jordan with partial pivoting; 0 on success. */
@@ -1259,7 +1303,7 @@ static void step_model_hoc(const orc_model* m, int i, const orc_opts* o, const d
   do {                                                                              \
     for (int u_ = 0; u_ < U; ++u_)                                                  \
       for (int j_ = 0; j_ < nd; ++j_) qunk_full[(size_t)u_ * n + d0 + j_] = (X)[u_ * nd + j_]; \
-    EOUT = hoc_eval_model(m, i, K, w, o->dt, pts, tau, &h, GRAD);                   \
+    EOUT = hoc_eval_model(m, i, K, w, o->dt, pts, tau, &h, GRAD, NULL, NULL);       \
   } while (0)
   double E;
   HOC_EVAL(q, g, E);
@@ -1389,6 +1433,208 @@ done:
   free(L);
   free(buf);
   hoc_free(&h);
+}
+
+/* One Eq. EQHOC step of model i by Levenberg-Marquardt (Sec. 5 "Optimization
+ * Algorithm"): each iteration forms the residuals r = (dt^2 r_u) and their
+ * Jacobian J (written out, hoc_eval_model), and solves
+ *     (J^T J + lambda I) v = -J^T r              (the paper's update; dense Cholesky)
+ * E = |r|^2, dE/dq = 2 J^T r.  lambda starts at lambda0 * max diag(J^T J) and is
+ * adapted by the gain ratio rho = (E - E(q+s)) / (E - |r + J s|^2) of the step s
+ * (Nielsen's rule: accepted steps scale lambda by max(1/3, 1 - (2 rho - 1)^3),
+ * rejected ones by nu, nu doubling while steps are rejected).  A step is
+ * accepted when it decreases E.  With `geodesic`, the step adds half the
+ * geodesic acceleration of Transtrum & Sethna's LM variant: with the second
+ * directional derivative of the residuals along v from a finite difference of
+ * step h, r_vv = (2/h) ((r(q + h v) - r)/h - J v), a = (J^T J + lambda I)^-1
+ * (-J^T r_vv) and s = v + a/2; a step whose acceleration is large against its
+ * velocity (2|a| > alpha |v|) is rejected like one that increases E.
+ * lambda is kept at least 1e-15 max diag(J^T J) so that the Cholesky factor
+ * exists.  Stop when |dE/dq| <= tol |dE/dq at the warm start| (flag 1), when an
+ * accepted point equals the iterate or lambda overflows (flag 2), or after
+ * max_iter iterations, accepted or not (flag 4).  Warm start as orc_step_hoc. */
+static void step_model_lm(const orc_model* m, int i, const orc_lm_opts* o, const double* qprev,
+                          const double* qk, const double* tau, double* qunk_full, double* q_out,
+                          orc_stats* st) {
+  const int K = o->order_K, U = K - 1, n = m->n_dofs;
+  const int d0 = m->model_dof[i], nd = model_nd(m, i), N = U * nd;
+  orc_stats s = {0, 0, 0, 0, 0.0, 0.0};
+  if (nd == 0) {
+    s.flag = 1;
+    *st = s;
+    return;
+  }
+  double tauv[ORC_KMAX + 1], w[(ORC_KMAX - 1) * (ORC_KMAX + 1)];
+  orc_collocation(K, tauv, w);
+  hoc_ws h;
+  hoc_alloc(&h, K, nd);
+  const double* pts[ORC_KMAX + 1];
+  pts[0] = qprev;
+  pts[1] = qk;
+  for (int u = 0; u < U; ++u) pts[2 + u] = qunk_full + (size_t)u * n;
+  double* buf = (double*)calloc((size_t)N * 11, sizeof(double));
+  double *q = buf, *r = q + N, *g = r + N, *v = g + N, *a = v + N, *qt = a + N, *rt = qt + N, *Jv = rt + N,
+         *rvv = Jv + N, *sv = rvv + N, *tmp = sv + N;
+  double* J = (double*)malloc((size_t)N * N * sizeof(double));
+  double* JTJ = (double*)malloc((size_t)N * N * sizeof(double));
+  double* L = (double*)malloc((size_t)N * N * sizeof(double));
+#define LM_RES(X, ROUT, JOUT, EOUT)                                                 \
+  do {                                                                              \
+    for (int u_ = 0; u_ < U; ++u_)                                                  \
+      for (int j_ = 0; j_ < nd; ++j_) qunk_full[(size_t)u_ * n + d0 + j_] = (X)[u_ * nd + j_]; \
+    EOUT = hoc_eval_model(m, i, K, w, o->dt, pts, tau, &h, NULL, ROUT, JOUT);       \
+    ++s.evaluations;                                                                \
+  } while (0)
+  const double vscale = 1.0 / (tauv[1] - tauv[0]);
+  for (int u = 0; u < U; ++u)
+    for (int j = 0; j < nd; ++j) q[u * nd + j] = qk[d0 + j] + tauv[2 + u] * vscale * (qk[d0 + j] - qprev[d0 + j]);
+  double E;
+  LM_RES(q, r, J, E);
+  /* g = J^T r */
+  for (int c = 0; c < N; ++c) {
+    double t = 0.0;
+    for (int k = 0; k < N; ++k) t += J[(size_t)k * N + c] * r[k];
+    g[c] = t;
+  }
+  if (!isfinite(E) || !finitev(g, N)) {
+    s.flag = 8;
+    s.energy = E;
+    s.grad_norm = NAN;
+    goto out;
+  }
+  const double g0 = 2.0 * sqrt(dotv(g, g, N));
+  double gn = g0, lambda = -1.0, nu = 2.0;
+  if (g0 == 0.0) {
+    s.flag = 1;
+    goto fin;
+  }
+  for (int it = 0; it < o->max_iter; ++it) {
+    s.iterations++;
+    double dmax = 0.0;
+    for (int x = 0; x < N; ++x)
+      for (int y = 0; y <= x; ++y) {
+        double t = 0.0;
+        for (int k = 0; k < N; ++k) t += J[(size_t)k * N + x] * J[(size_t)k * N + y];
+        JTJ[(size_t)x * N + y] = t;
+        JTJ[(size_t)y * N + x] = t;
+      }
+    for (int x = 0; x < N; ++x) dmax = fmax(dmax, JTJ[(size_t)x * N + x]);
+    if (lambda < 0.0) lambda = o->lambda0 * dmax;
+    if (lambda < 1e-15 * dmax) lambda = 1e-15 * dmax;
+    if (!(lambda <= 1e300)) {
+      s.flag = 2;
+      break;
+    }
+    memcpy(L, JTJ, (size_t)N * N * sizeof(double));
+    for (int x = 0; x < N; ++x) L[(size_t)x * N + x] += lambda;
+    if (cholesky(L, N) != 0) {
+      lambda *= nu;
+      nu *= 2.0;
+      continue;
+    }
+    for (int x = 0; x < N; ++x) v[x] = -g[x];
+    chol_solve(L, N, v);
+    /* J v */
+    for (int k = 0; k < N; ++k) {
+      double t = 0.0;
+      for (int c = 0; c < N; ++c) t += J[(size_t)k * N + c] * v[c];
+      Jv[k] = t;
+    }
+    memcpy(sv, v, (size_t)N * sizeof(double));
+    if (o->geodesic) {
+      const double hh = o->geo_h;
+      double Eh;
+      for (int x = 0; x < N; ++x) qt[x] = q[x] + hh * v[x];
+      LM_RES(qt, rt, NULL, Eh);
+      (void)Eh;
+      for (int k = 0; k < N; ++k) rvv[k] = (2.0 / hh) * ((rt[k] - r[k]) / hh - Jv[k]);
+      for (int c = 0; c < N; ++c) {
+        double t = 0.0;
+        for (int k = 0; k < N; ++k) t += J[(size_t)k * N + c] * rvv[k];
+        a[c] = -t;
+      }
+      chol_solve(L, N, a);
+      const double na = sqrt(dotv(a, a, N)), nv = sqrt(dotv(v, v, N));
+      if (!(2.0 * na <= o->geo_alpha * nv)) {
+        lambda *= nu;
+        nu *= 2.0;
+        continue;
+      }
+      for (int x = 0; x < N; ++x) sv[x] = v[x] + 0.5 * a[x];
+    }
+    /* predicted objective |r + J s|^2 */
+    double pred = 0.0;
+    for (int k = 0; k < N; ++k) {
+      double t = r[k];
+      for (int c = 0; c < N; ++c) t += J[(size_t)k * N + c] * sv[c];
+      pred += t * t;
+    }
+    for (int x = 0; x < N; ++x) qt[x] = q[x] + sv[x];
+    double Et;
+    LM_RES(qt, rt, NULL, Et);
+    if (!(isfinite(Et) && Et < E)) {
+      lambda *= nu;
+      nu *= 2.0;
+      continue;
+    }
+    int moved = 0;
+    for (int x = 0; x < N; ++x) moved |= qt[x] != q[x];
+    if (!moved) {
+      s.flag = 2;
+      break;
+    }
+    double rho = (E - Et) / fmax(E - pred, 1e-300);
+    if (rho > 1.0) rho = 1.0;
+    const double c3 = 2.0 * rho - 1.0;
+    lambda *= fmax(1.0 / 3.0, 1.0 - c3 * c3 * c3);
+    nu = 2.0;
+    memcpy(q, qt, (size_t)N * sizeof(double));
+    LM_RES(q, r, J, E);
+    for (int c = 0; c < N; ++c) {
+      double t = 0.0;
+      for (int k = 0; k < N; ++k) t += J[(size_t)k * N + c] * r[k];
+      g[c] = t;
+    }
+    gn = 2.0 * sqrt(dotv(g, g, N));
+    if (gn <= o->tol * g0) {
+      s.flag = 1;
+      break;
+    }
+  }
+  if (s.flag == 0) s.flag = 4;
+fin:
+  s.grad_norm = gn;
+  s.energy = E;
+out:
+  for (int u = 0; u < U; ++u)
+    for (int j = 0; j < nd; ++j) q_out[(size_t)u * n + d0 + j] = q[u * nd + j];
+  *st = s;
+#undef LM_RES
+  (void)tmp;
+  free(J);
+  free(JTJ);
+  free(L);
+  free(buf);
+  hoc_free(&h);
+}
+
+int orc_step_lm_hoc(const orc_model* m, const orc_lm_opts* o, const double* q_known, const double* tau,
+                    double* q_out, orc_stats* stats, int n_threads) {
+  if (o->order_K < 2 || o->order_K > ORC_KMAX) return -1;
+  const int n = m->n_dofs > 0 ? m->n_dofs : 1, U = o->order_K - 1;
+  int nt = n_threads > 0 ? n_threads : 1;
+  double* scratch = (double*)malloc((size_t)nt * U * n * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  for (int i = 0; i < m->n_models; ++i) {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    double* qunk = scratch + (size_t)tid * U * n;
+    step_model_lm(m, i, o, q_known, q_known + m->n_dofs, tau, qunk, q_out, stats + i);
+  }
+  free(scratch);
+  return 0;
 }
 
 int orc_step_hoc(const orc_model* m, const orc_opts* o, const double* q_known, const double* tau,

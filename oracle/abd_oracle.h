@@ -37,6 +37,18 @@ typedef struct {
                       current iterate and drop the curvature pairs (0 = never) */
 } orc_opts;
 
+/* Levenberg-Marquardt options (order K >= 2 collocation, Eq. EQHOC). */
+typedef struct {
+  double dt;
+  int order_K;
+  int max_iter;      /* iterations, accepted or rejected */
+  double tol;        /* stop when |dE/dq| <= tol * |dE/dq at the warm start| */
+  double lambda0;    /* initial lambda relative to max diag(J^T J) */
+  int geodesic;      /* 1: add half the geodesic acceleration (Transtrum & Sethna) */
+  double geo_h;      /* finite-difference step of the second directional derivative */
+  double geo_alpha;  /* reject steps with 2|a| > geo_alpha |v| */
+} orc_lm_opts;
+
 typedef struct {
   int iterations;
   int evaluations;
@@ -103,6 +115,13 @@ void orc_eqhoc_objective_grad(const orc_model* m, int K, double dt, const double
                               const double* q_unknown, const double* tau, double* E, double* grad,
                               int n_threads);
 
+/* Residuals dt^2 r_u of Eq. HOC ([K-1][n_dofs]) at the unknown configurations
+ * and, if J is not NULL, their Jacobian: per model one dense row-major block of
+ * ((K-1) nd)^2 doubles (row (u, b), column (a, c)), packed model after model. */
+void orc_eqhoc_residual_jacobian(const orc_model* m, int K, double dt, const double* q_known,
+                                 const double* q_unknown, const double* tau, double* R, double* J,
+                                 int n_threads);
+
 /* One time step for every model: q_out = argmin of the step objective,
  * reached by preconditioned L-BFGS from the warm start 2 q_k - q_{k-1}. */
 int orc_step(const orc_model* m, const orc_opts* o, const double* q_hist, const double* tau,
@@ -113,6 +132,15 @@ int orc_step(const orc_model* m, const orc_opts* o, const double* q_hist, const 
  * the last one is q_{k+1}).  Returns 0, or -1 for an order out of range. */
 int orc_step_hoc(const orc_model* m, const orc_opts* o, const double* q_known, const double* tau,
                  double* q_out, orc_stats* stats, int n_threads);
+
+/* One Eq. EQHOC step (order_K = 2..8) for every model by Levenberg-Marquardt
+ * (Sec. 5): (J^T J + lambda I) v = -J^T r with the written-out Jacobian of the
+ * residuals and a dense Cholesky solve, Nielsen's lambda rule, optional
+ * geodesic acceleration.  Arguments as orc_step_hoc; stats count LM iterations
+ * (accepted or rejected) and residual evaluations.  Returns 0, or -1 for an
+ * order out of range. */
+int orc_step_lm_hoc(const orc_model* m, const orc_lm_opts* o, const double* q_known, const double* tau,
+                    double* q_out, orc_stats* stats, int n_threads);
 
 /* Reported total energy at step k: (1/2dt^2) sum tr(dA M dA^T) + V(q_k),
  * dA = A(q_k) - A(q_{k-1}). */

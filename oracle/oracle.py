@@ -37,6 +37,12 @@ class OrcOpts(C.Structure):
                 ("eps_w", C.c_double), ("precond", C.c_int), ("refresh", C.c_int)]
 
 
+class OrcLmOpts(C.Structure):
+    _fields_ = [("dt", C.c_double), ("order_K", C.c_int), ("max_iter", C.c_int), ("tol", C.c_double),
+                ("lambda0", C.c_double), ("geodesic", C.c_int), ("geo_h", C.c_double),
+                ("geo_alpha", C.c_double)]
+
+
 class OrcStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("evaluations", C.c_int), ("flag", C.c_int),
                 ("pad", C.c_int), ("grad_norm", C.c_double), ("energy", C.c_double)]
@@ -77,8 +83,12 @@ def lib():
         _lib.orc_collocation.argtypes = [C.c_int, dp, dp]
         _lib.orc_collocation.restype = C.c_int
         _lib.orc_eqhoc_objective_grad.argtypes = [C.c_void_p, C.c_int, C.c_double, dp, dp, dp, dp, dp, C.c_int]
+        _lib.orc_eqhoc_residual_jacobian.argtypes = [C.c_void_p, C.c_int, C.c_double, dp, dp, dp, dp, dp,
+                                                     C.c_int]
         _lib.orc_step_hoc.argtypes = [C.c_void_p, C.POINTER(OrcOpts), dp, dp, dp, C.c_void_p, C.c_int]
         _lib.orc_step_hoc.restype = C.c_int
+        _lib.orc_step_lm_hoc.argtypes = [C.c_void_p, C.POINTER(OrcLmOpts), dp, dp, dp, C.c_void_p, C.c_int]
+        _lib.orc_step_lm_hoc.restype = C.c_int
         _lib.orc_cross_hessian.argtypes = [C.c_void_p, dp, dp, C.c_double, dp, C.c_int]
         _lib.orc_step.argtypes = [C.c_void_p, C.POINTER(OrcOpts), dp, dp, dp, C.c_void_p, C.c_int]
         _lib.orc_step.restype = C.c_int
@@ -245,6 +255,28 @@ class Oracle:
         lib().orc_eqhoc_objective_grad(self._h, K, dt, _d(known), _d(unk), _d(tau), _d(E), _d(g), self.threads)
         return E, g.reshape(K - 1, self.n_dofs)
 
+    def eqhoc_residual_jacobian(self, K, dt, q_prev, q_curr, q_unknown, tau=None, jacobian=True):
+        """Residuals dt^2 r_u of Eq. HOC ([K-1, n]) at the unknown points and, with
+        jacobian, the list of dense per-model Jacobians ([(K-1) nd]^2, unknown-major)."""
+        U = K - 1
+        R = np.zeros(U * self.n_dofs)
+        known = _f64(np.concatenate([q_prev, q_curr]))
+        unk = _f64(np.asarray(q_unknown).reshape(-1))
+        tau = None if tau is None else _f64(tau)
+        nd = np.diff(self.desc.dof_offset).astype(np.int64)
+        J = np.zeros(max(1, int(np.sum((U * nd) ** 2)))) if jacobian else None
+        lib().orc_eqhoc_residual_jacobian(self._h, K, dt, _d(known), _d(unk), _d(tau), _d(R), _d(J),
+                                          self.threads)
+        R = R.reshape(U, self.n_dofs)
+        if not jacobian:
+            return R, None
+        out, o = [], 0
+        for n in nd:
+            N = int(U * n)
+            out.append(J[o:o + N * N].reshape(N, N))
+            o += N * N
+        return R, out
+
     def step_hoc(self, K, q_prev, q_curr, dt, tau=None, lbfgs_m=5, tol=1e-8, max_iter=500, max_ls=40,
                  eps_w=EPS64, precond=2):
         """One Eq. EQHOC step: returns the K-1 unknown configurations [K-1, n] and stats.
@@ -259,6 +291,34 @@ class Oracle:
         if rc != 0:
             raise ValueError(f"orc_step_hoc failed ({rc})")
         return out.reshape(K - 1, self.n_dofs), stats
+
+    def step_lm(self, K, q_prev, q_curr, dt, tau=None, tol=1e-8, max_iter=300, lambda0=1e-3, geodesic=True,
+                geo_h=0.1, geo_alpha=0.75):
+        """One Eq. EQHOC step (order K >= 2) by Levenberg-Marquardt (orc_step_lm_hoc):
+        returns the K-1 unknown configurations [K-1, n] and stats (iterations =
+        LM iterations, accepted or rejected; evaluations = residual evaluations)."""
+        opts = OrcLmOpts(dt, K, max_iter, tol, lambda0, 1 if geodesic else 0, geo_h, geo_alpha)
+        known = _f64(np.concatenate([q_prev, q_curr]))
+        out = np.zeros((K - 1) * self.n_dofs)
+        stats = np.zeros(self.n_models, dtype=STATS_DTYPE)
+        tau = None if tau is None else _f64(tau)
+        rc = lib().orc_step_lm_hoc(self._h, C.byref(opts), _d(known), _d(tau), _d(out),
+                                   stats.ctypes.data_as(C.c_void_p), self.threads)
+        if rc != 0:
+            raise ValueError(f"orc_step_lm_hoc failed ({rc})")
+        return out.reshape(K - 1, self.n_dofs), stats
+
+    def rollout_lm(self, K, q_prev, q0, steps, dt, **kw):
+        """Order-K rollout by Levenberg-Marquardt steps: q_0..q_steps and the stats."""
+        qs = [np.array(q0, dtype=np.float64)]
+        prev = np.array(q_prev, dtype=np.float64)
+        stats = []
+        for _ in range(steps):
+            pts, st = self.step_lm(K, prev, qs[-1], dt, **kw)
+            prev = pts[K - 3] if K >= 3 else qs[-1]
+            qs.append(pts[K - 2].copy())
+            stats.append(st)
+        return np.stack(qs), stats
 
     def rollout_hoc(self, K, q_prev, q0, steps, dt, **kw):
         """Order-K rollout from the known points (q_{-1+alpha_{K-2}}, q_0): returns
