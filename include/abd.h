@@ -177,6 +177,26 @@ int abd_rollout(abd_model* model, const abd_step_opts* opts, const double* q_ini
                 const double* tau, double* q_traj, abd_step_stats* stats, int n_steps,
                 void* stream);
 
+/* abd_rollout for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as abd_rollout, but every buffer the kernels write
+ * besides the caller's inputs and outputs (per-frame step constants, L-BFGS
+ * rings of models of more than 64 DOFs, preconditioner work space, order-K
+ * known-point seeds) lives in one fixed 64 MiB device array per GPU, held
+ * until the process ends; the call never allocates (abd_rollout allocates the
+ * order-K buffers on a model's first order-K call).  The array is cleared as
+ * needed by a kernel enqueued on `stream`.
+ *   Arguments and results as abd_rollout.  A model whose step scratch exceeds
+ *   64 MiB (about 144 bytes per DOF for serial chains of <= 64 DOFs, more for
+ *   longer or branched models and for order K > 2) is rejected with
+ *   ABD_ENOTSUP before anything is enqueued.
+ *   All calls on one GPU share its array: calls that overlap on one device
+ *   (different streams, or different host threads) race and give undefined
+ *   results; order them on one stream. */
+int abd_rollout_noalloc(abd_model* model, const abd_step_opts* opts, const double* q_init,
+                        const double* tau, double* q_traj, abd_step_stats* stats, int n_steps,
+                        void* stream);
+
 /* Objective and gradient without optimization (Eq. EQ scaled by dt^2; gradient by
  * the adjoint backward pass of Alg. 1).
  *   q        : [n_dofs] configuration to evaluate

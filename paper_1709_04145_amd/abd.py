@@ -61,6 +61,8 @@ _PROTOS = {
                            C.c_void_p, C.c_void_p]),
     "abd_rollout": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_int, C.c_void_p]),
+    "abd_rollout_noalloc": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_int, C.c_void_p]),
     "abd_objective_grad": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "abd_hvp": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
@@ -276,6 +278,22 @@ class Model:
         _check(load().abd_rollout(self._h, C.byref(o), _ptr(q_init), _ptr(torque), _ptr(q_traj), _ptr(stats),
                                   int(steps), _stream(stream)))
         return q_traj[:steps], stats
+
+    def rollout_noalloc(self, q_init: torch.Tensor, steps: int, opts: StepOptions, q_traj: torch.Tensor,
+                        stats: torch.Tensor, torque=None, stream=None):
+        """abd_rollout_noalloc: as rollout, with caller-provided outputs (q_traj, stats)
+        and the step scratch in the library's fixed device array (no allocation)."""
+        n = self.n_dofs
+        _dev_f64(q_init, 2 * n, "q_init")
+        _dev_f64(q_traj, max(1, steps) * (opts.order_K - 1) * n, "q_traj")
+        if torque is not None:
+            _dev_f64(torque, steps * n, "torque")
+        if stats is None or stats.numel() * stats.element_size() < STATS_BYTES * self.n_models * steps:
+            raise ValueError(f"stats must hold {STATS_BYTES} bytes per model and step")
+        o = opts.c()
+        _check(load().abd_rollout_noalloc(self._h, C.byref(o), _ptr(q_init), _ptr(torque), _ptr(q_traj),
+                                          _ptr(stats), int(steps), _stream(stream)))
+        return q_traj, stats
 
     def new_rollout_stats(self, steps: int) -> torch.Tensor:
         return torch.zeros((max(1, steps * self.n_models), STATS_BYTES // 8), dtype=torch.float64, device="cuda")

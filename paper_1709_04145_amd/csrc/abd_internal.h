@@ -28,6 +28,7 @@ struct abd_model {
   double* hist = nullptr;
   double* Bk = nullptr;  // known seed parts of order-K steps, allocated on first use
   double* hist3 = nullptr;  // order-K pairs of models of more than 64 DOFs, on first use
+  long long hinv_len = 0;  // doubles of preconditioner scratch (hinv) the model needs
   int* uidx = nullptr;
   int* fpar = nullptr;
   int* fend = nullptr;
@@ -42,11 +43,25 @@ int fail(int code, const std::string& msg);
 // Device allocation owned by the model (freed with it); ABD_ENOMEM on failure.
 int model_alloc(abd_model* m, void** dst, size_t bytes);
 
+// Where the kernels of a step or rollout keep the buffers they write besides their
+// inputs and outputs.  Without one (nullptr) they use the model's own buffers, the
+// order-K ones allocated on first use.
+struct StepScratch {
+  double* B64;    // [n_dofs][12]
+  float* B32;     // [n_dofs][12]
+  double* hist;   // models of more than 64 frames: [n_dofs][2*kMaxHist]
+  double* hinv;   // [hinv_len]
+  double* Bk;     // order K > 2: [n_dofs][3][12]
+  double* hist3;  // order K > 2, models of more than 64 frames: [n_dofs][2][kMaxHist][3]
+};
+
 // Kernel launches (stream-ordered; arguments already validated by the caller).
 int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
-                   const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream);
+                   const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream,
+                   const StepScratch* sc = nullptr);
 int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
-               const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream);
+               const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream,
+               const StepScratch* sc = nullptr);
 int launch_hoc_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,
                          const double* tau, double* E, double* grad, double* grad_tau, void* stream);
 int launch_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,

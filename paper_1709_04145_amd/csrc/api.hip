@@ -3,6 +3,7 @@
 #include "abd_device.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace abd_impl {
 
@@ -119,6 +120,54 @@ int check_opts(const abd_step_opts* o, bool for_step) {
     return fail(ABD_EINVAL, "schedule must be ABD_SCHEDULE_AUTO or ABD_SCHEDULE_WAVE");
   if (o->solver != ABD_SOLVER_LBFGS) return fail(ABD_EINVAL, "solver must be ABD_SOLVER_LBFGS");
   return ABD_OK;
+}
+
+int check_rollout_args(const abd_model* m, const abd_step_opts* o, const double* q_init, const double* q_traj,
+                       int n_steps) {
+  int rc = check_opts(o, true);  // options first: they are checked without a device
+  if (rc) return rc;
+  if (!m) return fail(ABD_EINVAL, "model is NULL");
+  if (n_steps < 0) return fail(ABD_EINVAL, "n_steps must be >= 0");
+  if (m->n_models == 0 || n_steps == 0) return ABD_OK;
+  if (!q_init || !q_traj) return fail(ABD_EINVAL, "q_init and q_traj must not be NULL");
+  const size_t nd = m->n_dofs;
+  if (q_traj < q_init + 2 * nd && q_init < q_traj + (size_t)n_steps * (o->order_K - 1) * nd)
+    return fail(ABD_EINVAL, "q_traj overlaps q_init");
+  return check_device(m);
+}
+
+// Step scratch of abd_rollout_noalloc: one fixed array per device, held until the
+// process ends.  Host code never uses the array's name as an address: the device
+// address comes from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device).
+int scratch_base(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(ABD_ENOTSUP, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(ABD_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return ABD_OK;
+}
+
+// Zero the first n doubles of the scratch (a kernel, so that the clear is an
+// ordinary node when a caller captures the stream in a graph).
+__global__ void k_zero_scratch(double* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
 }
 
 }  // namespace
@@ -266,6 +315,7 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   m->max_frames = max_frames;
   m->tree = !chain;
   m->jump_rounds = jump_rounds;
+  m->hinv_len = hoff[nm];
   for (int k = 0; k < 3; ++k) m->g[k] = desc->gravity[k];
   std::vector<float> fr32(fr64.begin(), fr64.end());
   int rc = ABD_OK;
@@ -329,18 +379,55 @@ int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const d
 int abd_rollout(abd_model* m, const abd_step_opts* o, const double* q_init, const double* tau, double* q_traj,
                 abd_step_stats* stats, int n_steps, void* stream) {
   g_err.clear();
-  int rc = check_opts(o, true);  // options first: they are checked without a device
-  if (rc) return rc;
-  if (!m) return fail(ABD_EINVAL, "model is NULL");
-  if (n_steps < 0) return fail(ABD_EINVAL, "n_steps must be >= 0");
-  if (m->n_models == 0 || n_steps == 0) return ABD_OK;
-  if (!q_init || !q_traj) return fail(ABD_EINVAL, "q_init and q_traj must not be NULL");
+  int rc = check_rollout_args(m, o, q_init, q_traj, n_steps);
+  if (rc || m->n_models == 0 || n_steps == 0) return rc;
   const size_t nd = m->n_dofs;
-  if (q_traj < q_init + 2 * nd && q_init < q_traj + (size_t)n_steps * (o->order_K - 1) * nd)
-    return fail(ABD_EINVAL, "q_traj overlaps q_init");
-  if ((rc = check_device(m))) return rc;
   if (o->order_K > 2) return abd_impl::launch_hoc(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
   return abd_impl::launch_rollout(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
+}
+
+int abd_rollout_noalloc(abd_model* m, const abd_step_opts* o, const double* q_init, const double* tau,
+                        double* q_traj, abd_step_stats* stats, int n_steps, void* stream) {
+  g_err.clear();
+  int rc = check_rollout_args(m, o, q_init, q_traj, n_steps);
+  if (rc || m->n_models == 0 || n_steps == 0) return rc;
+  if (o->order_K > 2 && (rc = abd_impl::check_hoc(m, o))) return rc;
+  // carve the step scratch out of this device's static array
+  unsigned char* base = nullptr;
+  if ((rc = scratch_base(m->device, &base))) return rc;
+  const size_t nd = m->n_dofs;
+  const bool ring = m->max_frames > kMaxFrames;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base + off;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  };
+  abd_impl::StepScratch sc;
+  sc.B64 = reinterpret_cast<double*>(take(12 * nd * sizeof(double)));
+  sc.B32 = reinterpret_cast<float*>(take(12 * nd * sizeof(float)));
+  const size_t cleared = off;  // the per-frame constants start finite (zero)
+  sc.hist = reinterpret_cast<double*>(take((ring ? 2 * kMaxHist * nd : 1) * sizeof(double)));
+  sc.hinv = reinterpret_cast<double*>(take(std::max<long long>(1, m->hinv_len) * sizeof(double)));
+  sc.Bk = nullptr;
+  sc.hist3 = nullptr;
+  if (o->order_K > 2) {
+    sc.Bk = reinterpret_cast<double*>(take(36 * nd * sizeof(double)));
+    if (ring) sc.hist3 = reinterpret_cast<double*>(take(2 * kMaxHist * 3 * nd * sizeof(double)));
+  }
+  if (off > kScratchBytes)
+    return fail(ABD_ENOTSUP, "abd_rollout_noalloc: this model needs " + std::to_string(off) +
+                                 " bytes of step scratch; the static buffer holds " +
+                                 std::to_string(kScratchBytes) + " (use abd_rollout)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t words = cleared / sizeof(double);
+  const int blocks = (int)std::min<size_t>(1024, (words + 255) / 256);
+  hipLaunchKernelGGL(k_zero_scratch, dim3(std::max(1, blocks)), dim3(256), 0, s,
+                     reinterpret_cast<double*>(base), words);
+  HIP_TRY(hipGetLastError());
+  if (o->order_K > 2)
+    return abd_impl::launch_hoc(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream, &sc);
+  return abd_impl::launch_rollout(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream, &sc);
 }
 
 int abd_objective_grad(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,

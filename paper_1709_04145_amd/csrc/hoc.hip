@@ -564,11 +564,17 @@ static void hoc_collocation(int K, double* tau, double* w) {
 }
 
 template <int U>
-static int fill_hoc_args(abd_model* m, const abd_step_opts* o, HocArgs<U>& a) {
+static int fill_hoc_args(abd_model* m, const abd_step_opts* o, HocArgs<U>& a, const StepScratch* sc = nullptr) {
   const int K = U + 1, np = K + 1;
   double tau[5], w[3 * 5];
   hoc_collocation(K, tau, w);
   a.d = dev_view(m);
+  if (sc) {
+    a.d.B64 = sc->B64;
+    a.d.B32 = sc->B32;
+    a.d.hist = sc->hist;
+    a.d.hinv = sc->hinv;
+  }
   a.dt2 = o->dt * o->dt;
   a.tol = o->tol;
   a.m = o->lbfgs_m;
@@ -604,6 +610,11 @@ static int fill_hoc_args(abd_model* m, const abd_step_opts* o, HocArgs<U>& a) {
   }
   for (int r = 0; r < U; ++r)
     for (int c = 0; c < U; ++c) a.minv[r][c] = g[r][U + c];
+  if (sc) {  // caller-placed scratch: nothing is allocated
+    a.Bk = sc->Bk;
+    a.hist3 = sc->hist3;
+    return ABD_OK;
+  }
   if (!m->Bk) {
     int rc = model_alloc(m, reinterpret_cast<void**>(&m->Bk), 36 * (size_t)m->n_dofs * sizeof(double));
     if (rc) return rc;
@@ -625,7 +636,8 @@ int check_hoc(const abd_model* m, const abd_step_opts* o) {
 }
 
 int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
-                      const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream) {
+               const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream,
+               const StepScratch* sc) {
   int rc = check_hoc(m, o);
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -637,7 +649,7 @@ int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const
 #define ABD_HOC(NW, TREE, UU)                                                                  \
   do {                                                                                         \
     HocArgs<UU> a;                                                                             \
-    if ((rc = fill_hoc_args<UU>(m, o, a))) return rc;                                          \
+    if ((rc = fill_hoc_args<UU>(m, o, a, sc))) return rc;                                      \
     a.n_steps = n_steps; a.q_prev = q_prev; a.q_curr = q_curr; a.tau = tau; a.q_out = q_out;   \
     a.stats = stats;                                                                           \
     hipLaunchKernelGGL((k_rollout_hoc<NW, TREE, UU>), grid, block, pair_bytes, s, a);          \

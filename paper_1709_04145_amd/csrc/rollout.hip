@@ -397,9 +397,16 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
 namespace abd_impl {
 
 int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
-                          const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream) {
+                   const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream,
+                   const StepScratch* sc) {
   StepArgs a;
   a.d = dev_view(m);
+  if (sc) {
+    a.d.B64 = sc->B64;
+    a.d.B32 = sc->B32;
+    a.d.hist = sc->hist;
+    a.d.hinv = sc->hinv;
+  }
   a.dt2 = o->dt * o->dt;
   a.tol = o->tol;
   a.m = o->lbfgs_m;
