@@ -70,36 +70,43 @@ VJP_TOL = 1e-10
 VJP_MAX_ITER = 200
 HOC_CPU_ITERS = 20
 
+# sources the order-2 rollout kernel is built from (the traffic summary is keyed to them)
+ROLLOUT_SOURCES = ("abd_device.h", "abd_internal.h", "rollout.hip")
+
+
 def kernel_source_digest():
-    """sha256 over the library's sources (csrc/*.hip and *.h in name order)."""
-    import glob
+    """sha256 over the order-2 rollout kernel's sources (in ROLLOUT_SOURCES order)."""
     import hashlib
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1709_04145_amd", "csrc", "*"))):
-        if p.endswith((".hip", ".h")):
-            h.update(open(p, "rb").read())
+    for name in ROLLOUT_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1709_04145_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
 
 def measured_traffic(workload, precision, warmup, steps):
     """HBM bytes of the timed launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, if it was taken on this kernel source and this launch; else None."""
-    import hashlib
+    summary: its machine-readable blocks (one per measured launch, separated by
+    blank lines) are searched for one taken on this kernel source, workload,
+    precision and step window; None if there is none."""
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
-    kv = {}
-    for line in text.splitlines():
-        if ": " in line and not line.startswith(("|", "#", " ")):
-            k, v = line.split(": ", 1)
-            kv[k.strip()] = v.strip()
     digest = kernel_source_digest()
     want = {"source_sha256": digest, "workload": workload, "precision": precision,
             "warmup": str(warmup), "steps": str(steps)}
-    if any(kv.get(k) != v for k, v in want.items()) or "traffic_bytes" not in kv:
-        return None
-    return float(kv["traffic_bytes"])
+    blocks, kv = [], {}
+    for line in text.splitlines() + [""]:
+        if ": " in line and not line.startswith(("|", "#", " ")):
+            k, v = line.split(": ", 1)
+            kv[k.strip()] = v.strip()
+        elif not line.strip() and kv:
+            blocks.append(kv)
+            kv = {}
+    for kv in blocks:
+        if all(kv.get(k) == v for k, v in want.items()) and "traffic_bytes" in kv:
+            return float(kv["traffic_bytes"])
+    return None
 
 
 def parse():
@@ -108,6 +115,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--solver", choices=("auto", "lbfgs", "lm"), default="auto",
+                    help="step optimizer: auto = Levenberg-Marquardt for order K > 2 (the sum-of-squares "
+                         "Eq. EQHOC), L-BFGS for order 2")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the teacher-forced parity sample")
@@ -221,7 +231,10 @@ def main():
     model = abd.Model(desc)
     L = desc.n_links
     K = wl.step.order_K
-    base = dict(dt=wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol, max_iter=wl.step.max_iter, order_K=K)
+    solver = {"lbfgs": abd.SOLVER_LBFGS, "lm": abd.SOLVER_LM}.get(args.solver,
+                                                                  abd.SOLVER_LM if K > 2 else abd.SOLVER_LBFGS)
+    base = dict(dt=wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol, max_iter=wl.step.max_iter, order_K=K,
+                solver=solver)
     runs = {}
     for name, prec in (("mixed", abd.MIXED), ("fp64", abd.FP64)):
         if name == "fp64" and args.no_fp64 and K == 2:
@@ -260,7 +273,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": W.CONFIG_NAMES[args.config], "models": desc.n_models, "links": L,
                    "dofs": desc.n_dofs, "dt": wl.step.dt, "order_K": K, "lbfgs_m": wl.step.lbfgs_m,
-                   "tol": wl.step.tol, "precond": "joint-space inertia", "launch": "one rollout per K steps"},
+                   "tol": wl.step.tol,
+                   "solver": "levenberg-marquardt" if solver == abd.SOLVER_LM else "l-bfgs",
+                   "precond": "joint-space inertia" if solver == abd.SOLVER_LBFGS else None,
+                   "launch": "one rollout per K steps"},
         "iterations_per_step": mixed["iters_mean"],
         "iterations_per_step_max": mixed["iters_max"],
         "evaluations_per_step": mixed["evals_mean"],
@@ -271,7 +287,8 @@ def main():
                      "traffic": measured_traffic(W.CONFIG_NAMES[args.config], "mixed" if "mixed" in runs else "fp64",
                                                  args.warmup, args.steps),
                      "kernel": "k_rollout<MIXED>" if "mixed" in runs else ("k_rollout<FP64>" if K == 2 else
-                                                                             "k_rollout_hoc"),
+                                                                             ("k_rollout_lm" if solver == abd.SOLVER_LM
+                                                                              else "k_rollout_hoc")),
                      "kernel_ms": mixed["kernel_ms"],
                      "algorithmic_bytes": mixed["bytes"],
                      "extra_bytes": mixed["extra_bytes"],
@@ -353,7 +370,8 @@ def main():
             print("[bench] parity: oracle solving the teacher-forced step", file=sys.stderr, flush=True)
             out["cpu_baseline"]["parity"] = parity_vs_oracle(abd, desc, wl, tf)
     if not args.no_cpu and K > 2:
-        out["cpu_baseline"] = hoc_cpu_baseline(desc, wl, runs["fp64"], K)
+        out["cpu_baseline"] = (hoc_lm_cpu_baseline(desc, wl, runs["fp64"], K) if solver == abd.SOLVER_LM
+                               else hoc_cpu_baseline(desc, wl, runs["fp64"], K))
     print(json.dumps(out), flush=True)
 
 
@@ -510,6 +528,32 @@ def hoc_cpu_baseline(desc, wl, run, K):
             "sample": f"one step of {nsub} of {desc.n_models} models ({sub.n_links} links) from the timed "
                       f"launch's starting state, at most {HOC_CPU_ITERS} iterations, float64, {el:.1f} s; "
                       f"compare with link_iterations_per_s"}
+
+
+def hoc_lm_cpu_baseline(desc, wl, run, K):
+    """The oracle's Levenberg-Marquardt step (dense written-out Jacobian, Cholesky)
+    on a bounded sample: the first timed step of a few models from the GPU's
+    starting state, and the largest distance of the GPU's result from the
+    oracle's on them (both solved to the workload's tolerance)."""
+    from oracle.oracle import Oracle
+    n = desc.n_dofs
+    threads = max(1, min(16, os.cpu_count() or 1))
+    nsub = min(desc.n_models, threads)
+    sample = np.arange(0, desc.n_models, max(1, desc.n_models // nsub))[:nsub]
+    sub = desc.subset(sample)
+    idx = desc.dof_subset_index(sample)
+    init = run["init"].cpu().numpy()
+    t0 = time.perf_counter()
+    ref, st = Oracle(sub, threads=threads).step_lm(K, init[:n][idx], init[n:][idx], wl.step.dt, tol=wl.step.tol,
+                                                  max_iter=wl.step.max_iter)
+    el = time.perf_counter() - t0
+    got = run["traj"][0].cpu().numpy()[:, idx]
+    return {"value": sub.n_links / el, "unit": "link-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first timed step of {nsub} of {desc.n_models} models ({sub.n_links} links) from the "
+                      f"timed launch's starting state, Levenberg-Marquardt with dense Jacobians, float64, {el:.1f} s",
+            "converged_fraction": float(np.mean(st["flag"] == 1)),
+            "iterations_per_step": float(st["iterations"].mean()),
+            "max_abs_q_diff_vs_gpu": float(np.max(np.abs(got - ref)))}
 
 
 if __name__ == "__main__":

@@ -29,6 +29,9 @@ struct abd_model {
   double* Bk = nullptr;  // known seed parts of order-K steps, allocated on first use
   double* hist3 = nullptr;  // order-K pairs of models of more than 64 DOFs, on first use
   long long hinv_len = 0;  // doubles of preconditioner scratch (hinv) the model needs
+  std::vector<int> f0_host; // [n_models+1] first frame of every model
+  double* lm_mat = nullptr;     // Levenberg-Marquardt matrices per model, on first use
+  long long* lm_off = nullptr;  // [n_models+1] start of every model's matrices
   int* uidx = nullptr;
   int* fpar = nullptr;
   int* fend = nullptr;
@@ -62,6 +65,8 @@ int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, c
 int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
                const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream,
                const StepScratch* sc = nullptr);
+int launch_lm_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
+                  const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream);
 int launch_hoc_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,
                          const double* tau, double* E, double* grad, double* grad_tau, void* stream);
 int launch_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,

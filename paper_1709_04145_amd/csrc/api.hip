@@ -118,7 +118,10 @@ int check_opts(const abd_step_opts* o, bool for_step) {
   if (o->refresh < 0) return fail(ABD_EINVAL, "refresh must be >= 0");
   if (o->schedule != ABD_SCHEDULE_AUTO && o->schedule != ABD_SCHEDULE_WAVE)
     return fail(ABD_EINVAL, "schedule must be ABD_SCHEDULE_AUTO or ABD_SCHEDULE_WAVE");
-  if (o->solver != ABD_SOLVER_LBFGS) return fail(ABD_EINVAL, "solver must be ABD_SOLVER_LBFGS");
+  if (o->solver != ABD_SOLVER_LBFGS && o->solver != ABD_SOLVER_LM)
+    return fail(ABD_EINVAL, "solver must be ABD_SOLVER_LBFGS or ABD_SOLVER_LM");
+  if (o->solver == ABD_SOLVER_LM && o->order_K == 2)
+    return fail(ABD_ENOTSUP, "ABD_SOLVER_LM handles order_K > 2 (Eq. EQHOC) in this build");
   return ABD_OK;
 }
 
@@ -316,6 +319,7 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   m->tree = !chain;
   m->jump_rounds = jump_rounds;
   m->hinv_len = hoff[nm];
+  m->f0_host = f0;
   for (int k = 0; k < 3; ++k) m->g[k] = desc->gravity[k];
   std::vector<float> fr32(fr64.begin(), fr64.end());
   int rc = ABD_OK;
@@ -372,6 +376,8 @@ int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const d
   if (q_out < q_hist + 2 * (size_t)m->n_dofs && q_hist < q_out + out_len)
     return fail(ABD_EINVAL, "q_out overlaps q_hist");
   if ((rc = check_device(m))) return rc;
+  if (o->order_K > 2 && o->solver == ABD_SOLVER_LM)
+    return abd_impl::launch_lm_hoc(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
   if (o->order_K > 2) return abd_impl::launch_hoc(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
   return abd_impl::launch_rollout(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
 }
@@ -382,6 +388,8 @@ int abd_rollout(abd_model* m, const abd_step_opts* o, const double* q_init, cons
   int rc = check_rollout_args(m, o, q_init, q_traj, n_steps);
   if (rc || m->n_models == 0 || n_steps == 0) return rc;
   const size_t nd = m->n_dofs;
+  if (o->order_K > 2 && o->solver == ABD_SOLVER_LM)
+    return abd_impl::launch_lm_hoc(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
   if (o->order_K > 2) return abd_impl::launch_hoc(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
   return abd_impl::launch_rollout(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
 }
@@ -392,6 +400,8 @@ int abd_rollout_noalloc(abd_model* m, const abd_step_opts* o, const double* q_in
   int rc = check_rollout_args(m, o, q_init, q_traj, n_steps);
   if (rc || m->n_models == 0 || n_steps == 0) return rc;
   if (o->order_K > 2 && (rc = abd_impl::check_hoc(m, o))) return rc;
+  if (o->solver == ABD_SOLVER_LM)
+    return fail(ABD_ENOTSUP, "abd_rollout_noalloc: ABD_SOLVER_LM keeps dense per-model matrices (use abd_rollout)");
   // carve the step scratch out of this device's static array
   unsigned char* base = nullptr;
   if ((rc = scratch_base(m->device, &base))) return rc;
