@@ -116,8 +116,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--solver", choices=("auto", "lbfgs", "lm"), default="auto",
-                    help="step optimizer: auto = Levenberg-Marquardt for order K > 2 (the sum-of-squares "
-                         "Eq. EQHOC), L-BFGS for order 2")
+                    help="step optimizer: auto = Levenberg-Marquardt for order K = 3 (the sum-of-squares "
+                         "Eq. EQHOC; the library's LM handles order 3), L-BFGS otherwise")
+    ap.add_argument("--order", type=int, default=0,
+                    help="collocation order K instead of the configuration's (0: the configuration's)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the teacher-forced parity sample")
@@ -230,9 +232,9 @@ def main():
         sys.exit(2)
     model = abd.Model(desc)
     L = desc.n_links
-    K = wl.step.order_K
+    K = args.order if args.order > 0 else wl.step.order_K
     solver = {"lbfgs": abd.SOLVER_LBFGS, "lm": abd.SOLVER_LM}.get(args.solver,
-                                                                  abd.SOLVER_LM if K > 2 else abd.SOLVER_LBFGS)
+                                                                  abd.SOLVER_LM if K == 3 else abd.SOLVER_LBFGS)
     base = dict(dt=wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol, max_iter=wl.step.max_iter, order_K=K,
                 solver=solver)
     runs = {}
