@@ -236,6 +236,22 @@ int abd_objective_grad(abd_model* model, const abd_step_opts* opts, const double
 int abd_hvp(abd_model* model, const abd_step_opts* opts, const double* q, const double* q_hist,
             const double* v, double* Hv, void* stream);
 
+/* Hessian d2E/dq dq of the step objective (Eq. EQ scaled by dt^2) at q, as
+ * explicit dense blocks (float64): the Jacobian of the Alg. 1 gradient, i.e.
+ * the inertial term's Gauss-Newton part sum_l <dA_l/dq_b M_l, dA_l/dq_c> plus
+ * the seed's second-derivative part sum_l <G_l, d2A_l/dq_b dq_c> (the blocks
+ * that Alg. 2/3 of the paper compute), each entry from sums over the links
+ * below the deeper of its two joints, so one workgroup assembles a model's
+ * n_i^2 entries after O(n_i) scans.
+ *   q      : [n_dofs]       q_hist : [2*n_dofs] = q_{k-1} followed by q_k
+ *   H      : [sum_i n_i^2] one row-major n_i x n_i block per model (the model's
+ *            DOFs in the caller's order), model after model
+ * opts->dt is used; the other fields are ignored.  Serial chains of up to 1024
+ * DOFs and branched models of up to 256 DOFs.  Uses the model's per-step scratch
+ * (calls on one model must be ordered on one stream). */
+int abd_hessian(abd_model* model, const abd_step_opts* opts, const double* q, const double* q_hist,
+                double* H, void* stream);
+
 /* Reverse-mode derivative of a rollout (float64).  Every step's result is
  * defined by the stationarity condition of its objective (Eq. PBAD), so by the
  * implicit function theorem, with lambda = dL/dq_{k+1} and H mu = lambda (H the

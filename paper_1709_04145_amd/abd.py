@@ -67,6 +67,8 @@ _PROTOS = {
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "abd_hvp": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
                           C.c_void_p, C.c_void_p]),
+    "abd_hessian": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_void_p]),
     "abd_rollout_vjp": (C.c_int, [C.c_void_p, C.POINTER(StepOptsC), C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "abd_poses": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -228,6 +230,21 @@ class Model:
         o = StepOptions(dt=dt).c()
         _check(load().abd_hvp(self._h, C.byref(o), _ptr(q), _ptr(q_hist), _ptr(v), _ptr(Hv), _stream(stream)))
         return Hv[:self.n_dofs]
+
+    def hessian(self, q, q_hist, dt, stream=None):
+        """Explicit Hessian of the step objective at q (abd_hessian): a list of dense
+        per-model [n_i, n_i] blocks (views of one device buffer)."""
+        _dev_f64(q, self.n_dofs, "q")
+        _dev_f64(q_hist, 2 * self.n_dofs, "q_hist")
+        per = np.diff(np.asarray(self.desc.dof_offset)).astype(np.int64)
+        H = torch.zeros(max(1, int(np.sum(per * per))), dtype=torch.float64, device="cuda")
+        o = StepOptions(dt=dt).c()
+        _check(load().abd_hessian(self._h, C.byref(o), _ptr(q), _ptr(q_hist), _ptr(H), _stream(stream)))
+        out, off = [], 0
+        for nd in per:
+            out.append(H[off:off + nd * nd].view(int(nd), int(nd)))
+            off += int(nd * nd)
+        return out
 
     def rollout_vjp(self, q_init, q_traj, dL_dq_traj, dt, tol=1e-10, max_iter=200, precond=PRECOND_INERTIA,
                     want_tau=True, stats=None, stream=None):

@@ -32,6 +32,7 @@ struct abd_model {
   std::vector<int> f0_host; // [n_models+1] first frame of every model
   double* lm_mat = nullptr;     // Levenberg-Marquardt matrices per model, on first use
   long long* lm_off = nullptr;  // [n_models+1] start of every model's matrices
+  long long* sq_off = nullptr;  // [n_models+1] start of every model's n_i x n_i block, on first use
   int* uidx = nullptr;
   int* fpar = nullptr;
   int* fend = nullptr;
@@ -67,6 +68,8 @@ int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const
                const StepScratch* sc = nullptr);
 int launch_lm_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
                   const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream);
+int launch_hessian(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist, double* H,
+                   void* stream);
 int launch_hoc_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,
                          const double* tau, double* E, double* grad, double* grad_tau, void* stream);
 int launch_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,

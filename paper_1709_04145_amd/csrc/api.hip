@@ -469,6 +469,18 @@ int abd_hvp(abd_model* m, const abd_step_opts* o, const double* q, const double*
   return abd_impl::launch_hvp(m, o, q, q_hist, v, Hv, stream);
 }
 
+int abd_hessian(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist, double* H,
+                void* stream) {
+  g_err.clear();
+  if (!m) return fail(ABD_EINVAL, "model is NULL");
+  int rc = check_opts(o, false);
+  if (rc) return rc;
+  if (m->n_models == 0) return ABD_OK;
+  if (!q || !q_hist || !H) return fail(ABD_EINVAL, "q, q_hist and H must not be NULL");
+  if ((rc = check_device(m))) return rc;
+  return abd_impl::launch_hessian(m, o, q, q_hist, H, stream);
+}
+
 int abd_rollout_vjp(abd_model* m, const abd_step_opts* o, const double* q_init, const double* q_traj,
                     const double* dL_dq_traj, double* dL_dq_init, double* dL_dtau, abd_step_stats* stats,
                     int n_steps, void* stream) {

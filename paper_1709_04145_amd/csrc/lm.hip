@@ -93,10 +93,14 @@ __device__ double lm_residual(Sc& sc, const HocArgs<U>& args, const FrameGeo& ge
 // Explicit Jacobian of the residuals at q into J (row (u, b), column (a, c),
 // row-major, leading dimension N = U nf; J must be zero where no entry is
 // written: entries of frames that are not above one another).  wp: LDS table
-// [U][nfmax][6] of the world axes and joint points of every frame.
+// [U][nfmax][6] of the world axes and joint points of every frame.  oidx (may
+// be null: the frame order) gives the row/column position of every frame of
+// the model.  With U = 1, weights (1, -2, 1) and Bk = A(q_{k-1}) - 2 A(q_k), the
+// residual is the gradient of Eq. EQ and J its Hessian.
 template <int U, typename Sc>
 __device__ void lm_jacobian(Sc& sc, const HocArgs<U>& args, const FrameGeo& geo, int f, bool valid, int j,
-                            int nf, int nfmax, const double q[U], double* J, double* wp) {
+                            int nf, int nfmax, const double q[U], double* J, double* wp,
+                            const int* oidx = nullptr) {
   const DevModel& d = args.d;
   const int N = U * nf;
   asm volatile("" ::: "memory");
@@ -146,13 +150,13 @@ __device__ void lm_jacobian(Sc& sc, const HocArgs<U>& args, const FrameGeo& geo,
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       v[i] = valid ? AM[0][4 * i + 3] : 0.0;
-      v[3 + i] = valid ? AM[1][4 * i + 3] : 0.0;
+      v[3 + i] = (valid && U > 1) ? AM[U > 1 ? 1 : 0][4 * i + 3] : 0.0;
     }
     sc.suffix6_total2(v, t0, t1);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       hs[0][i] = v[i];
-      hs[1][i] = v[3 + i];
+      if (U > 1) hs[U > 1 ? 1 : 0][i] = v[3 + i];
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) v[i] = (valid && U > 2) ? AM[U > 2 ? 2 : 1][4 * i + 3] : 0.0;
@@ -282,9 +286,11 @@ __device__ void lm_jacobian(Sc& sc, const HocArgs<U>& args, const FrameGeo& geo,
       for (int c = 0; c < 3; ++c) Ntw[c] = Nc[c] * wba[0] + Nc[3 + c] * wba[1] + Nc[6 + c] * wba[2];
       const double wba_hu = wba[0] * hu[0] + wba[1] * hu[1] + wba[2] * hu[2];
       const double hu_pba = hu[0] * pba[0] + hu[1] * pba[1] + hu[2] * pba[2];
-      double* row = J + ((size_t)u * nf + j) * N + (size_t)a * nf;       // J[(u, b)][(a, .)]
-      double* col = J + (size_t)a * nf + j;                               // J[(u, .)][(a, b)]
+      const int ob = oidx ? oidx[j] : j;                                  // position of this frame
+      double* row = J + ((size_t)u * nf + ob) * N + (size_t)a * nf;      // J[(u, b)][(a, .)]
+      double* col = J + (size_t)a * nf + ob;                              // J[(u, .)][(a, b)]
       for (int x = j; x >= 0; x = fpar[x]) {
+        const int ox = oidx ? oidx[x] : x;
         // row entry J[(u,b),(a,x)]: X = N - h_u p'^T - p_b h_a^T + m p_b p'^T
         const double* wx = wp + ((size_t)a * nfmax + x) * 6;
         const double wq[3] = {wx[0], wx[1], wx[2]}, pq[3] = {wx[3], wx[4], wx[5]};
@@ -307,7 +313,7 @@ __device__ void lm_jacobian(Sc& sc, const HocArgs<U>& args, const FrameGeo& geo,
                (wxu[0] * wb[0] + wxu[1] * wb[1] + wxu[2] * wb[2]) * trY;
           e += sv;
         }
-        row[x] = e;
+        row[ox] = e;
         if (x != j) {
           // column entry J[(u,x),(a,b)]: X' = N - h_u p_b(a)^T - p_x(u) h_a^T + m p_x(u) p_b(a)^T
           const double wxu[3] = {wu[0], wu[1], wu[2]}, pxu[3] = {wu[3], wu[4], wu[5]};
@@ -320,7 +326,7 @@ __device__ void lm_jacobian(Sc& sc, const HocArgs<U>& args, const FrameGeo& geo,
           const double wba_px = wba[0] * pxu[0] + wba[1] * pxu[1] + wba[2] * pxu[2];
           const double ha_wx = ha[0] * wxu[0] + ha[1] * wxu[1] + ha[2] * wxu[2];
           const double wXwc = Ntw_wx - wba_hu * pba_wx - wba_px * ha_wx + ms * wba_px * pba_wx;
-          col[((size_t)u * nf + x) * N] = wuu * (wx_wba * trXc - wXwc) + sv;
+          col[((size_t)u * nf + ox) * N] = wuu * (wx_wba * trXc - wXwc) + sv;
         }
       }
     }
@@ -768,6 +774,54 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_lm(LmArgs<U> la) {
 
 }  // namespace
 
+namespace {
+
+struct HessArgs {
+  HocArgs<1> h;           // model, dt^2, weights (1, -2, 1), Bk = the model's per-step B
+  const double* q;        // [n_dofs]
+  double* H;              // per model a dense n_i x n_i row-major block
+  const long long* hoff;  // [n_models+1] start of every model's block
+  int nfmax;
+};
+
+// Hessian of the step objective (Eq. EQ scaled by dt^2) at q, explicitly: the
+// Jacobian of its gradient, assembled like the order-K Jacobian with one point.
+template <int NW, bool TREE>
+__global__ void __launch_bounds__(NW* kWave) k_hessian(HessArgs a) {
+  __shared__ ScanLds<NW, TREE> L;
+  __shared__ int oidx[kMaxFrames * NW];
+  extern __shared__ double wp[];  // [nfmax][6]
+  const HocArgs<1>& args = a.h;
+  const DevModel& d = args.d;
+  const int j = threadIdx.x;
+  const int model = blockIdx.x;
+  const int f0 = d.f0[model];
+  const int nf = d.f0[model + 1] - f0;
+  if (nf == 0) return;
+  const bool valid = j < nf;
+  const int f = f0 + (valid ? j : 0);
+  typename ModelScan<NW, TREE>::type ws = ModelScan<NW, TREE>::make(L, d, j / kWave, j % kWave, j, f, valid);
+  const int io = TREE ? (valid ? d.uidx[f] : 0) : f;
+  if (valid) oidx[j] = io - f0;  // the model's DOFs are contiguous from f0 in the caller's order too
+  const FrameGeo geo = load_geo(d, f, valid);
+  const double q = valid ? a.q[io] : 0.0;
+  {
+    const Xf<double> Ap = fk_geo<double>(ws, geo, valid, valid ? args.q_prev[io] : 0.0);
+    const Xf<double> Ak = fk_geo<double>(ws, geo, valid, valid ? args.q_curr[io] : 0.0);
+    if (valid)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) args.Bk[(size_t)f * 12 + k] = Ap.m[k] - 2.0 * Ak.m[k];
+  }
+  double* Hm = a.H + a.hoff[model];
+  for (int e = j; e < nf * nf; e += NW * kWave) Hm[e] = 0.0;
+  __threadfence_block();
+  __syncthreads();
+  const double qq[1] = {q};
+  lm_jacobian<1>(ws, args, geo, f, valid, j, nf, a.nfmax, qq, Hm, wp, oidx);
+}
+
+}  // namespace
+
 namespace abd_impl {
 
 int launch_lm_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
@@ -821,6 +875,56 @@ int launch_lm_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, co
   }
 #undef ABD_LM_U
 #undef ABD_LM
+  HIP_TRY(hipGetLastError());
+  return ABD_OK;
+}
+
+int launch_hessian(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist, double* H,
+                   void* stream) {
+  int rc;
+  if (!m->sq_off) {
+    std::vector<long long> off(m->n_models + 1, 0);
+    for (int i = 0; i < m->n_models; ++i) {
+      const long long nfi = m->f0_host[i + 1] - m->f0_host[i];
+      off[i + 1] = off[i] + nfi * nfi;
+    }
+    void* p = nullptr;
+    if ((rc = model_alloc(m, &p, off.size() * sizeof(long long)))) return rc;
+    m->sq_off = static_cast<long long*>(p);
+    HIP_TRY(hipMemcpy(m->sq_off, off.data(), off.size() * sizeof(long long), hipMemcpyHostToDevice));
+  }
+  HessArgs a;
+  a.h.d = dev_view(m);
+  a.h.dt2 = o->dt * o->dt;
+  a.h.w[0][0] = 1.0;
+  a.h.w[0][1] = -2.0;
+  a.h.w[0][2] = 1.0;
+  a.h.q_prev = q_hist;
+  a.h.q_curr = q_hist + m->n_dofs;
+  a.h.Bk = m->B64;  // the model's per-step constant, rewritten here for this q_hist
+  a.q = q;
+  a.H = H;
+  a.hoff = m->sq_off;
+  a.nfmax = m->max_frames;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nw = waves_for(m->max_frames);
+  const size_t lds = (size_t)6 * m->max_frames * sizeof(double);
+  const dim3 grid(m->n_models), block(nw * kWave);
+#define ABD_HESS(NW, TREE) hipLaunchKernelGGL((k_hessian<NW, TREE>), grid, block, lds, s, a)
+  if (m->tree) {
+    if (nw == 1) ABD_HESS(1, true);
+    else if (nw == 2) ABD_HESS(2, true);
+    else ABD_HESS(4, true);
+  } else {
+    switch (nw) {
+      case 1: ABD_HESS(1, false); break;
+      case 2: ABD_HESS(2, false); break;
+      case 4: ABD_HESS(4, false); break;
+      case 8: ABD_HESS(8, false); break;
+      default: ABD_HESS(16, false); break;
+    }
+  }
+#undef ABD_HESS
   HIP_TRY(hipGetLastError());
   return ABD_OK;
 }
