@@ -61,19 +61,23 @@ extern "C" {
 
 /* optimizers (abd_step_opts.solver), Sec. 5 "Optimization Algorithm" */
 #define ABD_SOLVER_LBFGS 0  /* L-BFGS (two-loop recursion) with a backtracking line search */
-#define ABD_SOLVER_LM 1     /* order_K > 2 only: Levenberg-Marquardt on the sum of squares
-                               Eq. EQHOC, (J^T J + lambda I) v = -J^T r with the explicit
-                               Jacobian of the residuals and a per-model Cholesky
-                               factorization, lambda by Nielsen's gain-ratio rule (initial
-                               1e-3 max diag(J^T J), at least 1e-15 of it), plus half the
+#define ABD_SOLVER_LM 1     /* Levenberg-Marquardt (Sec. 5), ABD_FP64 only (ABD_ENOTSUP
+                               otherwise): (J^T J + lambda I) v = -grad E with a
+                               per-model Cholesky factorization; lambda by
+                               Nielsen's gain-ratio rule (initial 1e-3 max diag(J^T J), at
+                               least 1e-15 of it); a step is accepted when it decreases E.
+                               Order 2 (Eq. EQ, an integral of squares): J^T J is the
+                               joint-space inertia H_q(q), one objective evaluation per
+                               iteration.  Order 3 (Eq. EQHOC, a sum of squares of the
+                               residuals r): the explicit Jacobian of r, plus half the
                                geodesic acceleration of Transtrum & Sethna's variant
                                (finite-difference step 0.1, steps with 2|a| > 0.75|v|
-                               rejected); a step is accepted when it decreases E.
-                               max_iter counts iterations, accepted or rejected; stats
-                               evaluations count residual evaluations; flag 2 = lambda
-                               overflow or an accepted point equal to the iterate.
+                               rejected); order 4 is rejected (ABD_ENOTSUP).  max_iter
+                               counts iterations, accepted or rejected; stats evaluations
+                               count objective (order 2) or residual evaluations; flag 2 =
+                               lambda overflow or an accepted point equal to the iterate.
                                lbfgs_m, max_ls, precond and refresh are ignored.  Device
-                               memory: 3 ((K-1) n_i)^2 doubles per model, on first use. */
+                               memory: 27 n_i^2 doubles per model, on first use. */
 
 #define ABD_PRECOND_IDENTITY 0 /* L-BFGS initial inverse Hessian gamma*I */
 #define ABD_PRECOND_INERTIA 2  /* initial inverse Hessian = inverse joint-space

@@ -308,6 +308,93 @@ class Oracle:
             raise ValueError(f"orc_step_lm_hoc failed ({rc})")
         return out.reshape(K - 1, self.n_dofs), stats
 
+    def step_lm_eq(self, q_prev, q_curr, dt, tau=None, tol=1e-8, max_iter=300, lambda0=1e-3):
+        """One step of Eq. EQ (order 2) by Levenberg-Marquardt (Sec. 5): the kinetic
+        term is an integral of squares whose J^T J is the joint-space inertia
+        H_q(q) = sum_l tr(dA_l/dq_i M_l dA_l/dq_j^T) (orc_inertia_matrix); each
+        iteration solves (H_q + lambda I) v = -grad E by a dense Cholesky and
+        accepts v if it decreases E.  lambda starts at lambda0 max diag(H_q), stays
+        >= 1e-15 max diag(H_q), and follows Nielsen's rule with the gain ratio
+        against the model decrease -g.v - v.H_q v / 2.  Warm start 2 q_k - q_{k-1}.
+        Stops when |grad E| <= tol |grad E(warm start)| (flag 1), when lambda
+        overflows or an accepted point equals the iterate (flag 2), or after max_iter
+        iterations, accepted or rejected (flag 4).  Returns (q, stats); stats
+        count iterations and objective evaluations."""
+        qp, qc = _f64(q_prev), _f64(q_curr)
+        do = self.desc.dof_offset
+        nm = self.n_models
+        q = 2.0 * qc - qp
+        stats = np.zeros(nm, dtype=STATS_DTYPE)
+        E, g, _ = self.objective_grad(q, qp, qc, dt, tau)
+        stats["evaluations"] = 1
+        g0 = np.array([np.linalg.norm(g[do[i]:do[i + 1]]) for i in range(nm)])
+        lam = np.full(nm, -1.0)
+        nu = np.full(nm, 2.0)
+        active = np.ones(nm, bool)
+        for i in range(nm):
+            if not np.isfinite(E[i]) or not np.all(np.isfinite(g[do[i]:do[i + 1]])):
+                stats["flag"][i] = FLAG_NONFINITE
+                active[i] = False
+            elif g0[i] == 0.0:
+                stats["flag"][i] = FLAG_CONVERGED
+                active[i] = False
+        for _ in range(max_iter):
+            if not active.any():
+                break
+            H = self.inertia_matrix(q)
+            qt = q.copy()
+            pred = np.zeros(nm)
+            tried = np.zeros(nm, bool)
+            for i in np.nonzero(active)[0]:
+                sl = slice(do[i], do[i + 1])
+                stats["iterations"][i] += 1
+                dmax = float(np.max(np.diag(H[i])))
+                if lam[i] < 0.0:
+                    lam[i] = lambda0 * dmax
+                lam[i] = max(lam[i], 1e-15 * dmax)
+                if not lam[i] <= 1e300:
+                    stats["flag"][i] = FLAG_LS_FLOOR
+                    active[i] = False
+                    continue
+                try:
+                    L = np.linalg.cholesky(H[i] + lam[i] * np.eye(H[i].shape[0]))
+                except np.linalg.LinAlgError:
+                    lam[i] *= nu[i]
+                    nu[i] *= 2.0
+                    continue
+                v = -np.linalg.solve(L.T, np.linalg.solve(L, g[sl]))
+                qt[sl] = q[sl] + v
+                pred[i] = -(g[sl] @ v) - 0.5 * (v @ (H[i] @ v))
+                tried[i] = True
+            if not tried.any():
+                continue
+            Et, gt, _ = self.objective_grad(qt, qp, qc, dt, tau)
+            for i in np.nonzero(tried)[0]:
+                sl = slice(do[i], do[i + 1])
+                stats["evaluations"][i] += 1
+                if not (np.isfinite(Et[i]) and Et[i] < E[i]):
+                    lam[i] *= nu[i]
+                    nu[i] *= 2.0
+                    continue
+                if np.array_equal(qt[sl], q[sl]):
+                    stats["flag"][i] = FLAG_LS_FLOOR
+                    active[i] = False
+                    continue
+                rho = min(1.0, (E[i] - Et[i]) / max(pred[i], 1e-300))
+                lam[i] *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+                nu[i] = 2.0
+                q[sl] = qt[sl]
+                g[sl] = gt[sl]
+                E[i] = Et[i]
+                if np.linalg.norm(g[sl]) <= tol * g0[i]:
+                    stats["flag"][i] = FLAG_CONVERGED
+                    active[i] = False
+        stats["flag"][active] = FLAG_MAX_ITER
+        for i in range(nm):
+            stats["grad_norm"][i] = np.linalg.norm(g[do[i]:do[i + 1]])
+            stats["energy"][i] = E[i]
+        return q, stats
+
     def rollout_lm(self, K, q_prev, q0, steps, dt, **kw):
         """Order-K rollout by Levenberg-Marquardt steps: q_0..q_steps and the stats."""
         qs = [np.array(q0, dtype=np.float64)]

@@ -68,6 +68,8 @@ int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const
                const StepScratch* sc = nullptr);
 int launch_lm_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
                   const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream);
+int launch_lm2(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
+               const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream);
 int launch_hessian(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist, double* H,
                    void* stream);
 int launch_hoc_objective(abd_model* m, const abd_step_opts* o, const double* q, const double* q_hist,

@@ -120,8 +120,7 @@ int check_opts(const abd_step_opts* o, bool for_step) {
     return fail(ABD_EINVAL, "schedule must be ABD_SCHEDULE_AUTO or ABD_SCHEDULE_WAVE");
   if (o->solver != ABD_SOLVER_LBFGS && o->solver != ABD_SOLVER_LM)
     return fail(ABD_EINVAL, "solver must be ABD_SOLVER_LBFGS or ABD_SOLVER_LM");
-  if (o->solver == ABD_SOLVER_LM && o->order_K == 2)
-    return fail(ABD_ENOTSUP, "ABD_SOLVER_LM handles order_K > 2 (Eq. EQHOC) in this build");
+
   return ABD_OK;
 }
 
@@ -379,6 +378,8 @@ int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const d
   if (o->order_K > 2 && o->solver == ABD_SOLVER_LM)
     return abd_impl::launch_lm_hoc(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
   if (o->order_K > 2) return abd_impl::launch_hoc(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
+  if (o->solver == ABD_SOLVER_LM)
+    return abd_impl::launch_lm2(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
   return abd_impl::launch_rollout(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
 }
 
@@ -391,6 +392,8 @@ int abd_rollout(abd_model* m, const abd_step_opts* o, const double* q_init, cons
   if (o->order_K > 2 && o->solver == ABD_SOLVER_LM)
     return abd_impl::launch_lm_hoc(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
   if (o->order_K > 2) return abd_impl::launch_hoc(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
+  if (o->solver == ABD_SOLVER_LM)
+    return abd_impl::launch_lm2(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
   return abd_impl::launch_rollout(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
 }
 

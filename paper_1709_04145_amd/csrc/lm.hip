@@ -97,7 +97,7 @@ __device__ double lm_residual(Sc& sc, const HocArgs<U>& args, const FrameGeo& ge
 // be null: the frame order) gives the row/column position of every frame of
 // the model.  With U = 1, weights (1, -2, 1) and Bk = A(q_{k-1}) - 2 A(q_k), the
 // residual is the gradient of Eq. EQ and J its Hessian.
-template <int U, typename Sc>
+template <int U, typename Sc, bool WITH_S = true>
 __device__ void lm_jacobian(Sc& sc, const HocArgs<U>& args, const FrameGeo& geo, int f, bool valid, int j,
                             int nf, int nfmax, const double q[U], double* J, double* wp,
                             const int* oidx = nullptr) {
@@ -174,8 +174,8 @@ __device__ void lm_jacobian(Sc& sc, const HocArgs<U>& args, const FrameGeo& geo,
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     // seed G_u and the composite Y_u, F_u below this frame (for the S block)
-    double Y[9], Fv[3];
-    {
+    double Y[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Fv[3];
+    if (WITH_S) {
       double G[12];
 #pragma unroll
       for (int r = 0; r < 3; ++r)
@@ -307,7 +307,7 @@ __device__ void lm_jacobian(Sc& sc, const HocArgs<U>& args, const FrameGeo& geo,
         // S block (u == a): frame x above b, both at q_u
         const double* wu = wp + ((size_t)u * nfmax + x) * 6;
         double sv = 0.0;
-        if (u == a) {
+        if (WITH_S && u == a) {
           const double wxu[3] = {wu[0], wu[1], wu[2]};
           sv = (wxu[0] * Yw[0] + wxu[1] * Yw[1] + wxu[2] * Yw[2]) -
                (wxu[0] * wb[0] + wxu[1] * wb[1] + wxu[2] * wb[2]) * trY;
@@ -822,7 +822,192 @@ __global__ void __launch_bounds__(NW* kWave) k_hessian(HessArgs a) {
 
 }  // namespace
 
+namespace {
+
+struct Lm2Args {
+  DevModel d;
+  double dt2, tol;
+  int max_iter, n_steps;
+  const double* q_prev;   // q_{-1}
+  const double* q_curr;   // q_0
+  const double* tau;      // [n_steps][n_dofs] or NULL
+  double* q_out;          // [n_steps][n_dofs]
+  abd_step_stats* stats;  // [n_steps][n_models] or NULL
+  double* mat;            // per model: A = H_q (n_i x n_i), factor U
+  const long long* moff;  // [n_models+1] start of every model's matrices
+  int nfmax;
+};
+
+// Order 2 (Eq. EQ) by Levenberg-Marquardt (Sec. 5): the kinetic term is an
+// integral of squares whose J^T J is the joint-space inertia H_q = C(q, q)
+// (the Gauss-Newton part of the explicit Hessian, from composite sums); each
+// iteration solves (H_q + lambda I) v = -grad E by the per-model Cholesky and
+// accepts v if it decreases E (Nielsen's lambda rule against the model decrease
+// -g.v - v.H_q v / 2).  One evaluation per iteration, no line search.
+template <int NW, bool TREE>
+__global__ void __launch_bounds__(NW* kWave, 1) k_rollout_lm2(Lm2Args la) {
+  __shared__ ScanLds<NW, TREE> L;
+  __shared__ int bad;
+  __shared__ double red[NW];
+  extern __shared__ double dyn[];
+  const DevModel& d = la.d;
+  const int n = d.n_dofs;
+  const int j = threadIdx.x;
+  const bool lead = j == 0;
+  if (blockIdx.x >= d.n_models) return;
+  const int model = d.order[blockIdx.x];
+  const int f0 = d.f0[model];
+  const int nf = d.f0[model + 1] - f0;
+  if (nf == 0) {
+    if (lead && la.stats)
+      for (int k = 0; k < la.n_steps; ++k) {
+        abd_step_stats st = {0, 0, ABD_FLAG_CONVERGED, 0, 0, 0, 0.0, 0.0};
+        la.stats[(size_t)k * d.n_models + model] = st;
+      }
+    return;
+  }
+  const int N = nf;
+  double* const vv = dyn;                 // step
+  double* const hv = vv + la.nfmax;       // H_q v
+  double* const work = hv + la.nfmax;
+  double* const xs = work;
+  double* const ys = work + kTK * kTM;
+  double* const Dd = ys + kTK * kTN;
+  double* const Am = la.mat + la.moff[model];
+  double* const Um = Am + (size_t)N * N;
+  const bool valid = j < nf;
+  const int f = f0 + (valid ? j : 0);
+  typename ModelScan<NW, TREE>::type ws = ModelScan<NW, TREE>::make(L, d, j / kWave, j % kWave, j, f, valid);
+  const int io = TREE ? (valid ? d.uidx[f] : 0) : f;
+  const FrameGeo geo = load_geo(d, f, valid);
+  HocArgs<1> h;  // what the Gauss-Newton assembly reads: the model and C's weight 1
+  h.d = d;
+  h.dt2 = la.dt2;
+  h.w[0][0] = 1.0;
+  h.w[0][1] = -2.0;
+  h.w[0][2] = 1.0;
+  h.Bk = d.B64;
+  double qkm1 = valid ? la.q_prev[io] : 0.0;
+  double qk = valid ? la.q_curr[io] : 0.0;
+  for (int step = 0; step < la.n_steps; ++step) {
+    double q = valid ? 2.0 * qk - qkm1 : 0.0;
+    const double tau = (valid && la.tau) ? la.tau[(size_t)step * n + io] : 0.0;
+    int iters = 0, evals = 0, flag = 0;
+    write_B(ws, d, geo, f, valid, qkm1, qk);
+    __threadfence_block();
+    __syncthreads();
+    EvalResult r = evaluate<double>(ws, d, geo, f, valid, q, tau, la.dt2);
+    ++evals;
+    double E = r.E, g = r.g, gn = 0.0, g0 = 0.0, lambda = -1.0, nu = 2.0, dmax = 0.0;
+    bool fresh = false;  // H_q assembled at the current q
+    if (!isfinite(E) || !ws.all_finite(g)) {
+      flag = ABD_FLAG_NONFINITE;
+    } else {
+      g0 = uniform(sqrt(ws.sum(g * g)));
+      gn = g0;
+      if (g0 == 0.0) flag = ABD_FLAG_CONVERGED;
+    }
+    while (flag == 0) {
+      if (iters >= la.max_iter) {
+        flag = ABD_FLAG_MAX_ITER;
+        break;
+      }
+      ++iters;
+      if (!fresh) {
+        for (int e = j; e < N * N; e += NW * kWave) Am[e] = 0.0;
+        __threadfence_block();
+        __syncthreads();
+        const double qq[1] = {q};
+        lm_jacobian<1, decltype(ws), false>(ws, h, geo, f, valid, j, nf, la.nfmax, qq, Am, work);
+        __threadfence_block();
+        __syncthreads();
+        double dm = 0.0;
+        for (int i = j; i < N; i += NW * kWave) dm = fmax(dm, Am[(size_t)i * N + i]);
+        dmax = block_max<NW>(red, dm);
+        fresh = true;
+        if (lambda < 0.0) lambda = kLmLambda0 * dmax;
+      }
+      const double lam = fmax(lambda, kLmLambdaMin * dmax);
+      if (!(lam <= 1e300)) {
+        flag = ABD_FLAG_LS_FLOOR;
+        break;
+      }
+      if (!factor<NW>(Am, Um, N, lam, xs, ys, Dd, &bad)) {
+        lambda = lam * nu;
+        nu *= 2.0;
+        continue;
+      }
+      if (valid) vv[j] = -g;
+      __syncthreads();
+      chol_solve_lds<NW>(Um, N, vv);
+      matvec<NW>(Am, N, vv, hv);
+      const double v = valid ? vv[j] : 0.0;
+      const double pred = -ws.sum(g * v + 0.5 * v * (valid ? hv[j] : 0.0));
+      const double x = q + v;
+      const EvalResult rt = evaluate<double>(ws, d, geo, f, valid, x, tau, la.dt2);
+      ++evals;
+      if (!(isfinite(rt.E) && ws.all_finite(rt.g) && rt.E < E)) {
+        lambda = lam * nu;
+        nu *= 2.0;
+        continue;
+      }
+      if (uniform(ws.sum(valid && x != q ? 1.0 : 0.0)) == 0.0) {
+        flag = ABD_FLAG_LS_FLOOR;
+        break;
+      }
+      double gain = (E - rt.E) / fmax(pred, 1e-300);
+      if (gain > 1.0) gain = 1.0;
+      const double c3 = 2.0 * gain - 1.0;
+      lambda = lam * fmax(1.0 / 3.0, 1.0 - c3 * c3 * c3);
+      nu = 2.0;
+      q = x;
+      g = rt.g;
+      E = rt.E;
+      fresh = false;
+      gn = uniform(sqrt(ws.sum(g * g)));
+      if (gn <= la.tol * g0) flag = ABD_FLAG_CONVERGED;
+    }
+    if (valid) la.q_out[(size_t)step * n + io] = q;
+    if (la.stats && lead) {
+      abd_step_stats st;
+      st.iterations = iters;
+      st.evaluations = evals;
+      st.flag = flag;
+      st.f32_iterations = 0;
+      st.f32_evaluations = 0;
+      st.reserved = 0;
+      st.grad_norm = gn;
+      st.energy = E;
+      la.stats[(size_t)step * d.n_models + model] = st;
+    }
+    qkm1 = qk;
+    qk = q;
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
 namespace abd_impl {
+
+// Per-model dense matrices of the LM solvers, sized for three unknown points
+// (3 (3 n_i)^2 doubles per model), allocated on a model's first LM call.
+static int lm_matrices(abd_model* m) {
+  if (m->lm_mat) return ABD_OK;
+  std::vector<long long> off(m->n_models + 1, 0);
+  for (int i = 0; i < m->n_models; ++i) {
+    const long long nmat = 3LL * (m->f0_host[i + 1] - m->f0_host[i]);
+    off[i + 1] = off[i] + 3 * nmat * nmat;
+  }
+  void* p = nullptr;
+  int rc;
+  if ((rc = model_alloc(m, &p, std::max<long long>(1, off[m->n_models]) * sizeof(double)))) return rc;
+  m->lm_mat = static_cast<double*>(p);
+  if ((rc = model_alloc(m, &p, off.size() * sizeof(long long)))) return rc;
+  m->lm_off = static_cast<long long*>(p);
+  HIP_TRY(hipMemcpy(m->lm_off, off.data(), off.size() * sizeof(long long), hipMemcpyHostToDevice));
+  return ABD_OK;
+}
 
 int launch_lm_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
                   const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream) {
@@ -831,20 +1016,8 @@ int launch_lm_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, co
   const int U = o->order_K - 1;
   if (U != 2)
     return fail(ABD_ENOTSUP, "ABD_SOLVER_LM handles order_K = 3 in this build (order 4 is switched off)");
-  // per-model dense matrices (J, J^T J, factor), sized for three unknown points
-  if (!m->lm_mat) {
-    std::vector<long long> off(m->n_models + 1, 0);
-    for (int i = 0; i < m->n_models; ++i) {
-      const long long nmat = 3LL * (m->f0_host[i + 1] - m->f0_host[i]);
-      off[i + 1] = off[i] + 3 * nmat * nmat;
-    }
-    void* p = nullptr;
-    if ((rc = model_alloc(m, &p, std::max<long long>(1, off[m->n_models]) * sizeof(double)))) return rc;
-    m->lm_mat = static_cast<double*>(p);
-    if ((rc = model_alloc(m, &p, off.size() * sizeof(long long)))) return rc;
-    m->lm_off = static_cast<long long*>(p);
-    HIP_TRY(hipMemcpy(m->lm_off, off.data(), off.size() * sizeof(long long), hipMemcpyHostToDevice));
-  }
+  // per-model dense matrices (J, J^T J, factor)
+  if ((rc = lm_matrices(m))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nw = waves_for(m->max_frames);
   const int nfmax = m->max_frames;
@@ -925,6 +1098,55 @@ int launch_hessian(abd_model* m, const abd_step_opts* o, const double* q, const 
     }
   }
 #undef ABD_HESS
+  HIP_TRY(hipGetLastError());
+  return ABD_OK;
+}
+
+int launch_lm2(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
+               const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream) {
+  if (o->precision != ABD_FP64) return fail(ABD_ENOTSUP, "ABD_SOLVER_LM runs in ABD_FP64 only in this build");
+  int rc = lm_matrices(m);
+  if (rc) return rc;
+  Lm2Args a;
+  a.d = dev_view(m);
+  a.dt2 = o->dt * o->dt;
+  a.tol = o->tol;
+  a.max_iter = o->max_iter;
+  a.n_steps = n_steps;
+  a.q_prev = q_prev;
+  a.q_curr = q_curr;
+  a.tau = tau;
+  a.q_out = q_out;
+  a.stats = stats;
+  a.mat = m->lm_mat;
+  a.moff = m->lm_off;
+  a.nfmax = m->max_frames;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nw = waves_for(m->max_frames);
+  const size_t work = std::max<size_t>((size_t)6 * m->max_frames, (size_t)kTK * (kTM + kTN) + kTM * kTM);
+  const size_t lds = (2 * (size_t)m->max_frames + work) * sizeof(double);
+  const dim3 grid(m->n_models), block(nw * kWave);
+#define ABD_LM2(NW, TREE)                                                                       \
+  do {                                                                                          \
+    if (lds > 65536)                                                                            \
+      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rollout_lm2<NW, TREE>),      \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));       \
+    hipLaunchKernelGGL((k_rollout_lm2<NW, TREE>), grid, block, lds, s, a);                      \
+  } while (0)
+  if (m->tree) {
+    if (nw == 1) ABD_LM2(1, true);
+    else if (nw == 2) ABD_LM2(2, true);
+    else ABD_LM2(4, true);
+  } else {
+    switch (nw) {
+      case 1: ABD_LM2(1, false); break;
+      case 2: ABD_LM2(2, false); break;
+      case 4: ABD_LM2(4, false); break;
+      case 8: ABD_LM2(8, false); break;
+      default: ABD_LM2(16, false); break;
+    }
+  }
+#undef ABD_LM2
   HIP_TRY(hipGetLastError());
   return ABD_OK;
 }

@@ -180,3 +180,91 @@ def test_lm_rollout_has_the_collocation_order():
     assert 1.7 < math.log2(e3[0] / e3[1]) < 2.4, e3
     e4 = err(4, 0.01)
     assert e4 < 1e-2 * e3[0], (e3[0], e4)
+
+
+# ---------------------------------------------------------------- order 2 (Eq. EQ)
+# Sec. 5 applies Levenberg-Marquardt to Eq. EQ directly: its kinetic term is an
+# integral of squares whose Gauss-Newton matrix J^T J is the joint-space inertia
+# H_q(q).  step_lm_eq is pinned by the minimizer it must reach (the Newton-polished
+# L-BFGS result, within the tolerance-implied distance), by its first step in the
+# two limits of lambda (the Gauss-Newton step with the inertia of the test's own
+# Jacobian-form kinematics, and a gradient step of length |g| / lambda), and by the
+# degenerate start that is already a minimizer.
+
+
+def _eq_bound_check(orc, d, q, qp, qc, dt, tau=None):
+    qn, _ = orc.step(qp, qc, dt, tau, tol=1e-11, max_iter=2000)
+    qx, _ = orc.newton_polish(qn, qp, qc, dt, tau)
+    _, g, _ = orc.objective_grad(q, qp, qc, dt, tau)
+    H = orc.hessian(qx, qp, qc, dt)
+    do = d.dof_offset
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        bound = 1.5 * np.linalg.norm(np.linalg.inv(H[i]), 2) * np.linalg.norm(g[sl])
+        assert np.linalg.norm(q[sl] - qx[sl]) <= bound + 1e-12, (i, np.linalg.norm(q[sl] - qx[sl]), bound)
+
+
+def test_eq_lm_reaches_the_eq_minimizer_on_chains():
+    """Chains of the 4096-chain workload, third step of a rollout from rest."""
+    wl = W.config(2, n_models=5)
+    orc = Oracle(wl.model)
+    dt = wl.step.dt
+    qs, _ = orc.rollout(wl.q0, 2, dt)
+    qp, qc = qs[-2], qs[-1]
+    q, st = orc.step_lm_eq(qp, qc, dt, tol=1e-8)
+    assert np.all(st["flag"] == 1), st
+    # Gauss-Newton on a nearly consistent least-squares problem: few iterations
+    assert np.all(st["iterations"] <= 40), st["iterations"]
+    _eq_bound_check(orc, wl.model, q, qp, qc, dt)
+
+
+def test_eq_lm_reaches_the_eq_minimizer_on_trees_with_torques():
+    d = _tree(4, seed=140, max_links=6)
+    rng = np.random.default_rng(141)
+    qc = rng.uniform(-1, 1, d.n_dofs)
+    qp = qc - 0.02 * rng.standard_normal(d.n_dofs)
+    tau = rng.uniform(-20, 20, d.n_dofs)
+    orc = Oracle(d)
+    dt = 0.01
+    q, st = orc.step_lm_eq(qp, qc, dt, tau, tol=1e-7)  # 1e-8 is below one tree's float64 floor
+    assert np.all(st["flag"] == 1), st
+    _eq_bound_check(orc, d, q, qp, qc, dt, tau)
+
+
+def test_eq_lm_at_a_minimizer_start_takes_no_iteration():
+    """No gravity, no torque, at rest: the warm start q_0 is the minimizer (E = 0)."""
+    d = W.random_tree_models(3, 142, max_links=5, ball_prob=0.4, gravity=[0.0, 0.0, 0.0])
+    q0 = np.random.default_rng(143).uniform(-1, 1, d.n_dofs)
+    q, st = Oracle(d).step_lm_eq(q0, q0, 0.01)
+    assert np.all(st["flag"] == 1) and np.all(st["iterations"] == 0), st
+    assert np.array_equal(q, q0)
+
+
+@pytest.mark.parametrize("lambda0", [1e-20, 1e4])
+def test_eq_lm_first_step_in_the_limits_of_lambda(lambda0):
+    """One iteration from the warm start: with lambda at its floor (1e-15 max diag)
+    the step is the Gauss-Newton step -H_q^-1 g; with lambda = 1e4 max diag it is
+    the gradient step -g / lambda up to |H_q| / lambda.  H_q here comes from the test's own kinematics
+    (Jacobian form of the inertia), g from the pinned Alg. 1 gradient."""
+    d = _tree(3, seed=144, max_links=5)
+    rng = np.random.default_rng(145)
+    qc = rng.uniform(-1, 1, d.n_dofs)
+    qp = qc - 0.01 * rng.standard_normal(d.n_dofs)
+    dt = 0.01
+    orc = Oracle(d)
+    q, st = orc.step_lm_eq(qp, qc, dt, tol=1e-14, max_iter=1, lambda0=lambda0)
+    assert np.all(st["iterations"] == 1) and np.all(st["evaluations"] == 2), st
+    warm = 2 * qc - qp
+    _, g, _ = orc.objective_grad(warm, qp, qc, dt)
+    do = d.dof_offset
+    for i in range(d.n_models):
+        sl = slice(do[i], do[i + 1])
+        Hq = refkin.inertia_matrix(d.subset([i]), warm[sl], 0)
+        dmax = float(np.max(np.diag(Hq)))
+        if lambda0 < 1e-15:
+            ref = -np.linalg.solve(Hq, g[sl])
+            tol = 1e-9
+        else:
+            ref = -g[sl] / (lambda0 * dmax)
+            tol = 1.01 * np.linalg.norm(Hq, 2) / (lambda0 * dmax) + 1e-8
+        assert np.linalg.norm((q[sl] - warm[sl]) - ref) <= tol * np.linalg.norm(ref), i
