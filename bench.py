@@ -117,9 +117,11 @@ def parse():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--solver", choices=("auto", "lbfgs", "lm"), default="auto",
                     help="step optimizer: auto = Levenberg-Marquardt for order K = 3 (the sum-of-squares "
-                         "Eq. EQHOC; the library's LM handles order 3), L-BFGS otherwise")
+                         "Eq. EQHOC), L-BFGS otherwise; lm at order 2 runs float64 only")
     ap.add_argument("--order", type=int, default=0,
                     help="collocation order K instead of the configuration's (0: the configuration's)")
+    ap.add_argument("--dt", type=float, default=0.0, help="time step instead of the configuration's (0: the "
+                                                             "configuration's)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the teacher-forced parity sample")
@@ -225,6 +227,8 @@ def main():
     from paper_1709_04145_amd import workloads as W
 
     wl = W.config(args.config)
+    if args.dt > 0.0:
+        wl.step.dt = args.dt
     desc = wl.model
     if wl.torque is not None and args.warmup + args.steps > wl.torque.shape[0]:
         print(f"configuration {args.config} defines joint forces for {wl.torque.shape[0]} steps: "
@@ -238,11 +242,12 @@ def main():
     base = dict(dt=wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol, max_iter=wl.step.max_iter, order_K=K,
                 solver=solver)
     runs = {}
+    lm = solver == abd.SOLVER_LM
     for name, prec in (("mixed", abd.MIXED), ("fp64", abd.FP64)):
-        if name == "fp64" and args.no_fp64 and K == 2:
+        if name == "fp64" and args.no_fp64 and K == 2 and not lm:
             continue
-        if name == "mixed" and K > 2:
-            continue  # order K > 2 runs in float64 only
+        if name == "mixed" and (K > 2 or lm):
+            continue  # order K > 2 and Levenberg-Marquardt run in float64 only
         opts = abd.StepOptions(precision=prec, **base)
         init, traj, st, wall, kms = timed_rollout(torch, model, wl.q0, opts, args.warmup, args.steps, wl.torque)
         nbytes, xbytes = algorithmic_bytes(desc, st)
@@ -287,10 +292,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": mixed["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": mixed["achieved_gbs"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic(W.CONFIG_NAMES[args.config], "mixed" if "mixed" in runs else "fp64",
-                                                 args.warmup, args.steps),
-                     "kernel": "k_rollout<MIXED>" if "mixed" in runs else ("k_rollout<FP64>" if K == 2 else
-                                                                             ("k_rollout_lm" if solver == abd.SOLVER_LM
-                                                                              else "k_rollout_hoc")),
+                                                 args.warmup, args.steps) if args.dt == 0.0 else None,
+                     "kernel": "k_rollout<MIXED>" if "mixed" in runs else
+                     ("k_rollout_lm2" if lm and K == 2 else "k_rollout_lm" if lm else
+                      "k_rollout<FP64>" if K == 2 else "k_rollout_hoc"),
                      "kernel_ms": mixed["kernel_ms"],
                      "algorithmic_bytes": mixed["bytes"],
                      "extra_bytes": mixed["extra_bytes"],
@@ -313,10 +318,12 @@ def main():
         out["energy"] = energy_drift(torch, model, desc, wl, src, args)
 
     tf = None
-    if not args.no_parity and not args.no_cpu and K == 2:
+    if not args.no_parity and not args.no_cpu and K == 2 and not lm:
         tf = teacher_forced_gpu(torch, abd, model, desc, wl, runs, base, args)
 
-    if not args.no_cpu and K == 2:
+    if not args.no_cpu and K == 2 and lm:
+        out["cpu_baseline"] = eq_lm_cpu_baseline(desc, wl, runs["fp64"], args.warmup)
+    if not args.no_cpu and K == 2 and not lm:
         from oracle.oracle import Oracle
         threads = max(1, min(16, os.cpu_count() or 1))
         nsub = max(1, min(desc.n_models, args.cpu_models))
@@ -555,6 +562,35 @@ def hoc_lm_cpu_baseline(desc, wl, run, K):
                       f"timed launch's starting state, Levenberg-Marquardt with dense Jacobians, float64, {el:.1f} s",
             "converged_fraction": float(np.mean(st["flag"] == 1)),
             "iterations_per_step": float(st["iterations"].mean()),
+            "max_abs_q_diff_vs_gpu": float(np.max(np.abs(got - ref)))}
+
+
+def eq_lm_cpu_baseline(desc, wl, run, warmup):
+    """The oracle's order-2 Levenberg-Marquardt step (H_q from its pose derivatives,
+    dense Cholesky) on a bounded sample: the first timed step of a few models from
+    the GPU's starting state, and the largest distance of the GPU's result from the
+    oracle's on them (both solved to the workload's tolerance)."""
+    from oracle.oracle import Oracle
+    n = desc.n_dofs
+    threads = 1  # the oracle's LM runs its dense algebra in numpy, model by model
+    nsub = min(desc.n_models, 64)
+    sample = np.arange(0, desc.n_models, max(1, desc.n_models // nsub))[:nsub]
+    sub = desc.subset(sample)
+    idx = desc.dof_subset_index(sample)
+    init = run["init"].cpu().numpy()
+    t0 = time.perf_counter()
+    tau = None if wl.torque is None else wl.torque[warmup][idx]
+    ref, st = Oracle(sub, threads=threads).step_lm_eq(init[:n][idx], init[n:][idx], wl.step.dt, tau,
+                                                      tol=wl.step.tol, max_iter=wl.step.max_iter)
+    el = time.perf_counter() - t0
+    got = run["traj"][0].cpu().numpy()[idx]
+    gst = run["st"][0][sample]
+    return {"value": sub.n_links / el, "unit": "link-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first timed step of {nsub} of {desc.n_models} models ({sub.n_links} links) from the "
+                      f"timed launch's starting state, Levenberg-Marquardt with dense H_q, float64, {el:.1f} s",
+            "converged_fraction": float(np.mean(st["flag"] == 1)),
+            "iterations_per_step": float(st["iterations"].mean()),
+            "iterations_equal_gpu_fraction": float(np.mean(st["iterations"] == gst["iterations"])),
             "max_abs_q_diff_vs_gpu": float(np.max(np.abs(got - ref)))}
 
 

@@ -1,0 +1,54 @@
+"""Writes tests/golden/rope_steps.npz: the FP64 oracle's first three steps of four
+ropes of the 1000-link rope workload (dt = 0.1, L-BFGS history 10), the
+reference of the GPU's teacher-forced steps in tests/test_gpu_rope.py.
+
+Calls only the oracle (oracle/) and the seeded input generator (later steps of this
+workload reach the 3000-iteration cap in the oracle).  Per step k
+(0..2) it stores q_{k+1}, the oracle's stats, and the smallest eigenvalue of the
+step objective's Hessian at q_{k+1} (written-out second derivatives).  That
+eigenvalue is negative on these ropes: the step objective is not convex at this
+step size, the results are not isolated minimizers, and the test compares what
+the tolerance fixes (convergence, gradient, objective value), not configurations.
+
+Run from the repository root:  python tests/golden/make_rope_reference.py
+"""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle.oracle import Oracle  # noqa: E402
+from paper_1709_04145_amd import workloads as W  # noqa: E402
+
+MODELS, STEPS = 4, 3
+TOL, MAX_ITER = 1e-5, 3000
+
+
+def main():
+    wl = W.config(4, n_models=MODELS)
+    d, dt, m = wl.model, wl.step.dt, wl.step.lbfgs_m
+    orc = Oracle(d, threads=min(8, os.cpu_count() or 1))
+    qs = [wl.q0.copy(), wl.q0.copy()]  # q_{-1} = q_0 (zero initial velocity)
+    iters, flags, lam_min, gnorm = [], [], [], []
+    for k in range(STEPS):
+        q, st = orc.step(qs[-2], qs[-1], dt, lbfgs_m=m, tol=TOL, max_iter=MAX_ITER)
+        H = orc.hessian(q, qs[-2], qs[-1], dt)
+        lam_min.append([float(np.linalg.eigvalsh(0.5 * (h + h.T))[0]) for h in H])
+        iters.append(st["iterations"].copy())
+        flags.append(st["flag"].copy())
+        gnorm.append(st["grad_norm"].copy())
+        qs.append(q)
+        print(f"step {k}: iterations {st['iterations'].tolist()} flags {st['flag'].tolist()} "
+              f"lambda_min {['%.3g' % x for x in lam_min[-1]]}", flush=True)
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "rope_steps.npz")
+    np.savez_compressed(out, q=np.stack(qs), iterations=np.stack(iters), flag=np.stack(flags),
+                        grad_norm=np.stack(gnorm), lambda_min=np.array(lam_min), tol=TOL, max_iter=MAX_ITER,
+                        models=MODELS)
+    print("wrote", out)
+
+
+if __name__ == "__main__":
+    main()
