@@ -38,7 +38,16 @@ struct orc_model {
   int *frame_link;   /* [n_dofs] link owning the frame */
   int *frame_first;  /* [n_dofs] 1 if first frame of its link */
   int *frame_mass;   /* [n_dofs] link whose mass the frame carries, -1 = massless */
+  /* optional terms (orc_set_extras) */
+  int *dof_kind;     /* [n_dofs] 0 hinge, 1 slide; NULL = every DOF a hinge */
+  double *drag;      /* [n_links] drag coefficient of every link; NULL = no drag */
+  int *c_off;        /* [n_links+1] contact points of link l: c_off[l] .. c_off[l+1]-1; NULL = none */
+  double *c_pt;      /* [3*n_contacts] point in its link's frame, grouped by link */
+  double plane[4];   /* contact plane: unit normal n (world) and offset h */
+  double c_d1, c_d2; /* normal and friction penalties of Eq. FRI */
 };
+
+static int is_slide(const orc_model* m, int f) { return m->dof_kind && m->dof_kind[f] == 1; }
 
 /* ------------------------------------------------------------------ 4x4 -- */
 static void m4_eye(double* A) {
@@ -84,8 +93,14 @@ static void mm_full(const double* u, double* M) {
   for (int i = 0; i < 16; ++i) M[i] = u[idx[i]];
 }
 
-/* Rodrigues: R = I + sin(th) K + (1-cos(th)) K^2, K = [a]x.  t = [R o; 0 1]. */
-static void local_tf(const double* a, const double* o, double th, double* t) {
+/* Local transform of one DOF frame.  Hinge (Rodrigues): R = I + sin(th) K +
+ * (1-cos(th)) K^2, K = [a]x, t = [R o; 0 1].  Slide: t = [I, o + th a; 0 1]. */
+static void local_tf(const double* a, const double* o, double th, double* t, int slide) {
+  if (slide) {
+    m4_eye(t);
+    for (int i = 0; i < 3; ++i) t[4 * i + 3] = (o ? o[i] : 0.0) + th * a[i];
+    return;
+  }
   double K[9] = {0, -a[2], a[1], a[2], 0, -a[0], -a[1], a[0], 0};
   double K2[9];
   for (int i = 0; i < 3; ++i)
@@ -101,8 +116,13 @@ static void local_tf(const double* a, const double* o, double th, double* t) {
   for (int i = 0; i < 3; ++i) t[4 * i + 3] = o ? o[i] : 0.0;
   t[15] = 1.0;
 }
-/* dt/dth = [cos(th) K + sin(th) K^2, 0; 0 0] */
-static void local_dtf(const double* a, double th, double* dt) {
+/* dt/dth: hinge [cos(th) K + sin(th) K^2, 0; 0 0]; slide [0, a; 0 0] */
+static void local_dtf(const double* a, double th, double* dt, int slide) {
+  if (slide) {
+    memset(dt, 0, 16 * sizeof(double));
+    for (int i = 0; i < 3; ++i) dt[4 * i + 3] = a[i];
+    return;
+  }
   double K[9] = {0, -a[2], a[1], a[2], 0, -a[0], -a[1], a[0], 0};
   double K2[9];
   for (int i = 0; i < 3; ++i)
@@ -181,10 +201,131 @@ void orc_free(orc_model* m) {
   free(m->link_offset); free(m->parent); free(m->dofs_per_link); free(m->axis);
   free(m->offset); free(m->mm); free(m->link_dof); free(m->model_dof);
   free(m->frame_parent); free(m->frame_link); free(m->frame_first); free(m->frame_mass);
+  free(m->dof_kind); free(m->drag); free(m->c_off); free(m->c_pt);
   free(m);
 }
 
+int orc_set_extras(orc_model* m, const int* dof_kind, const double* drag, int n_contacts,
+                   const int* contact_link, const double* contact_point, const double* plane, double d1,
+                   double d2) {
+  int L = m->n_links, nd = m->n_dofs;
+  free(m->dof_kind); free(m->drag); free(m->c_off); free(m->c_pt);
+  m->dof_kind = NULL; m->drag = NULL; m->c_off = NULL; m->c_pt = NULL;
+  if (n_contacts < 0 || !(d1 >= 0.0) || !(d2 >= 0.0)) return -1;
+  if (dof_kind)
+    for (int f = 0; f < nd; ++f)
+      if (dof_kind[f] != 0 && dof_kind[f] != 1) return -1;
+  if (drag)
+    for (int l = 0; l < L; ++l)
+      if (!(drag[l] >= 0.0) || !isfinite(drag[l])) return -1;
+  for (int c = 0; c < n_contacts; ++c)
+    if (contact_link[c] < 0 || contact_link[c] >= L) return -1;
+  if (dof_kind) {
+    m->dof_kind = (int*)malloc((nd > 0 ? nd : 1) * sizeof(int));
+    for (int f = 0; f < nd; ++f) m->dof_kind[f] = dof_kind[f];
+  }
+  if (drag) {
+    m->drag = (double*)malloc((L > 0 ? L : 1) * sizeof(double));
+    for (int l = 0; l < L; ++l) m->drag[l] = drag[l];
+  }
+  if (n_contacts > 0) {
+    m->c_off = (int*)calloc(L + 1, sizeof(int));
+    m->c_pt = (double*)malloc(3 * (size_t)n_contacts * sizeof(double));
+    for (int c = 0; c < n_contacts; ++c) m->c_off[contact_link[c] + 1]++;
+    for (int l = 0; l < L; ++l) m->c_off[l + 1] += m->c_off[l];
+    int* fill = (int*)calloc(L > 0 ? L : 1, sizeof(int));
+    for (int c = 0; c < n_contacts; ++c) {
+      int l = contact_link[c], at = m->c_off[l] + fill[l]++;
+      for (int k = 0; k < 3; ++k) m->c_pt[3 * at + k] = contact_point[3 * c + k];
+    }
+    free(fill);
+    for (int k = 0; k < 4; ++k) m->plane[k] = plane[k];
+    m->c_d1 = d1;
+    m->c_d2 = d2;
+  }
+  return 0;
+}
+
 static int model_nd(const orc_model* m, int i) { return m->model_dof[i + 1] - m->model_dof[i]; }
+
+/* Eq. FRI for one contact point at world position x (xk at q_k), scaled by dt^2
+ * like the rest of the objective:
+ *   V = dt^2 D1 d^2 + D2 d^2 |P (x - xk)|^2,  d = max(0, h - n.x),  P = I - n n^T
+ * (penetration depth d of the half-space n.x < h, tangential displacement over
+ * the step).  Returns V; f = dV/dx; Hx (if not NULL) = d2V/dx2, 3x3 row-major. */
+static double contact_term(const orc_model* m, double dt2, const double* x, const double* xk, double* f,
+                           double* Hx) {
+  const double* n = m->plane;
+  double d = m->plane[3] - (n[0] * x[0] + n[1] * x[1] + n[2] * x[2]);
+  for (int k = 0; k < 3; ++k) f[k] = 0.0;
+  if (Hx) memset(Hx, 0, 9 * sizeof(double));
+  if (!(d > 0.0)) return 0.0;
+  double v[3], u[3], nv = 0.0;
+  for (int k = 0; k < 3; ++k) v[k] = x[k] - xk[k];
+  for (int k = 0; k < 3; ++k) nv += n[k] * v[k];
+  for (int k = 0; k < 3; ++k) u[k] = v[k] - nv * n[k];
+  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  double a = dt2 * m->c_d1 + m->c_d2 * uu;
+  /* d/dx: dd/dx = -n, d|u|^2/dx = 2u */
+  for (int k = 0; k < 3; ++k) f[k] = -2.0 * d * a * n[k] + 2.0 * m->c_d2 * d * d * u[k];
+  if (Hx)
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        Hx[3 * r + c] = 2.0 * a * n[r] * n[c] - 4.0 * m->c_d2 * d * (n[r] * u[c] + u[r] * n[c]) +
+                        2.0 * m->c_d2 * d * d * ((r == c ? 1.0 : 0.0) - n[r] * n[c]);
+  return d * d * a;
+}
+
+/* world position of the point p (link frame) under the pose T (rows 0..2) */
+static void point_at(const double* T, const double* p, double* x) {
+  for (int r = 0; r < 3; ++r) x[r] = T[4 * r] * p[0] + T[4 * r + 1] * p[1] + T[4 * r + 2] * p[2] + T[4 * r + 3];
+}
+
+/* Mass moment tensor of link l as a full 4x4; scaled: times 1 + 2 c_l (c_l the
+ * link's drag coefficient), the Gauss-Newton weight of the kinetic and drag
+ * terms together, which the step's inertia preconditioner uses.  (Contact
+ * stiffness is not represented: as an isotropic point mass it slows the
+ * sliding modes more than it helps the normal ones.) */
+static void link_mm(const orc_model* m, int l, double* M, int scaled) {
+  mm_full(m->mm + 10 * l, M);
+  if (scaled && m->drag)
+    for (int k = 0; k < 16; ++k) M[k] *= 1.0 + 2.0 * m->drag[l];
+}
+
+/* The drag and contact terms of link l (pose A at q, Ak at q_k) added to its
+ * energy e and seed G = dE/dA (3 rows of 4): drag c tr(dA M dA^T) with
+ * dA = A - Ak (the paper's drag potential D |(P - P_k)/dt|^2 integrated over
+ * the body, times dt^2, with c = D / rho), and Eq. FRI at the link's points. */
+static double extra_terms(const orc_model* m, int l, double dt2, const double* M, const double* A,
+                          const double* Ak, double* G) {
+  double e = 0.0;
+  if (m->drag && m->drag[l] != 0.0) {
+    double c = m->drag[l];
+    for (int r = 0; r < 3; ++r) {
+      double dA[4];
+      for (int k = 0; k < 4; ++k) dA[k] = A[4 * r + k] - Ak[4 * r + k];
+      for (int k = 0; k < 4; ++k) {
+        double dm = 0.0;
+        for (int x = 0; x < 4; ++x) dm += dA[x] * M[4 * x + k];
+        e += c * dm * dA[k];
+        G[4 * r + k] += 2.0 * c * dm;
+      }
+    }
+  }
+  if (m->c_off)
+    for (int p = m->c_off[l]; p < m->c_off[l + 1]; ++p) {
+      const double* pt = m->c_pt + 3 * p;
+      double x[3], xk[3], f[3];
+      point_at(A, pt, x);
+      point_at(Ak, pt, xk);
+      e += contact_term(m, dt2, x, xk, f, NULL);
+      for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) G[4 * r + k] += f[r] * pt[k];
+        G[4 * r + 3] += f[r];
+      }
+    }
+  return e;
+}
 
 /* Forward pass of Alg. 1 for model i: T[j] (world) and tl[j] (local), j local frame index. */
 static void fk_model(const orc_model* m, int i, const double* q, double* T, double* tl) {
@@ -195,7 +336,7 @@ static void fk_model(const orc_model* m, int i, const double* q, double* T, doub
     int f = d0 + j;
     const double* o = m->frame_first[f] ? m->offset + 3 * m->frame_link[f] : NULL;
     double* t = tl + 16 * j;
-    local_tf(m->axis + 3 * f, o, q[f], t);
+    local_tf(m->axis + 3 * f, o, q[f], t, is_slide(m, f));
     int p = m->frame_parent[f];
     m4_mul(p >= 0 ? T + 16 * (p - d0) : I4, t, T + 16 * j);
   }
@@ -228,7 +369,7 @@ static void alg1_backward(const orc_model* m, int i, const double* T, const doub
   for (int j = nd - 1; j >= 0; --j) {
     int f = d0 + j;
     int p = m->frame_parent[f];
-    local_dtf(m->axis + 3 * f, q[f], dt);
+    local_dtf(m->axis + 3 * f, q[f], dt, is_slide(m, f));
     m4_mul(p >= 0 ? T + 16 * (p - d0) : I4, dt, W);
     g[f] = m4_frob(W, Adj + 16 * j);
     if (p >= 0) m4_add_mul_bt(Adj + 16 * j, tl + 16 * j, Adj + 16 * (p - d0));
@@ -263,6 +404,7 @@ static double eval_model(const orc_model* m, int i, double dt, const double* q, 
       /* seed row r of dE/dA: D M - dt^2 g (M e4)^T */
       for (int c = 0; c < 4; ++c) w->Adj[16 * j + 4 * r + c] += DM[c] - dt2 * m->g[r] * M[4 * c + 3];
     }
+    e += extra_terms(m, l, dt2, M, A, Ak, w->Adj + 16 * j);
     E += e;
     Ssum += fabs(e);
   }
@@ -312,6 +454,17 @@ void orc_objective_grad(const orc_model* m, double dt, const double* q, const do
     if (S) S[i] = s;
     ws_free(&w);
   }
+}
+
+/* Eq. ATOM's pairing of one link: int rho P_a . P_b dp = sum_r row_r(A) M row_r(B)^T
+ * over the three pose rows. */
+static double link_I(const orc_model* m, int l, const double* A, const double* B) {
+  double M[16], s = 0.0;
+  mm_full(m->mm + 10 * l, M);
+  for (int r = 0; r < 3; ++r)
+    for (int x = 0; x < 4; ++x)
+      for (int y = 0; y < 4; ++y) s += A[4 * r + x] * M[4 * x + y] * B[4 * r + y];
+  return s;
 }
 
 /* I(q_a,q_b) of Eq. ATOM for model i with the homogeneous 4x4 transforms:
@@ -386,6 +539,20 @@ void orc_objective_Iform(const orc_model* m, double dt, const double* q, const d
     fk_model(m, i, q, w.T, w.tl);
     double e = 0.5 * atom_I(m, i, w.T, w.T) - 2.0 * atom_I(m, i, w.T, w.Tk) + atom_I(m, i, w.T, w.Tkm1);
     e += dt * dt * potential(m, i, w.T);
+    /* drag of App. A: c (I(q,q) - 2 I(q,q_k) + I(q_k,q_k)) per link; contact points */
+    for (int l = m->link_offset[i]; l < m->link_offset[i + 1]; ++l) {
+      int j = m->link_dof[l] + m->dofs_per_link[l] - 1 - d0;
+      if (m->drag && m->drag[l] != 0.0)
+        e += m->drag[l] * (link_I(m, l, w.T + 16 * j, w.T + 16 * j) - 2.0 * link_I(m, l, w.T + 16 * j, w.Tk + 16 * j) +
+                           link_I(m, l, w.Tk + 16 * j, w.Tk + 16 * j));
+      if (m->c_off)
+        for (int p = m->c_off[l]; p < m->c_off[l + 1]; ++p) {
+          double x[3], xk[3], f[3];
+          point_at(w.T + 16 * j, m->c_pt + 3 * p, x);
+          point_at(w.Tk + 16 * j, m->c_pt + 3 * p, xk);
+          e += contact_term(m, dt * dt, x, xk, f, NULL);
+        }
+    }
     if (tau)
       for (int j = 0; j < nd; ++j) e -= dt * dt * tau[d0 + j] * q[d0 + j];
     E[i] = e;
@@ -397,14 +564,14 @@ void orc_objective_Iform(const orc_model* m, double dt, const double* q, const d
  * h_n = sum over mass frames f below DOF n of tr(dA_f M dA_f^T),
  * dT^f/dq_n = T^{parent(n)} dt_n (T^n)^{-1} T^f. */
 static void inertia_diag_model(const orc_model* m, int i, const double* q, eval_ws* w, double* h,
-                               char* desc) {
+                               char* desc, int scaled) {
   int d0 = m->model_dof[i], nd = model_nd(m, i);
   fk_model(m, i, q, w->T, w->tl);
   double I4[16], dtl[16], W[16], Ti[16], tmp[16], dA[16], M[16];
   m4_eye(I4);
   for (int j = 0; j < nd; ++j) {
     int f = d0 + j, p = m->frame_parent[f];
-    local_dtf(m->axis + 3 * f, q[f], dtl);
+    local_dtf(m->axis + 3 * f, q[f], dtl, is_slide(m, f));
     m4_mul(p >= 0 ? w->T + 16 * (p - d0) : I4, dtl, tmp);
     m4_rigid_inv(w->T + 16 * j, Ti);
     m4_mul(tmp, Ti, W);
@@ -414,7 +581,7 @@ static void inertia_diag_model(const orc_model* m, int i, const double* q, eval_
       desc[k] = (k == j) || (pk >= d0 + j && desc[pk - d0]);
       int l = m->frame_mass[d0 + k];
       if (!desc[k] || l < 0) continue;
-      mm_full(m->mm + 10 * l, M);
+      link_mm(m, l, M, scaled);
       m4_mul(W, w->T + 16 * k, dA);
       for (int r = 0; r < 3; ++r)
         for (int x = 0; x < 4; ++x)
@@ -431,7 +598,7 @@ void orc_inertia_diag(const orc_model* m, const double* q, double* h, int n_thre
     eval_ws w;
     ws_alloc(&w, nd);
     char* desc = (char*)malloc(nd > 0 ? nd : 1);
-    inertia_diag_model(m, i, q, &w, h, desc);
+    inertia_diag_model(m, i, q, &w, h, desc, 0);
     free(desc);
     ws_free(&w);
   }
@@ -470,21 +637,21 @@ void orc_energy_report(const orc_model* m, double dt, const double* q_prev, cons
  * for i an ancestor-or-self of j,  H_ij = tr(W_i C_j W_j^T)  with
  * C_j = sum_{l below j} T^l M_l T^{lT}  (world moment tensor of the subtree). */
 static void inertia_matrix_model(const orc_model* m, int i, const double* q, eval_ws* w, double* H,
-                                 double* Wb, double* Cb) {
+                                 double* Wb, double* Cb, int scaled) {
   int d0 = m->model_dof[i], nd = model_nd(m, i);
   fk_model(m, i, q, w->T, w->tl);
   double I4[16], dtl[16], tmp[16], Ti[16], M[16];
   m4_eye(I4);
   for (int j = 0; j < nd; ++j) {
     int f = d0 + j, p = m->frame_parent[f];
-    local_dtf(m->axis + 3 * f, q[f], dtl);
+    local_dtf(m->axis + 3 * f, q[f], dtl, is_slide(m, f));
     m4_mul(p >= 0 ? w->T + 16 * (p - d0) : I4, dtl, tmp);
     m4_rigid_inv(w->T + 16 * j, Ti);
     m4_mul(tmp, Ti, Wb + 16 * j);
     memset(Cb + 16 * j, 0, 16 * sizeof(double));
     int l = m->frame_mass[f];
     if (l >= 0) {
-      mm_full(m->mm + 10 * l, M);
+      link_mm(m, l, M, scaled);
       m4_mul(w->T + 16 * j, M, tmp);
       m4_add_mul_bt(tmp, w->T + 16 * j, Cb + 16 * j);
     }
@@ -515,7 +682,7 @@ void orc_inertia_matrix(const orc_model* m, const double* q, double* H, int n_th
     eval_ws w;
     ws_alloc(&w, nd);
     double* Wb = (double*)malloc((size_t)(nd > 0 ? nd : 1) * 32 * sizeof(double));
-    inertia_matrix_model(m, i, q, &w, H + off[i], Wb, Wb + 16 * (size_t)(nd > 0 ? nd : 1));
+    inertia_matrix_model(m, i, q, &w, H + off[i], Wb, Wb + 16 * (size_t)(nd > 0 ? nd : 1), 0);
     free(Wb);
     ws_free(&w);
   }
@@ -533,7 +700,7 @@ static void generators_model(const orc_model* m, int i, const double* q, eval_ws
   m4_eye(I4);
   for (int j = 0; j < nd; ++j) {
     int f = d0 + j, p = m->frame_parent[f];
-    local_dtf(m->axis + 3 * f, q[f], dtl);
+    local_dtf(m->axis + 3 * f, q[f], dtl, is_slide(m, f));
     m4_mul(p >= 0 ? w->T + 16 * (p - d0) : I4, dtl, tmp);
     m4_rigid_inv(w->T + 16 * j, Ti);
     m4_mul(tmp, Ti, Wb + 16 * j);
@@ -583,6 +750,7 @@ static void hessian_model(const orc_model* m, int i, double dt, const double* q,
         for (int k = 0; k < 4; ++k) dm += (A[4 * r + k] - 2.0 * Ak[4 * r + k] + Akm1[4 * r + k]) * M[4 * k + c];
         Gb[16 * j + 4 * r + c] = dm - dt2 * m->g[r] * M[4 * c + 3];
       }
+    extra_terms(m, l, dt2, M, A, Ak, Gb + 16 * j);
   }
   memset(H, 0, (size_t)nd * nd * sizeof(double));
   double dAa[16], dAb[16], dAaM[16], WW[16], d2A[16], M[16];
@@ -595,12 +763,29 @@ static void hessian_model(const orc_model* m, int i, double dt, const double* q,
         int l = m->frame_mass[d0 + j];
         if (l < 0 || !below[(size_t)b * nd + j]) continue;
         mm_full(m->mm + 10 * l, M);
+        if (m->drag) /* the drag term adds 2 c_l tr(dA M dA'^T) */
+          for (int k = 0; k < 16; ++k) M[k] *= 1.0 + 2.0 * m->drag[l];
         m4_mul(Wb + 16 * a, w->T + 16 * j, dAa);
         m4_mul(Wb + 16 * b, w->T + 16 * j, dAb);
         m4_mul(dAa, M, dAaM);
         m4_mul(WW, w->T + 16 * j, d2A);
         for (int r = 0; r < 3; ++r)
           for (int c = 0; c < 4; ++c) v += dAaM[4 * r + c] * dAb[4 * r + c] + Gb[16 * j + 4 * r + c] * d2A[4 * r + c];
+        /* contact points: (dx/dq_a)^T d2V/dx2 (dx/dq_b), dx/dq = dA (p;1) */
+        if (m->c_off)
+          for (int p = m->c_off[l]; p < m->c_off[l + 1]; ++p) {
+            const double* pt = m->c_pt + 3 * p;
+            double x[3], xk[3], f[3], Hx[9], xa[3], xb[3];
+            point_at(w->T + 16 * j, pt, x);
+            point_at(w->Tk + 16 * j, pt, xk);
+            contact_term(m, dt2, x, xk, f, Hx);
+            for (int r = 0; r < 3; ++r) {
+              xa[r] = dAa[4 * r] * pt[0] + dAa[4 * r + 1] * pt[1] + dAa[4 * r + 2] * pt[2] + dAa[4 * r + 3];
+              xb[r] = dAb[4 * r] * pt[0] + dAb[4 * r + 1] * pt[1] + dAb[4 * r + 2] * pt[2] + dAb[4 * r + 3];
+            }
+            for (int r = 0; r < 3; ++r)
+              for (int c = 0; c < 3; ++c) v += xa[r] * Hx[3 * r + c] * xb[c];
+          }
       }
       H[(size_t)a * nd + b] = v;
       H[(size_t)b * nd + a] = v;
@@ -767,11 +952,11 @@ static void step_model(const orc_model* m, int i, const orc_opts* o, const doubl
   for (int j = 0; j < nd; ++j) P[j] = 1.0;
   if (mode == 2) {
     L = (double*)malloc(((size_t)nd * nd + 32 * (size_t)nd) * sizeof(double));
-    inertia_matrix_model(m, i, qfull, &w, L, L + (size_t)nd * nd, L + (size_t)nd * nd + 16 * nd);
+    inertia_matrix_model(m, i, qfull, &w, L, L + (size_t)nd * nd, L + (size_t)nd * nd + 16 * nd, 1);
     if (cholesky(L, nd) != 0) mode = 1; /* not positive definite: fall back to the diagonal */
   }
   if (mode == 1) {
-    inertia_diag_model(m, i, qfull, &w, gfull, desc);
+    inertia_diag_model(m, i, qfull, &w, gfull, desc, 1);
     for (int j = 0; j < nd; ++j) {
       double h = gfull[d0 + j];
       P[j] = (h > 0.0 && isfinite(h)) ? 1.0 / h : 1.0;
@@ -798,7 +983,7 @@ static void step_model(const orc_model* m, int i, const orc_opts* o, const doubl
     if (mode == 2 && o->refresh > 0 && it > 0 && it % o->refresh == 0) {
       /* H_q of the warm start no longer describes the iterate: re-form it at q
        * (qfull holds q after an accepted step) and restart the history */
-      inertia_matrix_model(m, i, qfull, &w, L, L + (size_t)nd * nd, L + (size_t)nd * nd + 16 * nd);
+      inertia_matrix_model(m, i, qfull, &w, L, L + (size_t)nd * nd, L + (size_t)nd * nd + 16 * nd, 1);
       if (cholesky(L, nd) != 0) {
         s.flag = 2;
         break;
@@ -1295,7 +1480,7 @@ static void step_model_hoc(const orc_model* m, int i, const orc_opts* o, const d
     eval_ws ew;
     ws_alloc(&ew, nd);
     L = (double*)malloc(((size_t)nd * nd + 32 * (size_t)nd) * sizeof(double));
-    inertia_matrix_model(m, i, qk, &ew, L, L + (size_t)nd * nd, L + (size_t)nd * nd + 16 * nd);
+    inertia_matrix_model(m, i, qk, &ew, L, L + (size_t)nd * nd, L + (size_t)nd * nd + 16 * nd, 0);
     ws_free(&ew);
     if (cholesky(L, nd) != 0 || small_inverse(WtW, U, Minv) != 0) mode = 0;
   }

@@ -63,6 +63,21 @@ orc_model* orc_create(int n_models, const int* link_offset, const int* parent,
                       const double* mass_moment, const double* gravity);
 void orc_free(orc_model* m);
 
+/* Optional terms of the step objective (Sec. 6 applications), replacing any set
+ * before.  dof_kind [n_dofs] (NULL: all hinges): 0 = hinge (rotation about the
+ * DOF's axis), 1 = slide (translation along it), so that a 6-DOF floating root
+ * is three slides and three hinges on one link.  drag [n_links] (NULL: none):
+ * per link c_l >= 0, adding c_l tr((A_l(q) - A_l(q_k)) M_l (...)^T) = dt^2 times
+ * the paper's drag potential D |(P(q) - P(q_k))/dt|^2 integrated over the body
+ * with c_l = D / rho_l.  n_contacts points (contact_link: global link index,
+ * contact_point [3*n_contacts] in the link frame) with the penalty potential of
+ * Eq. FRI against the half-space n.x < h (plane = n[3], h):
+ *   dt^2 D1 d^2 + D2 d^2 |(I - n n^T)(x(q) - x(q_k))|^2,  d = max(0, h - n.x).
+ * Returns 0, or -1 on invalid input (the model is then left without extras). */
+int orc_set_extras(orc_model* m, const int* dof_kind, const double* drag, int n_contacts,
+                   const int* contact_link, const double* contact_point, const double* plane, double d1,
+                   double d2);
+
 /* World poses A = [R|t] (3x4 row-major, 12 doubles) of every link at q. */
 void orc_poses(const orc_model* m, const double* q, double* poses, int n_threads);
 

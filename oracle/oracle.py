@@ -73,6 +73,8 @@ def lib():
         _lib.orc_create.restype = C.c_void_p
         _lib.orc_create.argtypes = [C.c_int, ip, ip, ip, dp, dp, dp, dp]
         _lib.orc_free.argtypes = [C.c_void_p]
+        _lib.orc_set_extras.argtypes = [C.c_void_p, ip, dp, C.c_int, ip, dp, dp, C.c_double, C.c_double]
+        _lib.orc_set_extras.restype = C.c_int
         _lib.orc_poses.argtypes = [C.c_void_p, dp, dp, C.c_int]
         _lib.orc_objective_grad.argtypes = [C.c_void_p, C.c_double, dp, dp, dp, dp, dp, dp, C.c_int]
         _lib.orc_objective_Iform.argtypes = [C.c_void_p, C.c_double, dp, dp, dp, dp, C.c_int]
@@ -136,12 +138,30 @@ class Oracle:
         self._h = lib().orc_create(desc.n_models, _i(k[0]), _i(k[1]), _i(k[2]),
                                    _d(k[3]), _d(k[4]), _d(k[5]), _d(k[6]))
         self.n_models, self.n_dofs, self.n_links = desc.n_models, desc.n_dofs, desc.n_links
+        self.extras = bool(getattr(desc, "has_extras", False))
+        if self.extras:
+            kind = None if desc.dof_kind is None else np.ascontiguousarray(desc.dof_kind, dtype=np.int32)
+            drag = None if desc.drag is None else _f64(desc.drag)
+            nc = desc.n_contacts
+            cl = np.ascontiguousarray(desc.contact_link if nc else np.zeros(1), dtype=np.int32)
+            cp = _f64(desc.contact_point if nc else np.zeros(3))
+            plane = _f64(desc.contact_plane)
+            self._keep += [kind, drag, cl, cp, plane]
+            rc = lib().orc_set_extras(self._h, None if kind is None else _i(kind), _d(drag), nc, _i(cl), _d(cp),
+                                      _d(plane), float(desc.contact_d1), float(desc.contact_d2))
+            if rc != 0:
+                raise ValueError("invalid slide / drag / contact description")
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
             lib().orc_free(h)
             self._h = None
+
+    def _no_extras(self, what):
+        if self.extras:
+            raise NotImplementedError(f"{what}: slide, drag and contact terms enter the order-2 objective "
+                                      f"(Eq. EQ) and its L-BFGS step only")
 
     # ---------------------------------------------------------------- queries
     def poses(self, q) -> np.ndarray:
@@ -209,6 +229,7 @@ class Oracle:
 
     def cross_hessian(self, q, q_other, scale):
         """List of per-model C[a][b] = scale sum_l <dA_l(q)/dq_a M_l, dA_l(q_o)/dq_o,b>."""
+        self._no_extras("cross_hessian")
         buf = self._block_buffer()
         lib().orc_cross_hessian(self._h, _d(_f64(q)), _d(_f64(q_other)), scale, _d(buf), self.threads)
         return self._blocks(buf)
@@ -247,6 +268,7 @@ class Oracle:
 
     def eqhoc_objective_grad(self, K, dt, q_prev, q_curr, q_unknown, tau=None):
         """Eq. EQHOC per model and its gradient [K-1, n] w.r.t. the unknown points."""
+        self._no_extras("eqhoc_objective_grad")
         E = np.zeros(self.n_models)
         g = np.zeros((K - 1) * self.n_dofs)
         known = _f64(np.concatenate([q_prev, q_curr]))
@@ -258,6 +280,7 @@ class Oracle:
     def eqhoc_residual_jacobian(self, K, dt, q_prev, q_curr, q_unknown, tau=None, jacobian=True):
         """Residuals dt^2 r_u of Eq. HOC ([K-1, n]) at the unknown points and, with
         jacobian, the list of dense per-model Jacobians ([(K-1) nd]^2, unknown-major)."""
+        self._no_extras("eqhoc_residual_jacobian")
         U = K - 1
         R = np.zeros(U * self.n_dofs)
         known = _f64(np.concatenate([q_prev, q_curr]))
@@ -281,6 +304,7 @@ class Oracle:
                  eps_w=EPS64, precond=2):
         """One Eq. EQHOC step: returns the K-1 unknown configurations [K-1, n] and stats.
         q_prev is the previous step's alpha_{K-2} point, q_curr = q_k."""
+        self._no_extras("step_hoc")
         opts = OrcOpts(dt, K, lbfgs_m, tol, max_iter, max_ls, eps_w, precond, 0)
         known = _f64(np.concatenate([q_prev, q_curr]))
         out = np.zeros((K - 1) * self.n_dofs)
@@ -297,6 +321,7 @@ class Oracle:
         """One Eq. EQHOC step (order K >= 2) by Levenberg-Marquardt (orc_step_lm_hoc):
         returns the K-1 unknown configurations [K-1, n] and stats (iterations =
         LM iterations, accepted or rejected; evaluations = residual evaluations)."""
+        self._no_extras("step_lm")
         opts = OrcLmOpts(dt, K, max_iter, tol, lambda0, 1 if geodesic else 0, geo_h, geo_alpha)
         known = _f64(np.concatenate([q_prev, q_curr]))
         out = np.zeros((K - 1) * self.n_dofs)
@@ -320,6 +345,7 @@ class Oracle:
         overflows or an accepted point equals the iterate (flag 2), or after max_iter
         iterations, accepted or rejected (flag 4).  Returns (q, stats); stats
         count iterations and objective evaluations."""
+        self._no_extras("step_lm_eq")
         qp, qc = _f64(q_prev), _f64(q_curr)
         do = self.desc.dof_offset
         nm = self.n_models
@@ -433,6 +459,7 @@ class Oracle:
         traj = [q_1..q_T] (T x n); dL_dtraj = dL/dq_1..q_T (T x n, the explicit
         dependence of the loss).  Returns (dL/dq_{-1}, dL/dq_0, dL/dtau [T x n]).
         Dense solves, model by model."""
+        self._no_extras("rollout_vjp")
         traj = np.asarray(traj, dtype=np.float64)
         T = traj.shape[0]
         n = self.n_dofs
