@@ -101,14 +101,38 @@ typedef struct {
                                  link_offset[i] .. link_offset[i+1]-1 */
   const int* parent;          /* [n_links] parent link index within the model, -1 =
                                  fixed world frame; a parent precedes its children */
-  const int* dofs_per_link;   /* [n_links] 1..3 consecutive hinges per joint */
-  const double* axis;         /* [3*n_dofs] unit hinge axis of each DOF, expressed in the
-                                 frame it rotates (link-major DOF order) */
+  const int* dofs_per_link;   /* [n_links] 1..6 consecutive elementary DOFs per joint */
+  const double* axis;         /* [3*n_dofs] unit axis of each DOF, expressed in the frame
+                                 it moves (link-major DOF order) */
   const double* offset;       /* [3*n_links] joint origin in the parent link frame */
   const double* mass_moment;  /* [10*n_links] upper triangle (row-major) of the symmetric
                                  positive semi-definite 4x4 M_l with M_l[3][3] = mass > 0 */
   double gravity[3];          /* gravitational acceleration (world frame) */
+  /* Optional terms of Sec. 6's applications (NULL / 0: absent).  A model that
+     uses any of them ("extras") takes abd_step / abd_rollout at order_K = 2
+     with ABD_SOLVER_LBFGS, abd_objective_grad and abd_poses; every other entry
+     point returns ABD_ENOTSUP for it, and it may have at most 256 DOFs. */
+  const int* dof_kind;        /* [n_dofs] ABD_DOF_HINGE (rotation about the axis) or
+                                 ABD_DOF_SLIDE (translation along it; the frame does
+                                 not rotate); NULL = all hinges.  A 6-DOF floating root
+                                 is a root link with three slides and three hinges. */
+  const double* drag;         /* [n_links] drag coefficient c_l >= 0 (finite): adds
+                                 c_l tr((A_l(q) - A_l(q_k)) M_l (A_l(q) - A_l(q_k))^T), which
+                                 is dt^2 times the drag potential D |(P(q) - P(q_k))/dt|^2
+                                 of Sec. 6 integrated over the body, c_l = D / rho_l;
+                                 NULL = none */
+  int n_contacts;             /* discrete contact points (>= 0) */
+  const int* contact_link;    /* [n_contacts] global link index of each point */
+  const double* contact_point;/* [3*n_contacts] point in its link's frame */
+  double contact_plane[4];    /* n (unit, world) and h: the obstacle is n.x < h */
+  double contact_d1;          /* D1 >= 0, normal penalty of Eq. FRI */
+  double contact_d2;          /* D2 >= 0, friction penalty of Eq. FRI: each point adds
+                                 dt^2 D1 d^2 + D2 d^2 |(I - n n^T)(x(q) - x(q_k))|^2,
+                                 d = max(0, h - n.x) its penetration depth */
 } abd_model_desc;
+
+#define ABD_DOF_HINGE 0
+#define ABD_DOF_SLIDE 1
 
 typedef struct {
   double dt;         /* time step > 0 */
@@ -149,7 +173,8 @@ typedef struct {
  * topology, finite values, unit axes, positive mass and positive semi-definite
  * moment tensors (ABD_EINVAL).  Synchronous.  *out receives the handle.
  * Limits of this build (ABD_ENOTSUP): serial chains of up to 1024 DOFs per
- * model, branched models (trees) of up to 256 DOFs per model.  abd_hvp and
+ * model, branched models (trees) of up to 256 DOFs per model, models with
+ * slides, drag or contact points of up to 256 DOFs.  abd_hvp and
  * abd_rollout_vjp take serial chains of up to 64 DOFs; order_K > 2 takes models
  * of up to 256 DOFs. */
 int abd_create_model(const abd_model_desc* desc, abd_model** out);

@@ -36,7 +36,17 @@ class ModelDescC(C.Structure):
                 ("axis", C.POINTER(C.c_double)),
                 ("offset", C.POINTER(C.c_double)),
                 ("mass_moment", C.POINTER(C.c_double)),
-                ("gravity", C.c_double * 3)]
+                ("gravity", C.c_double * 3),
+                ("dof_kind", C.POINTER(C.c_int)),
+                ("drag", C.POINTER(C.c_double)),
+                ("n_contacts", C.c_int),
+                ("contact_link", C.POINTER(C.c_int)),
+                ("contact_point", C.POINTER(C.c_double)),
+                ("contact_plane", C.c_double * 4),
+                ("contact_d1", C.c_double),
+                ("contact_d2", C.c_double)]
+
+DOF_HINGE, DOF_SLIDE = 0, 1
 
 
 class StepOptsC(C.Structure):
@@ -159,6 +169,25 @@ class Model:
         dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
         cd = ModelDescC(int(desc.n_models), ip(k[0]), ip(k[1]), ip(k[2]), dp(k[3]), dp(k[4]), dp(k[5]),
                         (C.c_double * 3)(*[float(x) for x in desc.gravity]))
+        # optional terms (slides, drag, contact points)
+        kind = getattr(desc, "dof_kind", None)
+        drag = getattr(desc, "drag", None)
+        nc = int(getattr(desc, "n_contacts", 0))
+        if kind is not None:
+            self._keep.append(np.ascontiguousarray(kind, dtype=np.int32))
+            cd.dof_kind = ip(self._keep[-1])
+        if drag is not None:
+            self._keep.append(np.ascontiguousarray(drag, dtype=np.float64))
+            cd.drag = dp(self._keep[-1])
+        if nc > 0:
+            self._keep += [np.ascontiguousarray(desc.contact_link, dtype=np.int32),
+                           np.ascontiguousarray(desc.contact_point, dtype=np.float64)]
+            cd.n_contacts = nc
+            cd.contact_link = ip(self._keep[-2])
+            cd.contact_point = dp(self._keep[-1])
+            cd.contact_plane = (C.c_double * 4)(*[float(x) for x in desc.contact_plane])
+            cd.contact_d1 = float(desc.contact_d1)
+            cd.contact_d2 = float(desc.contact_d2)
         h = C.c_void_p()
         _check(lib.abd_create_model(C.byref(cd), C.byref(h)))
         self._h = h

@@ -360,6 +360,15 @@ struct DevModel {
   const int* fend;          // [n_dofs] last frame below this one (within the model)
   int jump_rounds;          // ceil(log2(deepest frame path)) of the batch
   double gx, gy, gz;
+  // optional terms (models with slides, drag or contact points; NULL otherwise)
+  const signed char* fkind; // [n_dofs] 1 = slide (translation along the axis), 0 = hinge
+  const double* fdrag;      // [n_dofs] drag coefficient of the link whose mass the frame carries
+  const int* coff;          // [n_dofs+1] contact points of frame f: coff[f] .. coff[f+1]-1
+  const double* cpt;        // [n_contacts][3] point in the frame of its link
+  double* Ak64;             // [n_dofs][12] per-step A(q_k) (drag and friction)
+  float* Ak32;              // [n_dofs][12]
+  double plane[4];          // contact half-space n.x < h: n (unit, world), h
+  double cd1, cd2;          // normal and friction penalties of Eq. FRI
 };
 
 inline DevModel dev_view(const abd_model* m) {
@@ -380,6 +389,15 @@ inline DevModel dev_view(const abd_model* m) {
   d.fend = m->fend;
   d.jump_rounds = m->jump_rounds;
   d.gx = m->g[0]; d.gy = m->g[1]; d.gz = m->g[2];
+  d.fkind = m->fkind;
+  d.fdrag = m->fdrag;
+  d.coff = m->coff;
+  d.cpt = m->cpt;
+  d.Ak64 = m->Ak64;
+  d.Ak32 = m->Ak32;
+  for (int k = 0; k < 4; ++k) d.plane[k] = m->plane[k];
+  d.cd1 = m->cd1;
+  d.cd2 = m->cd2;
   return d;
 }
 
@@ -396,11 +414,13 @@ template <>
 struct Arr<double> {
   static __device__ __forceinline__ const double* fr(const DevModel& d) { return d.fr64; }
   static __device__ __forceinline__ const double* B(const DevModel& d) { return d.B64; }
+  static __device__ __forceinline__ const double* Ak(const DevModel& d) { return d.Ak64; }
 };
 template <>
 struct Arr<float> {
   static __device__ __forceinline__ const float* fr(const DevModel& d) { return d.fr32; }
   static __device__ __forceinline__ const float* B(const DevModel& d) { return d.B32; }
+  static __device__ __forceinline__ const float* Ak(const DevModel& d) { return d.Ak32; }
 };
 
 // ----------------------------------------------------------- scan policies --
@@ -665,15 +685,23 @@ struct TreeScan : BlockScan<NW> {
 // forward pass; frame j's joint is at its origin, offset o_j in the parent frame):
 //   R_j = R_{j-1} Rot(a_j, q_j)  -> prefix scan of hinge quaternions,
 //   t_j = t_{j-1} + R_{j-1} o_j  -> prefix sum of the parent-rotated offsets.
+// A slide frame (slide = true) does not rotate and moves its offset along its
+// axis: R_j = R_{j-1}, t_j = t_{j-1} + R_{j-1} (o_j + q_j a_j).
 template <typename R, typename S>
-__device__ __forceinline__ Xf<R> forward_kinematics(S& sc, const R a[3], const R o[3], bool valid, double q) {
-  Quat<R> Q = hinge_quat(a, valid ? q : 0.0);
-  if (!valid) Q = Quat<R>{R(1), R(0), R(0), R(0)};
+__device__ __forceinline__ Xf<R> forward_kinematics(S& sc, const R a[3], const R o[3], bool valid, double q,
+                                                    bool slide = false) {
+  Quat<R> Q = hinge_quat(a, valid && !slide ? q : 0.0);
+  if (!valid || slide) Q = Quat<R>{R(1), R(0), R(0), R(0)};
   Q = sc.prefix_quat(Q);
   // parent rotation: the predecessor's prefix (identity for the root frame)
   const Quat<R> Qp = sc.parent_quat(Q);
   R v[3];
-  qrotate(Qp, o, v);
+  if (slide) {
+    const R os[3] = {o[0] + R(q) * a[0], o[1] + R(q) * a[1], o[2] + R(q) * a[2]};
+    qrotate(Qp, os, v);
+  } else {
+    qrotate(Qp, o, v);
+  }
   sc.prefix_sum3(v);
   Xf<R> A;
   A.m[3] = v[0];
@@ -694,10 +722,14 @@ __device__ __forceinline__ Xf<R> forward_kinematics(S& sc, const R a[3], const R
   return A;
 }
 
-// axis and joint offset of this lane's frame (float64, kept in registers)
+// axis and joint offset of this lane's frame (float64, kept in registers), and
+// whether it is a slide (only read by the FX instantiations: models with slides,
+// drag or contact points)
 struct FrameGeo {
   double a[3], o[3];
+  bool slide;
 };
+template <bool FX = false>
 __device__ __forceinline__ FrameGeo load_geo(const DevModel& d, int f, bool valid) {
   FrameGeo g;
   const double* rec = d.fr64 + (size_t)f * 16;
@@ -706,13 +738,36 @@ __device__ __forceinline__ FrameGeo load_geo(const DevModel& d, int f, bool vali
     g.a[k] = ld_if(rec + k, valid);
     g.o[k] = ld_if(rec + 3 + k, valid);
   }
+  g.slide = FX && valid && d.fkind && d.fkind[f] == 1;
   return g;
 }
-template <typename R, typename S>
+template <typename R, bool FX = false, typename S>
 __device__ __forceinline__ Xf<R> fk_geo(S& sc, const FrameGeo& g, bool valid, double q) {
   const R a[3] = {(R)g.a[0], (R)g.a[1], (R)g.a[2]};
   const R o[3] = {(R)g.o[0], (R)g.o[1], (R)g.o[2]};
-  return forward_kinematics<R>(sc, a, o, valid, q);
+  return forward_kinematics<R>(sc, a, o, valid, q, FX && g.slide);
+}
+
+// Eq. FRI at one contact point, world position x (xk at q_k), times dt^2:
+//   V = dt^2 D1 d^2 + D2 d^2 |P (x - xk)|^2,  d = max(0, h - n.x),  P = I - n n^T.
+// Returns V and the force f = dV/dx.
+__device__ __forceinline__ double contact_force(const DevModel& d, double dt2, const double x[3],
+                                                const double xk[3], double f[3]) {
+  const double* n = d.plane;
+  const double pen = d.plane[3] - (n[0] * x[0] + n[1] * x[1] + n[2] * x[2]);
+  if (!(pen > 0.0)) {
+    f[0] = f[1] = f[2] = 0.0;
+    return 0.0;
+  }
+  const double v0 = x[0] - xk[0], v1 = x[1] - xk[1], v2 = x[2] - xk[2];
+  const double nv = n[0] * v0 + n[1] * v1 + n[2] * v2;
+  const double u0 = v0 - nv * n[0], u1 = v1 - nv * n[1], u2 = v2 - nv * n[2];
+  const double a = dt2 * d.cd1 + d.cd2 * (u0 * u0 + u1 * u1 + u2 * u2);
+  const double fn = -2.0 * pen * a, ft = 2.0 * d.cd2 * pen * pen;
+  f[0] = fn * n[0] + ft * u0;
+  f[1] = fn * n[1] + ft * u1;
+  f[2] = fn * n[2] + ft * u2;
+  return pen * pen * a;
 }
 
 struct EvalResult {
@@ -721,8 +776,9 @@ struct EvalResult {
   double g;  // dE/dq of this lane's DOF (0 on lanes without a frame)
 };
 
-// One objective + gradient evaluation for the model of this wave.
-template <typename R, typename S>
+// One objective + gradient evaluation for the model of this wave.  FX: the
+// model may have slides, drag and contact points.
+template <typename R, bool FX = false, typename S>
 __device__ EvalResult evaluate(S& sc, const DevModel& d, const FrameGeo& geo, int f, bool valid, double q,
                                double tau, double dt2) {
   // keep the per-frame loads inside the evaluation (no hoisting across calls,
@@ -736,7 +792,7 @@ __device__ EvalResult evaluate(S& sc, const DevModel& d, const FrameGeo& geo, in
   for (int k = 0; k < 10; ++k) M[k] = ld_if(rec + 6 + k, valid);
 #pragma unroll
   for (int k = 0; k < 4; ++k) Bn[k] = Bp[k];  // lanes without a frame: M = 0 zeroes every term
-  const Xf<R> A = fk_geo<R>(sc, geo, valid, q);
+  const Xf<R> A = fk_geo<R, FX>(sc, geo, valid, q);
   const R a[3] = {(R)geo.a[0], (R)geo.a[1], (R)geo.a[2]};
 
   // Row r of D = A + B (= A(q) - 2A(q_k) + A(q_{k-1})), of D M and of the seed
@@ -775,8 +831,56 @@ __device__ EvalResult evaluate(S& sc, const DevModel& d, const FrameGeo& geo, in
     }
     pot -= gr * AMe4;
   }
+  // drag c tr(dA M dA^T), dA = A - A(q_k), seed 2 c dA M; contact points (Eq. FRI):
+  // a point force f at x adds x x f to the moment sum and f to the force sum
+  double efx = 0.0;
+  if (FX && valid) {
+    const R* Akp = Arr<R>::Ak(d) + (size_t)f * 12;
+    const double c = d.fdrag ? d.fdrag[f] : 0.0;
+    if (c != 0.0) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        R dA[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) dA[x] = A.m[4 * r + x] - Akp[4 * r + x];
+        const int r1 = (r + 1) % 3, r2 = (r + 2) % 3;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          R dm = R(0);
+#pragma unroll
+          for (int x = 0; x < 4; ++x) dm += dA[x] * M[sym4(x, cc)];
+          efx += c * (double)dm * (double)dA[cc];
+          const double Grc = 2.0 * c * (double)dm;
+          const double u1 = A.m[4 * r1 + cc], u2 = A.m[4 * r2 + cc];
+          if (r == 0) { k1 += u2 * Grc; k2 -= u1 * Grc; }
+          if (r == 1) { k2 += u2 * Grc; k0 -= u1 * Grc; }
+          if (r == 2) { k0 += u2 * Grc; k1 -= u1 * Grc; }
+          if (cc == 3) fv[r] += Grc;
+        }
+      }
+    }
+    if (d.coff)
+      for (int p = d.coff[f]; p < d.coff[f + 1]; ++p) {
+        const double pt[3] = {d.cpt[3 * p], d.cpt[3 * p + 1], d.cpt[3 * p + 2]};
+        double x[3], xk[3], fc[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          x[r] = (double)A.m[4 * r] * pt[0] + (double)A.m[4 * r + 1] * pt[1] + (double)A.m[4 * r + 2] * pt[2] +
+                 (double)A.m[4 * r + 3];
+          xk[r] = (double)Akp[4 * r] * pt[0] + (double)Akp[4 * r + 1] * pt[1] + (double)Akp[4 * r + 2] * pt[2] +
+                  (double)Akp[4 * r + 3];
+        }
+        efx += contact_force(d, dt2, x, xk, fc);
+        k0 += x[1] * fc[2] - x[2] * fc[1];
+        k1 += x[2] * fc[0] - x[0] * fc[2];
+        k2 += x[0] * fc[1] - x[1] * fc[0];
+        fv[0] += fc[0];
+        fv[1] += fc[1];
+        fv[2] += fc[2];
+      }
+  }
   const double tq = dt2 * tau * q;
-  const double elane = (double)e + dt2 * (double)pot;
+  const double elane = (double)e + dt2 * (double)pot + efx;
   double Ev = elane - (valid ? tq : 0.0);
   double Sv = fabs(elane) + (valid ? fabs(tq) : 0.0);
 
@@ -790,9 +894,11 @@ __device__ EvalResult evaluate(S& sc, const DevModel& d, const FrameGeo& geo, in
   const double w1 = (double)A.m[4] * a[0] + (double)A.m[5] * a[1] + (double)A.m[6] * a[2];
   const double w2 = (double)A.m[8] * a[0] + (double)A.m[9] * a[1] + (double)A.m[10] * a[2];
   const double p0 = A.m[3], p1 = A.m[7], p2 = A.m[11];
-  const double m0 = suf[0] - (p1 * suf[5] - p2 * suf[4]);
-  const double m1 = suf[1] - (p2 * suf[3] - p0 * suf[5]);
-  const double m2 = suf[2] - (p0 * suf[4] - p1 * suf[3]);
+  // hinge: dE/dq = w.(K - p x F); slide: dE/dq = w.F
+  const bool sl = FX && geo.slide;
+  const double m0 = sl ? suf[3] : suf[0] - (p1 * suf[5] - p2 * suf[4]);
+  const double m1 = sl ? suf[4] : suf[1] - (p2 * suf[3] - p0 * suf[5]);
+  const double m2 = sl ? suf[5] : suf[2] - (p0 * suf[4] - p1 * suf[3]);
   EvalResult res;
   res.g = valid ? (w0 * m0 + w1 * m1 + w2 * m2 - dt2 * tau) : 0.0;
   res.E = Ev;
@@ -1242,27 +1348,30 @@ __device__ void aba_solve_tree(const double (*tab)[kTab], double* xb, const int*
 }
 
 // Inputs of the inertia preconditioner at configuration q (float64): this
-// frame's world spatial inertia about the origin and its hinge motion.
-template <typename S>
+// frame's world spatial inertia about the origin and its joint motion (FX: a
+// slide's motion is the pure translation (0; w), and a link's inertia is
+// weighted by 1 + 2c, the Gauss-Newton weight of its kinetic and drag terms).
+template <bool FX = false, typename S>
 __device__ __forceinline__ void precond_frame(S& sc, const DevModel& d, double* inert, double* tab,
                                               const FrameGeo& geo, int f, bool valid, double q0);
 
 // Setup of one step for this wave's model (float64): the per-step constant
-// B = -2 A(q_k) + A(q_{k-1}) of every frame, and for the inertia preconditioner
-// its inputs at the warm start.
-template <typename S>
+// B = -2 A(q_k) + A(q_{k-1}) of every frame (FX: and A(q_k) itself where the
+// model has drag or contact points), and for the inertia preconditioner its
+// inputs at the warm start.
+template <bool FX = false, typename S>
 __device__ __forceinline__ void step_setup(S& sc, const DevModel& d, double* inert, double* tab, const FrameGeo& geo,
                                            int f, bool valid, double qkm1, double qk, double q0, bool use_aba) {
   double* B64 = d.B64 + (size_t)f * 12;
   float* B32 = d.B32 + (size_t)f * 12;
   {
-    const Xf<double> Akm1 = fk_geo<double>(sc, geo, valid, qkm1);
+    const Xf<double> Akm1 = fk_geo<double, FX>(sc, geo, valid, qkm1);
     if (valid)
 #pragma unroll
       for (int k = 0; k < 12; ++k) B64[k] = Akm1.m[k];
   }
   {
-    const Xf<double> Ak = fk_geo<double>(sc, geo, valid, qk);
+    const Xf<double> Ak = fk_geo<double, FX>(sc, geo, valid, qk);
     if (valid)
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
@@ -1270,19 +1379,30 @@ __device__ __forceinline__ void step_setup(S& sc, const DevModel& d, double* ine
         B64[k] = b;
         B32[k] = (float)b;
       }
+    if (FX && valid && d.Ak64)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        d.Ak64[(size_t)f * 12 + k] = Ak.m[k];
+        d.Ak32[(size_t)f * 12 + k] = (float)Ak.m[k];
+      }
   }
-  if (use_aba) precond_frame(sc, d, inert, tab, geo, f, valid, q0);
+  if (use_aba) precond_frame<FX>(sc, d, inert, tab, geo, f, valid, q0);
 }
 
-template <typename S>
+template <bool FX, typename S>
 __device__ __forceinline__ void precond_frame(S& sc, const DevModel& d, double* inert, double* tab,
                                               const FrameGeo& geo, int f, bool valid, double q0) {
   const double* a = geo.a;
-  const Xf<double> A = fk_geo<double>(sc, geo, valid, q0);
+  const Xf<double> A = fk_geo<double, FX>(sc, geo, valid, q0);
   double M[10];
   const double* rec = d.fr64 + (size_t)f * 16;
 #pragma unroll
   for (int k = 0; k < 10; ++k) M[k] = ld_if(rec + 6 + k, valid);
+  if (FX && valid && d.fdrag) {
+    const double wgt = 1.0 + 2.0 * d.fdrag[f];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) M[k] *= wgt;
+  }
   const double ms = M[9];
   // world moment tensor: h = R (m c) + m t ; Sigma = R S R^T + R mc t^T + t (R mc)^T + m t t^T
   double Rmc[3];
@@ -1321,6 +1441,15 @@ __device__ __forceinline__ void precond_frame(S& sc, const DevModel& d, double* 
   const double w1 = A.m[4] * a[0] + A.m[5] * a[1] + A.m[6] * a[2];
   const double w2 = A.m[8] * a[0] + A.m[9] * a[1] + A.m[10] * a[2];
   double* ts = tab;
+  if (FX && geo.slide) {
+    ts[0] = 0.0;
+    ts[1] = 0.0;
+    ts[2] = 0.0;
+    ts[3] = w0;
+    ts[4] = w1;
+    ts[5] = w2;
+    return;
+  }
   ts[0] = valid ? w0 : 0.0;
   ts[1] = valid ? w1 : 0.0;
   ts[2] = valid ? w2 : 0.0;
@@ -1585,12 +1714,13 @@ __device__ double hess_vec(Sc& sc, const DevModel& d, const FrameGeo& geo, int f
   return valid ? r : 0.0;
 }
 
-// B = A(q_{k-1}) - 2 A(q_k) of this lane's frame into the model scratch.
-template <typename Sc>
+// B = A(q_{k-1}) - 2 A(q_k) of this lane's frame into the model scratch (FX:
+// and A(q_k) where the model has drag or contact points).
+template <bool FX = false, typename Sc>
 __device__ __forceinline__ void write_B(Sc& sc, const DevModel& d, const FrameGeo& geo, int f, bool valid,
                                         double qkm1, double qk) {
-  const Xf<double> Ak = fk_geo<double>(sc, geo, valid, qk);
-  const Xf<double> Akm1 = fk_geo<double>(sc, geo, valid, qkm1);
+  const Xf<double> Ak = fk_geo<double, FX>(sc, geo, valid, qk);
+  const Xf<double> Akm1 = fk_geo<double, FX>(sc, geo, valid, qkm1);
   if (valid) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -1598,6 +1728,12 @@ __device__ __forceinline__ void write_B(Sc& sc, const DevModel& d, const FrameGe
       d.B64[(size_t)f * 12 + k] = b;
       d.B32[(size_t)f * 12 + k] = (float)b;
     }
+    if (FX && d.Ak64)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        d.Ak64[(size_t)f * 12 + k] = Ak.m[k];
+        d.Ak32[(size_t)f * 12 + k] = (float)Ak.m[k];
+      }
   }
 }
 

@@ -36,6 +36,16 @@ struct abd_model {
   int* uidx = nullptr;
   int* fpar = nullptr;
   int* fend = nullptr;
+  // optional terms (slides, drag, contact points); fx = any of them present
+  bool fx = false;
+  signed char* fkind = nullptr;  // [n_dofs] 1 = slide, internal frame order; NULL: all hinges
+  double* fdrag = nullptr;       // [n_dofs] drag coefficient per frame; NULL: no drag
+  int* coff = nullptr;           // [n_dofs+1] contact points per frame; NULL: none
+  double* cpt = nullptr;         // [n_contacts][3]
+  double* Ak64 = nullptr;        // [n_dofs][12] per-step A(q_k) (drag, friction)
+  float* Ak32 = nullptr;
+  double plane[4] = {0, 0, 1, 0};
+  double cd1 = 0.0, cd2 = 0.0;
   std::vector<void*> allocs;
 };
 

@@ -198,7 +198,7 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   long long nd_ll = 0;
   for (int l = 0; l < nl; ++l) {
     const int k = desc->dofs_per_link[l];
-    if (k < 1 || k > 3) return fail(ABD_EINVAL, "dofs_per_link must be in 1..3 (link " + std::to_string(l) + ")");
+    if (k < 1 || k > 6) return fail(ABD_EINVAL, "dofs_per_link must be in 1..6 (link " + std::to_string(l) + ")");
     nd_ll += k;
   }
   if (nd_ll > (1ll << 30)) return fail(ABD_EINVAL, "too many DOFs");
@@ -239,6 +239,42 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   }
   if (max_frames > kMaxFrames * kMaxWaves)
     return fail(ABD_ENOTSUP, "models with more than 1024 DOFs are not handled by this build");
+  // optional terms: slides, drag, contact points
+  bool any_slide = false, any_drag = false;
+  if (desc->dof_kind)
+    for (int f = 0; f < nd; ++f) {
+      if (desc->dof_kind[f] != ABD_DOF_HINGE && desc->dof_kind[f] != ABD_DOF_SLIDE)
+        return fail(ABD_EINVAL, "dof_kind of DOF " + std::to_string(f) + " must be ABD_DOF_HINGE or ABD_DOF_SLIDE");
+      any_slide |= desc->dof_kind[f] == ABD_DOF_SLIDE;
+    }
+  if (desc->drag)
+    for (int l = 0; l < nl; ++l) {
+      if (!(desc->drag[l] >= 0.0) || !std::isfinite(desc->drag[l]))
+        return fail(ABD_EINVAL, "drag of link " + std::to_string(l) + " must be finite and >= 0");
+      any_drag |= desc->drag[l] != 0.0;
+    }
+  const int nc = desc->n_contacts;
+  if (nc < 0) return fail(ABD_EINVAL, "n_contacts < 0");
+  if (nc > 0) {
+    if (!desc->contact_link || !desc->contact_point) return fail(ABD_EINVAL, "contact arrays must not be NULL");
+    for (int c = 0; c < nc; ++c) {
+      if (desc->contact_link[c] < 0 || desc->contact_link[c] >= nl)
+        return fail(ABD_EINVAL, "contact_link of point " + std::to_string(c) + " out of range");
+      for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(desc->contact_point[3 * (size_t)c + k])) return fail(ABD_EINVAL, "contact_point not finite");
+    }
+    const double* pl = desc->contact_plane;
+    const double nrm = std::sqrt(pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2]);
+    if (!std::isfinite(nrm) || std::fabs(nrm - 1.0) > 1e-9 || !std::isfinite(pl[3]))
+      return fail(ABD_EINVAL, "contact_plane must be a unit normal and a finite offset");
+    if (!(desc->contact_d1 >= 0.0) || !std::isfinite(desc->contact_d1) || !(desc->contact_d2 >= 0.0) ||
+        !std::isfinite(desc->contact_d2))
+      return fail(ABD_EINVAL, "contact_d1 and contact_d2 must be finite and >= 0");
+  }
+  const bool fx = any_slide || any_drag || nc > 0;
+  if (fx && max_frames > 4 * kMaxFrames)
+    return fail(ABD_ENOTSUP, "models with slides, drag or contact points of more than 256 DOFs are not handled "
+                             "by this build");
   if (!chain && max_frames > 4 * kMaxFrames)
     return fail(ABD_ENOTSUP, "branched models of more than 256 DOFs are not handled by this build");
   // Internal frame order: depth-first preorder of each model's links (children
@@ -320,7 +356,41 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   m->hinv_len = hoff[nm];
   m->f0_host = f0;
   for (int k = 0; k < 3; ++k) m->g[k] = desc->gravity[k];
+  m->fx = fx;
+  if (nc > 0) {
+    for (int k = 0; k < 4; ++k) m->plane[k] = desc->contact_plane[k];
+    m->cd1 = desc->contact_d1;
+    m->cd2 = desc->contact_d2;
+  }
   std::vector<float> fr32(fr64.begin(), fr64.end());
+  // optional terms in internal frame order: slide flags, drag per frame (the link's
+  // coefficient on the frame carrying its mass), contact points grouped by frame
+  std::vector<signed char> fkind;
+  std::vector<double> fdrag, cpt;
+  std::vector<int> coff;
+  if (any_slide) {
+    fkind.assign(nd, 0);
+    for (int fr = 0; fr < nd; ++fr) fkind[fr] = desc->dof_kind[uidx[fr]] == ABD_DOF_SLIDE ? 1 : 0;
+  }
+  if (any_drag) {
+    fdrag.assign(nd, 0.0);
+    for (int fr = 0; fr < nd; ++fr)
+      if (pose_link[fr] >= 0) fdrag[fr] = desc->drag[pose_link[fr]];
+  }
+  if (nc > 0) {
+    std::vector<int> frame_of_link(nl, 0);
+    for (int fr = 0; fr < nd; ++fr)
+      if (pose_link[fr] >= 0) frame_of_link[pose_link[fr]] = fr;
+    coff.assign(nd + 1, 0);
+    for (int c = 0; c < nc; ++c) coff[frame_of_link[desc->contact_link[c]] + 1]++;
+    for (int fr = 0; fr < nd; ++fr) coff[fr + 1] += coff[fr];
+    std::vector<int> fill(nd, 0);
+    cpt.assign(3 * (size_t)nc, 0.0);
+    for (int c = 0; c < nc; ++c) {
+      const int fr = frame_of_link[desc->contact_link[c]], at = coff[fr] + fill[fr]++;
+      for (int k = 0; k < 3; ++k) cpt[3 * (size_t)at + k] = desc->contact_point[3 * (size_t)c + k];
+    }
+  }
   int rc = ABD_OK;
   if ((rc = upload(m, &m->f0, f0)) || (rc = upload(m, &m->order, order)) ||
       (rc = upload(m, &m->pose_link, pose_link)) ||
@@ -329,7 +399,11 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
       (rc = upload(m, &m->hoff, hoff)) || (rc = upload(m, &m->uidx, uidx)) ||
       (rc = upload(m, &m->fpar, fpar)) || (rc = upload(m, &m->fend, fend)) ||
       (rc = alloc(m, &m->hist, max_frames > kMaxFrames ? 2 * kMaxHist * (size_t)nd : 1)) ||
-      (rc = alloc(m, &m->hinv, (size_t)hoff[nm]))) {
+      (rc = alloc(m, &m->hinv, (size_t)hoff[nm])) ||
+      (any_slide && (rc = upload(m, &m->fkind, fkind))) || (any_drag && (rc = upload(m, &m->fdrag, fdrag))) ||
+      (nc > 0 && ((rc = upload(m, &m->coff, coff)) || (rc = upload(m, &m->cpt, cpt)))) ||
+      ((any_drag || nc > 0) &&
+       ((rc = alloc(m, &m->Ak64, 12 * (size_t)nd)) || (rc = alloc(m, &m->Ak32, 12 * (size_t)nd))))) {
     free_model(m);
     delete m;
     return rc;
@@ -375,6 +449,7 @@ int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const d
   if (q_out < q_hist + 2 * (size_t)m->n_dofs && q_hist < q_out + out_len)
     return fail(ABD_EINVAL, "q_out overlaps q_hist");
   if ((rc = check_device(m))) return rc;
+  if (m->fx && (o->order_K > 2 || o->solver == ABD_SOLVER_LM)) return fail(ABD_ENOTSUP, "models with slides, drag or contact points take order_K = 2 with ABD_SOLVER_LBFGS in this build");
   if (o->order_K > 2 && o->solver == ABD_SOLVER_LM)
     return abd_impl::launch_lm_hoc(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
   if (o->order_K > 2) return abd_impl::launch_hoc(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
@@ -389,6 +464,7 @@ int abd_rollout(abd_model* m, const abd_step_opts* o, const double* q_init, cons
   int rc = check_rollout_args(m, o, q_init, q_traj, n_steps);
   if (rc || m->n_models == 0 || n_steps == 0) return rc;
   const size_t nd = m->n_dofs;
+  if (m->fx && (o->order_K > 2 || o->solver == ABD_SOLVER_LM)) return fail(ABD_ENOTSUP, "models with slides, drag or contact points take order_K = 2 with ABD_SOLVER_LBFGS in this build");
   if (o->order_K > 2 && o->solver == ABD_SOLVER_LM)
     return abd_impl::launch_lm_hoc(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
   if (o->order_K > 2) return abd_impl::launch_hoc(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
@@ -405,6 +481,9 @@ int abd_rollout_noalloc(abd_model* m, const abd_step_opts* o, const double* q_in
   if (o->order_K > 2 && (rc = abd_impl::check_hoc(m, o))) return rc;
   if (o->solver == ABD_SOLVER_LM)
     return fail(ABD_ENOTSUP, "abd_rollout_noalloc: ABD_SOLVER_LM keeps dense per-model matrices (use abd_rollout)");
+  if (m->fx)
+    return fail(ABD_ENOTSUP, "abd_rollout_noalloc: models with slides, drag or contact points keep per-step "
+                             "poses in model memory (use abd_rollout)");
   // carve the step scratch out of this device's static array
   unsigned char* base = nullptr;
   if ((rc = scratch_base(m->device, &base))) return rc;
@@ -454,6 +533,8 @@ int abd_objective_grad(abd_model* m, const abd_step_opts* o, const double* q, co
   if ((rc = check_device(m))) return rc;
   if (o->order_K < 2) return fail(ABD_EINVAL, "order_K must be >= 2");
   if (o->order_K > 4) return fail(ABD_ENOTSUP, "order_K > 4 is not handled by this build");
+  if (m->fx && o->order_K > 2)
+    return fail(ABD_ENOTSUP, "slides, drag and contact points enter the order-2 objective (Eq. EQ) only");
   if (o->order_K > 2) return abd_impl::launch_hoc_objective(m, o, q, q_hist, tau, E, grad, grad_tau, stream);
   return abd_impl::launch_objective(m, o, q, q_hist, tau, E, grad, grad_tau, stream);
 }
@@ -466,8 +547,9 @@ int abd_hvp(abd_model* m, const abd_step_opts* o, const double* q, const double*
   if (rc) return rc;
   if (m->n_models == 0) return ABD_OK;
   if (!q || !q_hist || !v || !Hv) return fail(ABD_EINVAL, "q, q_hist, v and Hv must not be NULL");
-  if (m->max_frames > kMaxFrames || m->tree)
-    return fail(ABD_ENOTSUP, "abd_hvp handles serial chains of at most 64 DOFs in this build");
+  if (m->max_frames > kMaxFrames || m->tree || m->fx)
+    return fail(ABD_ENOTSUP, "abd_hvp handles serial hinge chains of at most 64 DOFs without drag or contact "
+                             "points in this build");
   if ((rc = check_device(m))) return rc;
   return abd_impl::launch_hvp(m, o, q, q_hist, v, Hv, stream);
 }
@@ -480,6 +562,7 @@ int abd_hessian(abd_model* m, const abd_step_opts* o, const double* q, const dou
   if (rc) return rc;
   if (m->n_models == 0) return ABD_OK;
   if (!q || !q_hist || !H) return fail(ABD_EINVAL, "q, q_hist and H must not be NULL");
+  if (m->fx) return fail(ABD_ENOTSUP, "abd_hessian handles models without slides, drag or contact points");
   if ((rc = check_device(m))) return rc;
   return abd_impl::launch_hessian(m, o, q, q_hist, H, stream);
 }
@@ -499,8 +582,9 @@ int abd_rollout_vjp(abd_model* m, const abd_step_opts* o, const double* q_init, 
   if (m->n_models == 0) return ABD_OK;
   if (!q_init || !q_traj || !dL_dq_traj || !dL_dq_init)
     return fail(ABD_EINVAL, "q_init, q_traj, dL_dq_traj and dL_dq_init must not be NULL");
-  if (m->max_frames > kMaxFrames || m->tree)
-    return fail(ABD_ENOTSUP, "abd_rollout_vjp handles serial chains of at most 64 DOFs in this build");
+  if (m->max_frames > kMaxFrames || m->tree || m->fx)
+    return fail(ABD_ENOTSUP, "abd_rollout_vjp handles serial hinge chains of at most 64 DOFs without drag or "
+                             "contact points in this build");
   if ((rc = check_device(m))) return rc;
   return abd_impl::launch_rollout_vjp(m, o, q_init, q_traj, dL_dq_traj, dL_dq_init, dL_dtau, stats, n_steps,
                                       stream);

@@ -17,7 +17,7 @@ struct EvalArgs {
   double* grad_tau;
 };
 
-template <int NW, bool TREE>
+template <int NW, bool TREE, bool FX = false>
 __global__ void __launch_bounds__(NW* kWave) k_objective_grad(EvalArgs a) {
   __shared__ ScanLds<NW, TREE> L;
   const DevModel& d = a.d;
@@ -32,20 +32,20 @@ __global__ void __launch_bounds__(NW* kWave) k_objective_grad(EvalArgs a) {
   typename ModelScan<NW, TREE>::type sc = ModelScan<NW, TREE>::make(L, d, j / kWave, j % kWave, j, f, valid);
   const int io = TREE ? (valid ? d.uidx[f] : 0) : f;
   const double qkm1 = valid ? a.q_prev[io] : 0.0, qk = valid ? a.q_curr[io] : 0.0;
-  const FrameGeo geo = load_geo(d, f, valid);
-  write_B(sc, d, geo, f, valid, qkm1, qk);
-  // the B rows of this thread were written by this thread: no barrier needed
+  const FrameGeo geo = load_geo<FX>(d, f, valid);
+  write_B<FX>(sc, d, geo, f, valid, qkm1, qk);
+  // the B (and A(q_k)) rows of this thread were written by this thread: no barrier needed
   const double q = valid ? a.q[io] : 0.0;
   const double tau = (valid && a.tau) ? a.tau[io] : 0.0;
-  const EvalResult r = a.precision == ABD_MIXED ? evaluate<float>(sc, d, geo, f, valid, q, tau, a.dt2)
-                                                : evaluate<double>(sc, d, geo, f, valid, q, tau, a.dt2);
+  const EvalResult r = a.precision == ABD_MIXED ? evaluate<float, FX>(sc, d, geo, f, valid, q, tau, a.dt2)
+                                                : evaluate<double, FX>(sc, d, geo, f, valid, q, tau, a.dt2);
   if (j == 0) a.E[model] = r.E;
   if (a.grad && valid) a.grad[io] = r.g;
   // E contains -dt^2 tau.q
   if (a.grad_tau && valid) a.grad_tau[io] = -a.dt2 * q;
 }
 
-template <int NW, bool TREE>
+template <int NW, bool TREE, bool FX = false>
 __global__ void __launch_bounds__(NW* kWave) k_poses(DevModel d, const double* q, double* poses) {
   __shared__ ScanLds<NW, TREE> L;
   const int model = blockIdx.x, j = threadIdx.x;
@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(NW* kWave) k_poses(DevModel d, const double* q
   const int f = f0 + (valid ? j : 0);
   typename ModelScan<NW, TREE>::type sc = ModelScan<NW, TREE>::make(L, d, j / kWave, j % kWave, j, f, valid);
   const int io = TREE ? (valid ? d.uidx[f] : 0) : f;
-  const Xf<double> A = fk_geo<double>(sc, load_geo(d, f, valid), valid, valid ? q[io] : 0.0);
+  const Xf<double> A = fk_geo<double, FX>(sc, load_geo<FX>(d, f, valid), valid, valid ? q[io] : 0.0);
   if (valid) {
     const int l = d.pose_link[f];
     if (l >= 0)
@@ -84,7 +84,17 @@ int launch_objective(abd_model* m, const abd_step_opts* o, const double* q, cons
   const int nw = waves_for(m->max_frames);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 grid(m->n_models), block(nw * kWave);
-  if (m->tree) {
+  if (m->fx) {  // at most 256 frames per model
+    if (m->tree) {
+      if (nw == 1) hipLaunchKernelGGL((k_objective_grad<1, true, true>), grid, block, 0, s, a);
+      else if (nw == 2) hipLaunchKernelGGL((k_objective_grad<2, true, true>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_objective_grad<4, true, true>), grid, block, 0, s, a);
+    } else {
+      if (nw == 1) hipLaunchKernelGGL((k_objective_grad<1, false, true>), grid, block, 0, s, a);
+      else if (nw == 2) hipLaunchKernelGGL((k_objective_grad<2, false, true>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_objective_grad<4, false, true>), grid, block, 0, s, a);
+    }
+  } else if (m->tree) {
     switch (nw) {
       case 1: hipLaunchKernelGGL((k_objective_grad<1, true>), grid, block, 0, s, a); break;
       case 2: hipLaunchKernelGGL((k_objective_grad<2, true>), grid, block, 0, s, a); break;
@@ -108,7 +118,17 @@ int launch_poses(abd_model* m, const double* q, double* poses, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const dim3 grid(m->n_models), block(nw * kWave);
   const DevModel d = dev_view(m);
-  if (m->tree) {
+  if (m->fx) {  // at most 256 frames per model
+    if (m->tree) {
+      if (nw == 1) hipLaunchKernelGGL((k_poses<1, true, true>), grid, block, 0, s, d, q, poses);
+      else if (nw == 2) hipLaunchKernelGGL((k_poses<2, true, true>), grid, block, 0, s, d, q, poses);
+      else hipLaunchKernelGGL((k_poses<4, true, true>), grid, block, 0, s, d, q, poses);
+    } else {
+      if (nw == 1) hipLaunchKernelGGL((k_poses<1, false, true>), grid, block, 0, s, d, q, poses);
+      else if (nw == 2) hipLaunchKernelGGL((k_poses<2, false, true>), grid, block, 0, s, d, q, poses);
+      else hipLaunchKernelGGL((k_poses<4, false, true>), grid, block, 0, s, d, q, poses);
+    }
+  } else if (m->tree) {
     switch (nw) {
       case 1: hipLaunchKernelGGL((k_poses<1, true>), grid, block, 0, s, d, q, poses); break;
       case 2: hipLaunchKernelGGL((k_poses<2, true>), grid, block, 0, s, d, q, poses); break;

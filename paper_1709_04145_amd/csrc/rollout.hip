@@ -3,7 +3,9 @@
 
 namespace {
 
-template <int NW, int PREC, bool TREE>
+// FX: models with slides, drag or contact points (the terms of Sec. 6's
+// applications; a separate instantiation, so that the others carry none of it)
+template <int NW, int PREC, bool TREE, bool FX = false>
 __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_rollout(StepArgs args) {
   __shared__ RollLds<NW, TREE> L;
   // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
@@ -38,7 +40,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   // one-wave chains: explicit inverse; otherwise inertias [nf][10] (then, for
   // branched models, the recursion's accumulators [nf][21])
   double* Hi = d.hinv + d.hoff[model];
-  const FrameGeo geo = load_geo(d, f, valid);
+  const FrameGeo geo = load_geo<FX>(d, f, valid);
   const double eps_w = PREC == ABD_MIXED ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
   const double c1 = 1e-4, dlt = 0.1;
 
@@ -127,11 +129,11 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         flag = ABD_FLAG_CONVERGED;
         step_done = true;
       } else {
-        step_setup(sc, d, inert, L.tab[j], geo, f, valid, qkm1, qk, q, use_aba);
+        step_setup<FX>(sc, d, inert, L.tab[j], geo, f, valid, qkm1, qk, q, use_aba);
         if (use_aba) factor_precond();
         PROF_ADD(0, t_s);
-        const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float>(sc, d, geo, f, valid, q, tau, args.dt2)
-                                                  : evaluate<double>(sc, d, geo, f, valid, q, tau, args.dt2);
+        const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float, FX>(sc, d, geo, f, valid, q, tau, args.dt2)
+                                                  : evaluate<double, FX>(sc, d, geo, f, valid, q, tau, args.dt2);
         ++evals;
         if (PREC == ABD_MIXED) ++f32_evals;
         E = r.E;
@@ -160,7 +162,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         // the preconditioner at q and restart the curvature history
         refreshed = iters;
         PROF_T(t_f);
-        precond_frame(sc, d, inert, L.tab[j], geo, f, valid, q);
+        precond_frame<FX>(sc, d, inert, L.tab[j], geo, f, valid, q);
         factor_precond();
         count = 0;
         head = 0;
@@ -176,7 +178,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         // or where float32 converged, met its rounding or stalled the search)
         to64 = false;
         f32 = false;
-        const EvalResult r = evaluate<double>(sc, d, geo, f, valid, q, tau, args.dt2);
+        const EvalResult r = evaluate<double, FX>(sc, d, geo, f, valid, q, tau, args.dt2);
         ++evals;
         E = r.E;
         g = r.g;
@@ -280,10 +282,10 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
             EvalResult rt;
             PROF_T(t_e);
             if (PREC == ABD_MIXED && f32) {
-              rt = evaluate<float>(sc, d, geo, f, valid, x, tau, args.dt2);
+              rt = evaluate<float, FX>(sc, d, geo, f, valid, x, tau, args.dt2);
               ++f32_evals;
             } else {
-              rt = evaluate<double>(sc, d, geo, f, valid, x, tau, args.dt2);
+              rt = evaluate<double, FX>(sc, d, geo, f, valid, x, tau, args.dt2);
             }
             PROF_ADD(6, t_e);
   #ifdef ABD_PROFILE
@@ -433,7 +435,24 @@ int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, c
     else                                                                                    \
       hipLaunchKernelGGL((k_rollout<NW, ABD_MIXED, TREE>), grid, block, pair_bytes, s, a);  \
   } while (0)
-  if (m->tree) {
+#define ABD_LAUNCH_FX(NW, TREE)                                                                   \
+  do {                                                                                            \
+    if (f64)                                                                                      \
+      hipLaunchKernelGGL((k_rollout<NW, ABD_FP64, TREE, true>), grid, block, pair_bytes, s, a);   \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_rollout<NW, ABD_MIXED, TREE, true>), grid, block, pair_bytes, s, a);  \
+  } while (0)
+  if (m->fx) {  // at most 256 frames per model (checked when the model is created)
+    if (m->tree) {
+      if (nw == 1) ABD_LAUNCH_FX(1, true);
+      else if (nw == 2) ABD_LAUNCH_FX(2, true);
+      else ABD_LAUNCH_FX(4, true);
+    } else {
+      if (nw == 1) ABD_LAUNCH_FX(1, false);
+      else if (nw == 2) ABD_LAUNCH_FX(2, false);
+      else ABD_LAUNCH_FX(4, false);
+    }
+  } else if (m->tree) {
     switch (nw) {
       case 1: ABD_LAUNCH(1, true); break;
       case 2: ABD_LAUNCH(2, true); break;
@@ -449,6 +468,7 @@ int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, c
     }
   }
 #undef ABD_LAUNCH
+#undef ABD_LAUNCH_FX
   HIP_TRY(hipGetLastError());
   return ABD_OK;
 }

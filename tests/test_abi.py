@@ -63,7 +63,7 @@ def _create(lib, d):
     (lambda d: d.mass_moment.__setitem__((1, 9), 0.0), "mass"),
     (lambda d: d.mass_moment.__setitem__((0, 0), -5.0), "PSD"),
     (lambda d: d.parent.__setitem__(1, 3), "precede"),
-    (lambda d: d.dofs_per_link.__setitem__(0, 4), "dofs_per_link"),
+    (lambda d: d.dofs_per_link.__setitem__(0, 7), "dofs_per_link"),
     (lambda d: d.offset.__setitem__((2, 1), np.nan), "offset"),
 ])
 def test_invalid_descriptions_are_rejected_on_the_host(lib, mutate, needle):
@@ -71,6 +71,33 @@ def test_invalid_descriptions_are_rejected_on_the_host(lib, mutate, needle):
     mutate(d)
     rc, msg = _create(lib, d)
     assert rc == abd.ABD_EINVAL
+    assert needle in msg
+
+
+def _create_extras(lib, d):
+    """abd_create_model through the binding's own marshalling of the optional terms."""
+    try:
+        abd.Model(d)
+    except abd.AbdError as e:
+        return e.code, str(e)
+    return abd.ABD_OK, ""
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda d: d.dof_kind.__setitem__(0, 2), "dof_kind"),
+    (lambda d: d.drag.__setitem__(0, -1.0), "drag"),
+    (lambda d: d.drag.__setitem__(0, np.inf), "drag"),
+    (lambda d: d.contact_link.__setitem__(0, 10 ** 6), "contact_link"),
+    (lambda d: d.contact_point.__setitem__((0, 1), np.nan), "contact_point"),
+    (lambda d: setattr(d, "contact_plane", np.array([0.0, 0.0, 2.0, 0.0])), "contact_plane"),
+    (lambda d: setattr(d, "contact_d2", -1.0), "contact_d1 and contact_d2"),
+])
+def test_invalid_optional_terms_are_rejected_on_the_host(lib, mutate, needle):
+    d = W.random_extras_models(3, 171)
+    assert d.dof_kind is not None and d.drag is not None and d.n_contacts > 0
+    mutate(d)
+    rc, msg = _create_extras(lib, d)
+    assert rc == abd.ABD_EINVAL, msg
     assert needle in msg
 
 
