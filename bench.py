@@ -120,6 +120,8 @@ def parse():
                          "Eq. EQHOC), L-BFGS otherwise; lm at order 2 runs float64 only")
     ap.add_argument("--order", type=int, default=0,
                     help="collocation order K instead of the configuration's (0: the configuration's)")
+    ap.add_argument("--schedule", choices=("auto", "wave", "tile"), default="auto",
+                    help="how models map onto wavefronts (auto: the library's autotuner)")
     ap.add_argument("--dt", type=float, default=0.0, help="time step instead of the configuration's (0: the "
                                                              "configuration's)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 run")
@@ -239,8 +241,9 @@ def main():
     K = args.order if args.order > 0 else wl.step.order_K
     solver = {"lbfgs": abd.SOLVER_LBFGS, "lm": abd.SOLVER_LM}.get(args.solver,
                                                                   abd.SOLVER_LM if K == 3 else abd.SOLVER_LBFGS)
+    schedule = {"auto": abd.SCHEDULE_AUTO, "wave": abd.SCHEDULE_WAVE, "tile": abd.SCHEDULE_TILE}[args.schedule]
     base = dict(dt=wl.step.dt, lbfgs_m=wl.step.lbfgs_m, tol=wl.step.tol, max_iter=wl.step.max_iter, order_K=K,
-                solver=solver)
+                solver=solver, schedule=schedule)
     runs = {}
     lm = solver == abd.SOLVER_LM
     for name, prec in (("mixed", abd.MIXED), ("fp64", abd.FP64)):
@@ -283,6 +286,7 @@ def main():
                    "tol": wl.step.tol,
                    "solver": "levenberg-marquardt" if solver == abd.SOLVER_LM else "l-bfgs",
                    "precond": "joint-space inertia" if solver == abd.SOLVER_LBFGS else None,
+                   "schedule": args.schedule,
                    "launch": "one rollout per K steps"},
         "iterations_per_step": mixed["iters_mean"],
         "iterations_per_step_max": mixed["iters_max"],

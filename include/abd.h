@@ -53,11 +53,22 @@ extern "C" {
                              directions only, not the converged solution) */
 
 /* schedules (abd_step_opts.schedule): how models are mapped onto the GPU */
-#define ABD_SCHEDULE_AUTO 0 /* the library picks (currently ABD_SCHEDULE_WAVE) */
+#define ABD_SCHEDULE_AUTO 0 /* the library picks: for the order-2 L-BFGS step of a
+                               batch of serial chains of at most 32 DOFs, the faster
+                               of WAVE and TILE, timed on the first (up to 8) steps of
+                               the model handle's first call at each precision (that call
+                               then synchronizes its stream once; under graph capture,
+                               and in abd_rollout_noalloc before a first timed call,
+                               WAVE is taken); otherwise WAVE */
 #define ABD_SCHEDULE_WAVE 1 /* one model per workgroup of the fewest wavefronts (64
                                frames each) that hold the batch's longest model,
                                models dispatched longest first (Sec. 5 "GPU
                                Parallelization": one workgroup per trajectory) */
+#define ABD_SCHEDULE_TILE 2 /* serial chains of at most 32 DOFs packed 4 (<= 16 DOFs)
+                               or 2 per wavefront, each model in its own lanes and
+                               branching on its own; other batches: ABD_ENOTSUP.
+                               Every schedule gives the same results, bit for bit;
+                               solvers other than order-2 L-BFGS ignore the choice. */
 
 /* optimizers (abd_step_opts.solver), Sec. 5 "Optimization Algorithm" */
 #define ABD_SOLVER_LBFGS 0  /* L-BFGS (two-loop recursion) with a backtracking line search */

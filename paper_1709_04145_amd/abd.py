@@ -24,7 +24,7 @@ PRECOND_IDENTITY, PRECOND_INERTIA = 0, 2
 # preconditioner at the current iterate
 REFRESH = 10
 FLAG_CONVERGED, FLAG_LS_FLOOR, FLAG_MAX_ITER, FLAG_NONFINITE = 1, 2, 4, 8
-SCHEDULE_AUTO, SCHEDULE_WAVE = 0, 1
+SCHEDULE_AUTO, SCHEDULE_WAVE, SCHEDULE_TILE = 0, 1, 2
 SOLVER_LBFGS, SOLVER_LM = 0, 1
 
 

@@ -110,6 +110,8 @@ __device__ __forceinline__ double uniform(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+__device__ __forceinline__ double wave_uniform(double v) { return uniform(v); }
+
 // Inclusive prefix sum over the 64 lanes (row shifts 1,2,4,8, then the
 // row-15 and row-31 broadcasts).  Every lane ends with its inclusive prefix.
 __device__ __forceinline__ double wave_prefix_sum(double v) {
@@ -459,7 +461,79 @@ struct WaveScan {
   __device__ __forceinline__ double sum(double v) { return wave_sum(v); }
   __device__ __forceinline__ void sum2(double& a, double& b) { wave_sum2(a, b); }
   __device__ __forceinline__ bool all_finite(double x) { return !__any(!isfinite(x)); }
-    __device__ __forceinline__ void sync() {}
+  __device__ __forceinline__ void sync() {}
+  // a model-uniform value kept in scalar registers
+  __device__ __forceinline__ double uniform(double v) { return wave_uniform(v); }
+};
+
+// Models packed S lanes apart in one wavefront (S = 16: one DPP row per model,
+// S = 32: two rows), frame j of the model in lane j of its segment.  The scans
+// are the wave scans without the steps that cross a segment (S = 16: no row
+// broadcasts; S = 32: the row-15 broadcast into rows 1 and 3 only), the totals
+// are read from the segment's last lane, and nothing is made wave-uniform: the
+// models of a wavefront branch independently.  Lanes past a model's last frame
+// hold identities and zeros exactly as in the wave scans, so every sum and
+// product takes the same operands in the same order as there (a model gets the
+// same results in either layout).
+template <int S>
+struct SegScan {
+  static_assert(S == 16 || S == 32, "segments of one or two DPP rows");
+  int fl;  // lane within the segment
+  template <typename R>
+  __device__ __forceinline__ Quat<R> prefix_quat(Quat<R> v) {
+    v = qmul(dpp_quat<R, 0x111, 0xF>(v), v);
+    v = qmul(dpp_quat<R, 0x112, 0xF>(v), v);
+    v = qmul(dpp_quat<R, 0x114, 0xF>(v), v);
+    v = qmul(dpp_quat<R, 0x118, 0xF>(v), v);
+    if (S == 32) v = qmul(dpp_quat<R, 0x142, 0xA>(v), v);
+    return v;
+  }
+  template <typename R>
+  __device__ __forceinline__ Quat<R> parent_quat(const Quat<R>& incl) {
+    const Quat<R> sh = dpp_quat<R, 0x138, 0xF>(incl);
+    return fl == 0 ? Quat<R>{R(1), R(0), R(0), R(0)} : sh;
+  }
+  template <typename R>
+  static __device__ __forceinline__ R prefix(R v) {
+    v += dpp0<0x111>(v);
+    v += dpp0<0x112>(v);
+    v += dpp0<0x114>(v);
+    v += dpp0<0x118>(v);
+    if (S == 32) v += dpp<0x142, 0xA>(R(0), v);
+    return v;
+  }
+  static __device__ __forceinline__ double last(double v) { return __shfl(v, S - 1, S); }
+  template <typename R>
+  __device__ __forceinline__ void prefix_sum3(R v[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = prefix(v[k]);
+  }
+  __device__ __forceinline__ void suffix6_total2(double v[6], double& a, double& b) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double pre = prefix(v[k]);
+      v[k] = (last(pre) - pre) + v[k];
+    }
+    sum2(a, b);
+  }
+  __device__ __forceinline__ double suffix(double v) {
+    const double pre = prefix(v);
+    return (last(pre) - pre) + v;
+  }
+  __device__ __forceinline__ double sum(double v) { return last(prefix(v)); }
+  __device__ __forceinline__ void sum2(double& a, double& b) {
+    a = prefix(a);
+    b = prefix(b);
+    a = last(a);
+    b = last(b);
+  }
+  __device__ __forceinline__ bool all_finite(double x) {
+    const unsigned long long bad = __ballot(!isfinite(x));
+    const int base = (int)(threadIdx.x % kWave) - fl;
+    return ((bad >> base) & ((1ull << S) - 1)) == 0;
+  }
+  __device__ __forceinline__ void sync() {}
+  __device__ __forceinline__ double uniform(double v) { return v; }
 };
 
 template <int NW>
@@ -474,6 +548,7 @@ struct BlockScan {
     return a;
   }
   __device__ __forceinline__ void sync() { __syncthreads(); }
+  __device__ __forceinline__ double uniform(double v) { return wave_uniform(v); }
 
   template <typename R>
   __device__ __forceinline__ Quat<R> prefix_quat(const Quat<R>& v0) {
@@ -930,12 +1005,16 @@ struct StepArgs {
 //   xch:   scan exchange areas of BlockScan
 //   branched models (TREE): pointer-jumping buffers of TreeScan (tq, tv, tanc),
 //   frame parents (tpar) and the sweep accumulators (acc)
-template <int NW, bool TREE = false>
+// SEGS: models per wavefront (packed one-wave chains): the per-model scalars of
+// the two-loop recursion are kept per segment, and the vector of the inverse
+// product has its own area (vb) instead of the recursion's table.
+template <int NW, bool TREE = false, int SEGS = 1>
 struct RollLds {
   double tab[kMaxFrames * NW][kTab];
   double inert[(NW == 1 && TREE) ? kMaxFrames : 1][10];  // one-wave chains: in the inverse's LDS
-  double rho[kMaxHist];  // 1/(s_i.y_i): k_rollout by ring slot of the pair, others newest first
-  double alp[kMaxHist];  // two-loop coefficients
+  double rho[kMaxHist * SEGS];  // 1/(s_i.y_i): k_rollout by ring slot of the pair, others newest first
+  double alp[kMaxHist * SEGS];  // two-loop coefficients
+  double vb[SEGS > 1 ? kWave : 1];
   double xb[(NW == 1 && !TREE) ? 1 : kMaxFrames * NW];
   double xch[2][NW][8];
   double tq[TREE ? kMaxFrames * NW : 1][4];
@@ -966,8 +1045,10 @@ __device__ __forceinline__ double recip(double x) {
 // 10-entry record (J 00 01 02 11 12 22, h, m).  The whole wave runs; lanes >= 6
 // shadow row 5 and store nothing.  The next frame's inputs are read while the
 // current one is processed.
+template <int SEG = kWave>
 __device__ void aba_setup_rows(const double* inert, double (*tab)[kTab], int nf_in, int lane) {
-  const int nf = __builtin_amdgcn_readfirstlane(nf_in);  // wave-uniform frame loop
+  // wave-uniform frame loop (segments of packed models: each its own)
+  const int nf = SEG == kWave ? __builtin_amdgcn_readfirstlane(nf_in) : nf_in;
   if (nf <= 0) return;
   const int r = lane < 6 ? lane : 5;
   int idx[6];
@@ -1014,7 +1095,7 @@ __device__ void aba_setup_rows(const double* inert, double (*tab)[kTab], int nf_
     const double U = (P[0] * s[0] + P[1] * s[1]) + (P[2] * s[2] + P[3] * s[3]) + (P[4] * s[4] + P[5] * s[5]);
     double Uc[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) Uc[c] = readlane(U, c);
+    for (int c = 0; c < 6; ++c) Uc[c] = SEG == kWave ? readlane(U, c) : __shfl(U, c, SEG);
     const double D = (s[0] * Uc[0] + s[1] * Uc[1]) + (s[2] * Uc[2] + s[3] * Uc[3]) + (s[4] * Uc[4] + s[5] * Uc[5]);
     const double iD = (D > 0.0) ? recip(D) : 0.0;
     if (lane < 6) tab[f][6 + lane] = U;
@@ -1042,9 +1123,15 @@ __device__ __forceinline__ int tri(int j) { return (j * (j + 1)) >> 1; }
 __host__ __device__ constexpr int inverse_lds_doubles(int nf) {
   return (nf * (nf + 1) / 2 > 10 * kMaxFrames) ? nf * (nf + 1) / 2 : 10 * kMaxFrames;
 }
+// The same area for one model of a wavefront packed with models of at most s
+// frames (the float32 full inverse, s^2 floats, fits in the triangle too).
+__host__ __device__ constexpr int tile_inverse_doubles(int s) {
+  return (s * (s + 1) / 2 > 10 * s) ? s * (s + 1) / 2 : 10 * s;
+}
 
+template <int SEG = kWave>
 __device__ void aba_inverse(const double (*tab)[kTab], int nf_in, int lane, double* P) {
-  const int nf = __builtin_amdgcn_readfirstlane(nf_in);  // wave-uniform frame loops
+  const int nf = SEG == kWave ? __builtin_amdgcn_readfirstlane(nf_in) : nf_in;  // wave-uniform frame loops
   const bool act = lane < nf;
   const int col = act ? lane : nf - 1;
   const int base = tri(col);  // lanes without a frame address the last column (in bounds, never stored)
@@ -1095,8 +1182,9 @@ __device__ void aba_inverse(const double (*tab)[kTab], int nf_in, int lane, doub
 // wave per workgroup.
 constexpr int kMvBatch = 8;
 
+template <int SEG = kWave>
 __device__ __forceinline__ double apply_inverse(const double* P, double* vb, int nf_in, int lane, double v) {
-  const int nf = __builtin_amdgcn_readfirstlane(nf_in);
+  const int nf = SEG == kWave ? __builtin_amdgcn_readfirstlane(nf_in) : nf_in;
   const bool act = lane < nf;
   const int col = act ? lane : nf - 1;
   const int base = tri(col);
@@ -1141,8 +1229,9 @@ __device__ __forceinline__ double apply_inverse(const double* P, double* vb, int
 // preconditioner, and they keep the packed float64 inverse.
 constexpr float kInv32MaxRatio = 1e5f;
 
+template <int SEG = kWave>
 __device__ void aba_inverse_f32(const double (*tab)[kTab], int nf_in, int lane, float* F) {
-  const int nf = __builtin_amdgcn_readfirstlane(nf_in);
+  const int nf = SEG == kWave ? __builtin_amdgcn_readfirstlane(nf_in) : nf_in;
   const bool act = lane < nf;
   const int col = act ? lane : nf - 1;
   double t[kTab], tn[kTab];
@@ -1186,8 +1275,9 @@ __device__ void aba_inverse_f32(const double (*tab)[kTab], int nf_in, int lane, 
 // is read back as broadcasts, products and sums in float32.  Rows past the last
 // (the batch tail) re-read the last row with weight zero.  One wave per
 // workgroup.
+template <int SEG = kWave>
 __device__ __forceinline__ double apply_inverse_f32(const float* F, float* vb, int nf_in, int lane, double v) {
-  const int nf = __builtin_amdgcn_readfirstlane(nf_in);
+  const int nf = SEG == kWave ? __builtin_amdgcn_readfirstlane(nf_in) : nf_in;
   const bool act = lane < nf;
   const float* Fc = F + (act ? lane : nf - 1);
   vb[lane] = act ? (float)v : 0.0f;

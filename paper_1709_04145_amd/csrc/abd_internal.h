@@ -46,6 +46,11 @@ struct abd_model {
   float* Ak32 = nullptr;
   double plane[4] = {0, 0, 1, 0};
   double cd1 = 0.0, cd2 = 0.0;
+  // ABD_SCHEDULE_AUTO: the schedule the autotuner chose per precision (FP64,
+  // MIXED): -1 not yet timed, 0 WAVE, 16 or 32 TILE; its scratch trajectory
+  int tile_choice[2] = {-1, -1};
+  double* tune_buf = nullptr;
+  size_t tune_len = 0;
   std::vector<void*> allocs;
 };
 

@@ -116,8 +116,8 @@ int check_opts(const abd_step_opts* o, bool for_step) {
   if (o->precond != ABD_PRECOND_IDENTITY && o->precond != ABD_PRECOND_INERTIA)
     return fail(ABD_EINVAL, "precond must be ABD_PRECOND_IDENTITY or ABD_PRECOND_INERTIA");
   if (o->refresh < 0) return fail(ABD_EINVAL, "refresh must be >= 0");
-  if (o->schedule != ABD_SCHEDULE_AUTO && o->schedule != ABD_SCHEDULE_WAVE)
-    return fail(ABD_EINVAL, "schedule must be ABD_SCHEDULE_AUTO or ABD_SCHEDULE_WAVE");
+  if (o->schedule != ABD_SCHEDULE_AUTO && o->schedule != ABD_SCHEDULE_WAVE && o->schedule != ABD_SCHEDULE_TILE)
+    return fail(ABD_EINVAL, "schedule must be ABD_SCHEDULE_AUTO, ABD_SCHEDULE_WAVE or ABD_SCHEDULE_TILE");
   if (o->solver != ABD_SOLVER_LBFGS && o->solver != ABD_SOLVER_LM)
     return fail(ABD_EINVAL, "solver must be ABD_SOLVER_LBFGS or ABD_SOLVER_LM");
 

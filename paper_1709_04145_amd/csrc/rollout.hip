@@ -4,24 +4,36 @@
 namespace {
 
 // FX: models with slides, drag or contact points (the terms of Sec. 6's
-// applications; a separate instantiation, so that the others carry none of it)
-template <int NW, int PREC, bool TREE, bool FX = false>
+// applications; a separate instantiation, so that the others carry none of it).
+// SEG < 64: one-wave chains packed kWave / SEG per wavefront, model b of the
+// dispatch order in segment b % (kWave / SEG) of workgroup b / (kWave / SEG);
+// each segment runs its model's steps on its own (the segments branch apart).
+template <int NW, int PREC, bool TREE, bool FX = false, int SEG = kWave>
 __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_rollout(StepArgs args) {
-  __shared__ RollLds<NW, TREE> L;
+  static_assert(SEG == kWave || (NW == 1 && !TREE), "packed models are one-wave chains");
+  constexpr int SEGS = kWave / SEG;  // models per wavefront
+  __shared__ RollLds<NW, TREE, SEGS> L;
   // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
   // y in [m, 2m), one double per lane per slot; one-wave chains: then the
   // explicit inverse (inverse_lds_doubles(max frames); packed float64, or the
-  // full float32 matrix for MIXED)
+  // full float32 matrix for MIXED), per segment of packed models
+  // tile_inverse_doubles(SEG) each
   extern __shared__ double pairs[];
-  double* const hl = pairs + 2 * args.m * kWave;
   const DevModel& d = args.d;
   const int n = d.n_dofs;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int j = threadIdx.x;  // frame of this thread within the model
-  const bool lead = threadIdx.x == 0;
-  const bool has_model = blockIdx.x < d.n_models;
+  const int seg = SEGS > 1 ? lane / SEG : 0;
+  const int j = SEGS > 1 ? lane % SEG : (int)threadIdx.x;  // frame of this thread within its model
+  const int jl = SEGS > 1 ? j : lane;                       // its lane in the one-wave helpers
+  double* const hl = pairs + 2 * args.m * kWave + (SEGS > 1 ? seg * tile_inverse_doubles(SEG) : 0);
+  double* const rho = L.rho + seg * kMaxHist;
+  double* const alp = L.alp + seg * kMaxHist;
+  double (*const tab)[kTab] = L.tab + seg * SEG;
+  const bool lead = j == 0;
+  const int mslot = blockIdx.x * SEGS + seg;
+  const bool has_model = mslot < d.n_models;
   if (!has_model) return;
-  const int model = d.order[blockIdx.x];
+  const int model = d.order[mslot];
   const int f0 = d.f0[model];
   const int nf = d.f0[model + 1] - f0;
   if (nf == 0) {  // a model without frames: every step is trivially converged
@@ -34,7 +46,10 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   }
   const bool valid = j < nf;
   const int f = f0 + (valid ? j : 0);  // invalid lanes alias frame 0 of the model (loads stay in bounds)
-  typename ModelScan<NW, TREE>::type sc = ModelScan<NW, TREE>::make(L, d, wave, lane, j, f, valid);
+  auto sc = [&]() {
+    if constexpr (SEGS > 1) return SegScan<SEG>{j};
+    else return ModelScan<NW, TREE>::make(L, d, wave, lane, j, f, valid);
+  }();
   const int io = TREE ? (valid ? d.uidx[f] : 0) : f;  // index of this frame's DOF in the caller's vectors
   const bool use_aba = args.precond == ABD_PRECOND_INERTIA;
   // one-wave chains: explicit inverse; otherwise inertias [nf][10] (then, for
@@ -84,7 +99,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
     if (TREE) {
       if (lead) aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
     } else if (wave == 0) {
-      aba_setup_rows(NW == 1 ? hl : Hi, L.tab, nf, lane);
+      aba_setup_rows<SEG>(NW == 1 ? hl : Hi, tab, nf, jl);
     }
     __syncthreads();
     PROF_ADD(2, t_r);
@@ -92,19 +107,22 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
     if (NW == 1 && !TREE) {
       if (PREC == ABD_MIXED) {
         // float32 inverse only while the pivots D_f span at most kInv32MaxRatio
-        float lo = (float)L.tab[lane < nf ? lane : 0][12], hi = lo;  // 1/D_f
+        float lo = (float)tab[jl < nf ? jl : 0][12], hi = lo;  // 1/D_f
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
+        for (int o = SEG / 2; o > 0; o >>= 1) {
           lo = fminf(lo, __shfl_xor(lo, o));
           hi = fmaxf(hi, __shfl_xor(hi, o));
         }
-        inv32 = __builtin_amdgcn_readfirstlane((int)(hi <= kInv32MaxRatio * lo)) != 0;
+        if (SEGS > 1)
+          inv32 = hi <= kInv32MaxRatio * lo;
+        else
+          inv32 = __builtin_amdgcn_readfirstlane((int)(hi <= kInv32MaxRatio * lo)) != 0;
       }
       // overwrites the inertias
       if (inv32)
-        aba_inverse_f32(L.tab, nf, lane, reinterpret_cast<float*>(hl));
+        aba_inverse_f32<SEG>(tab, nf, jl, reinterpret_cast<float*>(hl));
       else
-        aba_inverse(L.tab, nf, lane, hl);
+        aba_inverse<SEG>(tab, nf, jl, hl);
       __syncthreads();  // every lane reads the other lanes' columns
     }
     PROF_ADD(3, t_i);
@@ -112,7 +130,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   // frames' inertias: lanes without a frame of a multi-wave model write their
   // (zero) record to a sink, never to frame 0's slot, which lane 0 fills
   __shared__ double inert_sink[10];
-  double* const inert = NW == 1 ? (TREE ? L.inert[lane] : hl + 10 * lane) : (valid ? Hi + (size_t)j * 10 : inert_sink);
+  double* const inert = NW == 1 ? (TREE ? L.inert[lane] : hl + 10 * jl) : (valid ? Hi + (size_t)j * 10 : inert_sink);
 
   while (state != kDone) {
     bool step_done = false;
@@ -129,7 +147,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         flag = ABD_FLAG_CONVERGED;
         step_done = true;
       } else {
-        step_setup<FX>(sc, d, inert, L.tab[j], geo, f, valid, qkm1, qk, q, use_aba);
+        step_setup<FX>(sc, d, inert, tab[j], geo, f, valid, qkm1, qk, q, use_aba);
         if (use_aba) factor_precond();
         PROF_ADD(0, t_s);
         const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float, FX>(sc, d, geo, f, valid, q, tau, args.dt2)
@@ -143,7 +161,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
           flag = ABD_FLAG_NONFINITE;
           step_done = true;
         } else {
-          g0 = uniform(sqrt(sc.sum(g * g)));
+          g0 = sc.uniform(sqrt(sc.sum(g * g)));
           gn = g0;
           if (g0 == 0.0) {
             flag = ABD_FLAG_CONVERGED;
@@ -162,7 +180,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         // the preconditioner at q and restart the curvature history
         refreshed = iters;
         PROF_T(t_f);
-        precond_frame<FX>(sc, d, inert, L.tab[j], geo, f, valid, q);
+        precond_frame<FX>(sc, d, inert, tab[j], geo, f, valid, q);
         factor_precond();
         count = 0;
         head = 0;
@@ -182,7 +200,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         ++evals;
         E = r.E;
         g = r.g;
-        gn = uniform(sqrt(sc.sum(g * g)));
+        gn = sc.uniform(sqrt(sc.sum(g * g)));
         if (gn <= args.tol * g0) {
           flag = ABD_FLAG_CONVERGED;
           step_done = true;
@@ -207,8 +225,8 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
             // the reduction (a barrier for several waves) before the LDS read of
             // rho, which the lead lane writes when the pair is accepted
             const double sq = sc.sum(sk * qv);
-            const double a_k = uniform(L.rho[(head - k + args.m) % args.m] * sq);
-            if (lead) L.alp[k] = a_k;
+            const double a_k = sc.uniform(rho[(head - k + args.m) % args.m] * sq);
+            if (lead) alp[k] = a_k;
             qv -= a_k * yk;
             sk = sn;
             yk = yn;
@@ -221,8 +239,11 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         } else if (NW == 1 && !TREE) {
           PROF_T(t_h);
           // the recursion's table is free between formations
-          r = inv32 ? apply_inverse_f32(reinterpret_cast<const float*>(hl), reinterpret_cast<float*>(&L.tab[0][0]), nf, lane, qv)
-                    : apply_inverse(hl, &L.tab[0][0], nf, lane, qv);
+          // the vector goes through the recursion's table, which is free between
+          // formations (packed models: through an area of its own per segment)
+          double* const vb = SEGS > 1 ? L.vb + seg * SEG : &L.tab[0][0];
+          r = inv32 ? apply_inverse_f32<SEG>(reinterpret_cast<const float*>(hl), reinterpret_cast<float*>(vb), nf, jl, qv)
+                    : apply_inverse<SEG>(hl, vb, nf, jl, qv);
           PROF_ADD(14, t_h);
         } else {
           L.xb[j] = valid ? qv : 0.0;
@@ -249,15 +270,15 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
             const double sn = ld_if(hs + nxt * hstride, valid && k > 0);
             const double yn = ld_if(hs + ys + nxt * hstride, valid && k > 0);
             const double yr = sc.sum(yk * r);
-            const double b = uniform(L.rho[slot] * yr);
-            r += (L.alp[k] - b) * sk;
+            const double b = sc.uniform(rho[slot] * yr);
+            r += (alp[k] - b) * sk;
             sk = sn;
             yk = yn;
             slot = nxt;
           }
         }
         const double dir = valid ? -r : 0.0;
-        const double gd = uniform(sc.sum(g * dir));
+        const double gd = sc.uniform(sc.sum(g * dir));
         PROF_ADD(12, t_l);
         if (!(gd < 0.0)) {
           if (!reset) {
@@ -315,7 +336,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
             }
             // an accepted trial point that equals q in every coordinate is no
             // progress: at this precision the iteration cannot move any more
-            if (uniform(sc.sum(valid && x != q ? 1.0 : 0.0)) == 0.0) {
+            if (sc.uniform(sc.sum(valid && x != q ? 1.0 : 0.0)) == 0.0) {
               if (PREC == ABD_MIXED && f32) {
                 to64 = true;
                 break;
@@ -332,9 +353,9 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
             sc.sum2(sy, ss);
             sc.sum2(yy, gg);
             if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
-              gam = uniform(sy / yy);
+              gam = sc.uniform(sy / yy);
               head = count == 0 ? 0 : (head + 1) % args.m;
-              if (lead) L.rho[head] = 1.0 / sy;  // rho lives in the ring slot of its pair
+              if (lead) rho[head] = 1.0 / sy;  // rho lives in the ring slot of its pair
               if (valid) {
                 hs[head * hstride] = sv;
                 hs[ys + head * hstride] = y;
@@ -346,7 +367,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
             E = rt.E;
             ++iters;
             if (PREC == ABD_MIXED && f32) ++f32_iters;
-            gn = uniform(sqrt(gg));
+            gn = sc.uniform(sqrt(gg));
             PROF_ADD(13, t_u);
             const bool conv = gn <= args.tol * g0;
             if (PREC == ABD_MIXED && f32 && (conv || noisy)) {
@@ -398,36 +419,44 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
 
 namespace abd_impl {
 
-int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
-                   const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream,
-                   const StepScratch* sc) {
-  StepArgs a;
-  a.d = dev_view(m);
-  if (sc) {
-    a.d.B64 = sc->B64;
-    a.d.B32 = sc->B32;
-    a.d.hist = sc->hist;
-    a.d.hinv = sc->hinv;
-  }
-  a.dt2 = o->dt * o->dt;
-  a.tol = o->tol;
-  a.m = o->lbfgs_m;
-  a.max_iter = o->max_iter;
-  a.max_ls = o->max_ls;
-  a.precond = o->precond;
-  a.refresh = o->refresh;
-  a.n_steps = n_steps;
-  a.q_prev = q_prev;
-  a.q_curr = q_curr;
-  a.tau = tau;
-  a.q_out = q_out;
-  a.stats = stats;
-  hipStream_t s = static_cast<hipStream_t>(stream);
+// Segment width of the packed (TILE) schedule for this batch: serial chains of
+// at most 16 or 32 DOFs; 0 where the batch cannot be packed.
+static int tile_segment(const abd_model* m) {
+  if (m->tree || m->max_frames <= 0 || m->max_frames > 32) return 0;
+  return m->max_frames <= 16 ? 16 : 32;
+}
+
+// One launch of the order-2 rollout: seg = 0 one model per workgroup (WAVE),
+// 16 or 32 packed models of that many lanes (TILE).
+static int dispatch_rollout(const abd_model* m, const abd_step_opts* o, const StepArgs& a, int seg,
+                            hipStream_t s) {
   const int nw = waves_for(m->max_frames);
+  const bool f64 = o->precision == ABD_FP64;
+  if (seg > 0) {
+    const int segs = kWave / seg;
+    const dim3 grid((m->n_models + segs - 1) / segs), block(kWave);
+    const size_t bytes = (2 * (size_t)o->lbfgs_m * kWave + (size_t)segs * tile_inverse_doubles(seg)) * sizeof(double);
+#define ABD_TILE(S, FXV)                                                                              \
+  do {                                                                                                \
+    if (f64)                                                                                          \
+      hipLaunchKernelGGL((k_rollout<1, ABD_FP64, false, FXV, S>), grid, block, bytes, s, a);         \
+    else                                                                                              \
+      hipLaunchKernelGGL((k_rollout<1, ABD_MIXED, false, FXV, S>), grid, block, bytes, s, a);        \
+  } while (0)
+    if (m->fx) {
+      if (seg == 16) ABD_TILE(16, true);
+      else ABD_TILE(32, true);
+    } else {
+      if (seg == 16) ABD_TILE(16, false);
+      else ABD_TILE(32, false);
+    }
+#undef ABD_TILE
+    HIP_TRY(hipGetLastError());
+    return ABD_OK;
+  }
   const dim3 grid(m->n_models), block(nw * kWave);
   size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * kWave * sizeof(double) : 0;
   if (nw == 1 && !m->tree) pair_bytes += (size_t)inverse_lds_doubles(m->max_frames) * sizeof(double);
-  const bool f64 = o->precision == ABD_FP64;
 #define ABD_LAUNCH(NW, TREE)                                                                \
   do {                                                                                      \
     if (f64)                                                                                \
@@ -471,6 +500,99 @@ int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, c
 #undef ABD_LAUNCH_FX
   HIP_TRY(hipGetLastError());
   return ABD_OK;
+}
+
+// The schedule autotuner: times the first steps (up to 8) of this very call
+// under WAVE and under TILE (each run three times, the best of the last two
+// counted, outputs into the model's scratch trajectory, no stats),
+// synchronizing the stream, and keeps the faster for the model handle and
+// precision.  Both schedules give the same bits, so the choice changes only the
+// time.
+static int autotune_schedule(abd_model* m, const abd_step_opts* o, const StepArgs& a, hipStream_t s, int& choice) {
+  const int T = a.n_steps < 8 ? a.n_steps : 8;
+  const size_t need = (size_t)T * m->n_dofs;
+  if (m->tune_len < need) {
+    void* p = nullptr;
+    int rc = model_alloc(m, &p, need * sizeof(double));
+    if (rc) return rc;
+    m->tune_buf = static_cast<double*>(p);
+    m->tune_len = need;
+  }
+  StepArgs t = a;
+  t.n_steps = T;
+  t.q_out = m->tune_buf;
+  t.stats = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ABD_EDEVICE, "hipEventCreate failed");
+  }
+  const int cands[2] = {0, tile_segment(m)};
+  float best_ms = 0.0f;
+  int best = 0, rc = ABD_OK;
+  for (int c = 0; c < 2 && rc == ABD_OK; ++c)
+    for (int rep = 0; rep < 3 && rc == ABD_OK; ++rep) {
+      float ms = 0.0f;
+      if (hipEventRecord(e0, s) != hipSuccess || (rc = dispatch_rollout(m, o, t, cands[c], s)) != ABD_OK ||
+          hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        if (rc == ABD_OK) rc = fail(ABD_EDEVICE, "timing the schedules failed");
+        break;
+      }
+      if (rep > 0 && ((c == 0 && rep == 1) || ms < best_ms)) {
+        best_ms = ms;
+        best = cands[c];
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == ABD_OK) choice = best;
+  return rc;
+}
+
+int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
+                   const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream,
+                   const StepScratch* sc) {
+  StepArgs a;
+  a.d = dev_view(m);
+  if (sc) {
+    a.d.B64 = sc->B64;
+    a.d.B32 = sc->B32;
+    a.d.hist = sc->hist;
+    a.d.hinv = sc->hinv;
+  }
+  a.dt2 = o->dt * o->dt;
+  a.tol = o->tol;
+  a.m = o->lbfgs_m;
+  a.max_iter = o->max_iter;
+  a.max_ls = o->max_ls;
+  a.precond = o->precond;
+  a.refresh = o->refresh;
+  a.n_steps = n_steps;
+  a.q_prev = q_prev;
+  a.q_curr = q_curr;
+  a.tau = tau;
+  a.q_out = q_out;
+  a.stats = stats;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int seg = 0;
+  if (o->schedule == ABD_SCHEDULE_TILE) {
+    seg = tile_segment(m);
+    if (!seg) return fail(ABD_ENOTSUP, "ABD_SCHEDULE_TILE packs serial chains of at most 32 DOFs");
+  } else if (o->schedule == ABD_SCHEDULE_AUTO && tile_segment(m)) {
+    int& choice = m->tile_choice[o->precision == ABD_MIXED ? 1 : 0];
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs));
+    // callers that cannot allocate or synchronize (a given scratch, graph
+    // capture) take the decision already made, else WAVE
+    if (choice < 0 && !sc && cs == hipStreamCaptureStatusNone) {
+      int rc = autotune_schedule(m, o, a, s, choice);
+      if (rc) return rc;
+    }
+    seg = choice > 0 ? choice : 0;
+  }
+  return dispatch_rollout(m, o, a, seg, s);
 }
 
 }  // namespace abd_impl

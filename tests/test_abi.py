@@ -138,7 +138,7 @@ def test_step_options_are_validated_before_the_device(lib, field, value, needle)
 
 def test_valid_schedules_pass_the_option_check(lib):
     """A valid option set reaches the next check (the NULL model)."""
-    for sched in (abd.SCHEDULE_AUTO, abd.SCHEDULE_WAVE):
+    for sched in (abd.SCHEDULE_AUTO, abd.SCHEDULE_WAVE, abd.SCHEDULE_TILE):
         oc = abd.StepOptions(dt=0.01, schedule=sched).c()
         assert lib.abd_step(None, C.byref(oc), None, None, None, None, None) == abd.ABD_EINVAL
         assert "model is NULL" in lib.abd_last_error().decode()
