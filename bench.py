@@ -249,8 +249,8 @@ def main():
     for name, prec in (("mixed", abd.MIXED), ("fp64", abd.FP64)):
         if name == "fp64" and args.no_fp64 and K == 2 and not lm:
             continue
-        if name == "mixed" and (K > 2 or lm):
-            continue  # order K > 2 and Levenberg-Marquardt run in float64 only
+        if name == "mixed" and lm:
+            continue  # Levenberg-Marquardt runs in float64 only
         opts = abd.StepOptions(precision=prec, **base)
         init, traj, st, wall, kms = timed_rollout(torch, model, wl.q0, opts, args.warmup, args.steps, wl.torque)
         nbytes, xbytes = algorithmic_bytes(desc, st)
@@ -297,7 +297,8 @@ def main():
                      "frac": mixed["achieved_gbs"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic(W.CONFIG_NAMES[args.config], "mixed" if "mixed" in runs else "fp64",
                                                  args.warmup, args.steps) if args.dt == 0.0 else None,
-                     "kernel": ("k_rollout<MIXED, extras>" if desc.has_extras else "k_rollout<MIXED>") if "mixed" in runs else
+                     "kernel": ("k_rollout_hoc<MIXED>" if K > 2 else "k_rollout<MIXED, extras>" if desc.has_extras
+                                else "k_rollout<MIXED>") if "mixed" in runs else
                      ("k_rollout_lm2" if lm and K == 2 else "k_rollout_lm" if lm else
                       "k_rollout<FP64>" if K == 2 else "k_rollout_hoc"),
                      "kernel_ms": mixed["kernel_ms"],

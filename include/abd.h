@@ -50,7 +50,13 @@ extern "C" {
                              for one-wave chains whose articulated pivots span at
                              most 1e5, the inertia preconditioner's explicit
                              inverse is kept in float32 (it shapes the search
-                             directions only, not the converged solution) */
+                             directions only, not the converged solution).
+                             order_K > 2: the forward kinematics in float32 (the
+                             seeds, residuals and gradient from the widened poses
+                             in double) until the gradient has dropped to 1e-3 of
+                             the warm start's, float32 claims convergence, meets
+                             its rounding or gives no descent, then double with
+                             the L-BFGS history restarted */
 
 /* schedules (abd_step_opts.schedule): how models are mapped onto the GPU */
 #define ABD_SCHEDULE_AUTO 0 /* the library picks: for the order-2 L-BFGS step of a
@@ -149,7 +155,7 @@ typedef struct {
   double dt;         /* time step > 0 */
   int order_K;       /* collocation order K: 2 = Eq. EQ (one unknown configuration per
                         step); 3, 4 = Eq. EQHOC with K-1 unknown configurations per
-                        step (float64 only, models of <= 256 DOFs); other values are
+                        step (models of <= 256 DOFs); other values are
                         rejected (EINVAL below 2, ENOTSUP above 4) */
   int lbfgs_m;       /* L-BFGS history length, 1..10 */
   double tol;        /* stop when |grad| <= tol * |grad at the warm start| */

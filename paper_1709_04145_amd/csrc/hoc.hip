@@ -37,8 +37,11 @@ __device__ double adjoint_fixed_seed_tangent(Sc& sc, const Xf<double>& A, const 
   return valid ? r : 0.0;
 }
 
-// One EQHOC evaluation (float64): E (wave-uniform) and the gradient g[U] of this lane.
-template <int U, typename Sc>
+// One EQHOC evaluation: E (wave-uniform) and the gradient g[U] of this lane.
+// R: precision of the forward kinematics (float for the float32 phase of a
+// mixed step: the poses are then widened and everything after them, seeds,
+// residuals, tangents and adjoint sums, runs in float64).
+template <int U, typename R = double, typename Sc>
 __device__ double hoc_evaluate(Sc& sc, const HocArgs<U>& args, const FrameGeo& geo, int f, bool valid,
                                const double q[U], double tau, double g[U], double* rho_sum = nullptr) {
   const DevModel& d = args.d;
@@ -51,7 +54,11 @@ __device__ double hoc_evaluate(Sc& sc, const HocArgs<U>& args, const FrameGeo& g
   const double gv[3] = {d.gx, d.gy, d.gz};
   Xf<double> A[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) A[u] = fk_geo<double>(sc, geo, valid, q[u]);
+  for (int u = 0; u < U; ++u) {
+    const Xf<R> Ar = fk_geo<R>(sc, geo, valid, q[u]);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) A[u].m[k] = (double)Ar.m[k];
+  }
   // seeds, residuals and their suffix sums
   double rho[U], KF[U][6];
   double E = 0.0;
@@ -147,7 +154,16 @@ __device__ double hoc_evaluate(Sc& sc, const HocArgs<U>& args, const FrameGeo& g
   return E;
 }
 
-template <int NW, bool TREE, int U>
+// A mixed step (PREC = ABD_MIXED) evaluates with float32 kinematics until its
+// gradient has dropped to kHocF32Drop of the warm start's (the residuals are
+// sums of poses whose weights, up to 82 at K = 4, cancel to O(dt^2), so float32
+// poses resolve the gradient only to about that), float32 claims convergence,
+// its line search meets float32 rounding or fails, or its direction is no
+// descent; it then re-evaluates at the iterate in float64, drops the pairs and
+// goes on in float64.
+constexpr double kHocF32Drop = 1e-3;
+
+template <int NW, bool TREE, int U, int PREC = ABD_FP64>
 __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
   __shared__ RollLds<NW, TREE> L;
   // one-wave models: s ring [m][U][64], then y ring; one-wave chains: then the
@@ -180,7 +196,6 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
   double* Hi = d.hinv + d.hoff[model];
   __shared__ double inert_sink[10];  // written by lanes without a frame, never read
   const FrameGeo geo = load_geo(d, f, valid);
-  const double eps_w = 1.1102230246251565e-16;
   const double c1 = 1e-4, dlt = 0.1;
   double qprev = valid ? args.q_prev[io] : 0.0;
   double qk = valid ? args.q_curr[io] : 0.0;
@@ -201,9 +216,18 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
 #pragma unroll
     for (int u = 0; u < U; ++u) q[u] = valid ? qk + args.tau_u[u] * args.vscale * (qk - qprev) : 0.0;
     const double tau = (valid && args.tau) ? args.tau[(size_t)step * n + io] : 0.0;
-    int iters = 0, evals = 0, flag = 0, count = 0, head = 0;
+    int iters = 0, evals = 0, flag = 0, count = 0, head = 0, f32_iters = 0, f32_evals = 0;
     double E = 0.0, g0 = 0.0, gn = 0.0, gam = 1.0;
-    bool reset = false;
+    bool reset = false, f32 = PREC == ABD_MIXED, to64 = false;
+    // one evaluation at the precision of the step's current phase
+    auto evaluate_hoc = [&](const double* qq, double* gg) -> double {
+      ++evals;
+      if (PREC == ABD_MIXED && f32) {
+        ++f32_evals;
+        return hoc_evaluate<U, float>(ws, args, geo, f, valid, qq, tau, gg);
+      }
+      return hoc_evaluate<U, double>(ws, args, geo, f, valid, qq, tau, gg);
+    };
     if (nf == 0) {
       flag = ABD_FLAG_CONVERGED;
     } else {
@@ -235,8 +259,7 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           __syncthreads();  // every lane reads the other lanes' columns
         }
       }
-      E = hoc_evaluate<U>(ws, args, geo, f, valid, q, tau, g);
-      ++evals;
+      E = evaluate_hoc(q, g);
       bool fin = isfinite(E);
 #pragma unroll
       for (int u = 0; u < U; ++u) fin = fin && ws.all_finite(g[u]);
@@ -252,6 +275,34 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
         else if (args.max_iter <= 0) flag = ABD_FLAG_MAX_ITER;
       }
       while (flag == 0) {
+        if (PREC == ABD_MIXED && to64) {
+          // leave float32: re-evaluate at q in float64 and restart the history
+          to64 = false;
+          f32 = false;
+          count = 0;
+          reset = false;
+          E = evaluate_hoc(q, g);
+          bool fin64 = isfinite(E);
+          double gg = 0.0;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            fin64 = fin64 && ws.all_finite(g[u]);
+            gg += g[u] * g[u];
+          }
+          if (!fin64) {
+            flag = ABD_FLAG_NONFINITE;
+            break;
+          }
+          gn = uniform(sqrt(ws.sum(gg)));
+          if (gn <= args.tol * g0) {
+            flag = ABD_FLAG_CONVERGED;
+            break;
+          }
+          if (iters >= args.max_iter) {
+            flag = ABD_FLAG_MAX_ITER;
+            break;
+          }
+        }
         if (reset) count = 0;
         // ---- two-loop recursion, newest pair first
         double qv[U];
@@ -328,17 +379,21 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
             reset = true;
             continue;
           }
+          if (PREC == ABD_MIXED && f32) {
+            to64 = true;  // the float32 gradient gives no descent direction
+            continue;
+          }
           flag = ABD_FLAG_LS_FLOOR;
           break;
         }
         reset = false;
+        const double eps_w = (PREC == ABD_MIXED && f32) ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
         double alpha = 1.0, Et = 0.0, qt[U], gt[U];
-        bool ok = false;
+        bool ok = false, noisy = false;
         for (int ls = 0; ls < args.max_ls; ++ls) {
 #pragma unroll
           for (int u = 0; u < U; ++u) qt[u] = q[u] + alpha * dir[u];
-          Et = hoc_evaluate<U>(ws, args, geo, f, valid, qt, tau, gt);
-          ++evals;
+          Et = evaluate_hoc(qt, gt);
           bool fin = isfinite(Et);
 #pragma unroll
           for (int u = 0; u < U; ++u) fin = fin && ws.all_finite(gt[u]);
@@ -346,6 +401,7 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
             if (Et <= E + c1 * alpha * gd) {
               ok = true;
             } else if (fabs(Et - E) <= 10.0 * eps_w * Et) {
+              noisy = true;
               double gtdl = 0.0;
 #pragma unroll
               for (int u = 0; u < U; ++u) gtdl += gt[u] * dir[u];
@@ -356,6 +412,10 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
           alpha = next_alpha(alpha, E, Et, gd);
         }
         if (!ok) {
+          if (PREC == ABD_MIXED && f32) {
+            to64 = true;  // float32 stalls the search: continue in float64 from q
+            continue;
+          }
           flag = ABD_FLAG_LS_FLOOR;
           break;
         }
@@ -365,6 +425,10 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
 #pragma unroll
           for (int u = 0; u < U; ++u) mv += (valid && qt[u] != q[u]) ? 1.0 : 0.0;
           if (uniform(ws.sum(mv)) == 0.0) {
+            if (PREC == ABD_MIXED && f32) {
+              to64 = true;
+              continue;
+            }
             flag = ABD_FLAG_LS_FLOOR;
             break;
           }
@@ -402,7 +466,12 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
         }
         E = Et;
         ++iters;
+        if (PREC == ABD_MIXED && f32) ++f32_iters;
         gn = uniform(sqrt(ggl));
+        if (PREC == ABD_MIXED && f32 && (gn <= fmax(args.tol, kHocF32Drop) * g0 || noisy)) {
+          to64 = true;  // float32 has done what it can: confirm / continue in float64
+          continue;
+        }
         if (gn <= args.tol * g0) flag = ABD_FLAG_CONVERGED;
         else if (iters >= args.max_iter) flag = ABD_FLAG_MAX_ITER;
       }
@@ -415,8 +484,8 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
       st.iterations = iters;
       st.evaluations = evals;
       st.flag = flag;
-      st.f32_iterations = 0;
-      st.f32_evaluations = 0;
+      st.f32_iterations = f32_iters;
+      st.f32_evaluations = f32_evals;
       st.reserved = 0;
       st.grad_norm = gn;
       st.energy = E;
@@ -441,7 +510,7 @@ struct HocObjArgs {
   double* Bk;
 };
 
-template <int NW, bool TREE, int U>
+template <int NW, bool TREE, int U, typename R = double>
 __global__ void __launch_bounds__(NW* kWave) k_hoc_objective(HocObjArgs a) {
   __shared__ ScanLds<NW, TREE> L;
   const DevModel& d = a.d;
@@ -478,7 +547,7 @@ __global__ void __launch_bounds__(NW* kWave) k_hoc_objective(HocObjArgs a) {
   for (int u = 0; u < U; ++u) q[u] = valid ? a.q[(size_t)u * n + io] : 0.0;
   const double tau = (valid && a.tau) ? a.tau[io] : 0.0;
   double rsum = 0.0;
-  const double E = hoc_evaluate<U>(ws, h, geo, f, valid, q, tau, g, &rsum);
+  const double E = hoc_evaluate<U, R>(ws, h, geo, f, valid, q, tau, g, &rsum);
   if (j == 0) a.E[model] = E;
   // rho_u = (adjoint term) - dt^2 tau, so dE/dtau = -2 dt^2 sum_u rho_u
   if (a.grad_tau && valid) a.grad_tau[io] = -2.0 * a.dt2 * rsum;
@@ -535,7 +604,6 @@ void hoc_collocation(int K, double* tau, double* w) {
 int check_hoc(const abd_model* m, const abd_step_opts* o) {
   if (m->max_frames > 4 * kMaxFrames)
     return fail(ABD_ENOTSUP, "order_K > 2 handles models of at most 256 DOFs in this build");
-  if (o->precision != ABD_FP64) return fail(ABD_ENOTSUP, "order_K > 2 runs in ABD_FP64 only in this build");
   return ABD_OK;
 }
 
@@ -556,7 +624,10 @@ int launch_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, const
     if ((rc = fill_hoc_args<UU>(m, o, a, sc))) return rc;                                      \
     a.n_steps = n_steps; a.q_prev = q_prev; a.q_curr = q_curr; a.tau = tau; a.q_out = q_out;   \
     a.stats = stats;                                                                           \
-    hipLaunchKernelGGL((k_rollout_hoc<NW, TREE, UU>), grid, block, pair_bytes, s, a);          \
+    if (o->precision == ABD_MIXED)                                                             \
+      hipLaunchKernelGGL((k_rollout_hoc<NW, TREE, UU, ABD_MIXED>), grid, block, pair_bytes, s, a); \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_rollout_hoc<NW, TREE, UU>), grid, block, pair_bytes, s, a);        \
   } while (0)
 #define ABD_HOC_U(NW, TREE) \
   do {                      \
@@ -605,10 +676,15 @@ int launch_hoc_objective(abd_model* m, const abd_step_opts* o, const double* q, 
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nw = waves_for(m->max_frames);
   const dim3 grid(m->n_models), block(nw * kWave);
+  const bool f32 = o->precision == ABD_MIXED;  // float32 kinematics
 #define ABD_HOCOBJ(NW, TREE)                                                              \
   do {                                                                                    \
-    if (U == 2)                                                                           \
+    if (U == 2 && f32)                                                                    \
+      hipLaunchKernelGGL((k_hoc_objective<NW, TREE, 2, float>), grid, block, 0, s, h);    \
+    else if (U == 2)                                                                      \
       hipLaunchKernelGGL((k_hoc_objective<NW, TREE, 2>), grid, block, 0, s, h);           \
+    else if (f32)                                                                         \
+      hipLaunchKernelGGL((k_hoc_objective<NW, TREE, 3, float>), grid, block, 0, s, h);    \
     else                                                                                  \
       hipLaunchKernelGGL((k_hoc_objective<NW, TREE, 3>), grid, block, 0, s, h);           \
   } while (0)

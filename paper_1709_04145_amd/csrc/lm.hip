@@ -1013,6 +1013,7 @@ int launch_lm_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, co
                   const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream) {
   int rc = check_hoc(m, o);
   if (rc) return rc;
+  if (o->precision != ABD_FP64) return fail(ABD_ENOTSUP, "ABD_SOLVER_LM runs in ABD_FP64 only in this build");
   const int U = o->order_K - 1;
   if (U != 2)
     return fail(ABD_ENOTSUP, "ABD_SOLVER_LM handles order_K = 3 in this build (order 4 is switched off)");

@@ -193,8 +193,10 @@ def test_eqhoc_unsupported_cases_are_rejected():
     m = abd.Model(d)
     q = cu(np.zeros(d.n_dofs))
     out = torch.zeros((3, d.n_dofs), dtype=torch.float64, device="cuda")
-    with pytest.raises(abd.AbdError) as e:
-        m.step(torch.cat([q, q]), out, abd.StepOptions(dt=0.01, order_K=4, precision=abd.MIXED))
+    out2 = torch.zeros((2, d.n_dofs), dtype=torch.float64, device="cuda")
+    with pytest.raises(abd.AbdError) as e:  # Levenberg-Marquardt computes in float64 only
+        m.step(torch.cat([q, q]), out2, abd.StepOptions(dt=0.01, order_K=3, precision=abd.MIXED,
+                                                        solver=abd.SOLVER_LM))
     assert e.value.code == abd.ABD_ENOTSUP
     out5 = torch.zeros((4, d.n_dofs), dtype=torch.float64, device="cuda")
     with pytest.raises(abd.AbdError) as e:
@@ -240,3 +242,63 @@ def test_eqhoc_tree_step_matches_oracle():
     assert np.all(st["flag"] == abd.FLAG_CONVERGED), st["flag"]
     _, g_own = m.objective_grad(out.reshape(-1).contiguous(), cu(np.concatenate([q0, q0])), dt, order_K=K)
     _check_tolerance_implied(d, K, dt, tol, q0, out.cpu().numpy(), ref, g_own.cpu().numpy().reshape(K - 1, -1))
+
+
+# ------------------------------------------------------------- mixed precision
+# ABD_MIXED at order K > 2: float32 forward kinematics until the gradient has
+# dropped to 1e-3 of the warm start's (or float32 stalls), then float64.  The
+# result is a float64-converged step, so it is checked like the float64 path's:
+# the oracle's gradient at it within the tolerance and the distance to the
+# oracle's result within the tolerance-implied bound; the float32 phase must
+# have run (f32 iterations counted) and the pose error is far below 1e-5.
+
+
+@pytest.mark.parametrize("K", [3, 4])
+@pytest.mark.parametrize("which", ["chains", "trees"])
+def test_eqhoc_mixed_step_matches_oracle(K, which):
+    if which == "chains":
+        d = W.random_chain_models(8, 11, lo=4, hi=12)
+    else:
+        d = W.random_tree_models(8, 61, max_links=6, ball_prob=0.4)
+    q0 = np.random.default_rng(5).uniform(-0.5, 0.5, d.n_dofs)
+    dt, tol = 0.01, 1e-10
+    say(f"eqhoc mixed step K={K} {which}")
+    orc = Oracle(d)
+    ref, rst = orc.step_hoc(K, q0, q0, dt, tol=tol, max_iter=3000)
+    m = abd.Model(d)
+    out = torch.zeros((K - 1, d.n_dofs), dtype=torch.float64, device="cuda")
+    st = m.new_stats()
+    m.step(cu(np.concatenate([q0, q0])), out, abd.StepOptions(dt=dt, order_K=K, tol=tol, max_iter=3000,
+                                                                precision=abd.MIXED), stats=st)
+    torch.cuda.synchronize()
+    st = m.read_stats(st, d.n_models)
+    say(f"  iterations {st['iterations'].tolist()} of which float32 {st['f32_iterations'].tolist()}")
+    assert np.all(st["flag"] == abd.FLAG_CONVERGED), st["flag"]
+    assert np.all(rst["flag"] == 1)
+    assert np.all(st["f32_iterations"] > 0) and np.all(st["f32_evaluations"] > st["f32_iterations"])
+    _, g_own = m.objective_grad(out.reshape(-1).contiguous(), cu(np.concatenate([q0, q0])), dt, order_K=K)
+    got = out.cpu().numpy()
+    _check_tolerance_implied(d, K, dt, tol, q0, got, ref, g_own.cpu().numpy().reshape(K - 1, -1))
+    A, B = orc.poses(got[-1]), orc.poses(ref[-1])
+    assert np.max(np.abs(A - B)) <= 1e-5
+
+
+def test_eqhoc_mixed_objective_uses_float32_kinematics():
+    """The mixed objective at K > 2 differs from the float64 one by the float32
+    rounding of the poses (weights up to 82 cancel in the residuals): within
+    1e-2 of E, and not equal to it."""
+    K = 4
+    d = W.random_chain_models(6, 14, lo=4, hi=20)
+    rng = np.random.default_rng(15)
+    qp, qc = (rng.uniform(-0.5, 0.5, d.n_dofs) for _ in range(2))
+    qu = qc + 0.01 * rng.standard_normal((K - 1, d.n_dofs))
+    dt = 0.01
+    E, _ = Oracle(d).eqhoc_objective_grad(K, dt, qp, qc, qu)
+    m = abd.Model(d)
+    hist = cu(np.concatenate([qp, qc]))
+    E64, _ = m.objective_grad(cu(qu.reshape(-1)), hist, dt, order_K=K)
+    E32, _ = m.objective_grad(cu(qu.reshape(-1)), hist, dt, order_K=K, precision=abd.MIXED)
+    E64, E32 = E64.cpu().numpy(), E32.cpu().numpy()
+    np.testing.assert_allclose(E64, E, rtol=1e-10, atol=0)
+    assert np.all(np.abs(E32 - E) <= 1e-2 * E), np.max(np.abs(E32 - E) / E)
+    assert np.any(E32 != E64)
