@@ -1,14 +1,19 @@
-"""Writes tests/golden/rope_steps.npz: the FP64 oracle's first three steps of four
+"""Writes tests/golden/rope_steps.npz: the FP64 oracle's first ten steps of four
 ropes of the 1000-link rope workload (dt = 0.1, L-BFGS history 10), the
 reference of the GPU's teacher-forced steps in tests/test_gpu_rope.py.
 
-Calls only the oracle (oracle/) and the seeded input generator (later steps of this
-workload reach the 3000-iteration cap in the oracle).  Per step k
-(0..2) it stores q_{k+1}, the oracle's stats, and the smallest eigenvalue of the
-step objective's Hessian at q_{k+1} (written-out second derivatives).  That
-eigenvalue is negative on these ropes: the step objective is not convex at this
-step size, the results are not isolated minimizers, and the test compares what
-the tolerance fixes (convergence, gradient, objective value), not configurations.
+Calls only the oracle (oracle/) and the seeded input generator.  Per step k
+(0..9) it stores q_{k+1}, the oracle's stats (relative gradient tolerance 1e-5,
+at most 20000 iterations), and the smallest eigenvalue of the step objective's
+Hessian at q_{k+1} (written-out second derivatives).  That eigenvalue is
+negative on these ropes: the step objective is not convex at this step size, the
+results are not isolated minimizers, and the test compares what the tolerance
+fixes (convergence, gradient, objective value), not configurations.  The oracle
+itself converges on 34 of the 40 model-steps: rope 2 stops at its line-search
+floor in step 4 and reaches the cap from step 6 on, rope 3 stops at its floor in
+step 6 (where the Hessian has an eigenvalue near -1e3); later steps start from
+those results all the same (teacher forcing), and the test compares the 31
+model-steps that the oracle converged on and whose inputs are converged results.
 
 Run from the repository root:  python tests/golden/make_rope_reference.py
 """
@@ -23,8 +28,8 @@ sys.path.insert(0, ROOT)
 from oracle.oracle import Oracle  # noqa: E402
 from paper_1709_04145_amd import workloads as W  # noqa: E402
 
-MODELS, STEPS = 4, 3
-TOL, MAX_ITER = 1e-5, 3000
+MODELS, STEPS = 4, 10
+TOL, MAX_ITER = 1e-5, 20000
 
 
 def main():
