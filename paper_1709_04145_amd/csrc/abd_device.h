@@ -989,6 +989,7 @@ struct StepArgs {
   int m, max_iter, max_ls, precond;
   int refresh;                // re-form the inertia preconditioner every `refresh` iterations (0: never)
   int n_steps;                // time steps in this launch
+  int nfmax;                  // frames of the batch's largest model (sizes the LDS of one-wave chains)
   const double* q_prev;       // q_{-1}
   const double* q_curr;       // q_0
   const double* tau;          // [n_steps][n_dofs] or NULL
@@ -1008,9 +1009,11 @@ struct StepArgs {
 // SEGS: models per wavefront (packed one-wave chains): the per-model scalars of
 // the two-loop recursion are kept per segment, and the vector of the inverse
 // product has its own area (vb) instead of the recursion's table.
-template <int NW, bool TREE = false, int SEGS = 1>
+// TAB false: the table lives in dynamic LDS sized to the batch (k_rollout's
+// one-model-per-wavefront chains), and this struct keeps a placeholder row.
+template <int NW, bool TREE = false, int SEGS = 1, bool TAB = true>
 struct RollLds {
-  double tab[kMaxFrames * NW][kTab];
+  double tab[TAB ? kMaxFrames * NW : 1][kTab];
   double inert[(NW == 1 && TREE) ? kMaxFrames : 1][10];  // one-wave chains: in the inverse's LDS
   double rho[kMaxHist * SEGS];  // 1/(s_i.y_i): k_rollout by ring slot of the pair, others newest first
   double alp[kMaxHist * SEGS];  // two-loop coefficients
@@ -1122,6 +1125,11 @@ __device__ __forceinline__ int tri(int j) { return (j * (j + 1)) >> 1; }
 // inputs of the recursion (10 per frame) before the inverse is formed.
 __host__ __device__ constexpr int inverse_lds_doubles(int nf) {
   return (nf * (nf + 1) / 2 > 10 * kMaxFrames) ? nf * (nf + 1) / 2 : 10 * kMaxFrames;
+}
+// k_rollout's area for chains of at most nf frames, one per wavefront: only
+// the lanes of frames write inertia inputs there (the others write to a sink).
+__host__ __device__ constexpr int chain_lds_doubles(int nf) {
+  return (nf * (nf + 1) / 2 > 10 * nf) ? nf * (nf + 1) / 2 : 10 * nf;
 }
 // The same area for one model of a wavefront packed with models of at most s
 // frames (the float32 full inverse, s^2 floats, fits in the triangle too).

@@ -12,11 +12,16 @@ template <int NW, int PREC, bool TREE, bool FX = false, int SEG = kWave>
 __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_rollout(StepArgs args) {
   static_assert(SEG == kWave || (NW == 1 && !TREE), "packed models are one-wave chains");
   constexpr int SEGS = kWave / SEG;  // models per wavefront
-  __shared__ RollLds<NW, TREE, SEGS> L;
+  // chains of one wavefront each: the recursion's table in the dynamic LDS, so
+  // that all of it is sized to the batch's largest model
+  constexpr bool kDynTab = NW == 1 && !TREE && SEGS == 1;
+  __shared__ RollLds<NW, TREE, SEGS, !kDynTab> L;
   // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
-  // y in [m, 2m), one double per lane per slot; one-wave chains: then the
-  // explicit inverse (inverse_lds_doubles(max frames); packed float64, or the
-  // full float32 matrix for MIXED), per segment of packed models
+  // y in [m, 2m), ps doubles per slot (one per frame of the batch's largest
+  // model for chains of one wavefront each, else one per lane); one-wave
+  // chains: then the explicit inverse (chain_lds_doubles(nfmax); packed
+  // float64, or the full float32 matrix for MIXED) and the recursion's table
+  // (nfmax rows, at least 64 doubles), or per segment of packed models
   // tile_inverse_doubles(SEG) each
   extern __shared__ double pairs[];
   const DevModel& d = args.d;
@@ -25,10 +30,12 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   const int seg = SEGS > 1 ? lane / SEG : 0;
   const int j = SEGS > 1 ? lane % SEG : (int)threadIdx.x;  // frame of this thread within its model
   const int jl = SEGS > 1 ? j : lane;                       // its lane in the one-wave helpers
-  double* const hl = pairs + 2 * args.m * kWave + (SEGS > 1 ? seg * tile_inverse_doubles(SEG) : 0);
+  const int ps = kDynTab ? args.nfmax : kWave;
+  double* const hl = pairs + 2 * args.m * ps + (SEGS > 1 ? seg * tile_inverse_doubles(SEG) : 0);
   double* const rho = L.rho + seg * kMaxHist;
   double* const alp = L.alp + seg * kMaxHist;
-  double (*const tab)[kTab] = L.tab + seg * SEG;
+  double (*const tab)[kTab] =
+      kDynTab ? reinterpret_cast<double (*)[kTab]>(hl + chain_lds_doubles(args.nfmax)) : L.tab + seg * SEG;
   const bool lead = j == 0;
   const int mslot = blockIdx.x * SEGS + seg;
   const bool has_model = mslot < d.n_models;
@@ -70,8 +77,8 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   int hstride, ys;
   if (NW == 1) {
     hs = pairs + lane;
-    hstride = kWave;
-    ys = args.m * kWave;
+    hstride = ps;
+    ys = args.m * ps;
   } else {
     hs = d.hist + (size_t)f * (2 * kMaxHist);
     hstride = 1;
@@ -97,7 +104,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
     __syncthreads();
     PROF_T(t_r);
     if (TREE) {
-      if (lead) aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
+      if (lead) aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, tab, L.tpar, Hi + 10 * (size_t)nf, nf);
     } else if (wave == 0) {
       aba_setup_rows<SEG>(NW == 1 ? hl : Hi, tab, nf, jl);
     }
@@ -128,9 +135,15 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
     PROF_ADD(3, t_i);
   };
   // frames' inertias: lanes without a frame of a multi-wave model write their
-  // (zero) record to a sink, never to frame 0's slot, which lane 0 fills
+  // (zero) record to a sink, never to frame 0's slot, which lane 0 fills; so do
+  // the lanes past the model's frames of chains of one wavefront each, with
+  // their table rows, which have no place in the LDS sized to the batch (the
+  // recursion reads the model's frames only)
   __shared__ double inert_sink[10];
-  double* const inert = NW == 1 ? (TREE ? L.inert[lane] : hl + 10 * jl) : (valid ? Hi + (size_t)j * 10 : inert_sink);
+  __shared__ double tab_sink[kTab];
+  double* const inert = NW == 1 ? (TREE ? L.inert[lane] : ((kDynTab && !valid) ? inert_sink : hl + 10 * jl))
+                                : (valid ? Hi + (size_t)j * 10 : inert_sink);
+  double* const tab_j = (kDynTab && !valid) ? tab_sink : tab[j];
 
   while (state != kDone) {
     bool step_done = false;
@@ -147,7 +160,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         flag = ABD_FLAG_CONVERGED;
         step_done = true;
       } else {
-        step_setup<FX>(sc, d, inert, tab[j], geo, f, valid, qkm1, qk, q, use_aba);
+        step_setup<FX>(sc, d, inert, tab_j, geo, f, valid, qkm1, qk, q, use_aba);
         if (use_aba) factor_precond();
         PROF_ADD(0, t_s);
         const EvalResult r = (PREC == ABD_MIXED) ? evaluate<float, FX>(sc, d, geo, f, valid, q, tau, args.dt2)
@@ -180,7 +193,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         // the preconditioner at q and restart the curvature history
         refreshed = iters;
         PROF_T(t_f);
-        precond_frame<FX>(sc, d, inert, tab[j], geo, f, valid, q);
+        precond_frame<FX>(sc, d, inert, tab_j, geo, f, valid, q);
         factor_precond();
         count = 0;
         head = 0;
@@ -241,7 +254,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
           // the recursion's table is free between formations
           // the vector goes through the recursion's table, which is free between
           // formations (packed models: through an area of its own per segment)
-          double* const vb = SEGS > 1 ? L.vb + seg * SEG : &L.tab[0][0];
+          double* const vb = SEGS > 1 ? L.vb + seg * SEG : &tab[0][0];
           r = inv32 ? apply_inverse_f32<SEG>(reinterpret_cast<const float*>(hl), reinterpret_cast<float*>(vb), nf, jl, qv)
                     : apply_inverse<SEG>(hl, vb, nf, jl, qv);
           PROF_ADD(14, t_h);
@@ -250,9 +263,9 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
           __syncthreads();
           if (lead) {
             if (TREE)
-              aba_solve_tree(L.tab, L.xb, L.tpar, L.acc, nf);
+              aba_solve_tree(tab, L.xb, L.tpar, L.acc, nf);
             else
-              aba_solve(L.tab, L.xb, nf);
+              aba_solve(tab, L.xb, nf);
           }
           __syncthreads();
           r = ld_if(&L.xb[j], valid);
@@ -384,8 +397,8 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
             break;
           }
         }
+        PROF_ADD(5, t_c);
       }
-      PROF_ADD(5, t_c);
 #ifdef ABD_PROFILE
       if (lead && abd_prof) abd_prof[(size_t)model * 16 + 9] += 1;
 #endif
@@ -455,8 +468,16 @@ static int dispatch_rollout(const abd_model* m, const abd_step_opts* o, const St
     return ABD_OK;
   }
   const dim3 grid(m->n_models), block(nw * kWave);
-  size_t pair_bytes = nw == 1 ? 2 * (size_t)o->lbfgs_m * kWave * sizeof(double) : 0;
-  if (nw == 1 && !m->tree) pair_bytes += (size_t)inverse_lds_doubles(m->max_frames) * sizeof(double);
+  // one-wave models: the L-BFGS pairs; chains: per frame of the largest model,
+  // then the explicit inverse and the recursion's table (at least 64 doubles:
+  // it also carries the vector of the inverse product)
+  size_t pair_bytes = 0;
+  if (nw == 1 && m->tree) pair_bytes = 2 * (size_t)o->lbfgs_m * kWave * sizeof(double);
+  if (nw == 1 && !m->tree) {
+    const int nf = m->max_frames;
+    pair_bytes = (2 * (size_t)o->lbfgs_m * nf + chain_lds_doubles(nf) + (kTab * nf > kWave ? kTab * nf : kWave)) *
+                 sizeof(double);
+  }
 #define ABD_LAUNCH(NW, TREE)                                                                \
   do {                                                                                      \
     if (f64)                                                                                \
@@ -570,6 +591,7 @@ int launch_rollout(abd_model* m, const abd_step_opts* o, const double* q_prev, c
   a.precond = o->precond;
   a.refresh = o->refresh;
   a.n_steps = n_steps;
+  a.nfmax = m->max_frames;
   a.q_prev = q_prev;
   a.q_curr = q_curr;
   a.tau = tau;
