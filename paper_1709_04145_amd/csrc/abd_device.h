@@ -352,7 +352,9 @@ struct DevModel {
   const long long* hoff;    // [n_models+1] start of every model's block in hinv
   double* hinv;             // per model: chains of more than 64 frames, the frames' spatial
                             // inertias [nf][10]; branched models, those and the recursion's
-                            // accumulators [nf][31]; nothing for one-wave chains (their
+                            // accumulators [nf][31], then the explicit L^-1 of the
+                            // preconditioner (rows over the frames below: sum of
+                            // (fend - f + 1)); nothing for one-wave chains (their
                             // explicit inverse lives in LDS)
   double* hist;             // models of more than 64 frames: [n_dofs][2*kMaxHist] L-BFGS
                             // pairs, s ring then y ring
@@ -360,6 +362,8 @@ struct DevModel {
   const int* uidx;          // [n_dofs] index of the frame's DOF in the caller's vectors
   const int* fpar;          // [n_dofs] parent frame within the model, -1 = world
   const int* fend;          // [n_dofs] last frame below this one (within the model)
+  const int* wrow;          // branched models: [n_dofs] start of the frame's row of the
+                            // preconditioner's explicit L^-1 within the model's block
   int jump_rounds;          // ceil(log2(deepest frame path)) of the batch
   double gx, gy, gz;
   // optional terms (models with slides, drag or contact points; NULL otherwise)
@@ -389,6 +393,7 @@ inline DevModel dev_view(const abd_model* m) {
   d.uidx = m->uidx;
   d.fpar = m->fpar;
   d.fend = m->fend;
+  d.wrow = m->wrow;
   d.jump_rounds = m->jump_rounds;
   d.gx = m->g[0]; d.gy = m->g[1]; d.gz = m->g[2];
   d.fkind = m->fkind;
@@ -1002,10 +1007,12 @@ struct StepArgs {
 //   inert: per frame world spatial inertia about the origin (J 6, h 3, m), for
 //          one-wave trees; one-wave chains keep it in the LDS of their explicit
 //          inverse, NW > 1 in the model's device scratch
-//   xb:    NW > 1: the vector swept by the recursion
+//   xb:    NW > 1: the vector swept by the recursion; branched models: the
+//          vector of the preconditioner's product
 //   xch:   scan exchange areas of BlockScan
 //   branched models (TREE): pointer-jumping buffers of TreeScan (tq, tv, tanc),
-//   frame parents (tpar) and the sweep accumulators (acc)
+//   frame parents (tpar) and the middle vector of the preconditioner's product
+//   (acc, first nf doubles)
 // SEGS: models per wavefront (packed one-wave chains): the per-model scalars of
 // the two-loop recursion are kept per segment, and the vector of the inverse
 // product has its own area (vb) instead of the recursion's table.
@@ -1443,6 +1450,66 @@ __device__ void aba_solve_tree(const double (*tab)[kTab], double* xb, const int*
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc[f][k] = a[k] + t[k] * x;
   }
+}
+
+// The recursion's two sweeps are the factorization H = L D L^T of a branched
+// model's joint-space inertia in the world frame: with p_f summed over the
+// frames below f, the backward sweep solves (I + N) u = b, N_fg = s_f.U_g / D_g
+// for g below f, so u = L^-1 b with L = I + N; the forward sweep solves
+// (D + N') x = u with N'_fg = U_f.s_g = D_f N_gf for g above f, i.e.
+// D L^T x = u.  Hence H^-1 = L^-T D^-1 L^-1, and column j of L^-1 (the
+// backward sweep of e_j) is nonzero on j and the frames above it only:
+//   u_j = 1, then up the path  p <- p + U_g u_g / D_g,  u_a = -s_a.p.
+// W holds row a of L^-1 over the frames below a (a contiguous preorder range
+// [a, fend_a]) from wrow[a] on: entry (a, j) at W[wrow[a] + j - a].
+// tree_inverse_factor: this thread's column j of L^-1 into W (every frame's
+// thread at once; tab must hold s, U, 1/D of every frame of the model).
+__device__ __forceinline__ void tree_inverse_factor(const double (*tab)[kTab], const int* parent, const int* wrow,
+                                                    double* W, int j, bool valid) {
+  if (!valid) return;
+  double p[6] = {0, 0, 0, 0, 0, 0};
+  double u = 1.0;
+  int g = j;
+  for (;;) {
+    const double* t = tab[g];
+    W[wrow[g] + (j - g)] = u;
+    const double w = u * t[12];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] += t[6 + k] * w;
+    g = parent[g];
+    if (g < 0) break;
+    const double* s = tab[g];
+    u = -((s[0] * p[0] + s[1] * p[1]) + (s[2] * p[2] + s[3] * p[3]) + (s[4] * p[4] + s[5] * p[5]));
+  }
+}
+
+// r = H^-1 v on a branched model from W (tree_inverse_factor): z = L^-1 v, row a
+// of L^-1 times v over the frames below a; y = D^-1 z; r_j = sum over the
+// frames a on the path from j up of (L^-1)_aj y_a.  Every thread of the
+// workgroup calls it (lane j's frame: valid; fend_j: the last frame below it);
+// xb, yb: LDS vectors of the model's frames.
+__device__ __forceinline__ double tree_apply_inverse(const double (*tab)[kTab], const int* parent, const int* wrow,
+                                                     const double* W, double* xb, double* yb, int j, int fend_j,
+                                                     bool valid, double v) {
+  if (valid) xb[j] = v;
+  __syncthreads();
+  if (valid) {
+    const double* row = W + wrow[j] - j;
+    double z0 = 0.0, z1 = 0.0;
+    int i = j;
+    for (; i + 1 <= fend_j; i += 2) {
+      z0 += row[i] * xb[i];
+      z1 += row[i + 1] * xb[i + 1];
+    }
+    if (i <= fend_j) z0 += row[i] * xb[i];
+    yb[j] = (z0 + z1) * tab[j][12];
+  }
+  __syncthreads();
+  double r = 0.0;
+  if (valid)
+    for (int a = j; a >= 0; a = parent[a]) r += W[wrow[a] + (j - a)] * yb[a];
+  __syncthreads();  // xb, yb are reused by the next product
+  return r;
 }
 
 // Inputs of the inertia preconditioner at configuration q (float64): this

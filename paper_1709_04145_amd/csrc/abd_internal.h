@@ -36,6 +36,7 @@ struct abd_model {
   int* uidx = nullptr;
   int* fpar = nullptr;
   int* fend = nullptr;
+  int* wrow = nullptr;  // branched models: row offsets of the explicit L^-1 of the preconditioner
   // optional terms (slides, drag, contact points); fx = any of them present
   bool fx = false;
   signed char* fkind = nullptr;  // [n_dofs] 1 = slide, internal frame order; NULL: all hinges

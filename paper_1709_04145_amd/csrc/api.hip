@@ -332,12 +332,20 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
     pose_link.swap(pl);
   }
   // per-model preconditioner scratch: the per-frame spatial inertias (10 nf) of
-  // a chain longer than one wave, inertias and recursion accumulators (31 nf) of
-  // a branched model (one-wave chains keep theirs in LDS)
+  // a chain longer than one wave; inertias and recursion accumulators (31 nf) of
+  // a branched model, then its explicit L^-1 by rows, row f over the frames
+  // below f (wrow: where each row starts); one-wave chains keep theirs in LDS
   std::vector<long long> hoff(nm + 1, 0);
+  std::vector<int> wrow(chain ? 0 : nd);
   for (int i = 0; i < nm; ++i) {
     const long long k = f0[i + 1] - f0[i];
-    hoff[i + 1] = hoff[i] + (!chain ? 31 * k : k <= kMaxFrames ? 0 : 10 * k);
+    long long w = 0;
+    if (!chain)
+      for (int fr = f0[i]; fr < f0[i + 1]; ++fr) {
+        wrow[fr] = (int)w;
+        w += fend[fr] - (fr - f0[i]) + 1;
+      }
+    hoff[i + 1] = hoff[i] + (!chain ? 31 * k + w : k <= kMaxFrames ? 0 : 10 * k);
   }
 
   std::vector<int> order(nm);
@@ -398,6 +406,7 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
       (rc = alloc(m, &m->B64, 12 * (size_t)nd)) || (rc = alloc(m, &m->B32, 12 * (size_t)nd)) ||
       (rc = upload(m, &m->hoff, hoff)) || (rc = upload(m, &m->uidx, uidx)) ||
       (rc = upload(m, &m->fpar, fpar)) || (rc = upload(m, &m->fend, fend)) ||
+      (!chain && (rc = upload(m, &m->wrow, wrow))) ||
       (rc = alloc(m, &m->hist, max_frames > kMaxFrames ? 2 * kMaxHist * (size_t)nd : 1)) ||
       (rc = alloc(m, &m->hinv, (size_t)hoff[nm])) ||
       (any_slide && (rc = upload(m, &m->fkind, fkind))) || (any_drag && (rc = upload(m, &m->fdrag, fdrag))) ||

@@ -194,6 +194,7 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
   const bool use_aba = args.precond == ABD_PRECOND_INERTIA;
   const bool explicit_inverse = NW == 1 && !TREE;
   double* Hi = d.hinv + d.hoff[model];
+  const int fend_j = TREE && valid ? d.fend[f] : j;  // the last frame below this one
   __shared__ double inert_sink[10];  // written by lanes without a frame, never read
   const FrameGeo geo = load_geo(d, f, valid);
   const double c1 = 1e-4, dlt = 0.1;
@@ -257,6 +258,12 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
         if (explicit_inverse) {
           aba_inverse(L.tab, nf, lane, hl);  // overwrites the inertias
           __syncthreads();  // every lane reads the other lanes' columns
+        }
+        if (TREE && PREC == ABD_FP64) {
+          // the explicit L^-1 of the recursion, one column per frame's thread
+          tree_inverse_factor(L.tab, L.tpar, d.wrow + f0, Hi + 31 * (size_t)nf, j, valid);
+          __threadfence_block();
+          __syncthreads();
         }
       }
       E = evaluate_hoc(q, g);
@@ -327,19 +334,26 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
               y[u] = apply_inverse(hl, &L.tab[0][0], nf, lane, apply_inverse(hl, &L.tab[0][0], nf, lane, qv[u]));
+          } else if (TREE && PREC == ABD_FP64) {
+            const double* W = Hi + 31 * (size_t)nf;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+              y[u] = tree_apply_inverse(L.tab, L.tpar, d.wrow + f0, W, L.xb, &L.acc[0][0], j, fend_j, valid,
+                                        tree_apply_inverse(L.tab, L.tpar, d.wrow + f0, W, L.xb, &L.acc[0][0], j,
+                                                           fend_j, valid, qv[u]));
           } else {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
               L.xb[j] = valid ? qv[u] : 0.0;
               __syncthreads();
-              if (lead) {
+              // (the mixed kernels of branched models keep the one-thread sweeps)
+              if (lead)
                 for (int rep = 0; rep < 2; ++rep) {
                   if (TREE)
                     aba_solve_tree(L.tab, L.xb, L.tpar, L.acc, nf);
                   else
                     aba_solve(L.tab, L.xb, nf);
                 }
-              }
               __syncthreads();
               y[u] = valid ? L.xb[j] : 0.0;
               __syncthreads();

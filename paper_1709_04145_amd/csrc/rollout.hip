@@ -62,6 +62,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   // one-wave chains: explicit inverse; otherwise inertias [nf][10] (then, for
   // branched models, the recursion's accumulators [nf][21])
   double* Hi = d.hinv + d.hoff[model];
+  const int fend_j = TREE && valid ? d.fend[f] : j;  // the last frame below this one
   const FrameGeo geo = load_geo<FX>(d, f, valid);
   const double eps_w = PREC == ABD_MIXED ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
   const double c1 = 1e-4, dlt = 0.1;
@@ -109,6 +110,12 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
       aba_setup_rows<SEG>(NW == 1 ? hl : Hi, tab, nf, jl);
     }
     __syncthreads();
+    if (TREE) {
+      // the explicit L^-1 of the recursion, one column per frame's thread
+      tree_inverse_factor(tab, L.tpar, d.wrow + f0, Hi + 31 * (size_t)nf, j, valid);
+      __threadfence_block();
+      __syncthreads();
+    }
     PROF_ADD(2, t_r);
     PROF_T(t_i);
     if (NW == 1 && !TREE) {
@@ -258,15 +265,13 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
           r = inv32 ? apply_inverse_f32<SEG>(reinterpret_cast<const float*>(hl), reinterpret_cast<float*>(vb), nf, jl, qv)
                     : apply_inverse<SEG>(hl, vb, nf, jl, qv);
           PROF_ADD(14, t_h);
+        } else if (TREE) {
+          r = tree_apply_inverse(tab, L.tpar, d.wrow + f0, Hi + 31 * (size_t)nf, L.xb, &L.acc[0][0], j, fend_j, valid,
+                                 qv);
         } else {
           L.xb[j] = valid ? qv : 0.0;
           __syncthreads();
-          if (lead) {
-            if (TREE)
-              aba_solve_tree(tab, L.xb, L.tpar, L.acc, nf);
-            else
-              aba_solve(tab, L.xb, nf);
-          }
+          if (lead) aba_solve(tab, L.xb, nf);
           __syncthreads();
           r = ld_if(&L.xb[j], valid);
         }
