@@ -364,6 +364,8 @@ struct DevModel {
   const int* fend;          // [n_dofs] last frame below this one (within the model)
   const int* wrow;          // branched models: [n_dofs] start of the frame's row of the
                             // preconditioner's explicit L^-1 within the model's block
+  const int* fheight;       // branched models: [n_dofs] longest path down to a leaf
+  const int* mheight;       // branched models: [n_models] largest height of the model
   int jump_rounds;          // ceil(log2(deepest frame path)) of the batch
   double gx, gy, gz;
   // optional terms (models with slides, drag or contact points; NULL otherwise)
@@ -394,6 +396,8 @@ inline DevModel dev_view(const abd_model* m) {
   d.fpar = m->fpar;
   d.fend = m->fend;
   d.wrow = m->wrow;
+  d.fheight = m->fheight;
+  d.mheight = m->mheight;
   d.jump_rounds = m->jump_rounds;
   d.gx = m->g[0]; d.gy = m->g[1]; d.gz = m->g[2];
   d.fkind = m->fkind;
@@ -1416,6 +1420,63 @@ __device__ void aba_setup_tree(const double* inert, double (*tab)[kTab], const i
   }
 }
 
+// The same recursion with a thread per frame, level by level: a frame of
+// height h (the longest path down to a leaf) runs at round h, once every frame
+// below it has passed its articulated inertia up.  Thread j (frame j, valid)
+// sums the passed-up inertias of its children (c = j + 1, then the frame after
+// each child's range), adds its own, forms U, D and 1/D into tab[j] and leaves
+// P - U U^T / D at pacc[j] for its parent.  levels: the model's largest height;
+// every thread of the workgroup calls it.
+__device__ void aba_setup_tree_levels(const double* inert, double (*tab)[kTab], const int* fend, double* pacc, int j,
+                                      bool valid, int hj, int levels) {
+  for (int h = 0; h <= levels; ++h) {
+    if (valid && hj == h) {
+      double P[21];
+#pragma unroll
+      for (int k = 0; k < 21; ++k) P[k] = 0.0;
+      for (int c = j + 1; c <= fend[j]; c = fend[c] + 1)
+#pragma unroll
+        for (int k = 0; k < 21; ++k) P[k] += pacc[c * 21 + k];
+      double in[10], s[6];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) in[k] = inert[j * 10 + k];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) s[k] = tab[j][k];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) P[k] += in[k];
+      P[7] -= in[8]; P[8] += in[7]; P[9] += in[8]; P[11] -= in[6]; P[12] -= in[7]; P[13] += in[6];
+      P[15] += in[9]; P[18] += in[9]; P[20] += in[9];
+      double U[6];
+      U[0] = P[0] * s[0] + P[1] * s[1] + P[2] * s[2] + P[6] * s[3] + P[7] * s[4] + P[8] * s[5];
+      U[1] = P[1] * s[0] + P[3] * s[1] + P[4] * s[2] + P[9] * s[3] + P[10] * s[4] + P[11] * s[5];
+      U[2] = P[2] * s[0] + P[4] * s[1] + P[5] * s[2] + P[12] * s[3] + P[13] * s[4] + P[14] * s[5];
+      U[3] = P[6] * s[0] + P[9] * s[1] + P[12] * s[2] + P[15] * s[3] + P[16] * s[4] + P[17] * s[5];
+      U[4] = P[7] * s[0] + P[10] * s[1] + P[13] * s[2] + P[16] * s[3] + P[18] * s[4] + P[19] * s[5];
+      U[5] = P[8] * s[0] + P[11] * s[1] + P[14] * s[2] + P[17] * s[3] + P[19] * s[4] + P[20] * s[5];
+      const double D = (s[0] * U[0] + s[1] * U[1]) + (s[2] * U[2] + s[3] * U[3]) + (s[4] * U[4] + s[5] * U[5]);
+      const double iD = (D > 0.0) ? 1.0 / D : 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) tab[j][6 + k] = U[k];
+      tab[j][12] = iD;
+      double V[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) V[k] = U[k] * iD;
+      P[0] -= U[0] * V[0]; P[1] -= U[0] * V[1]; P[2] -= U[0] * V[2];
+      P[3] -= U[1] * V[1]; P[4] -= U[1] * V[2]; P[5] -= U[2] * V[2];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) P[6 + 3 * r + c] -= U[r] * V[3 + c];
+      P[15] -= U[3] * V[3]; P[16] -= U[3] * V[4]; P[17] -= U[3] * V[5];
+      P[18] -= U[4] * V[4]; P[19] -= U[4] * V[5]; P[20] -= U[5] * V[5];
+#pragma unroll
+      for (int k = 0; k < 21; ++k) pacc[j * 21 + k] = P[k];
+    }
+    __threadfence_block();  // pacc goes through device memory
+    __syncthreads();
+  }
+}
+
 // x = H^{-1} b on a branched model (one thread, in place in xb): backward sweep
 // in reverse preorder u_f = b_f - s_f.p_f, p_parent += p_f + U_f u_f / D_f;
 // forward sweep in preorder x_f = (u_f - U_f.a_parent) / D_f, a_f = a_parent + s_f x_f.
@@ -1494,15 +1555,19 @@ __device__ __forceinline__ double tree_apply_inverse(const double (*tab)[kTab], 
   if (valid) xb[j] = v;
   __syncthreads();
   if (valid) {
+    // eight entries of the row requested before the first is used
     const double* row = W + wrow[j] - j;
-    double z0 = 0.0, z1 = 0.0;
+    double z[4] = {0.0, 0.0, 0.0, 0.0};
     int i = j;
-    for (; i + 1 <= fend_j; i += 2) {
-      z0 += row[i] * xb[i];
-      z1 += row[i + 1] * xb[i + 1];
+    for (; i + 7 <= fend_j; i += 8) {
+      double w[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w[k] = row[i + k];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) z[k & 3] += w[k] * xb[i + k];
     }
-    if (i <= fend_j) z0 += row[i] * xb[i];
-    yb[j] = (z0 + z1) * tab[j][12];
+    for (; i <= fend_j; ++i) z[0] += row[i] * xb[i];
+    yb[j] = ((z[0] + z[1]) + (z[2] + z[3])) * tab[j][12];
   }
   __syncthreads();
   double r = 0.0;

@@ -37,6 +37,8 @@ struct abd_model {
   int* fpar = nullptr;
   int* fend = nullptr;
   int* wrow = nullptr;  // branched models: row offsets of the explicit L^-1 of the preconditioner
+  int* fheight = nullptr;  // branched models: frame heights (longest path down to a leaf)
+  int* mheight = nullptr;  // branched models: largest frame height of each model
   // optional terms (slides, drag, contact points); fx = any of them present
   bool fx = false;
   signed char* fkind = nullptr;  // [n_dofs] 1 = slide, internal frame order; NULL: all hinges

@@ -336,7 +336,13 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   // a branched model, then its explicit L^-1 by rows, row f over the frames
   // below f (wrow: where each row starts); one-wave chains keep theirs in LDS
   std::vector<long long> hoff(nm + 1, 0);
-  std::vector<int> wrow(chain ? 0 : nd);
+  std::vector<int> wrow(chain ? 0 : nd), fheight(chain ? 0 : nd, 0), mheight(chain ? 0 : nm, 0);
+  if (!chain)
+    for (int i = 0; i < nm; ++i)
+      for (int fr = f0[i + 1] - 1; fr >= f0[i]; --fr) {
+        if (fpar[fr] >= 0) fheight[f0[i] + fpar[fr]] = std::max(fheight[f0[i] + fpar[fr]], fheight[fr] + 1);
+        mheight[i] = std::max(mheight[i], fheight[fr]);
+      }
   for (int i = 0; i < nm; ++i) {
     const long long k = f0[i + 1] - f0[i];
     long long w = 0;
@@ -406,7 +412,8 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
       (rc = alloc(m, &m->B64, 12 * (size_t)nd)) || (rc = alloc(m, &m->B32, 12 * (size_t)nd)) ||
       (rc = upload(m, &m->hoff, hoff)) || (rc = upload(m, &m->uidx, uidx)) ||
       (rc = upload(m, &m->fpar, fpar)) || (rc = upload(m, &m->fend, fend)) ||
-      (!chain && (rc = upload(m, &m->wrow, wrow))) ||
+      (!chain && ((rc = upload(m, &m->wrow, wrow)) || (rc = upload(m, &m->fheight, fheight)) ||
+                  (rc = upload(m, &m->mheight, mheight)))) ||
       (rc = alloc(m, &m->hist, max_frames > kMaxFrames ? 2 * kMaxHist * (size_t)nd : 1)) ||
       (rc = alloc(m, &m->hinv, (size_t)hoff[nm])) ||
       (any_slide && (rc = upload(m, &m->fkind, fkind))) || (any_drag && (rc = upload(m, &m->fdrag, fdrag))) ||

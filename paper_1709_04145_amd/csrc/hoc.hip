@@ -250,7 +250,11 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_hoc(HocArgs<U> args) {
         if (NW > 1) __threadfence_block();
         __syncthreads();
         if (TREE) {
-          if (lead) aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
+          if (PREC == ABD_FP64)
+            aba_setup_tree_levels(NW == 1 ? &L.inert[0][0] : Hi, L.tab, d.fend + f0, Hi + 10 * (size_t)nf, j, valid,
+                                  valid ? d.fheight[f] : 0, d.mheight[model]);
+          else if (lead)
+            aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, L.tab, L.tpar, Hi + 10 * (size_t)nf, nf);
         } else if (wave == 0) {
           aba_setup_rows(NW == 1 ? hl : Hi, L.tab, nf, lane);
         }

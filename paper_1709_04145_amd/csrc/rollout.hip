@@ -63,6 +63,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   // branched models, the recursion's accumulators [nf][21])
   double* Hi = d.hinv + d.hoff[model];
   const int fend_j = TREE && valid ? d.fend[f] : j;  // the last frame below this one
+  const int hj = TREE && valid ? d.fheight[f] : 0;    // the longest path below this frame
   const FrameGeo geo = load_geo<FX>(d, f, valid);
   const double eps_w = PREC == ABD_MIXED ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
   const double c1 = 1e-4, dlt = 0.1;
@@ -105,7 +106,8 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
     __syncthreads();
     PROF_T(t_r);
     if (TREE) {
-      if (lead) aba_setup_tree(NW == 1 ? &L.inert[0][0] : Hi, tab, L.tpar, Hi + 10 * (size_t)nf, nf);
+      aba_setup_tree_levels(NW == 1 ? &L.inert[0][0] : Hi, tab, d.fend + f0, Hi + 10 * (size_t)nf, j, valid, hj,
+                            d.mheight[model]);
     } else if (wave == 0) {
       aba_setup_rows<SEG>(NW == 1 ? hl : Hi, tab, nf, jl);
     }
