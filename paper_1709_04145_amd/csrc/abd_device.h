@@ -1006,6 +1006,9 @@ struct StepArgs {
   abd_step_stats* stats;      // [n_steps][n_models] or NULL
 };
 
+// Largest number of segments of chain_solve (chains of more than one wave).
+constexpr int kSolveSegs = 32;
+
 // Per-model LDS of the rollout kernel (one model per workgroup of NW waves):
 //   tab:   per frame s (6 = world hinge motion (w; p x w)), U (6 = I^A s), 1/D
 //   inert: per frame world spatial inertia about the origin (J 6, h 3, m), for
@@ -1014,6 +1017,7 @@ struct StepArgs {
 //   xb:    NW > 1: the vector swept by the recursion; branched models: the
 //          vector of the preconditioner's product
 //   xch:   scan exchange areas of BlockScan
+//   sgm, sgin: SEGSOLVE, the segment maps and entry states of chain_solve
 //   branched models (TREE): pointer-jumping buffers of TreeScan (tq, tv, tanc),
 //   frame parents (tpar) and the middle vector of the preconditioner's product
 //   (acc, first nf doubles)
@@ -1022,7 +1026,7 @@ struct StepArgs {
 // product has its own area (vb) instead of the recursion's table.
 // TAB false: the table lives in dynamic LDS sized to the batch (k_rollout's
 // one-model-per-wavefront chains), and this struct keeps a placeholder row.
-template <int NW, bool TREE = false, int SEGS = 1, bool TAB = true>
+template <int NW, bool TREE = false, int SEGS = 1, bool TAB = true, bool SEGSOLVE = false>
 struct RollLds {
   double tab[TAB ? kMaxFrames * NW : 1][kTab];
   double inert[(NW == 1 && TREE) ? kMaxFrames : 1][10];  // one-wave chains: in the inverse's LDS
@@ -1036,6 +1040,9 @@ struct RollLds {
   double acc[TREE ? kMaxFrames * NW : 1][6];
   int tanc[TREE ? kMaxFrames * NW : 1];
   int tpar[TREE ? kMaxFrames * NW : 1];
+  // SEGSOLVE (chains of more than one wave): the segment maps of chain_solve
+  double sgm[SEGSOLVE ? kSolveSegs : 1][7][6];
+  double sgin[SEGSOLVE ? kSolveSegs : 1][6];
 };
 using ModelLds = RollLds<1, false>;
 
@@ -1319,6 +1326,121 @@ __device__ __forceinline__ double apply_inverse_f32(const float* F, float* vb, i
   }
   __syncthreads();  // vb is reused by the next product
   return act ? (double)(r0 + r1) : 0.0;
+}
+
+// x = H^{-1} b for a chain of more than one wave, in place in xb (LDS), by
+// segments instead of one thread's two sweeps.  Each sweep is an affine
+// recurrence in a 6-vector: backward (tip to root) p <- p + w_f (b_f - s_f.p),
+// w_f = U_f / D_f, giving u_f = b_f - s_f.p; forward (root to tip)
+// a <- a + s_f (u_f - U_f.a) / D_f, giving x_f = (u_f - U_f.a) / D_f.  The
+// frames split into S segments of L (L = max(16, ceil(n / kSolveSegs))); per
+// sweep:
+//   1. seven threads per segment run its frames on the unit vectors (the map's
+//      columns) and on zero with the right-hand side (its offset) at once;
+//   2. one wave chains the segment maps from the sweep's first segment on,
+//      giving every segment's entry state;
+//   3. one thread per segment re-runs its frames from its entry state and
+//      writes u (or x).
+// The arithmetic of a segment's frames in step 3 is the sweep's own; only the
+// entry states are composed differently (the preconditioner's rounding).
+// Every thread of the workgroup calls it; xb must hold b and be visible.
+template <int NW>
+__device__ void chain_solve(const double (*tab)[kTab], double* xb, double (*sgm)[7][6], double (*sgin)[6], int n,
+                            int tid) {
+  const int L = n > 16 * kSolveSegs ? (n + kSolveSegs - 1) / kSolveSegs : 16;
+  const int S = (n + L - 1) / L;
+  const int g = tid / 7, c = tid % 7;
+  const bool grp = g < S;
+  const int lo = g * L, hi = (lo + L < n ? lo + L : n) - 1;
+  // ---- backward sweep
+  if (grp) {
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (c < 6) v[c] = 1.0;
+    for (int f = hi; f >= lo; --f) {
+      const double* r = tab[f];
+      const double sv = (r[0] * v[0] + r[1] * v[1]) + (r[2] * v[2] + r[3] * v[3]) + (r[4] * v[4] + r[5] * v[5]);
+      const double w = ((c == 6 ? xb[f] : 0.0) - sv) * r[12];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v[k] += r[6 + k] * w;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sgm[g][c][k] = v[k];
+  }
+  __syncthreads();
+  if (tid < kWave) {  // entry states from the tip segment down
+    const int cc = tid < 6 ? tid : 5;
+    double p = 0.0;
+    for (int gg = S - 1; gg >= 0; --gg) {
+      if (tid < 6) sgin[gg][tid] = p;
+      double pk[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) pk[k] = __shfl(p, k);
+      double np = sgm[gg][6][cc];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) np += sgm[gg][k][cc] * pk[k];
+      p = np;
+    }
+  }
+  __syncthreads();
+  if (grp && c == 0) {
+    double p[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] = sgin[g][k];
+    for (int f = hi; f >= lo; --f) {
+      const double* r = tab[f];
+      const double sp = (r[0] * p[0] + r[1] * p[1]) + (r[2] * p[2] + r[3] * p[3]) + (r[4] * p[4] + r[5] * p[5]);
+      const double u = xb[f] - sp;
+      xb[f] = u;
+      const double w = u * r[12];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) p[k] += r[6 + k] * w;
+    }
+  }
+  __syncthreads();
+  // ---- forward sweep
+  if (grp) {
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (c < 6) v[c] = 1.0;
+    for (int f = lo; f <= hi; ++f) {
+      const double* r = tab[f];
+      const double Uv = (r[6] * v[0] + r[7] * v[1]) + (r[8] * v[2] + r[9] * v[3]) + (r[10] * v[4] + r[11] * v[5]);
+      const double x = ((c == 6 ? xb[f] : 0.0) - Uv) * r[12];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v[k] += r[k] * x;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sgm[g][c][k] = v[k];
+  }
+  __syncthreads();
+  if (tid < kWave) {  // entry states from the root segment up
+    const int cc = tid < 6 ? tid : 5;
+    double a = 0.0;
+    for (int gg = 0; gg < S; ++gg) {
+      if (tid < 6) sgin[gg][tid] = a;
+      double ak[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) ak[k] = __shfl(a, k);
+      double na = sgm[gg][6][cc];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) na += sgm[gg][k][cc] * ak[k];
+      a = na;
+    }
+  }
+  __syncthreads();
+  if (grp && c == 0) {
+    double a[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[k] = sgin[g][k];
+    for (int f = lo; f <= hi; ++f) {
+      const double* r = tab[f];
+      const double Ua = (r[6] * a[0] + r[7] * a[1]) + (r[8] * a[2] + r[9] * a[3]) + (r[10] * a[4] + r[11] * a[5]);
+      const double x = (xb[f] - Ua) * r[12];
+      xb[f] = x;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) a[k] += r[k] * x;
+    }
+  }
+  __syncthreads();
 }
 
 // x = H^{-1} b in O(n) by one thread (models of more than one wave): backward

@@ -15,7 +15,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   // chains of one wavefront each: the recursion's table in the dynamic LDS, so
   // that all of it is sized to the batch's largest model
   constexpr bool kDynTab = NW == 1 && !TREE && SEGS == 1;
-  __shared__ RollLds<NW, TREE, SEGS, !kDynTab> L;
+  __shared__ RollLds<NW, TREE, SEGS, !kDynTab, (NW > 1 && !TREE)> L;
   // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
   // y in [m, 2m), ps doubles per slot (one per frame of the batch's largest
   // model for chains of one wavefront each, else one per lane); one-wave
@@ -273,8 +273,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         } else {
           L.xb[j] = valid ? qv : 0.0;
           __syncthreads();
-          if (lead) aba_solve(tab, L.xb, nf);
-          __syncthreads();
+          chain_solve<NW>(tab, L.xb, L.sgm, L.sgin, nf, j);
           r = ld_if(&L.xb[j], valid);
         }
         PROF_ADD(1, t_a);
