@@ -1017,7 +1017,6 @@ constexpr int kSolveSegs = 32;
 //   xb:    NW > 1: the vector swept by the recursion; branched models: the
 //          vector of the preconditioner's product
 //   xch:   scan exchange areas of BlockScan
-//   sgm, sgin: SEGSOLVE, the segment maps and entry states of chain_solve
 //   branched models (TREE): pointer-jumping buffers of TreeScan (tq, tv, tanc),
 //   frame parents (tpar) and the middle vector of the preconditioner's product
 //   (acc, first nf doubles)
@@ -1026,7 +1025,7 @@ constexpr int kSolveSegs = 32;
 // product has its own area (vb) instead of the recursion's table.
 // TAB false: the table lives in dynamic LDS sized to the batch (k_rollout's
 // one-model-per-wavefront chains), and this struct keeps a placeholder row.
-template <int NW, bool TREE = false, int SEGS = 1, bool TAB = true, bool SEGSOLVE = false>
+template <int NW, bool TREE = false, int SEGS = 1, bool TAB = true>
 struct RollLds {
   double tab[TAB ? kMaxFrames * NW : 1][kTab];
   double inert[(NW == 1 && TREE) ? kMaxFrames : 1][10];  // one-wave chains: in the inverse's LDS
@@ -1040,11 +1039,24 @@ struct RollLds {
   double acc[TREE ? kMaxFrames * NW : 1][6];
   int tanc[TREE ? kMaxFrames * NW : 1];
   int tpar[TREE ? kMaxFrames * NW : 1];
-  // SEGSOLVE (chains of more than one wave): the segment maps of chain_solve
-  double sgm[SEGSOLVE ? kSolveSegs : 1][7][6];
-  double sgin[SEGSOLVE ? kSolveSegs : 1][6];
 };
 using ModelLds = RollLds<1, false>;
+
+// LDS of chains of more than one wave in k_rollout (a variable of its own, so
+// that the kernels without it allocate none): the segment maps and entry
+// states of chain_solve and the staged inertia records of aba_setup_rows_staged.
+template <bool ON>
+struct ChainLds {
+  double sgm[kSolveSegs][7][6];
+  double sgin[kSolveSegs][6];
+  double stg[2][kWave * 10];
+};
+template <>
+struct ChainLds<false> {
+  double sgm[1][7][6];
+  double sgin[1][6];
+  double stg[1][kWave * 10];
+};
 
 // 1/x for x > 0 from the hardware reciprocal and one Newton step (a few ulp;
 // used where the value only shapes a preconditioner).
@@ -1066,14 +1078,9 @@ __device__ __forceinline__ double recip(double x) {
 // 10-entry record (J 00 01 02 11 12 22, h, m).  The whole wave runs; lanes >= 6
 // shadow row 5 and store nothing.  The next frame's inputs are read while the
 // current one is processed.
-template <int SEG = kWave>
-__device__ void aba_setup_rows(const double* inert, double (*tab)[kTab], int nf_in, int lane) {
-  // wave-uniform frame loop (segments of packed models: each its own)
-  const int nf = SEG == kWave ? __builtin_amdgcn_readfirstlane(nf_in) : nf_in;
-  if (nf <= 0) return;
-  const int r = lane < 6 ? lane : 5;
-  int idx[6];
-  float sgn[6];  // -1, 0, +1
+// Lane r's picks of row r of the frame inertia from the 10-entry record:
+// entry c = sgn[c] * record[idx[c]].
+__device__ __forceinline__ void rows_pick(int r, int idx[6], float sgn[6]) {
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     const int a = r < 3 ? r : c, b = r < 3 ? c : r;  // (3x3 block row, column) of the pick
@@ -1095,6 +1102,37 @@ __device__ void aba_setup_rows(const double* inert, double (*tab)[kTab], int nf_
       }
     }
   }
+}
+
+// One frame of the recursion on the rows: P += in (this lane's row of the frame
+// inertia), U_r = P_r . s, broadcast, D, 1/D, table row f, P -= U U^T / D.
+template <int SEG>
+__device__ __forceinline__ void rows_step(double P[6], const double in[6], const double s[6], double* tabf,
+                                          int lane) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) P[c] += in[c];
+  const double U = (P[0] * s[0] + P[1] * s[1]) + (P[2] * s[2] + P[3] * s[3]) + (P[4] * s[4] + P[5] * s[5]);
+  double Uc[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) Uc[c] = SEG == kWave ? readlane(U, c) : __shfl(U, c, SEG);
+  const double D = (s[0] * Uc[0] + s[1] * Uc[1]) + (s[2] * Uc[2] + s[3] * Uc[3]) + (s[4] * Uc[4] + s[5] * Uc[5]);
+  const double iD = (D > 0.0) ? recip(D) : 0.0;
+  if (lane < 6) tabf[6 + lane] = U;
+  if (lane == 0) tabf[12] = iD;
+  const double V = U * iD;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) P[c] -= V * Uc[c];
+}
+
+template <int SEG = kWave>
+__device__ void aba_setup_rows(const double* inert, double (*tab)[kTab], int nf_in, int lane) {
+  // wave-uniform frame loop (segments of packed models: each its own)
+  const int nf = SEG == kWave ? __builtin_amdgcn_readfirstlane(nf_in) : nf_in;
+  if (nf <= 0) return;
+  const int r = lane < 6 ? lane : 5;
+  int idx[6];
+  float sgn[6];  // -1, 0, +1
+  rows_pick(r, idx, sgn);
   double P[6] = {0, 0, 0, 0, 0, 0};
   double in[6], s[6], inn[6], sn[6];
 #pragma unroll
@@ -1111,19 +1149,55 @@ __device__ void aba_setup_rows(const double* inert, double (*tab)[kTab], int nf_
       inn[c] = (double)sgn[c] * inert[fn * 10 + idx[c]];
       sn[c] = tab[fn][c];
     }
+    rows_step<SEG>(P, in, s, tab[f], lane);
+  }
+}
+
+// The same recursion for a chain of more than one wave, whose inertia records
+// live in device memory: they are staged into LDS 64 frames at a time (buf, two
+// chunks of 640 doubles), the waves other than wave 0 loading the next chunk
+// while wave 0 runs the current one.  Every thread of the workgroup calls it.
+template <int NW>
+__device__ void aba_setup_rows_staged(const double* inert, double (*tab)[kTab], int nf, int tid,
+                                      double (*buf)[kWave * 10]) {
+  static_assert(NW > 1, "one-wave chains keep their inertias in LDS");
+  const int wave = tid / kWave, lane = tid % kWave;
+  const int ktop = (nf - 1) / kWave;
+  auto stage = [&](int k, int t0, int stride) {
+    const int base = k * kWave, cnt = (nf - base < kWave ? nf - base : kWave) * 10;
+    for (int e = t0; e < cnt; e += stride) buf[k & 1][e] = inert[(size_t)base * 10 + e];
+  };
+  stage(ktop, tid, NW * kWave);
+  __syncthreads();
+  const int r = lane < 6 ? lane : 5;
+  int idx[6];
+  float sgn[6];
+  rows_pick(r, idx, sgn);
+  double P[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = ktop; k >= 0; --k) {
+    if (wave > 0 && k > 0) stage(k - 1, tid - kWave, (NW - 1) * kWave);
+    if (wave == 0) {
+      const int lo = k * kWave, hi = (lo + kWave < nf ? lo + kWave : nf) - 1;
+      const double* ib = buf[k & 1];
+      double in[6], s[6], inn[6], sn[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) P[c] += in[c];
-    const double U = (P[0] * s[0] + P[1] * s[1]) + (P[2] * s[2] + P[3] * s[3]) + (P[4] * s[4] + P[5] * s[5]);
-    double Uc[6];
+      for (int c = 0; c < 6; ++c) {
+        inn[c] = (double)sgn[c] * ib[(hi - lo) * 10 + idx[c]];
+        sn[c] = tab[hi][c];
+      }
+      for (int f = hi; f >= lo; --f) {
+        const int fn = f > lo ? f - 1 : lo;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) Uc[c] = SEG == kWave ? readlane(U, c) : __shfl(U, c, SEG);
-    const double D = (s[0] * Uc[0] + s[1] * Uc[1]) + (s[2] * Uc[2] + s[3] * Uc[3]) + (s[4] * Uc[4] + s[5] * Uc[5]);
-    const double iD = (D > 0.0) ? recip(D) : 0.0;
-    if (lane < 6) tab[f][6 + lane] = U;
-    if (lane == 0) tab[f][12] = iD;
-    const double V = U * iD;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) P[c] -= V * Uc[c];
+        for (int c = 0; c < 6; ++c) {
+          in[c] = inn[c];
+          s[c] = sn[c];
+          inn[c] = (double)sgn[c] * ib[(fn - lo) * 10 + idx[c]];
+          sn[c] = tab[fn][c];
+        }
+        rows_step<kWave>(P, in, s, tab[f], lane);
+      }
+    }
+    __syncthreads();
   }
 }
 

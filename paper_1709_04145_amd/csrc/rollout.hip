@@ -15,7 +15,8 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
   // chains of one wavefront each: the recursion's table in the dynamic LDS, so
   // that all of it is sized to the batch's largest model
   constexpr bool kDynTab = NW == 1 && !TREE && SEGS == 1;
-  __shared__ RollLds<NW, TREE, SEGS, !kDynTab, (NW > 1 && !TREE)> L;
+  __shared__ RollLds<NW, TREE, SEGS, !kDynTab> L;
+  __shared__ ChainLds<(NW > 1 && !TREE)> CL;
   // one-wave models: L-BFGS pairs of the current step, s in ring slots [0, m),
   // y in [m, 2m), ps doubles per slot (one per frame of the batch's largest
   // model for chains of one wavefront each, else one per lane); one-wave
@@ -105,11 +106,13 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
     if (NW > 1) __threadfence_block();  // inertias go through device memory
     __syncthreads();
     PROF_T(t_r);
-    if (TREE) {
+    if constexpr (TREE) {
       aba_setup_tree_levels(NW == 1 ? &L.inert[0][0] : Hi, tab, d.fend + f0, Hi + 10 * (size_t)nf, j, valid, hj,
                             d.mheight[model]);
-    } else if (wave == 0) {
-      aba_setup_rows<SEG>(NW == 1 ? hl : Hi, tab, nf, jl);
+    } else if constexpr (NW > 1) {
+      aba_setup_rows_staged<NW>(Hi, tab, nf, j, CL.stg);
+    } else {
+      if (wave == 0) aba_setup_rows<SEG>(hl, tab, nf, jl);
     }
     __syncthreads();
     if (TREE) {
@@ -273,7 +276,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
         } else {
           L.xb[j] = valid ? qv : 0.0;
           __syncthreads();
-          chain_solve<NW>(tab, L.xb, L.sgm, L.sgin, nf, j);
+          chain_solve<NW>(tab, L.xb, CL.sgm, CL.sgin, nf, j);
           r = ld_if(&L.xb[j], valid);
         }
         PROF_ADD(1, t_a);
