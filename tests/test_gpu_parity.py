@@ -268,14 +268,17 @@ def test_ragged_mixed_joint_chains_mixed():
 
 
 def test_identity_preconditioner_fp64():
+    """Without the inertia preconditioner (H0 = gamma I), both sides solved to a
+    1e-12 relative gradient (about 1000 iterations on the 10-link chain): the
+    same 1e-10 bound as the preconditioned path."""
     wl = W.config(1)
     q = wl.q0
     say("identity preconditioner")
-    ref, rst = Oracle(wl.model).step(q, q, wl.step.dt, precond=0, max_iter=3000)
-    out, st = _step_gpu(wl.model, q, q, abd.StepOptions(dt=wl.step.dt, precond=abd.PRECOND_IDENTITY,
-                                                         max_iter=3000))
-    assert st["flag"][0] == 1 and rst["flag"][0] == 1
-    assert rel_q(out, ref) <= 1e-6
+    ref, rst = Oracle(wl.model).step(q, q, wl.step.dt, precond=0, tol=1e-12, max_iter=20000)
+    out, st = _step_gpu(wl.model, q, q, abd.StepOptions(dt=wl.step.dt, precond=abd.PRECOND_IDENTITY, tol=1e-12,
+                                                         max_iter=20000))
+    assert st["flag"][0] == 1 and rst["flag"][0] == 1, (st["flag"], rst["flag"])
+    assert rel_q(out, ref) <= 1e-10, rel_q(out, ref)
 
 
 def _ill_conditioned_chains(n_models, seed):
