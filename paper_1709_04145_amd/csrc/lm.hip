@@ -501,6 +501,81 @@ __device__ void chol_solve_lds(const double* Uf, int N, double* x) {
   }
 }
 
+// chol_solve_lds for a workgroup of one wave and N <= 64 NS: the vector in
+// registers (lane i holds entries i, i + 64, ...), each row of the factor read
+// as one coalesced run while the previous row is used, and no barrier; the
+// same arithmetic per entry as chol_solve_lds (bitwise the same result).
+template <int NS>
+__device__ void chol_solve_wave(const double* Uf, int N, double* x) {
+  const int lane = threadIdx.x;
+  double v[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) v[s] = lane + kWave * s < N ? x[lane + kWave * s] : 0.0;
+  // U^T y = b: column j of U^T is row j of U (right of the diagonal)
+  double rn[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rn[s] = lane + kWave * s < N ? Uf[lane + kWave * s] : 0.0;
+  for (int jr = 0; jr < N; ++jr) {
+    double r[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) r[s] = rn[s];
+    if (jr + 1 < N)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int i = lane + kWave * s;
+        rn[s] = i < N ? Uf[(size_t)(jr + 1) * N + i] : 0.0;
+      }
+    const int so = jr / kWave, lo = jr % kWave;
+    double xj = 0.0, dj = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (s == so) {
+        xj = readlane(v[s], lo);
+        dj = readlane(r[s], lo);
+      }
+    const double yj = xj / dj;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int i = lane + kWave * s;
+      if (i > jr && i < N) v[s] -= r[s] * yj;
+      if (s == so && lane == lo) v[s] = yj;
+    }
+  }
+  // U x = y: column j of U above the diagonal is the mirrored row j
+#pragma unroll
+  for (int s = 0; s < NS; ++s) rn[s] = lane + kWave * s < N ? Uf[(size_t)(N - 1) * N + lane + kWave * s] : 0.0;
+  for (int jr = N - 1; jr >= 0; --jr) {
+    double r[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) r[s] = rn[s];
+    if (jr > 0)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int i = lane + kWave * s;
+        rn[s] = i < N ? Uf[(size_t)(jr - 1) * N + i] : 0.0;
+      }
+    const int so = jr / kWave, lo = jr % kWave;
+    double xj = 0.0, dj = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (s == so) {
+        xj = readlane(v[s], lo);
+        dj = readlane(r[s], lo);
+      }
+    const double xv = xj / dj;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int i = lane + kWave * s;
+      if (i < jr) v[s] -= r[s] * xv;
+      if (s == so && lane == lo) v[s] = xv;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+    if (lane + kWave * s < N) x[lane + kWave * s] = v[s];
+  __syncthreads();
+}
+
 // out = M^T v (out[c] = sum_k M[k][c] v[k]); v, out: LDS vectors of N.
 template <int NW>
 __device__ void matvec_t(const double* Mx, int N, const double* v, double* out, double scale) {
@@ -939,8 +1014,13 @@ __global__ void __launch_bounds__(NW* kWave, 1) k_rollout_lm2(Lm2Args la) {
       }
       if (valid) vv[j] = -g;
       __syncthreads();
-      chol_solve_lds<NW>(Um, N, vv);
-      matvec<NW>(Am, N, vv, hv);
+      if constexpr (NW == 1) {
+        chol_solve_wave<1>(Um, N, vv);
+        matvec_t<NW>(Am, N, vv, hv, 1.0);  // H_q v (the assembled H_q is symmetric)
+      } else {
+        chol_solve_lds<NW>(Um, N, vv);
+        matvec<NW>(Am, N, vv, hv);
+      }
       const double v = valid ? vv[j] : 0.0;
       const double pred = -ws.sum(g * v + 0.5 * v * (valid ? hv[j] : 0.0));
       const double x = q + v;
