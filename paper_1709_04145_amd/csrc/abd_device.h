@@ -137,20 +137,6 @@ __device__ __forceinline__ void wave_sum2(double& a, double& b) {
   b = readlane(b, 63);
 }
 
-// Four independent sums in one pass (each value takes the steps of wave_sum).
-__device__ __forceinline__ void wave_sum4(double& a, double& b, double& c, double& d) {
-  a += dpp0<0x111>(a); b += dpp0<0x111>(b); c += dpp0<0x111>(c); d += dpp0<0x111>(d);
-  a += dpp0<0x112>(a); b += dpp0<0x112>(b); c += dpp0<0x112>(c); d += dpp0<0x112>(d);
-  a += dpp0<0x114>(a); b += dpp0<0x114>(b); c += dpp0<0x114>(c); d += dpp0<0x114>(d);
-  a += dpp0<0x118>(a); b += dpp0<0x118>(b); c += dpp0<0x118>(c); d += dpp0<0x118>(d);
-  a += dpp<0x142, 0xA>(0.0, a); b += dpp<0x142, 0xA>(0.0, b); c += dpp<0x142, 0xA>(0.0, c); d += dpp<0x142, 0xA>(0.0, d);
-  a += dpp<0x143, 0xC>(0.0, a); b += dpp<0x143, 0xC>(0.0, b); c += dpp<0x143, 0xC>(0.0, c); d += dpp<0x143, 0xC>(0.0, d);
-  a = readlane(a, 63);
-  b = readlane(b, 63);
-  c = readlane(c, 63);
-  d = readlane(d, 63);
-}
-
 // Load *p on every lane and keep it where c holds (0 elsewhere).  The address
 // must be valid on every lane (callers clamp indices to the model's frames), so
 // the load is unconditional and needs no execution-mask branch.
@@ -483,10 +469,7 @@ struct WaveScan {
   }
   __device__ __forceinline__ double sum(double v) { return wave_sum(v); }
   __device__ __forceinline__ void sum2(double& a, double& b) { wave_sum2(a, b); }
-  __device__ __forceinline__ void sum4(double& a, double& b, double& c, double& d) { wave_sum4(a, b, c, d); }
   __device__ __forceinline__ bool all_finite(double x) { return !__any(!isfinite(x)); }
-  // true where no frame of the model has c (a ballot, no sum)
-  __device__ __forceinline__ bool none(bool c) { return !__any(c); }
   __device__ __forceinline__ void sync() {}
   // a model-uniform value kept in scalar registers
   __device__ __forceinline__ double uniform(double v) { return wave_uniform(v); }
@@ -553,21 +536,10 @@ struct SegScan {
     a = last(a);
     b = last(b);
   }
-  __device__ __forceinline__ void sum4(double& a, double& b, double& c, double& d) {
-    a = prefix(a);
-    b = prefix(b);
-    c = prefix(c);
-    d = prefix(d);
-    a = last(a);
-    b = last(b);
-    c = last(c);
-    d = last(d);
-  }
-  __device__ __forceinline__ bool all_finite(double x) { return none(!isfinite(x)); }
-  __device__ __forceinline__ bool none(bool c) {
-    const unsigned long long any = __ballot(c);
+  __device__ __forceinline__ bool all_finite(double x) {
+    const unsigned long long bad = __ballot(!isfinite(x));
     const int base = (int)(threadIdx.x % kWave) - fl;
-    return ((any >> base) & ((1ull << S) - 1)) == 0;
+    return ((bad >> base) & ((1ull << S) - 1)) == 0;
   }
   __device__ __forceinline__ void sync() {}
   __device__ __forceinline__ double uniform(double v) { return v; }
@@ -675,7 +647,6 @@ struct BlockScan {
     return t;
   }
   __device__ __forceinline__ bool all_finite(double x) { return sum(isfinite(x) ? 0.0 : 1.0) == 0.0; }
-  __device__ __forceinline__ bool none(bool c) { return sum(c ? 1.0 : 0.0) == 0.0; }
   __device__ __forceinline__ void sum2(double& x, double& y) {
     wave_sum2(x, y);
     double* a = next_area();
@@ -689,28 +660,6 @@ struct BlockScan {
     for (int w = 0; w < NW; ++w) {
       x += a[w * 8];
       y += a[w * 8 + 1];
-    }
-  }
-  // four sums with one exchange
-  __device__ __forceinline__ void sum4(double& x, double& y, double& z, double& u) {
-    wave_sum4(x, y, z, u);
-    double* a = next_area();
-    if (lane == 0) {
-      a[wave * 8] = x;
-      a[wave * 8 + 1] = y;
-      a[wave * 8 + 2] = z;
-      a[wave * 8 + 3] = u;
-    }
-    __syncthreads();
-    x = 0.0;
-    y = 0.0;
-    z = 0.0;
-    u = 0.0;
-    for (int w = 0; w < NW; ++w) {
-      x += a[w * 8];
-      y += a[w * 8 + 1];
-      z += a[w * 8 + 2];
-      u += a[w * 8 + 3];
     }
   }
 };

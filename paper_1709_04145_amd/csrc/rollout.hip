@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
             }
             // an accepted trial point that equals q in every coordinate is no
             // progress: at this precision the iteration cannot move any more
-            if (sc.none(valid && x != q)) {
+            if (sc.uniform(sc.sum(valid && x != q ? 1.0 : 0.0)) == 0.0) {
               if (PREC == ABD_MIXED && f32) {
                 to64 = true;
                 break;
@@ -372,7 +372,8 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
             const double sv = x - q;
             const double y = rt.g - g;
             double sy = sv * y, ss = sv * sv, yy = y * y, gg = rt.g * rt.g;
-            sc.sum4(sy, ss, yy, gg);
+            sc.sum2(sy, ss);
+            sc.sum2(yy, gg);
             if (sy > 1e-12 * sqrt(ss) * sqrt(yy)) {
               gam = sc.uniform(sy / yy);
               head = count == 0 ? 0 : (head + 1) % args.m;
