@@ -58,7 +58,8 @@ LBFGS_BYTES = 128                       # read g, q, s/y history (m=5); write d,
 PRECOND_BYTES = 240                     # per iteration: two sweeps over the recursion records (s, U, 1/D) + b/u/x
 SETUP_BYTES = 328                       # per step: read q_{k-1}, q_k, axis/offset, M; write B (f64+f32), records
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_rollout_chains4096_hbm_traffic.md")
+# committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of the order-2 rollout kernel, one per workload
+TRAFFIC_PROFILE_GLOB = os.path.join(ROOT, "profiles", "k_rollout_*_hbm_traffic.md")
 
 
 # tolerance of the parity sample: at 1e-12 a step's result is implied to ~3e-11
@@ -85,13 +86,14 @@ def kernel_source_digest():
 
 def measured_traffic(workload, precision, warmup, steps):
     """HBM bytes of the timed launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary: its machine-readable blocks (one per measured launch, separated by
+    summaries: their machine-readable blocks (one per measured launch, separated by
     blank lines) are searched for one taken on this kernel source, workload,
     precision and step window; None if there is none."""
-    try:
-        text = open(TRAFFIC_PROFILE).read()
-    except OSError:
-        return None
+    import glob
+    text = ""
+    for path in sorted(glob.glob(TRAFFIC_PROFILE_GLOB)):
+        with open(path) as f:
+            text += f.read() + "\n\n"
     digest = kernel_source_digest()
     want = {"source_sha256": digest, "workload": workload, "precision": precision,
             "warmup": str(warmup), "steps": str(steps)}

@@ -11,5 +11,5 @@ from paper_1709_04145_amd import workloads as W
 def test_traffic_profile_matches_the_kernel_sources():
     traffic = bench.measured_traffic(W.CONFIG_NAMES[2], "mixed", 5, 20)
     assert traffic is not None, ("no HBM-traffic block for source digest " + bench.kernel_source_digest() +
-                                 " in " + bench.TRAFFIC_PROFILE)
+                                 " in " + bench.TRAFFIC_PROFILE_GLOB)
     assert traffic > 0
