@@ -129,7 +129,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the teacher-forced parity sample")
-    ap.add_argument("--cpu-models", type=int, default=1024, help="models in the CPU baseline sample")
+    ap.add_argument("--cpu-models", type=int, default=4096, help="models in the CPU baseline sample")
     ap.add_argument("--vjp", action="store_true",
                     help="also time the rollout's reverse-mode derivative (abd_rollout_vjp; on for configuration 5)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -346,6 +346,7 @@ def main():
             qn, _ = orc.step(qa, qb, wl.step.dt, tq(k), **kw)
             qa, qb = qb, qn
             print(f"[bench] cpu baseline: warm-up step {k} done", file=sys.stderr, flush=True)
+        qa0, qb0 = qa.copy(), qb.copy()  # the state the timed steps start from
         t0 = time.perf_counter()
         nsteps = 0
         while nsteps < args.steps:
@@ -362,17 +363,16 @@ def main():
                                "sample": f"{len(sample)} of {desc.n_models} models ({sub.n_links} links), steps "
                                          f"{args.warmup}..{args.warmup + nsteps - 1} after a {args.warmup}-step "
                                          f"warm-up from rest, float64, OpenMP over models, {el:.1f} s"}
-        # one core: the same steps on the first 64 models of the sample
-        n1 = min(64, len(sample))
+        # one core: the same timed steps, from the same state, on the first models
+        # of the sample, as many as one core steps in about 2 s by the rate above
+        cpu_s_per_link_step = el * threads / (sub.n_links * nsteps)
+        links = np.cumsum(np.diff(sub.link_offset))
+        n1 = max(1, int(np.searchsorted(links, 2.0 / cpu_s_per_link_step, side="right")))
         sub1 = sub.subset(np.arange(n1))
         idx1 = sub.dof_subset_index(np.arange(n1))
         orc1 = Oracle(sub1, threads=1)
-        qa1 = wl.q0[idx][idx1].copy()
-        qb1 = qa1.copy()
+        qa1, qb1 = qa0[idx1].copy(), qb0[idx1].copy()
         tq1 = (lambda k: None) if wl.torque is None else (lambda k: wl.torque[k][idx][idx1])
-        for k in range(args.warmup):
-            qn, _ = orc1.step(qa1, qb1, wl.step.dt, tq1(k), **kw)
-            qa1, qb1 = qb1, qn
         t0 = time.perf_counter()
         n1steps = 0
         while n1steps < args.steps and time.perf_counter() - t0 < 15.0:
