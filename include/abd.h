@@ -40,7 +40,7 @@ extern "C" {
 #define ABD_EINVAL (-1)   /* invalid argument */
 #define ABD_ENOMEM (-2)   /* device allocation failed */
 #define ABD_EDEVICE (-3)  /* HIP runtime error */
-#define ABD_ENOTSUP (-4)  /* valid input that this build does not handle */
+#define ABD_ENOTSUP (-4)  /* valid input that this library does not handle */
 
 #define ABD_FP64 0        /* every operation in double precision */
 #define ABD_MIXED 1       /* kinematics and energy terms in float32 until the
@@ -189,7 +189,7 @@ typedef struct {
  * body integral of Eq. EQ into a contraction with the pose.  Checks
  * topology, finite values, unit axes, positive mass and positive semi-definite
  * moment tensors (ABD_EINVAL).  Synchronous.  *out receives the handle.
- * Limits of this build (ABD_ENOTSUP): serial chains of up to 1024 DOFs per
+ * Limits of this library (ABD_ENOTSUP): serial chains of up to 1024 DOFs per
  * model, branched models (trees) of up to 256 DOFs per model, models with
  * slides, drag or contact points of up to 256 DOFs.  abd_hvp and
  * abd_rollout_vjp take serial chains of up to 64 DOFs; order_K > 2 takes models

@@ -108,7 +108,7 @@ int check_opts(const abd_step_opts* o, bool for_step) {
     return fail(ABD_EINVAL, "precision must be ABD_FP64 or ABD_MIXED");
   if (!for_step) return ABD_OK;
   if (o->order_K < 2) return fail(ABD_EINVAL, "order_K must be >= 2");
-  if (o->order_K > 4) return fail(ABD_ENOTSUP, "order_K > 4 is not handled by this build");
+  if (o->order_K > 4) return fail(ABD_ENOTSUP, "order_K > 4 is not handled by this library");
   if (o->lbfgs_m < 1 || o->lbfgs_m > 10) return fail(ABD_EINVAL, "lbfgs_m must be in 1..10");
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(ABD_EINVAL, "tol must be finite and >= 0");
   if (o->max_iter < 0) return fail(ABD_EINVAL, "max_iter must be >= 0");
@@ -238,7 +238,7 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
     }
   }
   if (max_frames > kMaxFrames * kMaxWaves)
-    return fail(ABD_ENOTSUP, "models with more than 1024 DOFs are not handled by this build");
+    return fail(ABD_ENOTSUP, "models with more than 1024 DOFs are not handled by this library");
   // optional terms: slides, drag, contact points
   bool any_slide = false, any_drag = false;
   if (desc->dof_kind)
@@ -274,9 +274,9 @@ int abd_create_model(const abd_model_desc* desc, abd_model** out) {
   const bool fx = any_slide || any_drag || nc > 0;
   if (fx && max_frames > 4 * kMaxFrames)
     return fail(ABD_ENOTSUP, "models with slides, drag or contact points of more than 256 DOFs are not handled "
-                             "by this build");
+                             "by this library");
   if (!chain && max_frames > 4 * kMaxFrames)
-    return fail(ABD_ENOTSUP, "branched models of more than 256 DOFs are not handled by this build");
+    return fail(ABD_ENOTSUP, "branched models of more than 256 DOFs are not handled by this library");
   // Internal frame order: depth-first preorder of each model's links (children
   // in index order), the frames of a link consecutive, so that the frames below
   // any frame form a contiguous range.  For chains this is the caller's order.
@@ -465,7 +465,7 @@ int abd_step(abd_model* m, const abd_step_opts* o, const double* q_hist, const d
   if (q_out < q_hist + 2 * (size_t)m->n_dofs && q_hist < q_out + out_len)
     return fail(ABD_EINVAL, "q_out overlaps q_hist");
   if ((rc = check_device(m))) return rc;
-  if (m->fx && (o->order_K > 2 || o->solver == ABD_SOLVER_LM)) return fail(ABD_ENOTSUP, "models with slides, drag or contact points take order_K = 2 with ABD_SOLVER_LBFGS in this build");
+  if (m->fx && (o->order_K > 2 || o->solver == ABD_SOLVER_LM)) return fail(ABD_ENOTSUP, "models with slides, drag or contact points take order_K = 2 with ABD_SOLVER_LBFGS in this library");
   if (o->order_K > 2 && o->solver == ABD_SOLVER_LM)
     return abd_impl::launch_lm_hoc(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
   if (o->order_K > 2) return abd_impl::launch_hoc(m, o, q_hist, q_hist + m->n_dofs, tau, q_out, stats, 1, stream);
@@ -480,7 +480,7 @@ int abd_rollout(abd_model* m, const abd_step_opts* o, const double* q_init, cons
   int rc = check_rollout_args(m, o, q_init, q_traj, n_steps);
   if (rc || m->n_models == 0 || n_steps == 0) return rc;
   const size_t nd = m->n_dofs;
-  if (m->fx && (o->order_K > 2 || o->solver == ABD_SOLVER_LM)) return fail(ABD_ENOTSUP, "models with slides, drag or contact points take order_K = 2 with ABD_SOLVER_LBFGS in this build");
+  if (m->fx && (o->order_K > 2 || o->solver == ABD_SOLVER_LM)) return fail(ABD_ENOTSUP, "models with slides, drag or contact points take order_K = 2 with ABD_SOLVER_LBFGS in this library");
   if (o->order_K > 2 && o->solver == ABD_SOLVER_LM)
     return abd_impl::launch_lm_hoc(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
   if (o->order_K > 2) return abd_impl::launch_hoc(m, o, q_init, q_init + nd, tau, q_traj, stats, n_steps, stream);
@@ -548,7 +548,7 @@ int abd_objective_grad(abd_model* m, const abd_step_opts* o, const double* q, co
   if (!q || !q_hist || !E) return fail(ABD_EINVAL, "q, q_hist and E must not be NULL");
   if ((rc = check_device(m))) return rc;
   if (o->order_K < 2) return fail(ABD_EINVAL, "order_K must be >= 2");
-  if (o->order_K > 4) return fail(ABD_ENOTSUP, "order_K > 4 is not handled by this build");
+  if (o->order_K > 4) return fail(ABD_ENOTSUP, "order_K > 4 is not handled by this library");
   if (m->fx && o->order_K > 2)
     return fail(ABD_ENOTSUP, "slides, drag and contact points enter the order-2 objective (Eq. EQ) only");
   if (o->order_K > 2) return abd_impl::launch_hoc_objective(m, o, q, q_hist, tau, E, grad, grad_tau, stream);
@@ -565,7 +565,7 @@ int abd_hvp(abd_model* m, const abd_step_opts* o, const double* q, const double*
   if (!q || !q_hist || !v || !Hv) return fail(ABD_EINVAL, "q, q_hist, v and Hv must not be NULL");
   if (m->max_frames > kMaxFrames || m->tree || m->fx)
     return fail(ABD_ENOTSUP, "abd_hvp handles serial hinge chains of at most 64 DOFs without drag or contact "
-                             "points in this build");
+                             "points in this library");
   if ((rc = check_device(m))) return rc;
   return abd_impl::launch_hvp(m, o, q, q_hist, v, Hv, stream);
 }
@@ -600,7 +600,7 @@ int abd_rollout_vjp(abd_model* m, const abd_step_opts* o, const double* q_init, 
     return fail(ABD_EINVAL, "q_init, q_traj, dL_dq_traj and dL_dq_init must not be NULL");
   if (m->max_frames > kMaxFrames || m->tree || m->fx)
     return fail(ABD_ENOTSUP, "abd_rollout_vjp handles serial hinge chains of at most 64 DOFs without drag or "
-                             "contact points in this build");
+                             "contact points in this library");
   if ((rc = check_device(m))) return rc;
   return abd_impl::launch_rollout_vjp(m, o, q_init, q_traj, dL_dq_traj, dL_dq_init, dL_dtau, stats, n_steps,
                                       stream);

@@ -621,7 +621,7 @@ void hoc_collocation(int K, double* tau, double* w) {
 
 int check_hoc(const abd_model* m, const abd_step_opts* o) {
   if (m->max_frames > 4 * kMaxFrames)
-    return fail(ABD_ENOTSUP, "order_K > 2 handles models of at most 256 DOFs in this build");
+    return fail(ABD_ENOTSUP, "order_K > 2 handles models of at most 256 DOFs in this library");
   return ABD_OK;
 }
 

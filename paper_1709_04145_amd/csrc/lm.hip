@@ -1093,10 +1093,10 @@ int launch_lm_hoc(abd_model* m, const abd_step_opts* o, const double* q_prev, co
                   const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream) {
   int rc = check_hoc(m, o);
   if (rc) return rc;
-  if (o->precision != ABD_FP64) return fail(ABD_ENOTSUP, "ABD_SOLVER_LM runs in ABD_FP64 only in this build");
+  if (o->precision != ABD_FP64) return fail(ABD_ENOTSUP, "ABD_SOLVER_LM runs in ABD_FP64 only in this library");
   const int U = o->order_K - 1;
   if (U != 2)
-    return fail(ABD_ENOTSUP, "ABD_SOLVER_LM handles order_K = 3 in this build (order 4 is switched off)");
+    return fail(ABD_ENOTSUP, "ABD_SOLVER_LM handles order_K = 3 in this library (order 4 is switched off)");
   // per-model dense matrices (J, J^T J, factor)
   if ((rc = lm_matrices(m))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1185,7 +1185,7 @@ int launch_hessian(abd_model* m, const abd_step_opts* o, const double* q, const 
 
 int launch_lm2(abd_model* m, const abd_step_opts* o, const double* q_prev, const double* q_curr,
                const double* tau, double* q_out, abd_step_stats* stats, int n_steps, void* stream) {
-  if (o->precision != ABD_FP64) return fail(ABD_ENOTSUP, "ABD_SOLVER_LM runs in ABD_FP64 only in this build");
+  if (o->precision != ABD_FP64) return fail(ABD_ENOTSUP, "ABD_SOLVER_LM runs in ABD_FP64 only in this library");
   int rc = lm_matrices(m);
   if (rc) return rc;
   Lm2Args a;
