@@ -861,10 +861,15 @@ struct EvalResult {
 };
 
 // One objective + gradient evaluation for the model of this wave.  FX: the
-// model may have slides, drag and contact points.
-template <typename R, bool FX = false, typename S>
+// model may have slides, drag and contact points.  TRIAL (a line-search trial
+// that is likely rejected): the model totals E, S first, by the same sums in
+// the same order (bitwise the same values), and the adjoint scan and the
+// gradient only where an acceptance test will read them: sufficient decrease
+// (E <= bound) or a change within the objective's rounding (|E - E0| <=
+// tol_s S); g = 0 otherwise.
+template <typename R, bool FX = false, bool TRIAL = false, typename S>
 __device__ EvalResult evaluate(S& sc, const DevModel& d, const FrameGeo& geo, int f, bool valid, double q,
-                               double tau, double dt2) {
+                               double tau, double dt2, double bound = 0.0, double E0 = 0.0, double tol_s = 0.0) {
   // keep the per-frame loads inside the evaluation (no hoisting across calls,
   // which would pin them in registers for the whole solve); they are issued
   // first so that their latency overlaps the kinematics scan
@@ -971,7 +976,20 @@ __device__ EvalResult evaluate(S& sc, const DevModel& d, const FrameGeo& geo, in
   // suffix sums over the frames below (inclusive prefix, then total - prefix +
   // own) and the model totals of E and S
   double suf[6] = {k0, k1, k2, fv[0], fv[1], fv[2]};
-  sc.suffix6_total2(suf, Ev, Sv);
+  if constexpr (TRIAL) {
+    sc.sum2(Ev, Sv);
+    if (!(isfinite(Ev) && (Ev <= bound || fabs(Ev - E0) <= tol_s * Sv))) {
+      EvalResult res;
+      res.g = 0.0;
+      res.E = Ev;
+      res.S = Sv;
+      return res;
+    }
+    double ta = 0.0, tb = 0.0;  // totals formed again, not needed
+    sc.suffix6_total2(suf, ta, tb);
+  } else {
+    sc.suffix6_total2(suf, Ev, Sv);
+  }
 
   // world axis w = R a, joint point p = t
   const double w0 = (double)A.m[0] * a[0] + (double)A.m[1] * a[1] + (double)A.m[2] * a[2];
