@@ -324,11 +324,10 @@ __global__ void __launch_bounds__(NW* kWave, (NW >= 4 ? 1 : kWavesPerSimd)) k_ro
             const double x = q + alpha * dir;
             EvalResult rt;
             PROF_T(t_e);
-            // chains of more than 256 frames, whose searches take many trials:
             // the first trial of an iteration (usually accepted) is evaluated
             // with its gradient, later ones with it only where an acceptance
             // test below reads it (the same values either way)
-            const bool full = NW < 8 || ls == 0;
+            const bool full = ls == 0;
             const double bound = E + c1 * alpha * gd, tol_s = 10.0 * eps_w;
             if (PREC == ABD_MIXED && f32) {
               rt = full ? evaluate<float, FX>(sc, d, geo, f, valid, x, tau, args.dt2)
